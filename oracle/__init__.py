@@ -1,0 +1,42 @@
+"""CPU float64 oracle for the gp2Scale hot path (test infrastructure, not product code).
+
+This package is a plain, slow, obviously correct restatement of what the GPU path
+computes, written from the paper (arXiv 2512.06143):
+
+* the compactly supported kernel k(x_i, x_j) = g(x_i) g(x_j) W(||x_i - x_j|| / r),
+  the product construction of Sec. 3.1 with g a sum of bump functions (Sec. 3.3,
+  Eq. bump) and W the C^2 member of the Wendland family ("small variations" of
+  Eq. wendland);
+* its sparsity pattern, by brute force and by a k-d tree;
+* the log marginal likelihood of Sec. 2 (first displayed equation, zero prior
+  mean, noise on the diagonal) through a dense Cholesky factorisation;
+* its exact gradient with respect to the hyperparameters, and the same-probe
+  stochastic estimators (Hutchinson trace, probe log-determinant) that the GPU
+  path approximates with conjugate gradients and Lanczos quadrature;
+* the counter-based SplitMix64 probe signs.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. The product library never calls it, and it
+shares no code with the HIP path.
+
+Every function documents the passage it follows. Readings of the paper where it is
+silent or garbled are listed in ``readings.py``.
+"""
+from .kernel import (wendland_c2, wendland_c2_dr, wendland_c6, bump_values,
+                     kernel_params_check)
+from .pattern import (pairwise_sqdist, pattern_bruteforce, pattern_kdtree, mean_row_count,
+                      boundary_exempt_pairs, boundary_exempt_points)
+from .dense import covariance_dense, dcov_dense, lml_dense, grad_exact, LMLResult
+from .probes import splitmix64, rademacher_probes, probe_sign_masks
+from .estimators import logdet_same_probe, grad_same_probe, lml_same_probe, hutchinson_variance
+from .sparse import covariance_csr, covariance_rows, residual_rel, pcg_jacobi
+
+__all__ = [
+    "wendland_c2", "wendland_c2_dr", "wendland_c6", "bump_values", "kernel_params_check",
+    "pairwise_sqdist", "pattern_bruteforce", "pattern_kdtree", "mean_row_count",
+    "boundary_exempt_pairs", "boundary_exempt_points",
+    "covariance_dense", "dcov_dense", "lml_dense", "grad_exact", "LMLResult",
+    "splitmix64", "rademacher_probes", "probe_sign_masks",
+    "logdet_same_probe", "grad_same_probe", "lml_same_probe", "hutchinson_variance",
+    "covariance_csr", "covariance_rows", "residual_rel", "pcg_jacobi",
+]

@@ -1,0 +1,95 @@
+"""The pins must catch plausible mistakes: each case plants one in the oracle (CPU
+only, via monkeypatch) and checks that a pin test then fails."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.dense
+import oracle.kernel
+import oracle.probes
+import test_oracle_dense as TD
+import test_oracle_estimators as TE
+import test_oracle_kernel as TK
+
+
+def _fails(fn, *args):
+    with pytest.raises(AssertionError):
+        fn(*args)
+
+
+def _w_exp3(rho):
+    rho = np.asarray(rho, dtype=np.float64)
+    return np.where(rho < 1, (1 - rho) ** 3 * (4 * rho + 1), 0.0)
+
+
+def _w_sign(rho):
+    rho = np.asarray(rho, dtype=np.float64)
+    return np.where(rho < 1, (1 - rho) ** 4 * (4 * rho - 1), 0.0)
+
+
+@pytest.mark.parametrize("bad", [_w_exp3, _w_sign])
+def test_wrong_wendland_caught(monkeypatch, bad):
+    monkeypatch.setattr(oracle, "wendland_c2", bad)
+    _fails(TK.test_wendland_c2_closed_forms)
+    _fails(TK.test_wendland_integrals)
+
+
+def test_wrong_radius_derivative_caught(monkeypatch):
+    def bad(rho, r):  # dropped one factor of rho
+        rho = np.asarray(rho, dtype=np.float64)
+        return np.where(rho < 1, 20 * rho * (1 - rho) ** 3 / r, 0.0)
+    monkeypatch.setattr(oracle, "wendland_c2_dr", bad)
+    _fails(TK.test_wendland_radius_derivative_closed_form_and_fd)
+    monkeypatch.setattr(oracle.dense, "wendland_c2_dr", bad)
+    _fails(TD.test_gradient_matches_central_differences, 2, "uniform")
+
+
+def test_wrong_bump_caught(monkeypatch):
+    orig = oracle.kernel.bump_values
+
+    def bad(x, centers, bump_width, weights, chunk=1 << 16):  # width instead of width^2
+        return orig(x, centers, np.sqrt(bump_width), weights, chunk)
+    monkeypatch.setattr(oracle, "bump_values", bad)
+    _fails(TK.test_bump_closed_forms)
+
+
+def test_wrong_mask_product_caught(monkeypatch):
+    orig = oracle.kernel.bump_values
+
+    def bad(x, centers, bump_width, weights, chunk=1 << 16):  # g squared by mistake
+        g, b, gamma = orig(x, centers, bump_width, weights, chunk)
+        return g * g, b, gamma
+    monkeypatch.setattr(oracle.dense, "bump_values", bad)
+    _fails(TD.test_two_point_closed_form)
+
+
+def test_dropped_constant_caught(monkeypatch):
+    orig = oracle.dense.lml_dense
+
+    def bad(K, y):
+        r = orig(K, y)
+        return oracle.LMLResult(r.lml + 0.5 * len(y) * np.log(2 * np.pi), r.logdet, r.yTa, r.a)
+    monkeypatch.setattr(oracle, "lml_dense", bad)
+    _fails(TD.test_lml_matches_library_gaussian_density)
+
+
+def test_wrong_trace_term_caught(monkeypatch):
+    orig = oracle.dense.grad_exact
+
+    def bad(*args):  # trace term with the wrong sign
+        g, parts = orig(*args)
+        return parts["fit"] + parts["trace"], parts
+    monkeypatch.setattr(oracle, "grad_exact", bad)
+    _fails(TD.test_diagonal_case_closed_forms)
+
+
+def test_wrong_splitmix_caught(monkeypatch):
+    def bad(seed, k):
+        k = np.asarray(k, dtype=np.uint64)
+        with np.errstate(over="ignore"):
+            z = np.uint64(seed) + k * oracle.probes._GAMMA   # off-by-one counter
+            z = (z ^ (z >> np.uint64(30))) * oracle.probes._M1
+            z = (z ^ (z >> np.uint64(27))) * oracle.probes._M2
+            return z ^ (z >> np.uint64(31))
+    monkeypatch.setattr(oracle, "splitmix64", bad)
+    _fails(TE.test_splitmix64_published_outputs)
