@@ -1,0 +1,189 @@
+/*
+ * gp2s.h -- C ABI of the MI355X (gfx950) implementation of the gp2Scale hot path
+ * (arXiv 2512.06143): assemble the sparse covariance of a compactly supported,
+ * non-stationary kernel, multiply with it, solve with it, and evaluate the log
+ * marginal likelihood (LML) and its gradient with respect to the hyperparameters.
+ *
+ * Problem statement (Sec. 2, first displayed equation; Sec. 3.5):
+ *   data x_1..x_N in R^d (d = 2 or 3), targets y, zero prior mean, noise
+ *   variance sigma_n^2 on the diagonal;
+ *   K_ij = g(x_i) g(x_j) W(||x_i - x_j|| / r) + sigma_n^2 [i == j]
+ *   with W(rho) = (1 - rho)^4 (4 rho + 1) for rho < 1, else 0 (a C^2 member of the
+ *   Wendland family of Sec. 3.1, Eq. wendland), and the bump mask
+ *   g(x) = sum_k a_k exp(1 - 1 / (1 - ||x - c_k||^2 / w^2)) inside ||x - c_k|| < w
+ *   (Sec. 3.3, Eq. bump with shape parameter 1, amplitudes a_k = the bump weights,
+ *   g a sum of P bumps; the product g g W is a valid kernel by Theorem 1, App. A);
+ *   LML = -1/2 y^T K^{-1} y - 1/2 ln|K| - N/2 ln(2 pi).
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers unless the comment says HOST.
+ *   - Vectors are float64 and in USER order (the order of the rows of x); the
+ *     library reorders internally and undoes it on output.
+ *   - All device work is ordered on the context's stream. Calls that return
+ *     values to the host (report, gradient, nnz) synchronise that stream.
+ *   - The return value is a gp2s_status. No entry point aborts, throws or prints.
+ *     gp2s_last_error() gives a one-line description of the last failure. On
+ *     failure, outputs are unspecified; handles stay valid and must still be freed.
+ *   - Scalar arguments are validated on the host before any GPU call, so invalid
+ *     arguments are reported even on a machine without a GPU.
+ *   - A context is not thread-safe; use one context per host thread and stream.
+ */
+#ifndef GP2S_H
+#define GP2S_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GP2S_ABI_VERSION 1
+
+typedef int32_t gp2s_status;
+#define GP2S_OK           0
+#define GP2S_E_INVALID    1  /* an argument is out of range, null, or inconsistent   */
+#define GP2S_E_HIP        2  /* a HIP runtime call or kernel launch failed            */
+#define GP2S_E_OOM        3  /* the allocator returned NULL                            */
+#define GP2S_E_CAPACITY   4  /* a preplanned capacity (batched mode) was exceeded     */
+#define GP2S_E_NOT_SPD    5  /* CG met p^T K p <= 0: the matrix is not positive definite */
+#define GP2S_E_NOCONV     6  /* max_iter reached; outputs hold the last iterate        */
+#define GP2S_E_NONFINITE  7  /* a NaN or infinity in x, y, or the hyperparameters     */
+
+typedef int32_t gp2s_precision;
+#define GP2S_FP64   0  /* kernel evaluation, stored K and all vectors in float64        */
+#define GP2S_MIXED  1  /* kernel evaluation and stored K in float32 (distances in
+                          float64 so that 1 - rho^2 is accurate); CG dot products,
+                          solution and residual vectors, refinement and the
+                          log-determinant accumulate in float64                       */
+
+typedef struct gp2s_ctx_s* gp2s_ctx;
+typedef struct gp2s_matrix_s* gp2s_matrix;
+
+/* Device memory callbacks. alloc returns a device pointer (NULL on failure) aligned
+ * to at least 256 bytes; free releases it. Both are called on the host from within
+ * library calls, with the context's stream as the stream of use. Passing NULL for
+ * both makes the library use hipMalloc / hipFree. */
+typedef void* (*gp2s_alloc_fn)(size_t bytes, void* user);
+typedef void (*gp2s_free_fn)(void* ptr, void* user);
+
+/* Kernel hyperparameters theta = (r, a_1..a_P, sigma_n^2) plus the fixed bump
+ * geometry (centres and width are not differentiated). */
+typedef struct {
+  int32_t dim;            /* 2 or 3                                                  */
+  int32_t n_bumps;        /* P, 1..256                                               */
+  double radius;          /* Wendland support radius r > 0 (Sec. 3.1, r_0)           */
+  double bump_width;      /* bump radius w > 0 (Sec. 3.3, r in Eq. bump)             */
+  double noise_var;       /* sigma_n^2 >= 0, added on the diagonal (Sec. 2, V)       */
+  const double* centers;  /* HOST [n_bumps * dim], row-major bump centres c_k        */
+  const double* weights;  /* HOST [n_bumps], bump amplitudes a_k                     */
+} gp2s_params;
+
+/* Solver options. gp2s_default_opts() fills the defaults given in brackets. */
+typedef struct {
+  int32_t n_probes;       /* S in [0, 64] Rademacher probes for ln|K| and the trace
+                             term of the gradient [64]                               */
+  int32_t max_iter;       /* CG iteration cap per solve [20000]                       */
+  int32_t max_ir;         /* iterative-refinement restarts of the y solve [4]         */
+  int32_t check_every;    /* host convergence poll interval in iterations [16]        */
+  uint64_t seed;          /* probe seed [0]                                           */
+  double tol;             /* target ||y - K a|| / ||y|| (K as stored) [1e-8]          */
+  double probe_tol;       /* per-probe relative CG residual target [1e-7]             */
+} gp2s_solve_opts;
+
+/* Filled on return (HOST struct). */
+typedef struct {
+  double lml;             /* LML estimate (same-probe log-determinant)              */
+  double logdet;          /* ln|K| estimate                                          */
+  double yTa;             /* y^T a                                                    */
+  double resid;           /* ||y - K a|| / ||y|| recomputed in float64 at the end    */
+  double logdet_stderr;   /* standard error of the probe average                     */
+  int32_t iters;          /* CG iterations of the y solve, all restarts included     */
+  int32_t probe_iters;    /* CG iterations of the probe block (longest column)       */
+  int32_t ir_steps;       /* refinement restarts used                                */
+  int32_t n_probes;       /* probes used                                             */
+} gp2s_report;
+
+/* ---- version and options ------------------------------------------------------ */
+int32_t gp2s_abi_version(void);
+void gp2s_default_opts(gp2s_solve_opts* opts);     /* HOST struct; no-op on NULL    */
+const char* gp2s_status_string(gp2s_status s);     /* static string                 */
+
+/* ---- context --------------------------------------------------------------------
+ * stream: a hipStream_t (NULL = the default stream). No GPU call is made here; the
+ * device is the one current when the first compute call is made. */
+gp2s_status gp2s_create(gp2s_ctx* out, void* stream, gp2s_alloc_fn alloc, gp2s_free_fn free_fn,
+                        void* user);
+gp2s_status gp2s_destroy(gp2s_ctx ctx);
+const char* gp2s_last_error(gp2s_ctx ctx);         /* valid until the next call on ctx */
+
+/* Validate n and params on the host only (what gp2s_assemble checks first). */
+gp2s_status gp2s_check_params(gp2s_ctx ctx, int64_t n, const gp2s_params* params);
+
+/* ---- assembly (Sec. 3.5 covariance computation; App. B.7 pipeline) ---------------
+ * Builds K for points x (DEVICE [n * dim] float64, row-major, user order) as CSR in
+ * an internal, spatially sorted order. Only pairs within the kernel's support are
+ * evaluated: points are binned on a grid of side >= r, each row tests the points
+ * of its neighbouring bins, and survivors are compacted straight into CSR.
+ * Stored pattern: the diagonal plus every pair with ||x_i - x_j|| < r whose two
+ * points both lie strictly inside some bump (entries may be explicit zeros).
+ * The handle keeps a float copy of x, g, the permutation and the CSR; it is owned
+ * by the caller and released with gp2s_matrix_free. Non-finite coordinates give
+ * GP2S_E_NONFINITE. */
+gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_params* params,
+                          gp2s_precision precision, gp2s_matrix* out);
+
+gp2s_status gp2s_matrix_info(gp2s_matrix m, int64_t* n, int64_t* nnz, gp2s_precision* precision);
+
+/* Copy the CSR out (DEVICE, caller-allocated): row_ptr [n+1] int64, col [nnz] int32,
+ * val [nnz] float32 (GP2S_MIXED) or float64 (GP2S_FP64), perm [n] int32 with
+ * perm[internal row] = user row. Rows and columns are in internal order, columns
+ * ascending within a row. Any output pointer may be NULL to skip it. */
+gp2s_status gp2s_matrix_export(gp2s_ctx ctx, gp2s_matrix m, int64_t* row_ptr, int32_t* col,
+                               void* val, int32_t* perm);
+
+/* Wrap a caller's CSR (DEVICE; user order, columns ascending, diagonal present and
+ * positive) in a handle that gp2s_spmv / gp2s_solve / gp2s_lml accept. The data are
+ * copied. gp2s_lml_grad rejects imported handles: it needs the points and the
+ * hyperparameters to differentiate K. */
+gp2s_status gp2s_matrix_import(gp2s_ctx ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                               const int32_t* col, const void* val, gp2s_precision precision,
+                               gp2s_matrix* out);
+
+gp2s_status gp2s_matrix_free(gp2s_matrix m);
+
+/* ---- products and solves ------------------------------------------------------------
+ * Y = K X for nrhs in [1, 64] right-hand sides; X and Y are DEVICE [n * nrhs] float64,
+ * row-major (row i holds the nrhs values of point i). The CSR SpMV that drives the
+ * solve (Sec. 3.5; App. B.6 "MINRES"): products of stored values with float64
+ * vectors accumulate in float64. */
+gp2s_status gp2s_spmv(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X, double* Y);
+
+/* a = K^{-1} y (DEVICE [n] float64 each) by Jacobi-preconditioned CG with float64
+ * vectors and dot products, restarted from the recomputed residual (iterative
+ * refinement) until ||y - K a|| <= tol ||y||. The paper's host solver is MINRES
+ * (App. B.6); K is symmetric positive definite here, so CG reaches the same
+ * solution. report may be NULL. */
+gp2s_status gp2s_solve(gp2s_ctx ctx, gp2s_matrix m, const double* y, double* a,
+                       const gp2s_solve_opts* opts, gp2s_report* report);
+
+/* LML (Sec. 2): solves K a = y as gp2s_solve does, then estimates ln|K| from
+ * opts->n_probes Rademacher probes z_s (SplitMix64 signs, counter s * 2^40 + user
+ * index): ln|K| ~ sum_i ln K_ii + (1/S) sum_s z_s^T ln(Khat) z_s, Khat = D^-1/2 K
+ * D^-1/2, each quadratic form by Lanczos quadrature from the Jacobi-CG coefficients
+ * of the solve K q_s = D^1/2 z_s. report is required (HOST). a may be NULL. */
+gp2s_status gp2s_lml(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_solve_opts* opts,
+                     double* a, gp2s_report* report);
+
+/* gp2s_lml plus its gradient grad (HOST [n_bumps + 2] float64) in the order
+ * (r, a_1..a_P, sigma_n^2): dLML/dtheta = 1/2 a^T dK a - 1/2 tr(K^{-1} dK), the trace
+ * estimated as (1/S) sum_s q_s^T dK D^-1/2 z_s with the probe solutions q_s.
+ * dK/dtheta is recomputed from the points for every stored entry; no per-parameter
+ * matrix is formed. Requires a handle from gp2s_assemble and n_probes >= 1. */
+gp2s_status gp2s_lml_grad(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_solve_opts* opts,
+                          double* a, gp2s_report* report, double* grad);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GP2S_H */

@@ -1,0 +1,835 @@
+// Host runtime and C ABI of libgp2s: argument validation, contexts and matrix
+// handles, and the orchestration of the device kernels for assembly, products,
+// solves, the log marginal likelihood and its gradient.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "gp2s_internal.h"
+
+using namespace gp2s;
+
+struct gp2s_ctx_s {
+  hipStream_t stream = nullptr;
+  gp2s_alloc_fn alloc = nullptr;
+  gp2s_free_fn free_fn = nullptr;
+  void* user = nullptr;
+  std::string err;
+  void* pinned = nullptr;  // small pinned host buffer for scalar read-backs
+};
+
+struct gp2s_matrix_s {
+  gp2s_ctx ctx = nullptr;
+  int64_t n = 0, nnz = 0;
+  int prec = GP2S_FP64;
+  bool assembled = false;
+  // hyperparameters (assembled handles)
+  int dim = 0, P = 0;
+  double radius = 0, bump_width = 0, noise = 0;
+  std::vector<double> centers_h, weights_h;
+  double* centers_d = nullptr;
+  double* weights_d = nullptr;
+  GridDev grid{};
+  int32_t* perm = nullptr;  // internal -> user (null for imported handles)
+  float4* pts32 = nullptr;
+  double4* pts64 = nullptr;
+  double* x64 = nullptr;
+  double* g64 = nullptr;
+  int32_t* binid = nullptr;
+  int64_t* bin_start = nullptr;
+  int64_t* row_ptr = nullptr;
+  int32_t* col = nullptr;
+  void* val = nullptr;
+  double* diag = nullptr;
+  double* dinv = nullptr;
+  bool diag_ok = true;
+  std::vector<void*> owned;
+};
+
+namespace {
+
+constexpr size_t kPinnedBytes = 1 << 16;
+
+gp2s_status fail(gp2s_ctx c, gp2s_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+void* dalloc(gp2s_ctx c, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~size_t(255);
+  if (c->alloc) return c->alloc(bytes, c->user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void dfree(gp2s_ctx c, void* p) {
+  if (!p) return;
+  if (c->free_fn) c->free_fn(p, c->user);
+  else (void)hipFree(p);
+}
+
+// Temporary device buffers released when the call returns.
+struct Scratch {
+  gp2s_ctx c;
+  std::vector<void*> ptrs;
+  bool oom = false;
+  explicit Scratch(gp2s_ctx cc) : c(cc) {}
+  ~Scratch() {
+    if (!ptrs.empty()) (void)hipStreamSynchronize(c->stream);
+    for (void* p : ptrs) dfree(c, p);
+  }
+  template <typename T>
+  T* get(size_t count) {
+    void* p = dalloc(c, count * sizeof(T));
+    if (!p) {
+      oom = true;
+      return nullptr;
+    }
+    ptrs.push_back(p);
+    return static_cast<T*>(p);
+  }
+};
+
+template <typename T>
+T* own(gp2s_matrix m, size_t count) {
+  void* p = dalloc(m->ctx, count * sizeof(T));
+  if (p) m->owned.push_back(p);
+  return static_cast<T*>(p);
+}
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+#define HIPCHK(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess) return fail(ctx, GP2S_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define OOMCHK(ptr)                                                                             \
+  do {                                                                                          \
+    if (!(ptr)) return fail(ctx, GP2S_E_OOM, "device allocation failed (%s)", #ptr);            \
+  } while (0)
+
+gp2s_status ensure_device(gp2s_ctx ctx) {
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count == 0)
+    return fail(ctx, GP2S_E_HIP, "no HIP device available (%s)", hipGetErrorString(e));
+  if (!ctx->pinned) {
+    HIPCHK(hipHostMalloc(&ctx->pinned, kPinnedBytes, hipHostMallocDefault));
+  }
+  return GP2S_OK;
+}
+
+// Copy `bytes` from device to the pinned buffer and wait for the stream.
+gp2s_status readback(gp2s_ctx ctx, const void* dev, size_t bytes, void* host) {
+  if (bytes > kPinnedBytes) return fail(ctx, GP2S_E_INVALID, "internal: readback too large");
+  HIPCHK(hipMemcpyAsync(ctx->pinned, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  std::memcpy(host, ctx->pinned, bytes);
+  return GP2S_OK;
+}
+
+gp2s_status check_opts(gp2s_ctx ctx, const gp2s_solve_opts* o, bool need_probes) {
+  if (!o) return fail(ctx, GP2S_E_INVALID, "opts is NULL");
+  if (o->n_probes < 0 || o->n_probes > kMaxProbes)
+    return fail(ctx, GP2S_E_INVALID, "n_probes must be in [0, %d]", kMaxProbes);
+  if (need_probes && o->n_probes < 1) return fail(ctx, GP2S_E_INVALID, "n_probes must be >= 1");
+  if (o->max_iter < 1 || o->max_iter > 10000000) return fail(ctx, GP2S_E_INVALID, "max_iter out of range");
+  if (o->max_ir < 0 || o->max_ir > 100) return fail(ctx, GP2S_E_INVALID, "max_ir out of range");
+  if (o->check_every < 1) return fail(ctx, GP2S_E_INVALID, "check_every must be >= 1");
+  if (!is_fin(o->tol) || o->tol <= 0 || o->tol >= 1) return fail(ctx, GP2S_E_INVALID, "tol must be in (0, 1)");
+  if (!is_fin(o->probe_tol) || o->probe_tol <= 0 || o->probe_tol >= 1)
+    return fail(ctx, GP2S_E_INVALID, "probe_tol must be in (0, 1)");
+  return GP2S_OK;
+}
+
+gp2s_status check_matrix(gp2s_ctx ctx, gp2s_matrix m) {
+  if (!m) return fail(ctx, GP2S_E_INVALID, "matrix handle is NULL");
+  if (m->ctx != ctx) return fail(ctx, GP2S_E_INVALID, "matrix handle belongs to another context");
+  return GP2S_OK;
+}
+
+// ---- conjugate gradients ------------------------------------------------------------------
+struct CgRun {
+  CgState cs{};
+  int32_t host_iters[kMaxProbes] = {};
+  int32_t total_iters = 0;  // iterations executed (longest column)
+  bool converged = false;
+};
+
+// Jacobi-PCG for K X = B over S columns (internal order). X receives the solution.
+gp2s_status run_cg(gp2s_ctx ctx, gp2s_matrix m, int S, const double* B, double* X, double tol, int max_iter,
+                   int check_every, bool keep_hist, Scratch& sc, CgRun& out) {
+  const int64_t n = m->n;
+  const size_t nS = (size_t)n * S;
+  double* R = sc.get<double>(nS);
+  double* P = sc.get<double>(nS);
+  double* Q = sc.get<double>(nS);
+  double* sd = sc.get<double>(6 * S + (size_t)kReduceBlocks * S * 2);
+  int32_t* si = sc.get<int32_t>(2 * S + 4);
+  uint32_t* tk = sc.get<uint32_t>(4);
+  if (sc.oom) return fail(ctx, GP2S_E_OOM, "CG workspace allocation failed");
+  CgState& cs = out.cs;
+  cs.rz = sd;
+  cs.bb = sd + S;
+  cs.tol2 = sd + 2 * S;
+  cs.alpha = sd + 3 * S;
+  cs.beta = sd + 4 * S;
+  cs.rr = sd + 5 * S;
+  cs.partial = sd + 6 * S;
+  cs.done = si;
+  cs.iters = si + S;
+  cs.flags = si + 2 * S;
+  cs.ticket = tk;
+  cs.hist_a = cs.hist_b = nullptr;
+  cs.max_hist = 0;
+  if (keep_hist) {
+    cs.hist_a = sc.get<double>((size_t)max_iter * S);
+    cs.hist_b = sc.get<double>((size_t)max_iter * S);
+    if (sc.oom) return fail(ctx, GP2S_E_OOM, "CG history allocation failed");
+    cs.max_hist = max_iter;
+  }
+  HIPCHK(hipMemsetAsync(si, 0, (2 * S + 4) * sizeof(int32_t), ctx->stream));
+  HIPCHK(hipMemsetAsync(tk, 0, 4 * sizeof(uint32_t), ctx->stream));
+  HIPCHK(launch_cg_init(n, S, B, m->dinv, X, R, P, cs, &tol, ctx->stream));
+  int32_t flags[4];
+  gp2s_status st = readback(ctx, cs.flags, sizeof(flags), flags);
+  if (st) return st;
+  if (flags[2]) return fail(ctx, GP2S_E_NONFINITE, "non-finite right-hand side");
+  int it = 0;
+  bool open = flags[1] > 0;
+  while (open && it < max_iter) {
+    HIPCHK(launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, n, S, (double)m->nnz / (double)n, P, Q, cs,
+                            ctx->stream));
+    HIPCHK(launch_cg_update(n, S, X, R, P, Q, m->dinv, cs, it, ctx->stream));
+    HIPCHK(launch_cg_pupdate(n, S, P, R, m->dinv, cs, ctx->stream));
+    ++it;
+    if (it % check_every == 0 || it == max_iter) {
+      st = readback(ctx, cs.flags, sizeof(flags), flags);
+      if (st) return st;
+      if (flags[0]) return fail(ctx, GP2S_E_NOT_SPD, "CG breakdown: p^T K p <= 0 (matrix not positive definite)");
+      if (flags[2]) return fail(ctx, GP2S_E_NONFINITE, "non-finite values during CG");
+      open = flags[1] > 0;
+    }
+  }
+  st = readback(ctx, cs.iters, S * sizeof(int32_t), out.host_iters);
+  if (st) return st;
+  out.total_iters = 0;
+  for (int s = 0; s < S; ++s) out.total_iters = std::max(out.total_iters, out.host_iters[s]);
+  out.converged = !open;
+  return GP2S_OK;
+}
+
+// Scalar reductions through the pinned buffer.
+gp2s_status dot_host(gp2s_ctx ctx, int64_t n, const double* a, const double* b, double* buf, uint32_t* ticket,
+                     double* out) {
+  HIPCHK(launch_dot_partial(n, a, b, buf, ticket, ctx->stream));
+  return readback(ctx, buf, sizeof(double), out);
+}
+
+// Solve K a = y (internal order) with restarts from the recomputed residual.
+gp2s_status solve_internal(gp2s_ctx ctx, gp2s_matrix m, const double* y, double* a, const gp2s_solve_opts* o,
+                           Scratch& sc, gp2s_report* rep, bool* converged) {
+  const int64_t n = m->n;
+  double* red = sc.get<double>(1 + kReduceBlocks);
+  uint32_t* tk = sc.get<uint32_t>(1);
+  double* r = sc.get<double>(n);
+  double* d = sc.get<double>(n);
+  double* kx = sc.get<double>(n);
+  if (sc.oom) return fail(ctx, GP2S_E_OOM, "solve workspace allocation failed");
+  HIPCHK(hipMemsetAsync(tk, 0, sizeof(uint32_t), ctx->stream));
+  int32_t* flag = reinterpret_cast<int32_t*>(tk);  // reused below only after the ticket is idle
+  (void)flag;
+  double bb = 0.0;
+  gp2s_status st = dot_host(ctx, n, y, nullptr, red, tk, &bb);
+  if (st) return st;
+  if (!is_fin(bb)) return fail(ctx, GP2S_E_NONFINITE, "y contains NaN or infinity");
+  if (!m->diag_ok) return fail(ctx, GP2S_E_NOT_SPD, "diagonal of K is not positive");
+  int total = 0, ir = 0;
+  *converged = false;
+  double resid = 0.0;
+  if (bb == 0.0) {
+    HIPCHK(hipMemsetAsync(a, 0, n * sizeof(double), ctx->stream));
+    *converged = true;
+  } else {
+    CgRun run;
+    st = run_cg(ctx, m, 1, y, a, o->tol, o->max_iter, o->check_every, false, sc, run);
+    if (st) return st;
+    total += run.total_iters;
+    for (;;) {
+      HIPCHK(launch_spmv(m->prec, m->row_ptr, m->col, m->val, n, (double)m->nnz / n, a, kx, ctx->stream));
+      HIPCHK(launch_axpy_sub(n, y, kx, r, ctx->stream));
+      double rr = 0.0;
+      st = dot_host(ctx, n, r, nullptr, red, tk, &rr);
+      if (st) return st;
+      resid = std::sqrt(rr / bb);
+      if (!is_fin(resid)) return fail(ctx, GP2S_E_NONFINITE, "non-finite residual");
+      if (resid <= o->tol) {
+        *converged = true;
+        break;
+      }
+      if (ir >= o->max_ir || total >= o->max_iter) break;
+      ++ir;
+      const double inner = std::min(0.5, 0.5 * o->tol / resid);
+      CgRun r2;
+      st = run_cg(ctx, m, 1, r, d, inner, o->max_iter - total, o->check_every, false, sc, r2);
+      if (st) return st;
+      total += r2.total_iters;
+      HIPCHK(launch_add(n, a, d, ctx->stream));
+    }
+  }
+  if (rep) {
+    rep->resid = resid;
+    rep->iters = total;
+    rep->ir_steps = ir;
+  }
+  return GP2S_OK;
+}
+
+struct ProbeResult {
+  double logdet = 0.0, stderr_ = 0.0;
+  int iters = 0;
+  bool converged = false;
+};
+
+// Probe solves K q_s = D^1/2 z_s and the Lanczos log-determinant estimate.
+gp2s_status probes_internal(gp2s_ctx ctx, gp2s_matrix m, const gp2s_solve_opts* o, Scratch& sc,
+                            uint64_t* mask, double* Qsol, ProbeResult& pr) {
+  const int64_t n = m->n;
+  const int S = o->n_probes;
+  double* B = sc.get<double>((size_t)n * S);
+  double* red = sc.get<double>(1 + kReduceBlocks);
+  uint32_t* tk = sc.get<uint32_t>(1);
+  if (sc.oom) return fail(ctx, GP2S_E_OOM, "probe workspace allocation failed");
+  HIPCHK(hipMemsetAsync(tk, 0, sizeof(uint32_t), ctx->stream));
+  HIPCHK(launch_probe_masks(n, m->perm, o->seed, S, mask, ctx->stream));
+  HIPCHK(launch_probe_rhs(n, S, mask, m->diag, B, ctx->stream));
+  CgRun run;
+  gp2s_status st = run_cg(ctx, m, S, B, Qsol, o->probe_tol, o->max_iter, o->check_every, true, sc, run);
+  if (st) return st;
+  const int64_t max_m = std::max(1, run.total_iters);
+  double* work = sc.get<double>((size_t)2 * S * max_m);
+  double* quad = sc.get<double>(S);
+  if (sc.oom) return fail(ctx, GP2S_E_OOM, "quadrature workspace allocation failed");
+  HIPCHK(launch_slq_ws(S, run.cs.hist_a, run.cs.hist_b, run.cs.iters, work, max_m, quad, ctx->stream));
+  std::vector<double> qh(S);
+  st = readback(ctx, quad, S * sizeof(double), qh.data());
+  if (st) return st;
+  double sumlog = 0.0;
+  HIPCHK(launch_sum_log(n, m->diag, red, tk, ctx->stream));
+  st = readback(ctx, red, sizeof(double), &sumlog);
+  if (st) return st;
+  double mean = 0.0;
+  for (int s = 0; s < S; ++s) mean += (double)n * qh[s];
+  mean /= S;
+  double var = 0.0;
+  for (int s = 0; s < S; ++s) var += ((double)n * qh[s] - mean) * ((double)n * qh[s] - mean);
+  pr.stderr_ = S > 1 ? std::sqrt(var / (S - 1) / S) : 0.0;
+  pr.logdet = sumlog + mean;
+  pr.iters = run.total_iters;
+  pr.converged = run.converged;
+  return GP2S_OK;
+}
+
+gp2s_status lml_common(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_solve_opts* o, double* a,
+                       gp2s_report* rep, double* grad) {
+  if (!ctx) return GP2S_E_INVALID;
+  gp2s_status st = check_matrix(ctx, m);
+  if (st) return st;
+  st = check_opts(ctx, o, true);
+  if (st) return st;
+  if (!y) return fail(ctx, GP2S_E_INVALID, "y is NULL");
+  if (!rep) return fail(ctx, GP2S_E_INVALID, "report is NULL");
+  if (grad && !m->assembled)
+    return fail(ctx, GP2S_E_INVALID, "the gradient needs a handle from gp2s_assemble (imported CSR has no kernel)");
+  st = ensure_device(ctx);
+  if (st) return st;
+  const int64_t n = m->n;
+  const int S = o->n_probes;
+  Scratch sc(ctx);
+  double* yi = sc.get<double>(n);
+  double* ai = sc.get<double>(n);
+  double* Qs = sc.get<double>((size_t)n * S);
+  uint64_t* mask = sc.get<uint64_t>(n);
+  double* red = sc.get<double>(1 + kReduceBlocks);
+  uint32_t* tk = sc.get<uint32_t>(1);
+  if (sc.oom) return fail(ctx, GP2S_E_OOM, "LML workspace allocation failed");
+  HIPCHK(hipMemsetAsync(tk, 0, sizeof(uint32_t), ctx->stream));
+  HIPCHK(launch_gather_rows(n, 1, m->perm, y, yi, ctx->stream));
+  std::memset(rep, 0, sizeof(*rep));
+  bool conv_y = false;
+  st = solve_internal(ctx, m, yi, ai, o, sc, rep, &conv_y);
+  if (st) return st;
+  double yTa = 0.0;
+  st = dot_host(ctx, n, yi, ai, red, tk, &yTa);
+  if (st) return st;
+  ProbeResult pr;
+  st = probes_internal(ctx, m, o, sc, mask, Qs, pr);
+  if (st) return st;
+  rep->yTa = yTa;
+  rep->logdet = pr.logdet;
+  rep->logdet_stderr = pr.stderr_;
+  rep->probe_iters = pr.iters;
+  rep->n_probes = S;
+  rep->lml = -0.5 * yTa - 0.5 * pr.logdet - 0.5 * (double)n * std::log(2.0 * M_PI);
+  if (a) HIPCHK(launch_scatter_rows(n, 1, m->perm, ai, a, ctx->stream));
+  if (grad) {
+    double* Rr = sc.get<double>(n);
+    double* Tr = sc.get<double>(n);
+    double* Ur = sc.get<double>(n);
+    const int ncomp = m->P + 2;
+    double* gpart = sc.get<double>((size_t)256 * ncomp);
+    double* gd = sc.get<double>(ncomp);
+    uint32_t* tk2 = sc.get<uint32_t>(1);
+    if (sc.oom) return fail(ctx, GP2S_E_OOM, "gradient workspace allocation failed");
+    HIPCHK(hipMemsetAsync(tk2, 0, sizeof(uint32_t), ctx->stream));
+    BackwardArgs b{};
+    b.rp = m->row_ptr;
+    b.col = m->col;
+    b.pts32 = m->pts32;
+    b.pts64 = m->pts64;
+    b.g64 = m->g64;
+    b.a = ai;
+    b.Q = Qs;
+    b.mask = mask;
+    b.dinv = m->dinv;
+    b.n = n;
+    b.S = S;
+    b.radius = m->radius;
+    b.r2 = m->radius * m->radius;
+    b.inv_r2 = 1.0 / b.r2;
+    HIPCHK(launch_backward_rows(b, m->prec, Rr, Tr, Ur, ctx->stream));
+    HIPCHK(launch_grad_reduce(n, m->dim, m->P, S, m->x64, m->g64, ai, Rr, Tr, Ur, m->centers_d,
+                              m->bump_width * m->bump_width, gpart, tk2, gd, ctx->stream));
+    st = readback(ctx, gd, ncomp * sizeof(double), grad);
+    if (st) return st;
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (!conv_y || !pr.converged)
+    return fail(ctx, GP2S_E_NOCONV, "CG did not converge within max_iter (y: %s, probes: %s)",
+                conv_y ? "yes" : "no", pr.converged ? "yes" : "no");
+  return GP2S_OK;
+}
+
+}  // namespace
+
+// =====================================================================================
+extern "C" {
+
+int32_t gp2s_abi_version(void) { return GP2S_ABI_VERSION; }
+
+void gp2s_default_opts(gp2s_solve_opts* o) {
+  if (!o) return;
+  o->n_probes = 64;
+  o->max_iter = 20000;
+  o->max_ir = 4;
+  o->check_every = 16;
+  o->seed = 0;
+  o->tol = 1e-8;
+  o->probe_tol = 1e-7;
+}
+
+const char* gp2s_status_string(gp2s_status s) {
+  switch (s) {
+    case GP2S_OK: return "ok";
+    case GP2S_E_INVALID: return "invalid argument";
+    case GP2S_E_HIP: return "HIP runtime error";
+    case GP2S_E_OOM: return "out of device memory";
+    case GP2S_E_CAPACITY: return "capacity exceeded";
+    case GP2S_E_NOT_SPD: return "matrix not positive definite";
+    case GP2S_E_NOCONV: return "iteration did not converge";
+    case GP2S_E_NONFINITE: return "non-finite input";
+    default: return "unknown status";
+  }
+}
+
+gp2s_status gp2s_create(gp2s_ctx* out, void* stream, gp2s_alloc_fn alloc, gp2s_free_fn free_fn, void* user) {
+  if (!out) return GP2S_E_INVALID;
+  *out = nullptr;
+  if ((alloc == nullptr) != (free_fn == nullptr)) return GP2S_E_INVALID;
+  gp2s_ctx c = new (std::nothrow) gp2s_ctx_s();
+  if (!c) return GP2S_E_OOM;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->alloc = alloc;
+  c->free_fn = free_fn;
+  c->user = user;
+  *out = c;
+  return GP2S_OK;
+}
+
+gp2s_status gp2s_destroy(gp2s_ctx ctx) {
+  if (!ctx) return GP2S_E_INVALID;
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+  return GP2S_OK;
+}
+
+const char* gp2s_last_error(gp2s_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+gp2s_status gp2s_check_params(gp2s_ctx ctx, int64_t n, const gp2s_params* p) {
+  if (!ctx) return GP2S_E_INVALID;
+  if (n < 1 || n >= (int64_t)INT32_MAX) return fail(ctx, GP2S_E_INVALID, "n must be in [1, 2^31 - 1)");
+  if (!p) return fail(ctx, GP2S_E_INVALID, "params is NULL");
+  if (p->dim != 2 && p->dim != 3) return fail(ctx, GP2S_E_INVALID, "dim must be 2 or 3");
+  if (p->n_bumps < 1 || p->n_bumps > kMaxBumps)
+    return fail(ctx, GP2S_E_INVALID, "n_bumps must be in [1, %d]", kMaxBumps);
+  if (!p->centers || !p->weights) return fail(ctx, GP2S_E_INVALID, "centers and weights must be non-NULL");
+  if (!is_fin(p->radius) || !is_fin(p->bump_width) || !is_fin(p->noise_var))
+    return fail(ctx, GP2S_E_NONFINITE, "non-finite hyperparameter");
+  if (p->radius <= 0) return fail(ctx, GP2S_E_INVALID, "radius must be > 0");
+  if (p->bump_width <= 0) return fail(ctx, GP2S_E_INVALID, "bump_width must be > 0");
+  if (p->noise_var < 0) return fail(ctx, GP2S_E_INVALID, "noise_var must be >= 0");
+  for (int k = 0; k < p->n_bumps * p->dim; ++k)
+    if (!is_fin(p->centers[k])) return fail(ctx, GP2S_E_NONFINITE, "non-finite bump centre");
+  for (int k = 0; k < p->n_bumps; ++k)
+    if (!is_fin(p->weights[k])) return fail(ctx, GP2S_E_NONFINITE, "non-finite bump weight");
+  return GP2S_OK;
+}
+
+gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_params* p,
+                          gp2s_precision prec, gp2s_matrix* out) {
+  if (!ctx) return GP2S_E_INVALID;
+  if (!out) return fail(ctx, GP2S_E_INVALID, "out is NULL");
+  *out = nullptr;
+  gp2s_status st = gp2s_check_params(ctx, n, p);
+  if (st) return st;
+  if (!x) return fail(ctx, GP2S_E_INVALID, "x is NULL");
+  if (prec != GP2S_FP64 && prec != GP2S_MIXED) return fail(ctx, GP2S_E_INVALID, "unknown precision");
+  st = ensure_device(ctx);
+  if (st) return st;
+
+  gp2s_matrix m = new (std::nothrow) gp2s_matrix_s();
+  if (!m) return fail(ctx, GP2S_E_OOM, "host allocation failed");
+  struct Guard {
+    gp2s_matrix m;
+    bool keep = false;
+    ~Guard() {
+      if (!keep) gp2s_matrix_free(m);
+    }
+  } guard{m};
+  m->ctx = ctx;
+  m->n = n;
+  m->prec = prec;
+  m->assembled = true;
+  m->dim = p->dim;
+  m->P = p->n_bumps;
+  m->radius = p->radius;
+  m->bump_width = p->bump_width;
+  m->noise = p->noise_var;
+  m->centers_h.assign(p->centers, p->centers + (size_t)p->n_bumps * p->dim);
+  m->weights_h.assign(p->weights, p->weights + p->n_bumps);
+  const int dim = p->dim;
+  hipStream_t sm = ctx->stream;
+
+  m->centers_d = own<double>(m, m->centers_h.size());
+  m->weights_d = own<double>(m, m->weights_h.size());
+  OOMCHK(m->centers_d);
+  OOMCHK(m->weights_d);
+  HIPCHK(hipMemcpyAsync(m->centers_d, m->centers_h.data(), m->centers_h.size() * sizeof(double),
+                        hipMemcpyHostToDevice, sm));
+  HIPCHK(hipMemcpyAsync(m->weights_d, m->weights_h.data(), m->weights_h.size() * sizeof(double),
+                        hipMemcpyHostToDevice, sm));
+
+  Scratch sc(ctx);
+  // 1. bounding box and finiteness
+  const int bb_blocks = 256;
+  double* part = sc.get<double>(bb_blocks * 6);
+  int32_t* nonfinite = sc.get<int32_t>(1);
+  if (sc.oom) return fail(ctx, GP2S_E_OOM, "assembly workspace allocation failed");
+  HIPCHK(hipMemsetAsync(nonfinite, 0, sizeof(int32_t), sm));
+  HIPCHK(launch_bbox(x, n, dim, part, nonfinite, bb_blocks, sm));
+  std::vector<double> hp(bb_blocks * 6 + 1);
+  st = readback(ctx, part, bb_blocks * 6 * sizeof(double), hp.data());
+  if (st) return st;
+  int32_t nf = 0;
+  st = readback(ctx, nonfinite, sizeof(int32_t), &nf);
+  if (st) return st;
+  if (nf) return fail(ctx, GP2S_E_NONFINITE, "x contains NaN or infinity");
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int k = 0; k < dim; ++k) {
+    lo[k] = INFINITY;
+    hi[k] = -INFINITY;
+    for (int b = 0; b < bb_blocks; ++b) {
+      lo[k] = std::min(lo[k], hp[b * 6 + k]);
+      hi[k] = std::max(hi[k], hp[b * 6 + 3 + k]);
+    }
+  }
+  // 2. grid: side h >= r (enlarged by 1e-6 relative so rounding in the bin index
+  //    cannot separate a pair closer than r by two bins); capped bin count.
+  double h = p->radius * (1.0 + 1e-6);
+  const double max_bins = std::max(4.0 * (double)n, 65536.0);
+  GridDev g{};
+  g.dim = dim;
+  for (int iter = 0; iter < 64; ++iter) {
+    double nb_total = 1.0;
+    for (int k = 0; k < dim; ++k) nb_total *= std::floor((hi[k] - lo[k]) / h) + 1.0;
+    if (nb_total <= max_bins) break;
+    h *= std::pow(nb_total / max_bins, 1.0 / dim) * 1.01;
+  }
+  g.nbins = 1;
+  for (int k = 0; k < 3; ++k) {
+    g.origin[k] = k < dim ? lo[k] : 0.0;
+    g.nb[k] = k < dim ? (int32_t)(std::floor((hi[k] - lo[k]) / h) + 1.0) : 1;
+    g.nbins *= g.nb[k];
+  }
+  g.inv_h = 1.0 / h;
+  m->grid = g;
+
+  // 3. prologue, counting sort into bins, internal-order point copies
+  int32_t* bin_of = sc.get<int32_t>(n);
+  int32_t* slot = sc.get<int32_t>(n);
+  int32_t* bin_count = sc.get<int32_t>(g.nbins);
+  double* g64u = sc.get<double>(n);
+  uint8_t* gam = sc.get<uint8_t>(n);
+  int32_t* perm_tmp = sc.get<int32_t>(n);
+  void* scan_ws = sc.get<uint8_t>(std::max(scan_workspace_bytes(g.nbins), scan_workspace_bytes(n)));
+  int32_t* row_cnt = sc.get<int32_t>(n);
+  if (sc.oom) return fail(ctx, GP2S_E_OOM, "assembly workspace allocation failed");
+  m->bin_start = own<int64_t>(m, g.nbins + 1);
+  m->perm = own<int32_t>(m, n);
+  m->x64 = own<double>(m, (size_t)n * dim);
+  m->g64 = own<double>(m, n);
+  m->binid = own<int32_t>(m, n);
+  m->row_ptr = own<int64_t>(m, n + 1);
+  m->diag = own<double>(m, n);
+  m->dinv = own<double>(m, n);
+  OOMCHK(m->bin_start);
+  OOMCHK(m->perm);
+  OOMCHK(m->x64);
+  OOMCHK(m->g64);
+  OOMCHK(m->binid);
+  OOMCHK(m->row_ptr);
+  OOMCHK(m->diag);
+  OOMCHK(m->dinv);
+  if (prec == GP2S_MIXED) {
+    m->pts32 = own<float4>(m, n);
+    OOMCHK(m->pts32);
+  } else {
+    m->pts64 = own<double4>(m, n);
+    OOMCHK(m->pts64);
+  }
+  HIPCHK(hipMemsetAsync(bin_count, 0, g.nbins * sizeof(int32_t), sm));
+  HIPCHK(launch_prologue(x, n, g, m->centers_d, m->weights_d, m->P, p->bump_width * p->bump_width, bin_of, slot,
+                         bin_count, g64u, gam, sm));
+  HIPCHK(launch_exscan_i32_i64(bin_count, m->bin_start, g.nbins, scan_ws, sm));
+  HIPCHK(launch_scatter(n, bin_of, slot, m->bin_start, perm_tmp, sm));
+  HIPCHK(launch_binsort(n, perm_tmp, bin_of, m->bin_start, m->perm, sm));
+  HIPCHK(launch_gather_points(n, dim, x, m->perm, bin_of, g64u, gam, m->pts32, m->pts64, m->x64, m->g64,
+                              m->binid, sm));
+
+  // 4. count pass, row pointers, fill pass
+  AssembleArgs aa{};
+  aa.pts32 = m->pts32;
+  aa.pts64 = m->pts64;
+  aa.g64 = m->g64;
+  aa.binid = m->binid;
+  aa.bin_start = m->bin_start;
+  aa.grid = g;
+  aa.n = n;
+  aa.radius = p->radius;
+  aa.r2 = p->radius * p->radius;
+  aa.inv_r2 = 1.0 / aa.r2;
+  aa.noise = p->noise_var;
+  aa.r2f = (float)aa.r2;
+  HIPCHK(launch_assemble_count(aa, prec, row_cnt, sm));
+  HIPCHK(launch_exscan_i32_i64(row_cnt, m->row_ptr, n, scan_ws, sm));
+  int64_t nnz = 0;
+  st = readback(ctx, m->row_ptr + n, sizeof(int64_t), &nnz);
+  if (st) return st;
+  m->nnz = nnz;
+  m->col = own<int32_t>(m, nnz);
+  m->val = prec == GP2S_MIXED ? (void*)own<float>(m, nnz) : (void*)own<double>(m, nnz);
+  OOMCHK(m->col);
+  OOMCHK(m->val);
+  HIPCHK(launch_assemble_fill(aa, prec, m->row_ptr, m->col, m->val, m->diag, sm));
+  int32_t* bad = nonfinite;
+  HIPCHK(hipMemsetAsync(bad, 0, sizeof(int32_t), sm));
+  HIPCHK(launch_dinv(n, m->diag, m->dinv, bad, sm));
+  int32_t hb = 0;
+  st = readback(ctx, bad, sizeof(int32_t), &hb);
+  if (st) return st;
+  m->diag_ok = hb == 0;
+  HIPCHK(hipStreamSynchronize(sm));
+  guard.keep = true;
+  *out = m;
+  return GP2S_OK;
+}
+
+gp2s_status gp2s_matrix_info(gp2s_matrix m, int64_t* n, int64_t* nnz, gp2s_precision* prec) {
+  if (!m) return GP2S_E_INVALID;
+  if (n) *n = m->n;
+  if (nnz) *nnz = m->nnz;
+  if (prec) *prec = m->prec;
+  return GP2S_OK;
+}
+
+gp2s_status gp2s_matrix_export(gp2s_ctx ctx, gp2s_matrix m, int64_t* row_ptr, int32_t* col, void* val,
+                               int32_t* perm) {
+  if (!ctx) return GP2S_E_INVALID;
+  gp2s_status st = check_matrix(ctx, m);
+  if (st) return st;
+  st = ensure_device(ctx);
+  if (st) return st;
+  hipStream_t sm = ctx->stream;
+  if (row_ptr) HIPCHK(hipMemcpyAsync(row_ptr, m->row_ptr, (m->n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, sm));
+  if (col) HIPCHK(hipMemcpyAsync(col, m->col, m->nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, sm));
+  if (val)
+    HIPCHK(hipMemcpyAsync(val, m->val, m->nnz * (m->prec == GP2S_MIXED ? sizeof(float) : sizeof(double)),
+                          hipMemcpyDeviceToDevice, sm));
+  if (perm) {
+    if (m->perm) HIPCHK(hipMemcpyAsync(perm, m->perm, m->n * sizeof(int32_t), hipMemcpyDeviceToDevice, sm));
+    else return fail(ctx, GP2S_E_INVALID, "imported handles have no permutation");
+  }
+  HIPCHK(hipStreamSynchronize(sm));
+  return GP2S_OK;
+}
+
+gp2s_status gp2s_matrix_import(gp2s_ctx ctx, int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col,
+                               const void* val, gp2s_precision prec, gp2s_matrix* out) {
+  if (!ctx) return GP2S_E_INVALID;
+  if (!out) return fail(ctx, GP2S_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || n >= (int64_t)INT32_MAX) return fail(ctx, GP2S_E_INVALID, "n must be in [1, 2^31 - 1)");
+  if (nnz < n) return fail(ctx, GP2S_E_INVALID, "nnz must be >= n (the diagonal is required)");
+  if (!row_ptr || !col || !val) return fail(ctx, GP2S_E_INVALID, "CSR arrays must be non-NULL");
+  if (prec != GP2S_FP64 && prec != GP2S_MIXED) return fail(ctx, GP2S_E_INVALID, "unknown precision");
+  gp2s_status st = ensure_device(ctx);
+  if (st) return st;
+  gp2s_matrix m = new (std::nothrow) gp2s_matrix_s();
+  if (!m) return fail(ctx, GP2S_E_OOM, "host allocation failed");
+  struct Guard {
+    gp2s_matrix m;
+    bool keep = false;
+    ~Guard() {
+      if (!keep) gp2s_matrix_free(m);
+    }
+  } guard{m};
+  m->ctx = ctx;
+  m->n = n;
+  m->nnz = nnz;
+  m->prec = prec;
+  m->assembled = false;
+  const size_t vb = prec == GP2S_MIXED ? sizeof(float) : sizeof(double);
+  m->row_ptr = own<int64_t>(m, n + 1);
+  m->col = own<int32_t>(m, nnz);
+  m->val = own<uint8_t>(m, nnz * vb);
+  m->diag = own<double>(m, n);
+  m->dinv = own<double>(m, n);
+  OOMCHK(m->row_ptr);
+  OOMCHK(m->col);
+  OOMCHK(m->val);
+  OOMCHK(m->diag);
+  OOMCHK(m->dinv);
+  hipStream_t sm = ctx->stream;
+  HIPCHK(hipMemcpyAsync(m->row_ptr, row_ptr, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, sm));
+  HIPCHK(hipMemcpyAsync(m->col, col, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, sm));
+  HIPCHK(hipMemcpyAsync(m->val, val, nnz * vb, hipMemcpyDeviceToDevice, sm));
+  Scratch sc(ctx);
+  int32_t* bad = sc.get<int32_t>(2);
+  if (sc.oom) return fail(ctx, GP2S_E_OOM, "import workspace allocation failed");
+  HIPCHK(hipMemsetAsync(bad, 0, 2 * sizeof(int32_t), sm));
+  HIPCHK(launch_extract_diag(n, nnz, m->row_ptr, m->col, m->val, prec, m->diag, bad + 1, sm));
+  HIPCHK(launch_dinv(n, m->diag, m->dinv, bad, sm));
+  int32_t hb[2] = {0, 0};
+  st = readback(ctx, bad, sizeof(hb), hb);
+  if (st) return st;
+  if (hb[1]) return fail(ctx, GP2S_E_INVALID, "invalid CSR: a row lacks its diagonal, a column index is out of range or not ascending, or row_ptr is inconsistent");
+  m->diag_ok = hb[0] == 0;
+  guard.keep = true;
+  *out = m;
+  return GP2S_OK;
+}
+
+gp2s_status gp2s_matrix_free(gp2s_matrix m) {
+  if (!m) return GP2S_E_INVALID;
+  if (m->ctx) {
+    if (!m->owned.empty()) (void)hipStreamSynchronize(m->ctx->stream);
+    for (void* q : m->owned) dfree(m->ctx, q);
+  }
+  delete m;
+  return GP2S_OK;
+}
+
+gp2s_status gp2s_spmv(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X, double* Y) {
+  if (!ctx) return GP2S_E_INVALID;
+  gp2s_status st = check_matrix(ctx, m);
+  if (st) return st;
+  if (nrhs < 1 || nrhs > kMaxProbes) return fail(ctx, GP2S_E_INVALID, "nrhs must be in [1, %d]", kMaxProbes);
+  if (!X || !Y) return fail(ctx, GP2S_E_INVALID, "X and Y must be non-NULL");
+  st = ensure_device(ctx);
+  if (st) return st;
+  const int64_t n = m->n;
+  Scratch sc(ctx);
+  double* Xi = sc.get<double>((size_t)n * nrhs);
+  double* Yi = sc.get<double>((size_t)n * nrhs);
+  if (sc.oom) return fail(ctx, GP2S_E_OOM, "spmv workspace allocation failed");
+  HIPCHK(launch_gather_rows(n, nrhs, m->perm, X, Xi, ctx->stream));
+  if (nrhs == 1)
+    HIPCHK(launch_spmv(m->prec, m->row_ptr, m->col, m->val, n, (double)m->nnz / n, Xi, Yi, ctx->stream));
+  else
+    HIPCHK(launch_spmm(m->prec, m->row_ptr, m->col, m->val, n, nrhs, Xi, Yi, ctx->stream));
+  HIPCHK(launch_scatter_rows(n, nrhs, m->perm, Yi, Y, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return GP2S_OK;
+}
+
+gp2s_status gp2s_solve(gp2s_ctx ctx, gp2s_matrix m, const double* y, double* a, const gp2s_solve_opts* o,
+                       gp2s_report* rep) {
+  if (!ctx) return GP2S_E_INVALID;
+  gp2s_status st = check_matrix(ctx, m);
+  if (st) return st;
+  st = check_opts(ctx, o, false);
+  if (st) return st;
+  if (!y || !a) return fail(ctx, GP2S_E_INVALID, "y and a must be non-NULL");
+  st = ensure_device(ctx);
+  if (st) return st;
+  const int64_t n = m->n;
+  Scratch sc(ctx);
+  double* yi = sc.get<double>(n);
+  double* ai = sc.get<double>(n);
+  double* red = sc.get<double>(1 + kReduceBlocks);
+  uint32_t* tk = sc.get<uint32_t>(1);
+  if (sc.oom) return fail(ctx, GP2S_E_OOM, "solve workspace allocation failed");
+  HIPCHK(hipMemsetAsync(tk, 0, sizeof(uint32_t), ctx->stream));
+  HIPCHK(launch_gather_rows(n, 1, m->perm, y, yi, ctx->stream));
+  gp2s_report local{};
+  gp2s_report* r = rep ? rep : &local;
+  std::memset(r, 0, sizeof(*r));
+  bool conv = false;
+  st = solve_internal(ctx, m, yi, ai, o, sc, r, &conv);
+  if (st) return st;
+  double yTa = 0.0;
+  st = dot_host(ctx, n, yi, ai, red, tk, &yTa);
+  if (st) return st;
+  r->yTa = yTa;
+  HIPCHK(launch_scatter_rows(n, 1, m->perm, ai, a, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (!conv) return fail(ctx, GP2S_E_NOCONV, "CG did not reach tol within max_iter / max_ir");
+  return GP2S_OK;
+}
+
+gp2s_status gp2s_lml(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_solve_opts* o, double* a,
+                     gp2s_report* rep) {
+  return lml_common(ctx, m, y, o, a, rep, nullptr);
+}
+
+gp2s_status gp2s_lml_grad(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_solve_opts* o, double* a,
+                          gp2s_report* rep, double* grad) {
+  if (ctx && !grad) return fail(ctx, GP2S_E_INVALID, "grad is NULL");
+  return lml_common(ctx, m, y, o, a, rep, grad);
+}
+
+}  // extern "C"

@@ -1,0 +1,224 @@
+// Covariance assembly: pair culling, kernel evaluation and stream compaction into CSR.
+//
+// K_ij = g_i g_j W(||x_i - x_j|| / r) + sigma_n^2 [i == j], W(rho) = (1 - rho)^4 (4 rho + 1)
+// for rho < 1 (Sec. 3.1 product construction with a C^2 Wendland member; Sec. 3.3
+// bump mask g). The paper computes dense block pairs and keeps the non-zeros
+// (Sec. 3.5, App. B.7); here only candidates from the 3^d neighbouring bins are
+// tested, and a pair is stored when ||x_i - x_j|| < r and both points lie inside
+// some bump (the diagonal always).
+//
+// One wavefront owns one row. Lanes take consecutive candidates of a neighbour-bin
+// run (bins adjacent along x are contiguous in the sorted order), test them, and the
+// wave ballot plus the lane's popcount prefix (mbcnt) give every survivor its slot,
+// so each row is written as one contiguous, ascending, coalesced run. The count
+// pass and the fill pass execute the same candidate sequence and the same test.
+//
+// Float32 path: the support test uses float32 distances. Entry values use the
+// float64 squared distance (exact for float32 coordinates) to form t = 1 - rho^2
+// without cancellation, then 1 - rho = t / (1 + rho) and the polynomial in float32.
+#include "gp2s_internal.h"
+
+namespace gp2s {
+
+// Workgroups are dispatched round-robin over the 8 XCDs; remap so that consecutive
+// rows (which share neighbour bins) land on the same XCD and its L2.
+__device__ inline int64_t xcd_block(int64_t nblocks_padded) {
+  int64_t b = blockIdx.x;
+  int64_t per = nblocks_padded / 8;
+  return (b % 8) * per + b / 8;
+}
+
+__device__ inline uint32_t lane_prefix(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+template <int DIM>
+__device__ inline void decode_bin(int32_t b, const GridDev& g, int& bx, int& by, int& bz) {
+  bx = b % g.nb[0];
+  int t = b / g.nb[0];
+  if (DIM == 3) {
+    by = t % g.nb[1];
+    bz = t / g.nb[1];
+  } else {
+    by = t;
+    bz = 0;
+  }
+}
+
+// Squared distances for the support test. Explicit rounding intrinsics fix the
+// evaluation order, so the count pass and the fill pass (separate instantiations)
+// take bitwise the same decision, and K stays symmetric: swapping i and j only
+// negates the differences.
+template <int DIM>
+__device__ inline float sqdist_f32(const float4& a, const float4& b) {
+  const float dx = a.x - b.x, dy = a.y - b.y;
+  float d2 = __fmaf_rn(dy, dy, __fmul_rn(dx, dx));
+  if (DIM == 3) {
+    const float dz = a.z - b.z;
+    d2 = __fmaf_rn(dz, dz, d2);
+  }
+  return d2;
+}
+template <int DIM>
+__device__ inline double sqdist_f64(const double4& a, const double4& b) {
+  const double dx = a.x - b.x, dy = a.y - b.y;
+  double d2 = __fma_rn(dy, dy, __dmul_rn(dx, dx));
+  if (DIM == 3) {
+    const double dz = a.z - b.z;
+    d2 = __fma_rn(dz, dz, d2);
+  }
+  return d2;
+}
+
+// Float32 entry value for a surviving off-diagonal pair.
+__device__ inline float entry_f32(const float4& pi, const float4& pj, double r2, double inv_r2) {
+  double dx = (double)pi.x - (double)pj.x;
+  double dy = (double)pi.y - (double)pj.y;
+  double dz = (double)pi.z - (double)pj.z;
+  double d2 = dx * dx + dy * dy + dz * dz;
+  float t = (float)((r2 - d2) * inv_r2);          // 1 - rho^2, accurate near rho -> 1
+  t = fmaxf(t, 0.0f);
+  float rho = __builtin_amdgcn_sqrtf((float)(d2 * inv_r2));
+  float om = t * __builtin_amdgcn_rcpf(1.0f + rho);  // 1 - rho
+  float om2 = om * om;
+  return pi.w * pj.w * (om2 * om2 * (4.0f * rho + 1.0f));
+}
+
+__device__ inline double entry_f64(const double4& pi, const double4& pj, double r2, double inv_r2) {
+  double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+  double d2 = dx * dx + dy * dy + dz * dz;
+  double t = fmax((r2 - d2) * inv_r2, 0.0);
+  double rho = sqrt(d2 * inv_r2);
+  double om = t / (1.0 + rho);
+  double om2 = om * om;
+  return pi.w * pj.w * (om2 * om2 * (4.0 * rho + 1.0));
+}
+
+template <int DIM, bool FILL, bool F32>
+__global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs a, int64_t nblocks_padded,
+                                                     int32_t* __restrict__ row_cnt,
+                                                     const int64_t* __restrict__ row_ptr,
+                                                     int32_t* __restrict__ col, void* __restrict__ val,
+                                                     double* __restrict__ diag) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t lb = xcd_block(nblocks_padded);
+  const int64_t row = lb * (kBlock / kWave) + threadIdx.x / kWave;
+  if (row >= a.n) return;  // uniform per wave
+
+  float4 pi32;
+  double4 pi64;
+  bool in_i;
+  if (F32) {
+    pi32 = a.pts32[row];
+    in_i = pi32.w >= 0.0f;
+  } else {
+    pi64 = a.pts64[row];
+    in_i = pi64.w >= 0.0;
+  }
+  const int64_t base = FILL ? row_ptr[row] : 0;
+  const int64_t end = FILL ? row_ptr[row + 1] : 0;
+  if (!in_i) {
+    // Outside every bump: g_i = 0, only the noise on the diagonal is stored.
+    if (lane == 0) {
+      if (FILL) {
+        col[base] = (int32_t)row;
+        double d = a.noise;
+        if (F32) {
+          float v = (float)d;
+          static_cast<float*>(val)[base] = v;
+          diag[row] = (double)v;
+        } else {
+          static_cast<double*>(val)[base] = d;
+          diag[row] = d;
+        }
+      } else {
+        row_cnt[row] = 1;
+      }
+    }
+    return;
+  }
+  int bx, by, bz;
+  decode_bin<DIM>(a.binid[row], a.grid, bx, by, bz);
+  const int nbx = a.grid.nb[0], nby = a.grid.nb[1], nbz = a.grid.nb[2];
+  const int x0 = bx > 0 ? bx - 1 : 0;
+  const int x1 = bx + 1 < nbx ? bx + 1 : nbx - 1;
+  int64_t cnt = 0;
+  const double gi64 = a.g64[row];
+
+  for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
+    const int zz = bz + dz;
+    if (zz < 0 || zz >= nbz) continue;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int yy = by + dy;
+      if (yy < 0 || yy >= nby) continue;
+      const int64_t rb = ((int64_t)zz * nby + yy) * nbx;
+      const int64_t s = a.bin_start[rb + x0];
+      const int64_t e = a.bin_start[rb + x1 + 1];
+      for (int64_t c = s; c < e; c += kWave) {
+        const int64_t j = c + lane;
+        const bool ok = j < e;
+        bool pass;
+        float4 pj32;
+        double4 pj64;
+        if (F32) {
+          pj32 = ok ? a.pts32[j] : make_float4(0.f, 0.f, 0.f, -1.f);
+          pass = ok && (j == row || (pj32.w >= 0.0f && sqdist_f32<DIM>(pi32, pj32) < a.r2f));
+        } else {
+          pj64 = ok ? a.pts64[j] : make_double4(0., 0., 0., -1.);
+          pass = ok && (j == row || (pj64.w >= 0.0 && sqdist_f64<DIM>(pi64, pj64) < a.r2));
+        }
+        const uint64_t m = __ballot(pass);
+        const int64_t pos = base + cnt + lane_prefix(m);
+        if (FILL && pass && pos < end) {  // never past the row counted by the first pass
+          col[pos] = (int32_t)j;
+          if (F32) {
+            float v = (j == row) ? (float)(gi64 * gi64 + a.noise) : entry_f32(pi32, pj32, a.r2, a.inv_r2);
+            static_cast<float*>(val)[pos] = v;
+            if (j == row) diag[row] = (double)v;
+          } else {
+            double v = (j == row) ? gi64 * gi64 + a.noise : entry_f64(pi64, pj64, a.r2, a.inv_r2);
+            static_cast<double*>(val)[pos] = v;
+            if (j == row) diag[row] = v;
+          }
+        }
+        cnt += __popcll(m);
+      }
+    }
+  }
+  if (!FILL && lane == 0) row_cnt[row] = (int32_t)cnt;
+}
+
+template <bool FILL>
+static hipError_t launch_assemble_t(const AssembleArgs& a, int prec, int32_t* row_cnt,
+                                    const int64_t* row_ptr, int32_t* col, void* val, double* diag,
+                                    hipStream_t st) {
+  const int rows_per_block = kBlock / kWave;
+  int64_t nblocks = (a.n + rows_per_block - 1) / rows_per_block;
+  int64_t padded = (nblocks + 7) / 8 * 8;
+  dim3 grid((unsigned)padded), block(kBlock);
+  const bool f32 = prec == GP2S_MIXED;
+  if (a.grid.dim == 2) {
+    if (f32)
+      hipLaunchKernelGGL((k_assemble<2, FILL, true>), grid, block, 0, st, a, padded, row_cnt, row_ptr, col, val, diag);
+    else
+      hipLaunchKernelGGL((k_assemble<2, FILL, false>), grid, block, 0, st, a, padded, row_cnt, row_ptr, col, val, diag);
+  } else {
+    if (f32)
+      hipLaunchKernelGGL((k_assemble<3, FILL, true>), grid, block, 0, st, a, padded, row_cnt, row_ptr, col, val, diag);
+    else
+      hipLaunchKernelGGL((k_assemble<3, FILL, false>), grid, block, 0, st, a, padded, row_cnt, row_ptr, col, val, diag);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble_count(const AssembleArgs& a, int prec, int32_t* row_cnt, hipStream_t st) {
+  return launch_assemble_t<false>(a, prec, row_cnt, nullptr, nullptr, nullptr, nullptr, st);
+}
+
+hipError_t launch_assemble_fill(const AssembleArgs& a, int prec, const int64_t* row_ptr,
+                                int32_t* col, void* val, double* diag, hipStream_t st) {
+  return launch_assemble_t<true>(a, prec, nullptr, row_ptr, col, val, diag, st);
+}
+
+}  // namespace gp2s

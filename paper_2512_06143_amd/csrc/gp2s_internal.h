@@ -1,0 +1,150 @@
+// Internal declarations shared by the HIP kernels and the host runtime of libgp2s.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "gp2s.h"
+
+namespace gp2s {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kBlock = 256;        // threads per workgroup for streaming kernels
+constexpr int kMaxProbes = 64;     // one probe per lane in the block kernels
+constexpr int kMaxBumps = 256;
+constexpr int kReduceBlocks = 1024;  // workgroups of the reduction-carrying kernels
+
+// Uniform grid of cubic bins with side h >= r (slightly enlarged so that rounding
+// in the bin index can never separate two points closer than r by two bins).
+struct GridDev {
+  double origin[3];
+  double inv_h;
+  int32_t nb[3];
+  int32_t dim;
+  int64_t nbins;
+};
+
+// Device-resident solver state for one block CG run over S columns.
+struct CgState {
+  double* rz;        // [S] r^T M^-1 r of the current iterate
+  double* bb;        // [S] ||b||^2
+  double* tol2;      // [S] squared relative tolerance
+  double* alpha;     // [S] step of the current iteration (0 for finished columns)
+  double* beta;      // [S]
+  double* rr;        // [S] ||r||^2 of the current iterate
+  int32_t* done;     // [S] 1 once a column has converged
+  int32_t* iters;    // [S] iterations performed per column
+  int32_t* flags;    // [4] 0: not-SPD, 1: number of unfinished columns, 2: nonfinite
+  double* partial;   // [kReduceBlocks * S * 2] per-workgroup partial sums
+  uint32_t* ticket;  // [2] last-workgroup detection counters
+  double* hist_a;    // [max_iter * S] alpha history (Lanczos coefficients), or null
+  double* hist_b;    // [max_iter * S] beta history, or null
+  int32_t max_hist;
+};
+
+// ---- kernel launchers (defined in the .hip files) ---------------------------------
+// prologue.hip
+hipError_t launch_bbox(const double* x, int64_t n, int dim, double* part, int32_t* nonfinite,
+                       int nblocks, hipStream_t st);
+hipError_t launch_prologue(const double* x, int64_t n, const GridDev& g, const double* centers,
+                           const double* weights, int P, double bump_w2, int32_t* bin_of,
+                           int32_t* slot, int32_t* bin_count, double* g64_user, uint8_t* gam,
+                           hipStream_t st);
+hipError_t launch_scatter(int64_t n, const int32_t* bin_of, const int32_t* slot,
+                          const int64_t* bin_start, int32_t* perm_tmp, hipStream_t st);
+hipError_t launch_binsort(int64_t n, const int32_t* perm_tmp, const int32_t* bin_of,
+                          const int64_t* bin_start, int32_t* perm, hipStream_t st);
+hipError_t launch_gather_points(int64_t n, int dim, const double* x, const int32_t* perm,
+                                const int32_t* bin_of, const double* g64_user, const uint8_t* gam,
+                                float4* pts32, double4* pts64, double* x64, double* g64,
+                                int32_t* binid, hipStream_t st);
+hipError_t launch_probe_masks(int64_t n, const int32_t* perm, uint64_t seed, int S, uint64_t* mask,
+                              hipStream_t st);
+
+// scan.hip: exclusive prefix sum of int32 counts into int64 offsets (out has n+1 entries).
+size_t scan_workspace_bytes(int64_t n);
+hipError_t launch_exscan_i32_i64(const int32_t* in, int64_t* out, int64_t n, void* ws,
+                                 hipStream_t st);
+hipError_t launch_i64_to_i32(const int64_t* in, int32_t* out, int64_t n, hipStream_t st);
+
+// assemble.hip
+struct AssembleArgs {
+  const float4* pts32;
+  const double4* pts64;
+  const double* g64;
+  const int32_t* binid;
+  const int64_t* bin_start;
+  GridDev grid;
+  int64_t n;
+  double radius, r2, inv_r2, noise;
+  float r2f;
+};
+hipError_t launch_assemble_count(const AssembleArgs& a, int prec, int32_t* row_cnt, hipStream_t st);
+hipError_t launch_assemble_fill(const AssembleArgs& a, int prec, const int64_t* row_ptr,
+                                int32_t* col, void* val, double* diag, hipStream_t st);
+
+// spmv.hip
+hipError_t launch_spmv(int prec, const int64_t* rp, const int32_t* col, const void* val,
+                       int64_t n, double mean_row, const double* x, double* y, hipStream_t st);
+hipError_t launch_spmm(int prec, const int64_t* rp, const int32_t* col, const void* val,
+                       int64_t n, int S, const double* X, double* Y, hipStream_t st);
+// CG product step: Q = K P plus p^T q per column, then alpha = rz / p^T q.
+hipError_t launch_cg_matvec(int prec, const int64_t* rp, const int32_t* col, const void* val,
+                            int64_t n, int S, double mean_row, const double* P, double* Q,
+                            const CgState& cs, hipStream_t st);
+
+// pcg.hip
+hipError_t launch_cg_init(int64_t n, int S, const double* B, const double* dinv, double* X,
+                          double* R, double* P, const CgState& cs, const double* tol, hipStream_t st);
+hipError_t launch_cg_update(int64_t n, int S, double* X, double* R, const double* P,
+                            const double* Q, const double* dinv, const CgState& cs, int32_t iter,
+                            hipStream_t st);
+hipError_t launch_cg_pupdate(int64_t n, int S, double* P, const double* R, const double* dinv,
+                             const CgState& cs, hipStream_t st);
+hipError_t launch_axpy_sub(int64_t n, const double* b, const double* kx, double* r, hipStream_t st);
+hipError_t launch_add(int64_t n, double* x, const double* d, hipStream_t st);
+hipError_t launch_dot_partial(int64_t n, const double* a, const double* b, double* out,
+                              uint32_t* ticket, hipStream_t st);
+hipError_t launch_sum_log(int64_t n, const double* d, double* out, uint32_t* ticket, hipStream_t st);
+hipError_t launch_gather_rows(int64_t n, int S, const int32_t* perm, const double* src_user,
+                              double* dst_int, hipStream_t st);
+hipError_t launch_scatter_rows(int64_t n, int S, const int32_t* perm, const double* src_int,
+                               double* dst_user, hipStream_t st);
+hipError_t launch_probe_rhs(int64_t n, int S, const uint64_t* mask, const double* diag, double* B,
+                            hipStream_t st);
+hipError_t launch_dinv(int64_t n, const double* diag, double* dinv, int32_t* bad, hipStream_t st);
+hipError_t launch_extract_diag(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col, const void* val, int prec,
+                               double* diag, int32_t* bad, hipStream_t st);
+hipError_t launch_check_finite(int64_t n, const double* v, int32_t* flag, hipStream_t st);
+
+// slq.hip: per-probe e1^T ln(T) e1 from the CG coefficients.
+// work: 2 * S * max_m doubles, max_m >= every iters[s].
+hipError_t launch_slq_ws(int S, const double* hist_a, const double* hist_b, const int32_t* iters,
+                         double* work, int64_t max_m, double* out, hipStream_t st);
+
+// backward.hip
+struct BackwardArgs {
+  const int64_t* rp;
+  const int32_t* col;
+  const float4* pts32;
+  const double4* pts64;
+  const double* g64;
+  const double* a;        // [n] K^-1 y (internal order)
+  const double* Q;        // [n * S] probe solutions (internal order)
+  const uint64_t* mask;   // [n] probe sign bits
+  const double* dinv;     // [n] 1 / K_ii
+  int64_t n;
+  int S;
+  double radius, r2, inv_r2;
+};
+hipError_t launch_backward_rows(const BackwardArgs& b, int prec, double* Rrow, double* Trow,
+                                double* Urow, hipStream_t st);
+hipError_t launch_grad_reduce(int64_t n, int dim, int P, int S, const double* x64, const double* g64,
+                              const double* a, const double* Rrow, const double* Trow,
+                              const double* Urow, const double* centers, double bump_w2,
+                              double* partial, uint32_t* ticket, double* grad, hipStream_t st);
+
+}  // namespace gp2s

@@ -1,0 +1,224 @@
+// Per-point prologue and spatial binning (counting sort into a cell list).
+//
+// The paper evaluates every covariance entry in dense blocks (Sec. 3.5, App. B.7).
+// Here the support of the kernel is known before evaluation: W vanishes beyond r
+// (Sec. 3.1) and the bump mask vanishes outside every bump (Sec. 3.3). Points are
+// therefore sorted into bins of side >= r so that each row only tests the points of
+// its 3^d neighbouring bins.
+#include "gp2s_internal.h"
+
+namespace gp2s {
+
+// Bounding box and finiteness of the points. part[b*6 + k] = min of coordinate k,
+// part[b*6 + 3 + k] = max, over the points handled by workgroup b.
+__global__ __launch_bounds__(kBlock) void k_bbox(const double* __restrict__ x, int64_t n, int dim,
+                                                 double* __restrict__ part,
+                                                 int32_t* __restrict__ nonfinite) {
+  __shared__ double smin[3][kBlock];
+  __shared__ double smax[3][kBlock];
+  double lo[3] = {INFINITY, INFINITY, INFINITY};
+  double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bool bad = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    for (int k = 0; k < dim; ++k) {
+      double v = x[i * dim + k];
+      if (!isfinite(v)) bad = true;
+      lo[k] = fmin(lo[k], v);
+      hi[k] = fmax(hi[k], v);
+    }
+  }
+  if (bad) atomicOr(nonfinite, 1);
+  for (int k = 0; k < 3; ++k) {
+    smin[k][threadIdx.x] = lo[k];
+    smax[k][threadIdx.x] = hi[k];
+  }
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      for (int k = 0; k < 3; ++k) {
+        smin[k][threadIdx.x] = fmin(smin[k][threadIdx.x], smin[k][threadIdx.x + s]);
+        smax[k][threadIdx.x] = fmax(smax[k][threadIdx.x], smax[k][threadIdx.x + s]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 3; ++k) {
+      part[blockIdx.x * 6 + k] = smin[k][0];
+      part[blockIdx.x * 6 + 3 + k] = smax[k][0];
+    }
+  }
+}
+
+hipError_t launch_bbox(const double* x, int64_t n, int dim, double* part, int32_t* nonfinite,
+                       int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_bbox, dim3(nblocks), dim3(kBlock), 0, st, x, n, dim, part, nonfinite);
+  return hipGetLastError();
+}
+
+__device__ inline int32_t bin_coord(double v, double o, double inv_h, int32_t nb) {
+  double f = floor((v - o) * inv_h);
+  int32_t c = (int32_t)fmax(0.0, fmin(f, (double)(nb - 1)));
+  return c;
+}
+
+// Bin index, bump mask g (float64) and support flag gamma of every point (user order).
+// g_i = sum_k a_k exp(1 - 1/(1 - s_ik)), s_ik = ||x_i - c_k||^2 / w^2, for s_ik < 1
+// (Sec. 3.3, Eq. bump with shape parameter 1; g a sum of P bumps). gamma_i marks a
+// point strictly inside at least one bump; the pattern uses gamma, not g != 0.
+__global__ __launch_bounds__(kBlock) void k_prologue(const double* __restrict__ x, int64_t n,
+                                                     GridDev g, const double* __restrict__ centers,
+                                                     const double* __restrict__ weights, int P,
+                                                     double bump_w2, int32_t* __restrict__ bin_of,
+                                                     int32_t* __restrict__ slot,
+                                                     int32_t* __restrict__ bin_count,
+                                                     double* __restrict__ g64_user,
+                                                     uint8_t* __restrict__ gam) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int dim = g.dim;
+  double xi[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < dim; ++k) xi[k] = x[i * dim + k];
+  int64_t b = 0;
+  for (int k = dim - 1; k >= 0; --k) b = b * g.nb[k] + bin_coord(xi[k], g.origin[k], g.inv_h, g.nb[k]);
+  double gsum = 0.0;
+  bool inside = false;
+  for (int p = 0; p < P; ++p) {
+    double d2 = 0.0;
+    for (int k = 0; k < dim; ++k) {
+      double d = xi[k] - centers[p * dim + k];
+      d2 += d * d;
+    }
+    if (d2 < bump_w2) {
+      inside = true;
+      double s = d2 / bump_w2;
+      gsum += weights[p] * exp(1.0 - 1.0 / (1.0 - s));
+    }
+  }
+  bin_of[i] = (int32_t)b;
+  slot[i] = atomicAdd(&bin_count[b], 1);
+  g64_user[i] = inside ? gsum : 0.0;
+  gam[i] = inside ? 1 : 0;
+}
+
+hipError_t launch_prologue(const double* x, int64_t n, const GridDev& g, const double* centers,
+                           const double* weights, int P, double bump_w2, int32_t* bin_of,
+                           int32_t* slot, int32_t* bin_count, double* g64_user, uint8_t* gam,
+                           hipStream_t st) {
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_prologue, dim3((unsigned)blocks), dim3(kBlock), 0, st, x, n, g, centers,
+                     weights, P, bump_w2, bin_of, slot, bin_count, g64_user, gam);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter(int64_t n, const int32_t* __restrict__ bin_of,
+                                                    const int32_t* __restrict__ slot,
+                                                    const int64_t* __restrict__ bin_start,
+                                                    int32_t* __restrict__ perm_tmp) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  perm_tmp[bin_start[bin_of[i]] + slot[i]] = (int32_t)i;
+}
+
+hipError_t launch_scatter(int64_t n, const int32_t* bin_of, const int32_t* slot,
+                            const int64_t* bin_start, int32_t* perm_tmp, hipStream_t st) {
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(kBlock), 0, st, n, bin_of, slot,
+                     bin_start, perm_tmp);
+  return hipGetLastError();
+}
+
+// The atomic slots give an arbitrary order inside a bin. Make it deterministic:
+// the final position of a point is its bin start plus the number of points of the
+// same bin with a smaller user index (a stable counting sort by (bin, user index)).
+__global__ __launch_bounds__(kBlock) void k_binsort(int64_t n, const int32_t* __restrict__ perm_tmp,
+                                                    const int32_t* __restrict__ bin_of,
+                                                    const int64_t* __restrict__ bin_start,
+                                                    int32_t* __restrict__ perm) {
+  int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int32_t me = perm_tmp[p];
+  int32_t b = bin_of[me];
+  int64_t s = bin_start[b], e = bin_start[b + 1];
+  int64_t rank = 0;
+  for (int64_t q = s; q < e; ++q) rank += (perm_tmp[q] < me) ? 1 : 0;
+  perm[s + rank] = me;
+}
+
+hipError_t launch_binsort(int64_t n, const int32_t* perm_tmp, const int32_t* bin_of,
+                            const int64_t* bin_start, int32_t* perm, hipStream_t st) {
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_binsort, dim3((unsigned)blocks), dim3(kBlock), 0, st, n, perm_tmp, bin_of,
+                     bin_start, perm);
+  return hipGetLastError();
+}
+
+// Internal-order copies: float point + g (or -1 for points outside every bump) for
+// the float32 path, the same in float64 for the float64 path, float64 coordinates
+// for the gradient, g in float64, and the bin index.
+__global__ __launch_bounds__(kBlock) void k_gather_points(
+    int64_t n, int dim, const double* __restrict__ x, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ bin_of, const double* __restrict__ g64_user,
+    const uint8_t* __restrict__ gam, float4* __restrict__ pts32, double4* __restrict__ pts64,
+    double* __restrict__ x64, double* __restrict__ g64, int32_t* __restrict__ binid) {
+  int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int32_t u = perm[p];
+  double c[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < dim; ++k) {
+    c[k] = x[(int64_t)u * dim + k];
+    x64[p * dim + k] = c[k];
+  }
+  double gv = g64_user[u];
+  bool in = gam[u] != 0;
+  if (pts32) pts32[p] = make_float4((float)c[0], (float)c[1], (float)c[2], in ? (float)gv : -1.0f);
+  if (pts64) pts64[p] = make_double4(c[0], c[1], c[2], in ? gv : -1.0);
+  g64[p] = gv;
+  binid[p] = bin_of[u];
+}
+
+hipError_t launch_gather_points(int64_t n, int dim, const double* x, const int32_t* perm,
+                                const int32_t* bin_of, const double* g64_user, const uint8_t* gam,
+                                float4* pts32, double4* pts64, double* x64, double* g64,
+                                int32_t* binid, hipStream_t st) {
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_gather_points, dim3((unsigned)blocks), dim3(kBlock), 0, st, n, dim, x, perm,
+                     bin_of, g64_user, gam, pts32, pts64, x64, g64, binid);
+  return hipGetLastError();
+}
+
+// Rademacher probe signs from counter-based SplitMix64 (Steele, Lea and Flood, 2014):
+// output k of the stream seeded with `seed` is mix(seed + (k + 1) * 0x9E3779B97F4A7C15);
+// probe s at user point u uses k = s * 2^40 + u and is negative when bit 63 is set.
+// mask[p] holds the sign bits of all probes for internal point p.
+__device__ inline uint64_t splitmix_at(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(kBlock) void k_probe_masks(int64_t n, const int32_t* __restrict__ perm,
+                                                        uint64_t seed, int S,
+                                                        uint64_t* __restrict__ mask) {
+  int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  uint64_t u = perm ? (uint64_t)perm[p] : (uint64_t)p;
+  uint64_t m = 0;
+  for (int s = 0; s < S; ++s) {
+    uint64_t z = splitmix_at(seed, ((uint64_t)s << 40) + u);
+    m |= (z >> 63) << s;
+  }
+  mask[p] = m;
+}
+
+hipError_t launch_probe_masks(int64_t n, const int32_t* perm, uint64_t seed, int S, uint64_t* mask,
+                              hipStream_t st) {
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_probe_masks, dim3((unsigned)blocks), dim3(kBlock), 0, st, n, perm, seed, S,
+                     mask);
+  return hipGetLastError();
+}
+
+}  // namespace gp2s

@@ -1,0 +1,291 @@
+"""ctypes binding of libgp2s (the C ABI declared in include/gp2s.h).
+
+Argument marshalling only: every step of the computation runs in the library's HIP
+kernels. Torch supplies device memory (through the library's allocator callbacks,
+which forward to torch's caching allocator) and the current stream. The functions
+keep the C names: gp2s_assemble, gp2s_spmv, gp2s_solve, gp2s_lml, gp2s_lml_grad.
+If the shared library is missing this module raises ImportError: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgp2s.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2512_06143_amd.build`")
+
+lib = ctypes.CDLL(LIB_PATH)
+
+GP2S_OK, GP2S_E_INVALID, GP2S_E_HIP, GP2S_E_OOM, GP2S_E_CAPACITY = 0, 1, 2, 3, 4
+GP2S_E_NOT_SPD, GP2S_E_NOCONV, GP2S_E_NONFINITE = 5, 6, 7
+GP2S_FP64, GP2S_MIXED = 0, 1
+PRECISIONS = {"fp64": GP2S_FP64, "mixed": GP2S_MIXED}
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n_bumps", ctypes.c_int32), ("radius", ctypes.c_double),
+                ("bump_width", ctypes.c_double), ("noise_var", ctypes.c_double),
+                ("centers", ctypes.POINTER(ctypes.c_double)), ("weights", ctypes.POINTER(ctypes.c_double))]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("n_probes", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("max_ir", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("seed", ctypes.c_uint64), ("tol", ctypes.c_double),
+                ("probe_tol", ctypes.c_double)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("lml", ctypes.c_double), ("logdet", ctypes.c_double), ("yTa", ctypes.c_double),
+                ("resid", ctypes.c_double), ("logdet_stderr", ctypes.c_double), ("iters", ctypes.c_int32),
+                ("probe_iters", ctypes.c_int32), ("ir_steps", ctypes.c_int32), ("n_probes", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+_SIGS = {
+    "gp2s_abi_version": (_i32, []),
+    "gp2s_default_opts": (None, [ctypes.POINTER(SolveOpts)]),
+    "gp2s_status_string": (ctypes.c_char_p, [_i32]),
+    "gp2s_create": (_i32, [ctypes.POINTER(_vp), _vp, ALLOC_FN, FREE_FN, _vp]),
+    "gp2s_destroy": (_i32, [_vp]),
+    "gp2s_last_error": (ctypes.c_char_p, [_vp]),
+    "gp2s_check_params": (_i32, [_vp, _i64, ctypes.POINTER(Params)]),
+    "gp2s_assemble": (_i32, [_vp, _i64, _vp, ctypes.POINTER(Params), _i32, ctypes.POINTER(_vp)]),
+    "gp2s_matrix_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
+    "gp2s_matrix_export": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "gp2s_matrix_import": (_i32, [_vp, _i64, _i64, _vp, _vp, _vp, _i32, ctypes.POINTER(_vp)]),
+    "gp2s_matrix_free": (_i32, [_vp]),
+    "gp2s_spmv": (_i32, [_vp, _vp, _i32, _vp, _vp]),
+    "gp2s_solve": (_i32, [_vp, _vp, _vp, _vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(Report)]),
+    "gp2s_lml": (_i32, [_vp, _vp, _vp, ctypes.POINTER(SolveOpts), _vp, ctypes.POINTER(Report)]),
+    "gp2s_lml_grad": (_i32, [_vp, _vp, _vp, ctypes.POINTER(SolveOpts), _vp, ctypes.POINTER(Report),
+                             ctypes.POINTER(ctypes.c_double)]),
+}
+EXPORTED = tuple(_SIGS)
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class GP2SError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{lib.gp2s_status_string(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    lib.gp2s_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown solver option {k}")
+        setattr(o, k, v)
+    return o
+
+
+@dataclass
+class HostParams:
+    """Kernel hyperparameters (host values)."""
+    dim: int
+    radius: float
+    bump_width: float
+    noise_var: float
+    centers: np.ndarray
+    weights: np.ndarray
+
+    def to_c(self):
+        c = np.ascontiguousarray(self.centers, dtype=np.float64).reshape(-1)
+        w = np.ascontiguousarray(self.weights, dtype=np.float64).reshape(-1)
+        p = Params(int(self.dim), int(w.shape[0]), float(self.radius), float(self.bump_width),
+                   float(self.noise_var), c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                   w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        return p, (c, w)  # keep the arrays alive while p is used
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+class Context:
+    """A library context bound to a HIP stream (default: torch's current stream) whose
+    device allocations go through torch's caching allocator."""
+
+    def __init__(self, stream=None, use_torch_allocator=True):
+        import torch
+        self._torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device()) if torch.cuda.is_available() else None
+        if stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        handle = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+        if use_torch_allocator and torch.cuda.is_available():
+            dev = self.device.index
+            tstream = stream
+
+            def _alloc(nbytes, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, tstream)
+                except Exception:
+                    return None
+
+            def _free(ptr, user):
+                try:
+                    torch.cuda.caching_allocator_delete(int(ptr))
+                except Exception:
+                    pass
+
+            self._alloc, self._free = ALLOC_FN(_alloc), FREE_FN(_free)
+        else:
+            self._alloc, self._free = ALLOC_FN(), FREE_FN()
+        ctx = ctypes.c_void_p()
+        st = lib.gp2s_create(ctypes.byref(ctx), handle, self._alloc, self._free, None)
+        if st != GP2S_OK:
+            raise GP2SError(st, "gp2s_create failed")
+        self.ptr = ctx
+
+    def check(self, st):
+        if st != GP2S_OK:
+            raise GP2SError(st, lib.gp2s_last_error(self.ptr).decode())
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib.gp2s_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = None
+
+
+def default_context() -> Context:
+    global _default_ctx
+    import torch
+    if _default_ctx is None or (torch.cuda.is_available() and
+                                _default_ctx.stream != torch.cuda.current_stream()):
+        _default_ctx = Context()
+    return _default_ctx
+
+
+class Matrix:
+    """Handle to an assembled (or imported) covariance matrix."""
+
+    def __init__(self, ctx: Context, handle, params: HostParams | None, precision: int):
+        self.ctx, self.handle, self.params, self.precision = ctx, handle, params, precision
+        n, nnz, pr = _i64(), _i64(), _i32()
+        lib.gp2s_matrix_info(handle, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(pr))
+        self.n, self.nnz = n.value, nnz.value
+
+    def free(self):
+        if self.handle:
+            lib.gp2s_matrix_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def export(self):
+        """(row_ptr, col, val, perm) as device tensors, internal order."""
+        torch = self.ctx._torch
+        dev = self.ctx.device
+        rp = torch.empty(self.n + 1, dtype=torch.int64, device=dev)
+        col = torch.empty(self.nnz, dtype=torch.int32, device=dev)
+        val = torch.empty(self.nnz, dtype=torch.float32 if self.precision == GP2S_MIXED else torch.float64,
+                          device=dev)
+        perm = torch.empty(self.n, dtype=torch.int32, device=dev) if self.params is not None else None
+        self.ctx.check(lib.gp2s_matrix_export(self.ctx.ptr, self.handle, _ptr(rp), _ptr(col), _ptr(val),
+                                              _ptr(perm)))
+        return rp, col, val, perm
+
+
+def _as_dev64(t, ctx):
+    torch = ctx._torch
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.asarray(t, dtype=np.float64))
+    return t.to(device=ctx.device, dtype=torch.float64).contiguous()
+
+
+def gp2s_assemble(x, params: HostParams, precision="mixed", ctx: Context | None = None) -> Matrix:
+    ctx = ctx or default_context()
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    xd = _as_dev64(x, ctx)
+    p, keep = params.to_c()
+    h = ctypes.c_void_p()
+    ctx.check(lib.gp2s_assemble(ctx.ptr, int(xd.shape[0]), _ptr(xd), ctypes.byref(p), prec, ctypes.byref(h)))
+    return Matrix(ctx, h, params, prec)
+
+
+def gp2s_matrix_import(row_ptr, col, val, precision="fp64", ctx: Context | None = None) -> Matrix:
+    ctx = ctx or default_context()
+    torch = ctx._torch
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    rp = torch.as_tensor(row_ptr, dtype=torch.int64).to(ctx.device).contiguous()
+    cl = torch.as_tensor(col, dtype=torch.int32).to(ctx.device).contiguous()
+    vt = torch.float32 if prec == GP2S_MIXED else torch.float64
+    vl = torch.as_tensor(val).to(device=ctx.device, dtype=vt).contiguous()
+    h = ctypes.c_void_p()
+    ctx.check(lib.gp2s_matrix_import(ctx.ptr, rp.numel() - 1, cl.numel(), _ptr(rp), _ptr(cl), _ptr(vl), prec,
+                                     ctypes.byref(h)))
+    return Matrix(ctx, h, None, prec)
+
+
+def gp2s_spmv(m: Matrix, X):
+    ctx = m.ctx
+    Xd = _as_dev64(X, ctx)
+    nrhs = 1 if Xd.dim() == 1 else int(Xd.shape[1])
+    Y = ctx._torch.empty_like(Xd)
+    ctx.check(lib.gp2s_spmv(ctx.ptr, m.handle, nrhs, _ptr(Xd), _ptr(Y)))
+    return Y
+
+
+def gp2s_solve(m: Matrix, y, opts: SolveOpts | None = None):
+    ctx = m.ctx
+    yd = _as_dev64(y, ctx)
+    a = ctx._torch.empty_like(yd)
+    rep = Report()
+    o = opts or default_opts()
+    st = lib.gp2s_solve(ctx.ptr, m.handle, _ptr(yd), _ptr(a), ctypes.byref(o), ctypes.byref(rep))
+    ctx.check(st)
+    return a, rep
+
+
+def gp2s_lml(m: Matrix, y, opts: SolveOpts | None = None, want_a=True):
+    ctx = m.ctx
+    yd = _as_dev64(y, ctx)
+    a = ctx._torch.empty_like(yd) if want_a else None
+    rep = Report()
+    o = opts or default_opts()
+    ctx.check(lib.gp2s_lml(ctx.ptr, m.handle, _ptr(yd), ctypes.byref(o), _ptr(a), ctypes.byref(rep)))
+    return rep, a
+
+
+def gp2s_lml_grad(m: Matrix, y, opts: SolveOpts | None = None, want_a=True):
+    ctx = m.ctx
+    yd = _as_dev64(y, ctx)
+    a = ctx._torch.empty_like(yd) if want_a else None
+    rep = Report()
+    o = opts or default_opts()
+    P = int(m.params.weights.shape[0]) if m.params is not None else 0
+    grad = (ctypes.c_double * (P + 2))()
+    ctx.check(lib.gp2s_lml_grad(ctx.ptr, m.handle, _ptr(yd), ctypes.byref(o), _ptr(a), ctypes.byref(rep), grad))
+    return rep, np.array(grad[:], dtype=np.float64), a

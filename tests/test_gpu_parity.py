@@ -1,0 +1,133 @@
+"""HIP path vs the float64 oracle, element by element, through the C ABI.
+
+Tolerances (float32-assembled path unless stated): sparsity pattern exact except
+pairs within 1e-6 of the support boundary; K entries 1e-5 relative (float64 path
+1e-9); ||y - K a|| / ||y|| <= 1e-8 recomputed on the CPU from the exported CSR;
+the same-probe log-determinant within 1e-8 relative; the same-probe gradient within
+1e-4 relative per component (floor 1e-6 of the magnitude of its two halves).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import compare_patterns, exported_user_csr, params_of, pattern_pairs, rel_entry_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _G():
+    import paper_2512_06143_amd as G
+    return G
+
+
+CASES = {
+    "c1": lambda: workloads.make_problem("c1"),
+    "gmm3d": lambda: workloads.make_random_problem(31, 3001, 3, 0.09, n_bumps=5, bump_width=0.45, points="gmm"),
+    "ragged2d": lambda: workloads.make_random_problem(32, 1237, 2, 0.07, n_bumps=3, bump_width=0.35),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request, gpu):
+    prob = CASES[request.param]()
+    K = oracle.covariance_csr(prob.x, prob.radius, prob.bump_width, prob.centers, prob.weights, prob.noise_var)
+    _, _, gamma = oracle.bump_values(prob.x, prob.centers, prob.bump_width, prob.weights)
+    ex_pts = oracle.boundary_exempt_points(prob.x, prob.centers, prob.bump_width)
+    return request.param, prob, K, gamma, ex_pts
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_assembly_pattern_and_values(case, precision):
+    G = _G()
+    name, prob, Kref, gamma, ex_pts = case
+    m = G.gp2s_assemble(prob.x, params_of(prob), precision)
+    Kg, raw = exported_user_csr(m)
+    # columns ascending within each internal row, diagonal present
+    rp, col = raw["rp"], raw["col"]
+    for i in range(0, m.n, max(1, m.n // 500)):
+        c = col[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(c) > 0) and i in c
+    nmis, nex = compare_patterns(pattern_pairs(Kg), pattern_pairs(Kref), prob.x, prob, ex_pts)
+    print(f"[{name}/{precision}] n={m.n} nnz={m.nnz} pattern mismatches={nmis} exempt={nex}", flush=True)
+    assert nmis == 0
+    err, nsmall = rel_entry_errors(Kg, Kref)
+    tol = 1e-5 if precision == "mixed" else 1e-9
+    print(f"[{name}/{precision}] max rel K error {err:.3e} (tiny entries skipped: {nsmall})", flush=True)
+    assert err <= tol
+    # bitwise symmetry
+    D = (Kg - Kg.T).tocoo()
+    assert np.count_nonzero(D.data) == 0
+    # determinism: a second assembly is bitwise identical
+    m2 = G.gp2s_assemble(prob.x, params_of(prob), precision)
+    K2, raw2 = exported_user_csr(m2)
+    assert np.array_equal(raw["rp"], raw2["rp"]) and np.array_equal(raw["col"], raw2["col"])
+    assert np.array_equal(raw["val"], raw2["val"]) and np.array_equal(raw["perm"], raw2["perm"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("nrhs", [1, 7, 64])
+def test_spmv_matches_exported_matrix(case, precision, nrhs):
+    G = _G()
+    name, prob, Kref, gamma, ex_pts = case
+    m = G.gp2s_assemble(prob.x, params_of(prob), precision)
+    Kg, _ = exported_user_csr(m)
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((prob.n, nrhs)) if nrhs > 1 else rng.standard_normal(prob.n)
+    Y = G.gp2s_spmv(m, X).cpu().numpy()
+    ref = Kg @ X
+    np.testing.assert_allclose(Y, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    # and against the oracle's K (float32 storage effect bounded by 1e-5 relative per entry)
+    ref2 = Kref @ X
+    tol = 1e-5 if precision == "mixed" else 1e-10
+    assert np.abs(Y - ref2).max() <= tol * (abs(Kref) @ np.abs(X)).max()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_residual_and_solution(case, precision):
+    G = _G()
+    name, prob, Kref, gamma, ex_pts = case
+    m = G.gp2s_assemble(prob.x, params_of(prob), precision)
+    Kg, _ = exported_user_csr(m)
+    a, rep = G.gp2s_solve(m, prob.y, G.default_opts(tol=1e-8))
+    a = a.cpu().numpy()
+    res_cpu = oracle.residual_rel(Kg, a, prob.y)
+    res_true = oracle.residual_rel(Kref, a, prob.y)
+    print(f"[{name}/{precision}] CG iters={rep.iters} ir={rep.ir_steps} resid(stored K)={res_cpu:.3e} "
+          f"reported={rep.resid:.3e} resid(float64 K)={res_true:.3e}", flush=True)
+    assert res_cpu <= 1e-8
+    assert rep.resid == pytest.approx(res_cpu, rel=1e-3, abs=1e-12)
+    ref = oracle.lml_dense(Kg.toarray(), prob.y)
+    np.testing.assert_allclose(a, ref.a, rtol=0, atol=1e-5 * np.abs(ref.a).max())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_lml_and_gradient_same_probe(case, precision):
+    G = _G()
+    name, prob, Kref, gamma, ex_pts = case
+    S = 16
+    m = G.gp2s_assemble(prob.x, params_of(prob), precision)
+    Kg, _ = exported_user_csr(m)
+    opts = G.default_opts(n_probes=S, seed=7, tol=1e-10, probe_tol=1e-10, max_iter=40000)
+    rep, grad, a = G.gp2s_lml_grad(m, prob.y, opts)
+    Z = oracle.rademacher_probes(7, S, prob.n)
+    Kd = Kg.toarray()
+    gam_ref, terms = oracle.logdet_same_probe(Kd, Z)
+    rel = abs(rep.logdet - gam_ref) / abs(gam_ref)
+    lml_ref, parts = oracle.lml_same_probe(Kd, prob.y, Z)
+    exact = oracle.lml_dense(Kref.toarray(), prob.y)
+    print(f"[{name}/{precision}] logdet gpu={rep.logdet:.10f} oracle(same probes)={gam_ref:.10f} rel={rel:.2e} "
+          f"exact={exact.logdet:.6f} stderr={rep.logdet_stderr:.3f} iters={rep.iters}/{rep.probe_iters}",
+          flush=True)
+    assert rel <= 1e-8
+    assert abs(rep.lml - lml_ref) <= 1e-8 * abs(lml_ref)
+    assert abs(rep.logdet - exact.logdet) <= 5 * rep.logdet_stderr + 1e-6 * abs(exact.logdet)
+    gref, gparts = oracle.grad_same_probe(prob.x, prob.y, Z, prob.radius, prob.bump_width, prob.centers,
+                                          prob.weights, prob.noise_var, K=Kd)
+    scale = np.maximum(np.abs(gref), 1e-6 * (np.abs(gparts["fit"]) + 0.5 * np.abs(gparts["tau"])))
+    err = np.abs(grad - gref) / scale
+    print(f"[{name}/{precision}] grad max rel err {err.max():.2e}\n gpu={grad}\n ref={gref}", flush=True)
+    assert np.all(err <= 1e-4)
+    for k in range(len(gref)):
+        if gref[k] == 0.0:
+            assert grad[k] == 0.0
