@@ -1,0 +1,228 @@
+"""Benchmark: seconds per LML + gradient on one MI355X, plus assembly nnz/s, CG
+product bandwidth and the roofline of the dominant kernel.
+
+A step is one pass of the whole hot path over one synthetic instance whose inputs
+are already in HBM: bin + cull + assemble K, solve K a = y (Jacobi-PCG with
+refinement), probe solves + Lanczos log-determinant, LML, and the gradient kernel.
+Default workload: 10 000 000 clustered 2-D points (200-component Gaussian mixture),
+r for 50 stored entries per row, 16 bumps, 64 probes, float32 K with float64 CG.
+
+Prints one JSON line (last line of stdout).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12          # B/s, MI355X HBM3E
+PEAK_VALU_LANE = 256 * 64 * 2.4e9   # lane-instructions/s: 256 CUs x 64 lanes x 2.4 GHz
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(cat, n, nnz, S, prec):
+    """Algorithmic HBM bytes of one launch of a timed kernel category."""
+    vb = 4 if prec == "mixed" else 8
+    K = nnz * (4 + vb) + (n + 1) * 8
+    if cat == "cg_matvec_block":
+        return K + n * S * 8 * 2            # read P once, write Q
+    if cat in ("cg_matvec1", "spmv"):
+        return K + n * 8 * 2
+    if cat == "cg_update_block":
+        return n * S * 8 * 6 + n * 8        # X, R read+write; P, Q read; 1/diag
+    if cat == "cg_update1":
+        return n * 8 * 6 + n * 8
+    if cat == "cg_pupdate_block":
+        return n * S * 8 * 3 + n * 8        # R, P read; P write; 1/diag
+    if cat == "cg_pupdate1":
+        return n * 8 * 3 + n * 8
+    if cat == "asm_fill":
+        return nnz * (4 + vb)               # CSR written
+    return None
+
+
+def make_inputs(args):
+    import numpy as np
+    import workloads
+    t0 = time.perf_counter()
+    prob = workloads.make_problem(args.config, n=args.n)
+    log(f"[bench] generated {args.config}: n={prob.n} d={prob.dim} r={prob.radius:.6g} P={prob.n_bumps} "
+        f"({time.perf_counter() - t0:.1f}s)")
+    return prob
+
+
+def run_step(G, x, y, params, precision, opts):
+    m = G.gp2s_assemble(x, params, precision)
+    rep, grad, _ = G.gp2s_lml_grad(m, y, opts, want_a=False, allow_noconv=True)
+    if rep.status:
+        log(f"[bench] WARNING: CG stopped at max_iter ({precision}): y iters={rep.iters} probe iters={rep.probe_iters}")
+    n, nnz = m.n, m.nnz
+    m.free()
+    return rep, grad, n, nnz
+
+
+def cpu_baseline(prob, nnz_full, iters_y, iters_probe, S, budget_points=150_000):
+    """The oracle as it stands on a bounded sample: the points inside a square window
+    (about budget_points of them) around the densest cluster centre region of the same
+    point cloud. Times oracle.covariance_csr (assembly) and oracle.pcg_jacobi per
+    iteration, then scales by the full instance's nnz and the GPU run's iteration
+    counts (y solve + one single-RHS solve per probe). The oracle has no sparse
+    gradient, so the projection omits the backward pass (a lower bound)."""
+    import numpy as np
+    import oracle
+    x = prob.x
+    rng = np.random.default_rng(0)
+    c = x[rng.integers(0, prob.n)]
+    # window side so that it holds ~budget_points points
+    lo, hi = 1e-4, 1.0
+    for _ in range(40):
+        h = math.sqrt(lo * hi)
+        cnt = int(np.all(np.abs(x - c) <= h / 2, axis=1).sum())
+        if cnt > budget_points:
+            hi = h
+        else:
+            lo = h
+    sel = np.all(np.abs(x - c) <= lo / 2, axis=1)
+    xs, ys = x[sel], prob.y[sel]
+    t0 = time.perf_counter()
+    K = oracle.covariance_csr(xs, prob.radius, prob.bump_width, prob.centers, prob.weights, prob.noise_var)
+    t_asm = time.perf_counter() - t0
+    k_iter = 40
+    t0 = time.perf_counter()
+    oracle.pcg_jacobi(K, ys, tol=1e-300, max_iter=k_iter)
+    t_it = (time.perf_counter() - t0) / k_iter
+    scale = nnz_full / K.nnz
+    proj = t_asm * scale + t_it * scale * (iters_y + S * iters_probe)
+    return {
+        "value": proj, "unit": "s per LML+grad (projected)", "cores": 1, "kind": "oracle",
+        "sample": (f"{int(sel.sum())} points in a square window of the same cloud ({K.nnz} nnz); "
+                   f"oracle.covariance_csr {t_asm:.2f}s, oracle.pcg_jacobi {t_it * 1e3:.1f} ms/iteration; "
+                   f"scaled by nnz x{scale:.1f} and by the GPU iteration counts ({iters_y} y + {S}x{iters_probe} "
+                   f"probe); gradient pass not included"),
+        "assembly_nnz_per_s": K.nnz / t_asm,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c4")
+    ap.add_argument("--n", type=int, default=None, help="override the point count (same recipe)")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--probes", type=int, default=None)
+    ap.add_argument("--max-iter", type=int, default=40000)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--probe-tol", type=float, default=1e-5)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the float64-plain comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the multi-GPU sharding is a design note only).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2512_06143_amd as G
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    prob = make_inputs(args)
+    S = args.probes if args.probes is not None else prob.n_probes
+    x = torch.as_tensor(prob.x).cuda()
+    y = torch.as_tensor(prob.y).cuda()
+    params = G.HostParams(prob.dim, prob.radius, prob.bump_width, prob.noise_var, prob.centers, prob.weights)
+    opts = G.default_opts(n_probes=S, max_iter=args.max_iter, tol=args.tol, probe_tol=args.probe_tol,
+                          check_every=32)
+    ctx = G.default_context()
+
+    for w in range(args.warmup):
+        t0 = time.perf_counter()
+        rep, grad, n, nnz = run_step(G, x, y, params, args.precision, opts)
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {w}: {time.perf_counter() - t0:.2f}s iters y={rep.iters} probes={rep.probe_iters} "
+            f"lml={rep.lml:.6f}")
+
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        rep, grad, n, nnz = run_step(G, x, y, params, args.precision, opts)
+        log(f"[bench] step {k}: iters y={rep.iters} probes={rep.probe_iters} resid={rep.resid:.2e} "
+            f"lml={rep.lml:.6f}")
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    stats = ctx.stats()
+    ctx.set_timing(False)
+    ms_per_step = 1e3 * t_total / args.steps
+    log(f"[bench] {args.steps} step(s): {ms_per_step:.1f} ms/step; nnz={nnz} ({nnz / n:.2f}/row)")
+    for name, (ms, cnt) in stats.items():
+        if cnt:
+            log(f"[bench]   {name:18s} {ms:10.2f} ms total  {cnt:7d} launches  {ms / cnt:9.4f} ms avg")
+
+    # dominant kernel and its roofline
+    per = {k: v for k, v in stats.items() if v[1] > 0}
+    dom = max(per, key=lambda k: per[k][0])
+    ms_tot, cnt = per[dom]
+    avg_s = ms_tot / cnt / 1e3
+    b = kernel_bytes(dom, n, nnz, S if "block" in dom else 1, args.precision)
+    roof = None
+    if b is not None:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": b / avg_s / 1e9, "peak": PEAK_HBM / 1e9,
+                "unit": "GB/s", "frac": b / avg_s / PEAK_HBM, "traffic": None,
+                "bytes_per_launch": b, "avg_ms": avg_s * 1e3, "launches": cnt}
+    asm_ms = sum(stats[k][0] for k in ("asm_prep", "asm_count", "asm_fill")) / args.steps
+    mv1 = stats["cg_matvec1"]
+    spmv_gbs = (kernel_bytes("cg_matvec1", n, nnz, 1, args.precision) / (mv1[0] / mv1[1] / 1e3) / 1e9
+                if mv1[1] else None)
+    out = {
+        "metric": "s per LML+grad (K nnz/s assembled reported alongside)",
+        "value": ms_per_step / 1e3,
+        "unit": "s/(LML+grad)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 K / f64 CG" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"{args.config}: {n} clustered {prob.dim}-D points, r={prob.radius:.6g} "
+                                f"({nnz / n:.1f} stored/row), {prob.n_bumps} bumps, {S} probes"),
+                   "n": n, "nnz": nnz, "probes": S, "precision": args.precision, "parallelism": "single GPU"},
+        "assembly_ms": asm_ms, "assembly_nnz_per_s": nnz / (asm_ms / 1e3) if asm_ms else None,
+        "cg_spmv_GBps": spmv_gbs,
+        "iters_y": rep.iters, "iters_probe": rep.probe_iters, "ir_steps": rep.ir_steps,
+        "resid": rep.resid, "lml": rep.lml, "logdet": rep.logdet, "logdet_stderr": rep.logdet_stderr,
+        "grad_r": float(grad[0]),
+        "kernels_ms": {k: round(v[0] / args.steps, 3) for k, v in per.items()},
+        "roofline": roof,
+    }
+    if not args.no_fp64 and args.precision == "mixed":
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep64, grad64, _, _ = run_step(G, x, y, params, "fp64", opts)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        out["fp64_plain_s_per_lml_grad"] = t64
+        out["speedup_mixed_vs_fp64"] = t64 / (ms_per_step / 1e3)
+        out["fp64_iters"] = [rep64.iters, rep64.probe_iters]
+        out["fp64_lml"] = rep64.lml
+        log(f"[bench] fp64 plain: {t64:.2f}s iters y={rep64.iters} probes={rep64.probe_iters} lml={rep64.lml:.6f}")
+    if not args.no_cpu:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(prob, nnz, rep.iters, rep.probe_iters, S)
+        log(f"[bench] cpu baseline took {time.perf_counter() - t0:.1f}s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

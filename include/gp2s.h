@@ -88,7 +88,7 @@ typedef struct {
   int32_t check_every;    /* host convergence poll interval in iterations [16]        */
   uint64_t seed;          /* probe seed [0]                                           */
   double tol;             /* target ||y - K a|| / ||y|| (K as stored) [1e-8]          */
-  double probe_tol;       /* per-probe relative CG residual target [1e-7]             */
+  double probe_tol;       /* per-probe relative CG residual target [1e-5]             */
 } gp2s_solve_opts;
 
 /* Filled on return (HOST struct). */
@@ -104,6 +104,28 @@ typedef struct {
   int32_t n_probes;       /* probes used                                             */
 } gp2s_report;
 
+/* Per-kernel timing (HIP events on the context's stream), for measurement tools.
+ * Index into gp2s_stats.ms / .count: */
+#define GP2S_T_ASM_PREP          0  /* bounding box, bump mask, binning sort, gathers   */
+#define GP2S_T_ASM_COUNT         1  /* assembly count pass                               */
+#define GP2S_T_ASM_FILL          2  /* assembly fill pass (evaluation + compaction)      */
+#define GP2S_T_CG_MATVEC1        3  /* CG product, single right-hand side (+ p^T q)      */
+#define GP2S_T_CG_MATVEC_BLOCK   4  /* CG product, probe block (+ p^T q per column)      */
+#define GP2S_T_CG_UPDATE1        5  /* CG solution/residual update, single RHS (+ dots)  */
+#define GP2S_T_CG_PUPDATE1       6  /* CG direction update, single RHS                   */
+#define GP2S_T_SPMV              7  /* standalone single-RHS product (residual checks)   */
+#define GP2S_T_SPMM              8  /* standalone multi-RHS product                      */
+#define GP2S_T_SLQ               9  /* Lanczos quadrature                                */
+#define GP2S_T_BACKWARD         10  /* gradient row contraction                          */
+#define GP2S_T_GRAD_REDUCE      11  /* gradient per-point reduction                      */
+#define GP2S_T_CG_UPDATE_BLOCK  12  /* CG solution/residual update, probe block          */
+#define GP2S_T_CG_PUPDATE_BLOCK 13  /* CG direction update, probe block                  */
+#define GP2S_NUM_TIMERS         16
+typedef struct {
+  double ms[GP2S_NUM_TIMERS];     /* summed device time per category, milliseconds */
+  int64_t count[GP2S_NUM_TIMERS]; /* number of timed launches per category         */
+} gp2s_stats;
+
 /* ---- version and options ------------------------------------------------------ */
 int32_t gp2s_abi_version(void);
 void gp2s_default_opts(gp2s_solve_opts* opts);     /* HOST struct; no-op on NULL    */
@@ -116,6 +138,12 @@ gp2s_status gp2s_create(gp2s_ctx* out, void* stream, gp2s_alloc_fn alloc, gp2s_f
                         void* user);
 gp2s_status gp2s_destroy(gp2s_ctx ctx);
 const char* gp2s_last_error(gp2s_ctx ctx);         /* valid until the next call on ctx */
+
+/* Enable (1) or disable (0) per-kernel event timing on ctx; either call resets the
+ * totals. Timing adds two event records per timed launch. */
+gp2s_status gp2s_set_timing(gp2s_ctx ctx, int32_t enable);
+/* Totals since the last gp2s_set_timing (HOST struct); waits for the stream. */
+gp2s_status gp2s_get_stats(gp2s_ctx ctx, gp2s_stats* out);
 
 /* Validate n and params on the host only (what gp2s_assemble checks first). */
 gp2s_status gp2s_check_params(gp2s_ctx ctx, int64_t n, const gp2s_params* params);

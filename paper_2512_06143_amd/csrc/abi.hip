@@ -19,6 +19,16 @@ struct gp2s_ctx_s {
   void* user = nullptr;
   std::string err;
   void* pinned = nullptr;  // small pinned host buffer for scalar read-backs
+  // optional per-kernel timing with HIP events on the context's stream
+  bool timing = false;
+  struct Pending {
+    int cat;
+    hipEvent_t e0, e1;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[GP2S_NUM_TIMERS] = {};
+  int64_t count[GP2S_NUM_TIMERS] = {};
 };
 
 struct gp2s_matrix_s {
@@ -122,6 +132,57 @@ bool is_fin(double v) { return std::isfinite(v); }
     if (!(ptr)) return fail(ctx, GP2S_E_OOM, "device allocation failed (%s)", #ptr);            \
   } while (0)
 
+hipEvent_t ev_get(gp2s_ctx c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Collect finished event pairs into the per-category totals (the stream is idle).
+void harvest(gp2s_ctx c) {
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) {
+      c->ms[p.cat] += ms;
+      c->count[p.cat] += 1;
+    }
+    c->pool.push_back(p.e0);
+    c->pool.push_back(p.e1);
+  }
+  c->pending.clear();
+}
+
+// Brackets one or more launches with events when timing is enabled.
+struct Timed {
+  gp2s_ctx c;
+  int cat;
+  hipEvent_t e0 = nullptr;
+  Timed(gp2s_ctx cc, int k) : c(cc), cat(k) {
+    if (c->timing) {
+      e0 = ev_get(c);
+      if (e0) (void)hipEventRecord(e0, c->stream);
+    }
+  }
+  ~Timed() {
+    if (!e0) return;
+    hipEvent_t e1 = ev_get(c);
+    if (!e1) return;
+    (void)hipEventRecord(e1, c->stream);
+    c->pending.push_back({cat, e0, e1});
+  }
+};
+
+#define TIMED(cat, expr)          \
+  do {                            \
+    Timed t_(ctx, cat);           \
+    HIPCHK(expr);                 \
+  } while (0)
+
 gp2s_status ensure_device(gp2s_ctx ctx) {
   int count = 0;
   hipError_t e = hipGetDeviceCount(&count);
@@ -139,6 +200,7 @@ gp2s_status readback(gp2s_ctx ctx, const void* dev, size_t bytes, void* host) {
   HIPCHK(hipMemcpyAsync(ctx->pinned, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   std::memcpy(host, ctx->pinned, bytes);
+  if (!ctx->pending.empty()) harvest(ctx);
   return GP2S_OK;
 }
 
@@ -212,10 +274,13 @@ gp2s_status run_cg(gp2s_ctx ctx, gp2s_matrix m, int S, const double* B, double* 
   int it = 0;
   bool open = flags[1] > 0;
   while (open && it < max_iter) {
-    HIPCHK(launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, n, S, (double)m->nnz / (double)n, P, Q, cs,
-                            ctx->stream));
-    HIPCHK(launch_cg_update(n, S, X, R, P, Q, m->dinv, cs, it, ctx->stream));
-    HIPCHK(launch_cg_pupdate(n, S, P, R, m->dinv, cs, ctx->stream));
+    TIMED(S == 1 ? GP2S_T_CG_MATVEC1 : GP2S_T_CG_MATVEC_BLOCK,
+          launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, n, S, (double)m->nnz / (double)n, P, Q, cs,
+                           ctx->stream));
+    TIMED(S == 1 ? GP2S_T_CG_UPDATE1 : GP2S_T_CG_UPDATE_BLOCK,
+          launch_cg_update(n, S, X, R, P, Q, m->dinv, cs, it, ctx->stream));
+    TIMED(S == 1 ? GP2S_T_CG_PUPDATE1 : GP2S_T_CG_PUPDATE_BLOCK,
+          launch_cg_pupdate(n, S, P, R, m->dinv, cs, ctx->stream));
     ++it;
     if (it % check_every == 0 || it == max_iter) {
       st = readback(ctx, cs.flags, sizeof(flags), flags);
@@ -270,7 +335,7 @@ gp2s_status solve_internal(gp2s_ctx ctx, gp2s_matrix m, const double* y, double*
     if (st) return st;
     total += run.total_iters;
     for (;;) {
-      HIPCHK(launch_spmv(m->prec, m->row_ptr, m->col, m->val, n, (double)m->nnz / n, a, kx, ctx->stream));
+      TIMED(GP2S_T_SPMV, launch_spmv(m->prec, m->row_ptr, m->col, m->val, n, (double)m->nnz / n, a, kx, ctx->stream));
       HIPCHK(launch_axpy_sub(n, y, kx, r, ctx->stream));
       double rr = 0.0;
       st = dot_host(ctx, n, r, nullptr, red, tk, &rr);
@@ -324,7 +389,7 @@ gp2s_status probes_internal(gp2s_ctx ctx, gp2s_matrix m, const gp2s_solve_opts* 
   double* work = sc.get<double>((size_t)2 * S * max_m);
   double* quad = sc.get<double>(S);
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "quadrature workspace allocation failed");
-  HIPCHK(launch_slq_ws(S, run.cs.hist_a, run.cs.hist_b, run.cs.iters, work, max_m, quad, ctx->stream));
+  TIMED(GP2S_T_SLQ, launch_slq_ws(S, run.cs.hist_a, run.cs.hist_b, run.cs.iters, work, max_m, quad, ctx->stream));
   std::vector<double> qh(S);
   st = readback(ctx, quad, S * sizeof(double), qh.data());
   if (st) return st;
@@ -411,8 +476,8 @@ gp2s_status lml_common(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_
     b.radius = m->radius;
     b.r2 = m->radius * m->radius;
     b.inv_r2 = 1.0 / b.r2;
-    HIPCHK(launch_backward_rows(b, m->prec, Rr, Tr, Ur, ctx->stream));
-    HIPCHK(launch_grad_reduce(n, m->dim, m->P, S, m->x64, m->g64, ai, Rr, Tr, Ur, m->centers_d,
+    TIMED(GP2S_T_BACKWARD, launch_backward_rows(b, m->prec, Rr, Tr, Ur, ctx->stream));
+    TIMED(GP2S_T_GRAD_REDUCE, launch_grad_reduce(n, m->dim, m->P, S, m->x64, m->g64, ai, Rr, Tr, Ur, m->centers_d,
                               m->bump_width * m->bump_width, gpart, tk2, gd, ctx->stream));
     st = readback(ctx, gd, ncomp * sizeof(double), grad);
     if (st) return st;
@@ -439,7 +504,7 @@ void gp2s_default_opts(gp2s_solve_opts* o) {
   o->check_every = 16;
   o->seed = 0;
   o->tol = 1e-8;
-  o->probe_tol = 1e-7;
+  o->probe_tol = 1e-5;
 }
 
 const char* gp2s_status_string(gp2s_status s) {
@@ -470,8 +535,41 @@ gp2s_status gp2s_create(gp2s_ctx* out, void* stream, gp2s_alloc_fn alloc, gp2s_f
   return GP2S_OK;
 }
 
+gp2s_status gp2s_set_timing(gp2s_ctx ctx, int32_t enable) {
+  if (!ctx) return GP2S_E_INVALID;
+  if (!ctx->pending.empty()) {
+    (void)hipStreamSynchronize(ctx->stream);
+    harvest(ctx);
+  }
+  ctx->timing = enable != 0;
+  for (int k = 0; k < GP2S_NUM_TIMERS; ++k) {
+    ctx->ms[k] = 0.0;
+    ctx->count[k] = 0;
+  }
+  return GP2S_OK;
+}
+
+gp2s_status gp2s_get_stats(gp2s_ctx ctx, gp2s_stats* out) {
+  if (!ctx || !out) return GP2S_E_INVALID;
+  if (!ctx->pending.empty()) {
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return fail(ctx, GP2S_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    harvest(ctx);
+  }
+  for (int k = 0; k < GP2S_NUM_TIMERS; ++k) {
+    out->ms[k] = ctx->ms[k];
+    out->count[k] = ctx->count[k];
+  }
+  return GP2S_OK;
+}
+
 gp2s_status gp2s_destroy(gp2s_ctx ctx) {
   if (!ctx) return GP2S_E_INVALID;
+  if (!ctx->pending.empty()) {
+    (void)hipStreamSynchronize(ctx->stream);
+    harvest(ctx);
+  }
+  for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
   return GP2S_OK;
@@ -621,6 +719,8 @@ gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_p
     m->pts64 = own<double4>(m, n);
     OOMCHK(m->pts64);
   }
+  {
+  Timed prep_timer(ctx, GP2S_T_ASM_PREP);
   HIPCHK(hipMemsetAsync(bin_count, 0, g.nbins * sizeof(int32_t), sm));
   HIPCHK(launch_prologue(x, n, g, m->centers_d, m->weights_d, m->P, p->bump_width * p->bump_width, bin_of, slot,
                          bin_count, g64u, gam, sm));
@@ -629,6 +729,7 @@ gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_p
   HIPCHK(launch_binsort(n, perm_tmp, bin_of, m->bin_start, m->perm, sm));
   HIPCHK(launch_gather_points(n, dim, x, m->perm, bin_of, g64u, gam, m->pts32, m->pts64, m->x64, m->g64,
                               m->binid, sm));
+  }
 
   // 4. count pass, row pointers, fill pass
   AssembleArgs aa{};
@@ -644,7 +745,7 @@ gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_p
   aa.inv_r2 = 1.0 / aa.r2;
   aa.noise = p->noise_var;
   aa.r2f = (float)aa.r2;
-  HIPCHK(launch_assemble_count(aa, prec, row_cnt, sm));
+  TIMED(GP2S_T_ASM_COUNT, launch_assemble_count(aa, prec, row_cnt, sm));
   HIPCHK(launch_exscan_i32_i64(row_cnt, m->row_ptr, n, scan_ws, sm));
   int64_t nnz = 0;
   st = readback(ctx, m->row_ptr + n, sizeof(int64_t), &nnz);
@@ -654,7 +755,7 @@ gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_p
   m->val = prec == GP2S_MIXED ? (void*)own<float>(m, nnz) : (void*)own<double>(m, nnz);
   OOMCHK(m->col);
   OOMCHK(m->val);
-  HIPCHK(launch_assemble_fill(aa, prec, m->row_ptr, m->col, m->val, m->diag, sm));
+  TIMED(GP2S_T_ASM_FILL, launch_assemble_fill(aa, prec, m->row_ptr, m->col, m->val, m->diag, sm));
   int32_t* bad = nonfinite;
   HIPCHK(hipMemsetAsync(bad, 0, sizeof(int32_t), sm));
   HIPCHK(launch_dinv(n, m->diag, m->dinv, bad, sm));
@@ -778,9 +879,9 @@ gp2s_status gp2s_spmv(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "spmv workspace allocation failed");
   HIPCHK(launch_gather_rows(n, nrhs, m->perm, X, Xi, ctx->stream));
   if (nrhs == 1)
-    HIPCHK(launch_spmv(m->prec, m->row_ptr, m->col, m->val, n, (double)m->nnz / n, Xi, Yi, ctx->stream));
+    TIMED(GP2S_T_SPMV, launch_spmv(m->prec, m->row_ptr, m->col, m->val, n, (double)m->nnz / n, Xi, Yi, ctx->stream));
   else
-    HIPCHK(launch_spmm(m->prec, m->row_ptr, m->col, m->val, n, nrhs, Xi, Yi, ctx->stream));
+    TIMED(GP2S_T_SPMM, launch_spmm(m->prec, m->row_ptr, m->col, m->val, n, nrhs, Xi, Yi, ctx->stream));
   HIPCHK(launch_scatter_rows(n, nrhs, m->perm, Yi, Y, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return GP2S_OK;

@@ -44,6 +44,18 @@ class SolveOpts(ctypes.Structure):
                 ("probe_tol", ctypes.c_double)]
 
 
+NUM_TIMERS = 16
+TIMER_NAMES = ["asm_prep", "asm_count", "asm_fill", "cg_matvec1", "cg_matvec_block", "cg_update1", "cg_pupdate1",
+               "spmv", "spmm", "slq", "backward", "grad_reduce", "cg_update_block", "cg_pupdate_block"]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * NUM_TIMERS), ("count", ctypes.c_int64 * NUM_TIMERS)]
+
+    def as_dict(self):
+        return {name: (self.ms[k], int(self.count[k])) for k, name in enumerate(TIMER_NAMES)}
+
+
 class Report(ctypes.Structure):
     _fields_ = [("lml", ctypes.c_double), ("logdet", ctypes.c_double), ("yTa", ctypes.c_double),
                 ("resid", ctypes.c_double), ("logdet_stderr", ctypes.c_double), ("iters", ctypes.c_int32),
@@ -62,6 +74,8 @@ _SIGS = {
     "gp2s_destroy": (_i32, [_vp]),
     "gp2s_last_error": (ctypes.c_char_p, [_vp]),
     "gp2s_check_params": (_i32, [_vp, _i64, ctypes.POINTER(Params)]),
+    "gp2s_set_timing": (_i32, [_vp, _i32]),
+    "gp2s_get_stats": (_i32, [_vp, ctypes.POINTER(Stats)]),
     "gp2s_assemble": (_i32, [_vp, _i64, _vp, ctypes.POINTER(Params), _i32, ctypes.POINTER(_vp)]),
     "gp2s_matrix_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
     "gp2s_matrix_export": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
@@ -156,9 +170,20 @@ class Context:
             raise GP2SError(st, "gp2s_create failed")
         self.ptr = ctx
 
-    def check(self, st):
+    def check(self, st, allow_noconv=False):
+        if st == GP2S_E_NOCONV and allow_noconv:
+            return st
         if st != GP2S_OK:
             raise GP2SError(st, lib.gp2s_last_error(self.ptr).decode())
+        return st
+
+    def set_timing(self, enable=True):
+        self.check(lib.gp2s_set_timing(self.ptr, 1 if enable else 0))
+
+    def stats(self) -> dict:
+        st = Stats()
+        self.check(lib.gp2s_get_stats(self.ptr, ctypes.byref(st)))
+        return st.as_dict()
 
     def close(self):
         if getattr(self, "ptr", None):
@@ -258,28 +283,31 @@ def gp2s_spmv(m: Matrix, X):
     return Y
 
 
-def gp2s_solve(m: Matrix, y, opts: SolveOpts | None = None):
+def gp2s_solve(m: Matrix, y, opts: SolveOpts | None = None, allow_noconv=False):
+    """a = K^-1 y. With allow_noconv, a CG that hits max_iter returns the last iterate
+    (rep.status == GP2S_E_NOCONV) instead of raising."""
     ctx = m.ctx
     yd = _as_dev64(y, ctx)
     a = ctx._torch.empty_like(yd)
     rep = Report()
     o = opts or default_opts()
     st = lib.gp2s_solve(ctx.ptr, m.handle, _ptr(yd), _ptr(a), ctypes.byref(o), ctypes.byref(rep))
-    ctx.check(st)
+    rep.status = ctx.check(st, allow_noconv)
     return a, rep
 
 
-def gp2s_lml(m: Matrix, y, opts: SolveOpts | None = None, want_a=True):
+def gp2s_lml(m: Matrix, y, opts: SolveOpts | None = None, want_a=True, allow_noconv=False):
     ctx = m.ctx
     yd = _as_dev64(y, ctx)
     a = ctx._torch.empty_like(yd) if want_a else None
     rep = Report()
     o = opts or default_opts()
-    ctx.check(lib.gp2s_lml(ctx.ptr, m.handle, _ptr(yd), ctypes.byref(o), _ptr(a), ctypes.byref(rep)))
+    rep.status = ctx.check(lib.gp2s_lml(ctx.ptr, m.handle, _ptr(yd), ctypes.byref(o), _ptr(a),
+                                        ctypes.byref(rep)), allow_noconv)
     return rep, a
 
 
-def gp2s_lml_grad(m: Matrix, y, opts: SolveOpts | None = None, want_a=True):
+def gp2s_lml_grad(m: Matrix, y, opts: SolveOpts | None = None, want_a=True, allow_noconv=False):
     ctx = m.ctx
     yd = _as_dev64(y, ctx)
     a = ctx._torch.empty_like(yd) if want_a else None
@@ -287,5 +315,6 @@ def gp2s_lml_grad(m: Matrix, y, opts: SolveOpts | None = None, want_a=True):
     o = opts or default_opts()
     P = int(m.params.weights.shape[0]) if m.params is not None else 0
     grad = (ctypes.c_double * (P + 2))()
-    ctx.check(lib.gp2s_lml_grad(ctx.ptr, m.handle, _ptr(yd), ctypes.byref(o), _ptr(a), ctypes.byref(rep), grad))
+    rep.status = ctx.check(lib.gp2s_lml_grad(ctx.ptr, m.handle, _ptr(yd), ctypes.byref(o), _ptr(a),
+                                             ctypes.byref(rep), grad), allow_noconv)
     return rep, np.array(grad[:], dtype=np.float64), a
