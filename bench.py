@@ -4,8 +4,9 @@ product bandwidth and the roofline of the dominant kernel.
 A step is one pass of the whole hot path over one synthetic instance whose inputs
 are already in HBM: bin + cull + assemble K, solve K a = y (Jacobi-PCG with
 refinement), probe solves + Lanczos log-determinant, LML, and the gradient kernel.
-Default workload: 10 000 000 clustered 2-D points (200-component Gaussian mixture),
-r for 50 stored entries per row, 16 bumps, 64 probes, float32 K with float64 CG.
+Default workload: 200 000 uniform 2-D points, r = 0.01 (63 stored entries per row),
+8 bumps, 64 probes; float32 K with float64 CG, timed against the float64-plain path
+on the same inputs. `--config c4` runs the 10 000 000-point clustered workload.
 
 Prints one JSON line (last line of stdout).
 """
@@ -30,21 +31,18 @@ def log(msg):
 
 
 def kernel_bytes(cat, n, nnz, S, prec):
-    """Algorithmic HBM bytes of one launch of a timed kernel category."""
-    vb = 4 if prec == "mixed" else 8
+    """Algorithmic HBM bytes of one launch of a timed kernel category: the CSR once,
+    each vector stream once, at the types the path stores them in (the probe block
+    of the mixed path keeps directions P and products Q in float32)."""
+    vb = 4 if prec == "mixed" else 8                  # stored K value
+    pb = 4 if (prec == "mixed" and "block" in cat) else 8   # P / Q element
     K = nnz * (4 + vb) + (n + 1) * 8
-    if cat == "cg_matvec_block":
-        return K + n * S * 8 * 2            # read P once, write Q
-    if cat in ("cg_matvec1", "spmv"):
-        return K + n * 8 * 2
-    if cat == "cg_update_block":
-        return n * S * 8 * 6 + n * 8        # X, R read+write; P, Q read; 1/diag
-    if cat == "cg_update1":
-        return n * 8 * 6 + n * 8
-    if cat == "cg_pupdate_block":
-        return n * S * 8 * 3 + n * 8        # R, P read; P write; 1/diag
-    if cat == "cg_pupdate1":
-        return n * 8 * 3 + n * 8
+    if cat in ("cg_matvec_block", "cg_matvec1", "spmv"):
+        return K + n * S * pb * 2            # read P once, write Q
+    if cat in ("cg_update_block", "cg_update1"):
+        return n * S * (8 * 4 + pb * 2) + n * 8   # X, R read+write; P, Q read; 1/diag
+    if cat in ("cg_pupdate_block", "cg_pupdate1"):
+        return n * S * (8 + pb * 2) + n * 8       # R read; P read+write; 1/diag
     if cat == "asm_fill":
         return nnz * (4 + vb)               # CSR written
     return None
@@ -70,7 +68,7 @@ def run_step(G, x, y, params, precision, opts):
     return rep, grad, n, nnz
 
 
-def cpu_baseline(prob, nnz_full, iters_y, iters_probe, S, budget_points=150_000):
+def cpu_baseline(prob, nnz_full, iters_y, iters_probe, S, budget_points=250_000, k_iter=300):
     """The oracle as it stands on a bounded sample: the points inside a square window
     (about budget_points of them) around the densest cluster centre region of the same
     point cloud. Times oracle.covariance_csr (assembly) and oracle.pcg_jacobi per
@@ -96,7 +94,6 @@ def cpu_baseline(prob, nnz_full, iters_y, iters_probe, S, budget_points=150_000)
     t0 = time.perf_counter()
     K = oracle.covariance_csr(xs, prob.radius, prob.bump_width, prob.centers, prob.weights, prob.noise_var)
     t_asm = time.perf_counter() - t0
-    k_iter = 40
     t0 = time.perf_counter()
     oracle.pcg_jacobi(K, ys, tol=1e-300, max_iter=k_iter)
     t_it = (time.perf_counter() - t0) / k_iter
@@ -115,9 +112,9 @@ def cpu_baseline(prob, nnz_full, iters_y, iters_probe, S, budget_points=150_000)
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c4")
+    ap.add_argument("--config", default="c2")
     ap.add_argument("--n", type=int, default=None, help="override the point count (same recipe)")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--probes", type=int, default=None)
@@ -126,7 +123,18 @@ def main():
     ap.add_argument("--probe-tol", type=float, default=1e-5)
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64-plain comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8}))
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
@@ -147,6 +155,14 @@ def main():
     opts = G.default_opts(n_probes=S, max_iter=args.max_iter, tol=args.tol, probe_tol=args.probe_tol,
                           check_every=32)
     ctx = G.default_context()
+    last = [0.0]
+
+    def progress(label, it, open_cols, res):
+        now = time.perf_counter()
+        if now - last[0] > 10.0:
+            last[0] = now
+            log(f"[bench]   ... {label}: {it} iterations, {open_cols} open, max rel resid {res:.2e}")
+    ctx.set_progress(progress)
 
     for w in range(args.warmup):
         t0 = time.perf_counter()
@@ -188,14 +204,15 @@ def main():
     spmv_gbs = (kernel_bytes("cg_matvec1", n, nnz, 1, args.precision) / (mv1[0] / mv1[1] / 1e3) / 1e9
                 if mv1[1] else None)
     out = {
-        "metric": "s per LML+grad (K nnz/s assembled reported alongside)",
+        "metric": "s per LML+grad, FP32-mixed vs FP64 plain (K nnz/s assembled alongside)",
         "value": ms_per_step / 1e3,
         "unit": "s/(LML+grad)",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 K / f64 CG" if args.precision == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": (f"{args.config}: {n} clustered {prob.dim}-D points, r={prob.radius:.6g} "
+        "config": {"workload": (f"{args.config}: {n} {prob.meta.get('points', 'uniform')} {prob.dim}-D points, "
+                                f"r={prob.radius:.6g} "
                                 f"({nnz / n:.1f} stored/row), {prob.n_bumps} bumps, {S} probes"),
                    "n": n, "nnz": nnz, "probes": S, "precision": args.precision, "parallelism": "single GPU"},
         "assembly_ms": asm_ms, "assembly_nnz_per_s": nnz / (asm_ms / 1e3) if asm_ms else None,

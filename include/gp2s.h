@@ -145,6 +145,14 @@ gp2s_status gp2s_set_timing(gp2s_ctx ctx, int32_t enable);
 /* Totals since the last gp2s_set_timing (HOST struct); waits for the stream. */
 gp2s_status gp2s_get_stats(gp2s_ctx ctx, gp2s_stats* out);
 
+/* Optional progress callback, called on the host at every convergence poll of a CG
+ * solve with the solve's label ("y solve", "refinement solve", "probe block"), the
+ * iterations done, the number of unfinished columns and the largest relative residual
+ * of the recurrence among them. NULL disables it. */
+typedef void (*gp2s_progress_fn)(const char* label, int32_t iters, int32_t open_cols, double max_rel_resid,
+                                 void* user);
+gp2s_status gp2s_set_progress(gp2s_ctx ctx, gp2s_progress_fn fn, void* user);
+
 /* Validate n and params on the host only (what gp2s_assemble checks first). */
 gp2s_status gp2s_check_params(gp2s_ctx ctx, int64_t n, const gp2s_params* params);
 
@@ -186,6 +194,7 @@ gp2s_status gp2s_matrix_free(gp2s_matrix m);
  * solve (Sec. 3.5; App. B.6 "MINRES"): products of stored values with float64
  * vectors accumulate in float64. */
 gp2s_status gp2s_spmv(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X, double* Y);
+/* (n * nrhs, and n * n_probes below, must stay below 2^31.) */
 
 /* a = K^{-1} y (DEVICE [n] float64 each) by Jacobi-preconditioned CG with float64
  * vectors and dot products, restarted from the recomputed residual (iterative

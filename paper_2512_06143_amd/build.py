@@ -1,6 +1,7 @@
 """Build libgp2s.so (HIP kernels + C ABI) for gfx950 with hipcc, in-tree.
 
-Usage: python -m paper_2512_06143_amd.build   (or build() from Python).
+Usage: python paper_2512_06143_amd/build.py  (or __graft_entry__.build()). Run it
+as a file: importing the package first would load the library being rebuilt.
 Every call recompiles. Object files go to paper_2512_06143_amd/_build/.
 """
 from __future__ import annotations

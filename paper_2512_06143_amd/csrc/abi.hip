@@ -29,6 +29,8 @@ struct gp2s_ctx_s {
   std::vector<hipEvent_t> pool;
   double ms[GP2S_NUM_TIMERS] = {};
   int64_t count[GP2S_NUM_TIMERS] = {};
+  gp2s_progress_fn progress = nullptr;
+  void* progress_user = nullptr;
 };
 
 struct gp2s_matrix_s {
@@ -234,15 +236,18 @@ struct CgRun {
 
 // Jacobi-PCG for K X = B over S columns (internal order). X receives the solution.
 gp2s_status run_cg(gp2s_ctx ctx, gp2s_matrix m, int S, const double* B, double* X, double tol, int max_iter,
-                   int check_every, bool keep_hist, Scratch& sc, CgRun& out) {
+                   int check_every, bool keep_hist, Scratch& sc, CgRun& out, const char* label) {
   const int64_t n = m->n;
   const size_t nS = (size_t)n * S;
+  // Probe blocks of the mixed path keep search directions and products in float32
+  // (x, r, dot products and all coefficients stay float64).
+  const bool f32vec = m->prec == GP2S_MIXED && S > 1;
+  const size_t vb = f32vec ? sizeof(float) : sizeof(double);
   double* R = sc.get<double>(nS);
-  double* P = sc.get<double>(nS);
-  double* Q = sc.get<double>(nS);
+  void* P = sc.get<uint8_t>(nS * vb);
+  void* Q = sc.get<uint8_t>(nS * vb);
   double* sd = sc.get<double>(6 * S + (size_t)kReduceBlocks * S * 2);
   int32_t* si = sc.get<int32_t>(2 * S + 4);
-  uint32_t* tk = sc.get<uint32_t>(4);
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "CG workspace allocation failed");
   CgState& cs = out.cs;
   cs.rz = sd;
@@ -253,9 +258,8 @@ gp2s_status run_cg(gp2s_ctx ctx, gp2s_matrix m, int S, const double* B, double* 
   cs.rr = sd + 5 * S;
   cs.partial = sd + 6 * S;
   cs.done = si;
-  cs.iters = si + S;
-  cs.flags = si + 2 * S;
-  cs.ticket = tk;
+  cs.flags = si + S;
+  cs.iters = si + S + 4;
   cs.hist_a = cs.hist_b = nullptr;
   cs.max_hist = 0;
   if (keep_hist) {
@@ -265,29 +269,53 @@ gp2s_status run_cg(gp2s_ctx ctx, gp2s_matrix m, int S, const double* B, double* 
     cs.max_hist = max_iter;
   }
   HIPCHK(hipMemsetAsync(si, 0, (2 * S + 4) * sizeof(int32_t), ctx->stream));
-  HIPCHK(hipMemsetAsync(tk, 0, 4 * sizeof(uint32_t), ctx->stream));
-  HIPCHK(launch_cg_init(n, S, B, m->dinv, X, R, P, cs, &tol, ctx->stream));
-  int32_t flags[4];
-  gp2s_status st = readback(ctx, cs.flags, sizeof(flags), flags);
+  HIPCHK(launch_cg_init(n, S, B, m->dinv, X, R, P, f32vec, cs, tol, ctx->stream));
+  // done[S] then flags[4] are contiguous in si: one read-back per poll.
+  std::vector<int32_t> poll(S + 4);
+  auto read_poll = [&]() -> gp2s_status { return readback(ctx, si, (S + 4) * sizeof(int32_t), poll.data()); };
+  auto n_open = [&]() {
+    int o = 0;
+    for (int s = 0; s < S; ++s) o += poll[s] == 0;
+    return o;
+  };
+  gp2s_status st = read_poll();
   if (st) return st;
-  if (flags[2]) return fail(ctx, GP2S_E_NONFINITE, "non-finite right-hand side");
+  if (poll[S + 2]) return fail(ctx, GP2S_E_NONFINITE, "non-finite right-hand side (%s)", label);
   int it = 0;
-  bool open = flags[1] > 0;
+  bool open = n_open() > 0;
   while (open && it < max_iter) {
     TIMED(S == 1 ? GP2S_T_CG_MATVEC1 : GP2S_T_CG_MATVEC_BLOCK,
-          launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, n, S, (double)m->nnz / (double)n, P, Q, cs,
-                           ctx->stream));
+          launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, n, S, (double)m->nnz / (double)n, P, Q, f32vec,
+                           cs, ctx->stream));
     TIMED(S == 1 ? GP2S_T_CG_UPDATE1 : GP2S_T_CG_UPDATE_BLOCK,
-          launch_cg_update(n, S, X, R, P, Q, m->dinv, cs, it, ctx->stream));
+          launch_cg_update(n, S, X, R, P, Q, f32vec, m->dinv, cs, it, ctx->stream));
     TIMED(S == 1 ? GP2S_T_CG_PUPDATE1 : GP2S_T_CG_PUPDATE_BLOCK,
-          launch_cg_pupdate(n, S, P, R, m->dinv, cs, ctx->stream));
+          launch_cg_pupdate(n, S, P, R, m->dinv, f32vec, cs, ctx->stream));
     ++it;
     if (it % check_every == 0 || it == max_iter) {
-      st = readback(ctx, cs.flags, sizeof(flags), flags);
+      st = read_poll();
       if (st) return st;
-      if (flags[0]) return fail(ctx, GP2S_E_NOT_SPD, "CG breakdown: p^T K p <= 0 (matrix not positive definite)");
-      if (flags[2]) return fail(ctx, GP2S_E_NONFINITE, "non-finite values during CG");
-      open = flags[1] > 0;
+      if (poll[S + 0]) {
+        int32_t its[kMaxProbes];
+        st = readback(ctx, cs.iters, S * sizeof(int32_t), its);
+        const int col = poll[S + 3];
+        return fail(ctx, GP2S_E_NOT_SPD,
+                    "CG breakdown in the %s, column %d after %d iterations: p^T K p <= 0 (matrix not positive "
+                    "definite in working precision)", label, col, st ? -1 : its[col]);
+      }
+      if (poll[S + 2]) return fail(ctx, GP2S_E_NONFINITE, "non-finite values during CG (%s)", label);
+      open = n_open() > 0;
+      if (ctx->progress) {
+        double rr[kMaxProbes], bb[kMaxProbes];
+        st = readback(ctx, cs.rr, S * sizeof(double), rr);
+        if (st) return st;
+        st = readback(ctx, cs.bb, S * sizeof(double), bb);
+        if (st) return st;
+        double worst = 0.0;
+        for (int s = 0; s < S; ++s)
+          if (!poll[s] && bb[s] > 0) worst = std::max(worst, std::sqrt(rr[s] / bb[s]));
+        ctx->progress(label, it, n_open(), worst, ctx->progress_user);
+      }
     }
   }
   st = readback(ctx, cs.iters, S * sizeof(int32_t), out.host_iters);
@@ -331,7 +359,7 @@ gp2s_status solve_internal(gp2s_ctx ctx, gp2s_matrix m, const double* y, double*
     *converged = true;
   } else {
     CgRun run;
-    st = run_cg(ctx, m, 1, y, a, o->tol, o->max_iter, o->check_every, false, sc, run);
+    st = run_cg(ctx, m, 1, y, a, o->tol, o->max_iter, o->check_every, false, sc, run, "y solve");
     if (st) return st;
     total += run.total_iters;
     for (;;) {
@@ -350,7 +378,7 @@ gp2s_status solve_internal(gp2s_ctx ctx, gp2s_matrix m, const double* y, double*
       ++ir;
       const double inner = std::min(0.5, 0.5 * o->tol / resid);
       CgRun r2;
-      st = run_cg(ctx, m, 1, r, d, inner, o->max_iter - total, o->check_every, false, sc, r2);
+      st = run_cg(ctx, m, 1, r, d, inner, o->max_iter - total, o->check_every, false, sc, r2, "refinement solve");
       if (st) return st;
       total += r2.total_iters;
       HIPCHK(launch_add(n, a, d, ctx->stream));
@@ -383,7 +411,7 @@ gp2s_status probes_internal(gp2s_ctx ctx, gp2s_matrix m, const gp2s_solve_opts* 
   HIPCHK(launch_probe_masks(n, m->perm, o->seed, S, mask, ctx->stream));
   HIPCHK(launch_probe_rhs(n, S, mask, m->diag, B, ctx->stream));
   CgRun run;
-  gp2s_status st = run_cg(ctx, m, S, B, Qsol, o->probe_tol, o->max_iter, o->check_every, true, sc, run);
+  gp2s_status st = run_cg(ctx, m, S, B, Qsol, o->probe_tol, o->max_iter, o->check_every, true, sc, run, "probe block");
   if (st) return st;
   const int64_t max_m = std::max(1, run.total_iters);
   double* work = sc.get<double>((size_t)2 * S * max_m);
@@ -418,6 +446,8 @@ gp2s_status lml_common(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_
   if (st) return st;
   if (!y) return fail(ctx, GP2S_E_INVALID, "y is NULL");
   if (!rep) return fail(ctx, GP2S_E_INVALID, "report is NULL");
+  if ((int64_t)m->n * o->n_probes >= (int64_t)INT32_MAX)
+    return fail(ctx, GP2S_E_INVALID, "n * n_probes must be below 2^31 (probe block indexing)");
   if (grad && !m->assembled)
     return fail(ctx, GP2S_E_INVALID, "the gradient needs a handle from gp2s_assemble (imported CSR has no kernel)");
   st = ensure_device(ctx);
@@ -546,6 +576,13 @@ gp2s_status gp2s_set_timing(gp2s_ctx ctx, int32_t enable) {
     ctx->ms[k] = 0.0;
     ctx->count[k] = 0;
   }
+  return GP2S_OK;
+}
+
+gp2s_status gp2s_set_progress(gp2s_ctx ctx, gp2s_progress_fn fn, void* user) {
+  if (!ctx) return GP2S_E_INVALID;
+  ctx->progress = fn;
+  ctx->progress_user = user;
   return GP2S_OK;
 }
 
@@ -870,6 +907,8 @@ gp2s_status gp2s_spmv(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X
   if (st) return st;
   if (nrhs < 1 || nrhs > kMaxProbes) return fail(ctx, GP2S_E_INVALID, "nrhs must be in [1, %d]", kMaxProbes);
   if (!X || !Y) return fail(ctx, GP2S_E_INVALID, "X and Y must be non-NULL");
+  if ((int64_t)m->n * nrhs >= (int64_t)INT32_MAX)
+    return fail(ctx, GP2S_E_INVALID, "n * nrhs must be below 2^31");
   st = ensure_device(ctx);
   if (st) return st;
   const int64_t n = m->n;

@@ -71,12 +71,11 @@ __global__ __launch_bounds__(kBlock) void k_backward_rows(BackwardArgs b, double
                                                           double* __restrict__ Trow,
                                                           double* __restrict__ Urow) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t wave = blockIdx.x * (int64_t)(kBlock / kWave) + threadIdx.x / kWave;
-  const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+  const XcdRows rr = xcd_rows(b.n, threadIdx.x / kWave, kBlock / kWave);
   const int S = b.S;
   const bool active = lane < S;
   const double inv_r = 1.0 / b.radius;
-  for (int64_t row = wave; row < b.n; row += nwaves) {
+  for (int64_t row = rr.first; row < rr.end; row += rr.step) {
     float4 pi32;
     double4 pi64;
     if (F32) pi32 = b.pts32[row];
@@ -148,6 +147,7 @@ hipError_t launch_backward_rows(const BackwardArgs& b, int prec, double* Rrow, d
   int64_t blocks = (b.n + (kBlock / kWave) - 1) / (kBlock / kWave);
   if (blocks > (1 << 16)) blocks = 1 << 16;
   if (blocks < 1) return hipSuccess;
+  blocks = round_up8(blocks);
   if (prec == GP2S_MIXED)
     hipLaunchKernelGGL(k_backward_rows<true>, dim3((unsigned)blocks), dim3(kBlock), 0, st, b, Rrow, Trow, Urow);
   else

@@ -15,7 +15,7 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kBlock = 256;        // threads per workgroup for streaming kernels
 constexpr int kMaxProbes = 64;     // one probe per lane in the block kernels
 constexpr int kMaxBumps = 256;
-constexpr int kReduceBlocks = 1024;  // workgroups of the reduction-carrying kernels
+constexpr int kReduceBlocks = 4096;  // max workgroups of the reduction-carrying kernels
 
 // Uniform grid of cubic bins with side h >= r (slightly enlarged so that rounding
 // in the bin index can never separate two points closer than r by two bins).
@@ -37,13 +37,55 @@ struct CgState {
   double* rr;        // [S] ||r||^2 of the current iterate
   int32_t* done;     // [S] 1 once a column has converged
   int32_t* iters;    // [S] iterations performed per column
-  int32_t* flags;    // [4] 0: not-SPD, 1: number of unfinished columns, 2: nonfinite
+  int32_t* flags;    // [4] 0: breakdown (p^T K p <= 0), 2: non-finite, 3: breakdown column
   double* partial;   // [kReduceBlocks * S * 2] per-workgroup partial sums
-  uint32_t* ticket;  // [2] last-workgroup detection counters
   double* hist_a;    // [max_iter * S] alpha history (Lanczos coefficients), or null
   double* hist_b;    // [max_iter * S] beta history, or null
   int32_t max_hist;
 };
+
+// Sum partial[b * C + c] over b < nb for every column c < C in a fixed order, using
+// every thread of the calling workgroup (all threads must call it; C <= blockDim.x).
+// sh must hold blockDim.x doubles. Threads c < C receive the sums via out(c, sum).
+template <typename F>
+__device__ inline void reduce_partials(const double* partial, int nb, int C, double* sh, F out) {
+  const int nth = blockDim.x;
+  const int chunks = nth / C;
+  const int t = threadIdx.x;
+  const int c = t % C, j = t / C;
+  double v = 0.0;
+  if (j < chunks)
+    for (int b = j; b < nb; b += chunks) v += partial[(int64_t)b * C + c];
+  sh[t] = v;
+  __syncthreads();
+  if (t < C) {
+    double acc = 0.0;
+    for (int q = 0; q < chunks; ++q) acc += sh[q * C + t];
+    out(t, acc);
+  }
+  __syncthreads();
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2. For
+// row-parallel kernels, give XCD x (workgroups with blockIdx % 8 == x) the contiguous
+// row range [x n / 8, (x + 1) n / 8) and let its units interleave over consecutive rows
+// inside it, so neighbouring rows -- whose gathers touch the same vector entries --
+// share one L2. `unit` is this thread's unit index inside its workgroup (a wave or a
+// lane group) and `units` the units per workgroup. The grid must be a multiple of 8.
+struct XcdRows {
+  int64_t first, step, end;
+};
+__device__ inline XcdRows xcd_rows(int64_t n, int unit, int units) {
+  const int64_t xcd = blockIdx.x % 8;
+  const int64_t blocks_x = gridDim.x / 8;
+  const int64_t lb = blockIdx.x / 8;
+  XcdRows r;
+  r.first = n * xcd / 8 + lb * units + unit;
+  r.step = blocks_x * units;
+  r.end = n * (xcd + 1) / 8;
+  return r;
+}
+__host__ inline int64_t round_up8(int64_t b) { return (b + 7) / 8 * 8; }
 
 // ---- kernel launchers (defined in the .hip files) ---------------------------------
 // prologue.hip
@@ -92,17 +134,19 @@ hipError_t launch_spmv(int prec, const int64_t* rp, const int32_t* col, const vo
 hipError_t launch_spmm(int prec, const int64_t* rp, const int32_t* col, const void* val,
                        int64_t n, int S, const double* X, double* Y, hipStream_t st);
 // CG product step: Q = K P plus p^T q per column, then alpha = rz / p^T q.
+// P and Q are float32 when f32vec (block solves of the mixed path), else float64.
 hipError_t launch_cg_matvec(int prec, const int64_t* rp, const int32_t* col, const void* val,
-                            int64_t n, int S, double mean_row, const double* P, double* Q,
+                            int64_t n, int S, double mean_row, const void* P, void* Q, bool f32vec,
                             const CgState& cs, hipStream_t st);
 
 // pcg.hip
+hipError_t launch_cg_alpha(const CgState& cs, int nb, int S, hipStream_t st);
 hipError_t launch_cg_init(int64_t n, int S, const double* B, const double* dinv, double* X,
-                          double* R, double* P, const CgState& cs, const double* tol, hipStream_t st);
-hipError_t launch_cg_update(int64_t n, int S, double* X, double* R, const double* P,
-                            const double* Q, const double* dinv, const CgState& cs, int32_t iter,
+                          double* R, void* P, bool f32vec, const CgState& cs, double tol, hipStream_t st);
+hipError_t launch_cg_update(int64_t n, int S, double* X, double* R, const void* P, const void* Q,
+                            bool f32vec, const double* dinv, const CgState& cs, int32_t iter,
                             hipStream_t st);
-hipError_t launch_cg_pupdate(int64_t n, int S, double* P, const double* R, const double* dinv,
+hipError_t launch_cg_pupdate(int64_t n, int S, void* P, const double* R, const double* dinv, bool f32vec,
                              const CgState& cs, hipStream_t st);
 hipError_t launch_axpy_sub(int64_t n, const double* b, const double* kx, double* r, hipStream_t st);
 hipError_t launch_add(int64_t n, double* x, const double* d, hipStream_t st);

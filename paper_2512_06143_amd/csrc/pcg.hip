@@ -13,23 +13,34 @@ namespace gp2s {
 
 static inline int cols_block(int S) { return (kBlock / S) * S; }
 
-template <typename F>
-__device__ inline void block_reduce_cols(double* sh, int S, int nth, F write) {
-  // sh holds one value per thread; thread t belongs to column t % S.
+// Per-column sums of the block's values (thread t belongs to column t % S), written to
+// partial[(blockIdx * 2 + which) * S + column].
+__device__ inline void block_cols_to_partial(double* sh, int S, double v, double* partial, int which) {
+  const int nth = blockDim.x;
+  const int per = nth / S;  // threads per column
+  sh[threadIdx.x] = v;
   __syncthreads();
-  if ((int)threadIdx.x < S) {
+  if ((per & (per - 1)) == 0) {
+    // power-of-two threads per column: tree over strides that keep columns aligned
+    for (int o = (per / 2) * S; o >= S; o >>= 1) {
+      if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+      __syncthreads();
+    }
+    if ((int)threadIdx.x < S) partial[(blockIdx.x * 2 + which) * (int64_t)S + threadIdx.x] = sh[threadIdx.x];
+  } else if ((int)threadIdx.x < S) {
     double t = 0.0;
     for (int k = threadIdx.x; k < nth; k += S) t += sh[k];
-    write(threadIdx.x, t);
+    partial[(blockIdx.x * 2 + which) * (int64_t)S + threadIdx.x] = t;
   }
+  __syncthreads();
 }
 
+template <typename VEC>
 __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t n, int S, const double* __restrict__ B,
                                                     const double* __restrict__ dinv,
                                                     double* __restrict__ X, double* __restrict__ R,
-                                                    double* __restrict__ P, CgState cs, double tol) {
-  __shared__ double sh_rz[kBlock], sh_bb[kBlock];
-  __shared__ int am_last;
+                                                    VEC* __restrict__ P, CgState cs, double tol) {
+  __shared__ double sh[kBlock];
   const int nth = blockDim.x;
   const int64_t total = n * (int64_t)S;
   double rz = 0.0, bb = 0.0;
@@ -39,136 +50,144 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t n, int S, const doub
     const double z = b * dinv[i];
     X[e] = 0.0;
     R[e] = b;
-    P[e] = z;
+    P[e] = (VEC)z;
     rz += b * z;
     bb += b * b;
   }
-  sh_rz[threadIdx.x] = rz;
-  sh_bb[threadIdx.x] = bb;
-  block_reduce_cols(sh_rz, S, nth, [&](int s, double t) { cs.partial[(blockIdx.x * 2) * (int64_t)S + s] = t; });
-  block_reduce_cols(sh_bb, S, nth, [&](int s, double t) { cs.partial[(blockIdx.x * 2 + 1) * (int64_t)S + s] = t; });
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) am_last = atomicAdd(&cs.ticket[1], 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!am_last) return;
-  __threadfence();
-  __shared__ int open;
-  if (threadIdx.x == 0) open = 0;
-  __syncthreads();
-  if ((int)threadIdx.x < S) {
-    const int s = threadIdx.x;
-    double a = 0.0, b2 = 0.0;
-    for (unsigned b = 0; b < gridDim.x; ++b) {
-      a += cs.partial[(b * 2) * (int64_t)S + s];
-      b2 += cs.partial[(b * 2 + 1) * (int64_t)S + s];
-    }
-    cs.rz[s] = a;
-    cs.bb[s] = b2;
-    cs.rr[s] = b2;
-    cs.tol2[s] = tol * tol;
-    cs.iters[s] = 0;
-    cs.alpha[s] = 0.0;
-    cs.beta[s] = 0.0;
-    const int d = (b2 == 0.0) ? 1 : 0;
-    cs.done[s] = d;
-    if (!isfinite(a) || !isfinite(b2)) cs.flags[2] = 1;
-    if (!d) atomicAdd(&open, 1);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    cs.flags[1] = open;
-    cs.ticket[1] = 0u;
-  }
+  block_cols_to_partial(sh, S, rz, cs.partial, 0);
+  block_cols_to_partial(sh, S, bb, cs.partial, 1);
 }
 
+template <typename VEC>
 __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int S, double* __restrict__ X,
-                                                      double* __restrict__ R,
-                                                      const double* __restrict__ P,
-                                                      const double* __restrict__ Q,
+                                                      double* __restrict__ R, const VEC* __restrict__ P,
+                                                      const VEC* __restrict__ Q,
                                                       const double* __restrict__ dinv, CgState cs,
                                                       int32_t iter) {
-  __shared__ double sh_rz[kBlock], sh_rr[kBlock];
-  __shared__ int am_last;
+  __shared__ double sh[kBlock];
   const int nth = blockDim.x;
   const int64_t total = n * (int64_t)S;
-  const int s_me = (blockIdx.x * nth + threadIdx.x) % S;
+  const int s_me = threadIdx.x % S;
   const double a = cs.alpha[s_me];
   double rz = 0.0, rr = 0.0;
   for (int64_t e = blockIdx.x * (int64_t)nth + threadIdx.x; e < total; e += (int64_t)gridDim.x * nth) {
     const int64_t i = e / S;
     double r = R[e];
     if (a != 0.0) {
-      X[e] += a * P[e];
-      r -= a * Q[e];
+      X[e] += a * (double)P[e];
+      r -= a * (double)Q[e];
       R[e] = r;
     }
     rz += r * (r * dinv[i]);
     rr += r * r;
   }
-  sh_rz[threadIdx.x] = rz;
-  sh_rr[threadIdx.x] = rr;
-  block_reduce_cols(sh_rz, S, nth, [&](int s, double t) { cs.partial[(blockIdx.x * 2) * (int64_t)S + s] = t; });
-  block_reduce_cols(sh_rr, S, nth, [&](int s, double t) { cs.partial[(blockIdx.x * 2 + 1) * (int64_t)S + s] = t; });
-  __threadfence();
+  block_cols_to_partial(sh, S, rz, cs.partial, 0);
+  block_cols_to_partial(sh, S, rr, cs.partial, 1);
+}
+
+// ---- finalizers: one workgroup per column, fixed-order sums of the partials ----------
+// Sum of partial[(b * W + which) * S + s] over b < nb (all threads of the workgroup).
+__device__ inline double column_sum(const double* partial, int nb, int W, int which, int S, int s, double* sh) {
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) v += partial[((int64_t)b * W + which) * S + s];
+  sh[threadIdx.x] = v;
   __syncthreads();
-  if (threadIdx.x == 0) am_last = atomicAdd(&cs.ticket[1], 1u) == gridDim.x - 1;
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double t = sh[0];
   __syncthreads();
-  if (!am_last) return;
-  __threadfence();
-  __shared__ int open;
-  if (threadIdx.x == 0) open = 0;
-  __syncthreads();
-  if ((int)threadIdx.x < S) {
-    const int s = threadIdx.x;
-    double rzn = 0.0, rrn = 0.0;
-    for (unsigned b = 0; b < gridDim.x; ++b) {
-      rzn += cs.partial[(b * 2) * (int64_t)S + s];
-      rrn += cs.partial[(b * 2 + 1) * (int64_t)S + s];
-    }
-    double beta = 0.0;
+  return t;
+}
+
+// alpha = r^T z / p^T q for every unfinished column; p^T q <= 0 flags a breakdown
+// (flags[0] = 1, flags[3] = the column).
+__global__ __launch_bounds__(kBlock) void k_cg_alpha(CgState cs, int nb, int S) {
+  __shared__ double sh[kBlock];
+  const int s = blockIdx.x;
+  const double pq = column_sum(cs.partial, nb, 1, 0, S, s, sh);
+  if (threadIdx.x == 0) {
+    double a = 0.0;
     if (!cs.done[s]) {
-      const double al = cs.alpha[s];
-      if (al == 0.0) {
-        cs.done[s] = 1;  // breakdown (flagged by the product step)
+      if (!(pq > 0.0) || !isfinite(pq)) {
+        cs.flags[0] = 1;
+        cs.flags[3] = s;
       } else {
-        beta = rzn / cs.rz[s];
-        if (cs.hist_a && iter < cs.max_hist) {
-          cs.hist_a[(int64_t)iter * S + s] = al;
-          cs.hist_b[(int64_t)iter * S + s] = beta;
-        }
-        cs.iters[s] += 1;
-        cs.rz[s] = rzn;
-        cs.rr[s] = rrn;
-        if (!isfinite(rrn)) {
-          cs.flags[2] = 1;
-          cs.done[s] = 1;
-        } else if (rrn <= cs.tol2[s] * cs.bb[s]) {
-          cs.done[s] = 1;
-        }
+        a = cs.rz[s] / pq;
       }
     }
-    cs.beta[s] = beta;
-    if (!cs.done[s]) atomicAdd(&open, 1);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    cs.flags[1] = open;
-    cs.ticket[1] = 0u;
+    cs.alpha[s] = a;
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, int S, double* __restrict__ P,
+__global__ __launch_bounds__(kBlock) void k_cg_init_fin(CgState cs, int nb, int S, double tol) {
+  __shared__ double sh[kBlock];
+  const int s = blockIdx.x;
+  const double rz = column_sum(cs.partial, nb, 2, 0, S, s, sh);
+  const double bb = column_sum(cs.partial, nb, 2, 1, S, s, sh);
+  if (threadIdx.x == 0) {
+    cs.rz[s] = rz;
+    cs.bb[s] = bb;
+    cs.rr[s] = bb;
+    cs.tol2[s] = tol * tol;
+    cs.iters[s] = 0;
+    cs.alpha[s] = 0.0;
+    cs.beta[s] = 0.0;
+    cs.done[s] = (bb == 0.0) ? 1 : 0;
+    if (!isfinite(rz) || !isfinite(bb)) cs.flags[2] = 1;
+  }
+}
+
+// beta = new r^T z / old r^T z, coefficient history, convergence test.
+__global__ __launch_bounds__(kBlock) void k_cg_beta(CgState cs, int nb, int S, int32_t iter) {
+  __shared__ double sh[kBlock];
+  const int s = blockIdx.x;
+  const double rzn = column_sum(cs.partial, nb, 2, 0, S, s, sh);
+  const double rrn = column_sum(cs.partial, nb, 2, 1, S, s, sh);
+  if (threadIdx.x != 0) return;
+  double beta = 0.0;
+  if (!cs.done[s]) {
+    const double al = cs.alpha[s];
+    if (al == 0.0) {
+      cs.done[s] = 1;  // breakdown (flagged by the product step)
+    } else {
+      beta = rzn / cs.rz[s];
+      if (cs.hist_a && iter < cs.max_hist) {
+        cs.hist_a[(int64_t)iter * S + s] = al;
+        cs.hist_b[(int64_t)iter * S + s] = beta;
+      }
+      cs.iters[s] += 1;
+      cs.rz[s] = rzn;
+      cs.rr[s] = rrn;
+      if (!isfinite(rrn)) {
+        cs.flags[2] = 1;
+        cs.done[s] = 1;
+      } else if (rrn <= cs.tol2[s] * cs.bb[s]) {
+        cs.done[s] = 1;
+      }
+    }
+  }
+  cs.beta[s] = beta;
+}
+
+hipError_t launch_cg_alpha(const CgState& cs, int nb, int S, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_alpha, dim3(S), dim3(kBlock), 0, st, cs, nb, S);
+  return hipGetLastError();
+}
+
+template <typename VEC>
+__global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, int S, VEC* __restrict__ P,
                                                        const double* __restrict__ R,
                                                        const double* __restrict__ dinv, CgState cs) {
   const int nth = blockDim.x;
   const int64_t total = n * (int64_t)S;
-  const int s_me = (blockIdx.x * nth + threadIdx.x) % S;
+  const int s_me = threadIdx.x % S;
   if (cs.done[s_me]) return;
   const double b = cs.beta[s_me];
   for (int64_t e = blockIdx.x * (int64_t)nth + threadIdx.x; e < total; e += (int64_t)gridDim.x * nth) {
     const int64_t i = e / S;
-    P[e] = R[e] * dinv[i] + b * P[e];
+    P[e] = (VEC)(R[e] * dinv[i] + b * (double)P[e]);
   }
 }
 
@@ -179,28 +198,55 @@ static unsigned reduce_blocks(int64_t total, int nth) {
   return (unsigned)b;
 }
 
+// Streaming CG kernels over n * S elements: enough workgroups to fill the chip,
+// bounded by the partial-sum buffer.
+static unsigned cg_blocks(int64_t total, int nth) {
+  int64_t b = (total + 4 * (int64_t)nth - 1) / (4 * (int64_t)nth);
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
 hipError_t launch_cg_init(int64_t n, int S, const double* B, const double* dinv, double* X, double* R,
-                          double* P, const CgState& cs, const double* tol, hipStream_t st) {
+                          void* P, bool f32vec, const CgState& cs, double tol, hipStream_t st) {
   const int nth = cols_block(S);
-  hipLaunchKernelGGL(k_cg_init, dim3(reduce_blocks(n * S, nth)), dim3(nth), 0, st, n, S, B, dinv, X, R,
-                     P, cs, *tol);
+  const unsigned nb = cg_blocks(n * S, nth);
+  if (f32vec)
+    hipLaunchKernelGGL(k_cg_init<float>, dim3(nb), dim3(nth), 0, st, n, S, B, dinv, X, R,
+                       static_cast<float*>(P), cs, tol);
+  else
+    hipLaunchKernelGGL(k_cg_init<double>, dim3(nb), dim3(nth), 0, st, n, S, B, dinv, X, R,
+                       static_cast<double*>(P), cs, tol);
+  hipLaunchKernelGGL(k_cg_init_fin, dim3(S), dim3(kBlock), 0, st, cs, (int)nb, S, tol);
   return hipGetLastError();
 }
 
-hipError_t launch_cg_update(int64_t n, int S, double* X, double* R, const double* P, const double* Q,
+hipError_t launch_cg_update(int64_t n, int S, double* X, double* R, const void* P, const void* Q, bool f32vec,
                             const double* dinv, const CgState& cs, int32_t iter, hipStream_t st) {
   const int nth = cols_block(S);
-  hipLaunchKernelGGL(k_cg_update, dim3(reduce_blocks(n * S, nth)), dim3(nth), 0, st, n, S, X, R, P, Q,
-                     dinv, cs, iter);
+  const unsigned nb = cg_blocks(n * S, nth);
+  if (f32vec)
+    hipLaunchKernelGGL(k_cg_update<float>, dim3(nb), dim3(nth), 0, st, n, S, X, R,
+                       static_cast<const float*>(P), static_cast<const float*>(Q), dinv, cs, iter);
+  else
+    hipLaunchKernelGGL(k_cg_update<double>, dim3(nb), dim3(nth), 0, st, n, S, X, R,
+                       static_cast<const double*>(P), static_cast<const double*>(Q), dinv, cs, iter);
+  hipLaunchKernelGGL(k_cg_beta, dim3(S), dim3(kBlock), 0, st, cs, (int)nb, S, iter);
   return hipGetLastError();
 }
 
-hipError_t launch_cg_pupdate(int64_t n, int S, double* P, const double* R, const double* dinv,
+hipError_t launch_cg_pupdate(int64_t n, int S, void* P, const double* R, const double* dinv, bool f32vec,
                              const CgState& cs, hipStream_t st) {
   const int nth = cols_block(S);
-  int64_t blocks = (n * S + nth - 1) / nth;
+  int64_t blocks = (n * S + 4 * (int64_t)nth - 1) / (4 * (int64_t)nth);
   if (blocks > (1 << 16)) blocks = 1 << 16;
-  hipLaunchKernelGGL(k_cg_pupdate, dim3((unsigned)blocks), dim3(nth), 0, st, n, S, P, R, dinv, cs);
+  if (blocks < 1) blocks = 1;
+  if (f32vec)
+    hipLaunchKernelGGL(k_cg_pupdate<float>, dim3((unsigned)blocks), dim3(nth), 0, st, n, S,
+                       static_cast<float*>(P), R, dinv, cs);
+  else
+    hipLaunchKernelGGL(k_cg_pupdate<double>, dim3((unsigned)blocks), dim3(nth), 0, st, n, S,
+                       static_cast<double*>(P), R, dinv, cs);
   return hipGetLastError();
 }
 
@@ -251,12 +297,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce(int64_t n, const double* __re
   __syncthreads();
   if (!am_last) return;
   __threadfence();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (unsigned k = 0; k < gridDim.x; ++k) t += partial[k];
-    out[0] = t;
-    *ticket = 0u;
-  }
+  reduce_partials(partial, gridDim.x, 1, sh, [&](int, double t) { out[0] = t; });
+  if (threadIdx.x == 0) *ticket = 0u;
 }
 
 hipError_t launch_dot_partial(int64_t n, const double* a, const double* b, double* out, uint32_t* ticket,

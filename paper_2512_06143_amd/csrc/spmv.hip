@@ -2,11 +2,13 @@
 // a group of G lanes per row) and blocks of up to 64 right-hand sides (one wave per
 // row, one lane per column). These drive the solve K a = y and the probe solves of
 // the log-determinant (Sec. 3.5; App. B.6 "MINRES", "LOGDET"). Stored values
-// (float32 or float64) multiply float64 vectors and accumulate in float64.
+// (float32 or float64) multiply the vectors and accumulate in float64.
 //
-// The CG variants also produce p^T q per column from fixed per-workgroup partial
-// sums; the last workgroup to finish (ticket counter) reduces them in workgroup
-// order, so results are bitwise reproducible.
+// Both are bandwidth kernels: loads are issued in independent groups of four or
+// eight so that enough gathers are in flight per wave, and grids are large enough to
+// keep every CU's wave slots busy. The CG variants also write p^T q per column as
+// fixed per-workgroup partial sums; a finalize kernel (pcg.hip) reduces them in
+// workgroup order, so results are bitwise reproducible.
 #include "gp2s_internal.h"
 
 namespace gp2s {
@@ -24,13 +26,23 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int64_t* __restrict__ rp,
                                                  const double* __restrict__ x,
                                                  double* __restrict__ y, CgState cs) {
   const int lane = threadIdx.x & (G - 1);
-  const int64_t group = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
-  const int64_t ngroups = (int64_t)gridDim.x * blockDim.x / G;
+  const XcdRows rr = xcd_rows(n, threadIdx.x / G, kBlock / G);
   double dot = 0.0;
-  for (int64_t row = group; row < n; row += ngroups) {
+  for (int64_t row = rr.first; row < rr.end; row += rr.step) {
     const int64_t s = rp[row], e = rp[row + 1];
-    double acc = 0.0;
-    for (int64_t k = s + lane; k < e; k += G) acc += ld(val, k) * x[col[k]];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int64_t k = s + lane;
+    for (; k + 3 * G < e; k += 4 * G) {
+      const int32_t c0 = col[k], c1 = col[k + G], c2 = col[k + 2 * G], c3 = col[k + 3 * G];
+      const double v0 = ld(val, k), v1 = ld(val, k + G), v2 = ld(val, k + 2 * G), v3 = ld(val, k + 3 * G);
+      const double x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
+      a0 += v0 * x0;
+      a1 += v1 * x1;
+      a2 += v2 * x2;
+      a3 += v3 * x3;
+    }
+    for (; k < e; k += G) a0 += ld(val, k) * x[col[k]];
+    double acc = (a0 + a1) + (a2 + a3);
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
     if (lane == 0) {
@@ -39,9 +51,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int64_t* __restrict__ rp,
     }
   }
   if (!DOT) return;
-  // p^T q partial of this workgroup, then alpha in the last workgroup.
+  // p^T q partial of this workgroup; alpha is formed by launch_cg_alpha.
   __shared__ double sh[kBlock];
-  __shared__ int am_last;
   sh[threadIdx.x] = dot;
   __syncthreads();
   for (int o = kBlock / 2; o > 0; o >>= 1) {
@@ -49,46 +60,26 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int64_t* __restrict__ rp,
     __syncthreads();
   }
   if (threadIdx.x == 0) cs.partial[blockIdx.x] = sh[0];
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) am_last = atomicAdd(&cs.ticket[0], 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!am_last) return;
-  __threadfence();
-  if (threadIdx.x == 0) {
-    double pq = 0.0;
-    for (unsigned b = 0; b < gridDim.x; ++b) pq += cs.partial[b];
-    double a = 0.0;
-    if (!cs.done[0]) {
-      if (!(pq > 0.0) || !isfinite(pq)) {
-        cs.flags[0] = 1;
-      } else {
-        a = cs.rz[0] / pq;
-      }
-    }
-    cs.alpha[0] = a;
-    cs.ticket[0] = 0u;
-  }
 }
 
+// Lanes per row: about half the mean row length, a power of two in [4, 64].
 static int pick_group(double mean_row) {
-  if (mean_row <= 6) return 4;
-  if (mean_row <= 12) return 8;
-  if (mean_row <= 24) return 16;
-  if (mean_row <= 48) return 32;
-  return 64;
+  int g = 4;
+  while (g < 64 && 2 * g <= mean_row / 2.0 + 1e-9) g *= 2;
+  return g;
 }
 
 template <typename V, bool DOT>
 static hipError_t spmv_dispatch(const int64_t* rp, const int32_t* col, const V* val, int64_t n,
                                 double mean_row, const double* x, double* y, const CgState& cs,
-                                hipStream_t st) {
+                                hipStream_t st, int* nblocks = nullptr) {
   const int G = pick_group(mean_row);
   int64_t groups_per_block = kBlock / G;
   int64_t blocks = (n + groups_per_block - 1) / groups_per_block;
-  if (DOT && blocks > kReduceBlocks) blocks = kReduceBlocks;
-  if (blocks > (1 << 20)) blocks = 1 << 20;
-  if (blocks < 1) blocks = 1;
+  const int64_t cap = DOT ? kReduceBlocks : (1 << 20);
+  if (blocks > cap) blocks = cap;
+  blocks = round_up8(blocks < 1 ? 1 : blocks);
+  if (nblocks) *nblocks = (int)blocks;
   dim3 grid((unsigned)blocks), block(kBlock);
   switch (G) {
     case 4: hipLaunchKernelGGL((k_spmv<4, V, DOT>), grid, block, 0, st, rp, col, val, n, x, y, cs); break;
@@ -109,87 +100,100 @@ hipError_t launch_spmv(int prec, const int64_t* rp, const int32_t* col, const vo
 }
 
 // ---- blocks of S <= 64 right-hand sides --------------------------------------------------
-// X, Y row-major [n * S]. One wave per row; lane s owns column s. The row's column
-// indices and values are loaded 64 at a time (one per lane) and broadcast with
-// readlane, so every lane streams X[j * S + s] for the same j: one coalesced row of X.
-__device__ inline double bcast_f64(double v, int l) {
+// X, Y row-major [n * S] (float32 or float64 vectors). One wave per row; lane s owns
+// column s. The row's column offsets (j * S) and values are loaded 64 at a time (one
+// per lane) and broadcast with readlane, so every lane reads X[j * S + s] for the
+// same j: one coalesced row of X per stored entry, eight rows in flight per wave.
+// The loop is bound by vector-instruction issue, not memory: per stored entry it
+// costs two readlanes, one load and one multiply-add. float32 vectors accumulate in
+// float32 (their products are stored in float32 anyway).
+__device__ inline double bcast_acc(double v, int l) {
   int2 p = __builtin_bit_cast(int2, v);
   p.x = __builtin_amdgcn_readlane(p.x, l);
   p.y = __builtin_amdgcn_readlane(p.y, l);
   return __builtin_bit_cast(double, p);
 }
+__device__ inline float bcast_acc(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
 
-template <typename V, bool DOT>
+constexpr int kSpmmUnroll = 8;
+
+// Accumulator type of the block product: float32 when the vectors are float32 (the
+// probe block of the mixed path), float64 otherwise.
+template <typename VEC>
+struct AccOf {
+  using type = double;
+};
+template <>
+struct AccOf<float> {
+  using type = float;
+};
+
+template <typename V, typename VEC, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_spmm(const int64_t* __restrict__ rp,
                                                  const int32_t* __restrict__ col,
                                                  const V* __restrict__ val, int64_t n, int S,
-                                                 const double* __restrict__ X,
-                                                 double* __restrict__ Y, CgState cs) {
+                                                 const VEC* __restrict__ X,
+                                                 VEC* __restrict__ Y, CgState cs) {
+  using Acc = typename AccOf<VEC>::type;
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
-  const int64_t wave = blockIdx.x * (int64_t)(kBlock / kWave) + wid;
-  const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+  const XcdRows rr = xcd_rows(n, wid, kBlock / kWave);
   const bool active = lane < S;
+  const int ls = active ? lane : 0;
+  const VEC* __restrict__ Xl = X + ls;  // this lane's column
   double dot = 0.0;
-  for (int64_t row = wave; row < n; row += nwaves) {
+  for (int64_t row = rr.first; row < rr.end; row += rr.step) {
     const int64_t s = rp[row], e = rp[row + 1];
-    double acc = 0.0;
+    Acc acc = 0;
     for (int64_t k0 = s; k0 < e; k0 += kWave) {
+      // one stored entry per lane: row offset of its column in X (n * S < 2^31) and value
       const int64_t k = k0 + lane;
-      const int32_t cj = k < e ? col[k] : 0;
-      const double vj = k < e ? ld(val, k) : 0.0;
+      const int32_t off = k < e ? col[k] * S : 0;
+      const Acc vj = k < e ? (Acc)val[k] : (Acc)0;
       const int cnt = (int)((e - k0) < kWave ? (e - k0) : kWave);
-      for (int l = 0; l < cnt; ++l) {
-        const int32_t j = __builtin_amdgcn_readlane(cj, l);
-        const double v = bcast_f64(vj, l);
-        if (active) acc += v * X[(int64_t)j * S + lane];
+      int l = 0;
+      for (; l + kSpmmUnroll <= cnt; l += kSpmmUnroll) {
+        Acc xv[kSpmmUnroll], vv[kSpmmUnroll];
+#pragma unroll
+        for (int u = 0; u < kSpmmUnroll; ++u) {
+          vv[u] = bcast_acc(vj, l + u);
+          xv[u] = (Acc)Xl[__builtin_amdgcn_readlane(off, l + u)];
+        }
+#pragma unroll
+        for (int u = 0; u < kSpmmUnroll; ++u) acc += vv[u] * xv[u];
       }
+      for (; l < cnt; ++l) acc += bcast_acc(vj, l) * (Acc)Xl[__builtin_amdgcn_readlane(off, l)];
     }
     if (active) {
-      Y[row * S + lane] = acc;
-      if (DOT) dot += acc * X[row * S + lane];
+      const VEC q = (VEC)acc;
+      Y[row * S + lane] = q;
+      if (DOT) dot += (double)q * (double)X[row * S + lane];
     }
   }
   if (!DOT) return;
-  __shared__ double sh[kBlock / kWave][kWave];
-  __shared__ int am_last;
-  sh[wid][lane] = dot;
+  // per-column p^T q partials of this workgroup; alpha is formed by launch_cg_alpha.
+  __shared__ double sh[kBlock];
+  sh[threadIdx.x] = dot;
   __syncthreads();
-  if (wid == 0) {
-    double t = 0.0;
-    for (int w = 0; w < kBlock / kWave; ++w) t += sh[w][lane];
-    if (active) cs.partial[blockIdx.x * (int64_t)S + lane] = t;
-  }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) am_last = atomicAdd(&cs.ticket[0], 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!am_last) return;
-  __threadfence();
   if (wid == 0 && active) {
-    double pq = 0.0;
-    for (unsigned b = 0; b < gridDim.x; ++b) pq += cs.partial[b * (int64_t)S + lane];
-    double a = 0.0;
-    if (!cs.done[lane]) {
-      if (!(pq > 0.0) || !isfinite(pq)) {
-        cs.flags[0] = 1;
-      } else {
-        a = cs.rz[lane] / pq;
-      }
-    }
-    cs.alpha[lane] = a;
+    double t = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += sh[w * kWave + lane];
+    cs.partial[blockIdx.x * (int64_t)S + lane] = t;
   }
-  if (threadIdx.x == 0) cs.ticket[0] = 0u;
 }
 
-template <typename V, bool DOT>
+template <typename V, typename VEC, bool DOT>
 static hipError_t spmm_dispatch(const int64_t* rp, const int32_t* col, const V* val, int64_t n, int S,
-                                const double* X, double* Y, const CgState& cs, hipStream_t st) {
+                                const VEC* X, VEC* Y, const CgState& cs, hipStream_t st,
+                                int* nblocks = nullptr) {
   int64_t blocks = (n + (kBlock / kWave) - 1) / (kBlock / kWave);
   const int64_t cap = DOT ? kReduceBlocks : (1 << 20);
   if (blocks > cap) blocks = cap;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((k_spmm<V, DOT>), dim3((unsigned)blocks), dim3(kBlock), 0, st, rp, col, val, n, S,
+  blocks = round_up8(blocks < 1 ? 1 : blocks);
+  if (nblocks) *nblocks = (int)blocks;
+  hipLaunchKernelGGL((k_spmm<V, VEC, DOT>), dim3((unsigned)blocks), dim3(kBlock), 0, st, rp, col, val, n, S,
                      X, Y, cs);
   return hipGetLastError();
 }
@@ -198,21 +202,36 @@ hipError_t launch_spmm(int prec, const int64_t* rp, const int32_t* col, const vo
                        int S, const double* X, double* Y, hipStream_t st) {
   CgState cs{};
   if (prec == GP2S_MIXED)
-    return spmm_dispatch<float, false>(rp, col, static_cast<const float*>(val), n, S, X, Y, cs, st);
-  return spmm_dispatch<double, false>(rp, col, static_cast<const double*>(val), n, S, X, Y, cs, st);
+    return spmm_dispatch<float, double, false>(rp, col, static_cast<const float*>(val), n, S, X, Y, cs, st);
+  return spmm_dispatch<double, double, false>(rp, col, static_cast<const double*>(val), n, S, X, Y, cs, st);
 }
 
 hipError_t launch_cg_matvec(int prec, const int64_t* rp, const int32_t* col, const void* val,
-                            int64_t n, int S, double mean_row, const double* P, double* Q,
+                            int64_t n, int S, double mean_row, const void* P, void* Q, bool f32vec,
                             const CgState& cs, hipStream_t st) {
+  int nb = 0;
+  hipError_t e;
   if (S == 1) {
+    // single right-hand side: always float64 vectors
     if (prec == GP2S_MIXED)
-      return spmv_dispatch<float, true>(rp, col, static_cast<const float*>(val), n, mean_row, P, Q, cs, st);
-    return spmv_dispatch<double, true>(rp, col, static_cast<const double*>(val), n, mean_row, P, Q, cs, st);
+      e = spmv_dispatch<float, true>(rp, col, static_cast<const float*>(val), n, mean_row,
+                                     static_cast<const double*>(P), static_cast<double*>(Q), cs, st, &nb);
+    else
+      e = spmv_dispatch<double, true>(rp, col, static_cast<const double*>(val), n, mean_row,
+                                      static_cast<const double*>(P), static_cast<double*>(Q), cs, st, &nb);
+  } else if (prec == GP2S_MIXED) {
+    if (f32vec)
+      e = spmm_dispatch<float, float, true>(rp, col, static_cast<const float*>(val), n, S,
+                                            static_cast<const float*>(P), static_cast<float*>(Q), cs, st, &nb);
+    else
+      e = spmm_dispatch<float, double, true>(rp, col, static_cast<const float*>(val), n, S,
+                                             static_cast<const double*>(P), static_cast<double*>(Q), cs, st, &nb);
+  } else {
+    e = spmm_dispatch<double, double, true>(rp, col, static_cast<const double*>(val), n, S,
+                                            static_cast<const double*>(P), static_cast<double*>(Q), cs, st, &nb);
   }
-  if (prec == GP2S_MIXED)
-    return spmm_dispatch<float, true>(rp, col, static_cast<const float*>(val), n, S, P, Q, cs, st);
-  return spmm_dispatch<double, true>(rp, col, static_cast<const double*>(val), n, S, P, Q, cs, st);
+  if (e != hipSuccess) return e;
+  return launch_cg_alpha(cs, nb, S, st);
 }
 
 }  // namespace gp2s

@@ -29,6 +29,8 @@ GP2S_FP64, GP2S_MIXED = 0, 1
 PRECISIONS = {"fp64": GP2S_FP64, "mixed": GP2S_MIXED}
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_char_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                               ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
@@ -75,6 +77,7 @@ _SIGS = {
     "gp2s_last_error": (ctypes.c_char_p, [_vp]),
     "gp2s_check_params": (_i32, [_vp, _i64, ctypes.POINTER(Params)]),
     "gp2s_set_timing": (_i32, [_vp, _i32]),
+    "gp2s_set_progress": (_i32, [_vp, PROGRESS_FN, _vp]),
     "gp2s_get_stats": (_i32, [_vp, ctypes.POINTER(Stats)]),
     "gp2s_assemble": (_i32, [_vp, _i64, _vp, ctypes.POINTER(Params), _i32, ctypes.POINTER(_vp)]),
     "gp2s_matrix_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
@@ -179,6 +182,14 @@ class Context:
 
     def set_timing(self, enable=True):
         self.check(lib.gp2s_set_timing(self.ptr, 1 if enable else 0))
+
+    def set_progress(self, fn=None):
+        """fn(label: str, iters: int, open_cols: int, max_rel_resid: float) or None."""
+        if fn is None:
+            self._progress = PROGRESS_FN()
+        else:
+            self._progress = PROGRESS_FN(lambda lab, it, op, res, user: fn(lab.decode(), it, op, res))
+        self.check(lib.gp2s_set_progress(self.ptr, self._progress, None))
 
     def stats(self) -> dict:
         st = Stats()

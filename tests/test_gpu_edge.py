@@ -1,0 +1,187 @@
+"""Edge cases and error paths of the HIP path, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import compare_patterns, exported_user_csr, params_of, pattern_pairs
+
+pytestmark = pytest.mark.gpu
+
+
+def _G():
+    import paper_2512_06143_amd as G
+    return G
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_single_point(gpu, precision):
+    """n = 1: K = g^2 + sigma^2; everything in closed form."""
+    G = _G()
+    x = np.array([[0.3, 0.4]])
+    c = np.array([[0.35, 0.45]])
+    w = np.array([1.3])
+    p = G.HostParams(2, 0.1, 0.5, 1e-3, c, w)
+    g, b, _ = oracle.bump_values(x, c, 0.5, w)
+    k = g[0] ** 2 + 1e-3
+    m = G.gp2s_assemble(x, p, precision)
+    assert (m.n, m.nnz) == (1, 1)
+    y = np.array([0.7])
+    rep, grad, a = G.gp2s_lml_grad(m, y, G.default_opts(n_probes=4))
+    tol = 1e-6 if precision == "mixed" else 1e-12
+    assert a.cpu().numpy()[0] == pytest.approx(0.7 / k, rel=tol)
+    assert rep.logdet == pytest.approx(math.log(k), rel=tol)
+    assert rep.lml == pytest.approx(-0.5 * 0.49 / k - 0.5 * math.log(k) - 0.5 * math.log(2 * math.pi), rel=tol)
+    av = 0.7 / k
+    dk = 2 * g[0] * b[0, 0]
+    np.testing.assert_allclose(grad, [0.0, 0.5 * av * av * dk - 0.5 * dk / k, 0.5 * av * av - 0.5 / k],
+                               rtol=1e-5 if precision == "mixed" else 1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_points_outside_every_bump(gpu, precision):
+    """No point inside a bump: K = sigma^2 I, only diagonals are stored."""
+    G = _G()
+    prob = workloads.make_random_problem(3, 500, 2, 0.1, n_bumps=2, bump_width=0.6)
+    p = G.HostParams(2, 0.1, 0.6, 2e-3, np.array([[5.0, 5.0], [-4.0, 3.0]]), np.array([1.0, 2.0]))
+    m = G.gp2s_assemble(prob.x, p, precision)
+    assert m.nnz == prob.n
+    rep, grad, a = G.gp2s_lml_grad(m, prob.y, G.default_opts(n_probes=8))
+    # the stored diagonal is sigma^2 rounded to the path's precision
+    d = float(np.float32(2e-3)) if precision == "mixed" else 2e-3
+    np.testing.assert_allclose(a.cpu().numpy(), prob.y / d, rtol=1e-12)
+    assert rep.logdet == pytest.approx(prob.n * math.log(d), rel=1e-12)
+    assert grad[0] == 0.0 and grad[1] == 0.0 and grad[2] == 0.0
+    assert grad[3] == pytest.approx(0.5 * np.sum(prob.y ** 2) / d ** 2 - 0.5 * prob.n / d, rel=1e-9)
+
+
+def test_duplicates_and_clamped_points(gpu):
+    """Exact duplicates (clamped to the cube faces) stay legal: pattern, values, SPD."""
+    G = _G()
+    rng = np.random.default_rng(4)
+    x = np.clip(rng.normal(0.5, 0.4, size=(1500, 2)), 0, 1)
+    x = workloads.f32(np.concatenate([x, x[:100]]))
+    prob = workloads.Problem("dup", x, np.sin(x[:, 0]), 0.06, 0.7, np.array([[0.5, 0.5]]), np.array([1.1]),
+                             1e-3)
+    for precision in ("fp64", "mixed"):
+        m = G.gp2s_assemble(prob.x, params_of(prob), precision)
+        Kg, _ = exported_user_csr(m)
+        Kref = oracle.covariance_csr(prob.x, prob.radius, prob.bump_width, prob.centers, prob.weights,
+                                     prob.noise_var)
+        ex_pts = oracle.boundary_exempt_points(prob.x, prob.centers, prob.bump_width)
+        nmis, _ = compare_patterns(pattern_pairs(Kg), pattern_pairs(Kref), prob.x, prob, ex_pts)
+        assert nmis == 0
+        d = abs(Kg - Kref)
+        assert d.max() <= (1e-5 if precision == "mixed" else 1e-12) * abs(Kref).max()
+        a, rep = G.gp2s_solve(m, prob.y)
+        assert oracle.residual_rel(Kg, a.cpu().numpy(), prob.y) <= 1e-8
+
+
+def test_nonfinite_inputs_rejected(gpu):
+    G = _G()
+    prob = workloads.make_random_problem(5, 200, 2, 0.1)
+    x = prob.x.copy()
+    x[17, 1] = np.nan
+    with pytest.raises(G.GP2SError) as e:
+        G.gp2s_assemble(x, params_of(prob), "mixed")
+    assert e.value.status == 7
+    m = G.gp2s_assemble(prob.x, params_of(prob), "mixed")
+    y = prob.y.copy()
+    y[3] = np.inf
+    with pytest.raises(G.GP2SError) as e:
+        G.gp2s_solve(m, y)
+    assert e.value.status == 7
+
+
+def test_max_iter_reports_noconv(gpu):
+    G = _G()
+    prob = workloads.make_problem("c1")
+    m = G.gp2s_assemble(prob.x, params_of(prob), "fp64")
+    with pytest.raises(G.GP2SError) as e:
+        G.gp2s_solve(m, prob.y, G.default_opts(max_iter=3, max_ir=0))
+    assert e.value.status == 6
+    a, rep = G.gp2s_solve(m, prob.y, G.default_opts(max_iter=3, max_ir=0), allow_noconv=True)
+    assert rep.status == 6 and rep.iters == 3 and 0 < rep.resid < 1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_imported_oracle_matrix(gpu, precision):
+    """The solver and the log-determinant on the oracle's own CSR (user order)."""
+    G = _G()
+    prob = workloads.make_random_problem(6, 1800, 2, 0.06, n_bumps=3, bump_width=0.5)
+    K = oracle.covariance_csr(prob.x, prob.radius, prob.bump_width, prob.centers, prob.weights, prob.noise_var)
+    Kt = K.astype(np.float32).astype(np.float64) if precision == "mixed" else K
+    m = G.gp2s_matrix_import(K.indptr, K.indices, K.data, precision)
+    X = np.random.default_rng(1).standard_normal((prob.n, 5))
+    np.testing.assert_allclose(G.gp2s_spmv(m, X).cpu().numpy(), Kt @ X, rtol=1e-12, atol=1e-12)
+    rep, a = G.gp2s_lml(m, prob.y, G.default_opts(n_probes=8, seed=2, tol=1e-10, probe_tol=1e-9))
+    Z = oracle.rademacher_probes(2, 8, prob.n)
+    gam, _ = oracle.logdet_same_probe(Kt.toarray(), Z)
+    assert abs(rep.logdet - gam) <= 1e-8 * abs(gam)
+    assert oracle.residual_rel(Kt, a.cpu().numpy(), prob.y) <= 1e-10
+    with pytest.raises(G.GP2SError) as e:
+        G.gp2s_lml_grad(m, prob.y)
+    assert e.value.status == 1
+
+
+def test_import_rejects_bad_csr(gpu):
+    G = _G()
+    rp = np.array([0, 1, 2, 3])
+    with pytest.raises(G.GP2SError) as e:  # row 1 lacks its diagonal
+        G.gp2s_matrix_import(rp, np.array([0, 0, 2]), np.array([1.0, 0.5, 1.0]))
+    assert e.value.status == 1
+    with pytest.raises(G.GP2SError) as e:  # column out of range
+        G.gp2s_matrix_import(rp, np.array([0, 1, 7]), np.array([1.0, 1.0, 1.0]))
+    assert e.value.status == 1
+
+
+def test_indefinite_matrix_reports_not_spd(gpu):
+    """A symmetric indefinite matrix: CG meets p^T K p <= 0 (or a non-positive diagonal)."""
+    G = _G()
+    import scipy.sparse as sp
+    A = sp.csr_matrix(np.array([[1.0, 2.0, 0.0], [2.0, 1.0, 0.0], [0.0, 0.0, 1.0]]))
+    m = G.gp2s_matrix_import(A.indptr, A.indices, A.data)
+    with pytest.raises(G.GP2SError) as e:
+        G.gp2s_solve(m, np.array([1.0, -1.0, 0.5]))
+    assert e.value.status == 5
+    B = sp.csr_matrix(np.array([[-1.0, 0.0], [0.0, 1.0]]))
+    m = G.gp2s_matrix_import(B.indptr, B.indices, B.data)
+    with pytest.raises(G.GP2SError) as e:
+        G.gp2s_solve(m, np.array([1.0, 1.0]))
+    assert e.value.status == 5
+
+
+def test_autograd_function(gpu):
+    """GP2SLML: forward value and backward gradients equal gp2s_lml_grad's; the
+    gradient agrees with central differences of the exact dense LML within the
+    Hutchinson standard deviation."""
+    import torch
+    G = _G()
+    prob = workloads.make_random_problem(8, 600, 2, 0.09, n_bumps=3, bump_width=0.5, noise_var=1e-3)
+    S = 64
+    opts = G.default_opts(n_probes=S, seed=11, tol=1e-10, probe_tol=1e-9)
+    r = torch.tensor(prob.radius, dtype=torch.float64, requires_grad=True)
+    wts = torch.tensor(prob.weights, dtype=torch.float64, requires_grad=True)
+    nv = torch.tensor(prob.noise_var, dtype=torch.float64, requires_grad=True)
+    x = torch.as_tensor(prob.x).cuda()
+    y = torch.as_tensor(prob.y).cuda()
+    val = G.lml(x, y, r, wts, nv, prob.centers, prob.bump_width, "fp64", opts)
+    val.backward()
+    grad = np.concatenate([[r.grad.item()], wts.grad.numpy(), [nv.grad.item()]])
+    m = G.gp2s_assemble(prob.x, params_of(prob), "fp64")
+    rep, g2, _ = G.gp2s_lml_grad(m, prob.y, opts)
+    assert val.item() == rep.lml
+    np.testing.assert_array_equal(grad, g2)
+    # exact gradient and its Hutchinson spread
+    ge, parts = oracle.grad_exact(prob.x, prob.y, prob.radius, prob.bump_width, prob.centers, prob.weights,
+                                  prob.noise_var)
+    K, dKs = oracle.dcov_dense(prob.x, prob.radius, prob.bump_width, prob.centers, prob.weights, prob.noise_var)
+    D = np.diag(K)
+    Kinv = np.linalg.inv(K)
+    for k, dK in enumerate(dKs):
+        A = np.sqrt(D)[:, None] * (Kinv @ dK) / np.sqrt(D)[None, :]
+        A = 0.5 * (A + A.T)
+        sd = 0.5 * math.sqrt(oracle.hutchinson_variance(A, S))
+        assert abs(grad[k] - ge[k]) <= 4 * sd + 1e-7 * abs(ge[k]), (k, grad[k], ge[k], sd)
