@@ -48,6 +48,32 @@ def kernel_bytes(cat, n, nnz, S, prec):
     return None
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c2_mixed.md")
+TRAFFIC_KERNEL = {"cg_matvec_block": "k_spmm<float, float, true>", "cg_update_block": "k_cg_update<float>",
+                  "cg_pupdate_block": "k_cg_pupdate<float>", "cg_matvec1": "k_spmv<16, float, true>"}
+
+
+def measured_traffic(cat, config, precision):
+    """Scaled FETCH_SIZE + WRITE_SIZE bytes per dispatch from the committed rocprofv3
+    summary, or None when it does not cover this kernel/workload or the kernel
+    sources changed since the counters were taken."""
+    import hashlib
+    if config != "c2" or precision != "mixed" or cat not in TRAFFIC_KERNEL or not os.path.exists(TRAFFIC_FILE):
+        return None
+    h = hashlib.sha256()
+    for fn in ("spmv.hip", "pcg.hip"):
+        with open(os.path.join(ROOT, "paper_2512_06143_amd", "csrc", fn), "rb") as fh:
+            h.update(fh.read())
+    text = open(TRAFFIC_FILE).read()
+    if f"kernel-source-sha256: {h.hexdigest()}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith(f"| `{TRAFFIC_KERNEL[cat]}` |"):
+            cells = [c.strip() for c in line.strip("|").split("|")]
+            return (float(cells[2]) + float(cells[5])) * 1e6
+    return None
+
+
 def make_inputs(args):
     import numpy as np
     import workloads
@@ -197,7 +223,8 @@ def main():
     roof = None
     if b is not None:
         roof = {"kernel": dom, "bound": "hbm", "achieved": b / avg_s / 1e9, "peak": PEAK_HBM / 1e9,
-                "unit": "GB/s", "frac": b / avg_s / PEAK_HBM, "traffic": None,
+                "unit": "GB/s", "frac": b / avg_s / PEAK_HBM,
+                "traffic": measured_traffic(dom, args.config, args.precision),
                 "bytes_per_launch": b, "avg_ms": avg_s * 1e3, "launches": cnt}
     asm_ms = sum(stats[k][0] for k in ("asm_prep", "asm_count", "asm_fill")) / args.steps
     mv1 = stats["cg_matvec1"]
