@@ -33,18 +33,19 @@ def log(msg):
 def kernel_bytes(cat, n, nnz, S, prec):
     """Algorithmic HBM bytes of one launch of a timed kernel category: the CSR once,
     each vector stream once, at the types the path stores them in (the probe block
-    of the mixed path keeps directions P and products Q in float32)."""
-    vb = 4 if prec == "mixed" else 8                  # stored K value
-    pb = 4 if (prec == "mixed" and "block" in cat) else 8   # P / Q element
+    of the mixed path keeps its search directions P in float32; products Q, x and r
+    are float64)."""
+    vb = 4 if prec == "mixed" else 8                        # stored K value
+    pb = 4 if (prec == "mixed" and "block" in cat) else 8   # P element
     K = nnz * (4 + vb) + (n + 1) * 8
     if cat in ("cg_matvec_block", "cg_matvec1", "spmv"):
-        return K + n * S * pb * 2            # read P once, write Q
+        return K + n * S * (pb + 8)                 # read P once, write Q
     if cat in ("cg_update_block", "cg_update1"):
-        return n * S * (8 * 4 + pb * 2) + n * 8   # X, R read+write; P, Q read; 1/diag
+        return n * S * (8 * 4 + pb + 8) + n * 8     # X, R read+write; P, Q read; 1/diag
     if cat in ("cg_pupdate_block", "cg_pupdate1"):
-        return n * S * (8 + pb * 2) + n * 8       # R read; P read+write; 1/diag
+        return n * S * (8 + pb * 2) + n * 8         # R read; P read+write; 1/diag
     if cat == "asm_fill":
-        return nnz * (4 + vb)               # CSR written
+        return nnz * (4 + vb)                       # CSR written
     return None
 
 

@@ -220,6 +220,39 @@ gp2s_status gp2s_lml(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_so
 gp2s_status gp2s_lml_grad(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_solve_opts* opts,
                           double* a, gp2s_report* report, double* grad);
 
+/* ---- batched instances -------------------------------------------------------------
+ * Many independent instances (each its own points, dimension, targets and
+ * hyperparameters; Sec. 2 per instance) evaluated together: one block-diagonal system
+ * assembled in shared launches, solved by batched Jacobi-CG whose iterations run as
+ * replays of one captured hipGraph chunk, with per-instance step lengths, convergence
+ * and Lanczos coefficients. A plan fixes the points, dimensions, bump centres and
+ * widths, the precision and the solver options; runs may change r, the bump weights
+ * and the noise variance.
+ *
+ * gp2s_batch_plan: n (HOST [n_inst]) point counts; x (HOST array of n_inst DEVICE
+ * pointers, each [n[i] * dim_i] float64 row-major); params (HOST [n_inst]); opts
+ * (n_probes must be a power of two in [1, 64]). Planning binds the points (they are
+ * copied), picks the bin refinement and the lanes per row of both products by timing
+ * candidates (the plan's autotuner), assembles once and reserves the CSR capacity
+ * (1.25 x the planned entries). Returns GP2S_E_NONFINITE for non-finite points. */
+typedef struct gp2s_batch_s* gp2s_batch;
+gp2s_status gp2s_batch_plan(gp2s_ctx ctx, int32_t n_inst, const int64_t* n, const double* const* x,
+                            const gp2s_params* params, gp2s_precision precision, const gp2s_solve_opts* opts,
+                            gp2s_batch* out);
+/* Total points, stored entries, reserved capacity and the tuned choices
+ * tuned[3] = {bin refinement m, lanes per row of the single-RHS product, lanes per row
+ * of the probe-block product} (HOST outputs, each may be NULL). */
+gp2s_status gp2s_batch_info(gp2s_batch b, int64_t* n_total, int64_t* nnz, int64_t* capacity, int32_t* tuned);
+/* LML (and gradient) of every instance. y: HOST array of n_inst DEVICE pointers [n[i]];
+ * params: HOST [n_inst] new hyperparameters, or NULL to keep the planned ones (dimension,
+ * bump count, centres and width must match the plan, else GP2S_E_INVALID); lml: HOST
+ * [n_inst]; grad: HOST array of n_inst HOST pointers to [n_bumps_i + 2] (r, a_1..a_P,
+ * sigma^2), or NULL to skip the gradient; reports: HOST [n_inst] or NULL. If the new
+ * radius needs more stored entries than reserved: GP2S_E_CAPACITY (plan again). */
+gp2s_status gp2s_batch_run(gp2s_batch b, const double* const* y, const gp2s_params* params, double* lml,
+                           double* const* grad, gp2s_report* reports);
+gp2s_status gp2s_batch_free(gp2s_batch b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgp2s.so")
 
-SOURCES = ["abi.hip", "prologue.hip", "scan.hip", "assemble.hip", "spmv.hip", "pcg.hip", "slq.hip",
+SOURCES = ["abi.hip", "batch_abi.hip", "batch.hip", "prologue.hip", "scan.hip", "assemble.hip", "spmv.hip", "pcg.hip", "slq.hip",
            "backward.hip"]
 
 ARCH = os.environ.get("GP2S_OFFLOAD_ARCH", "gfx950")

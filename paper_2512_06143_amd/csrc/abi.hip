@@ -1,230 +1,13 @@
 // Host runtime and C ABI of libgp2s: argument validation, contexts and matrix
 // handles, and the orchestration of the device kernels for assembly, products,
 // solves, the log marginal likelihood and its gradient.
-#include <algorithm>
-#include <cmath>
-#include <cstdarg>
-#include <cstdio>
-#include <cstring>
-#include <vector>
-
-#include "gp2s_internal.h"
+#include "runtime.h"
 
 using namespace gp2s;
 
-struct gp2s_ctx_s {
-  hipStream_t stream = nullptr;
-  gp2s_alloc_fn alloc = nullptr;
-  gp2s_free_fn free_fn = nullptr;
-  void* user = nullptr;
-  std::string err;
-  void* pinned = nullptr;  // small pinned host buffer for scalar read-backs
-  // optional per-kernel timing with HIP events on the context's stream
-  bool timing = false;
-  struct Pending {
-    int cat;
-    hipEvent_t e0, e1;
-  };
-  std::vector<Pending> pending;
-  std::vector<hipEvent_t> pool;
-  double ms[GP2S_NUM_TIMERS] = {};
-  int64_t count[GP2S_NUM_TIMERS] = {};
-  gp2s_progress_fn progress = nullptr;
-  void* progress_user = nullptr;
-};
-
-struct gp2s_matrix_s {
-  gp2s_ctx ctx = nullptr;
-  int64_t n = 0, nnz = 0;
-  int prec = GP2S_FP64;
-  bool assembled = false;
-  // hyperparameters (assembled handles)
-  int dim = 0, P = 0;
-  double radius = 0, bump_width = 0, noise = 0;
-  std::vector<double> centers_h, weights_h;
-  double* centers_d = nullptr;
-  double* weights_d = nullptr;
-  GridDev grid{};
-  int32_t* perm = nullptr;  // internal -> user (null for imported handles)
-  float4* pts32 = nullptr;
-  double4* pts64 = nullptr;
-  double* x64 = nullptr;
-  double* g64 = nullptr;
-  int32_t* binid = nullptr;
-  int64_t* bin_start = nullptr;
-  int64_t* row_ptr = nullptr;
-  int32_t* col = nullptr;
-  void* val = nullptr;
-  double* diag = nullptr;
-  double* dinv = nullptr;
-  bool diag_ok = true;
-  std::vector<void*> owned;
-};
-
 namespace {
 
-constexpr size_t kPinnedBytes = 1 << 16;
-
-gp2s_status fail(gp2s_ctx c, gp2s_status s, const char* fmt, ...) {
-  if (c) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
-    va_end(ap);
-    c->err = buf;
-  }
-  return s;
-}
-
-void* dalloc(gp2s_ctx c, size_t bytes) {
-  if (bytes == 0) bytes = 256;
-  bytes = (bytes + 255) & ~size_t(255);
-  if (c->alloc) return c->alloc(bytes, c->user);
-  void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
-  return p;
-}
-
-void dfree(gp2s_ctx c, void* p) {
-  if (!p) return;
-  if (c->free_fn) c->free_fn(p, c->user);
-  else (void)hipFree(p);
-}
-
-// Temporary device buffers released when the call returns.
-struct Scratch {
-  gp2s_ctx c;
-  std::vector<void*> ptrs;
-  bool oom = false;
-  explicit Scratch(gp2s_ctx cc) : c(cc) {}
-  ~Scratch() {
-    if (!ptrs.empty()) (void)hipStreamSynchronize(c->stream);
-    for (void* p : ptrs) dfree(c, p);
-  }
-  template <typename T>
-  T* get(size_t count) {
-    void* p = dalloc(c, count * sizeof(T));
-    if (!p) {
-      oom = true;
-      return nullptr;
-    }
-    ptrs.push_back(p);
-    return static_cast<T*>(p);
-  }
-};
-
-template <typename T>
-T* own(gp2s_matrix m, size_t count) {
-  void* p = dalloc(m->ctx, count * sizeof(T));
-  if (p) m->owned.push_back(p);
-  return static_cast<T*>(p);
-}
-
-bool is_fin(double v) { return std::isfinite(v); }
-
-#define HIPCHK(expr)                                                                          \
-  do {                                                                                        \
-    hipError_t e_ = (expr);                                                                   \
-    if (e_ != hipSuccess) return fail(ctx, GP2S_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
-
-#define OOMCHK(ptr)                                                                             \
-  do {                                                                                          \
-    if (!(ptr)) return fail(ctx, GP2S_E_OOM, "device allocation failed (%s)", #ptr);            \
-  } while (0)
-
-hipEvent_t ev_get(gp2s_ctx c) {
-  if (!c->pool.empty()) {
-    hipEvent_t e = c->pool.back();
-    c->pool.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
-// Collect finished event pairs into the per-category totals (the stream is idle).
-void harvest(gp2s_ctx c) {
-  for (auto& p : c->pending) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) {
-      c->ms[p.cat] += ms;
-      c->count[p.cat] += 1;
-    }
-    c->pool.push_back(p.e0);
-    c->pool.push_back(p.e1);
-  }
-  c->pending.clear();
-}
-
-// Brackets one or more launches with events when timing is enabled.
-struct Timed {
-  gp2s_ctx c;
-  int cat;
-  hipEvent_t e0 = nullptr;
-  Timed(gp2s_ctx cc, int k) : c(cc), cat(k) {
-    if (c->timing) {
-      e0 = ev_get(c);
-      if (e0) (void)hipEventRecord(e0, c->stream);
-    }
-  }
-  ~Timed() {
-    if (!e0) return;
-    hipEvent_t e1 = ev_get(c);
-    if (!e1) return;
-    (void)hipEventRecord(e1, c->stream);
-    c->pending.push_back({cat, e0, e1});
-  }
-};
-
-#define TIMED(cat, expr)          \
-  do {                            \
-    Timed t_(ctx, cat);           \
-    HIPCHK(expr);                 \
-  } while (0)
-
-gp2s_status ensure_device(gp2s_ctx ctx) {
-  int count = 0;
-  hipError_t e = hipGetDeviceCount(&count);
-  if (e != hipSuccess || count == 0)
-    return fail(ctx, GP2S_E_HIP, "no HIP device available (%s)", hipGetErrorString(e));
-  if (!ctx->pinned) {
-    HIPCHK(hipHostMalloc(&ctx->pinned, kPinnedBytes, hipHostMallocDefault));
-  }
-  return GP2S_OK;
-}
-
-// Copy `bytes` from device to the pinned buffer and wait for the stream.
-gp2s_status readback(gp2s_ctx ctx, const void* dev, size_t bytes, void* host) {
-  if (bytes > kPinnedBytes) return fail(ctx, GP2S_E_INVALID, "internal: readback too large");
-  HIPCHK(hipMemcpyAsync(ctx->pinned, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
-  std::memcpy(host, ctx->pinned, bytes);
-  if (!ctx->pending.empty()) harvest(ctx);
-  return GP2S_OK;
-}
-
-gp2s_status check_opts(gp2s_ctx ctx, const gp2s_solve_opts* o, bool need_probes) {
-  if (!o) return fail(ctx, GP2S_E_INVALID, "opts is NULL");
-  if (o->n_probes < 0 || o->n_probes > kMaxProbes)
-    return fail(ctx, GP2S_E_INVALID, "n_probes must be in [0, %d]", kMaxProbes);
-  if (need_probes && o->n_probes < 1) return fail(ctx, GP2S_E_INVALID, "n_probes must be >= 1");
-  if (o->max_iter < 1 || o->max_iter > 10000000) return fail(ctx, GP2S_E_INVALID, "max_iter out of range");
-  if (o->max_ir < 0 || o->max_ir > 100) return fail(ctx, GP2S_E_INVALID, "max_ir out of range");
-  if (o->check_every < 1) return fail(ctx, GP2S_E_INVALID, "check_every must be >= 1");
-  if (!is_fin(o->tol) || o->tol <= 0 || o->tol >= 1) return fail(ctx, GP2S_E_INVALID, "tol must be in (0, 1)");
-  if (!is_fin(o->probe_tol) || o->probe_tol <= 0 || o->probe_tol >= 1)
-    return fail(ctx, GP2S_E_INVALID, "probe_tol must be in (0, 1)");
-  return GP2S_OK;
-}
-
-gp2s_status check_matrix(gp2s_ctx ctx, gp2s_matrix m) {
-  if (!m) return fail(ctx, GP2S_E_INVALID, "matrix handle is NULL");
-  if (m->ctx != ctx) return fail(ctx, GP2S_E_INVALID, "matrix handle belongs to another context");
-  return GP2S_OK;
-}
+using namespace gp2s::rt;
 
 // ---- conjugate gradients ------------------------------------------------------------------
 struct CgRun {
@@ -239,13 +22,13 @@ gp2s_status run_cg(gp2s_ctx ctx, gp2s_matrix m, int S, const double* B, double* 
                    int check_every, bool keep_hist, Scratch& sc, CgRun& out, const char* label) {
   const int64_t n = m->n;
   const size_t nS = (size_t)n * S;
-  // Probe blocks of the mixed path keep search directions and products in float32
-  // (x, r, dot products and all coefficients stay float64).
+  // Probe blocks of the mixed path keep search directions in float32 (products, x,
+  // r, dot products and all coefficients stay float64).
   const bool f32vec = m->prec == GP2S_MIXED && S > 1;
   const size_t vb = f32vec ? sizeof(float) : sizeof(double);
   double* R = sc.get<double>(nS);
   void* P = sc.get<uint8_t>(nS * vb);
-  void* Q = sc.get<uint8_t>(nS * vb);
+  void* Q = sc.get<double>(nS);
   double* sd = sc.get<double>(6 * S + (size_t)kReduceBlocks * S * 2);
   int32_t* si = sc.get<int32_t>(2 * S + 4);
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "CG workspace allocation failed");
@@ -520,6 +303,8 @@ gp2s_status lml_common(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_
 }
 
 }  // namespace
+
+using namespace gp2s::rt;
 
 // =====================================================================================
 extern "C" {

@@ -1,0 +1,866 @@
+// Batched instances: many independent GP instances of uneven size solved as one
+// block-diagonal system in the same launches.
+//
+// Assembly kernels work per row (each row knows its instance). The CG kernels use an
+// instance-aligned decomposition: every workgroup owns up to kBRows consecutive rows
+// of a single instance, so column sums, step lengths, convergence flags and Lanczos
+// coefficients are kept per (instance, column) with fixed-order reductions and no
+// atomics. The arithmetic of every step is the single-instance one (see
+// prologue.hip, assemble.hip, spmv.hip, pcg.hip, backward.hip).
+#include "gp2s_internal.h"
+
+namespace gp2s {
+
+__device__ inline int find_inst(const int64_t* rs, int M, int64_t u) {
+  int lo = 0, hi = M;  // rs[lo] <= u < rs[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (rs[mid] <= u) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// ---- prologue, binning, gathers ------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_bbbox(const double* __restrict__ x3, BatchGeom g,
+                                                  double* __restrict__ part, int32_t* __restrict__ nonfinite) {
+  __shared__ double sh[6][kBlock];
+  const int i = blockIdx.x;
+  const int64_t r0 = g.row_start[i], r1 = g.row_start[i + 1];
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bool bad = false;
+  for (int64_t u = r0 + threadIdx.x; u < r1; u += blockDim.x) {
+    for (int k = 0; k < 3; ++k) {
+      const double v = x3[u * 3 + k];
+      if (!isfinite(v)) bad = true;
+      lo[k] = fmin(lo[k], v);
+      hi[k] = fmax(hi[k], v);
+    }
+  }
+  if (bad) atomicOr(nonfinite, 1);
+  for (int k = 0; k < 3; ++k) {
+    sh[k][threadIdx.x] = lo[k];
+    sh[3 + k][threadIdx.x] = hi[k];
+  }
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int k = 0; k < 3; ++k) {
+        sh[k][threadIdx.x] = fmin(sh[k][threadIdx.x], sh[k][threadIdx.x + o]);
+        sh[3 + k][threadIdx.x] = fmax(sh[3 + k][threadIdx.x], sh[3 + k][threadIdx.x + o]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[i * 6 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+hipError_t launch_bbbox(const double* x3, const BatchGeom& g, double* part, int32_t* nonfinite, hipStream_t st) {
+  hipLaunchKernelGGL(k_bbbox, dim3(g.M), dim3(kBlock), 0, st, x3, g, part, nonfinite);
+  return hipGetLastError();
+}
+
+__device__ inline int32_t bcoord(double v, double o, double inv_h, int32_t nb) {
+  const double f = floor((v - o) * inv_h);
+  return (int32_t)fmax(0.0, fmin(f, (double)(nb - 1)));
+}
+
+__global__ __launch_bounds__(kBlock) void k_bprologue(const double* __restrict__ x3, BatchGeom g,
+                                                      const double* __restrict__ centers3,
+                                                      const double* __restrict__ weights,
+                                                      int32_t* __restrict__ bin_of, int32_t* __restrict__ slot,
+                                                      int32_t* __restrict__ bin_count,
+                                                      double* __restrict__ g64_user, uint8_t* __restrict__ gam) {
+  const int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (u >= g.n) return;
+  const int i = find_inst(g.row_start, g.M, u);
+  const BInst& I = g.inst[i];
+  const double xi[3] = {x3[u * 3], x3[u * 3 + 1], x3[u * 3 + 2]};
+  int64_t b = 0;
+  for (int k = 2; k >= 0; --k) b = b * I.grid.nb[k] + bcoord(xi[k], I.grid.origin[k], I.grid.inv_h, I.grid.nb[k]);
+  double gs = 0.0;
+  bool inside = false;
+  for (int p = 0; p < I.P; ++p) {
+    const double* c = centers3 + (int64_t)(I.cent0 + p) * 3;
+    double d2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double d = xi[k] - c[k];
+      d2 += d * d;
+    }
+    if (d2 < I.bump_w2) {
+      inside = true;
+      gs += weights[I.cent0 + p] * exp(1.0 - 1.0 / (1.0 - d2 / I.bump_w2));
+    }
+  }
+  b += I.bin0;
+  bin_of[u] = (int32_t)b;
+  slot[u] = atomicAdd(&bin_count[b], 1);
+  g64_user[u] = inside ? gs : 0.0;
+  gam[u] = inside ? 1 : 0;
+}
+
+hipError_t launch_bprologue(const double* x3, const BatchGeom& g, const double* centers3, const double* weights,
+                            int32_t* bin_of, int32_t* slot, int32_t* bin_count, double* g64_user, uint8_t* gam,
+                            hipStream_t st) {
+  const int64_t blocks = (g.n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_bprologue, dim3((unsigned)blocks), dim3(kBlock), 0, st, x3, g, centers3, weights, bin_of,
+                     slot, bin_count, g64_user, gam);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_bgather(const double* __restrict__ x3, BatchGeom g,
+                                                    const int32_t* __restrict__ perm,
+                                                    const int32_t* __restrict__ bin_of,
+                                                    const double* __restrict__ g64_user,
+                                                    const uint8_t* __restrict__ gam, float4* __restrict__ pts32,
+                                                    double4* __restrict__ pts64, double* __restrict__ x64,
+                                                    double* __restrict__ g64, int32_t* __restrict__ binid,
+                                                    int32_t* __restrict__ inst_of_row) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= g.n) return;
+  const int64_t u = perm[p];
+  const double c0 = x3[u * 3], c1 = x3[u * 3 + 1], c2 = x3[u * 3 + 2];
+  x64[p * 3] = c0;
+  x64[p * 3 + 1] = c1;
+  x64[p * 3 + 2] = c2;
+  const double gv = g64_user[u];
+  const bool in = gam[u] != 0;
+  if (pts32) pts32[p] = make_float4((float)c0, (float)c1, (float)c2, in ? (float)gv : -1.0f);
+  if (pts64) pts64[p] = make_double4(c0, c1, c2, in ? gv : -1.0);
+  g64[p] = gv;
+  binid[p] = bin_of[u];
+  inst_of_row[p] = find_inst(g.row_start, g.M, u);
+}
+
+hipError_t launch_bgather(const double* x3, const BatchGeom& g, const int32_t* perm, const int32_t* bin_of,
+                          const double* g64_user, const uint8_t* gam, float4* pts32, double4* pts64, double* x64,
+                          double* g64, int32_t* binid, int32_t* inst_of_row, hipStream_t st) {
+  const int64_t blocks = (g.n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_bgather, dim3((unsigned)blocks), dim3(kBlock), 0, st, x3, g, perm, bin_of, g64_user, gam,
+                     pts32, pts64, x64, g64, binid, inst_of_row);
+  return hipGetLastError();
+}
+
+// ---- assembly ----------------------------------------------------------------------------------
+__device__ inline float bsq32(const float4& a, const float4& b) {
+  const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+  return __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmul_rn(dx, dx)));
+}
+__device__ inline double bsq64(const double4& a, const double4& b) {
+  const double dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+  return __fma_rn(dz, dz, __fma_rn(dy, dy, __dmul_rn(dx, dx)));
+}
+__device__ inline float bentry32(const float4& pi, const float4& pj, double r2, double inv_r2) {
+  const double dx = (double)pi.x - (double)pj.x, dy = (double)pi.y - (double)pj.y, dz = (double)pi.z - (double)pj.z;
+  const double d2 = dx * dx + dy * dy + dz * dz;
+  const float t = fmaxf((float)((r2 - d2) * inv_r2), 0.0f);
+  const float rho = __builtin_amdgcn_sqrtf((float)(d2 * inv_r2));
+  const float om = t * __builtin_amdgcn_rcpf(1.0f + rho);
+  const float om2 = om * om;
+  return pi.w * pj.w * (om2 * om2 * (4.0f * rho + 1.0f));
+}
+__device__ inline double bentry64(const double4& pi, const double4& pj, double r2, double inv_r2) {
+  const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
+  const double d2 = dx * dx + dy * dy + dz * dz;
+  const double t = fmax((r2 - d2) * inv_r2, 0.0);
+  const double rho = sqrt(d2 * inv_r2);
+  const double om = t / (1.0 + rho);
+  const double om2 = om * om;
+  return pi.w * pj.w * (om2 * om2 * (4.0 * rho + 1.0));
+}
+
+__device__ inline uint32_t blane_prefix(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// One wavefront per row, as in the single-instance assembly; the instance's grid, radius
+// and noise come from its table entry, and neighbour runs reach +-m bins.
+template <bool FILL, bool F32>
+__global__ __launch_bounds__(kBlock) void k_bassemble(BAsm a, int64_t nblocks_padded, int32_t* __restrict__ row_cnt,
+                                                      const int64_t* __restrict__ row_ptr,
+                                                      int32_t* __restrict__ col, void* __restrict__ val,
+                                                      double* __restrict__ diag, int32_t* __restrict__ overflow) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t per = nblocks_padded / 8;
+  const int64_t lb = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int64_t row = lb * (kBlock / kWave) + threadIdx.x / kWave;
+  if (row >= a.g.n) return;
+  const BInst& I = a.g.inst[a.g.inst_of_row[row]];
+  float4 pi32;
+  double4 pi64;
+  bool in_i;
+  if (F32) {
+    pi32 = a.pts32[row];
+    in_i = pi32.w >= 0.0f;
+  } else {
+    pi64 = a.pts64[row];
+    in_i = pi64.w >= 0.0;
+  }
+  const float r2f = (float)I.r2;
+  const int64_t base = FILL ? row_ptr[row] : 0;
+  const int64_t end = FILL ? min(row_ptr[row + 1], a.cap) : 0;
+  if (FILL && lane == 0 && row_ptr[row + 1] > a.cap) atomicOr(overflow, 1);
+  if (!in_i) {
+    if (lane == 0) {
+      if (FILL) {
+        if (base < end) {
+          col[base] = (int32_t)row;
+          if (F32) {
+            const float v = (float)I.noise;
+            static_cast<float*>(val)[base] = v;
+            diag[row] = (double)v;
+          } else {
+            static_cast<double*>(val)[base] = I.noise;
+            diag[row] = I.noise;
+          }
+        }
+      } else {
+        row_cnt[row] = 1;
+      }
+    }
+    return;
+  }
+  const int32_t lbin = (int32_t)(a.binid[row] - I.bin0);
+  const int nbx = I.grid.nb[0], nby = I.grid.nb[1], nbz = I.grid.nb[2];
+  const int bx = lbin % nbx, t = lbin / nbx, by = t % nby, bz = t / nby;
+  const int m = I.m;
+  const int x0 = max(bx - m, 0), x1 = min(bx + m, nbx - 1);
+  const double gi64 = a.g64[row];
+  int64_t cnt = 0;
+  for (int dz = -m; dz <= m; ++dz) {
+    const int zz = bz + dz;
+    if (zz < 0 || zz >= nbz) continue;
+    for (int dy = -m; dy <= m; ++dy) {
+      const int yy = by + dy;
+      if (yy < 0 || yy >= nby) continue;
+      const int64_t rb = I.bin0 + ((int64_t)zz * nby + yy) * nbx;
+      const int64_t s = a.bin_start[rb + x0], e = a.bin_start[rb + x1 + 1];
+      for (int64_t c = s; c < e; c += kWave) {
+        const int64_t j = c + lane;
+        const bool ok = j < e;
+        bool pass;
+        float4 pj32;
+        double4 pj64;
+        if (F32) {
+          pj32 = ok ? a.pts32[j] : make_float4(0.f, 0.f, 0.f, -1.f);
+          pass = ok && (j == row || (pj32.w >= 0.0f && bsq32(pi32, pj32) < r2f));
+        } else {
+          pj64 = ok ? a.pts64[j] : make_double4(0., 0., 0., -1.);
+          pass = ok && (j == row || (pj64.w >= 0.0 && bsq64(pi64, pj64) < I.r2));
+        }
+        const uint64_t mk = __ballot(pass);
+        const int64_t pos = base + cnt + blane_prefix(mk);
+        if (FILL && pass && pos < end) {
+          col[pos] = (int32_t)j;
+          if (F32) {
+            const float v = (j == row) ? (float)(gi64 * gi64 + I.noise) : bentry32(pi32, pj32, I.r2, I.inv_r2);
+            static_cast<float*>(val)[pos] = v;
+            if (j == row) diag[row] = (double)v;
+          } else {
+            const double v = (j == row) ? gi64 * gi64 + I.noise : bentry64(pi64, pj64, I.r2, I.inv_r2);
+            static_cast<double*>(val)[pos] = v;
+            if (j == row) diag[row] = v;
+          }
+        }
+        cnt += __popcll(mk);
+      }
+    }
+  }
+  if (!FILL && lane == 0) row_cnt[row] = (int32_t)cnt;
+}
+
+template <bool FILL>
+static hipError_t bassemble(const BAsm& a, int prec, int32_t* row_cnt, const int64_t* row_ptr, int32_t* col,
+                            void* val, double* diag, int32_t* overflow, hipStream_t st) {
+  const int64_t nb = (a.g.n + (kBlock / kWave) - 1) / (kBlock / kWave);
+  const int64_t padded = (nb + 7) / 8 * 8;
+  if (prec == GP2S_MIXED)
+    hipLaunchKernelGGL((k_bassemble<FILL, true>), dim3((unsigned)padded), dim3(kBlock), 0, st, a, padded, row_cnt,
+                       row_ptr, col, val, diag, overflow);
+  else
+    hipLaunchKernelGGL((k_bassemble<FILL, false>), dim3((unsigned)padded), dim3(kBlock), 0, st, a, padded, row_cnt,
+                       row_ptr, col, val, diag, overflow);
+  return hipGetLastError();
+}
+hipError_t launch_bassemble_count(const BAsm& a, int prec, int32_t* row_cnt, hipStream_t st) {
+  return bassemble<false>(a, prec, row_cnt, nullptr, nullptr, nullptr, nullptr, nullptr, st);
+}
+hipError_t launch_bassemble_fill(const BAsm& a, int prec, const int64_t* row_ptr, int32_t* col, void* val,
+                                 double* diag, int32_t* overflow, hipStream_t st) {
+  return bassemble<true>(a, prec, nullptr, row_ptr, col, val, diag, overflow, st);
+}
+
+// Probe signs indexed by the instance-local user row (so each instance's probes are
+// those of a single-instance run with the same seed).
+__device__ inline uint64_t bsplitmix(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__global__ __launch_bounds__(kBlock) void k_bprobe_masks(BatchGeom g, const int32_t* __restrict__ perm, uint64_t seed,
+                                                         int S, uint64_t* __restrict__ mask) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= g.n) return;
+  const int i = g.inst_of_row[p];
+  const uint64_t u = (uint64_t)(perm[p] - g.row_start[i]);
+  uint64_t mk = 0;
+  for (int s = 0; s < S; ++s) mk |= (bsplitmix(seed, ((uint64_t)s << 40) + u) >> 63) << s;
+  mask[p] = mk;
+}
+hipError_t launch_bprobe_masks(const BatchGeom& g, const int32_t* perm, uint64_t seed, int S, uint64_t* mask,
+                               hipStream_t st) {
+  const int64_t blocks = (g.n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_bprobe_masks, dim3((unsigned)blocks), dim3(kBlock), 0, st, g, perm, seed, S, mask);
+  return hipGetLastError();
+}
+
+// ---- instance-aligned CG ------------------------------------------------------------------------
+struct BRows {
+  int inst;
+  int64_t lo, hi;
+};
+__device__ inline BRows brows(const BatchGeom& g) {
+  BRows r;
+  r.inst = g.blk_inst[blockIdx.x];
+  const BInst& I = g.inst[r.inst];
+  r.lo = I.row0 + (int64_t)(blockIdx.x - I.blk0) * kBRows;
+  r.hi = min(r.lo + (int64_t)kBRows, I.row0 + I.rows);
+  return r;
+}
+
+// Q = K P for one instance-aligned workgroup; `L` lanes per row (a power of two >= S),
+// 64 / L rows per wave side by side. Entries are exchanged inside a row's lane segment
+// with shuffles. P may be float32; products accumulate and are stored in float64.
+// Per-column p^T q partials go to partial[block * S + column].
+template <int L, typename V, typename PT>
+__global__ __launch_bounds__(kBlock) void k_bspmm(BatchGeom g, const int64_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col, const V* __restrict__ val, int S,
+                                                  const PT* __restrict__ X, double* __restrict__ Y, CgState cs) {
+  const BRows br = brows(g);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int seg = lane / L, sl = lane % L;
+  const int rows_per_pass = (kBlock / kWave) * (kWave / L);
+  const int slot = wid * (kWave / L) + seg;
+  const bool active = sl < S;
+  const PT* __restrict__ Xl = X + (active ? sl : 0);
+  double dot = 0.0;
+  for (int64_t row = br.lo + slot; row < br.hi; row += rows_per_pass) {
+    const int64_t s = rp[row], e = rp[row + 1];
+    double acc = 0.0;
+    for (int64_t k0 = s; k0 < e; k0 += L) {
+      const int64_t k = k0 + sl;
+      const int32_t off = k < e ? col[k] * S : 0;
+      const double vj = k < e ? (double)val[k] : 0.0;
+      const int cnt = (int)min((int64_t)L, e - k0);
+      for (int l = 0; l < cnt; ++l) {
+        const int32_t jo = __shfl(off, l, L);
+        const double vv = __shfl(vj, l, L);
+        acc += vv * (double)Xl[jo];
+      }
+    }
+    if (active) {
+      Y[row * S + sl] = acc;
+      dot += acc * (double)X[row * S + sl];
+    }
+  }
+  __shared__ double sh[kBlock];
+  sh[threadIdx.x] = dot;
+  __syncthreads();
+  if ((int)threadIdx.x < S) {
+    double t = 0.0;
+    for (int q = 0; q < kBlock / L; ++q) t += sh[q * L + threadIdx.x];
+    cs.partial[blockIdx.x * (int64_t)S + threadIdx.x] = t;
+  }
+}
+
+// single right-hand side per instance: G lanes per row
+template <int G, typename V>
+__global__ __launch_bounds__(kBlock) void k_bspmv(BatchGeom g, const int64_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col, const V* __restrict__ val,
+                                                  const double* __restrict__ x, double* __restrict__ y, CgState cs) {
+  const BRows br = brows(g);
+  const int lane = threadIdx.x & (G - 1);
+  const int grp = threadIdx.x / G;
+  double dot = 0.0;
+  for (int64_t row = br.lo + grp; row < br.hi; row += kBlock / G) {
+    const int64_t s = rp[row], e = rp[row + 1];
+    double a0 = 0.0, a1 = 0.0;
+    int64_t k = s + lane;
+    for (; k + G < e; k += 2 * G) {
+      a0 += (double)val[k] * x[col[k]];
+      a1 += (double)val[k + G] * x[col[k + G]];
+    }
+    if (k < e) a0 += (double)val[k] * x[col[k]];
+    double acc = a0 + a1;
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+    if (lane == 0) {
+      y[row] = acc;
+      dot += acc * x[row];
+    }
+  }
+  __shared__ double sh[kBlock];
+  sh[threadIdx.x] = dot;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cs.partial[blockIdx.x] = sh[0];
+}
+
+// Sum of partial[(b * W + which) * S + s] over instance i's workgroups.
+__device__ inline double binst_sum(const BatchGeom& g, const double* partial, int i, int W, int which, int S, int s,
+                                   double* sh) {
+  const BInst& I = g.inst[i];
+  double v = 0.0;
+  for (int64_t b = I.blk0 + threadIdx.x; b < I.blk0 + I.nblk; b += blockDim.x)
+    v += partial[(b * W + which) * S + s];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double t = sh[0];
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bcg_alpha(BatchGeom g, CgState cs, int S) {
+  __shared__ double sh[kBlock];
+  const int c = blockIdx.x, i = c / S, s = c % S;
+  const double pq = binst_sum(g, cs.partial, i, 1, 0, S, s, sh);
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    if (!cs.done[c]) {
+      if (!(pq > 0.0) || !isfinite(pq)) {
+        cs.flags[0] = 1;
+        cs.flags[3] = c;
+      } else {
+        a = cs.rz[c] / pq;
+      }
+    }
+    cs.alpha[c] = a;
+  }
+}
+
+template <int G, typename V>
+static void bspmv_g(const BatchGeom& g, const int64_t* rp, const int32_t* col, const V* val, const double* P, double* Q,
+                    const CgState& cs, hipStream_t st) {
+  hipLaunchKernelGGL((k_bspmv<G, V>), dim3((unsigned)g.nblk), dim3(kBlock), 0, st, g, rp, col, val, P, Q, cs);
+}
+template <int L, typename V, typename PT>
+static void bspmm_l(const BatchGeom& g, const int64_t* rp, const int32_t* col, const V* val, int S, const PT* P,
+                    double* Q, const CgState& cs, hipStream_t st) {
+  hipLaunchKernelGGL((k_bspmm<L, V, PT>), dim3((unsigned)g.nblk), dim3(kBlock), 0, st, g, rp, col, val, S, P, Q, cs);
+}
+template <typename V, typename PT>
+static void bspmm_any(int lanes, const BatchGeom& g, const int64_t* rp, const int32_t* col, const V* val, int S,
+                      const PT* P, double* Q, const CgState& cs, hipStream_t st) {
+  switch (lanes) {
+    case 2: bspmm_l<2>(g, rp, col, val, S, P, Q, cs, st); break;
+    case 4: bspmm_l<4>(g, rp, col, val, S, P, Q, cs, st); break;
+    case 8: bspmm_l<8>(g, rp, col, val, S, P, Q, cs, st); break;
+    case 16: bspmm_l<16>(g, rp, col, val, S, P, Q, cs, st); break;
+    case 32: bspmm_l<32>(g, rp, col, val, S, P, Q, cs, st); break;
+    default: bspmm_l<64>(g, rp, col, val, S, P, Q, cs, st); break;
+  }
+}
+template <typename V>
+static void bspmv_any(int G, const BatchGeom& g, const int64_t* rp, const int32_t* col, const V* val, const double* P,
+                      double* Q, const CgState& cs, hipStream_t st) {
+  switch (G) {
+    case 4: bspmv_g<4>(g, rp, col, val, P, Q, cs, st); break;
+    case 8: bspmv_g<8>(g, rp, col, val, P, Q, cs, st); break;
+    case 16: bspmv_g<16>(g, rp, col, val, P, Q, cs, st); break;
+    case 32: bspmv_g<32>(g, rp, col, val, P, Q, cs, st); break;
+    default: bspmv_g<64>(g, rp, col, val, P, Q, cs, st); break;
+  }
+}
+
+// `lanes`: lanes per row -- the SpMV lane group for S = 1, else lanes per row of the
+// block product (>= S). Both are chosen by the autotuner.
+hipError_t launch_bcg_matvec(int prec, const BatchGeom& g, const int64_t* rp, const int32_t* col, const void* val,
+                             int S, int lanes, const void* P, void* Q, bool f32vec, const CgState& cs,
+                             hipStream_t st) {
+  if (S == 1) {
+    if (prec == GP2S_MIXED)
+      bspmv_any(lanes, g, rp, col, static_cast<const float*>(val), static_cast<const double*>(P),
+                static_cast<double*>(Q), cs, st);
+    else
+      bspmv_any(lanes, g, rp, col, static_cast<const double*>(val), static_cast<const double*>(P),
+                static_cast<double*>(Q), cs, st);
+  } else if (f32vec) {
+    bspmm_any(lanes, g, rp, col, static_cast<const float*>(val), S, static_cast<const float*>(P),
+              static_cast<double*>(Q), cs, st);
+  } else if (prec == GP2S_MIXED) {
+    bspmm_any(lanes, g, rp, col, static_cast<const float*>(val), S, static_cast<const double*>(P),
+              static_cast<double*>(Q), cs, st);
+  } else {
+    bspmm_any(lanes, g, rp, col, static_cast<const double*>(val), S, static_cast<const double*>(P),
+              static_cast<double*>(Q), cs, st);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bcg_alpha, dim3((unsigned)(g.M * S)), dim3(kBlock), 0, st, g, cs, S);
+  return hipGetLastError();
+}
+
+// Per-column sums of one workgroup (thread t owns column t % S; S divides kBlock).
+__device__ inline void bcols_partial(double* sh, int S, double v, double* partial, int which) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = kBlock / 2; o >= S; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < S) partial[(blockIdx.x * 2 + which) * (int64_t)S + threadIdx.x] = sh[threadIdx.x];
+  __syncthreads();
+}
+
+template <typename VEC>
+__global__ __launch_bounds__(kBlock) void k_bcg_init(BatchGeom g, int S, const double* __restrict__ B,
+                                                     const double* __restrict__ dinv, double* __restrict__ X,
+                                                     double* __restrict__ R, VEC* __restrict__ P, CgState cs) {
+  __shared__ double sh[kBlock];
+  const BRows br = brows(g);
+  double rz = 0.0, bb = 0.0;
+  for (int64_t e = br.lo * S + threadIdx.x; e < br.hi * S; e += kBlock) {
+    const int64_t i = e / S;
+    const double b = B[e];
+    const double z = b * dinv[i];
+    X[e] = 0.0;
+    R[e] = b;
+    P[e] = (VEC)z;
+    rz += b * z;
+    bb += b * b;
+  }
+  bcols_partial(sh, S, rz, cs.partial, 0);
+  bcols_partial(sh, S, bb, cs.partial, 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bcg_init_fin(BatchGeom g, CgState cs, int S, double tol) {
+  __shared__ double sh[kBlock];
+  const int c = blockIdx.x, i = c / S, s = c % S;
+  const double rz = binst_sum(g, cs.partial, i, 2, 0, S, s, sh);
+  const double bb = binst_sum(g, cs.partial, i, 2, 1, S, s, sh);
+  if (threadIdx.x == 0) {
+    cs.rz[c] = rz;
+    cs.bb[c] = bb;
+    cs.rr[c] = bb;
+    cs.tol2[c] = tol * tol;
+    cs.iters[c] = 0;
+    cs.alpha[c] = 0.0;
+    cs.beta[c] = 0.0;
+    cs.done[c] = (bb == 0.0) ? 1 : 0;
+    if (!isfinite(rz) || !isfinite(bb)) cs.flags[2] = 1;
+  }
+}
+
+hipError_t launch_bcg_init(const BatchGeom& g, int S, const double* B, const double* dinv, double* X, double* R,
+                           void* P, bool f32vec, const CgState& cs, double tol, hipStream_t st) {
+  if (f32vec)
+    hipLaunchKernelGGL(k_bcg_init<float>, dim3((unsigned)g.nblk), dim3(kBlock), 0, st, g, S, B, dinv, X, R,
+                       static_cast<float*>(P), cs);
+  else
+    hipLaunchKernelGGL(k_bcg_init<double>, dim3((unsigned)g.nblk), dim3(kBlock), 0, st, g, S, B, dinv, X, R,
+                       static_cast<double*>(P), cs);
+  hipLaunchKernelGGL(k_bcg_init_fin, dim3((unsigned)(g.M * S)), dim3(kBlock), 0, st, g, cs, S, tol);
+  return hipGetLastError();
+}
+
+template <typename VEC>
+__global__ __launch_bounds__(kBlock) void k_bcg_update(BatchGeom g, int S, double* __restrict__ X,
+                                                       double* __restrict__ R, const VEC* __restrict__ P,
+                                                       const double* __restrict__ Q, const double* __restrict__ dinv,
+                                                       CgState cs) {
+  __shared__ double sh[kBlock];
+  const BRows br = brows(g);
+  const int s_me = threadIdx.x % S;
+  const double a = cs.alpha[br.inst * S + s_me];
+  double rz = 0.0, rr = 0.0;
+  for (int64_t e = br.lo * S + threadIdx.x; e < br.hi * S; e += kBlock) {
+    const int64_t i = e / S;
+    double r = R[e];
+    if (a != 0.0) {
+      X[e] += a * (double)P[e];
+      r -= a * Q[e];
+      R[e] = r;
+    }
+    rz += r * (r * dinv[i]);
+    rr += r * r;
+  }
+  bcols_partial(sh, S, rz, cs.partial, 0);
+  bcols_partial(sh, S, rr, cs.partial, 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bcg_beta(BatchGeom g, CgState cs, int S, const int32_t* __restrict__ iter_dev) {
+  __shared__ double sh[kBlock];
+  const int c = blockIdx.x, i = c / S, s = c % S;
+  const double rzn = binst_sum(g, cs.partial, i, 2, 0, S, s, sh);
+  const double rrn = binst_sum(g, cs.partial, i, 2, 1, S, s, sh);
+  if (threadIdx.x != 0) return;
+  const int32_t iter = *iter_dev;
+  const int SM = g.M * S;
+  double beta = 0.0;
+  if (!cs.done[c]) {
+    const double al = cs.alpha[c];
+    if (al == 0.0) {
+      cs.done[c] = 1;
+    } else {
+      beta = rzn / cs.rz[c];
+      if (cs.hist_a && iter < cs.max_hist) {
+        cs.hist_a[(int64_t)iter * SM + c] = al;
+        cs.hist_b[(int64_t)iter * SM + c] = beta;
+      }
+      cs.iters[c] += 1;
+      cs.rz[c] = rzn;
+      cs.rr[c] = rrn;
+      if (!isfinite(rrn)) {
+        cs.flags[2] = 1;
+        cs.done[c] = 1;
+      } else if (rrn <= cs.tol2[c] * cs.bb[c]) {
+        cs.done[c] = 1;
+      }
+    }
+  }
+  cs.beta[c] = beta;
+}
+
+hipError_t launch_bcg_update(const BatchGeom& g, int S, double* X, double* R, const void* P, const void* Q, bool f32vec,
+                             const double* dinv, const CgState& cs, const int32_t* iter_dev, hipStream_t st) {
+  if (f32vec)
+    hipLaunchKernelGGL(k_bcg_update<float>, dim3((unsigned)g.nblk), dim3(kBlock), 0, st, g, S, X, R,
+                       static_cast<const float*>(P), static_cast<const double*>(Q), dinv, cs);
+  else
+    hipLaunchKernelGGL(k_bcg_update<double>, dim3((unsigned)g.nblk), dim3(kBlock), 0, st, g, S, X, R,
+                       static_cast<const double*>(P), static_cast<const double*>(Q), dinv, cs);
+  hipLaunchKernelGGL(k_bcg_beta, dim3((unsigned)(g.M * S)), dim3(kBlock), 0, st, g, cs, S, iter_dev);
+  return hipGetLastError();
+}
+
+template <typename VEC>
+__global__ __launch_bounds__(kBlock) void k_bcg_pupdate(BatchGeom g, int S, VEC* __restrict__ P,
+                                                        const double* __restrict__ R, const double* __restrict__ dinv,
+                                                        CgState cs, int32_t* __restrict__ iter_dev) {
+  // The iteration counter advances once per iteration, after every reader of it.
+  if (blockIdx.x == 0 && threadIdx.x == 0) *iter_dev += 1;
+  const BRows br = brows(g);
+  const int c = br.inst * S + (int)(threadIdx.x % S);
+  if (cs.done[c]) return;
+  const double b = cs.beta[c];
+  for (int64_t e = br.lo * S + threadIdx.x; e < br.hi * S; e += kBlock) {
+    const int64_t i = e / S;
+    P[e] = (VEC)(R[e] * dinv[i] + b * (double)P[e]);
+  }
+}
+
+hipError_t launch_bcg_pupdate(const BatchGeom& g, int S, void* P, const double* R, const double* dinv, bool f32vec,
+                              const CgState& cs, int32_t* iter_dev, hipStream_t st) {
+  if (f32vec)
+    hipLaunchKernelGGL(k_bcg_pupdate<float>, dim3((unsigned)g.nblk), dim3(kBlock), 0, st, g, S,
+                       static_cast<float*>(P), R, dinv, cs, iter_dev);
+  else
+    hipLaunchKernelGGL(k_bcg_pupdate<double>, dim3((unsigned)g.nblk), dim3(kBlock), 0, st, g, S,
+                       static_cast<double*>(P), R, dinv, cs, iter_dev);
+  return hipGetLastError();
+}
+
+// ---- per-instance reductions ---------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_bseg_reduce(BatchGeom g, const double* __restrict__ a,
+                                                        const double* __restrict__ b, double* __restrict__ out) {
+  __shared__ double sh[kBlock];
+  const BInst& I = g.inst[blockIdx.x];
+  double v = 0.0;
+  for (int64_t r = I.row0 + threadIdx.x; r < I.row0 + I.rows; r += kBlock)
+    v += MODE == 0 ? a[r] * (b ? b[r] : a[r]) : log(a[r]);
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+hipError_t launch_bseg_reduce(const BatchGeom& g, int mode, const double* a, const double* b, double* out,
+                              hipStream_t st) {
+  if (mode == 0)
+    hipLaunchKernelGGL(k_bseg_reduce<0>, dim3(g.M), dim3(kBlock), 0, st, g, a, b, out);
+  else
+    hipLaunchKernelGGL(k_bseg_reduce<1>, dim3(g.M), dim3(kBlock), 0, st, g, a, b, out);
+  return hipGetLastError();
+}
+
+// ---- gradient ----------------------------------------------------------------------------------------
+__device__ inline double bb64(double v, int l) {
+  int2 p = __builtin_bit_cast(int2, v);
+  p.x = __builtin_amdgcn_readlane(p.x, l);
+  p.y = __builtin_amdgcn_readlane(p.y, l);
+  return __builtin_bit_cast(double, p);
+}
+__device__ inline uint64_t bbu64(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ inline double bwsum(double v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+template <bool F32>
+__global__ __launch_bounds__(kBlock) void k_bbackward_rows(BBackward b, double* __restrict__ Rrow,
+                                                           double* __restrict__ Trow, double* __restrict__ Urow) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const XcdRows rr = xcd_rows(b.g.n, threadIdx.x / kWave, kBlock / kWave);
+  const int S = b.S;
+  const bool active = lane < S;
+  for (int64_t row = rr.first; row < rr.end; row += rr.step) {
+    const BInst& I = b.g.inst[b.g.inst_of_row[row]];
+    const double inv_r = 1.0 / I.radius;
+    float4 pi32;
+    double4 pi64;
+    if (F32) pi32 = b.pts32[row];
+    else pi64 = b.pts64[row];
+    const double ai = b.a[row];
+    const uint64_t mi = b.mask[row];
+    const double dsi = sqrt(b.dinv[row]);
+    const double qi = active ? b.Q[row * S + lane] : 0.0;
+    const double wi = active ? (((mi >> lane) & 1ull) ? -dsi : dsi) : 0.0;
+    double accR = 0.0, accT = 0.0, aR = 0.0, aT = 0.0;
+    const int64_t s0 = b.rp[row], e0 = b.rp[row + 1];
+    for (int64_t k0 = s0; k0 < e0; k0 += kWave) {
+      const int64_t k = k0 + lane;
+      const bool valid = k < e0;
+      const int32_t j = valid ? b.col[k] : (int32_t)row;
+      double gW = 0.0, gWp = 0.0;
+      if (valid) {
+        double W, dW, gj;
+        if (F32) {
+          const float4 pj = b.pts32[j];
+          const double dx = (double)pi32.x - (double)pj.x, dy = (double)pi32.y - (double)pj.y,
+                       dz = (double)pi32.z - (double)pj.z;
+          const double d2 = dx * dx + dy * dy + dz * dz;
+          const float t = fmaxf((float)((I.r2 - d2) * I.inv_r2), 0.0f);
+          const float rho = __builtin_amdgcn_sqrtf((float)(d2 * I.inv_r2));
+          const float om = t * __builtin_amdgcn_rcpf(1.0f + rho);
+          const float om2 = om * om;
+          W = om2 * om2 * (4.0f * rho + 1.0f);
+          dW = 20.0f * rho * rho * om2 * om * (float)inv_r;
+          gj = fmaxf(pj.w, 0.0f);
+        } else {
+          const double4 pj = b.pts64[j];
+          const double dx = pi64.x - pj.x, dy = pi64.y - pj.y, dz = pi64.z - pj.z;
+          const double d2 = dx * dx + dy * dy + dz * dz;
+          const double t = fmax((I.r2 - d2) * I.inv_r2, 0.0);
+          const double rho = sqrt(d2 * I.inv_r2);
+          const double om = t / (1.0 + rho);
+          const double om2 = om * om;
+          W = om2 * om2 * (4.0 * rho + 1.0);
+          dW = 20.0 * rho * rho * om2 * om * inv_r;
+          gj = fmax(pj.w, 0.0);
+        }
+        gW = gj * W;
+        gWp = gj * dW;
+        const double aj = b.a[j];
+        aR += gW * aj;
+        aT += gWp * aj;
+      }
+      const uint64_t mj = valid ? b.mask[j] : 0ull;
+      const double dsj = valid ? sqrt(b.dinv[j]) : 0.0;
+      const int cnt = (int)((e0 - k0) < kWave ? (e0 - k0) : kWave);
+      for (int l = 0; l < cnt; ++l) {
+        const int32_t jj = __builtin_amdgcn_readlane(j, l);
+        const double gw = bb64(gW, l), gwp = bb64(gWp, l), ds = bb64(dsj, l);
+        const uint64_t mm = bbu64(mj, l);
+        if (active) {
+          const double qj = b.Q[(int64_t)jj * S + lane];
+          const double wj = ((mm >> lane) & 1ull) ? -ds : ds;
+          const double c = qi * wj + qj * wi;
+          accR += gw * c;
+          accT += gwp * c;
+        }
+      }
+    }
+    const double sR = bwsum(aR), sT = bwsum(aT), pR = bwsum(accR), pT = bwsum(accT), U = bwsum(qi * wi);
+    if (lane == 0) {
+      const double inv2S = 0.5 / (double)S;
+      Rrow[row] = ai * sR - inv2S * pR;
+      Trow[row] = ai * sT - inv2S * pT;
+      Urow[row] = U;
+    }
+  }
+}
+
+hipError_t launch_bbackward_rows(const BBackward& b, int prec, double* Rrow, double* Trow, double* Urow,
+                                 hipStream_t st) {
+  int64_t blocks = (b.g.n + (kBlock / kWave) - 1) / (kBlock / kWave);
+  if (blocks > (1 << 16)) blocks = 1 << 16;
+  blocks = round_up8(blocks < 1 ? 1 : blocks);
+  if (prec == GP2S_MIXED)
+    hipLaunchKernelGGL(k_bbackward_rows<true>, dim3((unsigned)blocks), dim3(kBlock), 0, st, b, Rrow, Trow, Urow);
+  else
+    hipLaunchKernelGGL(k_bbackward_rows<false>, dim3((unsigned)blocks), dim3(kBlock), 0, st, b, Rrow, Trow, Urow);
+  return hipGetLastError();
+}
+
+// One workgroup per instance: dLML/dr, dLML/da_k, dLML/dsigma^2 from the row sums.
+__global__ __launch_bounds__(kBlock) void k_bgrad_reduce(BatchGeom g, int S, const double* __restrict__ x64,
+                                                         const double* __restrict__ g64, const double* __restrict__ a,
+                                                         const double* __restrict__ Rrow,
+                                                         const double* __restrict__ Trow,
+                                                         const double* __restrict__ Urow,
+                                                         const double* __restrict__ centers3,
+                                                         const int32_t* __restrict__ goff, double* __restrict__ grad) {
+  __shared__ double sh[kBlock];
+  const int i = blockIdx.x;
+  const BInst& I = g.inst[i];
+  auto block_sum = [&](double v) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+      __syncthreads();
+    }
+    const double t = sh[0];
+    __syncthreads();
+    return t;
+  };
+  double cr = 0.0, cs2 = 0.0;
+  for (int64_t r = I.row0 + threadIdx.x; r < I.row0 + I.rows; r += kBlock) {
+    cr += 0.5 * g64[r] * Trow[r];
+    cs2 += 0.5 * (a[r] * a[r] - Urow[r] / (double)S);
+  }
+  double t = block_sum(cr);
+  if (threadIdx.x == 0) grad[goff[i]] = t;
+  t = block_sum(cs2);
+  if (threadIdx.x == 0) grad[goff[i] + I.P + 1] = t;
+  for (int k = 0; k < I.P; ++k) {
+    const double* c = centers3 + (int64_t)(I.cent0 + k) * 3;
+    double acc = 0.0;
+    for (int64_t r = I.row0 + threadIdx.x; r < I.row0 + I.rows; r += kBlock) {
+      double d2 = 0.0;
+      for (int q = 0; q < 3; ++q) {
+        const double d = x64[r * 3 + q] - c[q];
+        d2 += d * d;
+      }
+      if (d2 < I.bump_w2) acc += exp(1.0 - 1.0 / (1.0 - d2 / I.bump_w2)) * Rrow[r];
+    }
+    t = block_sum(acc);
+    if (threadIdx.x == 0) grad[goff[i] + 1 + k] = t;
+  }
+}
+
+hipError_t launch_bgrad_reduce(const BatchGeom& g, int S, const double* x64, const double* g64, const double* a,
+                               const double* Rrow, const double* Trow, const double* Urow, const double* centers3,
+                               const int32_t* goff, double* grad, hipStream_t st) {
+  hipLaunchKernelGGL(k_bgrad_reduce, dim3(g.M), dim3(kBlock), 0, st, g, S, x64, g64, a, Rrow, Trow, Urow, centers3,
+                     goff, grad);
+  return hipGetLastError();
+}
+
+}  // namespace gp2s

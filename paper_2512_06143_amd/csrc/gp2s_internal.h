@@ -87,6 +87,31 @@ __device__ inline XcdRows xcd_rows(int64_t n, int unit, int units) {
 }
 __host__ inline int64_t round_up8(int64_t b) { return (b + 7) / 8 * 8; }
 
+// ---- batched instances ---------------------------------------------------------------
+// Many independent instances form one block-diagonal system. Rows (and columns) are
+// instance-major, bin-major inside an instance. Points are stored with three
+// coordinates (z = 0 for 2-D instances, whose grids have nb[2] = 1), so one 3-D code
+// path serves both dimensions with identical arithmetic.
+constexpr int kBRows = 256;  // rows per workgroup in the batched CG kernels
+
+struct BInst {
+  GridDev grid;          // bins of side >= r / m (nb[2] = 1 in 2-D)
+  int64_t row0, rows;    // row range of the instance (user rows are instance-major too)
+  int64_t bin0;          // first global bin of the instance
+  int64_t blk0, nblk;    // its workgroups in the instance-aligned decomposition
+  double radius, r2, inv_r2, noise, bump_w2;
+  int32_t dim, P, cent0, m;  // bump offset into the shared centre/weight arrays; bin refinement
+};
+
+struct BatchGeom {
+  const BInst* inst;         // [M]
+  int32_t M;
+  const int64_t* row_start;  // [M + 1] row0 of every instance, then the total
+  const int32_t* inst_of_row;  // [N]
+  const int32_t* blk_inst;     // [number of workgroups] instance of each workgroup
+  int64_t n, nblk;
+};
+
 // ---- kernel launchers (defined in the .hip files) ---------------------------------
 // prologue.hip
 hipError_t launch_bbox(const double* x, int64_t n, int dim, double* part, int32_t* nonfinite,
@@ -134,7 +159,7 @@ hipError_t launch_spmv(int prec, const int64_t* rp, const int32_t* col, const vo
 hipError_t launch_spmm(int prec, const int64_t* rp, const int32_t* col, const void* val,
                        int64_t n, int S, const double* X, double* Y, hipStream_t st);
 // CG product step: Q = K P plus p^T q per column, then alpha = rz / p^T q.
-// P and Q are float32 when f32vec (block solves of the mixed path), else float64.
+// P is float32 when f32vec (block solves of the mixed path), else float64; Q is float64.
 hipError_t launch_cg_matvec(int prec, const int64_t* rp, const int32_t* col, const void* val,
                             int64_t n, int S, double mean_row, const void* P, void* Q, bool f32vec,
                             const CgState& cs, hipStream_t st);
@@ -190,5 +215,60 @@ hipError_t launch_grad_reduce(int64_t n, int dim, int P, int S, const double* x6
                               const double* a, const double* Rrow, const double* Trow,
                               const double* Urow, const double* centers, double bump_w2,
                               double* partial, uint32_t* ticket, double* grad, hipStream_t st);
+
+// batch.hip
+hipError_t launch_bbbox(const double* x3, const BatchGeom& g, double* part, int32_t* nonfinite, hipStream_t st);
+hipError_t launch_bprologue(const double* x3, const BatchGeom& g, const double* centers3, const double* weights,
+                            int32_t* bin_of, int32_t* slot, int32_t* bin_count, double* g64_user, uint8_t* gam,
+                            hipStream_t st);
+hipError_t launch_bgather(const double* x3, const BatchGeom& g, const int32_t* perm, const int32_t* bin_of,
+                          const double* g64_user, const uint8_t* gam, float4* pts32, double4* pts64, double* x64,
+                          double* g64, int32_t* binid, int32_t* inst_of_row, hipStream_t st);
+struct BAsm {
+  BatchGeom g;
+  const float4* pts32;
+  const double4* pts64;
+  const double* g64;
+  const int32_t* binid;
+  const int64_t* bin_start;
+  int64_t cap;  // fill: writes stop at this many entries (capacity of col/val)
+};
+hipError_t launch_bassemble_count(const BAsm& a, int prec, int32_t* row_cnt, hipStream_t st);
+hipError_t launch_bassemble_fill(const BAsm& a, int prec, const int64_t* row_ptr, int32_t* col, void* val,
+                                 double* diag, int32_t* overflow, hipStream_t st);
+hipError_t launch_bprobe_masks(const BatchGeom& g, const int32_t* perm, uint64_t seed, int S, uint64_t* mask,
+                               hipStream_t st);
+// Batched CG over instance-aligned workgroups; S columns per instance (a power of two <= 64).
+hipError_t launch_bcg_matvec(int prec, const BatchGeom& g, const int64_t* rp, const int32_t* col, const void* val,
+                             int S, int lanes, const void* P, void* Q, bool f32vec, const CgState& cs,
+                             hipStream_t st);
+hipError_t launch_bcg_init(const BatchGeom& g, int S, const double* B, const double* dinv, double* X, double* R,
+                           void* P, bool f32vec, const CgState& cs, double tol, hipStream_t st);
+hipError_t launch_bcg_update(const BatchGeom& g, int S, double* X, double* R, const void* P, const void* Q,
+                             bool f32vec, const double* dinv, const CgState& cs, const int32_t* iter_dev,
+                             hipStream_t st);
+hipError_t launch_bcg_pupdate(const BatchGeom& g, int S, void* P, const double* R, const double* dinv, bool f32vec,
+                              const CgState& cs, int32_t* iter_dev, hipStream_t st);
+// out[i] over instance i's rows: mode 0 = a.b, 1 = sum ln a
+hipError_t launch_bseg_reduce(const BatchGeom& g, int mode, const double* a, const double* b, double* out,
+                              hipStream_t st);
+struct BBackward {
+  BatchGeom g;
+  const int64_t* rp;
+  const int32_t* col;
+  const float4* pts32;
+  const double4* pts64;
+  const double* a;
+  const double* Q;
+  const uint64_t* mask;
+  const double* dinv;
+  int S;
+};
+hipError_t launch_bbackward_rows(const BBackward& b, int prec, double* Rrow, double* Trow, double* Urow,
+                                 hipStream_t st);
+// grad[goff[i] + c] for c < P_i + 2 (r, a_1..a_P, sigma^2) of every instance
+hipError_t launch_bgrad_reduce(const BatchGeom& g, int S, const double* x64, const double* g64, const double* a,
+                               const double* Rrow, const double* Trow, const double* Urow, const double* centers3,
+                               const int32_t* goff, double* grad, hipStream_t st);
 
 }  // namespace gp2s

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t n, int S, const doub
 template <typename VEC>
 __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int S, double* __restrict__ X,
                                                       double* __restrict__ R, const VEC* __restrict__ P,
-                                                      const VEC* __restrict__ Q,
+                                                      const double* __restrict__ Q,
                                                       const double* __restrict__ dinv, CgState cs,
                                                       int32_t iter) {
   __shared__ double sh[kBlock];
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int S, double* 
     double r = R[e];
     if (a != 0.0) {
       X[e] += a * (double)P[e];
-      r -= a * (double)Q[e];
+      r -= a * Q[e];
       R[e] = r;
     }
     rz += r * (r * dinv[i]);
@@ -227,7 +227,7 @@ hipError_t launch_cg_update(int64_t n, int S, double* X, double* R, const void* 
   const unsigned nb = cg_blocks(n * S, nth);
   if (f32vec)
     hipLaunchKernelGGL(k_cg_update<float>, dim3(nb), dim3(nth), 0, st, n, S, X, R,
-                       static_cast<const float*>(P), static_cast<const float*>(Q), dinv, cs, iter);
+                       static_cast<const float*>(P), static_cast<const double*>(Q), dinv, cs, iter);
   else
     hipLaunchKernelGGL(k_cg_update<double>, dim3(nb), dim3(nth), 0, st, n, S, X, R,
                        static_cast<const double*>(P), static_cast<const double*>(Q), dinv, cs, iter);

@@ -104,9 +104,9 @@ hipError_t launch_spmv(int prec, const int64_t* rp, const int32_t* col, const vo
 // column s. The row's column offsets (j * S) and values are loaded 64 at a time (one
 // per lane) and broadcast with readlane, so every lane reads X[j * S + s] for the
 // same j: one coalesced row of X per stored entry, eight rows in flight per wave.
-// The loop is bound by vector-instruction issue, not memory: per stored entry it
-// costs two readlanes, one load and one multiply-add. float32 vectors accumulate in
-// float32 (their products are stored in float32 anyway).
+// The loop is bound by vector-instruction issue, not memory. Search directions may be
+// float32 (the probe block of the mixed path); products accumulate and are stored in
+// float64 either way.
 __device__ inline double bcast_acc(double v, int l) {
   int2 p = __builtin_bit_cast(int2, v);
   p.x = __builtin_amdgcn_readlane(p.x, l);
@@ -119,55 +119,43 @@ __device__ inline float bcast_acc(float v, int l) {
 
 constexpr int kSpmmUnroll = 8;
 
-// Accumulator type of the block product: float32 when the vectors are float32 (the
-// probe block of the mixed path), float64 otherwise.
-template <typename VEC>
-struct AccOf {
-  using type = double;
-};
-template <>
-struct AccOf<float> {
-  using type = float;
-};
-
-template <typename V, typename VEC, bool DOT>
+template <typename V, typename PT, typename QT, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_spmm(const int64_t* __restrict__ rp,
                                                  const int32_t* __restrict__ col,
                                                  const V* __restrict__ val, int64_t n, int S,
-                                                 const VEC* __restrict__ X,
-                                                 VEC* __restrict__ Y, CgState cs) {
-  using Acc = typename AccOf<VEC>::type;
+                                                 const PT* __restrict__ X,
+                                                 QT* __restrict__ Y, CgState cs) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   const XcdRows rr = xcd_rows(n, wid, kBlock / kWave);
   const bool active = lane < S;
   const int ls = active ? lane : 0;
-  const VEC* __restrict__ Xl = X + ls;  // this lane's column
+  const PT* __restrict__ Xl = X + ls;  // this lane's column
   double dot = 0.0;
   for (int64_t row = rr.first; row < rr.end; row += rr.step) {
     const int64_t s = rp[row], e = rp[row + 1];
-    Acc acc = 0;
+    double acc = 0.0;
     for (int64_t k0 = s; k0 < e; k0 += kWave) {
       // one stored entry per lane: row offset of its column in X (n * S < 2^31) and value
       const int64_t k = k0 + lane;
       const int32_t off = k < e ? col[k] * S : 0;
-      const Acc vj = k < e ? (Acc)val[k] : (Acc)0;
+      const V vj = k < e ? val[k] : (V)0;
       const int cnt = (int)((e - k0) < kWave ? (e - k0) : kWave);
       int l = 0;
       for (; l + kSpmmUnroll <= cnt; l += kSpmmUnroll) {
-        Acc xv[kSpmmUnroll], vv[kSpmmUnroll];
+        double xv[kSpmmUnroll], vv[kSpmmUnroll];
 #pragma unroll
         for (int u = 0; u < kSpmmUnroll; ++u) {
-          vv[u] = bcast_acc(vj, l + u);
-          xv[u] = (Acc)Xl[__builtin_amdgcn_readlane(off, l + u)];
+          vv[u] = (double)bcast_acc(vj, l + u);
+          xv[u] = (double)Xl[__builtin_amdgcn_readlane(off, l + u)];
         }
 #pragma unroll
         for (int u = 0; u < kSpmmUnroll; ++u) acc += vv[u] * xv[u];
       }
-      for (; l < cnt; ++l) acc += bcast_acc(vj, l) * (Acc)Xl[__builtin_amdgcn_readlane(off, l)];
+      for (; l < cnt; ++l) acc += (double)bcast_acc(vj, l) * (double)Xl[__builtin_amdgcn_readlane(off, l)];
     }
     if (active) {
-      const VEC q = (VEC)acc;
+      const QT q = (QT)acc;
       Y[row * S + lane] = q;
       if (DOT) dot += (double)q * (double)X[row * S + lane];
     }
@@ -184,16 +172,16 @@ __global__ __launch_bounds__(kBlock) void k_spmm(const int64_t* __restrict__ rp,
   }
 }
 
-template <typename V, typename VEC, bool DOT>
+template <typename V, typename PT, typename QT, bool DOT>
 static hipError_t spmm_dispatch(const int64_t* rp, const int32_t* col, const V* val, int64_t n, int S,
-                                const VEC* X, VEC* Y, const CgState& cs, hipStream_t st,
+                                const PT* X, QT* Y, const CgState& cs, hipStream_t st,
                                 int* nblocks = nullptr) {
   int64_t blocks = (n + (kBlock / kWave) - 1) / (kBlock / kWave);
   const int64_t cap = DOT ? kReduceBlocks : (1 << 20);
   if (blocks > cap) blocks = cap;
   blocks = round_up8(blocks < 1 ? 1 : blocks);
   if (nblocks) *nblocks = (int)blocks;
-  hipLaunchKernelGGL((k_spmm<V, VEC, DOT>), dim3((unsigned)blocks), dim3(kBlock), 0, st, rp, col, val, n, S,
+  hipLaunchKernelGGL((k_spmm<V, PT, QT, DOT>), dim3((unsigned)blocks), dim3(kBlock), 0, st, rp, col, val, n, S,
                      X, Y, cs);
   return hipGetLastError();
 }
@@ -202,8 +190,8 @@ hipError_t launch_spmm(int prec, const int64_t* rp, const int32_t* col, const vo
                        int S, const double* X, double* Y, hipStream_t st) {
   CgState cs{};
   if (prec == GP2S_MIXED)
-    return spmm_dispatch<float, double, false>(rp, col, static_cast<const float*>(val), n, S, X, Y, cs, st);
-  return spmm_dispatch<double, double, false>(rp, col, static_cast<const double*>(val), n, S, X, Y, cs, st);
+    return spmm_dispatch<float, double, double, false>(rp, col, static_cast<const float*>(val), n, S, X, Y, cs, st);
+  return spmm_dispatch<double, double, double, false>(rp, col, static_cast<const double*>(val), n, S, X, Y, cs, st);
 }
 
 hipError_t launch_cg_matvec(int prec, const int64_t* rp, const int32_t* col, const void* val,
@@ -221,14 +209,17 @@ hipError_t launch_cg_matvec(int prec, const int64_t* rp, const int32_t* col, con
                                       static_cast<const double*>(P), static_cast<double*>(Q), cs, st, &nb);
   } else if (prec == GP2S_MIXED) {
     if (f32vec)
-      e = spmm_dispatch<float, float, true>(rp, col, static_cast<const float*>(val), n, S,
-                                            static_cast<const float*>(P), static_cast<float*>(Q), cs, st, &nb);
+      e = spmm_dispatch<float, float, double, true>(rp, col, static_cast<const float*>(val), n, S,
+                                                    static_cast<const float*>(P), static_cast<double*>(Q), cs, st,
+                                                    &nb);
     else
-      e = spmm_dispatch<float, double, true>(rp, col, static_cast<const float*>(val), n, S,
-                                             static_cast<const double*>(P), static_cast<double*>(Q), cs, st, &nb);
+      e = spmm_dispatch<float, double, double, true>(rp, col, static_cast<const float*>(val), n, S,
+                                                     static_cast<const double*>(P), static_cast<double*>(Q), cs, st,
+                                                     &nb);
   } else {
-    e = spmm_dispatch<double, double, true>(rp, col, static_cast<const double*>(val), n, S,
-                                            static_cast<const double*>(P), static_cast<double*>(Q), cs, st, &nb);
+    e = spmm_dispatch<double, double, double, true>(rp, col, static_cast<const double*>(val), n, S,
+                                                    static_cast<const double*>(P), static_cast<double*>(Q), cs, st,
+                                                    &nb);
   }
   if (e != hipSuccess) return e;
   return launch_cg_alpha(cs, nb, S, st);

@@ -89,6 +89,13 @@ _SIGS = {
     "gp2s_lml": (_i32, [_vp, _vp, _vp, ctypes.POINTER(SolveOpts), _vp, ctypes.POINTER(Report)]),
     "gp2s_lml_grad": (_i32, [_vp, _vp, _vp, ctypes.POINTER(SolveOpts), _vp, ctypes.POINTER(Report),
                              ctypes.POINTER(ctypes.c_double)]),
+    "gp2s_batch_plan": (_i32, [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_vp), ctypes.POINTER(Params), _i32,
+                               ctypes.POINTER(SolveOpts), ctypes.POINTER(_vp)]),
+    "gp2s_batch_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                               ctypes.POINTER(_i32)]),
+    "gp2s_batch_run": (_i32, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.POINTER(ctypes.c_double)), ctypes.POINTER(Report)]),
+    "gp2s_batch_free": (_i32, [_vp]),
 }
 EXPORTED = tuple(_SIGS)
 for _name, (_res, _args) in _SIGS.items():
@@ -329,3 +336,68 @@ def gp2s_lml_grad(m: Matrix, y, opts: SolveOpts | None = None, want_a=True, allo
     rep.status = ctx.check(lib.gp2s_lml_grad(ctx.ptr, m.handle, _ptr(yd), ctypes.byref(o), _ptr(a),
                                              ctypes.byref(rep), grad), allow_noconv)
     return rep, np.array(grad[:], dtype=np.float64), a
+
+
+class Batch:
+    """Many instances planned together (gp2s_batch_plan) and evaluated together
+    (gp2s_batch_run). `xs` are (n_i, d_i) arrays or tensors, `params` HostParams."""
+
+    def __init__(self, xs, params, precision="mixed", opts: SolveOpts | None = None, ctx: Context | None = None):
+        self.ctx = ctx or default_context()
+        self.prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.opts = opts or default_opts(n_probes=16)
+        self.M = len(xs)
+        self._xs = [_as_dev64(x, self.ctx) for x in xs]
+        self.n = [int(x.shape[0]) for x in self._xs]
+        self.params = list(params)
+        self.P = [int(np.asarray(p.weights).reshape(-1).shape[0]) for p in self.params]
+        n_arr = (_i64 * self.M)(*self.n)
+        x_arr = (_vp * self.M)(*[_ptr(x) for x in self._xs])
+        p_arr, self._keep = self._params_array(self.params)
+        h = ctypes.c_void_p()
+        self.ctx.check(lib.gp2s_batch_plan(self.ctx.ptr, self.M, n_arr, x_arr, p_arr, self.prec,
+                                           ctypes.byref(self.opts), ctypes.byref(h)))
+        self.handle = h
+
+    def _params_array(self, params):
+        arr = (Params * len(params))()
+        keep = []
+        for i, p in enumerate(params):
+            c, k = p.to_c()
+            arr[i] = c
+            keep.append(k)
+        return arr, keep
+
+    def info(self):
+        nt, nnz, cap = _i64(), _i64(), _i64()
+        tuned = (_i32 * 3)()
+        self.ctx.check(lib.gp2s_batch_info(self.handle, ctypes.byref(nt), ctypes.byref(nnz), ctypes.byref(cap),
+                                           tuned))
+        return dict(n_total=nt.value, nnz=nnz.value, capacity=cap.value, bin_refinement=tuned[0],
+                    spmv_lanes=tuned[1], spmm_lanes=tuned[2])
+
+    def run(self, ys, params=None, want_grad=True, allow_noconv=False):
+        """Returns (lml [M], list of gradients or None, list of report dicts)."""
+        yd = [_as_dev64(y, self.ctx) for y in ys]
+        y_arr = (_vp * self.M)(*[_ptr(y) for y in yd])
+        p_arr, keep = (self._params_array(params) if params is not None else (None, None))
+        lml = (ctypes.c_double * self.M)()
+        grads = [(ctypes.c_double * (p + 2))() for p in self.P] if want_grad else None
+        g_arr = ((ctypes.POINTER(ctypes.c_double) * self.M)(*[ctypes.cast(g, ctypes.POINTER(ctypes.c_double))
+                                                               for g in grads]) if want_grad else None)
+        reps = (Report * self.M)()
+        st = lib.gp2s_batch_run(self.handle, y_arr, p_arr, lml, g_arr, reps)
+        self.ctx.check(st, allow_noconv)
+        return (np.array(lml[:]), [np.array(g[:]) for g in grads] if want_grad else None,
+                [r.as_dict() for r in reps])
+
+    def free(self):
+        if getattr(self, "handle", None):
+            lib.gp2s_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

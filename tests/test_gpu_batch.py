@@ -1,0 +1,90 @@
+"""Batched instances: each instance of a batch equals its own single-instance run
+(same probes), and the oracle on the same probes; hyperparameter changes and the
+capacity limit behave as documented."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import exported_user_csr, params_of
+
+pytestmark = pytest.mark.gpu
+
+
+def _G():
+    import paper_2512_06143_amd as G
+    return G
+
+
+def _instances():
+    specs = [(900, 2, 0.07, "uniform"), (2500, 3, 0.12, "gmm"), (1300, 2, 0.05, "gmm"), (3100, 3, 0.09, "uniform"),
+             (700, 2, 0.11, "uniform"), (2049, 2, 0.04, "uniform")]
+    out = []
+    for k, (n, d, r, pts) in enumerate(specs):
+        p = workloads.make_random_problem(70 + k, n, d, r, n_bumps=2 + k % 3, bump_width=0.55, points=pts,
+                                          noise_var=[1e-4, 1e-3, 3e-4][k % 3])
+        out.append(p)
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_matches_single_runs_and_oracle(gpu, precision):
+    G = _G()
+    probs = _instances()
+    S = 16
+    opts = G.default_opts(n_probes=S, seed=5, tol=1e-10, probe_tol=1e-9, max_iter=30000)
+    b = G.Batch([p.x for p in probs], [params_of(p) for p in probs], precision, opts)
+    info = b.info()
+    print(f"[batch/{precision}] {info}", flush=True)
+    lml, grads, reps = b.run([p.y for p in probs])
+    for i, p in enumerate(probs):
+        m = G.gp2s_assemble(p.x, params_of(p), precision)
+        rep, g1, _ = G.gp2s_lml_grad(m, p.y, opts)
+        assert abs(lml[i] - rep.lml) <= 1e-9 * abs(rep.lml), (i, lml[i], rep.lml)
+        assert abs(reps[i]["logdet"] - rep.logdet) <= 1e-9 * abs(rep.logdet)
+        scale = np.maximum(np.abs(g1), 1e-8 * np.abs(g1).max())
+        assert np.all(np.abs(grads[i] - g1) <= 1e-6 * scale), (i, grads[i], g1)
+        assert reps[i]["resid"] <= 1e-10
+        if i in (1, 4):
+            Kd = exported_user_csr(m)[0].toarray()
+            Z = oracle.rademacher_probes(5, S, p.n)
+            gam, _ = oracle.logdet_same_probe(Kd, Z)
+            assert abs(reps[i]["logdet"] - gam) <= 1e-8 * abs(gam)
+            gref, parts = oracle.grad_same_probe(p.x, p.y, Z, p.radius, p.bump_width, p.centers, p.weights,
+                                                 p.noise_var, K=Kd)
+            sc = np.maximum(np.abs(gref), 1e-6 * (np.abs(parts["fit"]) + 0.5 * np.abs(parts["tau"])))
+            assert np.all(np.abs(grads[i] - gref) <= 1e-4 * sc)
+    b.free()
+
+
+def test_batch_new_hyperparameters_and_capacity(gpu):
+    G = _G()
+    probs = _instances()[:3]
+    opts = G.default_opts(n_probes=8, seed=1, tol=1e-9, probe_tol=1e-7)
+    b = G.Batch([p.x for p in probs], [params_of(p) for p in probs], "fp64", opts)
+    # smaller radius and new weights / noise: equals a fresh single-instance evaluation
+    new = []
+    for p in probs:
+        q = params_of(p)
+        q.radius = p.radius * 0.9
+        q.weights = np.asarray(p.weights) * 1.1
+        q.noise_var = p.noise_var * 2
+        new.append(q)
+    lml, grads, reps = b.run([p.y for p in probs], params=new)
+    for i, p in enumerate(probs):
+        m = G.gp2s_assemble(p.x, new[i], "fp64")
+        rep, g1, _ = G.gp2s_lml_grad(m, p.y, opts)
+        assert abs(lml[i] - rep.lml) <= 1e-8 * abs(rep.lml)
+    # a much larger radius needs more entries than reserved
+    big = [params_of(p) for p in probs]
+    big[0].radius = probs[0].radius * 12  # every pair of the first instance
+    with pytest.raises(G.GP2SError) as e:
+        b.run([p.y for p in probs], params=big)
+    assert e.value.status == 4
+    # geometry changes are rejected
+    bad = [params_of(p) for p in probs]
+    bad[1].bump_width = 0.3
+    with pytest.raises(G.GP2SError) as e:
+        b.run([p.y for p in probs], params=bad)
+    assert e.value.status == 1
+    b.free()

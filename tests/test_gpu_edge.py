@@ -52,9 +52,11 @@ def test_points_outside_every_bump(gpu, precision):
     # the stored diagonal is sigma^2 rounded to the path's precision
     d = float(np.float32(2e-3)) if precision == "mixed" else 2e-3
     np.testing.assert_allclose(a.cpu().numpy(), prob.y / d, rtol=1e-12)
-    assert rep.logdet == pytest.approx(prob.n * math.log(d), rel=1e-12)
+    # the mixed path's float32 probe directions perturb the CG steps at ~1e-8
+    tol = 1e-8 if precision == "mixed" else 1e-12
+    assert rep.logdet == pytest.approx(prob.n * math.log(d), rel=tol)
     assert grad[0] == 0.0 and grad[1] == 0.0 and grad[2] == 0.0
-    assert grad[3] == pytest.approx(0.5 * np.sum(prob.y ** 2) / d ** 2 - 0.5 * prob.n / d, rel=1e-9)
+    assert grad[3] == pytest.approx(0.5 * np.sum(prob.y ** 2) / d ** 2 - 0.5 * prob.n / d, rel=100 * tol)
 
 
 def test_duplicates_and_clamped_points(gpu):
