@@ -317,15 +317,23 @@ hipError_t launch_bprobe_masks(const BatchGeom& g, const int32_t* perm, uint64_t
 // ---- instance-aligned CG ------------------------------------------------------------------------
 struct BRows {
   int inst;
-  int64_t lo, hi;
+  int64_t blk, lo, hi;
 };
+// Row block of this workgroup: the identity for set-up kernels (blk_map null), the
+// compacted list of open instances' blocks inside the CG loop.
 __device__ inline BRows brows(const BatchGeom& g) {
   BRows r;
-  r.inst = g.blk_inst[blockIdx.x];
+  r.blk = g.blk_map ? (int64_t)g.blk_map[blockIdx.x] : (int64_t)blockIdx.x;
+  r.inst = g.blk_inst[r.blk];
   const BInst& I = g.inst[r.inst];
-  r.lo = I.row0 + (int64_t)(blockIdx.x - I.blk0) * kBRows;
+  r.lo = I.row0 + (r.blk - I.blk0) * kBRows;
   r.hi = min(r.lo + (int64_t)kBRows, I.row0 + I.rows);
   return r;
+}
+
+// True when some column of instance i is still iterating (uniform over the workgroup).
+__device__ inline bool inst_open(const CgState& cs, int i, int S) {
+  return __syncthreads_or((int)threadIdx.x < S && !cs.done[i * S + threadIdx.x]) != 0;
 }
 
 // Q = K P for one instance-aligned workgroup; `L` lanes per row (a power of two >= S),
@@ -336,7 +344,9 @@ template <int L, typename V, typename PT>
 __global__ __launch_bounds__(kBlock) void k_bspmm(BatchGeom g, const int64_t* __restrict__ rp,
                                                   const int32_t* __restrict__ col, const V* __restrict__ val, int S,
                                                   const PT* __restrict__ X, double* __restrict__ Y, CgState cs) {
+  constexpr int U = L < 8 ? L : 8;
   const BRows br = brows(g);
+  if (!inst_open(cs, br.inst, S)) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   const int seg = lane / L, sl = lane % L;
@@ -351,12 +361,19 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(BatchGeom g, const int64_t* __
     for (int64_t k0 = s; k0 < e; k0 += L) {
       const int64_t k = k0 + sl;
       const int32_t off = k < e ? col[k] * S : 0;
-      const double vj = k < e ? (double)val[k] : 0.0;
+      const V vj = k < e ? val[k] : (V)0;
       const int cnt = (int)min((int64_t)L, e - k0);
-      for (int l = 0; l < cnt; ++l) {
-        const int32_t jo = __shfl(off, l, L);
-        const double vv = __shfl(vj, l, L);
-        acc += vv * (double)Xl[jo];
+      // U gathers in flight per step; lanes past the row end hold (offset 0, value 0)
+      for (int l = 0; l < cnt; l += U) {
+        V vv[U];
+        double xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          vv[u] = __shfl(vj, l + u, L);
+          xv[u] = (double)Xl[__shfl(off, l + u, L)];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += (double)vv[u] * xv[u];
       }
     }
     if (active) {
@@ -370,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(BatchGeom g, const int64_t* __
   if ((int)threadIdx.x < S) {
     double t = 0.0;
     for (int q = 0; q < kBlock / L; ++q) t += sh[q * L + threadIdx.x];
-    cs.partial[blockIdx.x * (int64_t)S + threadIdx.x] = t;
+    cs.partial[(int64_t)threadIdx.x * g.nblk + br.blk] = t;
   }
 }
 
@@ -380,19 +397,26 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(BatchGeom g, const int64_t* __
                                                   const int32_t* __restrict__ col, const V* __restrict__ val,
                                                   const double* __restrict__ x, double* __restrict__ y, CgState cs) {
   const BRows br = brows(g);
+  if (!inst_open(cs, br.inst, 1)) return;
   const int lane = threadIdx.x & (G - 1);
   const int grp = threadIdx.x / G;
   double dot = 0.0;
   for (int64_t row = br.lo + grp; row < br.hi; row += kBlock / G) {
     const int64_t s = rp[row], e = rp[row + 1];
-    double a0 = 0.0, a1 = 0.0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int64_t k = s + lane;
-    for (; k + G < e; k += 2 * G) {
-      a0 += (double)val[k] * x[col[k]];
-      a1 += (double)val[k + G] * x[col[k + G]];
+    for (; k + 3 * G < e; k += 4 * G) {
+      const int32_t c0 = col[k], c1 = col[k + G], c2 = col[k + 2 * G], c3 = col[k + 3 * G];
+      const double v0 = (double)val[k], v1 = (double)val[k + G], v2 = (double)val[k + 2 * G],
+                   v3 = (double)val[k + 3 * G];
+      const double x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
+      a0 += v0 * x0;
+      a1 += v1 * x1;
+      a2 += v2 * x2;
+      a3 += v3 * x3;
     }
-    if (k < e) a0 += (double)val[k] * x[col[k]];
-    double acc = a0 + a1;
+    for (; k < e; k += G) a0 += (double)val[k] * x[col[k]];
+    double acc = (a0 + a1) + (a2 + a3);
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
     if (lane == 0) {
@@ -407,16 +431,18 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(BatchGeom g, const int64_t* __
     if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) cs.partial[blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) cs.partial[br.blk] = sh[0];
 }
 
-// Sum of partial[(b * W + which) * S + s] over instance i's workgroups.
-__device__ inline double binst_sum(const BatchGeom& g, const double* partial, int i, int W, int which, int S, int s,
+// Per-workgroup partials are stored column-major, partial[(which * S + s) * nblk + block],
+// so one column's partials over an instance's workgroups are contiguous. Returns their sum.
+__device__ inline double binst_sum(const BatchGeom& g, const double* partial, int i, int which, int S, int s,
                                    double* sh) {
   const BInst& I = g.inst[i];
+  const double* __restrict__ part = partial + ((int64_t)which * S + s) * g.nblk;
   double v = 0.0;
   for (int64_t b = I.blk0 + threadIdx.x; b < I.blk0 + I.nblk; b += blockDim.x)
-    v += partial[(b * W + which) * S + s];
+    v += part[b];
   sh[threadIdx.x] = v;
   __syncthreads();
   for (int o = blockDim.x / 2; o > 0; o >>= 1) {
@@ -431,16 +457,18 @@ __device__ inline double binst_sum(const BatchGeom& g, const double* partial, in
 __global__ __launch_bounds__(kBlock) void k_bcg_alpha(BatchGeom g, CgState cs, int S) {
   __shared__ double sh[kBlock];
   const int c = blockIdx.x, i = c / S, s = c % S;
-  const double pq = binst_sum(g, cs.partial, i, 1, 0, S, s, sh);
+  if (cs.done[c]) {
+    if (threadIdx.x == 0) cs.alpha[c] = 0.0;
+    return;
+  }
+  const double pq = binst_sum(g, cs.partial, i, 0, S, s, sh);
   if (threadIdx.x == 0) {
     double a = 0.0;
-    if (!cs.done[c]) {
-      if (!(pq > 0.0) || !isfinite(pq)) {
-        cs.flags[0] = 1;
-        cs.flags[3] = c;
-      } else {
-        a = cs.rz[c] / pq;
-      }
+    if (!(pq > 0.0) || !isfinite(pq)) {
+      cs.flags[0] = 1;
+      cs.flags[3] = c;
+    } else {
+      a = cs.rz[c] / pq;
     }
     cs.alpha[c] = a;
   }
@@ -449,12 +477,12 @@ __global__ __launch_bounds__(kBlock) void k_bcg_alpha(BatchGeom g, CgState cs, i
 template <int G, typename V>
 static void bspmv_g(const BatchGeom& g, const int64_t* rp, const int32_t* col, const V* val, const double* P, double* Q,
                     const CgState& cs, hipStream_t st) {
-  hipLaunchKernelGGL((k_bspmv<G, V>), dim3((unsigned)g.nblk), dim3(kBlock), 0, st, g, rp, col, val, P, Q, cs);
+  hipLaunchKernelGGL((k_bspmv<G, V>), dim3((unsigned)g.grid), dim3(kBlock), 0, st, g, rp, col, val, P, Q, cs);
 }
 template <int L, typename V, typename PT>
 static void bspmm_l(const BatchGeom& g, const int64_t* rp, const int32_t* col, const V* val, int S, const PT* P,
                     double* Q, const CgState& cs, hipStream_t st) {
-  hipLaunchKernelGGL((k_bspmm<L, V, PT>), dim3((unsigned)g.nblk), dim3(kBlock), 0, st, g, rp, col, val, S, P, Q, cs);
+  hipLaunchKernelGGL((k_bspmm<L, V, PT>), dim3((unsigned)g.grid), dim3(kBlock), 0, st, g, rp, col, val, S, P, Q, cs);
 }
 template <typename V, typename PT>
 static void bspmm_any(int lanes, const BatchGeom& g, const int64_t* rp, const int32_t* col, const V* val, int S,
@@ -509,14 +537,15 @@ hipError_t launch_bcg_matvec(int prec, const BatchGeom& g, const int64_t* rp, co
 }
 
 // Per-column sums of one workgroup (thread t owns column t % S; S divides kBlock).
-__device__ inline void bcols_partial(double* sh, int S, double v, double* partial, int which) {
+__device__ inline void bcols_partial(double* sh, int S, double v, double* partial, int64_t nblk, int64_t blk,
+                                     int which) {
   sh[threadIdx.x] = v;
   __syncthreads();
   for (int o = kBlock / 2; o >= S; o >>= 1) {
     if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
-  if ((int)threadIdx.x < S) partial[(blockIdx.x * 2 + which) * (int64_t)S + threadIdx.x] = sh[threadIdx.x];
+  if ((int)threadIdx.x < S) partial[((int64_t)which * S + threadIdx.x) * nblk + blk] = sh[threadIdx.x];
   __syncthreads();
 }
 
@@ -537,15 +566,15 @@ __global__ __launch_bounds__(kBlock) void k_bcg_init(BatchGeom g, int S, const d
     rz += b * z;
     bb += b * b;
   }
-  bcols_partial(sh, S, rz, cs.partial, 0);
-  bcols_partial(sh, S, bb, cs.partial, 1);
+  bcols_partial(sh, S, rz, cs.partial, g.nblk, br.blk, 0);
+  bcols_partial(sh, S, bb, cs.partial, g.nblk, br.blk, 1);
 }
 
 __global__ __launch_bounds__(kBlock) void k_bcg_init_fin(BatchGeom g, CgState cs, int S, double tol) {
   __shared__ double sh[kBlock];
   const int c = blockIdx.x, i = c / S, s = c % S;
-  const double rz = binst_sum(g, cs.partial, i, 2, 0, S, s, sh);
-  const double bb = binst_sum(g, cs.partial, i, 2, 1, S, s, sh);
+  const double rz = binst_sum(g, cs.partial, i, 0, S, s, sh);
+  const double bb = binst_sum(g, cs.partial, i, 1, S, s, sh);
   if (threadIdx.x == 0) {
     cs.rz[c] = rz;
     cs.bb[c] = bb;
@@ -578,6 +607,7 @@ __global__ __launch_bounds__(kBlock) void k_bcg_update(BatchGeom g, int S, doubl
                                                        CgState cs) {
   __shared__ double sh[kBlock];
   const BRows br = brows(g);
+  if (!inst_open(cs, br.inst, S)) return;
   const int s_me = threadIdx.x % S;
   const double a = cs.alpha[br.inst * S + s_me];
   double rz = 0.0, rr = 0.0;
@@ -592,38 +622,40 @@ __global__ __launch_bounds__(kBlock) void k_bcg_update(BatchGeom g, int S, doubl
     rz += r * (r * dinv[i]);
     rr += r * r;
   }
-  bcols_partial(sh, S, rz, cs.partial, 0);
-  bcols_partial(sh, S, rr, cs.partial, 1);
+  bcols_partial(sh, S, rz, cs.partial, g.nblk, br.blk, 0);
+  bcols_partial(sh, S, rr, cs.partial, g.nblk, br.blk, 1);
 }
 
 __global__ __launch_bounds__(kBlock) void k_bcg_beta(BatchGeom g, CgState cs, int S, const int32_t* __restrict__ iter_dev) {
   __shared__ double sh[kBlock];
   const int c = blockIdx.x, i = c / S, s = c % S;
-  const double rzn = binst_sum(g, cs.partial, i, 2, 0, S, s, sh);
-  const double rrn = binst_sum(g, cs.partial, i, 2, 1, S, s, sh);
+  if (cs.done[c]) {
+    if (threadIdx.x == 0) cs.beta[c] = 0.0;
+    return;
+  }
+  const double rzn = binst_sum(g, cs.partial, i, 0, S, s, sh);
+  const double rrn = binst_sum(g, cs.partial, i, 1, S, s, sh);
   if (threadIdx.x != 0) return;
   const int32_t iter = *iter_dev;
   const int SM = g.M * S;
   double beta = 0.0;
-  if (!cs.done[c]) {
-    const double al = cs.alpha[c];
-    if (al == 0.0) {
+  const double al = cs.alpha[c];
+  if (al == 0.0) {
+    cs.done[c] = 1;
+  } else {
+    beta = rzn / cs.rz[c];
+    if (cs.hist_a && iter < cs.max_hist) {
+      cs.hist_a[(int64_t)iter * SM + c] = al;
+      cs.hist_b[(int64_t)iter * SM + c] = beta;
+    }
+    cs.iters[c] += 1;
+    cs.rz[c] = rzn;
+    cs.rr[c] = rrn;
+    if (!isfinite(rrn)) {
+      cs.flags[2] = 1;
       cs.done[c] = 1;
-    } else {
-      beta = rzn / cs.rz[c];
-      if (cs.hist_a && iter < cs.max_hist) {
-        cs.hist_a[(int64_t)iter * SM + c] = al;
-        cs.hist_b[(int64_t)iter * SM + c] = beta;
-      }
-      cs.iters[c] += 1;
-      cs.rz[c] = rzn;
-      cs.rr[c] = rrn;
-      if (!isfinite(rrn)) {
-        cs.flags[2] = 1;
-        cs.done[c] = 1;
-      } else if (rrn <= cs.tol2[c] * cs.bb[c]) {
-        cs.done[c] = 1;
-      }
+    } else if (rrn <= cs.tol2[c] * cs.bb[c]) {
+      cs.done[c] = 1;
     }
   }
   cs.beta[c] = beta;
@@ -632,10 +664,10 @@ __global__ __launch_bounds__(kBlock) void k_bcg_beta(BatchGeom g, CgState cs, in
 hipError_t launch_bcg_update(const BatchGeom& g, int S, double* X, double* R, const void* P, const void* Q, bool f32vec,
                              const double* dinv, const CgState& cs, const int32_t* iter_dev, hipStream_t st) {
   if (f32vec)
-    hipLaunchKernelGGL(k_bcg_update<float>, dim3((unsigned)g.nblk), dim3(kBlock), 0, st, g, S, X, R,
+    hipLaunchKernelGGL(k_bcg_update<float>, dim3((unsigned)g.grid), dim3(kBlock), 0, st, g, S, X, R,
                        static_cast<const float*>(P), static_cast<const double*>(Q), dinv, cs);
   else
-    hipLaunchKernelGGL(k_bcg_update<double>, dim3((unsigned)g.nblk), dim3(kBlock), 0, st, g, S, X, R,
+    hipLaunchKernelGGL(k_bcg_update<double>, dim3((unsigned)g.grid), dim3(kBlock), 0, st, g, S, X, R,
                        static_cast<const double*>(P), static_cast<const double*>(Q), dinv, cs);
   hipLaunchKernelGGL(k_bcg_beta, dim3((unsigned)(g.M * S)), dim3(kBlock), 0, st, g, cs, S, iter_dev);
   return hipGetLastError();
@@ -660,10 +692,10 @@ __global__ __launch_bounds__(kBlock) void k_bcg_pupdate(BatchGeom g, int S, VEC*
 hipError_t launch_bcg_pupdate(const BatchGeom& g, int S, void* P, const double* R, const double* dinv, bool f32vec,
                               const CgState& cs, int32_t* iter_dev, hipStream_t st) {
   if (f32vec)
-    hipLaunchKernelGGL(k_bcg_pupdate<float>, dim3((unsigned)g.nblk), dim3(kBlock), 0, st, g, S,
+    hipLaunchKernelGGL(k_bcg_pupdate<float>, dim3((unsigned)g.grid), dim3(kBlock), 0, st, g, S,
                        static_cast<float*>(P), R, dinv, cs, iter_dev);
   else
-    hipLaunchKernelGGL(k_bcg_pupdate<double>, dim3((unsigned)g.nblk), dim3(kBlock), 0, st, g, S,
+    hipLaunchKernelGGL(k_bcg_pupdate<double>, dim3((unsigned)g.grid), dim3(kBlock), 0, st, g, S,
                        static_cast<double*>(P), R, dinv, cs, iter_dev);
   return hipGetLastError();
 }

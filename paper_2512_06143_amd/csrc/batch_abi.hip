@@ -25,6 +25,7 @@ struct gp2s_batch_s {
   int64_t* row_start_d = nullptr;
   int32_t* inst_of_row = nullptr;
   int32_t* blk_inst = nullptr;
+  int32_t* blk_map = nullptr;  // compacted row blocks of the open instances (CG loop)
   int64_t nblk = 0;
   double* centers3_d = nullptr;
   double* weights_d = nullptr;
@@ -71,6 +72,8 @@ BatchGeom geom(const gp2s_batch b) {
   g.blk_inst = b->blk_inst;
   g.n = b->N;
   g.nblk = b->nblk;
+  g.blk_map = nullptr;
+  g.grid = b->nblk;
   return g;
 }
 
@@ -269,35 +272,52 @@ gp2s_status run_bcg(gp2s_batch b, int S, const double* B, double* X, const doubl
   bool open = n_open() > 0;
   int it = 0;
   if (open) {
-    // capture one chunk of iterations on the private stream
+    // One chunk of iterations is captured on the private stream and replayed. When
+    // the row blocks of the still-open instances fall to half of those launched, the
+    // chunk is captured again over just those blocks (at most log2(blocks) times).
     const int chunk = std::max(1, std::min(b->opts.check_every, max_iter));
     HIPCHK(hipEventRecord(b->ev, st));
     HIPCHK(hipStreamWaitEvent(b->cap_stream, b->ev, 0));
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t ce = hipSuccess;
-    for (int k = 0; k < chunk && ce == hipSuccess; ++k) {
-      ce = launch_bcg_matvec(b->prec, g, b->row_ptr, b->col, b->val, S, S == 1 ? b->spmv_lanes : b->spmm_lanes, P, Q,
-                             f32vec, cs, b->cap_stream);
-      if (ce == hipSuccess) ce = launch_bcg_update(g, S, X, R, P, Q, f32vec, b->dinv, cs, iter_dev, b->cap_stream);
-      if (ce == hipSuccess) ce = launch_bcg_pupdate(g, S, P, R, b->dinv, f32vec, cs, iter_dev, b->cap_stream);
-    }
-    hipError_t ee = hipStreamEndCapture(b->cap_stream, &graph);
-    if (ce != hipSuccess || ee != hipSuccess) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return fail(ctx, GP2S_E_HIP, "capturing the CG chunk failed: %s",
-                  hipGetErrorString(ce != hipSuccess ? ce : ee));
-    }
-    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (ie != hipSuccess) return fail(ctx, GP2S_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
     struct ExecGuard {
-      hipGraphExec_t e;
-      ~ExecGuard() { (void)hipGraphExecDestroy(e); }
-    } eg{exec};
+      hipGraphExec_t e = nullptr;
+      ~ExecGuard() {
+        if (e) (void)hipGraphExecDestroy(e);
+      }
+    } eg;
+    BatchGeom gc = g;
+    std::vector<int32_t> map;
+    auto capture = [&]() -> gp2s_status {
+      if (eg.e) {
+        (void)hipGraphExecDestroy(eg.e);
+        eg.e = nullptr;
+      }
+      hipGraph_t graph = nullptr;
+      HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t ce = hipSuccess;
+      for (int k = 0; k < chunk && ce == hipSuccess; ++k) {
+        ce = launch_bcg_matvec(b->prec, gc, b->row_ptr, b->col, b->val, S, S == 1 ? b->spmv_lanes : b->spmm_lanes, P,
+                               Q, f32vec, cs, b->cap_stream);
+        if (ce == hipSuccess) ce = launch_bcg_update(gc, S, X, R, P, Q, f32vec, b->dinv, cs, iter_dev, b->cap_stream);
+        if (ce == hipSuccess) ce = launch_bcg_pupdate(gc, S, P, R, b->dinv, f32vec, cs, iter_dev, b->cap_stream);
+      }
+      hipError_t ee = hipStreamEndCapture(b->cap_stream, &graph);
+      if (ce != hipSuccess || ee != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(ctx, GP2S_E_HIP, "capturing the CG chunk failed: %s",
+                    hipGetErrorString(ce != hipSuccess ? ce : ee));
+      }
+      hipError_t ie = hipGraphInstantiate(&eg.e, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) {
+        eg.e = nullptr;
+        return fail(ctx, GP2S_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+      }
+      return GP2S_OK;
+    };
+    s = capture();
+    if (s) return s;
     while (open && it < max_iter) {
-      HIPCHK(hipGraphLaunch(exec, b->cap_stream));
+      HIPCHK(hipGraphLaunch(eg.e, b->cap_stream));
       it += chunk;
       s = readback_on(ctx, b->cap_stream, si, (SM + 4) * sizeof(int32_t), poll.data());
       if (s) return s;
@@ -307,6 +327,29 @@ gp2s_status run_bcg(gp2s_batch b, int S, const double* B, double* X, const doubl
       if (poll[SM + 2]) return fail(ctx, GP2S_E_NONFINITE, "non-finite values during the batched %s", label);
       open = n_open() > 0;
       if (ctx->progress) ctx->progress(label, it, n_open(), 0.0, ctx->progress_user);
+      if (!open || it >= max_iter) break;
+      int64_t active = 0;
+      for (int i = 0; i < b->M; ++i) {
+        bool any = false;
+        for (int c = 0; c < S; ++c) any = any || poll[i * S + c] == 0;
+        if (any) active += b->inst_h[i].nblk;
+      }
+      if (2 * active <= gc.grid) {
+        map.clear();
+        for (int i = 0; i < b->M; ++i) {
+          bool any = false;
+          for (int c = 0; c < S; ++c) any = any || poll[i * S + c] == 0;
+          if (any)
+            for (int64_t k = 0; k < b->inst_h[i].nblk; ++k) map.push_back((int32_t)(b->inst_h[i].blk0 + k));
+        }
+        // ordered after the last replay and before the next on the private stream
+        HIPCHK(hipMemcpyAsync(b->blk_map, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                              b->cap_stream));
+        gc.blk_map = b->blk_map;
+        gc.grid = (int64_t)map.size();
+        s = capture();
+        if (s) return s;
+      }
     }
     HIPCHK(hipEventRecord(b->ev, b->cap_stream));
     HIPCHK(hipStreamWaitEvent(st, b->ev, 0));
@@ -501,6 +544,8 @@ gp2s_status gp2s_batch_plan(gp2s_ctx ctx, int32_t n_inst, const int64_t* n, cons
     if (m == 1) {
       b->blk_inst = bown<int32_t>(b, b->nblk);
       OOMCHK(b->blk_inst);
+      b->blk_map = bown<int32_t>(b, b->nblk);
+      OOMCHK(b->blk_map);
       std::vector<int32_t> bi(b->nblk);
       for (int i = 0; i < n_inst; ++i)
         for (int64_t k = 0; k < b->inst_h[i].nblk; ++k) bi[b->inst_h[i].blk0 + k] = i;

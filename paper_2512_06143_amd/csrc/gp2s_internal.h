@@ -92,7 +92,7 @@ __host__ inline int64_t round_up8(int64_t b) { return (b + 7) / 8 * 8; }
 // instance-major, bin-major inside an instance. Points are stored with three
 // coordinates (z = 0 for 2-D instances, whose grids have nb[2] = 1), so one 3-D code
 // path serves both dimensions with identical arithmetic.
-constexpr int kBRows = 256;  // rows per workgroup in the batched CG kernels
+constexpr int kBRows = 64;  // rows per workgroup in the batched CG kernels
 
 struct BInst {
   GridDev grid;          // bins of side >= r / m (nb[2] = 1 in 2-D)
@@ -110,6 +110,10 @@ struct BatchGeom {
   const int32_t* inst_of_row;  // [N]
   const int32_t* blk_inst;     // [number of workgroups] instance of each workgroup
   int64_t n, nblk;
+  // CG row kernels launch `grid` workgroups; workgroup k works on row block
+  // blk_map[k] (identity when blk_map is null), so converged instances can be dropped.
+  const int32_t* blk_map;
+  int64_t grid;
 };
 
 // ---- kernel launchers (defined in the .hip files) ---------------------------------
