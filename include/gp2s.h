@@ -188,6 +188,15 @@ gp2s_status gp2s_matrix_import(gp2s_ctx ctx, int64_t n, int64_t nnz, const int64
 
 gp2s_status gp2s_matrix_free(gp2s_matrix m);
 
+/* Block-product kernel used for `nrhs` columns (2..64) of this matrix, in CG probe
+ * blocks and gp2s_spmv: 0 one lane per column (any nrhs), 1 a 16-byte column slice
+ * per lane, 4 / 8 / 16 that many lanes splitting each row's stored entries (1, 4, 8
+ * and 16 need nrhs in {8, 16, 32, 64}, and G <= nrhs), -1 (the default) times the
+ * candidates on the first CG block product and keeps the fastest. A variant that does
+ * not apply gives GP2S_E_INVALID. All variants give the same products up to the
+ * order of float64 summation. */
+gp2s_status gp2s_matrix_set_block_product(gp2s_matrix m, int32_t nrhs, int32_t variant);
+
 /* ---- products and solves ------------------------------------------------------------
  * Y = K X for nrhs in [1, 64] right-hand sides; X and Y are DEVICE [n * nrhs] float64,
  * row-major (row i holds the nrhs values of point i). The CSR SpMV that drives the
@@ -241,7 +250,9 @@ gp2s_status gp2s_batch_plan(gp2s_ctx ctx, int32_t n_inst, const int64_t* n, cons
                             gp2s_batch* out);
 /* Total points, stored entries, reserved capacity and the tuned choices
  * tuned[3] = {bin refinement m, lanes per row of the single-RHS product, lanes per row
- * of the probe-block product} (HOST outputs, each may be NULL). */
+ * of the probe-block product: L > 1 for one lane per column in segments of L lanes, 1
+ * for 16-byte column slices per lane, -G for G lanes splitting each row's stored
+ * entries} (HOST outputs, each may be NULL). */
 gp2s_status gp2s_batch_info(gp2s_batch b, int64_t* n_total, int64_t* nnz, int64_t* capacity, int32_t* tuned);
 /* LML (and gradient) of every instance. y: HOST array of n_inst DEVICE pointers [n[i]];
  * params: HOST [n_inst] new hyperparameters, or NULL to keep the planned ones (dimension,

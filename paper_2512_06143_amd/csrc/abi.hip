@@ -17,6 +17,52 @@ struct CgRun {
   bool converged = false;
 };
 
+// Chooses the block product for S columns of this matrix by timing each variant on the
+// first CG product (the product and its alpha are recomputed by the first iteration).
+gp2s_status tune_block_product(gp2s_ctx ctx, gp2s_matrix m, int S, const void* P, void* Q, bool f32vec,
+                               const CgState& cs) {
+  std::vector<int> cand{0};
+  if (S == 8 || S == 16 || S == 32 || S == 64) cand.push_back(1);
+  for (int G = 4; G <= 16; G *= 2)
+    if (entry_product_ok(S, G)) cand.push_back(G);
+  if (cand.size() == 1) {
+    m->spmm_variant[S] = 0;
+    return GP2S_OK;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(ctx, GP2S_E_HIP, "hipEventCreate failed");
+  }
+  const double mean_row = (double)m->nnz / (double)m->n;
+  float best = 1e30f;
+  int pick = 0;
+  hipError_t err = hipSuccess;
+  for (int v : cand) {
+    err = launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, m->n, S, mean_row, v, P, Q, f32vec, cs,
+                           ctx->stream);
+    if (err == hipSuccess) err = hipEventRecord(e0, ctx->stream);
+    for (int r = 0; r < 3 && err == hipSuccess; ++r)
+      err = launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, m->n, S, mean_row, v, P, Q, f32vec, cs,
+                             ctx->stream);
+    if (err == hipSuccess) err = hipEventRecord(e1, ctx->stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    if (err != hipSuccess) break;
+    if (ms < best) {
+      best = ms;
+      pick = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(ctx, GP2S_E_HIP, "timing the block products: %s", hipGetErrorString(err));
+  m->spmm_variant[S] = pick;
+  return GP2S_OK;
+}
+
 // Jacobi-PCG for K X = B over S columns (internal order). X receives the solution.
 gp2s_status run_cg(gp2s_ctx ctx, gp2s_matrix m, int S, const double* B, double* X, double tol, int max_iter,
                    int check_every, bool keep_hist, Scratch& sc, CgRun& out, const char* label) {
@@ -64,12 +110,17 @@ gp2s_status run_cg(gp2s_ctx ctx, gp2s_matrix m, int S, const double* B, double* 
   gp2s_status st = read_poll();
   if (st) return st;
   if (poll[S + 2]) return fail(ctx, GP2S_E_NONFINITE, "non-finite right-hand side (%s)", label);
+  if (S > 1 && m->spmm_variant[S] == -2) {
+    st = tune_block_product(ctx, m, S, P, Q, f32vec, cs);
+    if (st) return st;
+  }
+  const int variant = S > 1 ? m->spmm_variant[S] : 0;
   int it = 0;
   bool open = n_open() > 0;
   while (open && it < max_iter) {
     TIMED(S == 1 ? GP2S_T_CG_MATVEC1 : GP2S_T_CG_MATVEC_BLOCK,
-          launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, n, S, (double)m->nnz / (double)n, P, Q, f32vec,
-                           cs, ctx->stream));
+          launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, n, S, (double)m->nnz / (double)n, variant, P, Q,
+                           f32vec, cs, ctx->stream));
     TIMED(S == 1 ? GP2S_T_CG_UPDATE1 : GP2S_T_CG_UPDATE_BLOCK,
           launch_cg_update(n, S, X, R, P, Q, f32vec, m->dinv, cs, it, ctx->stream));
     TIMED(S == 1 ? GP2S_T_CG_PUPDATE1 : GP2S_T_CG_PUPDATE_BLOCK,
@@ -686,6 +737,15 @@ gp2s_status gp2s_matrix_free(gp2s_matrix m) {
   return GP2S_OK;
 }
 
+gp2s_status gp2s_matrix_set_block_product(gp2s_matrix m, int32_t nrhs, int32_t variant) {
+  if (!m || nrhs < 2 || nrhs > kMaxProbes) return GP2S_E_INVALID;
+  const bool sliced = nrhs == 8 || nrhs == 16 || nrhs == 32 || nrhs == 64;
+  const bool ok = variant == -1 || variant == 0 || (variant == 1 && sliced) || entry_product_ok(nrhs, variant);
+  if (!ok) return GP2S_E_INVALID;
+  m->spmm_variant[nrhs] = variant == -1 ? -2 : variant;
+  return GP2S_OK;
+}
+
 gp2s_status gp2s_spmv(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X, double* Y) {
   if (!ctx) return GP2S_E_INVALID;
   gp2s_status st = check_matrix(ctx, m);
@@ -705,7 +765,9 @@ gp2s_status gp2s_spmv(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X
   if (nrhs == 1)
     TIMED(GP2S_T_SPMV, launch_spmv(m->prec, m->row_ptr, m->col, m->val, n, (double)m->nnz / n, Xi, Yi, ctx->stream));
   else
-    TIMED(GP2S_T_SPMM, launch_spmm(m->prec, m->row_ptr, m->col, m->val, n, nrhs, Xi, Yi, ctx->stream));
+    TIMED(GP2S_T_SPMM, launch_spmm(m->prec, m->row_ptr, m->col, m->val, n, nrhs, (double)m->nnz / n,
+                                           m->spmm_variant[nrhs] >= 0 ? m->spmm_variant[nrhs] : -1, Xi, Yi,
+                                           ctx->stream));
   HIPCHK(launch_scatter_rows(n, nrhs, m->perm, Yi, Y, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return GP2S_OK;

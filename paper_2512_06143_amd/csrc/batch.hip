@@ -8,6 +8,7 @@
 // atomics. The arithmetic of every step is the single-instance one (see
 // prologue.hip, assemble.hip, spmv.hip, pcg.hip, backward.hip).
 #include "gp2s_internal.h"
+#include "spmm_rows.h"
 
 namespace gp2s {
 
@@ -391,6 +392,90 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(BatchGeom g, const int64_t* __
   }
 }
 
+// Entry-parallel variant (spmm_rows.h) for S in {8, 16, 32, 64}: G lanes per row.
+template <int G, int S, typename V, typename PT>
+__global__ __launch_bounds__(kBlock) void k_bspmm_e(BatchGeom g, const int64_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ col, const V* __restrict__ val,
+                                                    const PT* __restrict__ X, double* __restrict__ Y, CgState cs) {
+  constexpr int CW = S < 16 ? S : 16;
+  constexpr int NP = S / CW;
+  constexpr int OW = CW / G;
+  const BRows br = brows(g);
+  if (!inst_open(cs, br.inst, S)) return;
+  const int lane = threadIdx.x % G;
+  double dot[NP * OW];
+#pragma unroll
+  for (int j = 0; j < NP * OW; ++j) dot[j] = 0.0;
+  for (int64_t row = br.lo + threadIdx.x / G; row < br.hi; row += kBlock / G) {
+    const int64_t s = rp[row], e = rp[row + 1];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      double q[OW];
+      row_cols_product<G, CW>(col, val, s, e, lane, X, S, p * CW, q);
+      const int64_t o = row * S + p * CW + lane * OW;
+#pragma unroll
+      for (int j = 0; j < OW; ++j) {
+        Y[o + j] = q[j];
+        dot[p * OW + j] += q[j] * (double)X[o + j];
+      }
+    }
+  }
+  __shared__ double sh[kBlock / kWave][S];
+  const int wid = threadIdx.x / kWave, wl = threadIdx.x % kWave;
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int j = 0; j < OW; ++j) {
+      const double t = wave_sum_strided<G>(dot[p * OW + j]);
+      if (wl < G) sh[wid][p * CW + wl * OW + j] = t;
+    }
+  __syncthreads();
+  if ((int)threadIdx.x < S) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += sh[w][threadIdx.x];
+    cs.partial[(int64_t)threadIdx.x * g.nblk + br.blk] = t;
+  }
+}
+
+// Slice-per-lane variant (spmm_rows.h) for S in {8, 16, 32, 64}: one wave per row.
+template <int S, typename V, typename PT>
+__global__ __launch_bounds__(kBlock) void k_bspmm_s(BatchGeom g, const int64_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ col, const V* __restrict__ val,
+                                                    const PT* __restrict__ X, double* __restrict__ Y, CgState cs) {
+  constexpr int VW = 16 / sizeof(PT);
+  constexpr int LE = S / VW;
+  const BRows br = brows(g);
+  if (!inst_open(cs, br.inst, S)) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int cq = lane % LE;
+  double dot[VW];
+#pragma unroll
+  for (int c = 0; c < VW; ++c) dot[c] = 0.0;
+  for (int64_t row = br.lo + wid; row < br.hi; row += kBlock / kWave) {
+    double acc[VW];
+    row_slices_product<S>(col, val, rp[row], rp[row + 1], lane, X, acc);
+    if (lane < LE) {
+      const int64_t o = row * S + cq * VW;
+#pragma unroll
+      for (int c = 0; c < VW; ++c) {
+        Y[o + c] = acc[c];
+        dot[c] += acc[c] * (double)X[o + c];
+      }
+    }
+  }
+  __shared__ double sh[kBlock / kWave][S];
+  if (lane < LE)
+#pragma unroll
+    for (int c = 0; c < VW; ++c) sh[wid][cq * VW + c] = dot[c];
+  __syncthreads();
+  if ((int)threadIdx.x < S) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += sh[w][threadIdx.x];
+    cs.partial[(int64_t)threadIdx.x * g.nblk + br.blk] = t;
+  }
+}
+
 // single right-hand side per instance: G lanes per row
 template <int G, typename V>
 __global__ __launch_bounds__(kBlock) void k_bspmv(BatchGeom g, const int64_t* __restrict__ rp,
@@ -508,8 +593,39 @@ static void bspmv_any(int G, const BatchGeom& g, const int64_t* rp, const int32_
   }
 }
 
-// `lanes`: lanes per row -- the SpMV lane group for S = 1, else lanes per row of the
-// block product (>= S). Both are chosen by the autotuner.
+template <typename V, typename PT>
+static void bspmm_slices(const BatchGeom& g, const int64_t* rp, const int32_t* col, const V* val, int S,
+                         const PT* P, double* Q, const CgState& cs, hipStream_t st) {
+  dim3 grid((unsigned)g.grid), block(kBlock);
+  switch (S) {
+    case 8: hipLaunchKernelGGL((k_bspmm_s<8, V, PT>), grid, block, 0, st, g, rp, col, val, P, Q, cs); break;
+    case 16: hipLaunchKernelGGL((k_bspmm_s<16, V, PT>), grid, block, 0, st, g, rp, col, val, P, Q, cs); break;
+    case 32: hipLaunchKernelGGL((k_bspmm_s<32, V, PT>), grid, block, 0, st, g, rp, col, val, P, Q, cs); break;
+    default: hipLaunchKernelGGL((k_bspmm_s<64, V, PT>), grid, block, 0, st, g, rp, col, val, P, Q, cs); break;
+  }
+}
+
+// Entry-parallel block product with G lanes per row; false if S has no instance.
+template <typename V, typename PT>
+static bool bspmm_entry(int G, const BatchGeom& g, const int64_t* rp, const int32_t* col, const V* val, int S,
+                        const PT* P, double* Q, const CgState& cs, hipStream_t st) {
+  dim3 grid((unsigned)g.grid), block(kBlock);
+#define GP2S_BSPMM_E(GG, SS)                                                                            \
+  if (G == GG && S == SS) {                                                                            \
+    hipLaunchKernelGGL((k_bspmm_e<GG, SS, V, PT>), grid, block, 0, st, g, rp, col, val, P, Q, cs);     \
+    return true;                                                                                       \
+  }
+  GP2S_BSPMM_E(4, 8) GP2S_BSPMM_E(8, 8)
+  GP2S_BSPMM_E(4, 16) GP2S_BSPMM_E(8, 16) GP2S_BSPMM_E(16, 16)
+  GP2S_BSPMM_E(4, 32) GP2S_BSPMM_E(8, 32) GP2S_BSPMM_E(16, 32)
+  GP2S_BSPMM_E(4, 64) GP2S_BSPMM_E(8, 64) GP2S_BSPMM_E(16, 64)
+#undef GP2S_BSPMM_E
+  return false;
+}
+
+// `lanes`: lanes per row -- the SpMV lane group for S = 1; for S > 1 the lanes per row
+// of the lane-per-column product (>= S), 1 for the slice-per-lane product, or -G for
+// the entry-parallel product with G lanes per row. Both are chosen by the autotuner.
 hipError_t launch_bcg_matvec(int prec, const BatchGeom& g, const int64_t* rp, const int32_t* col, const void* val,
                              int S, int lanes, const void* P, void* Q, bool f32vec, const CgState& cs,
                              hipStream_t st) {
@@ -520,6 +636,22 @@ hipError_t launch_bcg_matvec(int prec, const BatchGeom& g, const int64_t* rp, co
     else
       bspmv_any(lanes, g, rp, col, static_cast<const double*>(val), static_cast<const double*>(P),
                 static_cast<double*>(Q), cs, st);
+  } else if (lanes == 1 && (S == 8 || S == 16 || S == 32 || S == 64) && (f32vec || prec != GP2S_MIXED) &&
+             (reinterpret_cast<uintptr_t>(P) & 15) == 0) {
+    if (f32vec)
+      bspmm_slices(g, rp, col, static_cast<const float*>(val), S, static_cast<const float*>(P),
+                   static_cast<double*>(Q), cs, st);
+    else
+      bspmm_slices(g, rp, col, static_cast<const double*>(val), S, static_cast<const double*>(P),
+                   static_cast<double*>(Q), cs, st);
+  } else if (lanes < 0 && entry_product_ok(S, -lanes) && (f32vec || prec != GP2S_MIXED) &&
+             (reinterpret_cast<uintptr_t>(P) & 15) == 0) {
+    if (f32vec)
+      bspmm_entry(-lanes, g, rp, col, static_cast<const float*>(val), S, static_cast<const float*>(P),
+                  static_cast<double*>(Q), cs, st);
+    else
+      bspmm_entry(-lanes, g, rp, col, static_cast<const double*>(val), S, static_cast<const double*>(P),
+                  static_cast<double*>(Q), cs, st);
   } else if (f32vec) {
     bspmm_any(lanes, g, rp, col, static_cast<const float*>(val), S, static_cast<const float*>(P),
               static_cast<double*>(Q), cs, st);

@@ -593,7 +593,12 @@ gp2s_status gp2s_batch_plan(gp2s_ctx ctx, int32_t n_inst, const int64_t* n, cons
     }
     b->tune_ms[2] = bt;
     bt = 1e30f;
-    for (int L = S; L <= 64; L *= 2) {
+    std::vector<int> cand;
+    for (int L = S; L <= 64; L *= 2) cand.push_back(L);
+    if (S == 8 || S == 16 || S == 32 || S == 64) cand.push_back(1);
+    for (int G = 4; G <= 16; G *= 2)
+      if (entry_product_ok(S, G)) cand.push_back(-G);
+    for (int L : cand) {
       float ms = 0.f;
       st = time_matvec(b, S, L, sc2, &ms);
       if (st) return st;

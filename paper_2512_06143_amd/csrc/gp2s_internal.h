@@ -87,6 +87,11 @@ __device__ inline XcdRows xcd_rows(int64_t n, int unit, int units) {
 }
 __host__ inline int64_t round_up8(int64_t b) { return (b + 7) / 8 * 8; }
 
+// The entry-parallel block products exist for S in {8, 16, 32, 64} and G in {4, 8, 16}, G <= S.
+__host__ inline bool entry_product_ok(int S, int G) {
+  return (S == 8 || S == 16 || S == 32 || S == 64) && (G == 4 || G == 8 || G == 16) && G <= S;
+}
+
 // ---- batched instances ---------------------------------------------------------------
 // Many independent instances form one block-diagonal system. Rows (and columns) are
 // instance-major, bin-major inside an instance. Points are stored with three
@@ -161,11 +166,13 @@ hipError_t launch_assemble_fill(const AssembleArgs& a, int prec, const int64_t* 
 hipError_t launch_spmv(int prec, const int64_t* rp, const int32_t* col, const void* val,
                        int64_t n, double mean_row, const double* x, double* y, hipStream_t st);
 hipError_t launch_spmm(int prec, const int64_t* rp, const int32_t* col, const void* val,
-                       int64_t n, int S, const double* X, double* Y, hipStream_t st);
+                       int64_t n, int S, double mean_row, int variant, const double* X, double* Y, hipStream_t st);
 // CG product step: Q = K P plus p^T q per column, then alpha = rz / p^T q.
 // P is float32 when f32vec (block solves of the mixed path), else float64; Q is float64.
+// `variant` selects the block product for S > 1: 0 one lane per column, G > 0 the
+// entry-parallel product with G lanes per row, -1 a choice from S and the mean row length.
 hipError_t launch_cg_matvec(int prec, const int64_t* rp, const int32_t* col, const void* val,
-                            int64_t n, int S, double mean_row, const void* P, void* Q, bool f32vec,
+                            int64_t n, int S, double mean_row, int variant, const void* P, void* Q, bool f32vec,
                             const CgState& cs, hipStream_t st);
 
 // pcg.hip

@@ -38,6 +38,11 @@ struct gp2s_matrix_s {
   gp2s_ctx ctx = nullptr;
   int64_t n = 0, nnz = 0;
   int prec = GP2S_FP64;
+  // block-product variant per column count, measured on first use (-2: not yet)
+  int spmm_variant[gp2s::kMaxProbes + 1];
+  gp2s_matrix_s() {
+    for (int& v : spmm_variant) v = -2;
+  }
   bool assembled = false;
   // hyperparameters (assembled handles)
   int dim = 0, P = 0;

@@ -10,6 +10,7 @@
 // fixed per-workgroup partial sums; a finalize kernel (pcg.hip) reduces them in
 // workgroup order, so results are bitwise reproducible.
 #include "gp2s_internal.h"
+#include "spmm_rows.h"
 
 namespace gp2s {
 
@@ -172,30 +173,182 @@ __global__ __launch_bounds__(kBlock) void k_spmm(const int64_t* __restrict__ rp,
   }
 }
 
-template <typename V, typename PT, typename QT, bool DOT>
+// Entry-parallel block product (spmm_rows.h) for S in {8, 16, 32, 64}: G lanes per row,
+// CW = min(S, 16) columns per pass over the row. p^T q partials per workgroup and
+// column as in k_spmm.
+template <int G, int S, typename V, typename PT, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_spmm_e(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                   const V* __restrict__ val, int64_t n, const PT* __restrict__ X,
+                                                   double* __restrict__ Y, CgState cs) {
+  constexpr int CW = S < 16 ? S : 16;
+  constexpr int NP = S / CW;
+  constexpr int OW = CW / G;
+  const int lane = threadIdx.x % G;
+  const XcdRows rr = xcd_rows(n, threadIdx.x / G, kBlock / G);
+  double dot[NP * OW];
+#pragma unroll
+  for (int j = 0; j < NP * OW; ++j) dot[j] = 0.0;
+  for (int64_t row = rr.first; row < rr.end; row += rr.step) {
+    const int64_t s = rp[row], e = rp[row + 1];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      double q[OW];
+      row_cols_product<G, CW>(col, val, s, e, lane, X, S, p * CW, q);
+      const int64_t o = row * S + p * CW + lane * OW;
+#pragma unroll
+      for (int j = 0; j < OW; ++j) {
+        Y[o + j] = q[j];
+        if (DOT) dot[p * OW + j] += q[j] * (double)X[o + j];
+      }
+    }
+  }
+  if (!DOT) return;
+  __shared__ double sh[kBlock / kWave][S];
+  const int wid = threadIdx.x / kWave, wl = threadIdx.x % kWave;
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int j = 0; j < OW; ++j) {
+      const double t = wave_sum_strided<G>(dot[p * OW + j]);
+      if (wl < G) sh[wid][p * CW + wl * OW + j] = t;
+    }
+  __syncthreads();
+  if ((int)threadIdx.x < S) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += sh[w][threadIdx.x];
+    cs.partial[blockIdx.x * (int64_t)S + threadIdx.x] = t;
+  }
+}
+
+// Slice-per-lane block product (spmm_rows.h) for S in {8, 16, 32, 64}: one wave per
+// row, 16-byte column slices per lane. p^T q partials per workgroup and column as in k_spmm.
+template <int S, typename V, typename PT, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_spmm_s(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                   const V* __restrict__ val, int64_t n, const PT* __restrict__ X,
+                                                   double* __restrict__ Y, CgState cs) {
+  constexpr int VW = 16 / sizeof(PT);
+  constexpr int LE = S / VW;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int cq = lane % LE;
+  const XcdRows rr = xcd_rows(n, wid, kBlock / kWave);
+  double dot[VW];
+#pragma unroll
+  for (int c = 0; c < VW; ++c) dot[c] = 0.0;
+  for (int64_t row = rr.first; row < rr.end; row += rr.step) {
+    double acc[VW];
+    row_slices_product<S>(col, val, rp[row], rp[row + 1], lane, X, acc);
+    if (lane < LE) {
+      const int64_t o = row * S + cq * VW;
+#pragma unroll
+      for (int c = 0; c < VW; ++c) {
+        Y[o + c] = acc[c];
+        if (DOT) dot[c] += acc[c] * (double)X[o + c];
+      }
+    }
+  }
+  if (!DOT) return;
+  __shared__ double sh[kBlock / kWave][S];
+  if (lane < LE)
+#pragma unroll
+    for (int c = 0; c < VW; ++c) sh[wid][cq * VW + c] = dot[c];
+  __syncthreads();
+  if ((int)threadIdx.x < S) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += sh[w][threadIdx.x];
+    cs.partial[blockIdx.x * (int64_t)S + threadIdx.x] = t;
+  }
+}
+
+// Lanes per row of the entry-parallel product: about a sixth of the mean row length,
+// a power of two in [4, min(16, S)].
+static int pick_entry_group(double mean_row, int S) {
+  int g = 4;
+  const int gmax = S < 16 ? S : 16;
+  while (g < gmax && 2 * g <= mean_row / 6.0 + 1e-9) g *= 2;
+  return g;
+}
+
+// Launches k_spmm_e with G lanes per row when (S, G) has an instance and X is 16-byte
+// aligned; returns false otherwise.
+template <typename V, typename PT, bool DOT>
+static bool spmm_entry(int G, const int64_t* rp, const int32_t* col, const V* val, int64_t n, int S, const PT* X,
+                       double* Y, const CgState& cs, hipStream_t st, int64_t blocks) {
+  if (!entry_product_ok(S, G) || (reinterpret_cast<uintptr_t>(X) & 15) != 0) return false;
+  dim3 grid((unsigned)blocks), block(kBlock);
+#define GP2S_SPMM_E(GG, SS)                                                                            \
+  if (G == GG && S == SS) {                                                                           \
+    hipLaunchKernelGGL((k_spmm_e<GG, SS, V, PT, DOT>), grid, block, 0, st, rp, col, val, n, X, Y, cs); \
+    return true;                                                                                      \
+  }
+  GP2S_SPMM_E(4, 8) GP2S_SPMM_E(8, 8)
+  GP2S_SPMM_E(4, 16) GP2S_SPMM_E(8, 16) GP2S_SPMM_E(16, 16)
+  GP2S_SPMM_E(4, 32) GP2S_SPMM_E(8, 32) GP2S_SPMM_E(16, 32)
+  GP2S_SPMM_E(4, 64) GP2S_SPMM_E(8, 64) GP2S_SPMM_E(16, 64)
+#undef GP2S_SPMM_E
+  return false;
+}
+
+// Launches k_spmm_s when S has an instance and X is 16-byte aligned.
+template <typename V, typename PT, bool DOT>
+static bool spmm_slices(const int64_t* rp, const int32_t* col, const V* val, int64_t n, int S, const PT* X, double* Y,
+                        const CgState& cs, hipStream_t st, int64_t blocks) {
+  if ((S != 8 && S != 16 && S != 32 && S != 64) || (reinterpret_cast<uintptr_t>(X) & 15) != 0) return false;
+  dim3 grid((unsigned)blocks), block(kBlock);
+  switch (S) {
+    case 8: hipLaunchKernelGGL((k_spmm_s<8, V, PT, DOT>), grid, block, 0, st, rp, col, val, n, X, Y, cs); break;
+    case 16: hipLaunchKernelGGL((k_spmm_s<16, V, PT, DOT>), grid, block, 0, st, rp, col, val, n, X, Y, cs); break;
+    case 32: hipLaunchKernelGGL((k_spmm_s<32, V, PT, DOT>), grid, block, 0, st, rp, col, val, n, X, Y, cs); break;
+    default: hipLaunchKernelGGL((k_spmm_s<64, V, PT, DOT>), grid, block, 0, st, rp, col, val, n, X, Y, cs); break;
+  }
+  return true;
+}
+
+// variant: 0 lane per column, 1 slice per lane, G > 1 entry-parallel with G lanes per
+// row, -1 heuristic (entry-parallel up to 32 columns, else one lane per column).
+template <typename V, typename PT, bool DOT>
 static hipError_t spmm_dispatch(const int64_t* rp, const int32_t* col, const V* val, int64_t n, int S,
-                                const PT* X, QT* Y, const CgState& cs, hipStream_t st,
-                                int* nblocks = nullptr) {
-  int64_t blocks = (n + (kBlock / kWave) - 1) / (kBlock / kWave);
+                                double mean_row, int variant, const PT* X, double* Y, const CgState& cs,
+                                hipStream_t st, int* nblocks = nullptr) {
   const int64_t cap = DOT ? kReduceBlocks : (1 << 20);
-  if (blocks > cap) blocks = cap;
-  blocks = round_up8(blocks < 1 ? 1 : blocks);
+  auto grid_for = [&](int64_t rows_per_block) {
+    int64_t b = (n + rows_per_block - 1) / rows_per_block;
+    if (b > cap) b = cap;
+    return round_up8(b < 1 ? 1 : b);
+  };
+  const int G = variant >= 0 ? variant : (S <= 32 ? pick_entry_group(mean_row, S) : 0);
+  if (G == 1) {
+    const int64_t sb = grid_for(kBlock / kWave);
+    if (spmm_slices<V, PT, DOT>(rp, col, val, n, S, X, Y, cs, st, sb)) {
+      if (nblocks) *nblocks = (int)sb;
+      return hipGetLastError();
+    }
+  } else if (G > 1) {
+    const int64_t eb = grid_for(kBlock / G);
+    if (spmm_entry<V, PT, DOT>(G, rp, col, val, n, S, X, Y, cs, st, eb)) {
+      if (nblocks) *nblocks = (int)eb;
+      return hipGetLastError();
+    }
+  }
+  const int64_t blocks = grid_for(kBlock / kWave);
   if (nblocks) *nblocks = (int)blocks;
-  hipLaunchKernelGGL((k_spmm<V, PT, QT, DOT>), dim3((unsigned)blocks), dim3(kBlock), 0, st, rp, col, val, n, S,
+  hipLaunchKernelGGL((k_spmm<V, PT, double, DOT>), dim3((unsigned)blocks), dim3(kBlock), 0, st, rp, col, val, n, S,
                      X, Y, cs);
   return hipGetLastError();
 }
 
 hipError_t launch_spmm(int prec, const int64_t* rp, const int32_t* col, const void* val, int64_t n,
-                       int S, const double* X, double* Y, hipStream_t st) {
+                       int S, double mean_row, int variant, const double* X, double* Y, hipStream_t st) {
   CgState cs{};
   if (prec == GP2S_MIXED)
-    return spmm_dispatch<float, double, double, false>(rp, col, static_cast<const float*>(val), n, S, X, Y, cs, st);
-  return spmm_dispatch<double, double, double, false>(rp, col, static_cast<const double*>(val), n, S, X, Y, cs, st);
+    return spmm_dispatch<float, double, false>(rp, col, static_cast<const float*>(val), n, S, mean_row, variant, X,
+                                               Y, cs, st);
+  return spmm_dispatch<double, double, false>(rp, col, static_cast<const double*>(val), n, S, mean_row, variant, X,
+                                              Y, cs, st);
 }
 
 hipError_t launch_cg_matvec(int prec, const int64_t* rp, const int32_t* col, const void* val,
-                            int64_t n, int S, double mean_row, const void* P, void* Q, bool f32vec,
+                            int64_t n, int S, double mean_row, int variant, const void* P, void* Q, bool f32vec,
                             const CgState& cs, hipStream_t st) {
   int nb = 0;
   hipError_t e;
@@ -209,17 +362,14 @@ hipError_t launch_cg_matvec(int prec, const int64_t* rp, const int32_t* col, con
                                       static_cast<const double*>(P), static_cast<double*>(Q), cs, st, &nb);
   } else if (prec == GP2S_MIXED) {
     if (f32vec)
-      e = spmm_dispatch<float, float, double, true>(rp, col, static_cast<const float*>(val), n, S,
-                                                    static_cast<const float*>(P), static_cast<double*>(Q), cs, st,
-                                                    &nb);
+      e = spmm_dispatch<float, float, true>(rp, col, static_cast<const float*>(val), n, S, mean_row, variant,
+                                            static_cast<const float*>(P), static_cast<double*>(Q), cs, st, &nb);
     else
-      e = spmm_dispatch<float, double, double, true>(rp, col, static_cast<const float*>(val), n, S,
-                                                     static_cast<const double*>(P), static_cast<double*>(Q), cs, st,
-                                                     &nb);
+      e = spmm_dispatch<float, double, true>(rp, col, static_cast<const float*>(val), n, S, mean_row, variant,
+                                             static_cast<const double*>(P), static_cast<double*>(Q), cs, st, &nb);
   } else {
-    e = spmm_dispatch<double, double, double, true>(rp, col, static_cast<const double*>(val), n, S,
-                                                    static_cast<const double*>(P), static_cast<double*>(Q), cs, st,
-                                                    &nb);
+    e = spmm_dispatch<double, double, true>(rp, col, static_cast<const double*>(val), n, S, mean_row, variant,
+                                            static_cast<const double*>(P), static_cast<double*>(Q), cs, st, &nb);
   }
   if (e != hipSuccess) return e;
   return launch_cg_alpha(cs, nb, S, st);

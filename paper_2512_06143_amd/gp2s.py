@@ -84,6 +84,7 @@ _SIGS = {
     "gp2s_matrix_export": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "gp2s_matrix_import": (_i32, [_vp, _i64, _i64, _vp, _vp, _vp, _i32, ctypes.POINTER(_vp)]),
     "gp2s_matrix_free": (_i32, [_vp]),
+    "gp2s_matrix_set_block_product": (_i32, [_vp, _i32, _i32]),
     "gp2s_spmv": (_i32, [_vp, _vp, _i32, _vp, _vp]),
     "gp2s_solve": (_i32, [_vp, _vp, _vp, _vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(Report)]),
     "gp2s_lml": (_i32, [_vp, _vp, _vp, ctypes.POINTER(SolveOpts), _vp, ctypes.POINTER(Report)]),
@@ -235,6 +236,12 @@ class Matrix:
         n, nnz, pr = _i64(), _i64(), _i32()
         lib.gp2s_matrix_info(handle, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(pr))
         self.n, self.nnz = n.value, nnz.value
+
+    def set_block_product(self, nrhs: int, variant: int):
+        """Pin the block-product kernel for `nrhs` columns (see include/gp2s.h); -1 retunes."""
+        st = lib.gp2s_matrix_set_block_product(self.handle, int(nrhs), int(variant))
+        if st != GP2S_OK:
+            raise GP2SError(st, f"block-product variant {variant} does not apply to {nrhs} columns")
 
     def free(self):
         if self.handle:

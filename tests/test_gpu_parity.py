@@ -66,7 +66,7 @@ def test_assembly_pattern_and_values(case, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("nrhs", [1, 7, 64])
+@pytest.mark.parametrize("nrhs", [1, 7, 8, 16, 32, 64])
 def test_spmv_matches_exported_matrix(case, precision, nrhs):
     G = _G()
     name, prob, Kref, gamma, ex_pts = case
@@ -131,3 +131,52 @@ def test_lml_and_gradient_same_probe(case, precision):
     for k in range(len(gref)):
         if gref[k] == 0.0:
             assert grad[k] == 0.0
+
+
+BLOCK_VARIANTS = [0, 1, 4, 8, 16]  # lane per column, column slices, 4/8/16 lanes per row
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("nrhs", [8, 16, 64])
+def test_block_product_variants(case, precision, nrhs):
+    """Every block-product kernel gives the stored matrix's product."""
+    G = _G()
+    name, prob, Kref, gamma, ex_pts = case
+    m = G.gp2s_assemble(prob.x, params_of(prob), precision)
+    Kg, _ = exported_user_csr(m)
+    X = np.random.default_rng(11).standard_normal((prob.n, nrhs))
+    ref = Kg @ X
+    for v in BLOCK_VARIANTS:
+        if v > nrhs:
+            with pytest.raises(G.GP2SError):
+                m.set_block_product(nrhs, v)
+            continue
+        m.set_block_product(nrhs, v)
+        Y = G.gp2s_spmv(m, X).cpu().numpy()
+        np.testing.assert_allclose(Y, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max(), err_msg=f"variant {v}")
+    with pytest.raises(G.GP2SError):
+        m.set_block_product(7, 1)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_probe_block_variants_same_probe(case, precision):
+    """The CG probe block (products plus per-column p^T q partials) with every kernel
+    reaches the same-probe log-determinant and gradient of the oracle."""
+    G = _G()
+    name, prob, Kref, gamma, ex_pts = case
+    S = 16
+    m = G.gp2s_assemble(prob.x, params_of(prob), precision)
+    Kd = exported_user_csr(m)[0].toarray()
+    opts = G.default_opts(n_probes=S, seed=3, tol=1e-10, probe_tol=1e-10, max_iter=40000)
+    Z = oracle.rademacher_probes(3, S, prob.n)
+    gam_ref, _ = oracle.logdet_same_probe(Kd, Z)
+    gref, gparts = oracle.grad_same_probe(prob.x, prob.y, Z, prob.radius, prob.bump_width, prob.centers,
+                                          prob.weights, prob.noise_var, K=Kd)
+    scale = np.maximum(np.abs(gref), 1e-6 * (np.abs(gparts["fit"]) + 0.5 * np.abs(gparts["tau"])))
+    for v in BLOCK_VARIANTS:
+        m.set_block_product(S, v)
+        rep, grad, _ = G.gp2s_lml_grad(m, prob.y, opts)
+        rel = abs(rep.logdet - gam_ref) / abs(gam_ref)
+        print(f"[{name}/{precision}] variant {v}: logdet rel {rel:.2e} probe iters {rep.probe_iters}", flush=True)
+        assert rel <= 1e-8
+        assert np.all(np.abs(grad - gref) <= 1e-4 * scale)
