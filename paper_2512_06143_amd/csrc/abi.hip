@@ -17,10 +17,51 @@ struct CgRun {
   bool converged = false;
 };
 
+// Jacobi-PCG for K X = B over S columns (internal order) on stream `st`, driven one
+// iteration at a time so that two solves can be interleaved on two streams. The host
+// polls the per-column done flags without stalling the stream: every check_every
+// iterations it queues an asynchronous copy of the flags into a pinned slot plus an
+// event, and evaluates the copy queued one check earlier (whose event has long
+// completed). Converged columns make the extra iterations no-ops (alpha = 0, p kept).
+struct Cg {
+  gp2s_ctx ctx = nullptr;
+  gp2s_matrix m = nullptr;
+  int S = 1;
+  double* X = nullptr;
+  int max_iter = 0, check_every = 16;
+  const char* label = "";
+  hipStream_t st = nullptr;
+  int slot0 = 0;  // first of this solve's two pinned poll slots
+  // state
+  CgState cs{};
+  bool f32vec = false;
+  int variant = 0;
+  double* R = nullptr;
+  void* P = nullptr;
+  void* Q = nullptr;
+  int32_t* si = nullptr;
+  int it = 0;          // iterations queued
+  int polled_it = -1;  // iteration count of the poll in flight (-1: none)
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int nq = 0;  // polls queued
+  bool open = true;
+  int32_t host_iters[kMaxProbes] = {};
+  int32_t total_iters = 0;
+  bool converged = false;
+
+  int32_t* slot(int k) const {
+    return reinterpret_cast<int32_t*>(static_cast<char*>(ctx->pinned) + kReadbackBytes + (slot0 + k) * kPollSlot);
+  }
+  ~Cg() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
 // Chooses the block product for S columns of this matrix by timing each variant on the
 // first CG product (the product and its alpha are recomputed by the first iteration).
 gp2s_status tune_block_product(gp2s_ctx ctx, gp2s_matrix m, int S, const void* P, void* Q, bool f32vec,
-                               const CgState& cs) {
+                               const CgState& cs, hipStream_t st) {
   std::vector<int> cand{0};
   if (S == 8 || S == 16 || S == 32 || S == 64) cand.push_back(1);
   for (int G = 4; G <= 16; G *= 2)
@@ -40,13 +81,11 @@ gp2s_status tune_block_product(gp2s_ctx ctx, gp2s_matrix m, int S, const void* P
   int pick = 0;
   hipError_t err = hipSuccess;
   for (int v : cand) {
-    err = launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, m->n, S, mean_row, v, P, Q, f32vec, cs,
-                           ctx->stream);
-    if (err == hipSuccess) err = hipEventRecord(e0, ctx->stream);
+    err = launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, m->n, S, mean_row, v, P, Q, f32vec, cs, st);
+    if (err == hipSuccess) err = hipEventRecord(e0, st);
     for (int r = 0; r < 3 && err == hipSuccess; ++r)
-      err = launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, m->n, S, mean_row, v, P, Q, f32vec, cs,
-                             ctx->stream);
-    if (err == hipSuccess) err = hipEventRecord(e1, ctx->stream);
+      err = launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, m->n, S, mean_row, v, P, Q, f32vec, cs, st);
+    if (err == hipSuccess) err = hipEventRecord(e1, st);
     if (err == hipSuccess) err = hipEventSynchronize(e1);
     float ms = 0.f;
     if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
@@ -63,22 +102,24 @@ gp2s_status tune_block_product(gp2s_ctx ctx, gp2s_matrix m, int S, const void* P
   return GP2S_OK;
 }
 
-// Jacobi-PCG for K X = B over S columns (internal order). X receives the solution.
-gp2s_status run_cg(gp2s_ctx ctx, gp2s_matrix m, int S, const double* B, double* X, double tol, int max_iter,
-                   int check_every, bool keep_hist, Scratch& sc, CgRun& out, const char* label) {
+// Allocates the workspace, initialises the state and reads the initial flags.
+gp2s_status cg_begin(Cg& c, const double* B, double tol, bool keep_hist, Scratch& sc) {
+  gp2s_ctx ctx = c.ctx;
+  gp2s_matrix m = c.m;
+  const int S = c.S;
   const int64_t n = m->n;
   const size_t nS = (size_t)n * S;
   // Probe blocks of the mixed path keep search directions in float32 (products, x,
   // r, dot products and all coefficients stay float64).
-  const bool f32vec = m->prec == GP2S_MIXED && S > 1;
-  const size_t vb = f32vec ? sizeof(float) : sizeof(double);
-  double* R = sc.get<double>(nS);
-  void* P = sc.get<uint8_t>(nS * vb);
-  void* Q = sc.get<double>(nS);
+  c.f32vec = m->prec == GP2S_MIXED && S > 1;
+  const size_t vb = c.f32vec ? sizeof(float) : sizeof(double);
+  c.R = sc.get<double>(nS);
+  c.P = sc.get<uint8_t>(nS * vb);
+  c.Q = sc.get<double>(nS);
   double* sd = sc.get<double>(6 * S + (size_t)kReduceBlocks * S * 2);
-  int32_t* si = sc.get<int32_t>(2 * S + 4);
+  c.si = sc.get<int32_t>(2 * S + 4);
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "CG workspace allocation failed");
-  CgState& cs = out.cs;
+  CgState& cs = c.cs;
   cs.rz = sd;
   cs.bb = sd + S;
   cs.tol2 = sd + 2 * S;
@@ -86,77 +127,174 @@ gp2s_status run_cg(gp2s_ctx ctx, gp2s_matrix m, int S, const double* B, double* 
   cs.beta = sd + 4 * S;
   cs.rr = sd + 5 * S;
   cs.partial = sd + 6 * S;
-  cs.done = si;
-  cs.flags = si + S;
-  cs.iters = si + S + 4;
+  cs.done = c.si;
+  cs.flags = c.si + S;
+  cs.iters = c.si + S + 4;
   cs.hist_a = cs.hist_b = nullptr;
   cs.max_hist = 0;
   if (keep_hist) {
-    cs.hist_a = sc.get<double>((size_t)max_iter * S);
-    cs.hist_b = sc.get<double>((size_t)max_iter * S);
+    cs.hist_a = sc.get<double>((size_t)c.max_iter * S);
+    cs.hist_b = sc.get<double>((size_t)c.max_iter * S);
     if (sc.oom) return fail(ctx, GP2S_E_OOM, "CG history allocation failed");
-    cs.max_hist = max_iter;
+    cs.max_hist = c.max_iter;
   }
-  HIPCHK(hipMemsetAsync(si, 0, (2 * S + 4) * sizeof(int32_t), ctx->stream));
-  HIPCHK(launch_cg_init(n, S, B, m->dinv, X, R, P, f32vec, cs, tol, ctx->stream));
-  // done[S] then flags[4] are contiguous in si: one read-back per poll.
-  std::vector<int32_t> poll(S + 4);
-  auto read_poll = [&]() -> gp2s_status { return readback(ctx, si, (S + 4) * sizeof(int32_t), poll.data()); };
-  auto n_open = [&]() {
-    int o = 0;
-    for (int s = 0; s < S; ++s) o += poll[s] == 0;
-    return o;
-  };
-  gp2s_status st = read_poll();
-  if (st) return st;
-  if (poll[S + 2]) return fail(ctx, GP2S_E_NONFINITE, "non-finite right-hand side (%s)", label);
+  HIPCHK(hipEventCreateWithFlags(&c.ev[0], hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&c.ev[1], hipEventDisableTiming));
+  HIPCHK(hipMemsetAsync(c.si, 0, (2 * S + 4) * sizeof(int32_t), c.st));
+  HIPCHK(launch_cg_init(n, S, B, m->dinv, c.X, c.R, c.P, c.f32vec, cs, tol, c.st));
+  // done[S] then flags[4] are contiguous in si
+  int32_t* pin = c.slot(0);
+  HIPCHK(hipMemcpyAsync(pin, c.si, (S + 4) * sizeof(int32_t), hipMemcpyDeviceToHost, c.st));
+  HIPCHK(hipStreamSynchronize(c.st));
+  if (pin[S + 2]) return fail(ctx, GP2S_E_NONFINITE, "non-finite right-hand side (%s)", c.label);
+  int open = 0;
+  for (int s = 0; s < S; ++s) open += pin[s] == 0;
+  c.open = open > 0;
   if (S > 1 && m->spmm_variant[S] == -2) {
-    st = tune_block_product(ctx, m, S, P, Q, f32vec, cs);
+    gp2s_status st = tune_block_product(ctx, m, S, c.P, c.Q, c.f32vec, cs, c.st);
     if (st) return st;
   }
-  const int variant = S > 1 ? m->spmm_variant[S] : 0;
-  int it = 0;
-  bool open = n_open() > 0;
-  while (open && it < max_iter) {
-    TIMED(S == 1 ? GP2S_T_CG_MATVEC1 : GP2S_T_CG_MATVEC_BLOCK,
-          launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, n, S, (double)m->nnz / (double)n, variant, P, Q,
-                           f32vec, cs, ctx->stream));
-    TIMED(S == 1 ? GP2S_T_CG_UPDATE1 : GP2S_T_CG_UPDATE_BLOCK,
-          launch_cg_update(n, S, X, R, P, Q, f32vec, m->dinv, cs, it, ctx->stream));
-    TIMED(S == 1 ? GP2S_T_CG_PUPDATE1 : GP2S_T_CG_PUPDATE_BLOCK,
-          launch_cg_pupdate(n, S, P, R, m->dinv, f32vec, cs, ctx->stream));
-    ++it;
-    if (it % check_every == 0 || it == max_iter) {
-      st = read_poll();
+  c.variant = S > 1 ? m->spmm_variant[S] : 0;
+  return GP2S_OK;
+}
+
+// Queues one iteration.
+gp2s_status cg_step(Cg& c) {
+  gp2s_ctx ctx = c.ctx;
+  gp2s_matrix m = c.m;
+  const int64_t n = m->n;
+  const int S = c.S;
+  TIMED_ON(S == 1 ? GP2S_T_CG_MATVEC1 : GP2S_T_CG_MATVEC_BLOCK, c.st,
+           launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, n, S, (double)m->nnz / (double)n, c.variant, c.P,
+                            c.Q, c.f32vec, c.cs, c.st));
+  TIMED_ON(S == 1 ? GP2S_T_CG_UPDATE1 : GP2S_T_CG_UPDATE_BLOCK, c.st,
+           launch_cg_update(n, S, c.X, c.R, c.P, c.Q, c.f32vec, m->dinv, c.cs, c.it, c.st));
+  TIMED_ON(S == 1 ? GP2S_T_CG_PUPDATE1 : GP2S_T_CG_PUPDATE_BLOCK, c.st,
+           launch_cg_pupdate(n, S, c.P, c.R, m->dinv, c.f32vec, c.cs, c.st));
+  ++c.it;
+  return GP2S_OK;
+}
+
+// Evaluates a completed poll copy (flags of iteration `at`).
+gp2s_status cg_eval(Cg& c, const int32_t* f, int at) {
+  gp2s_ctx ctx = c.ctx;
+  const int S = c.S;
+  if (f[S + 0]) {
+    int32_t its[kMaxProbes];
+    gp2s_status st = readback_on(ctx, c.st, c.cs.iters, S * sizeof(int32_t), its);
+    const int col = f[S + 3];
+    return fail(ctx, GP2S_E_NOT_SPD,
+                "CG breakdown in the %s, column %d after %d iterations: p^T K p <= 0 (matrix not positive "
+                "definite in working precision)", c.label, col, st ? -1 : its[col]);
+  }
+  if (f[S + 2]) return fail(ctx, GP2S_E_NONFINITE, "non-finite values during CG (%s)", c.label);
+  int open = 0;
+  for (int s = 0; s < S; ++s) open += f[s] == 0;
+  c.open = open > 0;
+  if (ctx->progress) {
+    // rr[S] and bb[S] follow the flags in the slot (queued with them)
+    const double* rr = reinterpret_cast<const double*>(f + kMaxProbes + 4);
+    const double* bb = rr + kMaxProbes;
+    double worst = 0.0;
+    for (int s = 0; s < S; ++s)
+      if (!f[s] && bb[s] > 0) worst = std::max(worst, std::sqrt(rr[s] / bb[s]));
+    ctx->progress(c.label, at, open, worst, ctx->progress_user);
+  }
+  return GP2S_OK;
+}
+
+// At a check point: evaluate the previous poll (if any), then queue a new one.
+gp2s_status cg_check(Cg& c) {
+  gp2s_ctx ctx = c.ctx;
+  const int S = c.S;
+  if (c.nq > 0) {
+    const int k = (c.nq - 1) & 1;
+    HIPCHK(hipEventSynchronize(c.ev[k]));
+    gp2s_status st = cg_eval(c, c.slot(k), c.polled_it);
+    if (st) return st;
+    if (!c.open) return GP2S_OK;
+  }
+  const int k = c.nq & 1;
+  int32_t* f = c.slot(k);
+  HIPCHK(hipMemcpyAsync(f, c.si, (S + 4) * sizeof(int32_t), hipMemcpyDeviceToHost, c.st));
+  if (ctx->progress) {
+    double* rr = reinterpret_cast<double*>(f + kMaxProbes + 4);
+    HIPCHK(hipMemcpyAsync(rr, c.cs.rr, S * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    HIPCHK(hipMemcpyAsync(rr + kMaxProbes, c.cs.bb, S * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  }
+  HIPCHK(hipEventRecord(c.ev[k], c.st));
+  c.polled_it = c.it;
+  ++c.nq;
+  return GP2S_OK;
+}
+
+bool cg_active(const Cg& c) { return c.open && c.it < c.max_iter; }
+
+// Final synchronous poll and iteration counts.
+gp2s_status cg_end(Cg& c) {
+  gp2s_ctx ctx = c.ctx;
+  const int S = c.S;
+  if (c.it > 0) {
+    int32_t f[kMaxProbes + 4];
+    gp2s_status st = readback_on(ctx, c.st, c.si, (S + 4) * sizeof(int32_t), f);
+    if (st) return st;
+    gp2s_progress_fn keep = ctx->progress;  // no residuals in this copy
+    ctx->progress = nullptr;
+    st = cg_eval(c, f, c.it);
+    ctx->progress = keep;
+    if (st) return st;
+  }
+  gp2s_status st = readback_on(ctx, c.st, c.cs.iters, S * sizeof(int32_t), c.host_iters);
+  if (st) return st;
+  c.total_iters = 0;
+  for (int s = 0; s < S; ++s) c.total_iters = std::max(c.total_iters, c.host_iters[s]);
+  c.converged = !c.open;
+  return GP2S_OK;
+}
+
+// Runs one or two solves to completion, interleaving their iterations.
+gp2s_status cg_drive(Cg* a, Cg* b) {
+  for (;;) {
+    const bool ra = a && cg_active(*a), rb = b && cg_active(*b);
+    if (!ra && !rb) break;
+    for (Cg* c : {a, b}) {
+      if (!c || !cg_active(*c)) continue;
+      gp2s_status st = cg_step(*c);
       if (st) return st;
-      if (poll[S + 0]) {
-        int32_t its[kMaxProbes];
-        st = readback(ctx, cs.iters, S * sizeof(int32_t), its);
-        const int col = poll[S + 3];
-        return fail(ctx, GP2S_E_NOT_SPD,
-                    "CG breakdown in the %s, column %d after %d iterations: p^T K p <= 0 (matrix not positive "
-                    "definite in working precision)", label, col, st ? -1 : its[col]);
-      }
-      if (poll[S + 2]) return fail(ctx, GP2S_E_NONFINITE, "non-finite values during CG (%s)", label);
-      open = n_open() > 0;
-      if (ctx->progress) {
-        double rr[kMaxProbes], bb[kMaxProbes];
-        st = readback(ctx, cs.rr, S * sizeof(double), rr);
+      if (c->it % c->check_every == 0) {
+        st = cg_check(*c);
         if (st) return st;
-        st = readback(ctx, cs.bb, S * sizeof(double), bb);
-        if (st) return st;
-        double worst = 0.0;
-        for (int s = 0; s < S; ++s)
-          if (!poll[s] && bb[s] > 0) worst = std::max(worst, std::sqrt(rr[s] / bb[s]));
-        ctx->progress(label, it, n_open(), worst, ctx->progress_user);
       }
     }
   }
-  st = readback(ctx, cs.iters, S * sizeof(int32_t), out.host_iters);
+  for (Cg* c : {a, b}) {
+    if (!c) continue;
+    gp2s_status st = cg_end(*c);
+    if (st) return st;
+  }
+  return GP2S_OK;
+}
+
+gp2s_status run_cg(gp2s_ctx ctx, gp2s_matrix m, int S, const double* B, double* X, double tol, int max_iter,
+                   int check_every, bool keep_hist, Scratch& sc, CgRun& out, const char* label) {
+  Cg c;
+  c.ctx = ctx;
+  c.m = m;
+  c.S = S;
+  c.X = X;
+  c.max_iter = max_iter;
+  c.check_every = check_every;
+  c.label = label;
+  c.st = ctx->stream;
+  c.slot0 = 0;
+  gp2s_status st = cg_begin(c, B, tol, keep_hist, sc);
   if (st) return st;
-  out.total_iters = 0;
-  for (int s = 0; s < S; ++s) out.total_iters = std::max(out.total_iters, out.host_iters[s]);
-  out.converged = !open;
+  st = cg_drive(&c, nullptr);
+  if (st) return st;
+  out.cs = c.cs;
+  std::memcpy(out.host_iters, c.host_iters, sizeof(c.host_iters));
+  out.total_iters = c.total_iters;
+  out.converged = c.converged;
   return GP2S_OK;
 }
 
@@ -167,9 +305,11 @@ gp2s_status dot_host(gp2s_ctx ctx, int64_t n, const double* a, const double* b, 
   return readback(ctx, buf, sizeof(double), out);
 }
 
-// Solve K a = y (internal order) with restarts from the recomputed residual.
+// Solve K a = y (internal order) with restarts from the recomputed residual. `side`,
+// if given, is a solve begun on the second stream; its iterations are interleaved with
+// those of the first CG run of y and it is complete on return.
 gp2s_status solve_internal(gp2s_ctx ctx, gp2s_matrix m, const double* y, double* a, const gp2s_solve_opts* o,
-                           Scratch& sc, gp2s_report* rep, bool* converged) {
+                           Scratch& sc, gp2s_report* rep, bool* converged, Cg* side = nullptr) {
   const int64_t n = m->n;
   double* red = sc.get<double>(1 + kReduceBlocks);
   uint32_t* tk = sc.get<uint32_t>(1);
@@ -191,11 +331,26 @@ gp2s_status solve_internal(gp2s_ctx ctx, gp2s_matrix m, const double* y, double*
   if (bb == 0.0) {
     HIPCHK(hipMemsetAsync(a, 0, n * sizeof(double), ctx->stream));
     *converged = true;
+    if (side) {
+      st = cg_drive(nullptr, side);
+      if (st) return st;
+    }
   } else {
-    CgRun run;
-    st = run_cg(ctx, m, 1, y, a, o->tol, o->max_iter, o->check_every, false, sc, run, "y solve");
+    Cg cy;
+    cy.ctx = ctx;
+    cy.m = m;
+    cy.S = 1;
+    cy.X = a;
+    cy.max_iter = o->max_iter;
+    cy.check_every = o->check_every;
+    cy.label = "y solve";
+    cy.st = ctx->stream;
+    cy.slot0 = 0;
+    st = cg_begin(cy, y, o->tol, false, sc);
     if (st) return st;
-    total += run.total_iters;
+    st = cg_drive(&cy, side);
+    if (st) return st;
+    total += cy.total_iters;
     for (;;) {
       TIMED(GP2S_T_SPMV, launch_spmv(m->prec, m->row_ptr, m->col, m->val, n, (double)m->nnz / n, a, kx, ctx->stream));
       HIPCHK(launch_axpy_sub(n, y, kx, r, ctx->stream));
@@ -232,28 +387,43 @@ struct ProbeResult {
   bool converged = false;
 };
 
-// Probe solves K q_s = D^1/2 z_s and the Lanczos log-determinant estimate.
-gp2s_status probes_internal(gp2s_ctx ctx, gp2s_matrix m, const gp2s_solve_opts* o, Scratch& sc,
-                            uint64_t* mask, double* Qsol, ProbeResult& pr) {
+// Probe solves K q_s = D^1/2 z_s (Sec. 3.5; App. B.6 "LOGDET"): queues the probe
+// signs and right-hand sides on the second stream and begins the block solve there.
+gp2s_status probes_begin(gp2s_ctx ctx, gp2s_matrix m, const gp2s_solve_opts* o, Scratch& sc, uint64_t* mask,
+                         double* Qsol, Cg& cp) {
   const int64_t n = m->n;
   const int S = o->n_probes;
   double* B = sc.get<double>((size_t)n * S);
+  if (sc.oom) return fail(ctx, GP2S_E_OOM, "probe workspace allocation failed");
+  HIPCHK(launch_probe_masks(n, m->perm, o->seed, S, mask, ctx->aux));
+  HIPCHK(launch_probe_rhs(n, S, mask, m->diag, B, ctx->aux));
+  cp.ctx = ctx;
+  cp.m = m;
+  cp.S = S;
+  cp.X = Qsol;
+  cp.max_iter = o->max_iter;
+  cp.check_every = o->check_every;
+  cp.label = "probe block";
+  cp.st = ctx->aux;
+  cp.slot0 = 2;
+  return cg_begin(cp, B, o->probe_tol, true, sc);
+}
+
+// The Lanczos log-determinant estimate from the finished probe block (after the
+// second stream has been joined into the context's stream).
+gp2s_status probes_finish(gp2s_ctx ctx, gp2s_matrix m, Scratch& sc, const Cg& cp, ProbeResult& pr) {
+  const int64_t n = m->n;
+  const int S = cp.S;
   double* red = sc.get<double>(1 + kReduceBlocks);
   uint32_t* tk = sc.get<uint32_t>(1);
-  if (sc.oom) return fail(ctx, GP2S_E_OOM, "probe workspace allocation failed");
-  HIPCHK(hipMemsetAsync(tk, 0, sizeof(uint32_t), ctx->stream));
-  HIPCHK(launch_probe_masks(n, m->perm, o->seed, S, mask, ctx->stream));
-  HIPCHK(launch_probe_rhs(n, S, mask, m->diag, B, ctx->stream));
-  CgRun run;
-  gp2s_status st = run_cg(ctx, m, S, B, Qsol, o->probe_tol, o->max_iter, o->check_every, true, sc, run, "probe block");
-  if (st) return st;
-  const int64_t max_m = std::max(1, run.total_iters);
+  const int64_t max_m = std::max(1, cp.total_iters);
   double* work = sc.get<double>((size_t)2 * S * max_m);
   double* quad = sc.get<double>(S);
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "quadrature workspace allocation failed");
-  TIMED(GP2S_T_SLQ, launch_slq_ws(S, run.cs.hist_a, run.cs.hist_b, run.cs.iters, work, max_m, quad, ctx->stream));
+  HIPCHK(hipMemsetAsync(tk, 0, sizeof(uint32_t), ctx->stream));
+  TIMED(GP2S_T_SLQ, launch_slq_ws(S, cp.cs.hist_a, cp.cs.hist_b, cp.cs.iters, work, max_m, quad, ctx->stream));
   std::vector<double> qh(S);
-  st = readback(ctx, quad, S * sizeof(double), qh.data());
+  gp2s_status st = readback(ctx, quad, S * sizeof(double), qh.data());
   if (st) return st;
   double sumlog = 0.0;
   HIPCHK(launch_sum_log(n, m->diag, red, tk, ctx->stream));
@@ -266,10 +436,25 @@ gp2s_status probes_internal(gp2s_ctx ctx, gp2s_matrix m, const gp2s_solve_opts* 
   for (int s = 0; s < S; ++s) var += ((double)n * qh[s] - mean) * ((double)n * qh[s] - mean);
   pr.stderr_ = S > 1 ? std::sqrt(var / (S - 1) / S) : 0.0;
   pr.logdet = sumlog + mean;
-  pr.iters = run.total_iters;
-  pr.converged = run.converged;
+  pr.iters = cp.total_iters;
+  pr.converged = cp.converged;
   return GP2S_OK;
 }
+
+// Makes the context's stream wait for everything queued on the second stream.
+struct AuxJoin {
+  gp2s_ctx ctx;
+  ~AuxJoin() {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess) {
+      (void)hipEventRecord(e, ctx->aux);
+      (void)hipStreamWaitEvent(ctx->stream, e, 0);
+      (void)hipEventDestroy(e);
+    } else {
+      (void)hipStreamSynchronize(ctx->aux);
+    }
+  }
+};
 
 gp2s_status lml_common(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_solve_opts* o, double* a,
                        gp2s_report* rep, double* grad) {
@@ -299,14 +484,32 @@ gp2s_status lml_common(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_
   HIPCHK(hipMemsetAsync(tk, 0, sizeof(uint32_t), ctx->stream));
   HIPCHK(launch_gather_rows(n, 1, m->perm, y, yi, ctx->stream));
   std::memset(rep, 0, sizeof(*rep));
+  // The probe block runs on the second stream beside the y solve: it starts after
+  // the work already queued on the context's stream and is joined back before the
+  // quadrature (and on every early return, before the workspace is released).
+  {
+    hipEvent_t e = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    hipError_t e1 = hipEventRecord(e, ctx->stream);
+    hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(ctx->aux, e, 0) : e1;
+    (void)hipEventDestroy(e);
+    if (e2 != hipSuccess) return fail(ctx, GP2S_E_HIP, "ordering the probe stream: %s", hipGetErrorString(e2));
+  }
+  AuxJoin join{ctx};
+  Cg cp;
+  st = probes_begin(ctx, m, o, sc, mask, Qs, cp);
+  if (st) return st;
   bool conv_y = false;
-  st = solve_internal(ctx, m, yi, ai, o, sc, rep, &conv_y);
+  st = solve_internal(ctx, m, yi, ai, o, sc, rep, &conv_y, &cp);
   if (st) return st;
   double yTa = 0.0;
   st = dot_host(ctx, n, yi, ai, red, tk, &yTa);
   if (st) return st;
+  {
+    AuxJoin j2{ctx};
+  }
   ProbeResult pr;
-  st = probes_internal(ctx, m, o, sc, mask, Qs, pr);
+  st = probes_finish(ctx, m, sc, cp, pr);
   if (st) return st;
   rep->yTa = yTa;
   rep->logdet = pr.logdet;
@@ -403,6 +606,7 @@ gp2s_status gp2s_create(gp2s_ctx* out, void* stream, gp2s_alloc_fn alloc, gp2s_f
 
 gp2s_status gp2s_set_timing(gp2s_ctx ctx, int32_t enable) {
   if (!ctx) return GP2S_E_INVALID;
+  if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
   if (!ctx->pending.empty()) {
     (void)hipStreamSynchronize(ctx->stream);
     harvest(ctx);
@@ -424,6 +628,7 @@ gp2s_status gp2s_set_progress(gp2s_ctx ctx, gp2s_progress_fn fn, void* user) {
 
 gp2s_status gp2s_get_stats(gp2s_ctx ctx, gp2s_stats* out) {
   if (!ctx || !out) return GP2S_E_INVALID;
+  if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
   if (!ctx->pending.empty()) {
     hipError_t e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return fail(ctx, GP2S_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
@@ -438,11 +643,17 @@ gp2s_status gp2s_get_stats(gp2s_ctx ctx, gp2s_stats* out) {
 
 gp2s_status gp2s_destroy(gp2s_ctx ctx) {
   if (!ctx) return GP2S_E_INVALID;
+  if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
   if (!ctx->pending.empty()) {
     (void)hipStreamSynchronize(ctx->stream);
     harvest(ctx);
   }
+  for (auto& p : ctx->pending) {
+    (void)hipEventDestroy(p.e0);
+    (void)hipEventDestroy(p.e1);
+  }
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+  if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   delete ctx;
   return GP2S_OK;
@@ -593,7 +804,7 @@ gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_p
     OOMCHK(m->pts64);
   }
   {
-  Timed prep_timer(ctx, GP2S_T_ASM_PREP);
+  Timed prep_timer(ctx, GP2S_T_ASM_PREP, ctx->stream);
   HIPCHK(hipMemsetAsync(bin_count, 0, g.nbins * sizeof(int32_t), sm));
   HIPCHK(launch_prologue(x, n, g, m->centers_d, m->weights_d, m->P, p->bump_width * p->bump_width, bin_of, slot,
                          bin_count, g64u, gam, sm));

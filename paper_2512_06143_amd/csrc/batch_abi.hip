@@ -77,14 +77,6 @@ BatchGeom geom(const gp2s_batch b) {
   return g;
 }
 
-gp2s_status readback_on(gp2s_ctx ctx, hipStream_t s, const void* dev, size_t bytes, void* host) {
-  if (bytes > (1 << 16)) return fail(ctx, GP2S_E_INVALID, "internal: readback too large");
-  HIPCHK(hipMemcpyAsync(ctx->pinned, dev, bytes, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  std::memcpy(host, ctx->pinned, bytes);
-  return GP2S_OK;
-}
-
 // Grids of every instance for bin refinement m (bins of side >= r / m, at most
 // max(4 n, 4096) bins per instance), and the per-instance table.
 void build_grids(gp2s_batch b, int m) {

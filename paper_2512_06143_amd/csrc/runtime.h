@@ -20,6 +20,8 @@ struct gp2s_ctx_s {
   void* user = nullptr;
   std::string err;
   void* pinned = nullptr;  // small pinned host buffer for scalar read-backs
+  // second stream (default priority) for the probe block, which runs beside the y solve
+  hipStream_t aux = nullptr;
   // optional per-kernel timing with HIP events on the context's stream
   bool timing = false;
   struct Pending {
@@ -153,9 +155,15 @@ inline hipEvent_t ev_get(gp2s_ctx c) {
   return e;
 }
 
-// Collect finished event pairs into the per-category totals (the stream is idle).
+// Collect finished event pairs into the per-category totals; pairs still in flight
+// (on another stream) stay pending.
 inline void harvest(gp2s_ctx c) {
+  size_t keep = 0;
   for (auto& p : c->pending) {
+    if (hipEventQuery(p.e1) != hipSuccess) {
+      c->pending[keep++] = p;
+      continue;
+    }
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) {
       c->ms[p.cat] += ms;
@@ -164,33 +172,39 @@ inline void harvest(gp2s_ctx c) {
     c->pool.push_back(p.e0);
     c->pool.push_back(p.e1);
   }
-  c->pending.clear();
+  c->pending.resize(keep);
 }
 
-// Brackets one or more launches with events when timing is enabled.
+// Brackets one or more launches on stream `st` with events when timing is enabled.
 struct Timed {
   gp2s_ctx c;
   int cat;
+  hipStream_t st;
   hipEvent_t e0 = nullptr;
-  Timed(gp2s_ctx cc, int k) : c(cc), cat(k) {
+  Timed(gp2s_ctx cc, int k, hipStream_t s) : c(cc), cat(k), st(s) {
     if (c->timing) {
       e0 = ev_get(c);
-      if (e0) (void)hipEventRecord(e0, c->stream);
+      if (e0) (void)hipEventRecord(e0, st);
     }
   }
   ~Timed() {
     if (!e0) return;
     hipEvent_t e1 = ev_get(c);
     if (!e1) return;
-    (void)hipEventRecord(e1, c->stream);
+    (void)hipEventRecord(e1, st);
     c->pending.push_back({cat, e0, e1});
   }
 };
 
-#define TIMED(cat, expr)          \
-  do {                            \
-    Timed t_(ctx, cat);           \
-    HIPCHK(expr);                 \
+#define TIMED(cat, expr)                \
+  do {                                  \
+    Timed t_(ctx, cat, ctx->stream);    \
+    HIPCHK(expr);                       \
+  } while (0)
+#define TIMED_ON(cat, stream, expr)     \
+  do {                                  \
+    Timed t_(ctx, cat, stream);         \
+    HIPCHK(expr);                       \
   } while (0)
 
 inline gp2s_status ensure_device(gp2s_ctx ctx) {
@@ -201,16 +215,33 @@ inline gp2s_status ensure_device(gp2s_ctx ctx) {
   if (!ctx->pinned) {
     HIPCHK(hipHostMalloc(&ctx->pinned, kPinnedBytes, hipHostMallocDefault));
   }
+  if (!ctx->aux) {
+    HIPCHK(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+  }
   return GP2S_OK;
 }
 
+// The first half of the pinned buffer serves read-backs; the second half holds the
+// lagged convergence polls of the CG drivers (kPollSlot bytes per slot).
+constexpr size_t kReadbackBytes = kPinnedBytes / 2;
+constexpr size_t kPollSlot = 2048;
+
 // Copy `bytes` from device to the pinned buffer and wait for the stream.
 inline gp2s_status readback(gp2s_ctx ctx, const void* dev, size_t bytes, void* host) {
-  if (bytes > kPinnedBytes) return fail(ctx, GP2S_E_INVALID, "internal: readback too large");
+  if (bytes > kReadbackBytes) return fail(ctx, GP2S_E_INVALID, "internal: readback too large");
   HIPCHK(hipMemcpyAsync(ctx->pinned, dev, bytes, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   std::memcpy(host, ctx->pinned, bytes);
   if (!ctx->pending.empty()) harvest(ctx);
+  return GP2S_OK;
+}
+
+// Same as readback, on stream `s`.
+inline gp2s_status readback_on(gp2s_ctx ctx, hipStream_t s, const void* dev, size_t bytes, void* host) {
+  if (bytes > kReadbackBytes) return fail(ctx, GP2S_E_INVALID, "internal: readback too large");
+  HIPCHK(hipMemcpyAsync(ctx->pinned, dev, bytes, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::memcpy(host, ctx->pinned, bytes);
   return GP2S_OK;
 }
 
