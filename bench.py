@@ -50,26 +50,36 @@ def kernel_bytes(cat, n, nnz, S, prec):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c2_mixed.md")
-TRAFFIC_KERNEL = {"cg_matvec_block": "k_spmm<float, float, true>", "cg_update_block": "k_cg_update<float>",
-                  "cg_pupdate_block": "k_cg_pupdate<float>", "cg_matvec1": "k_spmv<16, float, true>"}
+TRAFFIC_KERNEL = {"cg_update_block": "k_cg_update<float>", "cg_pupdate_block": "k_cg_pupdate<float>",
+                  "cg_matvec1": "k_spmv<16, float, true>"}
 
 
-def measured_traffic(cat, config, precision):
+def block_kernel_name(variant, S):
+    """Kernel name (as rocprofv3 prints it) of the mixed path's probe-block product."""
+    if variant == 0:
+        return "k_spmm<float, float, double, true>"
+    if variant == 1:
+        return f"k_spmm_s<{S}, float, float, true>"
+    return f"k_spmm_e<{variant}, {S}, float, float, true>"
+
+
+def measured_traffic(cat, config, precision, kernel_name=None):
     """Scaled FETCH_SIZE + WRITE_SIZE bytes per dispatch from the committed rocprofv3
     summary, or None when it does not cover this kernel/workload or the kernel
     sources changed since the counters were taken."""
     import hashlib
-    if config != "c2" or precision != "mixed" or cat not in TRAFFIC_KERNEL or not os.path.exists(TRAFFIC_FILE):
+    name = kernel_name or TRAFFIC_KERNEL.get(cat)
+    if config != "c2" or precision != "mixed" or name is None or not os.path.exists(TRAFFIC_FILE):
         return None
     h = hashlib.sha256()
-    for fn in ("spmv.hip", "pcg.hip"):
+    for fn in ("spmv.hip", "spmm_rows.h", "pcg.hip"):
         with open(os.path.join(ROOT, "paper_2512_06143_amd", "csrc", fn), "rb") as fh:
             h.update(fh.read())
     text = open(TRAFFIC_FILE).read()
     if f"kernel-source-sha256: {h.hexdigest()}" not in text:
         return None
     for line in text.splitlines():
-        if line.startswith(f"| `{TRAFFIC_KERNEL[cat]}` |"):
+        if line.startswith(f"| `{name}` |"):
             cells = [c.strip() for c in line.strip("|").split("|")]
             return (float(cells[2]) + float(cells[5])) * 1e6
     return None
@@ -85,17 +95,25 @@ def make_inputs(args):
     return prob
 
 
-def run_step(G, x, y, params, precision, opts):
+BLOCK_PRODUCT = {}  # variant of the probe-block product chosen in the last step
+
+
+def run_step(G, x, y, params, precision, opts, block_product=None):
     m = G.gp2s_assemble(x, params, precision)
+    S = opts.n_probes
+    if block_product is not None and S > 1:
+        m.set_block_product(S, block_product)
     rep, grad, _ = G.gp2s_lml_grad(m, y, opts, want_a=False, allow_noconv=True)
     if rep.status:
         log(f"[bench] WARNING: CG stopped at max_iter ({precision}): y iters={rep.iters} probe iters={rep.probe_iters}")
+    if S > 1:
+        BLOCK_PRODUCT[precision] = m.block_product(S)
     n, nnz = m.n, m.nnz
     m.free()
     return rep, grad, n, nnz
 
 
-def cpu_baseline(prob, nnz_full, iters_y, iters_probe, S, budget_points=250_000, k_iter=300):
+def cpu_baseline(prob, nnz_full, iters_y, iters_probe, S, budget_points=250_000, budget_s=15.0):
     """The oracle as it stands on a bounded sample: the points inside a square window
     (about budget_points of them) around the densest cluster centre region of the same
     point cloud. Times oracle.covariance_csr (assembly) and oracle.pcg_jacobi per
@@ -121,6 +139,11 @@ def cpu_baseline(prob, nnz_full, iters_y, iters_probe, S, budget_points=250_000,
     t0 = time.perf_counter()
     K = oracle.covariance_csr(xs, prob.radius, prob.bump_width, prob.centers, prob.weights, prob.noise_var)
     t_asm = time.perf_counter() - t0
+    # iteration count sized so that the whole sample takes about budget_s seconds
+    t0 = time.perf_counter()
+    oracle.pcg_jacobi(K, ys, tol=1e-300, max_iter=20)
+    t_est = (time.perf_counter() - t0) / 20
+    k_iter = int(min(5000, max(50, (budget_s - t_asm - 20 * t_est) / max(t_est, 1e-6))))
     t0 = time.perf_counter()
     oracle.pcg_jacobi(K, ys, tol=1e-300, max_iter=k_iter)
     t_it = (time.perf_counter() - t0) / k_iter
@@ -129,7 +152,8 @@ def cpu_baseline(prob, nnz_full, iters_y, iters_probe, S, budget_points=250_000,
     return {
         "value": proj, "unit": "s per LML+grad (projected)", "cores": 1, "kind": "oracle",
         "sample": (f"{int(sel.sum())} points in a square window of the same cloud ({K.nnz} nnz); "
-                   f"oracle.covariance_csr {t_asm:.2f}s, oracle.pcg_jacobi {t_it * 1e3:.1f} ms/iteration; "
+                   f"oracle.covariance_csr {t_asm:.2f}s, oracle.pcg_jacobi {t_it * 1e3:.1f} ms/iteration over "
+                   f"{k_iter} iterations; "
                    f"scaled by nnz x{scale:.1f} and by the GPU iteration counts ({iters_y} y + {S}x{iters_probe} "
                    f"probe); gradient pass not included"),
         "assembly_nnz_per_s": K.nnz / t_asm,
@@ -277,7 +301,9 @@ def main():
     if b is not None:
         roof = {"kernel": dom, "bound": "hbm", "achieved": b / avg_s / 1e9, "peak": PEAK_HBM / 1e9,
                 "unit": "GB/s", "frac": b / avg_s / PEAK_HBM,
-                "traffic": measured_traffic(dom, args.config, args.precision),
+                "traffic": measured_traffic(dom, args.config, args.precision,
+                                            block_kernel_name(BLOCK_PRODUCT.get(args.precision), S)
+                                            if dom == "cg_matvec_block" and args.precision == "mixed" else None),
                 "bytes_per_launch": b, "avg_ms": avg_s * 1e3, "launches": cnt}
     asm_ms = sum(stats[k][0] for k in ("asm_prep", "asm_count", "asm_fill")) / args.steps
     mv1 = stats["cg_matvec1"]
@@ -298,6 +324,8 @@ def main():
         "assembly_ms": asm_ms, "assembly_nnz_per_s": nnz / (asm_ms / 1e3) if asm_ms else None,
         "cg_spmv_GBps": spmv_gbs,
         "iters_y": rep.iters, "iters_probe": rep.probe_iters, "ir_steps": rep.ir_steps,
+        "block_product": (block_kernel_name(BLOCK_PRODUCT[args.precision], S)
+                          if BLOCK_PRODUCT.get(args.precision) is not None else None),
         "resid": rep.resid, "lml": rep.lml, "logdet": rep.logdet, "logdet_stderr": rep.logdet_stderr,
         "grad_r": float(grad[0]),
         "kernels_ms": {k: round(v[0] / args.steps, 3) for k, v in per.items()},

@@ -196,6 +196,8 @@ gp2s_status gp2s_matrix_free(gp2s_matrix m);
  * not apply gives GP2S_E_INVALID. All variants give the same products up to the
  * order of float64 summation. */
 gp2s_status gp2s_matrix_set_block_product(gp2s_matrix m, int32_t nrhs, int32_t variant);
+/* The variant in use for `nrhs` columns (HOST output), -1 while not yet chosen. */
+gp2s_status gp2s_matrix_get_block_product(gp2s_matrix m, int32_t nrhs, int32_t* variant);
 
 /* ---- products and solves ------------------------------------------------------------
  * Y = K X for nrhs in [1, 64] right-hand sides; X and Y are DEVICE [n * nrhs] float64,

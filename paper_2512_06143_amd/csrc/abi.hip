@@ -957,6 +957,12 @@ gp2s_status gp2s_matrix_set_block_product(gp2s_matrix m, int32_t nrhs, int32_t v
   return GP2S_OK;
 }
 
+gp2s_status gp2s_matrix_get_block_product(gp2s_matrix m, int32_t nrhs, int32_t* variant) {
+  if (!m || !variant || nrhs < 2 || nrhs > kMaxProbes) return GP2S_E_INVALID;
+  *variant = m->spmm_variant[nrhs] == -2 ? -1 : m->spmm_variant[nrhs];
+  return GP2S_OK;
+}
+
 gp2s_status gp2s_spmv(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X, double* Y) {
   if (!ctx) return GP2S_E_INVALID;
   gp2s_status st = check_matrix(ctx, m);

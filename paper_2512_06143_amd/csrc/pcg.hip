@@ -14,7 +14,8 @@ namespace gp2s {
 static inline int cols_block(int S) { return (kBlock / S) * S; }
 
 // Per-column sums of the block's values (thread t belongs to column t % S), written to
-// partial[(blockIdx * 2 + which) * S + column].
+// partial[(which * S + column) * gridDim + blockIdx] (column-major, so that the
+// finalize kernels read each column's partials contiguously).
 __device__ inline void block_cols_to_partial(double* sh, int S, double v, double* partial, int which) {
   const int nth = blockDim.x;
   const int per = nth / S;  // threads per column
@@ -26,11 +27,11 @@ __device__ inline void block_cols_to_partial(double* sh, int S, double v, double
       if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
       __syncthreads();
     }
-    if ((int)threadIdx.x < S) partial[(blockIdx.x * 2 + which) * (int64_t)S + threadIdx.x] = sh[threadIdx.x];
+    if ((int)threadIdx.x < S) partial[((int64_t)which * S + threadIdx.x) * gridDim.x + blockIdx.x] = sh[threadIdx.x];
   } else if ((int)threadIdx.x < S) {
     double t = 0.0;
     for (int k = threadIdx.x; k < nth; k += S) t += sh[k];
-    partial[(blockIdx.x * 2 + which) * (int64_t)S + threadIdx.x] = t;
+    partial[((int64_t)which * S + threadIdx.x) * gridDim.x + blockIdx.x] = t;
   }
   __syncthreads();
 }
@@ -86,10 +87,13 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int S, double* 
 }
 
 // ---- finalizers: one workgroup per column, fixed-order sums of the partials ----------
-// Sum of partial[(b * W + which) * S + s] over b < nb (all threads of the workgroup).
+// Sum of partial[(which * S + s) * nb + b] over b < nb (all threads of the workgroup);
+// W (partials per block and column) is implied by the layout and kept for clarity.
 __device__ inline double column_sum(const double* partial, int nb, int W, int which, int S, int s, double* sh) {
   double v = 0.0;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) v += partial[((int64_t)b * W + which) * S + s];
+  (void)W;
+  const double* __restrict__ col = partial + ((int64_t)which * S + s) * nb;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) v += col[b];
   sh[threadIdx.x] = v;
   __syncthreads();
   for (int o = blockDim.x / 2; o > 0; o >>= 1) {

@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm(const int64_t* __restrict__ rp,
   if (wid == 0 && active) {
     double t = 0.0;
     for (int w = 0; w < kBlock / kWave; ++w) t += sh[w * kWave + lane];
-    cs.partial[blockIdx.x * (int64_t)S + lane] = t;
+    cs.partial[(int64_t)lane * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_e(const int64_t* __restrict__ r
   if ((int)threadIdx.x < S) {
     double t = 0.0;
     for (int w = 0; w < kBlock / kWave; ++w) t += sh[w][threadIdx.x];
-    cs.partial[blockIdx.x * (int64_t)S + threadIdx.x] = t;
+    cs.partial[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_s(const int64_t* __restrict__ r
   if ((int)threadIdx.x < S) {
     double t = 0.0;
     for (int w = 0; w < kBlock / kWave; ++w) t += sh[w][threadIdx.x];
-    cs.partial[blockIdx.x * (int64_t)S + threadIdx.x] = t;
+    cs.partial[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
   }
 }
 

@@ -85,6 +85,7 @@ _SIGS = {
     "gp2s_matrix_import": (_i32, [_vp, _i64, _i64, _vp, _vp, _vp, _i32, ctypes.POINTER(_vp)]),
     "gp2s_matrix_free": (_i32, [_vp]),
     "gp2s_matrix_set_block_product": (_i32, [_vp, _i32, _i32]),
+    "gp2s_matrix_get_block_product": (_i32, [_vp, _i32, ctypes.POINTER(_i32)]),
     "gp2s_spmv": (_i32, [_vp, _vp, _i32, _vp, _vp]),
     "gp2s_solve": (_i32, [_vp, _vp, _vp, _vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(Report)]),
     "gp2s_lml": (_i32, [_vp, _vp, _vp, ctypes.POINTER(SolveOpts), _vp, ctypes.POINTER(Report)]),
@@ -242,6 +243,14 @@ class Matrix:
         st = lib.gp2s_matrix_set_block_product(self.handle, int(nrhs), int(variant))
         if st != GP2S_OK:
             raise GP2SError(st, f"block-product variant {variant} does not apply to {nrhs} columns")
+
+    def block_product(self, nrhs: int) -> int:
+        """The block-product variant in use for `nrhs` columns (-1 before the first solve)."""
+        v = _i32()
+        st = lib.gp2s_matrix_get_block_product(self.handle, int(nrhs), ctypes.byref(v))
+        if st != GP2S_OK:
+            raise GP2SError(st, f"no block product for {nrhs} columns")
+        return v.value
 
     def free(self):
         if self.handle:
