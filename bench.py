@@ -60,6 +60,8 @@ def block_kernel_name(variant, S):
         return "k_spmm<float, float, double, true>"
     if variant == 1:
         return f"k_spmm_s<{S}, float, float, true>"
+    if variant == 2:
+        return f"k_spmm_t<{S}, float, float, true>"
     return f"k_spmm_e<{variant}, {S}, float, float, true>"
 
 

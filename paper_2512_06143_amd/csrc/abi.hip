@@ -58,12 +58,89 @@ struct Cg {
   }
 };
 
+// Row tiles of about kTileRows bin-sorted rows inside one bin row (band) of the grid, at
+// most kTileMaxRows each, with the column intervals of the neighbouring bins: for every
+// neighbouring band, the bins from one before the tile's first bin to one after its
+// last are consecutive in bin order, so their points form one run of columns. Built on
+// the host from bin_start, once per assembled matrix.
+constexpr int kTileRows = 32;
+constexpr int64_t kTileMaxBins = int64_t(1) << 23;
+
+gp2s_status ensure_tiles(gp2s_ctx ctx, gp2s_matrix m) {
+  if (m->tiles_tried) return GP2S_OK;
+  m->tiles_tried = true;
+  if (!m->assembled || !m->bin_start || m->grid.nbins < 1 || m->grid.nbins > kTileMaxBins) return GP2S_OK;
+  const GridDev& g = m->grid;
+  std::vector<int64_t> bs((size_t)g.nbins + 1);
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipMemcpy(bs.data(), m->bin_start, bs.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+  const int nb0 = g.nb[0], nb1 = g.dim >= 2 ? g.nb[1] : 1, nb2 = g.dim == 3 ? g.nb[2] : 1;
+  std::vector<RowTile> tiles;
+  tiles.reserve((size_t)(m->n / kTileRows) + 16);
+  for (int bz = 0; bz < nb2; ++bz)
+    for (int by = 0; by < nb1; ++by) {
+      const int64_t band = (int64_t)nb0 * (by + (int64_t)nb1 * bz);
+      int bx = 0;
+      while (bx < nb0) {
+        const int b0 = bx;
+        int64_t rows = 0;
+        while (bx < nb0 && rows < kTileRows) {
+          rows += bs[band + bx + 1] - bs[band + bx];
+          ++bx;
+        }
+        if (rows == 0) continue;
+        const int b1 = bx - 1;
+        RowTile T{};
+        T.niv = 0;
+        for (int dz = (g.dim == 3 ? -1 : 0); dz <= (g.dim == 3 ? 1 : 0); ++dz)
+          for (int dy = -1; dy <= 1; ++dy) {
+            const int yy = by + dy, zz = bz + dz;
+            if (yy < 0 || yy >= nb1 || zz < 0 || zz >= nb2) continue;
+            const int64_t nband = (int64_t)nb0 * (yy + (int64_t)nb1 * zz);
+            const int64_t lo = bs[nband + std::max(b0 - 1, 0)];
+            const int64_t hi = bs[nband + std::min(b1 + 1, nb0 - 1) + 1];
+            if (hi > lo && T.niv < kTileMaxIv) {
+              T.lo[T.niv] = (int32_t)lo;
+              T.len[T.niv] = (int32_t)(hi - lo);
+              ++T.niv;
+            }
+          }
+        const int64_t r0 = bs[band + b0];
+        for (int64_t c = 0; c < rows; c += kTileMaxRows) {
+          T.row0 = r0 + c;
+          T.rows = (int32_t)std::min<int64_t>(kTileMaxRows, rows - c);
+          tiles.push_back(T);
+        }
+      }
+    }
+  if (tiles.empty()) return GP2S_OK;
+  RowTile* d = own<RowTile>(m, tiles.size());
+  if (!d) return GP2S_OK;  // no room: the other block products remain
+  HIPCHK(hipMemcpyAsync(d, tiles.data(), tiles.size() * sizeof(RowTile), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  m->tiles = d;
+  m->ntiles = (int64_t)tiles.size();
+  return GP2S_OK;
+}
+
+TileSet tile_set(gp2s_matrix m) {
+  TileSet t;
+  t.t = m->tiles;
+  t.n = m->ntiles;
+  return t;
+}
+
 // Chooses the block product for S columns of this matrix by timing each variant on the
 // first CG product (the product and its alpha are recomputed by the first iteration).
 gp2s_status tune_block_product(gp2s_ctx ctx, gp2s_matrix m, int S, const void* P, void* Q, bool f32vec,
                                const CgState& cs, hipStream_t st) {
   std::vector<int> cand{0};
-  if (S == 8 || S == 16 || S == 32 || S == 64) cand.push_back(1);
+  if (S == 8 || S == 16 || S == 32 || S == 64) {
+    cand.push_back(1);
+    gp2s_status ts = ensure_tiles(ctx, m);
+    if (ts) return ts;
+    if (m->tiles) cand.push_back(2);
+  }
   for (int G = 4; G <= 16; G *= 2)
     if (entry_product_ok(S, G)) cand.push_back(G);
   if (cand.size() == 1) {
@@ -81,10 +158,12 @@ gp2s_status tune_block_product(gp2s_ctx ctx, gp2s_matrix m, int S, const void* P
   int pick = 0;
   hipError_t err = hipSuccess;
   for (int v : cand) {
-    err = launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, m->n, S, mean_row, v, P, Q, f32vec, cs, st);
+    err = launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, m->n, S, mean_row, v, tile_set(m), P, Q, f32vec, cs,
+                           st);
     if (err == hipSuccess) err = hipEventRecord(e0, st);
     for (int r = 0; r < 3 && err == hipSuccess; ++r)
-      err = launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, m->n, S, mean_row, v, P, Q, f32vec, cs, st);
+      err = launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, m->n, S, mean_row, v, tile_set(m), P, Q, f32vec, cs,
+                           st);
     if (err == hipSuccess) err = hipEventRecord(e1, st);
     if (err == hipSuccess) err = hipEventSynchronize(e1);
     float ms = 0.f;
@@ -165,8 +244,8 @@ gp2s_status cg_step(Cg& c) {
   const int64_t n = m->n;
   const int S = c.S;
   TIMED_ON(S == 1 ? GP2S_T_CG_MATVEC1 : GP2S_T_CG_MATVEC_BLOCK, c.st,
-           launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, n, S, (double)m->nnz / (double)n, c.variant, c.P,
-                            c.Q, c.f32vec, c.cs, c.st));
+           launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, n, S, (double)m->nnz / (double)n, c.variant,
+                            tile_set(m), c.P, c.Q, c.f32vec, c.cs, c.st));
   TIMED_ON(S == 1 ? GP2S_T_CG_UPDATE1 : GP2S_T_CG_UPDATE_BLOCK, c.st,
            launch_cg_update(n, S, c.X, c.R, c.P, c.Q, c.f32vec, m->dinv, c.cs, c.it, c.st));
   TIMED_ON(S == 1 ? GP2S_T_CG_PUPDATE1 : GP2S_T_CG_PUPDATE_BLOCK, c.st,
@@ -951,7 +1030,8 @@ gp2s_status gp2s_matrix_free(gp2s_matrix m) {
 gp2s_status gp2s_matrix_set_block_product(gp2s_matrix m, int32_t nrhs, int32_t variant) {
   if (!m || nrhs < 2 || nrhs > kMaxProbes) return GP2S_E_INVALID;
   const bool sliced = nrhs == 8 || nrhs == 16 || nrhs == 32 || nrhs == 64;
-  const bool ok = variant == -1 || variant == 0 || (variant == 1 && sliced) || entry_product_ok(nrhs, variant);
+  const bool ok = variant == -1 || variant == 0 || (variant == 1 && sliced) || (variant == 2 && sliced && m->assembled) ||
+                  entry_product_ok(nrhs, variant);
   if (!ok) return GP2S_E_INVALID;
   m->spmm_variant[nrhs] = variant == -1 ? -2 : variant;
   return GP2S_OK;
@@ -978,13 +1058,17 @@ gp2s_status gp2s_spmv(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X
   double* Xi = sc.get<double>((size_t)n * nrhs);
   double* Yi = sc.get<double>((size_t)n * nrhs);
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "spmv workspace allocation failed");
+  if (nrhs > 1 && m->spmm_variant[nrhs] == 2) {
+    st = ensure_tiles(ctx, m);
+    if (st) return st;
+  }
   HIPCHK(launch_gather_rows(n, nrhs, m->perm, X, Xi, ctx->stream));
   if (nrhs == 1)
     TIMED(GP2S_T_SPMV, launch_spmv(m->prec, m->row_ptr, m->col, m->val, n, (double)m->nnz / n, Xi, Yi, ctx->stream));
   else
     TIMED(GP2S_T_SPMM, launch_spmm(m->prec, m->row_ptr, m->col, m->val, n, nrhs, (double)m->nnz / n,
-                                           m->spmm_variant[nrhs] >= 0 ? m->spmm_variant[nrhs] : -1, Xi, Yi,
-                                           ctx->stream));
+                                           m->spmm_variant[nrhs] >= 0 ? m->spmm_variant[nrhs] : -1, tile_set(m),
+                                           Xi, Yi, ctx->stream));
   HIPCHK(launch_scatter_rows(n, nrhs, m->perm, Yi, Y, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return GP2S_OK;

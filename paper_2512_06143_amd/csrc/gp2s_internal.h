@@ -87,6 +87,23 @@ __device__ inline XcdRows xcd_rows(int64_t n, int unit, int units) {
 }
 __host__ inline int64_t round_up8(int64_t b) { return (b + 7) / 8 * 8; }
 
+// A tile of consecutive (bin-sorted) rows for the LDS-staged block product, with the
+// column intervals its rows can reference: the points of the neighbouring bins, which
+// form one contiguous run of columns per neighbouring bin row (3 in 2-D, 9 in 3-D).
+constexpr int kTileMaxIv = 9;
+struct RowTile {
+  int64_t row0;
+  int32_t rows, niv;
+  int32_t lo[kTileMaxIv], len[kTileMaxIv];
+};
+struct TileSet {
+  const RowTile* t = nullptr;
+  int64_t n = 0;
+};
+constexpr int kTileLdsBytes = 72 * 1024;  // staged rows of X per workgroup (2 workgroups per CU)
+constexpr int kTileBlock = 1024;          // 16 waves per workgroup hide the row-pointer latency
+constexpr int kTileMaxRows = 64;          // rows per tile (at most)
+
 // The entry-parallel block products exist for S in {8, 16, 32, 64} and G in {4, 8, 16}, G <= S.
 __host__ inline bool entry_product_ok(int S, int G) {
   return (S == 8 || S == 16 || S == 32 || S == 64) && (G == 4 || G == 8 || G == 16) && G <= S;
@@ -166,14 +183,15 @@ hipError_t launch_assemble_fill(const AssembleArgs& a, int prec, const int64_t* 
 hipError_t launch_spmv(int prec, const int64_t* rp, const int32_t* col, const void* val,
                        int64_t n, double mean_row, const double* x, double* y, hipStream_t st);
 hipError_t launch_spmm(int prec, const int64_t* rp, const int32_t* col, const void* val,
-                       int64_t n, int S, double mean_row, int variant, const double* X, double* Y, hipStream_t st);
+                       int64_t n, int S, double mean_row, int variant, const TileSet& tiles, const double* X,
+                       double* Y, hipStream_t st);
 // CG product step: Q = K P plus p^T q per column, then alpha = rz / p^T q.
 // P is float32 when f32vec (block solves of the mixed path), else float64; Q is float64.
 // `variant` selects the block product for S > 1: 0 one lane per column, G > 0 the
 // entry-parallel product with G lanes per row, -1 a choice from S and the mean row length.
 hipError_t launch_cg_matvec(int prec, const int64_t* rp, const int32_t* col, const void* val,
-                            int64_t n, int S, double mean_row, int variant, const void* P, void* Q, bool f32vec,
-                            const CgState& cs, hipStream_t st);
+                            int64_t n, int S, double mean_row, int variant, const TileSet& tiles, const void* P,
+                            void* Q, bool f32vec, const CgState& cs, hipStream_t st);
 
 // pcg.hip
 hipError_t launch_cg_alpha(const CgState& cs, int nb, int S, hipStream_t st);

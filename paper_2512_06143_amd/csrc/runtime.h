@@ -42,6 +42,10 @@ struct gp2s_matrix_s {
   int prec = GP2S_FP64;
   // block-product variant per column count, measured on first use (-2: not yet)
   int spmm_variant[gp2s::kMaxProbes + 1];
+  // row tiles of the LDS-staged block product (assembled handles; built on first use)
+  gp2s::RowTile* tiles = nullptr;
+  int64_t ntiles = 0;
+  bool tiles_tried = false;
   gp2s_matrix_s() {
     for (int& v : spmm_variant) v = -2;
   }

@@ -38,6 +38,28 @@ __device__ inline void load_cols(const double* __restrict__ p, double (&v)[CW]) 
   }
 }
 
+// As load_cols, through a generic pointer that may address LDS or global memory.
+template <int CW>
+__device__ inline void load_cols_generic(const float* p, float (&v)[CW]) {
+#pragma unroll
+  for (int q = 0; q < CW / 4; ++q) {
+    const float4 t = reinterpret_cast<const float4*>(p)[q];
+    v[4 * q] = t.x;
+    v[4 * q + 1] = t.y;
+    v[4 * q + 2] = t.z;
+    v[4 * q + 3] = t.w;
+  }
+}
+template <int CW>
+__device__ inline void load_cols_generic(const double* p, double (&v)[CW]) {
+#pragma unroll
+  for (int q = 0; q < CW / 2; ++q) {
+    const double2 t = reinterpret_cast<const double2*>(p)[q];
+    v[2 * q] = t.x;
+    v[2 * q + 1] = t.y;
+  }
+}
+
 // Columns c0 .. c0 + CW of row [s, e) times X (row stride S). `lane` in [0, G) is the
 // lane's index inside its row group; every lane of the group must call this together
 // (the exchange uses width-G shuffles). On return out[j] holds column
@@ -118,6 +140,62 @@ __device__ inline void row_slices_product(const int32_t* __restrict__ col, const
         const int src = (j + u) * EPS + q;
         v[u] = __shfl(vj, src);
         load_cols<VW>(X + __shfl(off, src) + cq * VW, x[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int c = 0; c < VW; ++c) acc[c] += (double)v[u] * (double)x[u][c];
+    }
+  }
+#pragma unroll
+  for (int m = LE; m < kWave; m <<= 1)
+#pragma unroll
+    for (int c = 0; c < VW; ++c) acc[c] += __shfl_xor(acc[c], m);
+}
+
+// As row_slices_product, for a row of an LDS-staged tile: rows of X in the tile's staged
+// column intervals are read from `lds` (row-major, S values per row), all others from X.
+// iv_lo / iv_len / iv_base describe the tile's intervals (base -1: not staged).
+template <int S, typename V, typename PT>
+__device__ inline void row_tiled_product(const int32_t* __restrict__ col, const V* __restrict__ val, int64_t s,
+                                         int64_t e, int lane, const PT* __restrict__ X, const PT* lds, int niv,
+                                         const int32_t* iv_lo, const int32_t* iv_len, const int32_t* iv_base,
+                                         double (&acc)[16 / sizeof(PT)]) {
+  constexpr int VW = 16 / sizeof(PT);
+  constexpr int LE = S / VW;
+  constexpr int EPS = kWave / LE;
+  constexpr int U = LE < 4 ? LE : 4;
+  const int q = lane / LE, cq = lane % LE;
+#pragma unroll
+  for (int c = 0; c < VW; ++c) acc[c] = 0.0;
+  for (int64_t k0 = s; k0 < e; k0 += kWave) {
+    const int64_t k = k0 + lane;
+    int32_t off = 0, loc = -1;
+    V vj = (V)0;
+    if (k < e) {
+      const int32_t c = col[k];
+      off = c * S;
+      vj = val[k];
+      for (int t = 0; t < niv; ++t) {
+        const int32_t d = c - iv_lo[t];
+        if (d >= 0 && d < iv_len[t] && iv_base[t] >= 0) loc = (iv_base[t] + d) * S;
+      }
+    }
+    const int cnt = (int)min((int64_t)kWave, e - k0);
+    const int steps = (cnt + EPS - 1) / EPS;
+    for (int j = 0; j < steps; j += U) {
+      V v[U];
+      PT x[U][VW];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int src = (j + u) * EPS + q;
+        v[u] = __shfl(vj, src);
+        const int32_t l = __shfl(loc, src);
+        const int32_t o = __shfl(off, src);
+        // one generic (flat) load whose address lies in LDS or in global memory, so
+        // that the U loads of a step stay in flight together
+        const PT* p = l >= 0 ? lds + l + cq * VW : X + o + cq * VW;
+        load_cols_generic<VW>(p, x[u]);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)

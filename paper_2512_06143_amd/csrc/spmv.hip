@@ -260,6 +260,97 @@ __global__ __launch_bounds__(kBlock) void k_spmm_s(const int64_t* __restrict__ r
   }
 }
 
+// LDS-staged block product over row tiles (S in {8, 16, 32, 64}). A workgroup takes the
+// tiles of an XCD-contiguous range in turn: it copies the rows of X in the tile's column
+// intervals into LDS (as many whole intervals as fit in kTileLdsBytes), then each wave
+// multiplies whole rows with row_tiled_product, reading staged rows from LDS and the
+// rest from X. p^T q partials per workgroup and column as in k_spmm.
+template <int S, typename V, typename PT, bool DOT>
+__global__ __launch_bounds__(kTileBlock) void k_spmm_t(const int64_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ col, const V* __restrict__ val,
+                                                       const RowTile* __restrict__ tiles, int64_t ntiles,
+                                                       const PT* __restrict__ X, double* __restrict__ Y, CgState cs) {
+  constexpr int VW = 16 / sizeof(PT);
+  constexpr int LE = S / VW;
+  constexpr int NW = kTileBlock / kWave;
+  constexpr int BUDGET = kTileLdsBytes / (S * (int)sizeof(PT));  // rows of X
+  __shared__ __align__(16) PT lds[BUDGET * S];
+  __shared__ int32_t iv_lo[kTileMaxIv], iv_len[kTileMaxIv], iv_base[kTileMaxIv];
+  __shared__ int64_t t_rp[kTileMaxRows + 1];
+  __shared__ int64_t t_row0;
+  __shared__ int32_t t_rows, t_niv;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int cq = lane % LE;
+  const XcdRows tr = xcd_rows(ntiles, 0, 1);
+  double dot[VW];
+#pragma unroll
+  for (int c = 0; c < VW; ++c) dot[c] = 0.0;
+  for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+    if (threadIdx.x == 0) {
+      const RowTile& T = tiles[t];
+      t_row0 = T.row0;
+      t_rows = T.rows < kTileMaxRows ? T.rows : kTileMaxRows;
+      const int niv = T.niv < kTileMaxIv ? T.niv : kTileMaxIv;
+      t_niv = niv;
+      int cum = 0;
+      for (int k = 0; k < niv; ++k) {
+        iv_lo[k] = T.lo[k];
+        iv_len[k] = T.len[k];
+        if (T.len[k] > 0 && cum + T.len[k] <= BUDGET) {
+          iv_base[k] = cum;
+          cum += T.len[k];
+        } else {
+          iv_base[k] = -1;
+        }
+      }
+    }
+    __syncthreads();
+    const int niv = t_niv;
+    const int64_t r0 = t_row0;
+    const int nrows = t_rows;
+    if ((int)threadIdx.x <= nrows) t_rp[threadIdx.x] = rp[r0 + threadIdx.x];
+    for (int k = 0; k < niv; ++k) {
+      if (iv_base[k] < 0) continue;
+      const float4* __restrict__ src = reinterpret_cast<const float4*>(X + (int64_t)iv_lo[k] * S);
+      float4* dst = reinterpret_cast<float4*>(lds + (int64_t)iv_base[k] * S);
+      const int nvec = iv_len[k] * (S * (int)sizeof(PT) / 16);
+      int i = threadIdx.x;
+      for (; i + kTileBlock < nvec; i += 2 * kTileBlock) {  // two loads in flight per thread
+        const float4 a = src[i], b = src[i + kTileBlock];
+        dst[i] = a;
+        dst[i + kTileBlock] = b;
+      }
+      if (i < nvec) dst[i] = src[i];
+    }
+    __syncthreads();
+    for (int rl = wid; rl < nrows; rl += NW) {
+      double acc[VW];
+      row_tiled_product<S>(col, val, t_rp[rl], t_rp[rl + 1], lane, X, lds, niv, iv_lo, iv_len, iv_base, acc);
+      if (lane < LE) {
+        const int64_t o = (r0 + rl) * S + cq * VW;
+#pragma unroll
+        for (int c = 0; c < VW; ++c) {
+          Y[o + c] = acc[c];
+          if (DOT) dot[c] += acc[c] * (double)X[o + c];
+        }
+      }
+    }
+    __syncthreads();  // the next tile overwrites LDS and the descriptors
+  }
+  if (!DOT) return;
+  double* sh = reinterpret_cast<double*>(lds);  // LDS is free now (NW * S doubles)
+  if (lane < LE)
+#pragma unroll
+    for (int c = 0; c < VW; ++c) sh[wid * S + cq * VW + c] = dot[c];
+  __syncthreads();
+  if ((int)threadIdx.x < S) {
+    double tsum = 0.0;
+    for (int w = 0; w < NW; ++w) tsum += sh[w * S + threadIdx.x];
+    cs.partial[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = tsum;
+  }
+}
+
 // Lanes per row of the entry-parallel product: about a sixth of the mean row length,
 // a power of two in [4, min(16, S)].
 static int pick_entry_group(double mean_row, int S) {
@@ -304,12 +395,38 @@ static bool spmm_slices(const int64_t* rp, const int32_t* col, const V* val, int
   return true;
 }
 
-// variant: 0 lane per column, 1 slice per lane, G > 1 entry-parallel with G lanes per
-// row, -1 heuristic (entry-parallel up to 32 columns, else one lane per column).
+// Launches k_spmm_t when S has an instance, tiles exist and X is 16-byte aligned.
+template <typename V, typename PT, bool DOT>
+static bool spmm_tiles(const int64_t* rp, const int32_t* col, const V* val, int S, const TileSet& tiles,
+                       const PT* X, double* Y, const CgState& cs, hipStream_t st, int64_t blocks) {
+  if ((S != 8 && S != 16 && S != 32 && S != 64) || !tiles.t || tiles.n < 1 ||
+      (reinterpret_cast<uintptr_t>(X) & 15) != 0)
+    return false;
+  dim3 grid((unsigned)blocks), block(kTileBlock);
+  switch (S) {
+    case 8:
+      hipLaunchKernelGGL((k_spmm_t<8, V, PT, DOT>), grid, block, 0, st, rp, col, val, tiles.t, tiles.n, X, Y, cs);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_spmm_t<16, V, PT, DOT>), grid, block, 0, st, rp, col, val, tiles.t, tiles.n, X, Y, cs);
+      break;
+    case 32:
+      hipLaunchKernelGGL((k_spmm_t<32, V, PT, DOT>), grid, block, 0, st, rp, col, val, tiles.t, tiles.n, X, Y, cs);
+      break;
+    default:
+      hipLaunchKernelGGL((k_spmm_t<64, V, PT, DOT>), grid, block, 0, st, rp, col, val, tiles.t, tiles.n, X, Y, cs);
+      break;
+  }
+  return true;
+}
+
+// variant: 0 lane per column, 1 slice per lane, 2 LDS-staged row tiles, G > 2
+// entry-parallel with G lanes per row, -1 heuristic (entry-parallel up to 32 columns,
+// else one lane per column).
 template <typename V, typename PT, bool DOT>
 static hipError_t spmm_dispatch(const int64_t* rp, const int32_t* col, const V* val, int64_t n, int S,
-                                double mean_row, int variant, const PT* X, double* Y, const CgState& cs,
-                                hipStream_t st, int* nblocks = nullptr) {
+                                double mean_row, int variant, const TileSet& tiles, const PT* X, double* Y,
+                                const CgState& cs, hipStream_t st, int* nblocks = nullptr) {
   const int64_t cap = DOT ? kReduceBlocks : (1 << 20);
   auto grid_for = [&](int64_t rows_per_block) {
     int64_t b = (n + rows_per_block - 1) / rows_per_block;
@@ -323,7 +440,14 @@ static hipError_t spmm_dispatch(const int64_t* rp, const int32_t* col, const V* 
       if (nblocks) *nblocks = (int)sb;
       return hipGetLastError();
     }
-  } else if (G > 1) {
+  } else if (G == 2) {
+    int64_t tb = tiles.n < cap ? tiles.n : cap;
+    tb = round_up8(tb < 1 ? 1 : tb);
+    if (spmm_tiles<V, PT, DOT>(rp, col, val, S, tiles, X, Y, cs, st, tb)) {
+      if (nblocks) *nblocks = (int)tb;
+      return hipGetLastError();
+    }
+  } else if (G > 2) {
     const int64_t eb = grid_for(kBlock / G);
     if (spmm_entry<V, PT, DOT>(G, rp, col, val, n, S, X, Y, cs, st, eb)) {
       if (nblocks) *nblocks = (int)eb;
@@ -338,18 +462,19 @@ static hipError_t spmm_dispatch(const int64_t* rp, const int32_t* col, const V* 
 }
 
 hipError_t launch_spmm(int prec, const int64_t* rp, const int32_t* col, const void* val, int64_t n,
-                       int S, double mean_row, int variant, const double* X, double* Y, hipStream_t st) {
+                       int S, double mean_row, int variant, const TileSet& tiles, const double* X, double* Y,
+                       hipStream_t st) {
   CgState cs{};
   if (prec == GP2S_MIXED)
-    return spmm_dispatch<float, double, false>(rp, col, static_cast<const float*>(val), n, S, mean_row, variant, X,
-                                               Y, cs, st);
-  return spmm_dispatch<double, double, false>(rp, col, static_cast<const double*>(val), n, S, mean_row, variant, X,
-                                              Y, cs, st);
+    return spmm_dispatch<float, double, false>(rp, col, static_cast<const float*>(val), n, S, mean_row, variant,
+                                               tiles, X, Y, cs, st);
+  return spmm_dispatch<double, double, false>(rp, col, static_cast<const double*>(val), n, S, mean_row, variant,
+                                              tiles, X, Y, cs, st);
 }
 
 hipError_t launch_cg_matvec(int prec, const int64_t* rp, const int32_t* col, const void* val,
-                            int64_t n, int S, double mean_row, int variant, const void* P, void* Q, bool f32vec,
-                            const CgState& cs, hipStream_t st) {
+                            int64_t n, int S, double mean_row, int variant, const TileSet& tiles, const void* P,
+                            void* Q, bool f32vec, const CgState& cs, hipStream_t st) {
   int nb = 0;
   hipError_t e;
   if (S == 1) {
@@ -362,13 +487,13 @@ hipError_t launch_cg_matvec(int prec, const int64_t* rp, const int32_t* col, con
                                       static_cast<const double*>(P), static_cast<double*>(Q), cs, st, &nb);
   } else if (prec == GP2S_MIXED) {
     if (f32vec)
-      e = spmm_dispatch<float, float, true>(rp, col, static_cast<const float*>(val), n, S, mean_row, variant,
+      e = spmm_dispatch<float, float, true>(rp, col, static_cast<const float*>(val), n, S, mean_row, variant, tiles,
                                             static_cast<const float*>(P), static_cast<double*>(Q), cs, st, &nb);
     else
-      e = spmm_dispatch<float, double, true>(rp, col, static_cast<const float*>(val), n, S, mean_row, variant,
+      e = spmm_dispatch<float, double, true>(rp, col, static_cast<const float*>(val), n, S, mean_row, variant, tiles,
                                              static_cast<const double*>(P), static_cast<double*>(Q), cs, st, &nb);
   } else {
-    e = spmm_dispatch<double, double, true>(rp, col, static_cast<const double*>(val), n, S, mean_row, variant,
+    e = spmm_dispatch<double, double, true>(rp, col, static_cast<const double*>(val), n, S, mean_row, variant, tiles,
                                             static_cast<const double*>(P), static_cast<double*>(Q), cs, st, &nb);
   }
   if (e != hipSuccess) return e;

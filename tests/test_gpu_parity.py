@@ -133,7 +133,7 @@ def test_lml_and_gradient_same_probe(case, precision):
             assert grad[k] == 0.0
 
 
-BLOCK_VARIANTS = [0, 1, 4, 8, 16]  # lane per column, column slices, 4/8/16 lanes per row
+BLOCK_VARIANTS = [0, 1, 2, 4, 8, 16]  # lane per column, column slices, LDS tiles, 4/8/16 lanes per row
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -152,6 +152,7 @@ def test_block_product_variants(case, precision, nrhs):
                 m.set_block_product(nrhs, v)
             continue
         m.set_block_product(nrhs, v)
+        assert m.block_product(nrhs) == v
         Y = G.gp2s_spmv(m, X).cpu().numpy()
         np.testing.assert_allclose(Y, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max(), err_msg=f"variant {v}")
     with pytest.raises(G.GP2SError):
