@@ -25,7 +25,6 @@ struct gp2s_batch_s {
   int64_t* row_start_d = nullptr;
   int32_t* inst_of_row = nullptr;
   int32_t* blk_inst = nullptr;
-  int32_t* blk_map = nullptr;  // compacted row blocks of the open instances (CG loop)
   int64_t nblk = 0;
   double* centers3_d = nullptr;
   double* weights_d = nullptr;
@@ -49,8 +48,9 @@ struct gp2s_batch_s {
   // tuned launch shapes
   int m_ref = 1, spmv_lanes = 16, spmm_lanes = 64;
   double tune_ms[8] = {};
-  hipStream_t cap_stream = nullptr;
-  hipEvent_t ev = nullptr;
+  hipStream_t cap_stream = nullptr;  // y solves and refinement
+  hipStream_t cap2 = nullptr;        // probe block, beside the y solves
+  int32_t* pin = nullptr;  // pinned poll slots: 4 x (M * S + 8) int32
   std::vector<void*> owned;
 };
 
@@ -201,30 +201,115 @@ gp2s_status assemble_fill(gp2s_batch b, Scratch& sc) {
   return GP2S_OK;
 }
 
-// Batched Jacobi-PCG over M instances x S columns. Iterations run as replays of a
-// captured chunk of `check_every` iterations.
-struct BCgRun {
+// Host copy through pageable memory (any size), ordered on stream `s`.
+gp2s_status bread(gp2s_ctx ctx, hipStream_t s, const void* dev, size_t bytes, void* host) {
+  HIPCHK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return GP2S_OK;
+}
+
+// Makes stream `to` wait for the work queued so far on stream `from`.
+gp2s_status order_after(gp2s_ctx ctx, hipStream_t from, hipStream_t to) {
+  hipEvent_t e = nullptr;
+  HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  hipError_t e1 = hipEventRecord(e, from);
+  hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(to, e, 0) : e1;
+  (void)hipEventDestroy(e);
+  if (e2 != hipSuccess) return fail(ctx, GP2S_E_HIP, "stream ordering: %s", hipGetErrorString(e2));
+  return GP2S_OK;
+}
+
+// Batched Jacobi-PCG over M instances x S columns on its own stream. Iterations run as
+// replays of a captured chunk of `check_every` iterations. After each replay the host
+// queues an asynchronous copy of the done flags into a pinned slot plus an event, and
+// evaluates the copy queued one replay earlier, so the stream never drains while the
+// host polls. When the row blocks of instances with open columns fall to half of those
+// launched, the chunk is captured again over just those blocks (a block map private to
+// this solve), so two solves can run side by side on two streams.
+struct BCg {
+  gp2s_batch b = nullptr;
+  int S = 1;
+  double* X = nullptr;
+  const char* label = "";
+  hipStream_t st = nullptr;
+  int32_t* slots = nullptr;  // two pinned slots of SM + 4 int32
+  // state
   CgState cs{};
-  std::vector<int32_t> iters, done;
+  bool f32vec = false;
+  int SM = 0, max_iter = 0, chunk = 1;
+  double* R = nullptr;
+  void* P = nullptr;
+  void* Q = nullptr;
+  int32_t* si = nullptr;
+  int32_t* iter_dev = nullptr;
+  int32_t* map_d = nullptr;
+  BatchGeom gc{};
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int nq = 0, it = 0;
+  bool open = true;
+  std::vector<int32_t> map, iters, done;
   int total = 0;
   bool converged = false;
+
+  int32_t* slot(int k) const { return slots + (size_t)k * (SM + 4); }
+  ~BCg() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
-gp2s_status run_bcg(gp2s_batch b, int S, const double* B, double* X, const double* tol_dev, double tol, bool keep_hist,
-                    Scratch& sc, BCgRun& out, const char* label) {
+gp2s_status bcg_capture(BCg& c) {
+  gp2s_batch b = c.b;
+  gp2s_ctx ctx = b->ctx;
+  if (c.exec) {
+    (void)hipGraphExecDestroy(c.exec);
+    c.exec = nullptr;
+  }
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(c.st, hipStreamCaptureModeThreadLocal));
+  hipError_t ce = hipSuccess;
+  for (int k = 0; k < c.chunk && ce == hipSuccess; ++k) {
+    ce = launch_bcg_matvec(b->prec, c.gc, b->row_ptr, b->col, b->val, c.S, c.S == 1 ? b->spmv_lanes : b->spmm_lanes,
+                           c.P, c.Q, c.f32vec, c.cs, c.st);
+    if (ce == hipSuccess) ce = launch_bcg_update(c.gc, c.S, c.X, c.R, c.P, c.Q, c.f32vec, b->dinv, c.cs, c.iter_dev, c.st);
+    if (ce == hipSuccess) ce = launch_bcg_pupdate(c.gc, c.S, c.P, c.R, b->dinv, c.f32vec, c.cs, c.iter_dev, c.st);
+  }
+  hipError_t ee = hipStreamEndCapture(c.st, &graph);
+  if (ce != hipSuccess || ee != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(ctx, GP2S_E_HIP, "capturing the CG chunk failed: %s", hipGetErrorString(ce != hipSuccess ? ce : ee));
+  }
+  hipError_t ie = hipGraphInstantiate(&c.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) {
+    c.exec = nullptr;
+    return fail(ctx, GP2S_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+  }
+  return GP2S_OK;
+}
+
+// Workspace, initial state (after the work queued on the context's stream) and the
+// first chunk's graph.
+gp2s_status bcg_begin(BCg& c, const double* B, const double* tol_dev, double tol, bool keep_hist, Scratch& sc) {
+  gp2s_batch b = c.b;
   gp2s_ctx ctx = b->ctx;
   const int64_t n = b->N;
-  const int SM = b->M * S;
-  const bool f32vec = b->prec == GP2S_MIXED && S > 1;
-  const size_t vb = f32vec ? sizeof(float) : sizeof(double);
-  const int max_iter = b->opts.max_iter;
-  double* R = sc.get<double>((size_t)n * S);
-  void* P = sc.get<uint8_t>((size_t)n * S * vb);
-  void* Q = sc.get<double>((size_t)n * S);
+  const int S = c.S;
+  c.SM = b->M * S;
+  const int SM = c.SM;
+  c.f32vec = b->prec == GP2S_MIXED && S > 1;
+  const size_t vb = c.f32vec ? sizeof(float) : sizeof(double);
+  c.max_iter = b->opts.max_iter;
+  c.R = sc.get<double>((size_t)n * S);
+  c.P = sc.get<uint8_t>((size_t)n * S * vb);
+  c.Q = sc.get<double>((size_t)n * S);
   double* sd = sc.get<double>(6 * (size_t)SM + (size_t)b->nblk * S * 2);
-  int32_t* si = sc.get<int32_t>(2 * (size_t)SM + 8);
+  c.si = sc.get<int32_t>(2 * (size_t)SM + 8);
+  c.map_d = sc.get<int32_t>((size_t)b->nblk);
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "batch CG workspace allocation failed");
-  CgState& cs = out.cs;
+  CgState& cs = c.cs;
   cs.rz = sd;
   cs.bb = sd + SM;
   cs.tol2 = sd + 2 * SM;
@@ -232,128 +317,155 @@ gp2s_status run_bcg(gp2s_batch b, int S, const double* B, double* X, const doubl
   cs.beta = sd + 4 * SM;
   cs.rr = sd + 5 * SM;
   cs.partial = sd + 6 * SM;
-  cs.done = si;
-  cs.flags = si + SM;
-  int32_t* iter_dev = si + SM + 4;
-  cs.iters = si + SM + 8;
+  cs.done = c.si;
+  cs.flags = c.si + SM;
+  c.iter_dev = c.si + SM + 4;
+  cs.iters = c.si + SM + 8;
   cs.hist_a = cs.hist_b = nullptr;
   cs.max_hist = 0;
   if (keep_hist) {
-    cs.hist_a = sc.get<double>((size_t)max_iter * SM);
-    cs.hist_b = sc.get<double>((size_t)max_iter * SM);
+    cs.hist_a = sc.get<double>((size_t)c.max_iter * SM);
+    cs.hist_b = sc.get<double>((size_t)c.max_iter * SM);
     if (sc.oom) return fail(ctx, GP2S_E_OOM, "batch CG history allocation failed");
-    cs.max_hist = max_iter;
+    cs.max_hist = c.max_iter;
   }
-  hipStream_t st = ctx->stream;
-  HIPCHK(hipMemsetAsync(si, 0, (2 * (size_t)SM + 8) * sizeof(int32_t), st));
+  HIPCHK(hipEventCreateWithFlags(&c.ev[0], hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&c.ev[1], hipEventDisableTiming));
+  gp2s_status s = order_after(ctx, ctx->stream, c.st);
+  if (s) return s;
+  HIPCHK(hipMemsetAsync(c.si, 0, (2 * (size_t)SM + 8) * sizeof(int32_t), c.st));
   const BatchGeom g = geom(b);
-  HIPCHK(launch_bcg_init(g, S, B, b->dinv, X, R, P, f32vec, cs, tol, st));
+  HIPCHK(launch_bcg_init(g, S, B, b->dinv, c.X, c.R, c.P, c.f32vec, cs, tol, c.st));
   if (tol_dev) {
     // per-column squared tolerances (refinement restarts)
-    HIPCHK(hipMemcpyAsync(cs.tol2, tol_dev, SM * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(cs.tol2, tol_dev, SM * sizeof(double), hipMemcpyDeviceToDevice, c.st));
   }
   std::vector<int32_t> poll(SM + 4);
-  gp2s_status s = readback(ctx, si, (SM + 4) * sizeof(int32_t), poll.data());
+  s = bread(ctx, c.st, c.si, (SM + 4) * sizeof(int32_t), poll.data());
   if (s) return s;
-  if (poll[SM + 2]) return fail(ctx, GP2S_E_NONFINITE, "non-finite right-hand side (%s)", label);
-  auto n_open = [&]() {
-    int o = 0;
-    for (int c = 0; c < SM; ++c) o += poll[c] == 0;
-    return o;
-  };
-  bool open = n_open() > 0;
-  int it = 0;
-  if (open) {
-    // One chunk of iterations is captured on the private stream and replayed. When
-    // the row blocks of the still-open instances fall to half of those launched, the
-    // chunk is captured again over just those blocks (at most log2(blocks) times).
-    const int chunk = std::max(1, std::min(b->opts.check_every, max_iter));
-    HIPCHK(hipEventRecord(b->ev, st));
-    HIPCHK(hipStreamWaitEvent(b->cap_stream, b->ev, 0));
-    struct ExecGuard {
-      hipGraphExec_t e = nullptr;
-      ~ExecGuard() {
-        if (e) (void)hipGraphExecDestroy(e);
-      }
-    } eg;
-    BatchGeom gc = g;
-    std::vector<int32_t> map;
-    auto capture = [&]() -> gp2s_status {
-      if (eg.e) {
-        (void)hipGraphExecDestroy(eg.e);
-        eg.e = nullptr;
-      }
-      hipGraph_t graph = nullptr;
-      HIPCHK(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-      hipError_t ce = hipSuccess;
-      for (int k = 0; k < chunk && ce == hipSuccess; ++k) {
-        ce = launch_bcg_matvec(b->prec, gc, b->row_ptr, b->col, b->val, S, S == 1 ? b->spmv_lanes : b->spmm_lanes, P,
-                               Q, f32vec, cs, b->cap_stream);
-        if (ce == hipSuccess) ce = launch_bcg_update(gc, S, X, R, P, Q, f32vec, b->dinv, cs, iter_dev, b->cap_stream);
-        if (ce == hipSuccess) ce = launch_bcg_pupdate(gc, S, P, R, b->dinv, f32vec, cs, iter_dev, b->cap_stream);
-      }
-      hipError_t ee = hipStreamEndCapture(b->cap_stream, &graph);
-      if (ce != hipSuccess || ee != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return fail(ctx, GP2S_E_HIP, "capturing the CG chunk failed: %s",
-                    hipGetErrorString(ce != hipSuccess ? ce : ee));
-      }
-      hipError_t ie = hipGraphInstantiate(&eg.e, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (ie != hipSuccess) {
-        eg.e = nullptr;
-        return fail(ctx, GP2S_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ie));
-      }
-      return GP2S_OK;
-    };
-    s = capture();
-    if (s) return s;
-    while (open && it < max_iter) {
-      HIPCHK(hipGraphLaunch(eg.e, b->cap_stream));
-      it += chunk;
-      s = readback_on(ctx, b->cap_stream, si, (SM + 4) * sizeof(int32_t), poll.data());
-      if (s) return s;
-      if (poll[SM + 0])
-        return fail(ctx, GP2S_E_NOT_SPD, "CG breakdown in the batched %s (instance %d, column %d)", label,
-                    poll[SM + 3] / S, poll[SM + 3] % S);
-      if (poll[SM + 2]) return fail(ctx, GP2S_E_NONFINITE, "non-finite values during the batched %s", label);
-      open = n_open() > 0;
-      if (ctx->progress) ctx->progress(label, it, n_open(), 0.0, ctx->progress_user);
-      if (!open || it >= max_iter) break;
-      int64_t active = 0;
-      for (int i = 0; i < b->M; ++i) {
-        bool any = false;
-        for (int c = 0; c < S; ++c) any = any || poll[i * S + c] == 0;
-        if (any) active += b->inst_h[i].nblk;
-      }
-      if (2 * active <= gc.grid) {
-        map.clear();
-        for (int i = 0; i < b->M; ++i) {
-          bool any = false;
-          for (int c = 0; c < S; ++c) any = any || poll[i * S + c] == 0;
-          if (any)
-            for (int64_t k = 0; k < b->inst_h[i].nblk; ++k) map.push_back((int32_t)(b->inst_h[i].blk0 + k));
-        }
-        // ordered after the last replay and before the next on the private stream
-        HIPCHK(hipMemcpyAsync(b->blk_map, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                              b->cap_stream));
-        gc.blk_map = b->blk_map;
-        gc.grid = (int64_t)map.size();
-        s = capture();
-        if (s) return s;
-      }
-    }
-    HIPCHK(hipEventRecord(b->ev, b->cap_stream));
-    HIPCHK(hipStreamWaitEvent(st, b->ev, 0));
-  }
-  out.iters.resize(SM);
-  s = readback(ctx, cs.iters, SM * sizeof(int32_t), out.iters.data());
-  if (s) return s;
-  out.done.assign(poll.begin(), poll.begin() + SM);
-  out.total = 0;
-  for (int c = 0; c < SM; ++c) out.total = std::max(out.total, out.iters[c]);
-  out.converged = !open;
+  if (poll[SM + 2]) return fail(ctx, GP2S_E_NONFINITE, "non-finite right-hand side (%s)", c.label);
+  int o = 0;
+  for (int k = 0; k < SM; ++k) o += poll[k] == 0;
+  c.open = o > 0;
+  c.done.assign(poll.begin(), poll.begin() + SM);
+  c.chunk = std::max(1, std::min(b->opts.check_every, c.max_iter));
+  c.gc = g;
+  if (c.open) return bcg_capture(c);
   return GP2S_OK;
+}
+
+// Evaluates a poll copy: errors, open columns, progress, and compaction of the grid.
+gp2s_status bcg_eval(BCg& c, const int32_t* f, int at) {
+  gp2s_batch b = c.b;
+  gp2s_ctx ctx = b->ctx;
+  const int S = c.S, SM = c.SM;
+  if (f[SM + 0])
+    return fail(ctx, GP2S_E_NOT_SPD, "CG breakdown in the batched %s (instance %d, column %d)", c.label,
+                f[SM + 3] / S, f[SM + 3] % S);
+  if (f[SM + 2]) return fail(ctx, GP2S_E_NONFINITE, "non-finite values during the batched %s", c.label);
+  int o = 0;
+  for (int k = 0; k < SM; ++k) o += f[k] == 0;
+  c.open = o > 0;
+  if (ctx->progress) ctx->progress(c.label, at, o, 0.0, ctx->progress_user);
+  if (!c.open || c.it >= c.max_iter) return GP2S_OK;
+  int64_t active = 0;
+  for (int i = 0; i < b->M; ++i) {
+    bool any = false;
+    for (int k = 0; k < S; ++k) any = any || f[i * S + k] == 0;
+    if (any) active += b->inst_h[i].nblk;
+  }
+  if (2 * active > c.gc.grid) return GP2S_OK;
+  c.map.clear();
+  for (int i = 0; i < b->M; ++i) {
+    bool any = false;
+    for (int k = 0; k < S; ++k) any = any || f[i * S + k] == 0;
+    if (any)
+      for (int64_t k = 0; k < b->inst_h[i].nblk; ++k) c.map.push_back((int32_t)(b->inst_h[i].blk0 + k));
+  }
+  // the replay in flight still reads the old map: let it finish first
+  HIPCHK(hipStreamSynchronize(c.st));
+  HIPCHK(hipMemcpyAsync(c.map_d, c.map.data(), c.map.size() * sizeof(int32_t), hipMemcpyHostToDevice, c.st));
+  HIPCHK(hipStreamSynchronize(c.st));
+  c.gc.blk_map = c.map_d;
+  c.gc.grid = (int64_t)c.map.size();
+  return bcg_capture(c);
+}
+
+bool bcg_active(const BCg& c) { return c.open && c.it < c.max_iter; }
+
+// One replay of the chunk, then the lagged poll.
+gp2s_status bcg_step(BCg& c) {
+  gp2s_ctx ctx = c.b->ctx;
+  HIPCHK(hipGraphLaunch(c.exec, c.st));
+  c.it += c.chunk;
+  if (c.nq > 0) {
+    const int k = (c.nq - 1) & 1;
+    HIPCHK(hipEventSynchronize(c.ev[k]));
+    gp2s_status s = bcg_eval(c, c.slot(k), c.it - c.chunk);
+    if (s) return s;
+  }
+  const int k = c.nq & 1;
+  HIPCHK(hipMemcpyAsync(c.slot(k), c.si, (c.SM + 4) * sizeof(int32_t), hipMemcpyDeviceToHost, c.st));
+  HIPCHK(hipEventRecord(c.ev[k], c.st));
+  ++c.nq;
+  return GP2S_OK;
+}
+
+// Final flags and iteration counts; the context's stream then waits for this solve.
+gp2s_status bcg_end(BCg& c) {
+  gp2s_ctx ctx = c.b->ctx;
+  const int SM = c.SM;
+  std::vector<int32_t> f(SM + 4);
+  gp2s_status s = bread(ctx, c.st, c.si, (SM + 4) * sizeof(int32_t), f.data());
+  if (s) return s;
+  if (c.it > 0) {
+    gp2s_progress_fn keep = ctx->progress;
+    ctx->progress = nullptr;
+    s = bcg_eval(c, f.data(), c.it);
+    ctx->progress = keep;
+    if (s) return s;
+  }
+  c.iters.resize(SM);
+  s = bread(ctx, c.st, c.cs.iters, SM * sizeof(int32_t), c.iters.data());
+  if (s) return s;
+  c.done.assign(f.begin(), f.begin() + SM);
+  c.total = 0;
+  for (int k = 0; k < SM; ++k) c.total = std::max(c.total, c.iters[k]);
+  c.converged = !c.open;
+  return order_after(ctx, c.st, ctx->stream);
+}
+
+// Runs one or two batched solves to completion, interleaving their replays.
+gp2s_status bcg_drive(BCg* a, BCg* d) {
+  for (;;) {
+    const bool ra = a && bcg_active(*a), rd = d && bcg_active(*d);
+    if (!ra && !rd) break;
+    for (BCg* c : {a, d}) {
+      if (!c || !bcg_active(*c)) continue;
+      gp2s_status s = bcg_step(*c);
+      if (s) return s;
+    }
+  }
+  for (BCg* c : {a, d}) {
+    if (!c) continue;
+    gp2s_status s = bcg_end(*c);
+    if (s) return s;
+  }
+  return GP2S_OK;
+}
+
+// A single batched solve on the y stream (refinement restarts).
+gp2s_status run_bcg(gp2s_batch b, int S, const double* B, double* X, const double* tol_dev, double tol, bool keep_hist,
+                    Scratch& sc, BCg& c, const char* label) {
+  c.b = b;
+  c.S = S;
+  c.X = X;
+  c.label = label;
+  c.st = b->cap_stream;
+  c.slots = b->pin;
+  gp2s_status s = bcg_begin(c, B, tol_dev, tol, keep_hist, sc);
+  if (s) return s;
+  return bcg_drive(&c, nullptr);
 }
 
 // Time `reps` launches of a CG product with the given lane setting.
@@ -466,7 +578,9 @@ gp2s_status gp2s_batch_plan(gp2s_ctx ctx, int32_t n_inst, const int64_t* n, cons
   }
   hipStream_t sm = ctx->stream;
   HIPCHK(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
-  HIPCHK(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming));
+  HIPCHK(hipStreamCreateWithFlags(&b->cap2, hipStreamNonBlocking));
+  HIPCHK(hipHostMalloc((void**)&b->pin, (2 * ((size_t)n_inst + 4) + 2 * ((size_t)n_inst * S + 4)) * sizeof(int32_t),
+                       hipHostMallocDefault));
   b->x3 = bown<double>(b, (size_t)N * 3);
   b->inst_d = bown<BInst>(b, n_inst);
   b->row_start_d = bown<int64_t>(b, n_inst + 1);
@@ -536,8 +650,6 @@ gp2s_status gp2s_batch_plan(gp2s_ctx ctx, int32_t n_inst, const int64_t* n, cons
     if (m == 1) {
       b->blk_inst = bown<int32_t>(b, b->nblk);
       OOMCHK(b->blk_inst);
-      b->blk_map = bown<int32_t>(b, b->nblk);
-      OOMCHK(b->blk_map);
       std::vector<int32_t> bi(b->nblk);
       for (int i = 0; i < n_inst; ++i)
         for (int64_t k = 0; k < b->inst_h[i].nblk; ++k) bi[b->inst_h[i].blk0 + k] = i;
@@ -656,6 +768,14 @@ gp2s_status gp2s_batch_run(gp2s_batch b, const double* const* y, const gp2s_para
   const int64_t N = b->N;
   const BatchGeom g = geom(b);
   Scratch sc(ctx);
+  // every exit waits for the solve streams before the workspace is released
+  struct StreamsIdle {
+    gp2s_batch b;
+    ~StreamsIdle() {
+      (void)hipStreamSynchronize(b->cap_stream);
+      (void)hipStreamSynchronize(b->cap2);
+    }
+  } idle{b};
   double* yu = sc.get<double>(N);
   double* yi = sc.get<double>(N);
   double* ai = sc.get<double>(N);
@@ -674,21 +794,40 @@ gp2s_status gp2s_batch_run(gp2s_batch b, const double* const* y, const gp2s_para
   // y solves, then refinement restarts for instances above the tolerance
   std::vector<double> bb(M), rr(M), resid(M, 0.0);
   HIPCHK(launch_bseg_reduce(g, 0, yi, nullptr, seg, sm));
-  st = readback(ctx, seg, M * sizeof(double), bb.data());
+  st = bread(ctx, sm, seg, M * sizeof(double), bb.data());
   if (st) return st;
   for (int i = 0; i < M; ++i)
     if (!is_fin(bb[i])) return fail(ctx, GP2S_E_NONFINITE, "y[%d] contains NaN or infinity", i);
-  BCgRun run;
-  st = run_bcg(b, 1, yi, ai, nullptr, b->opts.tol, false, sc, run, "y solve");
+  // The probe block runs on its own stream beside the y solves (both start after the
+  // work queued so far on the context's stream and are joined back into it).
+  HIPCHK(launch_bprobe_masks(g, b->perm, b->opts.seed, S, mask, sm));
+  HIPCHK(launch_probe_rhs(N, S, mask, b->diag, Bp, sm));
+  BCg cy, pr;
+  cy.b = pr.b = b;
+  cy.S = 1;
+  cy.X = ai;
+  cy.label = "y solve";
+  cy.st = b->cap_stream;
+  cy.slots = b->pin;
+  pr.S = S;
+  pr.X = Qs;
+  pr.label = "probe block";
+  pr.st = b->cap2;
+  pr.slots = b->pin + 2 * ((size_t)M + 4);
+  st = bcg_begin(pr, Bp, nullptr, b->opts.probe_tol, true, sc);
+  if (st) return st;
+  st = bcg_begin(cy, yi, nullptr, b->opts.tol, false, sc);
+  if (st) return st;
+  st = bcg_drive(&cy, &pr);
   if (st) return st;
   std::vector<int> iters_y(M, 0), ir(M, 0);
-  for (int i = 0; i < M; ++i) iters_y[i] = run.iters[i];
+  for (int i = 0; i < M; ++i) iters_y[i] = cy.iters[i];
   bool conv = false;
   for (int step = 0;; ++step) {
     HIPCHK(launch_spmv(b->prec, b->row_ptr, b->col, b->val, N, (double)b->nnz / N, ai, kx, sm));
     HIPCHK(launch_axpy_sub(N, yi, kx, r, sm));
     HIPCHK(launch_bseg_reduce(g, 0, r, nullptr, seg, sm));
-    st = readback(ctx, seg, M * sizeof(double), rr.data());
+    st = bread(ctx, sm, seg, M * sizeof(double), rr.data());
     if (st) return st;
     conv = true;
     std::vector<double> tl(M);
@@ -703,18 +842,13 @@ gp2s_status gp2s_batch_run(gp2s_batch b, const double* const* y, const gp2s_para
     for (int i = 0; i < M; ++i)
       if (resid[i] > b->opts.tol) ir[i] += 1;
     HIPCHK(hipMemcpyAsync(tolv, tl.data(), M * sizeof(double), hipMemcpyHostToDevice, sm));
-    BCgRun r2;
+    BCg r2;
     st = run_bcg(b, 1, r, d, tolv, b->opts.tol, false, sc, r2, "refinement solve");
     if (st) return st;
     for (int i = 0; i < M; ++i) iters_y[i] += r2.iters[i];
     HIPCHK(launch_add(N, ai, d, sm));
   }
-  // probes and the quadrature
-  HIPCHK(launch_bprobe_masks(g, b->perm, b->opts.seed, S, mask, sm));
-  HIPCHK(launch_probe_rhs(N, S, mask, b->diag, Bp, sm));
-  BCgRun pr;
-  st = run_bcg(b, S, Bp, Qs, nullptr, b->opts.probe_tol, true, sc, pr, "probe block");
-  if (st) return st;
+  // the quadrature
   const int SM = M * S;
   const int64_t max_m = std::max(1, pr.total);
   double* work = sc.get<double>((size_t)2 * SM * max_m);
@@ -722,13 +856,13 @@ gp2s_status gp2s_batch_run(gp2s_batch b, const double* const* y, const gp2s_para
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "quadrature workspace allocation failed");
   HIPCHK(launch_slq_ws(SM, pr.cs.hist_a, pr.cs.hist_b, pr.cs.iters, work, max_m, quad, sm));
   std::vector<double> qh(SM), sumlog(M), yta(M);
-  st = readback(ctx, quad, SM * sizeof(double), qh.data());
+  st = bread(ctx, sm, quad, SM * sizeof(double), qh.data());
   if (st) return st;
   HIPCHK(launch_bseg_reduce(g, 1, b->diag, nullptr, seg, sm));
-  st = readback(ctx, seg, M * sizeof(double), sumlog.data());
+  st = bread(ctx, sm, seg, M * sizeof(double), sumlog.data());
   if (st) return st;
   HIPCHK(launch_bseg_reduce(g, 0, yi, ai, seg, sm));
-  st = readback(ctx, seg, M * sizeof(double), yta.data());
+  st = bread(ctx, sm, seg, M * sizeof(double), yta.data());
   if (st) return st;
   for (int i = 0; i < M; ++i) {
     double mean = 0.0, var = 0.0;
@@ -794,10 +928,12 @@ gp2s_status gp2s_batch_free(gp2s_batch b) {
   if (b->ctx) {
     (void)hipStreamSynchronize(b->ctx->stream);
     if (b->cap_stream) (void)hipStreamSynchronize(b->cap_stream);
+    if (b->cap2) (void)hipStreamSynchronize(b->cap2);
     for (void* q : b->owned) dfree(b->ctx, q);
   }
-  if (b->ev) (void)hipEventDestroy(b->ev);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->cap2) (void)hipStreamDestroy(b->cap2);
+  if (b->pin) (void)hipHostFree(b->pin);
   delete b;
   return GP2S_OK;
 }
