@@ -13,14 +13,16 @@ computes, written from the paper (arXiv 2512.06143):
 * its exact gradient with respect to the hyperparameters, and the same-probe
   stochastic estimators (Hutchinson trace, probe log-determinant) that the GPU
   path approximates with conjugate gradients and Lanczos quadrature;
-* the counter-based SplitMix64 probe signs.
+* the counter-based SplitMix64 probe signs;
+* the posterior mean and variance of the latent function at test points (Sec. 2,
+  Eq. posterior).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package. The product library never calls it, and it
 shares no code with the HIP path.
 
-Every function documents the passage it follows. Readings of the paper where it is
-silent or garbled are listed in ``readings.py``.
+Every function documents the passage it follows, and states the reading it takes
+where the paper is silent or garbled.
 """
 from .kernel import (wendland_c2, wendland_c2_dr, wendland_c6, bump_values,
                      kernel_params_check)
@@ -30,6 +32,7 @@ from .dense import covariance_dense, dcov_dense, lml_dense, grad_exact, LMLResul
 from .probes import splitmix64, rademacher_probes, probe_sign_masks
 from .estimators import logdet_same_probe, grad_same_probe, lml_same_probe, hutchinson_variance
 from .sparse import covariance_csr, covariance_rows, residual_rel, pcg_jacobi
+from .posterior import cross_covariance, posterior_dense
 
 __all__ = [
     "wendland_c2", "wendland_c2_dr", "wendland_c6", "bump_values", "kernel_params_check",
@@ -38,5 +41,6 @@ __all__ = [
     "covariance_dense", "dcov_dense", "lml_dense", "grad_exact", "LMLResult",
     "splitmix64", "rademacher_probes", "probe_sign_masks",
     "logdet_same_probe", "grad_same_probe", "lml_same_probe", "hutchinson_variance",
+    "cross_covariance", "posterior_dense",
     "covariance_csr", "covariance_rows", "residual_rel", "pcg_jacobi",
 ]
