@@ -232,6 +232,31 @@ gp2s_status gp2s_lml(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_so
 gp2s_status gp2s_lml_grad(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_solve_opts* opts,
                           double* a, gp2s_report* report, double* grad);
 
+/* ---- posterior at test points ------------------------------------------------------
+ * Posterior mean and variance of the latent function f at n_test test points x*
+ * (Sec. 2, Eq. posterior, zero prior mean):
+ *   mean_t = k(X, x*_t)^T a,   a = K^{-1} y as returned by gp2s_solve / gp2s_lml,
+ *   var_t  = g(x*_t)^2 - k(X, x*_t)^T K^{-1} k(X, x*_t),
+ * with k the noise-free kernel of the handle (k(x*, x*) = g(x*)^2; the noise belongs to
+ * the observations, so a test point equal to a training point gets none). The
+ * cross-covariance uses the training pattern (||x* - x_j|| < r, both points inside
+ * some bump) and the handle's storage precision. The variance solves K v_t =
+ * k(X, x*_t) with Jacobi-PCG, 64 test points per block, to the relative residual
+ * opts->tol within opts->max_iter iterations (opts->n_probes is not used).
+ *   x_test: DEVICE [n_test * dim] float64, row-major; a: DEVICE [n] float64, user order;
+ *   mean: DEVICE [n_test] float64 (test order); var: DEVICE [n_test] float64, or NULL to
+ *   skip the variance; report: HOST, may be NULL.
+ * Requires a handle from gp2s_assemble. Non-finite test coordinates give
+ * GP2S_E_NONFINITE; a variance block that misses the tolerance gives GP2S_E_NOCONV
+ * with every output written. */
+typedef struct {
+  int64_t nnz_cross;    /* stored entries of k(X, x*) over all test points */
+  int32_t var_blocks;   /* block solves run for the variance */
+  int32_t var_iters;    /* most CG iterations of any block */
+} gp2s_predict_report;
+gp2s_status gp2s_predict(gp2s_ctx ctx, gp2s_matrix m, int64_t n_test, const double* x_test, const double* a,
+                         const gp2s_solve_opts* opts, double* mean, double* var, gp2s_predict_report* report);
+
 /* ---- batched instances -------------------------------------------------------------
  * Many independent instances (each its own points, dimension, targets and
  * hyperparameters; Sec. 2 per instance) evaluated together: one block-diagonal system

@@ -38,9 +38,13 @@ def cross_covariance(x_test, x, radius, bump_width, centers, weights):
     return np.where(keep, gs[:, None] * g[None, :] * wendland_c2(rho), 0.0), gs
 
 
-def posterior_dense(x, y, x_test, radius, bump_width, centers, weights, noise_var):
-    """(mean, var, a) at the test points, by Cholesky of the dense training K."""
-    K = covariance_dense(x, radius, bump_width, centers, weights, noise_var)
+def posterior_dense(x, y, x_test, radius, bump_width, centers, weights, noise_var, K=None):
+    """(mean, var, a) at the test points, by Cholesky of the dense training K.
+
+    K may be given (for instance the matrix a device path stored, in user order);
+    otherwise it is built from the points."""
+    if K is None:
+        K = covariance_dense(x, radius, bump_width, centers, weights, noise_var)
     Ks, gs = cross_covariance(x_test, x, radius, bump_width, centers, weights)
     c = scipy.linalg.cho_factor(K, lower=True)
     a = scipy.linalg.cho_solve(c, np.asarray(y, dtype=np.float64))

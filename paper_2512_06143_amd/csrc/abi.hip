@@ -1120,4 +1120,100 @@ gp2s_status gp2s_lml_grad(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp
   return lml_common(ctx, m, y, o, a, rep, grad);
 }
 
+gp2s_status gp2s_predict(gp2s_ctx ctx, gp2s_matrix m, int64_t n_test, const double* x_test, const double* a,
+                         const gp2s_solve_opts* o, double* mean, double* var, gp2s_predict_report* rep) {
+  if (!ctx) return GP2S_E_INVALID;
+  gp2s_status st = check_matrix(ctx, m);
+  if (st) return st;
+  if (!m->assembled)
+    return fail(ctx, GP2S_E_INVALID, "prediction needs a handle from gp2s_assemble (imported CSR has no kernel)");
+  st = check_opts(ctx, o, false);
+  if (st) return st;
+  if (n_test < 0 || n_test >= (int64_t)INT32_MAX) return fail(ctx, GP2S_E_INVALID, "n_test must be in [0, 2^31)");
+  if (n_test > 0 && (!x_test || !a || !mean)) return fail(ctx, GP2S_E_INVALID, "x_test, a and mean must be non-NULL");
+  constexpr int kVarBlock = 64;
+  if (var && (int64_t)m->n * kVarBlock >= (int64_t)INT32_MAX)
+    return fail(ctx, GP2S_E_INVALID, "n * 64 must be below 2^31 for the variance blocks");
+  if (rep) std::memset(rep, 0, sizeof(*rep));
+  if (n_test == 0) return GP2S_OK;
+  st = ensure_device(ctx);
+  if (st) return st;
+  const int64_t n = m->n, nt = n_test;
+  const bool f32 = m->prec == GP2S_MIXED;
+  hipStream_t sm = ctx->stream;
+  Scratch sc(ctx);
+  float4* t32 = f32 ? sc.get<float4>(nt) : nullptr;
+  double4* t64 = f32 ? nullptr : sc.get<double4>(nt);
+  double* g64t = sc.get<double>(nt);
+  int32_t* tbin = sc.get<int32_t>(nt);
+  int32_t* flag = sc.get<int32_t>(1);
+  int32_t* row_cnt = sc.get<int32_t>(nt);
+  int64_t* rp = sc.get<int64_t>(nt + 1);
+  void* scan_ws = sc.get<uint8_t>(scan_workspace_bytes(nt));
+  double* ai = sc.get<double>(n);
+  if (sc.oom) return fail(ctx, GP2S_E_OOM, "prediction workspace allocation failed");
+  // test-point prologue on the training grid
+  HIPCHK(hipMemsetAsync(flag, 0, sizeof(int32_t), sm));
+  HIPCHK(launch_test_prologue(x_test, nt, m->grid, m->centers_d, m->weights_d, m->P, m->bump_width * m->bump_width,
+                              t32, t64, g64t, tbin, flag, sm));
+  int32_t nf = 0;
+  st = readback(ctx, flag, sizeof(int32_t), &nf);
+  if (st) return st;
+  if (nf) return fail(ctx, GP2S_E_NONFINITE, "x_test contains NaN or infinity");
+  // cross-covariance k(x*, X): count, scan, fill
+  CrossArgs ca{};
+  ca.test32 = t32;
+  ca.test64 = t64;
+  ca.test_bin = tbin;
+  ca.nt = nt;
+  ca.pts32 = m->pts32;
+  ca.pts64 = m->pts64;
+  ca.bin_start = m->bin_start;
+  ca.grid = m->grid;
+  ca.r2 = m->radius * m->radius;
+  ca.inv_r2 = 1.0 / ca.r2;
+  ca.r2f = (float)ca.r2;
+  HIPCHK(launch_cross_count(ca, m->prec, row_cnt, sm));
+  HIPCHK(launch_exscan_i32_i64(row_cnt, rp, nt, scan_ws, sm));
+  int64_t nnz = 0;
+  st = readback(ctx, rp + nt, sizeof(int64_t), &nnz);
+  if (st) return st;
+  int32_t* ccol = sc.get<int32_t>(std::max<int64_t>(nnz, 1));
+  void* cval = sc.get<uint8_t>((size_t)std::max<int64_t>(nnz, 1) * (f32 ? sizeof(float) : sizeof(double)));
+  if (sc.oom) return fail(ctx, GP2S_E_OOM, "cross-covariance allocation failed (%lld entries)", (long long)nnz);
+  HIPCHK(launch_cross_fill(ca, m->prec, rp, ccol, cval, sm));
+  // mean = K* a (a gathered into internal order)
+  HIPCHK(launch_gather_rows(n, 1, m->perm, a, ai, sm));
+  HIPCHK(launch_spmv(m->prec, rp, ccol, cval, nt, nnz > 0 ? (double)nnz / (double)nt : 1.0, ai, mean, sm));
+  int32_t blocks = 0, worst = 0;
+  bool conv = true;
+  if (var) {
+    double* B = sc.get<double>((size_t)n * kVarBlock);
+    double* Vs = sc.get<double>((size_t)n * kVarBlock);
+    double* csc = sc.get<double>(kVarBlock);
+    if (sc.oom) return fail(ctx, GP2S_E_OOM, "variance block allocation failed");
+    for (int64_t t0 = 0; t0 < nt; t0 += kVarBlock) {
+      const int S = (int)std::min<int64_t>(kVarBlock, nt - t0);
+      HIPCHK(hipMemsetAsync(B, 0, (size_t)n * S * sizeof(double), sm));
+      HIPCHK(launch_cross_block(m->prec, rp, ccol, cval, t0, S, B, csc, sm));
+      Scratch scb(ctx);  // the block solve's workspace is released per block
+      CgRun run;
+      st = run_cg(ctx, m, S, B, Vs, o->tol, o->max_iter, o->check_every, false, scb, run, "variance block");
+      if (st) return st;
+      HIPCHK(launch_cross_var(m->prec, rp, ccol, cval, t0, S, Vs, csc, g64t, var, sm));
+      ++blocks;
+      worst = std::max(worst, run.total_iters);
+      conv = conv && run.converged;
+    }
+  }
+  HIPCHK(hipStreamSynchronize(sm));
+  if (rep) {
+    rep->nnz_cross = nnz;
+    rep->var_blocks = blocks;
+    rep->var_iters = worst;
+  }
+  if (!conv) return fail(ctx, GP2S_E_NOCONV, "a variance block did not converge within max_iter");
+  return GP2S_OK;
+}
+
 }  // extern "C"

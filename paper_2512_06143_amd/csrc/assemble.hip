@@ -17,83 +17,9 @@
 // float64 squared distance (exact for float32 coordinates) to form t = 1 - rho^2
 // without cancellation, then 1 - rho = t / (1 + rho) and the polynomial in float32.
 #include "gp2s_internal.h"
+#include "pair.h"
 
 namespace gp2s {
-
-// Workgroups are dispatched round-robin over the 8 XCDs; remap so that consecutive
-// rows (which share neighbour bins) land on the same XCD and its L2.
-__device__ inline int64_t xcd_block(int64_t nblocks_padded) {
-  int64_t b = blockIdx.x;
-  int64_t per = nblocks_padded / 8;
-  return (b % 8) * per + b / 8;
-}
-
-__device__ inline uint32_t lane_prefix(uint64_t m) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-template <int DIM>
-__device__ inline void decode_bin(int32_t b, const GridDev& g, int& bx, int& by, int& bz) {
-  bx = b % g.nb[0];
-  int t = b / g.nb[0];
-  if (DIM == 3) {
-    by = t % g.nb[1];
-    bz = t / g.nb[1];
-  } else {
-    by = t;
-    bz = 0;
-  }
-}
-
-// Squared distances for the support test. Explicit rounding intrinsics fix the
-// evaluation order, so the count pass and the fill pass (separate instantiations)
-// take bitwise the same decision, and K stays symmetric: swapping i and j only
-// negates the differences.
-template <int DIM>
-__device__ inline float sqdist_f32(const float4& a, const float4& b) {
-  const float dx = a.x - b.x, dy = a.y - b.y;
-  float d2 = __fmaf_rn(dy, dy, __fmul_rn(dx, dx));
-  if (DIM == 3) {
-    const float dz = a.z - b.z;
-    d2 = __fmaf_rn(dz, dz, d2);
-  }
-  return d2;
-}
-template <int DIM>
-__device__ inline double sqdist_f64(const double4& a, const double4& b) {
-  const double dx = a.x - b.x, dy = a.y - b.y;
-  double d2 = __fma_rn(dy, dy, __dmul_rn(dx, dx));
-  if (DIM == 3) {
-    const double dz = a.z - b.z;
-    d2 = __fma_rn(dz, dz, d2);
-  }
-  return d2;
-}
-
-// Float32 entry value for a surviving off-diagonal pair.
-__device__ inline float entry_f32(const float4& pi, const float4& pj, double r2, double inv_r2) {
-  double dx = (double)pi.x - (double)pj.x;
-  double dy = (double)pi.y - (double)pj.y;
-  double dz = (double)pi.z - (double)pj.z;
-  double d2 = dx * dx + dy * dy + dz * dz;
-  float t = (float)((r2 - d2) * inv_r2);          // 1 - rho^2, accurate near rho -> 1
-  t = fmaxf(t, 0.0f);
-  float rho = __builtin_amdgcn_sqrtf((float)(d2 * inv_r2));
-  float om = t * __builtin_amdgcn_rcpf(1.0f + rho);  // 1 - rho
-  float om2 = om * om;
-  return pi.w * pj.w * (om2 * om2 * (4.0f * rho + 1.0f));
-}
-
-__device__ inline double entry_f64(const double4& pi, const double4& pj, double r2, double inv_r2) {
-  double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
-  double d2 = dx * dx + dy * dy + dz * dz;
-  double t = fmax((r2 - d2) * inv_r2, 0.0);
-  double rho = sqrt(d2 * inv_r2);
-  double om = t / (1.0 + rho);
-  double om2 = om * om;
-  return pi.w * pj.w * (om2 * om2 * (4.0 * rho + 1.0));
-}
 
 template <int DIM, bool FILL, bool F32>
 __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs a, int64_t nblocks_padded,

@@ -179,6 +179,30 @@ hipError_t launch_assemble_count(const AssembleArgs& a, int prec, int32_t* row_c
 hipError_t launch_assemble_fill(const AssembleArgs& a, int prec, const int64_t* row_ptr,
                                 int32_t* col, void* val, double* diag, hipStream_t st);
 
+// predict.hip: cross-covariance of test points with the training points
+struct CrossArgs {
+  const float4* test32;   // test points (float32 path) or null
+  const double4* test64;  // test points (float64 path) or null
+  const int32_t* test_bin;
+  int64_t nt;
+  const float4* pts32;  // training points, internal order
+  const double4* pts64;
+  const int64_t* bin_start;
+  GridDev grid;
+  double r2, inv_r2;
+  float r2f;
+};
+hipError_t launch_test_prologue(const double* x, int64_t nt, const GridDev& g, const double* centers,
+                                const double* weights, int P, double bump_w2, float4* pts32, double4* pts64,
+                                double* g64, int32_t* bin, int32_t* nonfinite, hipStream_t st);
+hipError_t launch_cross_count(const CrossArgs& a, int prec, int32_t* row_cnt, hipStream_t st);
+hipError_t launch_cross_fill(const CrossArgs& a, int prec, const int64_t* row_ptr, int32_t* col, void* val,
+                             hipStream_t st);
+hipError_t launch_cross_block(int prec, const int64_t* rp, const int32_t* col, const void* val, int64_t t0, int S,
+                              double* B, double* cs, hipStream_t st);
+hipError_t launch_cross_var(int prec, const int64_t* rp, const int32_t* col, const void* val, int64_t t0, int S,
+                            const double* Vs, const double* cs, const double* g64t, double* var, hipStream_t st);
+
 // spmv.hip
 hipError_t launch_spmv(int prec, const int64_t* rp, const int32_t* col, const void* val,
                        int64_t n, double mean_row, const double* x, double* y, hipStream_t st);

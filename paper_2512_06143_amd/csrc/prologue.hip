@@ -6,6 +6,7 @@
 // therefore sorted into bins of side >= r so that each row only tests the points of
 // its 3^d neighbouring bins.
 #include "gp2s_internal.h"
+#include "pair.h"
 
 namespace gp2s {
 
@@ -57,11 +58,6 @@ hipError_t launch_bbox(const double* x, int64_t n, int dim, double* part, int32_
   return hipGetLastError();
 }
 
-__device__ inline int32_t bin_coord(double v, double o, double inv_h, int32_t nb) {
-  double f = floor((v - o) * inv_h);
-  int32_t c = (int32_t)fmax(0.0, fmin(f, (double)(nb - 1)));
-  return c;
-}
 
 // Bin index, bump mask g (float64) and support flag gamma of every point (user order).
 // g_i = sum_k a_k exp(1 - 1/(1 - s_ik)), s_ik = ||x_i - c_k||^2 / w^2, for s_ik < 1
@@ -80,22 +76,10 @@ __global__ __launch_bounds__(kBlock) void k_prologue(const double* __restrict__ 
   const int dim = g.dim;
   double xi[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < dim; ++k) xi[k] = x[i * dim + k];
-  int64_t b = 0;
-  for (int k = dim - 1; k >= 0; --k) b = b * g.nb[k] + bin_coord(xi[k], g.origin[k], g.inv_h, g.nb[k]);
+  const int64_t b = bin_index(xi, g);
   double gsum = 0.0;
   bool inside = false;
-  for (int p = 0; p < P; ++p) {
-    double d2 = 0.0;
-    for (int k = 0; k < dim; ++k) {
-      double d = xi[k] - centers[p * dim + k];
-      d2 += d * d;
-    }
-    if (d2 < bump_w2) {
-      inside = true;
-      double s = d2 / bump_w2;
-      gsum += weights[p] * exp(1.0 - 1.0 / (1.0 - s));
-    }
-  }
+  bump_mask(xi, dim, centers, weights, P, bump_w2, gsum, inside);
   bin_of[i] = (int32_t)b;
   slot[i] = atomicAdd(&bin_count[b], 1);
   g64_user[i] = inside ? gsum : 0.0;

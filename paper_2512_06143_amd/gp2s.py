@@ -67,6 +67,13 @@ class Report(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class PredictReport(ctypes.Structure):
+    _fields_ = [("nnz_cross", ctypes.c_int64), ("var_blocks", ctypes.c_int32), ("var_iters", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
 _SIGS = {
     "gp2s_abi_version": (_i32, []),
@@ -91,6 +98,8 @@ _SIGS = {
     "gp2s_lml": (_i32, [_vp, _vp, _vp, ctypes.POINTER(SolveOpts), _vp, ctypes.POINTER(Report)]),
     "gp2s_lml_grad": (_i32, [_vp, _vp, _vp, ctypes.POINTER(SolveOpts), _vp, ctypes.POINTER(Report),
                              ctypes.POINTER(ctypes.c_double)]),
+    "gp2s_predict": (_i32, [_vp, _vp, _i64, _vp, _vp, ctypes.POINTER(SolveOpts), _vp, _vp,
+                            ctypes.POINTER(PredictReport)]),
     "gp2s_batch_plan": (_i32, [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_vp), ctypes.POINTER(Params), _i32,
                                ctypes.POINTER(SolveOpts), ctypes.POINTER(_vp)]),
     "gp2s_batch_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
@@ -328,6 +337,22 @@ def gp2s_solve(m: Matrix, y, opts: SolveOpts | None = None, allow_noconv=False):
     st = lib.gp2s_solve(ctx.ptr, m.handle, _ptr(yd), _ptr(a), ctypes.byref(o), ctypes.byref(rep))
     rep.status = ctx.check(st, allow_noconv)
     return a, rep
+
+
+def gp2s_predict(m: Matrix, x_test, a, opts: SolveOpts | None = None, want_var=True, allow_noconv=False):
+    """Posterior mean (and variance) of the latent function at the rows of x_test, given
+    a = K^-1 y from gp2s_solve / gp2s_lml. Returns (mean, var or None, report)."""
+    ctx = m.ctx
+    xd = _as_dev64(x_test, ctx)
+    nt = int(xd.shape[0]) if xd.dim() > 1 else 0
+    ad = _as_dev64(a, ctx)
+    mean = ctx._torch.empty(nt, dtype=ctx._torch.float64, device=ad.device)
+    var = ctx._torch.empty(nt, dtype=ctx._torch.float64, device=ad.device) if want_var else None
+    rep = PredictReport()
+    o = opts or default_opts()
+    rep.status = ctx.check(lib.gp2s_predict(ctx.ptr, m.handle, nt, _ptr(xd), _ptr(ad), ctypes.byref(o), _ptr(mean),
+                                            _ptr(var), ctypes.byref(rep)), allow_noconv)
+    return mean, var, rep
 
 
 def gp2s_lml(m: Matrix, y, opts: SolveOpts | None = None, want_a=True, allow_noconv=False):

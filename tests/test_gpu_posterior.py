@@ -1,0 +1,114 @@
+"""Posterior mean and variance at test points (Sec. 2, Eq. posterior) through the C ABI,
+against the dense oracle on the same training matrix.
+
+The oracle solves with the matrix the device stored (exported CSR, user order), so
+the mixed path is compared with its own float32-rounded K. Remaining differences:
+the device's a (CG to 1e-12 relative residual), the variance solves (CG to 1e-10)
+and, in the mixed path, the float32 cross-covariance entries, which carry the same
+per-entry bar as the stored K (1e-5 relative). Hence |d mean_t| <= tol_m * sum_j
+|k_tj a_j| and |d var_t| <= tol_v * g(x*_t)^2 (+1e-14 absolute), where k^T K^{-1} k <=
+g^2 bounds the quadratic form: tol_m = 1e-5, tol_v = 2e-5 (mixed: one and two
+perturbed factors) or 1e-9 (float64). The number of stored cross entries equals the oracle's pattern up
+to pairs within 1e-6 of the support boundary.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import exported_user_csr, params_of
+
+pytestmark = pytest.mark.gpu
+
+
+def _G():
+    import paper_2512_06143_amd as G
+    return G
+
+
+CASES = {
+    "c1": lambda: workloads.make_problem("c1"),
+    "gmm3d": lambda: workloads.make_random_problem(31, 3001, 3, 0.09, n_bumps=5, bump_width=0.45, points="gmm"),
+    "ragged2d": lambda: workloads.make_random_problem(32, 1237, 2, 0.07, n_bumps=3, bump_width=0.35),
+}
+
+
+def _test_points(prob, seed=0):
+    """Uniform points over the bounding box widened by 10% (some outside it), copies of
+    training points, and points far outside the data."""
+    rng = np.random.default_rng(seed)
+    lo, hi = prob.x.min(0), prob.x.max(0)
+    w = hi - lo
+    u = lo - 0.1 * w + 1.2 * w * rng.random((150, prob.dim))
+    dup = prob.x[rng.choice(prob.n, 20, replace=False)]
+    far = hi + 3.0 * prob.radius + rng.random((3, prob.dim))
+    return workloads.f32(np.vstack([u, dup, far]))
+
+
+def _near_boundary(prob, xt):
+    d2 = oracle.pairwise_sqdist(xt, prob.x) / prob.radius ** 2
+    return int(np.count_nonzero(np.abs(d2 - 1.0) <= 1e-6))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_posterior_matches_oracle(gpu, name, precision):
+    G = _G()
+    prob = CASES[name]()
+    m = G.gp2s_assemble(prob.x, params_of(prob), precision)
+    Kd = exported_user_csr(m)[0].toarray()
+    a, _ = G.gp2s_solve(m, prob.y, G.default_opts(tol=1e-12, max_iter=100000))
+    xt = _test_points(prob)
+    mean, var, rep = G.gp2s_predict(m, xt, a, G.default_opts(tol=1e-10, max_iter=100000))
+    mean, var = mean.cpu().numpy(), var.cpu().numpy()
+    mref, vref, aref = oracle.posterior_dense(prob.x, prob.y, xt, prob.radius, prob.bump_width, prob.centers,
+                                             prob.weights, prob.noise_var, K=Kd)
+    Ks, gs = oracle.cross_covariance(xt, prob.x, prob.radius, prob.bump_width, prob.centers, prob.weights)
+    tol_m, tol_v = (1e-5, 2e-5) if precision == "mixed" else (1e-9, 1e-9)
+    scale_m = np.abs(Ks) @ np.abs(aref)
+    err_m = np.abs(mean - mref)
+    err_v = np.abs(var - vref)
+    print(f"[{name}/{precision}] n_test={len(xt)} nnz_cross={rep.nnz_cross} blocks={rep.var_blocks} "
+          f"iters={rep.var_iters} max mean err/scale={np.max((err_m / np.maximum(scale_m, 1e-300))[scale_m > 1e-9]):.2e} "
+          f"max var err/g2={np.max((err_v / np.maximum(gs ** 2, 1e-300))[gs ** 2 > 1e-9]):.2e}", flush=True)
+    assert np.all(err_m <= tol_m * scale_m + 1e-14)
+    assert np.all(err_v <= tol_v * gs ** 2 + 1e-14)
+    # structural pattern (entries can be explicit zeros where a bump value underflows)
+    _, _, gams = oracle.bump_values(xt, prob.centers, prob.bump_width, prob.weights)
+    _, _, gam = oracle.bump_values(prob.x, prob.centers, prob.bump_width, prob.weights)
+    d2 = oracle.pairwise_sqdist(xt, prob.x)
+    n_ref = int(np.count_nonzero((d2 < prob.radius ** 2) & gams[:, None] & gam[None, :]))
+    assert rep.nnz_cross == pytest.approx(n_ref, abs=_near_boundary(prob, xt))
+    assert rep.var_blocks == (len(xt) + 63) // 64
+    # points outside every bump and far from the data: exactly zero
+    far = gs == 0.0
+    assert np.all(mean[far] == 0.0) and np.all(var[far] == 0.0)
+    m.free()
+
+
+def test_posterior_mean_only_and_edges(gpu):
+    G = _G()
+    prob = workloads.make_random_problem(5, 900, 2, 0.08, n_bumps=3, bump_width=0.5)
+    m = G.gp2s_assemble(prob.x, params_of(prob), "fp64")
+    a, _ = G.gp2s_solve(m, prob.y, G.default_opts(tol=1e-12))
+    xt = _test_points(prob, seed=2)
+    mean, var, rep = G.gp2s_predict(m, xt, a, want_var=False)
+    assert var is None and rep.var_blocks == 0
+    mean2, _, _ = G.gp2s_predict(m, xt, a)
+    assert np.array_equal(mean.cpu().numpy(), mean2.cpu().numpy())
+    # no test points
+    mean0, var0, rep0 = G.gp2s_predict(m, np.zeros((0, 2)), a)
+    assert mean0.numel() == 0 and rep0.nnz_cross == 0
+    # non-finite coordinates are rejected
+    bad = xt.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(G.GP2SError) as e:
+        G.gp2s_predict(m, bad, a)
+    assert e.value.status == 7
+    # an imported matrix has no kernel to evaluate at test points
+    Kg, _ = exported_user_csr(m)
+    mi = G.gp2s_matrix_import(Kg.indptr, Kg.indices, Kg.data, "fp64")
+    with pytest.raises(G.GP2SError) as e:
+        G.gp2s_predict(mi, xt, a)
+    assert e.value.status == 1
+    m.free()
