@@ -162,6 +162,37 @@ def cpu_baseline(prob, nnz_full, iters_y, iters_probe, S, budget_points=250_000,
     }
 
 
+def bench_posterior(G, x, y, params, precision, prob, n_mean=100_000, n_var=64):
+    """Posterior at test points (outside the timed step): the mean at n_mean uniform
+    points over the data's box (cross-covariance assembly + one SpMV) and the variance
+    at n_var of them (one 64-column block solve)."""
+    import numpy as np
+    import torch
+    import workloads
+    m = G.gp2s_assemble(x, params, precision)
+    a, _ = G.gp2s_solve(m, y)
+    rng = np.random.default_rng(77)
+    lo, hi = prob.x.min(0), prob.x.max(0)
+    xt = torch.as_tensor(workloads.f32(lo + (hi - lo) * rng.random((n_mean, prob.dim)))).cuda()
+    G.gp2s_predict(m, xt[:1000], a, want_var=False)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mean, _, rep = G.gp2s_predict(m, xt, a, want_var=False)
+    torch.cuda.synchronize()
+    t_mean = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, var, rep_v = G.gp2s_predict(m, xt[:n_var], a, allow_noconv=True)
+    torch.cuda.synchronize()
+    t_var = time.perf_counter() - t0
+    m.free()
+    res = {"test_points": n_mean, "cross_nnz": int(rep.nnz_cross), "mean_s": t_mean,
+           "mean_points_per_s": n_mean / t_mean, "var_points": n_var, "var_s": t_var,
+           "var_iters": int(rep_v.var_iters), "var_blocks": int(rep_v.var_blocks)}
+    log(f"[bench] posterior: mean at {n_mean} points {t_mean * 1e3:.2f} ms ({rep.nnz_cross} cross entries); "
+        f"variance at {n_var} points {t_var:.2f} s ({rep_v.var_iters} CG iterations)")
+    return res
+
+
 def bench_batch(args):
     """64 independent instances (c5) planned once, then evaluated together per step:
     reassembly with the step's hyperparameters, y solves, probe solves, log-dets, LMLs
@@ -226,6 +257,7 @@ def main():
     ap.add_argument("--probe-tol", type=float, default=1e-5)
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64-plain comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-predict", action="store_true", help="skip the posterior (test-point) measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -344,6 +376,8 @@ def main():
         out["fp64_iters"] = [rep64.iters, rep64.probe_iters]
         out["fp64_lml"] = rep64.lml
         log(f"[bench] fp64 plain: {t64:.2f}s iters y={rep64.iters} probes={rep64.probe_iters} lml={rep64.lml:.6f}")
+    if not args.no_predict:
+        out["posterior"] = bench_posterior(G, x, y, params, args.precision, prob)
     if not args.no_cpu:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(prob, nnz, rep.iters, rep.probe_iters, S)
