@@ -24,8 +24,8 @@ shares no code with the HIP path.
 Every function documents the passage it follows, and states the reading it takes
 where the paper is silent or garbled.
 """
-from .kernel import (wendland_c2, wendland_c2_dr, wendland_c6, bump_values,
-                     kernel_params_check)
+from .kernel import (wendland_c2, wendland_c2_dr, wendland_c6, wendland_c6_dr, wendland, wendland_dr,
+                     KERNELS, bump_values, kernel_params_check)
 from .pattern import (pairwise_sqdist, pattern_bruteforce, pattern_kdtree, mean_row_count,
                       boundary_exempt_pairs, boundary_exempt_points)
 from .dense import covariance_dense, dcov_dense, lml_dense, grad_exact, LMLResult
@@ -35,7 +35,8 @@ from .sparse import covariance_csr, covariance_rows, residual_rel, pcg_jacobi
 from .posterior import cross_covariance, posterior_dense
 
 __all__ = [
-    "wendland_c2", "wendland_c2_dr", "wendland_c6", "bump_values", "kernel_params_check",
+    "wendland_c2", "wendland_c2_dr", "wendland_c6", "wendland_c6_dr", "wendland", "wendland_dr", "KERNELS",
+    "bump_values", "kernel_params_check",
     "pairwise_sqdist", "pattern_bruteforce", "pattern_kdtree", "mean_row_count",
     "boundary_exempt_pairs", "boundary_exempt_points",
     "covariance_dense", "dcov_dense", "lml_dense", "grad_exact", "LMLResult",

@@ -19,7 +19,7 @@ from dataclasses import dataclass
 import numpy as np
 import scipy.linalg
 
-from .kernel import bump_values, wendland_c2, wendland_c2_dr
+from .kernel import bump_values, wendland, wendland_dr
 
 
 def _pattern_mask(d2, radius, gamma):
@@ -28,8 +28,9 @@ def _pattern_mask(d2, radius, gamma):
     return keep
 
 
-def covariance_dense(x, radius, bump_width, centers, weights, noise_var, return_parts=False):
-    """Dense K (n x n, float64) on the structural pattern of oracle.pattern."""
+def covariance_dense(x, radius, bump_width, centers, weights, noise_var, return_parts=False, kernel="c2"):
+    """Dense K (n x n, float64) on the structural pattern of oracle.pattern; `kernel`
+    selects the Wendland member (oracle.kernel.wendland)."""
     from .pattern import pairwise_sqdist
 
     x = np.asarray(x, dtype=np.float64)
@@ -37,7 +38,7 @@ def covariance_dense(x, radius, bump_width, centers, weights, noise_var, return_
     d2 = pairwise_sqdist(x, x)
     keep = _pattern_mask(d2, radius, gamma)
     rho = np.sqrt(d2) / float(radius)
-    W = np.where(keep, wendland_c2(rho), 0.0)
+    W = np.where(keep, wendland(rho, kernel), 0.0)
     K = g[:, None] * g[None, :] * W
     K[np.diag_indices_from(K)] += float(noise_var)
     if return_parts:
@@ -45,7 +46,7 @@ def covariance_dense(x, radius, bump_width, centers, weights, noise_var, return_
     return K
 
 
-def dcov_dense(x, radius, bump_width, centers, weights, noise_var):
+def dcov_dense(x, radius, bump_width, centers, weights, noise_var, kernel="c2"):
     """List of dense dK/dtheta in the order (r, a_1..a_P, sigma_n^2).
 
     dK/dr      = g_i g_j dW/dr                      (Wendland derivative)
@@ -53,9 +54,9 @@ def dcov_dense(x, radius, bump_width, centers, weights, noise_var):
     dK/dsigma2 = I
     """
     K, parts = covariance_dense(x, radius, bump_width, centers, weights, noise_var,
-                                return_parts=True)
+                                return_parts=True, kernel=kernel)
     g, b, keep, rho, W = parts["g"], parts["b"], parts["keep"], parts["rho"], parts["W"]
-    out = [g[:, None] * g[None, :] * np.where(keep, wendland_c2_dr(rho, float(radius)), 0.0)]
+    out = [g[:, None] * g[None, :] * np.where(keep, wendland_dr(rho, float(radius), kernel), 0.0)]
     for k in range(b.shape[1]):
         bk = b[:, k]
         out.append((bk[:, None] * g[None, :] + g[:, None] * bk[None, :]) * W)
@@ -83,11 +84,11 @@ def lml_dense(K, y):
     return LMLResult(lml, logdet, yTa, a)
 
 
-def grad_exact(x, y, radius, bump_width, centers, weights, noise_var):
+def grad_exact(x, y, radius, bump_width, centers, weights, noise_var, kernel="c2"):
     """Exact gradient (n_bumps + 2,) in the order (r, a_1..a_P, sigma_n^2), with
     K^{-1} formed from the Cholesky factor. Also returns the two halves
     (data-fit 1/2 a^T dK a and trace 1/2 tr(K^{-1} dK)) for diagnostics."""
-    K, dKs = dcov_dense(x, radius, bump_width, centers, weights, noise_var)
+    K, dKs = dcov_dense(x, radius, bump_width, centers, weights, noise_var, kernel)
     res = lml_dense(K, y)
     c = scipy.linalg.cho_factor(K, lower=True)
     Kinv = scipy.linalg.cho_solve(c, np.eye(K.shape[0]))

@@ -48,6 +48,43 @@ def wendland_c6(rho):
     return out
 
 
+def wendland_c6_dr(rho, r):
+    """Derivative of the C^6 member W(d / r) (Eq. wendland) with respect to r, at rho = d / r.
+
+    dW/drho = -22 rho (1 - rho)^7 (16 rho^2 + 7 rho + 1) (product rule on the printed
+    form), drho/dr = -rho / r, so the product is 22 rho^2 (1 - rho)^7 (16 rho^2 + 7 rho
+    + 1) / r inside the support and 0 outside.
+    """
+    rho = np.asarray(rho, dtype=np.float64)
+    out = np.zeros_like(rho)
+    inside = rho < 1.0
+    p = rho[inside]
+    out[inside] = 22.0 * p ** 2 * (1.0 - p) ** 7 * (16.0 * p ** 2 + 7.0 * p + 1.0) / r
+    return out
+
+
+KERNELS = ("c2", "c6")
+
+
+def wendland(rho, kernel="c2"):
+    """The Wendland member selected by `kernel`: "c2" (the workloads' member) or "c6"
+    (Eq. wendland as printed)."""
+    if kernel == "c2":
+        return wendland_c2(rho)
+    if kernel == "c6":
+        return wendland_c6(rho)
+    raise ValueError(f"unknown kernel {kernel!r}")
+
+
+def wendland_dr(rho, r, kernel="c2"):
+    """d/dr of the selected member at rho = d / r."""
+    if kernel == "c2":
+        return wendland_c2_dr(rho, r)
+    if kernel == "c6":
+        return wendland_c6_dr(rho, r)
+    raise ValueError(f"unknown kernel {kernel!r}")
+
+
 def kernel_params_check(dim, radius, bump_width, centers, weights, noise_var):
     centers = np.asarray(centers, dtype=np.float64).reshape(-1, dim)
     weights = np.asarray(weights, dtype=np.float64).reshape(-1)

@@ -22,11 +22,11 @@ import numpy as np
 import scipy.linalg
 
 from .dense import covariance_dense
-from .kernel import bump_values, wendland_c2
+from .kernel import bump_values, wendland
 from .pattern import pairwise_sqdist
 
 
-def cross_covariance(x_test, x, radius, bump_width, centers, weights):
+def cross_covariance(x_test, x, radius, bump_width, centers, weights, kernel="c2"):
     """k(x*_t, x_j) for every test point t and training point j (n_test x N)."""
     x_test = np.asarray(x_test, dtype=np.float64)
     x = np.asarray(x, dtype=np.float64)
@@ -35,17 +35,17 @@ def cross_covariance(x_test, x, radius, bump_width, centers, weights):
     d2 = pairwise_sqdist(x_test, x)
     keep = (d2 < float(radius) ** 2) & gams[:, None] & gam[None, :]
     rho = np.sqrt(d2) / float(radius)
-    return np.where(keep, gs[:, None] * g[None, :] * wendland_c2(rho), 0.0), gs
+    return np.where(keep, gs[:, None] * g[None, :] * wendland(rho, kernel), 0.0), gs
 
 
-def posterior_dense(x, y, x_test, radius, bump_width, centers, weights, noise_var, K=None):
+def posterior_dense(x, y, x_test, radius, bump_width, centers, weights, noise_var, K=None, kernel="c2"):
     """(mean, var, a) at the test points, by Cholesky of the dense training K.
 
     K may be given (for instance the matrix a device path stored, in user order);
     otherwise it is built from the points."""
     if K is None:
-        K = covariance_dense(x, radius, bump_width, centers, weights, noise_var)
-    Ks, gs = cross_covariance(x_test, x, radius, bump_width, centers, weights)
+        K = covariance_dense(x, radius, bump_width, centers, weights, noise_var, kernel=kernel)
+    Ks, gs = cross_covariance(x_test, x, radius, bump_width, centers, weights, kernel)
     c = scipy.linalg.cho_factor(K, lower=True)
     a = scipy.linalg.cho_solve(c, np.asarray(y, dtype=np.float64))
     V = scipy.linalg.cho_solve(c, Ks.T)

@@ -12,16 +12,16 @@ import numpy as np
 import scipy.sparse as sp
 from scipy.spatial import cKDTree
 
-from .kernel import bump_values, wendland_c2
+from .kernel import bump_values, wendland
 from .pattern import sqdist_pairs
 
 
-def _values(x, radius, g, i, j):
+def _values(x, radius, g, i, j, kernel):
     d2 = sqdist_pairs(x[i], x[j])
-    return g[i] * g[j] * wendland_c2(np.sqrt(d2) / float(radius)), d2
+    return g[i] * g[j] * wendland(np.sqrt(d2) / float(radius), kernel), d2
 
 
-def covariance_csr(x, radius, bump_width, centers, weights, noise_var):
+def covariance_csr(x, radius, bump_width, centers, weights, noise_var, kernel="c2"):
     """Full K as scipy.sparse.csr_matrix (columns ascending within each row)."""
     x = np.asarray(x, dtype=np.float64)
     n = x.shape[0]
@@ -29,7 +29,7 @@ def covariance_csr(x, radius, bump_width, centers, weights, noise_var):
     tree = cKDTree(x)
     pairs = tree.query_pairs(float(radius), output_type="ndarray")
     if pairs.size:
-        v, d2 = _values(x, radius, g, pairs[:, 0], pairs[:, 1])
+        v, d2 = _values(x, radius, g, pairs[:, 0], pairs[:, 1], kernel)
         keep = (d2 < float(radius) ** 2) & gamma[pairs[:, 0]] & gamma[pairs[:, 1]]
         pairs, v = pairs[keep], v[keep]
     else:
@@ -44,7 +44,7 @@ def covariance_csr(x, radius, bump_width, centers, weights, noise_var):
 
 
 def covariance_rows(x, radius, bump_width, centers, weights, noise_var, rows, tree=None,
-                    g=None, gamma=None):
+                    g=None, gamma=None, kernel="c2"):
     """Rows `rows` of K (user order): list of (cols ascending, values) per row."""
     x = np.asarray(x, dtype=np.float64)
     if g is None or gamma is None:
@@ -63,7 +63,7 @@ def covariance_rows(x, radius, bump_width, centers, weights, noise_var, rows, tr
         if i not in cols:
             cols = np.sort(np.append(cols, i))
         rho = np.sqrt(sqdist_pairs(np.broadcast_to(x[i], (len(cols), x.shape[1])), x[cols])) / float(radius)
-        vals = g[i] * g[cols] * wendland_c2(rho)
+        vals = g[i] * g[cols] * wendland(rho, kernel)
         vals[cols == i] = g[i] * g[i] + float(noise_var)
         out.append((cols, vals))
     return out

@@ -106,13 +106,14 @@ def test_diagonal_case_closed_forms():
     np.testing.assert_allclose(grad, expect, rtol=1e-12, atol=1e-12)
 
 
-@pytest.mark.parametrize("dim,points", [(2, "uniform"), (3, "gmm")])
-def test_gradient_matches_central_differences(dim, points):
+@pytest.mark.parametrize("dim,points,kernel", [(2, "uniform", "c2"), (3, "gmm", "c2"), (2, "uniform", "c6"),
+                                               (3, "gmm", "c6")])
+def test_gradient_matches_central_differences(dim, points, kernel):
     p = _small(seed=12, n=250, dim=dim, r=0.15 if dim == 2 else 0.25, P=3, w=0.55, points=points)
-    grad, _ = oracle.grad_exact(p.x, p.y, p.radius, p.bump_width, p.centers, p.weights, p.noise_var)
+    grad, _ = oracle.grad_exact(p.x, p.y, p.radius, p.bump_width, p.centers, p.weights, p.noise_var, kernel=kernel)
 
     def lml(theta):
-        K = oracle.covariance_dense(p.x, theta[0], p.bump_width, p.centers, theta[1:-1], theta[-1])
+        K = oracle.covariance_dense(p.x, theta[0], p.bump_width, p.centers, theta[1:-1], theta[-1], kernel=kernel)
         return oracle.lml_dense(K, p.y).lml
 
     theta = np.concatenate([[p.radius], p.weights, [p.noise_var]])
@@ -123,3 +124,13 @@ def test_gradient_matches_central_differences(dim, points):
         tm[k] -= h
         fd = (lml(tp) - lml(tm)) / (2 * h)
         assert grad[k] == pytest.approx(fd, rel=2e-6, abs=1e-6 * max(1.0, abs(grad).max()))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_c6_covariance_positive_definite(dim):
+    """Eq. wendland's member is positive definite in up to three dimensions, so K - sigma^2 I
+    (the noise-free part) has no negative eigenvalue on distinct points."""
+    p = _small(seed=21, n=300, dim=dim, r=0.3, P=3, w=0.8, points="uniform")
+    K = oracle.covariance_dense(p.x, p.radius, p.bump_width, p.centers, p.weights, 0.0, kernel="c6")
+    lam = np.linalg.eigvalsh(K)
+    assert lam.min() > -1e-12 * lam.max()

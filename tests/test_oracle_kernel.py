@@ -54,6 +54,29 @@ def test_wendland_radius_derivative_closed_form_and_fd():
     np.testing.assert_allclose(oracle.wendland_c2_dr(d / r, r), fd, rtol=1e-7, atol=1e-10)
 
 
+def test_wendland_c6_radius_derivative_and_integral():
+    """The printed member (Eq. wendland): d/dr closed form at rho = 1/2, central
+    differences in r, and its integral over the unit disk from Beta functions."""
+    from fractions import Fraction
+    from math import factorial
+    import scipy.integrate
+    # 22 (1/2)^2 (1/2)^7 (16/4 + 7/2 + 1) / r at r = 2
+    assert oracle.wendland_c6_dr(np.array([0.5]), 2.0)[0] == pytest.approx(float(Fraction(22 * 17, 4 * 128 * 2 * 2)),
+                                                                            rel=1e-14)
+    d = np.linspace(0.01, 0.99, 37)
+    h = 1e-6
+    fd = (oracle.wendland_c6(d / (1.0 + h)) - oracle.wendland_c6(d / (1.0 - h))) / (2 * h)
+    np.testing.assert_allclose(oracle.wendland_c6_dr(d, 1.0), fd, rtol=1e-7, atol=1e-9)  # FD rounding ~eps/h
+    # int_0^1 W(rho) rho drho = sum_k c_k B(k + 2, 9) with W = (1-rho)^8 sum_k c_k rho^k
+    beta = lambda a, b: Fraction(factorial(a - 1) * factorial(b - 1), factorial(a + b - 1))
+    exact = sum(Fraction(c) * beta(k + 2, 9) for k, c in [(0, 1), (1, 8), (2, 25), (3, 32)])
+    num, _ = scipy.integrate.quad(lambda t: oracle.wendland_c6(np.array([t]))[0] * t, 0, 1, epsabs=1e-15)
+    assert num == pytest.approx(float(exact), rel=1e-12)
+    assert oracle.wendland(d, "c6") is not None and np.array_equal(oracle.wendland(d, "c6"), oracle.wendland_c6(d))
+    with pytest.raises(ValueError):
+        oracle.wendland(d, "c4")
+
+
 def test_bump_closed_forms():
     w = 0.5
     c = np.array([[0.3, 0.4]])
