@@ -77,7 +77,13 @@ typedef struct {
   double noise_var;       /* sigma_n^2 >= 0, added on the diagonal (Sec. 2, V)       */
   const double* centers;  /* HOST [n_bumps * dim], row-major bump centres c_k        */
   const double* weights;  /* HOST [n_bumps], bump amplitudes a_k                     */
+  int32_t kernel;         /* Wendland member W (Sec. 3.1): GP2S_WENDLAND_C2 (0) is
+                             (1-rho)^4 (4 rho + 1); GP2S_WENDLAND_C6 (1) is Eq. wendland
+                             as printed, (1-rho)^8 (32 rho^3 + 25 rho^2 + 8 rho + 1).
+                             Zero-initialised params select C2.                      */
 } gp2s_params;
+#define GP2S_WENDLAND_C2 0
+#define GP2S_WENDLAND_C6 1
 
 /* Solver options. gp2s_default_opts() fills the defaults given in brackets. */
 typedef struct {

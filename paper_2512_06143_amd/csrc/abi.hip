@@ -622,6 +622,7 @@ gp2s_status lml_common(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_
     b.radius = m->radius;
     b.r2 = m->radius * m->radius;
     b.inv_r2 = 1.0 / b.r2;
+    b.kern = m->kern;
     TIMED(GP2S_T_BACKWARD, launch_backward_rows(b, m->prec, Rr, Tr, Ur, ctx->stream));
     TIMED(GP2S_T_GRAD_REDUCE, launch_grad_reduce(n, m->dim, m->P, S, m->x64, m->g64, ai, Rr, Tr, Ur, m->centers_d,
                               m->bump_width * m->bump_width, gpart, tk2, gd, ctx->stream));
@@ -753,6 +754,8 @@ gp2s_status gp2s_check_params(gp2s_ctx ctx, int64_t n, const gp2s_params* p) {
   if (p->radius <= 0) return fail(ctx, GP2S_E_INVALID, "radius must be > 0");
   if (p->bump_width <= 0) return fail(ctx, GP2S_E_INVALID, "bump_width must be > 0");
   if (p->noise_var < 0) return fail(ctx, GP2S_E_INVALID, "noise_var must be >= 0");
+  if (p->kernel != GP2S_WENDLAND_C2 && p->kernel != GP2S_WENDLAND_C6)
+    return fail(ctx, GP2S_E_INVALID, "kernel must be GP2S_WENDLAND_C2 or GP2S_WENDLAND_C6");
   for (int k = 0; k < p->n_bumps * p->dim; ++k)
     if (!is_fin(p->centers[k])) return fail(ctx, GP2S_E_NONFINITE, "non-finite bump centre");
   for (int k = 0; k < p->n_bumps; ++k)
@@ -790,6 +793,7 @@ gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_p
   m->radius = p->radius;
   m->bump_width = p->bump_width;
   m->noise = p->noise_var;
+  m->kern = p->kernel;
   m->centers_h.assign(p->centers, p->centers + (size_t)p->n_bumps * p->dim);
   m->weights_h.assign(p->weights, p->weights + p->n_bumps);
   const int dim = p->dim;
@@ -908,6 +912,7 @@ gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_p
   aa.inv_r2 = 1.0 / aa.r2;
   aa.noise = p->noise_var;
   aa.r2f = (float)aa.r2;
+  aa.kern = m->kern;
   TIMED(GP2S_T_ASM_COUNT, launch_assemble_count(aa, prec, row_cnt, sm));
   HIPCHK(launch_exscan_i32_i64(row_cnt, m->row_ptr, n, scan_ws, sm));
   int64_t nnz = 0;
@@ -1173,6 +1178,7 @@ gp2s_status gp2s_predict(gp2s_ctx ctx, gp2s_matrix m, int64_t n_test, const doub
   ca.r2 = m->radius * m->radius;
   ca.inv_r2 = 1.0 / ca.r2;
   ca.r2f = (float)ca.r2;
+  ca.kern = m->kern;
   HIPCHK(launch_cross_count(ca, m->prec, row_cnt, sm));
   HIPCHK(launch_exscan_i32_i64(row_cnt, rp, nt, scan_ws, sm));
   int64_t nnz = 0;

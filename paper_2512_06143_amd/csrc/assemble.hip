@@ -1,8 +1,8 @@
 // Covariance assembly: pair culling, kernel evaluation and stream compaction into CSR.
 //
-// K_ij = g_i g_j W(||x_i - x_j|| / r) + sigma_n^2 [i == j], W(rho) = (1 - rho)^4 (4 rho + 1)
-// for rho < 1 (Sec. 3.1 product construction with a C^2 Wendland member; Sec. 3.3
-// bump mask g). The paper computes dense block pairs and keeps the non-zeros
+// K_ij = g_i g_j W(||x_i - x_j|| / r) + sigma_n^2 [i == j], W a Wendland member for
+// rho < 1: the C^2 (1 - rho)^4 (4 rho + 1) or Eq. wendland's C^6 (Sec. 3.1 product
+// construction; Sec. 3.3 bump mask g). The paper computes dense block pairs and keeps the non-zeros
 // (Sec. 3.5, App. B.7); here only candidates from the 3^d neighbouring bins are
 // tested, and a pair is stored when ||x_i - x_j|| < r and both points lie inside
 // some bump (the diagonal always).
@@ -99,11 +99,11 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs a, int64_t nbl
         if (FILL && pass && pos < end) {  // never past the row counted by the first pass
           col[pos] = (int32_t)j;
           if (F32) {
-            float v = (j == row) ? (float)(gi64 * gi64 + a.noise) : entry_f32(pi32, pj32, a.r2, a.inv_r2);
+            float v = (j == row) ? (float)(gi64 * gi64 + a.noise) : entry_f32(pi32, pj32, a.r2, a.inv_r2, a.kern);
             static_cast<float*>(val)[pos] = v;
             if (j == row) diag[row] = (double)v;
           } else {
-            double v = (j == row) ? gi64 * gi64 + a.noise : entry_f64(pi64, pj64, a.r2, a.inv_r2);
+            double v = (j == row) ? gi64 * gi64 + a.noise : entry_f64(pi64, pj64, a.r2, a.inv_r2, a.kern);
             static_cast<double*>(val)[pos] = v;
             if (j == row) diag[row] = v;
           }

@@ -5,7 +5,8 @@
 // w_s = D^-1/2 z_s as (1/S) sum_s q_s^T dK w_s. With the symmetrised weight
 //   P_ij = a_i a_j - (1/2S) sum_s (q_si w_sj + q_sj w_si)
 // every component reduces to per-row sums over the stored pattern:
-//   dK_ij/dr      = g_i g_j dW/dr,    dW/dr = 20 rho^2 (1 - rho)^3 / r
+//   dK_ij/dr      = g_i g_j dW/dr,    dW/dr = 20 rho^2 (1 - rho)^3 / r for the C^2
+//                                     member, 22 rho^2 (1 - rho)^7 (16 rho^2 + 7 rho + 1) / r for C^6
 //   dK_ij/da_k    = (b_k(x_i) g_j + g_i b_k(x_j)) W_ij          (b_k: unweighted bump)
 //   dK_ij/dsigma2 = [i == j]
 //   R_i = sum_j g_j W_ij P_ij,  T_i = sum_j g_j dW/dr_ij P_ij,
@@ -15,6 +16,7 @@
 // W and dW/dr are recomputed from the coordinates for every stored entry: no
 // per-parameter matrix is ever formed.
 #include "gp2s_internal.h"
+#include "pair.h"
 
 namespace gp2s {
 
@@ -41,7 +43,7 @@ __device__ inline double wave_sum(double v) {
 }
 
 // W and dW/dr for a stored pair (float32 path: accurate 1 - rho^2 from float64 distance).
-__device__ inline void w_dw_f32(const float4& pi, const float4& pj, double r2, double inv_r2, float inv_r,
+__device__ inline void w_dw_f32(const float4& pi, const float4& pj, double r2, double inv_r2, float inv_r, int kern,
                                 float& W, float& dW) {
   double dx = (double)pi.x - (double)pj.x;
   double dy = (double)pi.y - (double)pj.y;
@@ -50,20 +52,16 @@ __device__ inline void w_dw_f32(const float4& pi, const float4& pj, double r2, d
   float t = fmaxf((float)((r2 - d2) * inv_r2), 0.0f);
   float rho = __builtin_amdgcn_sqrtf((float)(d2 * inv_r2));
   float om = t * __builtin_amdgcn_rcpf(1.0f + rho);
-  float om2 = om * om;
-  W = om2 * om2 * (4.0f * rho + 1.0f);
-  dW = 20.0f * rho * rho * om2 * om * inv_r;
+  wendland_w_dr<float>(kern, rho, om, inv_r, W, dW);
 }
-__device__ inline void w_dw_f64(const double4& pi, const double4& pj, double r2, double inv_r2, double inv_r,
+__device__ inline void w_dw_f64(const double4& pi, const double4& pj, double r2, double inv_r2, double inv_r, int kern,
                                 double& W, double& dW) {
   double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
   double d2 = dx * dx + dy * dy + dz * dz;
   double t = fmax((r2 - d2) * inv_r2, 0.0);
   double rho = sqrt(d2 * inv_r2);
   double om = t / (1.0 + rho);
-  double om2 = om * om;
-  W = om2 * om2 * (4.0 * rho + 1.0);
-  dW = 20.0 * rho * rho * om2 * om * inv_r;
+  wendland_w_dr<double>(kern, rho, om, inv_r, W, dW);
 }
 
 template <bool F32>
@@ -96,14 +94,14 @@ __global__ __launch_bounds__(kBlock) void k_backward_rows(BackwardArgs b, double
         if (F32) {
           const float4 pj = b.pts32[j];
           float W, dW;
-          w_dw_f32(pi32, pj, b.r2, b.inv_r2, (float)inv_r, W, dW);
+          w_dw_f32(pi32, pj, b.r2, b.inv_r2, (float)inv_r, b.kern, W, dW);
           const float gj = fmaxf(pj.w, 0.0f);
           gW = (double)(gj * W);
           gWp = (double)(gj * dW);
         } else {
           const double4 pj = b.pts64[j];
           double W, dW;
-          w_dw_f64(pi64, pj, b.r2, b.inv_r2, inv_r, W, dW);
+          w_dw_f64(pi64, pj, b.r2, b.inv_r2, inv_r, b.kern, W, dW);
           const double gj = fmax(pj.w, 0.0);
           gW = gj * W;
           gWp = gj * dW;

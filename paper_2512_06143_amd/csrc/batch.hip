@@ -8,6 +8,7 @@
 // atomics. The arithmetic of every step is the single-instance one (see
 // prologue.hip, assemble.hip, spmv.hip, pcg.hip, backward.hip).
 #include "gp2s_internal.h"
+#include "pair.h"
 #include "spmm_rows.h"
 
 namespace gp2s {
@@ -150,23 +151,21 @@ __device__ inline double bsq64(const double4& a, const double4& b) {
   const double dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
   return __fma_rn(dz, dz, __fma_rn(dy, dy, __dmul_rn(dx, dx)));
 }
-__device__ inline float bentry32(const float4& pi, const float4& pj, double r2, double inv_r2) {
+__device__ inline float bentry32(const float4& pi, const float4& pj, double r2, double inv_r2, int kern) {
   const double dx = (double)pi.x - (double)pj.x, dy = (double)pi.y - (double)pj.y, dz = (double)pi.z - (double)pj.z;
   const double d2 = dx * dx + dy * dy + dz * dz;
   const float t = fmaxf((float)((r2 - d2) * inv_r2), 0.0f);
   const float rho = __builtin_amdgcn_sqrtf((float)(d2 * inv_r2));
   const float om = t * __builtin_amdgcn_rcpf(1.0f + rho);
-  const float om2 = om * om;
-  return pi.w * pj.w * (om2 * om2 * (4.0f * rho + 1.0f));
+  return pi.w * pj.w * wendland_w<float>(kern, rho, om);
 }
-__device__ inline double bentry64(const double4& pi, const double4& pj, double r2, double inv_r2) {
+__device__ inline double bentry64(const double4& pi, const double4& pj, double r2, double inv_r2, int kern) {
   const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
   const double d2 = dx * dx + dy * dy + dz * dz;
   const double t = fmax((r2 - d2) * inv_r2, 0.0);
   const double rho = sqrt(d2 * inv_r2);
   const double om = t / (1.0 + rho);
-  const double om2 = om * om;
-  return pi.w * pj.w * (om2 * om2 * (4.0 * rho + 1.0));
+  return pi.w * pj.w * wendland_w<double>(kern, rho, om);
 }
 
 __device__ inline uint32_t blane_prefix(uint64_t m) {
@@ -253,11 +252,11 @@ __global__ __launch_bounds__(kBlock) void k_bassemble(BAsm a, int64_t nblocks_pa
         if (FILL && pass && pos < end) {
           col[pos] = (int32_t)j;
           if (F32) {
-            const float v = (j == row) ? (float)(gi64 * gi64 + I.noise) : bentry32(pi32, pj32, I.r2, I.inv_r2);
+            const float v = (j == row) ? (float)(gi64 * gi64 + I.noise) : bentry32(pi32, pj32, I.r2, I.inv_r2, I.kern);
             static_cast<float*>(val)[pos] = v;
             if (j == row) diag[row] = (double)v;
           } else {
-            const double v = (j == row) ? gi64 * gi64 + I.noise : bentry64(pi64, pj64, I.r2, I.inv_r2);
+            const double v = (j == row) ? gi64 * gi64 + I.noise : bentry64(pi64, pj64, I.r2, I.inv_r2, I.kern);
             static_cast<double*>(val)[pos] = v;
             if (j == row) diag[row] = v;
           }
@@ -912,9 +911,10 @@ __global__ __launch_bounds__(kBlock) void k_bbackward_rows(BBackward b, double* 
           const float t = fmaxf((float)((I.r2 - d2) * I.inv_r2), 0.0f);
           const float rho = __builtin_amdgcn_sqrtf((float)(d2 * I.inv_r2));
           const float om = t * __builtin_amdgcn_rcpf(1.0f + rho);
-          const float om2 = om * om;
-          W = om2 * om2 * (4.0f * rho + 1.0f);
-          dW = 20.0f * rho * rho * om2 * om * (float)inv_r;
+          float Wf, dWf;
+          wendland_w_dr<float>(I.kern, rho, om, (float)inv_r, Wf, dWf);
+          W = Wf;
+          dW = dWf;
           gj = fmaxf(pj.w, 0.0f);
         } else {
           const double4 pj = b.pts64[j];
@@ -923,9 +923,7 @@ __global__ __launch_bounds__(kBlock) void k_bbackward_rows(BBackward b, double* 
           const double t = fmax((I.r2 - d2) * I.inv_r2, 0.0);
           const double rho = sqrt(d2 * I.inv_r2);
           const double om = t / (1.0 + rho);
-          const double om2 = om * om;
-          W = om2 * om2 * (4.0 * rho + 1.0);
-          dW = 20.0 * rho * rho * om2 * om * inv_r;
+          wendland_w_dr<double>(I.kern, rho, om, inv_r, W, dW);
           gj = fmax(pj.w, 0.0);
         }
         gW = gj * W;

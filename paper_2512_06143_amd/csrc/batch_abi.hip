@@ -13,7 +13,7 @@ struct gp2s_batch_s {
   gp2s_solve_opts opts{};
   std::vector<int64_t> n, row0;
   int64_t N = 0;
-  std::vector<int> dim, P, cent0;
+  std::vector<int> dim, P, cent0, kern;
   int Ptot = 0;
   std::vector<double> radius, width, noise, centers3, weights;
   std::vector<double> bbox;  // [M * 6]
@@ -118,6 +118,7 @@ void build_grids(gp2s_batch b, int m) {
     I.P = b->P[i];
     I.cent0 = b->cent0[i];
     I.m = m;
+    I.kern = b->kern[i];
   }
   b->nbins = bin0;
   b->nblk = blk;
@@ -564,6 +565,7 @@ gp2s_status gp2s_batch_plan(gp2s_ctx ctx, int32_t n_inst, const int64_t* n, cons
   for (int i = 0; i < n_inst; ++i) {
     b->row0[i + 1] = b->row0[i] + n[i];
     b->dim.push_back(params[i].dim);
+    b->kern.push_back(params[i].kernel);
     b->P.push_back(params[i].n_bumps);
     b->cent0.push_back(b->Ptot);
     b->Ptot += params[i].n_bumps;
@@ -747,8 +749,10 @@ gp2s_status gp2s_batch_run(gp2s_batch b, const double* const* y, const gp2s_para
     st = check_batch_params(ctx, M, b->n.data(), params);
     if (st) return st;
     for (int i = 0; i < M; ++i) {
-      if (params[i].dim != b->dim[i] || params[i].n_bumps != b->P[i] || params[i].bump_width != b->width[i])
-        return fail(ctx, GP2S_E_INVALID, "instance %d: dimension, bump count and width are fixed by the plan", i);
+      if (params[i].dim != b->dim[i] || params[i].n_bumps != b->P[i] || params[i].bump_width != b->width[i] ||
+          params[i].kernel != b->kern[i])
+        return fail(ctx, GP2S_E_INVALID, "instance %d: dimension, bump count, width and kernel are fixed by the plan",
+                    i);
       for (int k = 0; k < b->P[i] * b->dim[i]; ++k)
         if (params[i].centers[k] != b->centers3[(size_t)(b->cent0[i] + k / b->dim[i]) * 3 + k % b->dim[i]])
           return fail(ctx, GP2S_E_INVALID, "instance %d: bump centres are fixed by the plan", i);

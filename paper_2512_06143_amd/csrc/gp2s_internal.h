@@ -123,6 +123,7 @@ struct BInst {
   int64_t blk0, nblk;    // its workgroups in the instance-aligned decomposition
   double radius, r2, inv_r2, noise, bump_w2;
   int32_t dim, P, cent0, m;  // bump offset into the shared centre/weight arrays; bin refinement
+  int32_t kern;              // Wendland member (0: C^2, 1: C^6)
 };
 
 struct BatchGeom {
@@ -174,6 +175,7 @@ struct AssembleArgs {
   int64_t n;
   double radius, r2, inv_r2, noise;
   float r2f;
+  int32_t kern;  // Wendland member (0: C^2, 1: C^6)
 };
 hipError_t launch_assemble_count(const AssembleArgs& a, int prec, int32_t* row_cnt, hipStream_t st);
 hipError_t launch_assemble_fill(const AssembleArgs& a, int prec, const int64_t* row_ptr,
@@ -191,6 +193,7 @@ struct CrossArgs {
   GridDev grid;
   double r2, inv_r2;
   float r2f;
+  int32_t kern;
 };
 hipError_t launch_test_prologue(const double* x, int64_t nt, const GridDev& g, const double* centers,
                                 const double* weights, int P, double bump_w2, float4* pts32, double4* pts64,
@@ -261,6 +264,7 @@ struct BackwardArgs {
   int64_t n;
   int S;
   double radius, r2, inv_r2;
+  int32_t kern;  // Wendland member (0: C^2, 1: C^6)
 };
 hipError_t launch_backward_rows(const BackwardArgs& b, int prec, double* Rrow, double* Trow,
                                 double* Urow, hipStream_t st);

@@ -95,8 +95,32 @@ __device__ inline double sqdist_f64(const double4& a, const double4& b) {
   return d2;
 }
 
+// Wendland members (Sec. 3.1): kern 0 is the C^2 member (1 - rho)^4 (4 rho + 1), the
+// workloads' "small variation"; kern 1 is the C^6 member of Eq. wendland as printed,
+// (1 - rho)^8 (32 rho^3 + 25 rho^2 + 8 rho + 1). om = 1 - rho is passed in, formed
+// from 1 - rho^2 without cancellation near the support boundary.
+template <typename T>
+__device__ inline T wendland_w(int kern, T rho, T om) {
+  const T om2 = om * om, om4 = om2 * om2;
+  if (kern == 1) return om4 * om4 * ((((T)32 * rho + (T)25) * rho + (T)8) * rho + (T)1);
+  return om4 * ((T)4 * rho + (T)1);
+}
+// W and its derivative in the radius at rho = d / r: dW/dr = -(rho / r) dW/drho, i.e.
+// 20 rho^2 (1 - rho)^3 / r (C^2) and 22 rho^2 (1 - rho)^7 (16 rho^2 + 7 rho + 1) / r (C^6).
+template <typename T>
+__device__ inline void wendland_w_dr(int kern, T rho, T om, T inv_r, T& W, T& dW) {
+  const T om2 = om * om, om4 = om2 * om2;
+  if (kern == 1) {
+    W = om4 * om4 * ((((T)32 * rho + (T)25) * rho + (T)8) * rho + (T)1);
+    dW = (T)22 * rho * rho * om4 * om2 * om * (((T)16 * rho + (T)7) * rho + (T)1) * inv_r;
+  } else {
+    W = om4 * ((T)4 * rho + (T)1);
+    dW = (T)20 * rho * rho * om2 * om * inv_r;
+  }
+}
+
 // Float32 entry value for a surviving off-diagonal pair.
-__device__ inline float entry_f32(const float4& pi, const float4& pj, double r2, double inv_r2) {
+__device__ inline float entry_f32(const float4& pi, const float4& pj, double r2, double inv_r2, int kern) {
   double dx = (double)pi.x - (double)pj.x;
   double dy = (double)pi.y - (double)pj.y;
   double dz = (double)pi.z - (double)pj.z;
@@ -105,18 +129,16 @@ __device__ inline float entry_f32(const float4& pi, const float4& pj, double r2,
   t = fmaxf(t, 0.0f);
   float rho = __builtin_amdgcn_sqrtf((float)(d2 * inv_r2));
   float om = t * __builtin_amdgcn_rcpf(1.0f + rho);  // 1 - rho
-  float om2 = om * om;
-  return pi.w * pj.w * (om2 * om2 * (4.0f * rho + 1.0f));
+  return pi.w * pj.w * wendland_w<float>(kern, rho, om);
 }
 
-__device__ inline double entry_f64(const double4& pi, const double4& pj, double r2, double inv_r2) {
+__device__ inline double entry_f64(const double4& pi, const double4& pj, double r2, double inv_r2, int kern) {
   double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
   double d2 = dx * dx + dy * dy + dz * dz;
   double t = fmax((r2 - d2) * inv_r2, 0.0);
   double rho = sqrt(d2 * inv_r2);
   double om = t / (1.0 + rho);
-  double om2 = om * om;
-  return pi.w * pj.w * (om2 * om2 * (4.0 * rho + 1.0));
+  return pi.w * pj.w * wendland_w<double>(kern, rho, om);
 }
 
 }  // namespace gp2s

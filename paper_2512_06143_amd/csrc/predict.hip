@@ -119,9 +119,9 @@ __global__ __launch_bounds__(kBlock) void k_cross(CrossArgs a, int64_t nblocks_p
         if (FILL && pass && pos < end) {  // never past the row counted by the first pass
           col[pos] = (int32_t)j;
           if (F32)
-            static_cast<float*>(val)[pos] = entry_f32(pi32, pj32, a.r2, a.inv_r2);
+            static_cast<float*>(val)[pos] = entry_f32(pi32, pj32, a.r2, a.inv_r2, a.kern);
           else
-            static_cast<double*>(val)[pos] = entry_f64(pi64, pj64, a.r2, a.inv_r2);
+            static_cast<double*>(val)[pos] = entry_f64(pi64, pj64, a.r2, a.inv_r2, a.kern);
         }
         cnt += __popcll(m);
       }

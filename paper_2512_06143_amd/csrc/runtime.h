@@ -53,6 +53,7 @@ struct gp2s_matrix_s {
   // hyperparameters (assembled handles)
   int dim = 0, P = 0;
   double radius = 0, bump_width = 0, noise = 0;
+  int kern = 0;  // Wendland member
   std::vector<double> centers_h, weights_h;
   double* centers_d = nullptr;
   double* weights_d = nullptr;

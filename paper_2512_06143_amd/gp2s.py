@@ -37,7 +37,11 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 class Params(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n_bumps", ctypes.c_int32), ("radius", ctypes.c_double),
                 ("bump_width", ctypes.c_double), ("noise_var", ctypes.c_double),
-                ("centers", ctypes.POINTER(ctypes.c_double)), ("weights", ctypes.POINTER(ctypes.c_double))]
+                ("centers", ctypes.POINTER(ctypes.c_double)), ("weights", ctypes.POINTER(ctypes.c_double)),
+                ("kernel", ctypes.c_int32)]
+
+
+WENDLAND = {"c2": 0, "c6": 1}  # Wendland member: C^2, or the printed C^6 of Eq. wendland
 
 
 class SolveOpts(ctypes.Structure):
@@ -140,13 +144,15 @@ class HostParams:
     noise_var: float
     centers: np.ndarray
     weights: np.ndarray
+    kernel: int | str = 0  # 0 / "c2" or 1 / "c6"
 
     def to_c(self):
         c = np.ascontiguousarray(self.centers, dtype=np.float64).reshape(-1)
         w = np.ascontiguousarray(self.weights, dtype=np.float64).reshape(-1)
+        kern = WENDLAND[self.kernel] if isinstance(self.kernel, str) else int(self.kernel)
         p = Params(int(self.dim), int(w.shape[0]), float(self.radius), float(self.bump_width),
                    float(self.noise_var), c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                   w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                   w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), kern)
         return p, (c, w)  # keep the arrays alive while p is used
 
 

@@ -50,6 +50,9 @@ def _params(B, **kw):
     (dict(weights=[float("inf")]), 10, 7),
     (dict(), 0, 1),
     (dict(), 1 << 31, 1),
+    (dict(kernel=1), 10, 0),
+    (dict(kernel="c6"), 10, 0),
+    (dict(kernel=2), 10, 1),
 ])
 def test_host_validation(kw, n, code):
     B, ctx = _ctx()
@@ -64,6 +67,9 @@ def test_entry_points_reject_bad_arguments_without_gpu():
     B, ctx = _ctx()
     p, keep = _params(B)
     h = ctypes.c_void_p()
+    o0 = B.default_opts()
+    rep = B.PredictReport()
+    assert B.lib.gp2s_predict(ctx, None, 4, 1234, 1234, ctypes.byref(o0), 1234, None, ctypes.byref(rep)) == 1
     # invalid precision / null pointers are rejected before any device call
     assert B.lib.gp2s_assemble(ctx, 10, None, ctypes.byref(p), 0, ctypes.byref(h)) == 1
     assert B.lib.gp2s_assemble(ctx, 10, 1234, ctypes.byref(p), 9, ctypes.byref(h)) == 1
