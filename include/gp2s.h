@@ -194,6 +194,15 @@ gp2s_status gp2s_matrix_import(gp2s_ctx ctx, int64_t n, int64_t nnz, const int64
 
 gp2s_status gp2s_matrix_free(gp2s_matrix m);
 
+/* New hyperparameters on an assembled handle that keep its stored pattern: the bump
+ * weights, the noise variance and the Wendland member may change; the dimension,
+ * radius, bump count, centres and width must equal the handle's (the pattern depends
+ * only on them), else GP2S_E_INVALID. Recomputes g and every stored value in place
+ * (no count pass, no allocation of the CSR): the step a sampler takes when a move
+ * leaves r and the bump geometry unchanged (Sec. 3.5 and App. D, block-MCMC). The result equals a
+ * fresh gp2s_assemble with the same parameters, bit for bit. */
+gp2s_status gp2s_matrix_refill(gp2s_ctx ctx, gp2s_matrix m, const gp2s_params* params);
+
 /* Block-product kernel used for `nrhs` columns (2..64) of this matrix, in CG probe
  * blocks and gp2s_spmv: 0 one lane per column (any nrhs), 1 a 16-byte column slice
  * per lane, 2 the same with the rows of X that a tile of bin-sorted rows references

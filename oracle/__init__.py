@@ -15,7 +15,8 @@ computes, written from the paper (arXiv 2512.06143):
   path approximates with conjugate gradients and Lanczos quadrature;
 * the counter-based SplitMix64 probe signs;
 * the posterior mean and variance of the latent function at test points (Sec. 2,
-  Eq. posterior).
+  Eq. posterior);
+* the block Metropolis-Hastings sampler of the hyperparameters (Sec. 3.5, App. D).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package. The product library never calls it, and it
@@ -33,6 +34,7 @@ from .probes import splitmix64, rademacher_probes, probe_sign_masks
 from .estimators import logdet_same_probe, grad_same_probe, lml_same_probe, hutchinson_variance
 from .sparse import covariance_csr, covariance_rows, residual_rel, pcg_jacobi
 from .posterior import cross_covariance, posterior_dense
+from .mcmc import block_mh
 
 __all__ = [
     "wendland_c2", "wendland_c2_dr", "wendland_c6", "wendland_c6_dr", "wendland", "wendland_dr", "KERNELS",
@@ -42,6 +44,6 @@ __all__ = [
     "covariance_dense", "dcov_dense", "lml_dense", "grad_exact", "LMLResult",
     "splitmix64", "rademacher_probes", "probe_sign_masks",
     "logdet_same_probe", "grad_same_probe", "lml_same_probe", "hutchinson_variance",
-    "cross_covariance", "posterior_dense",
+    "cross_covariance", "posterior_dense", "block_mh",
     "covariance_csr", "covariance_rows", "residual_rel", "pcg_jacobi",
 ]

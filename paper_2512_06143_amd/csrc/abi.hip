@@ -470,6 +470,8 @@ struct ProbeResult {
 // signs and right-hand sides on the second stream and begins the block solve there.
 gp2s_status probes_begin(gp2s_ctx ctx, gp2s_matrix m, const gp2s_solve_opts* o, Scratch& sc, uint64_t* mask,
                          double* Qsol, Cg& cp) {
+  // Qsol == nullptr: the probe solutions are not needed (no gradient), only the CG
+  // coefficients the quadrature uses.
   const int64_t n = m->n;
   const int S = o->n_probes;
   double* B = sc.get<double>((size_t)n * S);
@@ -555,7 +557,7 @@ gp2s_status lml_common(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_
   Scratch sc(ctx);
   double* yi = sc.get<double>(n);
   double* ai = sc.get<double>(n);
-  double* Qs = sc.get<double>((size_t)n * S);
+  double* Qs = grad ? sc.get<double>((size_t)n * S) : nullptr;  // probe solutions (gradient only)
   uint64_t* mask = sc.get<uint64_t>(n);
   double* red = sc.get<double>(1 + kReduceBlocks);
   uint32_t* tk = sc.get<uint32_t>(1);
@@ -1029,6 +1031,60 @@ gp2s_status gp2s_matrix_free(gp2s_matrix m) {
     for (void* q : m->owned) dfree(m->ctx, q);
   }
   delete m;
+  return GP2S_OK;
+}
+
+gp2s_status gp2s_matrix_refill(gp2s_ctx ctx, gp2s_matrix m, const gp2s_params* p) {
+  if (!ctx) return GP2S_E_INVALID;
+  gp2s_status st = check_matrix(ctx, m);
+  if (st) return st;
+  if (!m->assembled) return fail(ctx, GP2S_E_INVALID, "refill needs a handle from gp2s_assemble");
+  st = gp2s_check_params(ctx, m->n, p);
+  if (st) return st;
+  bool same = p->dim == m->dim && p->n_bumps == m->P && p->radius == m->radius && p->bump_width == m->bump_width;
+  for (int k = 0; same && k < p->n_bumps * p->dim; ++k) same = p->centers[k] == m->centers_h[k];
+  if (!same)
+    return fail(ctx, GP2S_E_INVALID,
+                "refill keeps the pattern: dimension, radius, bump count, centres and width must be unchanged "
+                "(assemble a new handle instead)");
+  st = ensure_device(ctx);
+  if (st) return st;
+  hipStream_t sm = ctx->stream;
+  const int64_t n = m->n;
+  m->weights_h.assign(p->weights, p->weights + p->n_bumps);
+  m->noise = p->noise_var;
+  m->kern = p->kernel;
+  HIPCHK(hipMemcpyAsync(m->weights_d, m->weights_h.data(), m->weights_h.size() * sizeof(double),
+                        hipMemcpyHostToDevice, sm));
+  Scratch sc(ctx);
+  int32_t* bad = sc.get<int32_t>(1);
+  if (sc.oom) return fail(ctx, GP2S_E_OOM, "refill workspace allocation failed");
+  {
+    Timed prep_timer(ctx, GP2S_T_ASM_PREP, ctx->stream);
+    HIPCHK(launch_refresh_g(n, m->dim, m->x64, m->centers_d, m->weights_d, m->P, m->bump_width * m->bump_width,
+                            m->pts32, m->pts64, m->g64, sm));
+  }
+  AssembleArgs aa{};
+  aa.pts32 = m->pts32;
+  aa.pts64 = m->pts64;
+  aa.g64 = m->g64;
+  aa.binid = m->binid;
+  aa.bin_start = m->bin_start;
+  aa.grid = m->grid;
+  aa.n = n;
+  aa.radius = m->radius;
+  aa.r2 = m->radius * m->radius;
+  aa.inv_r2 = 1.0 / aa.r2;
+  aa.noise = m->noise;
+  aa.r2f = (float)aa.r2;
+  aa.kern = m->kern;
+  TIMED(GP2S_T_ASM_FILL, launch_assemble_fill(aa, m->prec, m->row_ptr, m->col, m->val, m->diag, sm));
+  HIPCHK(hipMemsetAsync(bad, 0, sizeof(int32_t), sm));
+  HIPCHK(launch_dinv(n, m->diag, m->dinv, bad, sm));
+  int32_t hb = 0;
+  st = readback(ctx, bad, sizeof(int32_t), &hb);
+  if (st) return st;
+  m->diag_ok = hb == 0;
   return GP2S_OK;
 }
 

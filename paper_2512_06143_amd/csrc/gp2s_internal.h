@@ -151,6 +151,8 @@ hipError_t launch_scatter(int64_t n, const int32_t* bin_of, const int32_t* slot,
                           const int64_t* bin_start, int32_t* perm_tmp, hipStream_t st);
 hipError_t launch_binsort(int64_t n, const int32_t* perm_tmp, const int32_t* bin_of,
                           const int64_t* bin_start, int32_t* perm, hipStream_t st);
+hipError_t launch_refresh_g(int64_t n, int dim, const double* x64, const double* centers, const double* weights,
+                            int P, double bump_w2, float4* pts32, double4* pts64, double* g64, hipStream_t st);
 hipError_t launch_gather_points(int64_t n, int dim, const double* x, const int32_t* perm,
                                 const int32_t* bin_of, const double* g64_user, const uint8_t* gam,
                                 float4* pts32, double4* pts64, double* x64, double* g64,
@@ -224,6 +226,7 @@ hipError_t launch_cg_matvec(int prec, const int64_t* rp, const int32_t* col, con
 hipError_t launch_cg_alpha(const CgState& cs, int nb, int S, hipStream_t st);
 hipError_t launch_cg_init(int64_t n, int S, const double* B, const double* dinv, double* X,
                           double* R, void* P, bool f32vec, const CgState& cs, double tol, hipStream_t st);
+// X == nullptr: the solution is not formed (coefficients only).
 hipError_t launch_cg_update(int64_t n, int S, double* X, double* R, const void* P, const void* Q,
                             bool f32vec, const double* dinv, const CgState& cs, int32_t iter,
                             hipStream_t st);

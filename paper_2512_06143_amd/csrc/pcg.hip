@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t n, int S, const doub
     const int64_t i = e / S;
     const double b = B[e];
     const double z = b * dinv[i];
-    X[e] = 0.0;
+    if (X) X[e] = 0.0;
     R[e] = b;
     P[e] = (VEC)z;
     rz += b * z;
@@ -59,7 +59,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(int64_t n, int S, const doub
   block_cols_to_partial(sh, S, bb, cs.partial, 1);
 }
 
-template <typename VEC>
+// WANTX = false skips the solution update (the probe block of an LML without gradient
+// needs only the CG coefficients).
+template <typename VEC, bool WANTX>
 __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int S, double* __restrict__ X,
                                                       double* __restrict__ R, const VEC* __restrict__ P,
                                                       const double* __restrict__ Q,
@@ -75,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(int64_t n, int S, double* 
     const int64_t i = e / S;
     double r = R[e];
     if (a != 0.0) {
-      X[e] += a * (double)P[e];
+      if (WANTX) X[e] += a * (double)P[e];
       r -= a * Q[e];
       R[e] = r;
     }
@@ -229,11 +231,18 @@ hipError_t launch_cg_update(int64_t n, int S, double* X, double* R, const void* 
                             const double* dinv, const CgState& cs, int32_t iter, hipStream_t st) {
   const int nth = cols_block(S);
   const unsigned nb = cg_blocks(n * S, nth);
-  if (f32vec)
-    hipLaunchKernelGGL(k_cg_update<float>, dim3(nb), dim3(nth), 0, st, n, S, X, R,
+  const bool wx = X != nullptr;
+  if (f32vec && wx)
+    hipLaunchKernelGGL((k_cg_update<float, true>), dim3(nb), dim3(nth), 0, st, n, S, X, R,
                        static_cast<const float*>(P), static_cast<const double*>(Q), dinv, cs, iter);
+  else if (f32vec)
+    hipLaunchKernelGGL((k_cg_update<float, false>), dim3(nb), dim3(nth), 0, st, n, S, X, R,
+                       static_cast<const float*>(P), static_cast<const double*>(Q), dinv, cs, iter);
+  else if (wx)
+    hipLaunchKernelGGL((k_cg_update<double, true>), dim3(nb), dim3(nth), 0, st, n, S, X, R,
+                       static_cast<const double*>(P), static_cast<const double*>(Q), dinv, cs, iter);
   else
-    hipLaunchKernelGGL(k_cg_update<double>, dim3(nb), dim3(nth), 0, st, n, S, X, R,
+    hipLaunchKernelGGL((k_cg_update<double, false>), dim3(nb), dim3(nth), 0, st, n, S, X, R,
                        static_cast<const double*>(P), static_cast<const double*>(Q), dinv, cs, iter);
   hipLaunchKernelGGL(k_cg_beta, dim3(S), dim3(kBlock), 0, st, cs, (int)nb, S, iter);
   return hipGetLastError();

@@ -162,6 +162,34 @@ __global__ __launch_bounds__(kBlock) void k_gather_points(
   binid[p] = bin_of[u];
 }
 
+// New bump weights on an assembled handle: g and the point records' w of every
+// internal point from its stored coordinates. The support flag depends only on the
+// centres and the width, which stay fixed, so the pattern is unchanged.
+__global__ __launch_bounds__(kBlock) void k_refresh_g(int64_t n, int dim, const double* __restrict__ x64,
+                                                      const double* __restrict__ centers,
+                                                      const double* __restrict__ weights, int P, double bump_w2,
+                                                      float4* __restrict__ pts32, double4* __restrict__ pts64,
+                                                      double* __restrict__ g64) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  double xi[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < dim; ++k) xi[k] = x64[p * dim + k];
+  double gs = 0.0;
+  bool inside = false;
+  bump_mask(xi, dim, centers, weights, P, bump_w2, gs, inside);
+  g64[p] = inside ? gs : 0.0;
+  if (pts32) pts32[p].w = inside ? (float)gs : -1.0f;
+  if (pts64) pts64[p].w = inside ? gs : -1.0;
+}
+
+hipError_t launch_refresh_g(int64_t n, int dim, const double* x64, const double* centers, const double* weights,
+                            int P, double bump_w2, float4* pts32, double4* pts64, double* g64, hipStream_t st) {
+  const int64_t blocks = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_refresh_g, dim3((unsigned)blocks), dim3(kBlock), 0, st, n, dim, x64, centers, weights, P,
+                     bump_w2, pts32, pts64, g64);
+  return hipGetLastError();
+}
+
 hipError_t launch_gather_points(int64_t n, int dim, const double* x, const int32_t* perm,
                                 const int32_t* bin_of, const double* g64_user, const uint8_t* gam,
                                 float4* pts32, double4* pts64, double* x64, double* g64,

@@ -95,6 +95,7 @@ _SIGS = {
     "gp2s_matrix_export": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "gp2s_matrix_import": (_i32, [_vp, _i64, _i64, _vp, _vp, _vp, _i32, ctypes.POINTER(_vp)]),
     "gp2s_matrix_free": (_i32, [_vp]),
+    "gp2s_matrix_refill": (_i32, [_vp, _vp, ctypes.POINTER(Params)]),
     "gp2s_matrix_set_block_product": (_i32, [_vp, _i32, _i32]),
     "gp2s_matrix_get_block_product": (_i32, [_vp, _i32, ctypes.POINTER(_i32)]),
     "gp2s_spmv": (_i32, [_vp, _vp, _i32, _vp, _vp]),
@@ -252,6 +253,12 @@ class Matrix:
         n, nnz, pr = _i64(), _i64(), _i32()
         lib.gp2s_matrix_info(handle, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(pr))
         self.n, self.nnz = n.value, nnz.value
+
+    def refill(self, params: "HostParams"):
+        """New weights / noise / Wendland member on the same pattern (see gp2s_matrix_refill)."""
+        p, keep = params.to_c()
+        self.ctx.check(lib.gp2s_matrix_refill(self.ctx.ptr, self.handle, ctypes.byref(p)))
+        self.params = params
 
     def set_block_product(self, nrhs: int, variant: int):
         """Pin the block-product kernel for `nrhs` columns (see include/gp2s.h); -1 retunes."""

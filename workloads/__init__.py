@@ -208,3 +208,15 @@ def make_c5(max_instances: int | None = None) -> list[Problem]:
         out.append(Problem(f"c5_{i}", x, y, float(radii[i]), BUMP_WIDTH, centers, weights,
                            spec["noise_var"], 16, dict(spec)))
     return out
+
+
+def mcmc_draws(seed: int, n_iter: int, block_sizes) -> list:
+    """Seeded random inputs of a block Metropolis-Hastings run: for every iteration and
+    block, the standard-normal proposal offsets (one per parameter of the block) and the
+    uniform acceptance draw. Shared by the sampler and its oracle so that both take the
+    same decisions; holds none of the sampler's arithmetic."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_iter):
+        out.append([(rng.standard_normal(int(k)), float(rng.random())) for k in block_sizes])
+    return out
