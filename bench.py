@@ -193,6 +193,35 @@ def bench_posterior(G, x, y, params, precision, prob, n_mean=100_000, n_var=64):
     return res
 
 
+def bench_mcmc(G, x, y, params, precision, opts, n_sweeps=1):
+    """Block Metropolis-Hastings sweeps over (r, bump amplitudes, noise variance) on the
+    timed workload (outside the timed step): one LML without gradient per block move,
+    a pattern refill for moves that keep r, a fresh assembly for moves of r."""
+    import numpy as np
+    import torch
+    import workloads
+    P = len(np.asarray(params.weights))
+    blocks = [[0], list(range(1, P + 1)), [P + 1]]
+    theta = G.mcmc.theta_of(params)
+    steps = np.concatenate([[0.01 * theta[0]], 0.05 * np.ones(P), [0.05 * theta[-1]]])
+    draws = workloads.mcmc_draws(2024, n_sweeps, [len(b) for b in blocks])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mh = G.BlockMH(x, y, params, precision, opts, blocks=blocks, steps=steps)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
+    res = mh.run(n_sweeps, draws=draws)
+    mh.free()
+    out = {"sweeps": n_sweeps, "blocks": len(blocks), "s_per_sweep": res["seconds"] / n_sweeps,
+           "s_per_lml": res["seconds"] / max(res["evals"], 1), "init_s": t_init,
+           "evals": res["evals"], "refills": res["refills"], "assemblies": res["assemblies"],
+           "accepted": res["accepted"], "lml": [float(v) for v in res["lml"]]}
+    log(f"[bench] mcmc: {n_sweeps} sweep(s) of {len(blocks)} blocks in {res['seconds']:.2f}s "
+        f"({out['s_per_lml']:.2f}s per LML; {res['refills']} refills, {res['assemblies']} assemblies; "
+        f"accepted {res['accepted']})")
+    return out
+
+
 def bench_batch(args):
     """64 independent instances (c5) planned once, then evaluated together per step:
     reassembly with the step's hyperparameters, y solves, probe solves, log-dets, LMLs
@@ -258,6 +287,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64-plain comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-predict", action="store_true", help="skip the posterior (test-point) measurement")
+    ap.add_argument("--no-mcmc", action="store_true", help="skip the block Metropolis-Hastings sweep")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -378,6 +408,8 @@ def main():
         log(f"[bench] fp64 plain: {t64:.2f}s iters y={rep64.iters} probes={rep64.probe_iters} lml={rep64.lml:.6f}")
     if not args.no_predict:
         out["posterior"] = bench_posterior(G, x, y, params, args.precision, prob)
+    if not args.no_mcmc:
+        out["mcmc"] = bench_mcmc(G, x, y, params, args.precision, opts)
     if not args.no_cpu:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(prob, nnz, rep.iters, rep.probe_iters, S)

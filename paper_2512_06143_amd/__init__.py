@@ -13,7 +13,9 @@ from .gp2s import (GP2S_FP64, GP2S_MIXED, Batch, GP2SError, Context, HostParams,
                    default_context, default_opts, gp2s_assemble, gp2s_lml, gp2s_lml_grad,
                    gp2s_matrix_import, gp2s_predict, gp2s_solve, gp2s_spmv, lib)
 
-__all__ = ["GP2S_FP64", "GP2S_MIXED", "Batch", "GP2SError", "Context", "HostParams", "Matrix", "Report", "SolveOpts",
+from .mcmc import BlockMH  # noqa: E402
+
+__all__ = ["BlockMH", "GP2S_FP64", "GP2S_MIXED", "Batch", "GP2SError", "Context", "HostParams", "Matrix", "Report", "SolveOpts",
            "default_context", "default_opts", "gp2s_assemble", "gp2s_lml", "gp2s_lml_grad",
            "gp2s_matrix_import", "gp2s_predict", "gp2s_solve", "gp2s_spmv", "GP2SLML", "lml"]
 
