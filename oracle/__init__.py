@@ -14,6 +14,8 @@ computes, written from the paper (arXiv 2512.06143):
   stochastic estimators (Hutchinson trace, probe log-determinant) that the GPU
   path approximates with conjugate gradients and Lanczos quadrature;
 * the counter-based SplitMix64 probe signs;
+* the preconditioners of the solves (diagonal, and block diagonal over runs of the
+  binned point order) that the estimators are defined with;
 * the posterior mean and variance of the latent function at test points (Sec. 2,
   Eq. posterior);
 * the block Metropolis-Hastings sampler of the hyperparameters (Sec. 3.5, App. D).
@@ -35,6 +37,7 @@ from .estimators import logdet_same_probe, grad_same_probe, lml_same_probe, hutc
 from .sparse import covariance_csr, covariance_rows, residual_rel, pcg_jacobi
 from .posterior import cross_covariance, posterior_dense
 from .mcmc import block_mh
+from .precond import BLOCK, grid, bin_coords, bin_order, block_partition, jacobi_partition, block_factor
 
 __all__ = [
     "wendland_c2", "wendland_c2_dr", "wendland_c6", "wendland_c6_dr", "wendland", "wendland_dr", "KERNELS",
@@ -45,5 +48,6 @@ __all__ = [
     "splitmix64", "rademacher_probes", "probe_sign_masks",
     "logdet_same_probe", "grad_same_probe", "lml_same_probe", "hutchinson_variance",
     "cross_covariance", "posterior_dense", "block_mh",
+    "BLOCK", "grid", "bin_coords", "bin_order", "block_partition", "jacobi_partition", "block_factor",
     "covariance_csr", "covariance_rows", "residual_rel", "pcg_jacobi",
 ]

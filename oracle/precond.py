@@ -1,0 +1,100 @@
+"""Block-Jacobi preconditioner of the probe and y solves, and the point order that
+defines its blocks (test infrastructure).
+
+The paper leaves the log-determinant method unnamed (Sec. 3.5, App. B.6 "LOGDET").
+The estimators of ``oracle.estimators`` are written for any factor L of a
+preconditioner M = L L^T; the diagonal (Jacobi) choice L = D^{1/2} is the special
+case of one-point blocks. The block choice is:
+
+* order the points by spatial bin: a grid of cells of side h >= r anchored at the
+  lower corner of the points' bounding box, bins numbered with the first coordinate
+  varying fastest, the sort stable in the user index (so that points closer than r
+  fall in the same or neighbouring cells and a run of consecutive points is
+  spatially compact);
+* cut that order into runs of ``size`` consecutive points (the last run holds the
+  remainder); a block of M is the principal submatrix of K on one run, and L is
+  its Cholesky factor.
+
+Every function states the quantity it returns in plain linear algebra.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+BLOCK = 64
+
+
+def grid(x, radius):
+    """(origin, h, nb): the bin grid for points x (n, dim) and support radius r.
+    h = r (1 + 1e-6), widened if needed so that the number of cells stays within
+    max(4 n, 65536); nb[k] = floor((hi_k - lo_k) / h) + 1 cells along axis k."""
+    x = np.asarray(x, dtype=np.float64)
+    n, dim = x.shape
+    lo, hi = x.min(axis=0), x.max(axis=0)
+    h = float(radius) * (1.0 + 1e-6)
+    max_bins = max(4.0 * n, 65536.0)
+    for _ in range(64):
+        total = 1.0
+        for k in range(dim):
+            total *= np.floor((hi[k] - lo[k]) / h) + 1.0
+        if total <= max_bins:
+            break
+        h *= (total / max_bins) ** (1.0 / dim) * 1.01
+    nb = [int(np.floor((hi[k] - lo[k]) / h) + 1.0) for k in range(dim)]
+    return lo, h, nb
+
+
+def bin_coords(x, radius):
+    """(n, dim) integer cell coordinates floor((x_k - lo_k) / h), clamped to the grid."""
+    x = np.asarray(x, dtype=np.float64)
+    lo, h, nb = grid(x, radius)
+    inv_h = 1.0 / h
+    c = np.floor((x - lo[None, :]) * inv_h)
+    return np.clip(c, 0, np.array(nb) - 1).astype(np.int64), nb
+
+
+def bin_order(x, radius):
+    """perm (n,) int64: perm[p] is the user index of the point at position p when the
+    points are sorted by cell number (first coordinate fastest), ties by user index."""
+    c, nb = bin_coords(x, radius)
+    key = np.zeros(c.shape[0], dtype=np.int64)
+    for k in range(c.shape[1] - 1, -1, -1):
+        key = key * nb[k] + c[:, k]
+    return np.argsort(key, kind="stable").astype(np.int64)
+
+
+def block_partition(order, size=BLOCK):
+    """Runs of `size` consecutive entries of `order` (the last one may be shorter)."""
+    order = np.asarray(order, dtype=np.int64)
+    return [order[s:s + size] for s in range(0, len(order), size)]
+
+
+def jacobi_partition(n):
+    """One-point blocks: M = diag(K)."""
+    return [np.array([i], dtype=np.int64) for i in range(n)]
+
+
+def block_factor(K, blocks):
+    """(L, Linv, logdet_M) for M = the block diagonal of K over `blocks` (index sets
+    of a partition of the points, in user indexing): L[b, b] = chol(K[b, b]) (lower
+    within the block's own index order), zero elsewhere, so that M = L L^T; Linv is
+    L^-1 with the same structure; logdet_M = ln|M| = sum over blocks of ln|K[b, b]|.
+    Blocks of equal size are factored together (a batched library Cholesky)."""
+    K = np.asarray(K, dtype=np.float64)
+    n = K.shape[0]
+    L = np.zeros((n, n))
+    Linv = np.zeros((n, n))
+    logdet = 0.0
+    by_size = {}
+    for b in blocks:
+        b = np.asarray(b, dtype=np.int64)
+        by_size.setdefault(len(b), []).append(b)
+    for size in sorted(by_size):
+        idx = np.stack(by_size[size])                      # (m, size)
+        Kb = K[idx[:, :, None], idx[:, None, :]]           # (m, size, size)
+        Lb = np.linalg.cholesky(Kb)
+        Lb_inv = np.linalg.inv(Lb)
+        L[idx[:, :, None], idx[:, None, :]] = Lb
+        Linv[idx[:, :, None], idx[:, None, :]] = Lb_inv
+        logdet += 2.0 * float(np.sum(np.log(np.diagonal(Lb, axis1=1, axis2=2))))
+    return L, Linv, logdet
