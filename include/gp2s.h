@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define GP2S_ABI_VERSION 1
+#define GP2S_ABI_VERSION 2
 
 typedef int32_t gp2s_status;
 #define GP2S_OK           0
@@ -95,7 +95,25 @@ typedef struct {
   uint64_t seed;          /* probe seed [0]                                           */
   double tol;             /* target ||y - K a|| / ||y|| (K as stored) [1e-8]          */
   double probe_tol;       /* per-probe relative CG residual target [1e-5]             */
+  int32_t precond;        /* preconditioner M of every CG solve [GP2S_PRECOND_BLOCK]:
+                             GP2S_PRECOND_JACOBI (0): M = diag(K);
+                             GP2S_PRECOND_BLOCK (1): M = the block diagonal of K over
+                             runs of 64 consecutive points of the handle's internal
+                             order (the bin order of an assembled handle, the given
+                             order of an imported one; the last run holds the
+                             remainder), factored M = L L^T blockwise by Cholesky.
+                             The log-determinant estimate is ln|M| + the Lanczos
+                             estimate of ln|L^-1 K L^-T| on right-hand sides L z_s; the
+                             gradient's trace uses q_s = K^-1 L z_s and w_s = L^-T z_s.
+                             Either choice leaves E[ln|K| estimate] = ln|K| (the
+                             same-probe value depends on it). The factor is computed on
+                             the first solve that needs it and kept with the handle
+                             (gp2s_matrix_refill drops it); a block that is not
+                             positive definite fails with GP2S_E_NOT_SPD. The batched
+                             path (gp2s_batch_*) always uses the diagonal.          */
 } gp2s_solve_opts;
+#define GP2S_PRECOND_JACOBI 0
+#define GP2S_PRECOND_BLOCK 1
 
 /* Filled on return (HOST struct). */
 typedef struct {

@@ -32,11 +32,13 @@ struct Cg {
   const char* label = "";
   hipStream_t st = nullptr;
   int slot0 = 0;  // first of this solve's two pinned poll slots
+  int precond = GP2S_PRECOND_JACOBI;
   // state
   CgState cs{};
   bool f32vec = false;
   int variant = 0;
   double* R = nullptr;
+  double* Z = nullptr;  // M^-1 r (block preconditioner)
   void* P = nullptr;
   void* Q = nullptr;
   int32_t* si = nullptr;
@@ -181,6 +183,34 @@ gp2s_status tune_block_product(gp2s_ctx ctx, gp2s_matrix m, int S, const void* P
   return GP2S_OK;
 }
 
+// Builds the block-Jacobi factor of the handle's current values if it is not there
+// (on the context's stream; synchronous, since a block that is not positive definite
+// is reported here).
+gp2s_status ensure_bj(gp2s_ctx ctx, gp2s_matrix m) {
+  if (m->bj_ready) return GP2S_OK;
+  const int64_t n = m->n;
+  const size_t nblk = (size_t)((n + kBJ - 1) / kBJ);
+  if (!m->bj_L) {
+    m->bj_L = own<double>(m, nblk * kBJ * kBJ);
+    m->bj_M = own<double>(m, nblk * kBJ * kBJ);
+    m->bj_piv = own<double>(m, (size_t)n);
+    if (!m->bj_L || !m->bj_M || !m->bj_piv) return fail(ctx, GP2S_E_OOM, "block preconditioner allocation failed");
+  }
+  Scratch sc(ctx);
+  int32_t* bad = sc.get<int32_t>(1);
+  if (sc.oom) return fail(ctx, GP2S_E_OOM, "block preconditioner workspace allocation failed");
+  HIPCHK(hipMemsetAsync(bad, 0, sizeof(int32_t), ctx->stream));
+  HIPCHK(launch_bj_factor(n, m->row_ptr, m->col, m->val, m->prec, m->bj_L, m->bj_M, m->bj_piv, bad, ctx->stream));
+  int32_t hb = 0;
+  gp2s_status st = readback(ctx, bad, sizeof(int32_t), &hb);
+  if (st) return st;
+  if (hb)
+    return fail(ctx, GP2S_E_NOT_SPD,
+                "a 64-point diagonal block of K is not positive definite (Cholesky pivot <= 0 in float64)");
+  m->bj_ready = true;
+  return GP2S_OK;
+}
+
 // Allocates the workspace, initialises the state and reads the initial flags.
 gp2s_status cg_begin(Cg& c, const double* B, double tol, bool keep_hist, Scratch& sc) {
   gp2s_ctx ctx = c.ctx;
@@ -193,6 +223,7 @@ gp2s_status cg_begin(Cg& c, const double* B, double tol, bool keep_hist, Scratch
   c.f32vec = m->prec == GP2S_MIXED && S > 1;
   const size_t vb = c.f32vec ? sizeof(float) : sizeof(double);
   c.R = sc.get<double>(nS);
+  if (c.precond == GP2S_PRECOND_BLOCK) c.Z = sc.get<double>(nS);
   c.P = sc.get<uint8_t>(nS * vb);
   c.Q = sc.get<double>(nS);
   double* sd = sc.get<double>(6 * S + (size_t)kReduceBlocks * S * 2);
@@ -220,7 +251,14 @@ gp2s_status cg_begin(Cg& c, const double* B, double tol, bool keep_hist, Scratch
   HIPCHK(hipEventCreateWithFlags(&c.ev[0], hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&c.ev[1], hipEventDisableTiming));
   HIPCHK(hipMemsetAsync(c.si, 0, (2 * S + 4) * sizeof(int32_t), c.st));
-  HIPCHK(launch_cg_init(n, S, B, m->dinv, c.X, c.R, c.P, c.f32vec, cs, tol, c.st));
+  if (c.precond == GP2S_PRECOND_BLOCK) {
+    if (!m->bj_ready) return fail(ctx, GP2S_E_INVALID, "block preconditioner not built (%s)", c.label);
+    HIPCHK(launch_bj_update(n, S, B, c.X, c.R, nullptr, nullptr, c.f32vec, m->bj_M, c.Z, cs, c.st));
+    HIPCHK(launch_cg_init_fin(cs, (int)bj_update_blocks(n), S, tol, c.st));
+    HIPCHK(launch_copy_dir(n, S, c.Z, c.P, c.f32vec, c.st));
+  } else {
+    HIPCHK(launch_cg_init(n, S, B, m->dinv, c.X, c.R, c.P, c.f32vec, cs, tol, c.st));
+  }
   // done[S] then flags[4] are contiguous in si
   int32_t* pin = c.slot(0);
   HIPCHK(hipMemcpyAsync(pin, c.si, (S + 4) * sizeof(int32_t), hipMemcpyDeviceToHost, c.st));
@@ -246,10 +284,18 @@ gp2s_status cg_step(Cg& c) {
   TIMED_ON(S == 1 ? GP2S_T_CG_MATVEC1 : GP2S_T_CG_MATVEC_BLOCK, c.st,
            launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, n, S, (double)m->nnz / (double)n, c.variant,
                             tile_set(m), c.P, c.Q, c.f32vec, c.cs, c.st));
-  TIMED_ON(S == 1 ? GP2S_T_CG_UPDATE1 : GP2S_T_CG_UPDATE_BLOCK, c.st,
-           launch_cg_update(n, S, c.X, c.R, c.P, c.Q, c.f32vec, m->dinv, c.cs, c.it, c.st));
-  TIMED_ON(S == 1 ? GP2S_T_CG_PUPDATE1 : GP2S_T_CG_PUPDATE_BLOCK, c.st,
-           launch_cg_pupdate(n, S, c.P, c.R, m->dinv, c.f32vec, c.cs, c.st));
+  if (c.precond == GP2S_PRECOND_BLOCK) {
+    TIMED_ON(S == 1 ? GP2S_T_CG_UPDATE1 : GP2S_T_CG_UPDATE_BLOCK, c.st,
+             launch_bj_update(n, S, nullptr, c.X, c.R, c.P, c.Q, c.f32vec, m->bj_M, c.Z, c.cs, c.st));
+    HIPCHK(launch_cg_beta(c.cs, (int)bj_update_blocks(n), S, c.it, c.st));
+    TIMED_ON(S == 1 ? GP2S_T_CG_PUPDATE1 : GP2S_T_CG_PUPDATE_BLOCK, c.st,
+             launch_cg_pupdate(n, S, c.P, c.Z, nullptr, c.f32vec, c.cs, c.st));
+  } else {
+    TIMED_ON(S == 1 ? GP2S_T_CG_UPDATE1 : GP2S_T_CG_UPDATE_BLOCK, c.st,
+             launch_cg_update(n, S, c.X, c.R, c.P, c.Q, c.f32vec, m->dinv, c.cs, c.it, c.st));
+    TIMED_ON(S == 1 ? GP2S_T_CG_PUPDATE1 : GP2S_T_CG_PUPDATE_BLOCK, c.st,
+             launch_cg_pupdate(n, S, c.P, c.R, m->dinv, c.f32vec, c.cs, c.st));
+  }
   ++c.it;
   return GP2S_OK;
 }
@@ -355,11 +401,12 @@ gp2s_status cg_drive(Cg* a, Cg* b) {
 }
 
 gp2s_status run_cg(gp2s_ctx ctx, gp2s_matrix m, int S, const double* B, double* X, double tol, int max_iter,
-                   int check_every, bool keep_hist, Scratch& sc, CgRun& out, const char* label) {
+                   int check_every, bool keep_hist, Scratch& sc, CgRun& out, const char* label, int precond) {
   Cg c;
   c.ctx = ctx;
   c.m = m;
   c.S = S;
+  c.precond = precond;
   c.X = X;
   c.max_iter = max_iter;
   c.check_every = check_every;
@@ -419,6 +466,7 @@ gp2s_status solve_internal(gp2s_ctx ctx, gp2s_matrix m, const double* y, double*
     cy.ctx = ctx;
     cy.m = m;
     cy.S = 1;
+    cy.precond = o->precond;
     cy.X = a;
     cy.max_iter = o->max_iter;
     cy.check_every = o->check_every;
@@ -446,7 +494,8 @@ gp2s_status solve_internal(gp2s_ctx ctx, gp2s_matrix m, const double* y, double*
       ++ir;
       const double inner = std::min(0.5, 0.5 * o->tol / resid);
       CgRun r2;
-      st = run_cg(ctx, m, 1, r, d, inner, o->max_iter - total, o->check_every, false, sc, r2, "refinement solve");
+      st = run_cg(ctx, m, 1, r, d, inner, o->max_iter - total, o->check_every, false, sc, r2, "refinement solve",
+                  o->precond);
       if (st) return st;
       total += r2.total_iters;
       HIPCHK(launch_add(n, a, d, ctx->stream));
@@ -466,10 +515,13 @@ struct ProbeResult {
   bool converged = false;
 };
 
-// Probe solves K q_s = D^1/2 z_s (Sec. 3.5; App. B.6 "LOGDET"): queues the probe
+// Probe solves K q_s = L z_s (Sec. 3.5; App. B.6 "LOGDET"; L = D^1/2 for the diagonal
+// preconditioner, the blockwise Cholesky factor for the block one): queues the probe
 // signs and right-hand sides on the second stream and begins the block solve there.
+// Wsol (block preconditioner, gradient only) receives w_s = L^-T z_s = M^-1 L z_s, the
+// preconditioned initial residual.
 gp2s_status probes_begin(gp2s_ctx ctx, gp2s_matrix m, const gp2s_solve_opts* o, Scratch& sc, uint64_t* mask,
-                         double* Qsol, Cg& cp) {
+                         double* Qsol, double* Wsol, Cg& cp) {
   // Qsol == nullptr: the probe solutions are not needed (no gradient), only the CG
   // coefficients the quadrature uses.
   const int64_t n = m->n;
@@ -477,17 +529,24 @@ gp2s_status probes_begin(gp2s_ctx ctx, gp2s_matrix m, const gp2s_solve_opts* o, 
   double* B = sc.get<double>((size_t)n * S);
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "probe workspace allocation failed");
   HIPCHK(launch_probe_masks(n, m->perm, o->seed, S, mask, ctx->aux));
-  HIPCHK(launch_probe_rhs(n, S, mask, m->diag, B, ctx->aux));
+  if (o->precond == GP2S_PRECOND_BLOCK)
+    HIPCHK(launch_bj_rhs(n, S, mask, m->bj_L, B, ctx->aux));
+  else
+    HIPCHK(launch_probe_rhs(n, S, mask, m->diag, B, ctx->aux));
   cp.ctx = ctx;
   cp.m = m;
   cp.S = S;
   cp.X = Qsol;
+  cp.precond = o->precond;
   cp.max_iter = o->max_iter;
   cp.check_every = o->check_every;
   cp.label = "probe block";
   cp.st = ctx->aux;
   cp.slot0 = 2;
-  return cg_begin(cp, B, o->probe_tol, true, sc);
+  gp2s_status st = cg_begin(cp, B, o->probe_tol, true, sc);
+  if (st) return st;
+  if (Wsol) HIPCHK(hipMemcpyAsync(Wsol, cp.Z, (size_t)n * S * sizeof(double), hipMemcpyDeviceToDevice, ctx->aux));
+  return GP2S_OK;
 }
 
 // The Lanczos log-determinant estimate from the finished probe block (after the
@@ -507,7 +566,7 @@ gp2s_status probes_finish(gp2s_ctx ctx, gp2s_matrix m, Scratch& sc, const Cg& cp
   gp2s_status st = readback(ctx, quad, S * sizeof(double), qh.data());
   if (st) return st;
   double sumlog = 0.0;
-  HIPCHK(launch_sum_log(n, m->diag, red, tk, ctx->stream));
+  HIPCHK(launch_sum_log(n, cp.precond == GP2S_PRECOND_BLOCK ? m->bj_piv : m->diag, red, tk, ctx->stream));
   st = readback(ctx, red, sizeof(double), &sumlog);
   if (st) return st;
   double mean = 0.0;
@@ -558,6 +617,7 @@ gp2s_status lml_common(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_
   double* yi = sc.get<double>(n);
   double* ai = sc.get<double>(n);
   double* Qs = grad ? sc.get<double>((size_t)n * S) : nullptr;  // probe solutions (gradient only)
+  double* Ws = grad && o->precond == GP2S_PRECOND_BLOCK ? sc.get<double>((size_t)n * S) : nullptr;
   uint64_t* mask = sc.get<uint64_t>(n);
   double* red = sc.get<double>(1 + kReduceBlocks);
   uint32_t* tk = sc.get<uint32_t>(1);
@@ -565,6 +625,11 @@ gp2s_status lml_common(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_
   HIPCHK(hipMemsetAsync(tk, 0, sizeof(uint32_t), ctx->stream));
   HIPCHK(launch_gather_rows(n, 1, m->perm, y, yi, ctx->stream));
   std::memset(rep, 0, sizeof(*rep));
+  if (o->precond == GP2S_PRECOND_BLOCK) {
+    if (!m->diag_ok) return fail(ctx, GP2S_E_NOT_SPD, "diagonal of K is not positive");
+    st = ensure_bj(ctx, m);
+    if (st) return st;
+  }
   // The probe block runs on the second stream beside the y solve: it starts after
   // the work already queued on the context's stream and is joined back before the
   // quadrature (and on every early return, before the workspace is released).
@@ -578,7 +643,7 @@ gp2s_status lml_common(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_
   }
   AuxJoin join{ctx};
   Cg cp;
-  st = probes_begin(ctx, m, o, sc, mask, Qs, cp);
+  st = probes_begin(ctx, m, o, sc, mask, Qs, Ws, cp);
   if (st) return st;
   bool conv_y = false;
   st = solve_internal(ctx, m, yi, ai, o, sc, rep, &conv_y, &cp);
@@ -619,6 +684,7 @@ gp2s_status lml_common(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_
     b.Q = Qs;
     b.mask = mask;
     b.dinv = m->dinv;
+    b.W = Ws;
     b.n = n;
     b.S = S;
     b.radius = m->radius;
@@ -656,6 +722,7 @@ void gp2s_default_opts(gp2s_solve_opts* o) {
   o->seed = 0;
   o->tol = 1e-8;
   o->probe_tol = 1e-5;
+  o->precond = GP2S_PRECOND_BLOCK;
 }
 
 const char* gp2s_status_string(gp2s_status s) {
@@ -1051,6 +1118,7 @@ gp2s_status gp2s_matrix_refill(gp2s_ctx ctx, gp2s_matrix m, const gp2s_params* p
   if (st) return st;
   hipStream_t sm = ctx->stream;
   const int64_t n = m->n;
+  m->bj_ready = false;  // the block factor belongs to the old values
   m->weights_h.assign(p->weights, p->weights + p->n_bumps);
   m->noise = p->noise_var;
   m->kern = p->kernel;
@@ -1157,6 +1225,10 @@ gp2s_status gp2s_solve(gp2s_ctx ctx, gp2s_matrix m, const double* y, double* a, 
   gp2s_report local{};
   gp2s_report* r = rep ? rep : &local;
   std::memset(r, 0, sizeof(*r));
+  if (o->precond == GP2S_PRECOND_BLOCK && m->diag_ok) {
+    st = ensure_bj(ctx, m);
+    if (st) return st;
+  }
   bool conv = false;
   st = solve_internal(ctx, m, yi, ai, o, sc, r, &conv);
   if (st) return st;
@@ -1250,6 +1322,11 @@ gp2s_status gp2s_predict(gp2s_ctx ctx, gp2s_matrix m, int64_t n_test, const doub
   int32_t blocks = 0, worst = 0;
   bool conv = true;
   if (var) {
+    if (o->precond == GP2S_PRECOND_BLOCK) {
+      if (!m->diag_ok) return fail(ctx, GP2S_E_NOT_SPD, "diagonal of K is not positive");
+      st = ensure_bj(ctx, m);
+      if (st) return st;
+    }
     double* B = sc.get<double>((size_t)n * kVarBlock);
     double* Vs = sc.get<double>((size_t)n * kVarBlock);
     double* csc = sc.get<double>(kVarBlock);
@@ -1260,7 +1337,8 @@ gp2s_status gp2s_predict(gp2s_ctx ctx, gp2s_matrix m, int64_t n_test, const doub
       HIPCHK(launch_cross_block(m->prec, rp, ccol, cval, t0, S, B, csc, sm));
       Scratch scb(ctx);  // the block solve's workspace is released per block
       CgRun run;
-      st = run_cg(ctx, m, S, B, Vs, o->tol, o->max_iter, o->check_every, false, scb, run, "variance block");
+      st = run_cg(ctx, m, S, B, Vs, o->tol, o->max_iter, o->check_every, false, scb, run, "variance block",
+                  o->precond);
       if (st) return st;
       HIPCHK(launch_cross_var(m->prec, rp, ccol, cval, t0, S, Vs, csc, g64t, var, sm));
       ++blocks;

@@ -1,8 +1,10 @@
 // Gradient of the log marginal likelihood with respect to theta = (r, a_1..a_P, sigma_n^2).
 //
 // dLML/dtheta = 1/2 a^T dK a - 1/2 tr(K^-1 dK), a = K^-1 y (Sec. 2 log density); the
-// trace is estimated with the probe solutions q_s = K^-1 D^1/2 z_s and
-// w_s = D^-1/2 z_s as (1/S) sum_s q_s^T dK w_s. With the symmetrised weight
+// trace is estimated with the probe solutions q_s = K^-1 L z_s and w_s = L^-T z_s
+// (M = L L^T the preconditioner: L = D^1/2, w_s recomputed from the signs, or the
+// blockwise Cholesky factor, w_s read from memory) as (1/S) sum_s q_s^T dK w_s. With
+// the symmetrised weight
 //   P_ij = a_i a_j - (1/2S) sum_s (q_si w_sj + q_sj w_si)
 // every component reduces to per-row sums over the stored pattern:
 //   dK_ij/dr      = g_i g_j dW/dr,    dW/dr = 20 rho^2 (1 - rho)^3 / r for the C^2
@@ -42,17 +44,20 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// W and dW/dr for a stored pair (float32 path: accurate 1 - rho^2 from float64 distance).
-__device__ inline void w_dw_f32(const float4& pi, const float4& pj, double r2, double inv_r2, float inv_r, int kern,
-                                float& W, float& dW) {
+// W and dW/dr for a stored pair of the float32-assembled path, evaluated in float64 from
+// the float32 coordinates: the trace term sums q_i dK_ij w_j over terms that cancel
+// heavily, so dK is not rounded to float32 here (one pass per gradient; the float32
+// values are the CG operator's business only).
+__device__ inline void w_dw_mixed(const float4& pi, const float4& pj, double r2, double inv_r2, double inv_r,
+                                  int kern, double& W, double& dW) {
   double dx = (double)pi.x - (double)pj.x;
   double dy = (double)pi.y - (double)pj.y;
   double dz = (double)pi.z - (double)pj.z;
   double d2 = dx * dx + dy * dy + dz * dz;
-  float t = fmaxf((float)((r2 - d2) * inv_r2), 0.0f);
-  float rho = __builtin_amdgcn_sqrtf((float)(d2 * inv_r2));
-  float om = t * __builtin_amdgcn_rcpf(1.0f + rho);
-  wendland_w_dr<float>(kern, rho, om, inv_r, W, dW);
+  double t = fmax((r2 - d2) * inv_r2, 0.0);
+  double rho = sqrt(d2 * inv_r2);
+  double om = t / (1.0 + rho);
+  wendland_w_dr<double>(kern, rho, om, inv_r, W, dW);
 }
 __device__ inline void w_dw_f64(const double4& pi, const double4& pj, double r2, double inv_r2, double inv_r, int kern,
                                 double& W, double& dW) {
@@ -82,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_backward_rows(BackwardArgs b, double
     const uint64_t mi = b.mask[row];
     const double dsi = sqrt(b.dinv[row]);
     const double qi = active ? b.Q[row * S + lane] : 0.0;
-    const double wi = active ? (((mi >> lane) & 1ull) ? -dsi : dsi) : 0.0;
+    const double wi = !active ? 0.0 : b.W ? b.W[row * S + lane] : (((mi >> lane) & 1ull) ? -dsi : dsi);
     double accR = 0.0, accT = 0.0, aR = 0.0, aT = 0.0;
     const int64_t s0 = b.rp[row], e0 = b.rp[row + 1];
     for (int64_t k0 = s0; k0 < e0; k0 += kWave) {
@@ -92,12 +97,11 @@ __global__ __launch_bounds__(kBlock) void k_backward_rows(BackwardArgs b, double
       double gW = 0.0, gWp = 0.0;
       if (valid) {
         if (F32) {
-          const float4 pj = b.pts32[j];
-          float W, dW;
-          w_dw_f32(pi32, pj, b.r2, b.inv_r2, (float)inv_r, b.kern, W, dW);
-          const float gj = fmaxf(pj.w, 0.0f);
-          gW = (double)(gj * W);
-          gWp = (double)(gj * dW);
+          double W, dW;
+          w_dw_mixed(pi32, b.pts32[j], b.r2, b.inv_r2, inv_r, b.kern, W, dW);
+          const double gj = b.g64[j];
+          gW = gj * W;
+          gWp = gj * dW;
         } else {
           const double4 pj = b.pts64[j];
           double W, dW;
@@ -121,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_backward_rows(BackwardArgs b, double
         const double ds = bcast64(dsj, l);
         if (active) {
           const double qj = b.Q[(int64_t)jj * S + lane];
-          const double wj = ((mm >> lane) & 1ull) ? -ds : ds;
+          const double wj = b.W ? b.W[(int64_t)jj * S + lane] : (((mm >> lane) & 1ull) ? -ds : ds);
           const double c = qi * wj + qj * wi;
           accR += gw * c;
           accT += gwp * c;

@@ -904,18 +904,16 @@ __global__ __launch_bounds__(kBlock) void k_bbackward_rows(BBackward b, double* 
       if (valid) {
         double W, dW, gj;
         if (F32) {
+          // float64 evaluation from the float32 coordinates (the trace term cancels heavily)
           const float4 pj = b.pts32[j];
           const double dx = (double)pi32.x - (double)pj.x, dy = (double)pi32.y - (double)pj.y,
                        dz = (double)pi32.z - (double)pj.z;
           const double d2 = dx * dx + dy * dy + dz * dz;
-          const float t = fmaxf((float)((I.r2 - d2) * I.inv_r2), 0.0f);
-          const float rho = __builtin_amdgcn_sqrtf((float)(d2 * I.inv_r2));
-          const float om = t * __builtin_amdgcn_rcpf(1.0f + rho);
-          float Wf, dWf;
-          wendland_w_dr<float>(I.kern, rho, om, (float)inv_r, Wf, dWf);
-          W = Wf;
-          dW = dWf;
-          gj = fmaxf(pj.w, 0.0f);
+          const double t = fmax((I.r2 - d2) * I.inv_r2, 0.0);
+          const double rho = sqrt(d2 * I.inv_r2);
+          const double om = t / (1.0 + rho);
+          wendland_w_dr<double>(I.kern, rho, om, inv_r, W, dW);
+          gj = b.g64[j];
         } else {
           const double4 pj = b.pts64[j];
           const double dx = pi64.x - pj.x, dy = pi64.y - pj.y, dz = pi64.z - pj.z;

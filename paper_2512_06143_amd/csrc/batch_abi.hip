@@ -911,6 +911,7 @@ gp2s_status gp2s_batch_run(gp2s_batch b, const double* const* y, const gp2s_para
     bw.Q = Qs;
     bw.mask = mask;
     bw.dinv = b->dinv;
+    bw.g64 = b->g64;
     bw.S = S;
     HIPCHK(launch_bbackward_rows(bw, b->prec, Rr, Tr, Ur, sm));
     HIPCHK(launch_bgrad_reduce(g, S, b->x64, b->g64, ai, Rr, Tr, Ur, b->centers3_d, b->goff_d, gd, sm));

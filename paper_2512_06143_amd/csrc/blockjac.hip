@@ -1,0 +1,323 @@
+// Block-Jacobi preconditioner of the CG solves: M = the block diagonal of K over runs
+// of 64 consecutive rows of the internal (bin-sorted) order, M = L L^T blockwise.
+//
+// The log-determinant and trace estimators use M through its Cholesky factor (the
+// probe right-hand sides are L z, the gradient's trace vectors L^-T z, and
+// ln|K| = ln|M| + ln|L^-1 K L^-T|), so one kernel per matrix factors every block and
+// stores, per block:
+//   - L (row-major 64 x 64, zero above the diagonal)      for the probe right-hand sides,
+//   - M^-1 = L^-T L^-1 in the operand order of the f64 matrix-core instruction,
+//   - the pivots L_ii^2 (sum of logs = ln|M|).
+// Applying M^-1 to a 64-row block of S residual columns is a dense 64 x 64 by 64 x S
+// product: it runs on the matrix cores (v_mfma_f64_16x16x4), fused with the CG
+// solution/residual update so that the residual block is read once.
+//
+// A ragged last block (n not a multiple of 64) is padded with identity rows and
+// columns; padded rows are never read or written outside the workgroup.
+#include "gp2s_internal.h"
+
+namespace gp2s {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int kBJThreads = 256;
+constexpr int kBJStride = kBJ + 1;  // LDS row stride of the factor kernel (doubles)
+
+// Operand order of M^-1 (per block, 4096 doubles): wave w = i / 16 owns rows
+// 16w..16w+15; for k-step kk (columns 4kk..4kk+3) lane l holds M^-1[16w + l % 16][4kk + l / 16]
+// at offset w * 1024 + kk * 64 + l, so every wave reads its operands as whole cache lines.
+template <typename V>
+__global__ __launch_bounds__(kBJThreads) void k_bj_factor(int64_t n, const int64_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ col,
+                                                          const V* __restrict__ val, double* __restrict__ Lout,
+                                                          double* __restrict__ Mfrag, double* __restrict__ piv,
+                                                          int32_t* __restrict__ bad) {
+  __shared__ double A[kBJ * kBJStride];   // block of K, then its factor L (lower part)
+  __shared__ double Li[kBJ * kBJStride];  // L^-1 (lower part)
+  const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
+  const int64_t nblk = (n + kBJ - 1) / kBJ;
+  bool failed = false;
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t r0 = blk * kBJ;
+    const int m = (int)((n - r0) < kBJ ? (n - r0) : kBJ);
+    for (int e = t; e < kBJ * kBJ; e += kBJThreads) {
+      const int i = e / kBJ, j = e % kBJ;
+      A[i * kBJStride + j] = (i == j && i >= m) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int i = wave; i < m; i += kBJThreads / kWave) {
+      const int64_t s = rp[r0 + i], e = rp[r0 + i + 1];
+      for (int64_t k = s + lane; k < e; k += kWave) {
+        const int64_t c = (int64_t)col[k] - r0;
+        if (c >= 0 && c < m) A[i * kBJStride + (int)c] = (double)val[k];
+      }
+    }
+    __syncthreads();
+    // right-looking Cholesky on the lower triangle
+    for (int k = 0; k < kBJ; ++k) {
+      if (t == 0) {
+        double d = A[k * kBJStride + k];
+        if (!(d > 0.0) || !isfinite(d)) {
+          failed = true;
+          d = 1.0;
+        }
+        A[k * kBJStride + k] = sqrt(d);
+      }
+      __syncthreads();
+      const double dk = A[k * kBJStride + k];
+      for (int i = k + 1 + t; i < kBJ; i += kBJThreads) A[i * kBJStride + k] /= dk;
+      __syncthreads();
+      const int cnt = kBJ - 1 - k;
+      for (int e = t; e < cnt * cnt; e += kBJThreads) {
+        const int ii = e / cnt, jj = e % cnt;
+        if (jj <= ii) {
+          const int i = k + 1 + ii, j = k + 1 + jj;
+          A[i * kBJStride + j] -= A[i * kBJStride + k] * A[j * kBJStride + k];
+        }
+      }
+      __syncthreads();
+    }
+    if (t < m) {
+      const double l = A[t * kBJStride + t];
+      piv[r0 + t] = l * l;
+    }
+    double* Lb = Lout + blk * (int64_t)(kBJ * kBJ);
+    for (int e = t; e < kBJ * kBJ; e += kBJThreads) {
+      const int i = e / kBJ, j = e % kBJ;
+      Lb[e] = j <= i ? A[i * kBJStride + j] : 0.0;
+    }
+    // L^-1 by forward substitution, one column per thread
+    if (t < kBJ) {
+      const int j = t;
+      for (int i = 0; i < kBJ; ++i) {
+        double v;
+        if (i < j) {
+          v = 0.0;
+        } else if (i == j) {
+          v = 1.0 / A[j * kBJStride + j];
+        } else {
+          double s = 0.0;
+          for (int k = j; k < i; ++k) s += A[i * kBJStride + k] * Li[k * kBJStride + j];
+          v = -s / A[i * kBJStride + i];
+        }
+        Li[i * kBJStride + j] = v;
+      }
+    }
+    __syncthreads();
+    // M^-1[i][j] = sum_{k >= max(i, j)} Li[k][i] Li[k][j] (the same sum for (j, i): exactly symmetric)
+    double* Mb = Mfrag + blk * (int64_t)(kBJ * kBJ);
+    for (int e = t; e < kBJ * kBJ; e += kBJThreads) {
+      const int w = e >> 10, kk = (e >> 6) & 15, l = e & 63;
+      const int i = 16 * w + (l & 15), j = 4 * kk + (l >> 4);
+      double s = 0.0;
+      for (int k = i > j ? i : j; k < kBJ; ++k) s += Li[k * kBJStride + i] * Li[k * kBJStride + j];
+      Mb[e] = s;
+    }
+    __syncthreads();
+  }
+  if (failed) atomicOr(bad, 1);
+}
+
+// One CG update with the block preconditioner, per 64-row block:
+//   INIT:  r = b, x = 0;  otherwise  x += alpha p, r -= alpha q   (columns with alpha = 0 keep r)
+//   z = M^-1 r (matrix cores), and the per-column partials of r^T z (which 0) and r^T r (which 1).
+// Thread t of the elementwise phase owns column t % S; waves own 16 rows of z each.
+// Operands of the f64 16x16x4 instruction: lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16] of a 16 x 4 by 4 x 16 step.
+template <typename VEC, bool WANTX, bool INIT>
+__global__ __launch_bounds__(kBJThreads) void k_bj_update(int64_t n, int S, const double* __restrict__ B,
+                                                          double* __restrict__ X, double* __restrict__ R,
+                                                          const VEC* __restrict__ P, const double* __restrict__ Q,
+                                                          const double* __restrict__ Mfrag, double* __restrict__ Z,
+                                                          CgState cs) {
+  __shared__ double Rs[kBJ * kBJ];  // residual block [row][column], column stride 64
+  __shared__ double red[kBJThreads / kWave][kBJ];
+  const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
+  const int nth = (kBJThreads / S) * S;
+  const int s_me = t % S;
+  const double a = (INIT || t >= nth) ? 0.0 : cs.alpha[s_me];
+  const int ntile = (S + 15) / 16;
+  const int64_t nblk = (n + kBJ - 1) / kBJ;
+  double rr = 0.0;
+  double rz[kBJ / 16] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t r0 = blk * kBJ;
+    const int m = (int)((n - r0) < kBJ ? (n - r0) : kBJ);
+    if (t < nth) {
+      for (int e = t; e < kBJ * S; e += nth) {
+        const int i = e / S;
+        double r = 0.0;
+        if (i < m) {
+          const int64_t g = r0 * S + e;
+          if (INIT) {
+            r = B[g];
+            R[g] = r;
+            if (WANTX) X[g] = 0.0;
+          } else {
+            r = R[g];
+            if (a != 0.0) {
+              if (WANTX) X[g] += a * (double)P[g];
+              r -= a * Q[g];
+              R[g] = r;
+            }
+          }
+          rr += r * r;
+        }
+        Rs[i * kBJ + s_me] = r;
+      }
+    }
+    __syncthreads();
+    const double* F = Mfrag + blk * (int64_t)(kBJ * kBJ) + wave * 1024;
+    double af[16];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) af[kk] = F[kk * 64 + lane];
+    // result layout of the f64 16x16x4 instruction: lane l, register v holds row
+    // l / 16 + 4 v, column l % 16 of the 16 x 16 tile
+    const int row_base = 16 * wave + (lane >> 4);
+#pragma unroll
+    for (int jt = 0; jt < kBJ / 16; ++jt) {
+      if (jt < ntile) {
+        const int c = 16 * jt + (lane & 15);
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+          const double bv = c < S ? Rs[(4 * kk + (lane >> 4)) * kBJ + c] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af[kk], bv, acc, 0, 0, 0);
+        }
+        if (c < S) {
+          double part = 0.0;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = row_base + 4 * v;
+            if (row < m) {
+              Z[(r0 + row) * S + c] = acc[v];
+              part += Rs[row * kBJ + c] * acc[v];
+            }
+          }
+          rz[jt] += part;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // r^T z: lanes sharing a column (lane % 16) across row groups, then across waves
+#pragma unroll
+  for (int jt = 0; jt < kBJ / 16; ++jt) {
+    double v = rz[jt];
+    v += __shfl_xor(v, 16, kWave);
+    v += __shfl_xor(v, 32, kWave);
+    if (lane < 16) red[wave][16 * jt + lane] = v;
+  }
+  __syncthreads();
+  if (t < S) {
+    double v = 0.0;
+    for (int w = 0; w < kBJThreads / kWave; ++w) v += red[w][t];
+    cs.partial[(int64_t)t * gridDim.x + blockIdx.x] = v;
+  }
+  __syncthreads();
+  // r^T r: thread t holds column t % S (threads >= nth hold zero)
+  Rs[t] = rr;
+  __syncthreads();
+  if (t < S) {
+    double v = 0.0;
+    for (int k = t; k < kBJThreads; k += S) v += Rs[k];
+    cs.partial[((int64_t)S + t) * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+// Probe right-hand sides B = L z (z = +-1 from the sign masks), per block.
+__global__ __launch_bounds__(kBJThreads) void k_bj_rhs(int64_t n, int S, const uint64_t* __restrict__ mask,
+                                                       const double* __restrict__ Lg, double* __restrict__ B) {
+  __shared__ double Ls[kBJ * kBJ];
+  __shared__ uint64_t ms[kBJ];
+  const int t = threadIdx.x;
+  const int64_t nblk = (n + kBJ - 1) / kBJ;
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t r0 = blk * kBJ;
+    const int m = (int)((n - r0) < kBJ ? (n - r0) : kBJ);
+    const double* Lb = Lg + blk * (int64_t)(kBJ * kBJ);
+    for (int e = t; e < kBJ * kBJ; e += kBJThreads) Ls[e] = Lb[e];
+    if (t < kBJ) ms[t] = t < m ? mask[r0 + t] : 0ull;
+    __syncthreads();
+    for (int e = t; e < m * S; e += kBJThreads) {
+      const int i = e / S, s = e % S;
+      double v = 0.0;
+      for (int k = 0; k <= i; ++k) {
+        const double l = Ls[i * kBJ + k];
+        v += ((ms[k] >> s) & 1ull) ? -l : l;
+      }
+      B[r0 * S + e] = v;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename VEC>
+__global__ void k_copy_dir(int64_t total, const double* __restrict__ Z, VEC* __restrict__ P) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+    P[e] = (VEC)Z[e];
+}
+
+static unsigned bj_grid(int64_t n, int64_t cap) {
+  int64_t nblk = (n + kBJ - 1) / kBJ;
+  if (nblk > cap) nblk = cap;
+  if (nblk < 1) nblk = 1;
+  return (unsigned)nblk;
+}
+
+hipError_t launch_bj_factor(int64_t n, const int64_t* rp, const int32_t* col, const void* val, int prec,
+                            double* L, double* Mfrag, double* piv, int32_t* bad, hipStream_t st) {
+  const unsigned g = bj_grid(n, 8192);
+  if (prec == GP2S_MIXED)
+    hipLaunchKernelGGL(k_bj_factor<float>, dim3(g), dim3(kBJThreads), 0, st, n, rp, col,
+                       static_cast<const float*>(val), L, Mfrag, piv, bad);
+  else
+    hipLaunchKernelGGL(k_bj_factor<double>, dim3(g), dim3(kBJThreads), 0, st, n, rp, col,
+                       static_cast<const double*>(val), L, Mfrag, piv, bad);
+  return hipGetLastError();
+}
+
+unsigned bj_update_blocks(int64_t n) { return bj_grid(n, kReduceBlocks); }
+
+hipError_t launch_bj_update(int64_t n, int S, const double* B, double* X, double* R, const void* P, const void* Q,
+                            bool f32vec, const double* Mfrag, double* Z, const CgState& cs, hipStream_t st) {
+  const unsigned g = bj_update_blocks(n);
+  const bool wx = X != nullptr;
+  const double* Qd = static_cast<const double*>(Q);
+#define GP2S_BJ(VEC, WX, INIT)                                                                                  \
+  hipLaunchKernelGGL((k_bj_update<VEC, WX, INIT>), dim3(g), dim3(kBJThreads), 0, st, n, S, B, X, R,          \
+                     static_cast<const VEC*>(P), Qd, Mfrag, Z, cs)
+  if (B) {
+    if (wx) GP2S_BJ(double, true, true);
+    else GP2S_BJ(double, false, true);
+  } else if (f32vec) {
+    if (wx) GP2S_BJ(float, true, false);
+    else GP2S_BJ(float, false, false);
+  } else {
+    if (wx) GP2S_BJ(double, true, false);
+    else GP2S_BJ(double, false, false);
+  }
+#undef GP2S_BJ
+  return hipGetLastError();
+}
+
+hipError_t launch_bj_rhs(int64_t n, int S, const uint64_t* mask, const double* L, double* B, hipStream_t st) {
+  hipLaunchKernelGGL(k_bj_rhs, dim3(bj_grid(n, 8192)), dim3(kBJThreads), 0, st, n, S, mask, L, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_dir(int64_t n, int S, const double* Z, void* P, bool f32vec, hipStream_t st) {
+  int64_t total = n * (int64_t)S;
+  int64_t blocks = (total + kBlock - 1) / kBlock;
+  if (blocks > (1 << 16)) blocks = 1 << 16;
+  if (blocks < 1) return hipSuccess;
+  if (f32vec)
+    hipLaunchKernelGGL(k_copy_dir<float>, dim3((unsigned)blocks), dim3(kBlock), 0, st, total, Z,
+                       static_cast<float*>(P));
+  else
+    hipLaunchKernelGGL(k_copy_dir<double>, dim3((unsigned)blocks), dim3(kBlock), 0, st, total, Z,
+                       static_cast<double*>(P));
+  return hipGetLastError();
+}
+
+}  // namespace gp2s

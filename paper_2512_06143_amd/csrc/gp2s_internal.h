@@ -16,6 +16,7 @@ constexpr int kBlock = 256;        // threads per workgroup for streaming kernel
 constexpr int kMaxProbes = 64;     // one probe per lane in the block kernels
 constexpr int kMaxBumps = 256;
 constexpr int kReduceBlocks = 4096;  // max workgroups of the reduction-carrying kernels
+constexpr int kBJ = 64;             // rows per block of the block-Jacobi preconditioner
 
 // Uniform grid of cubic bins with side h >= r (slightly enlarged so that rounding
 // in the bin index can never separate two points closer than r by two bins).
@@ -241,6 +242,20 @@ hipError_t launch_gather_rows(int64_t n, int S, const int32_t* perm, const doubl
                               double* dst_int, hipStream_t st);
 hipError_t launch_scatter_rows(int64_t n, int S, const int32_t* perm, const double* src_int,
                                double* dst_user, hipStream_t st);
+hipError_t launch_cg_init_fin(const CgState& cs, int nb, int S, double tol, hipStream_t st);
+hipError_t launch_cg_beta(const CgState& cs, int nb, int S, int32_t iter, hipStream_t st);
+
+// blockjac.hip: block-Jacobi factor (L, M^-1 in matrix-core operand order, pivots
+// L_ii^2; bad != 0 when a block is not positive definite), the fused update
+// (B != nullptr: initialisation r = B, x = 0) with z = M^-1 r, the probe right-hand
+// sides L z, and the direction copy P = Z.
+hipError_t launch_bj_factor(int64_t n, const int64_t* rp, const int32_t* col, const void* val, int prec,
+                            double* L, double* Mfrag, double* piv, int32_t* bad, hipStream_t st);
+unsigned bj_update_blocks(int64_t n);
+hipError_t launch_bj_update(int64_t n, int S, const double* B, double* X, double* R, const void* P, const void* Q,
+                            bool f32vec, const double* Mfrag, double* Z, const CgState& cs, hipStream_t st);
+hipError_t launch_bj_rhs(int64_t n, int S, const uint64_t* mask, const double* L, double* B, hipStream_t st);
+hipError_t launch_copy_dir(int64_t n, int S, const double* Z, void* P, bool f32vec, hipStream_t st);
 hipError_t launch_probe_rhs(int64_t n, int S, const uint64_t* mask, const double* diag, double* B,
                             hipStream_t st);
 hipError_t launch_dinv(int64_t n, const double* diag, double* dinv, int32_t* bad, hipStream_t st);
@@ -264,6 +279,8 @@ struct BackwardArgs {
   const double* Q;        // [n * S] probe solutions (internal order)
   const uint64_t* mask;   // [n] probe sign bits
   const double* dinv;     // [n] 1 / K_ii
+  const double* W;        // [n * S] trace vectors w_s (block preconditioner), or nullptr:
+                          // w_s = D^-1/2 z_s from the signs and dinv
   int64_t n;
   int S;
   double radius, r2, inv_r2;
@@ -322,6 +339,7 @@ struct BBackward {
   const double* Q;
   const uint64_t* mask;
   const double* dinv;
+  const double* g64;  // [n_total] bump values (float64; the mixed path's dK is evaluated in float64)
   int S;
 };
 hipError_t launch_bbackward_rows(const BBackward& b, int prec, double* Rrow, double* Trow, double* Urow,

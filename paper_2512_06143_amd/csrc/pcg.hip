@@ -193,7 +193,8 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, int S, VEC* __
   const double b = cs.beta[s_me];
   for (int64_t e = blockIdx.x * (int64_t)nth + threadIdx.x; e < total; e += (int64_t)gridDim.x * nth) {
     const int64_t i = e / S;
-    P[e] = (VEC)(R[e] * dinv[i] + b * (double)P[e]);
+    const double z = dinv ? R[e] * dinv[i] : R[e];  // dinv == nullptr: R holds z = M^-1 r
+    P[e] = (VEC)(z + b * (double)P[e]);
   }
 }
 
@@ -245,6 +246,16 @@ hipError_t launch_cg_update(int64_t n, int S, double* X, double* R, const void* 
     hipLaunchKernelGGL((k_cg_update<double, false>), dim3(nb), dim3(nth), 0, st, n, S, X, R,
                        static_cast<const double*>(P), static_cast<const double*>(Q), dinv, cs, iter);
   hipLaunchKernelGGL(k_cg_beta, dim3(S), dim3(kBlock), 0, st, cs, (int)nb, S, iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_init_fin(const CgState& cs, int nb, int S, double tol, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_init_fin, dim3(S), dim3(kBlock), 0, st, cs, nb, S, tol);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_beta(const CgState& cs, int nb, int S, int32_t iter, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_beta, dim3(S), dim3(kBlock), 0, st, cs, nb, S, iter);
   return hipGetLastError();
 }
 

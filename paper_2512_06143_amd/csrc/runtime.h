@@ -71,6 +71,11 @@ struct gp2s_matrix_s {
   double* diag = nullptr;
   double* dinv = nullptr;
   bool diag_ok = true;
+  // block-Jacobi factor (built on first use, dropped when the values change)
+  double* bj_L = nullptr;    // [nblk * 64 * 64] row-major L per block
+  double* bj_M = nullptr;    // [nblk * 64 * 64] M^-1 per block, matrix-core operand order
+  double* bj_piv = nullptr;  // [n] L_ii^2
+  bool bj_ready = false;
   std::vector<void*> owned;
 };
 
@@ -261,6 +266,8 @@ inline gp2s_status check_opts(gp2s_ctx ctx, const gp2s_solve_opts* o, bool need_
   if (!is_fin(o->tol) || o->tol <= 0 || o->tol >= 1) return fail(ctx, GP2S_E_INVALID, "tol must be in (0, 1)");
   if (!is_fin(o->probe_tol) || o->probe_tol <= 0 || o->probe_tol >= 1)
     return fail(ctx, GP2S_E_INVALID, "probe_tol must be in (0, 1)");
+  if (o->precond != GP2S_PRECOND_JACOBI && o->precond != GP2S_PRECOND_BLOCK)
+    return fail(ctx, GP2S_E_INVALID, "precond must be GP2S_PRECOND_JACOBI (0) or GP2S_PRECOND_BLOCK (1)");
   return GP2S_OK;
 }
 

@@ -47,7 +47,10 @@ WENDLAND = {"c2": 0, "c6": 1}  # Wendland member: C^2, or the printed C^6 of Eq.
 class SolveOpts(ctypes.Structure):
     _fields_ = [("n_probes", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("max_ir", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("seed", ctypes.c_uint64), ("tol", ctypes.c_double),
-                ("probe_tol", ctypes.c_double)]
+                ("probe_tol", ctypes.c_double), ("precond", ctypes.c_int32)]
+
+
+PRECOND = {"jacobi": 0, "block": 1}  # preconditioner of the CG solves (include/gp2s.h)
 
 
 NUM_TIMERS = 16
@@ -132,6 +135,8 @@ def default_opts(**kw) -> SolveOpts:
     for k, v in kw.items():
         if not hasattr(o, k):
             raise TypeError(f"unknown solver option {k}")
+        if k == "precond" and isinstance(v, str):
+            v = PRECOND[v]
         setattr(o, k, v)
     return o
 

@@ -11,6 +11,24 @@ def params_of(prob):
     return G.HostParams(prob.dim, prob.radius, prob.bump_width, prob.noise_var, prob.centers, prob.weights)
 
 
+def oracle_blocks(x, radius, precond="block"):
+    """The preconditioner blocks the oracle's estimators need for a handle assembled
+    from x with support radius r: None (diagonal) or runs of 64 points of the binned
+    order, computed by the oracle from its own definition."""
+    import oracle
+    if precond in ("jacobi", 0):
+        return None
+    return oracle.block_partition(oracle.bin_order(x, radius), oracle.BLOCK)
+
+
+def imported_blocks(n, precond="block"):
+    """The same for an imported handle (its order is the given one)."""
+    import oracle
+    if precond in ("jacobi", 0):
+        return None
+    return oracle.block_partition(np.arange(n), oracle.BLOCK)
+
+
 def exported_user_csr(m):
     """The handle's CSR as a scipy matrix in user order (values promoted to float64)."""
     rp, col, val, perm = m.export()

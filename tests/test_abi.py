@@ -22,7 +22,7 @@ def test_every_declared_symbol_is_exported():
     for n in names:
         assert hasattr(B.lib, n), n
     assert set(names) == set(B.EXPORTED)
-    assert B.lib.gp2s_abi_version() == 1
+    assert B.lib.gp2s_abi_version() == 2
 
 
 def _ctx():

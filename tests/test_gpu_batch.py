@@ -32,7 +32,7 @@ def test_batch_matches_single_runs_and_oracle(gpu, precision):
     G = _G()
     probs = _instances()
     S = 16
-    opts = G.default_opts(n_probes=S, seed=5, tol=1e-10, probe_tol=1e-9, max_iter=30000)
+    opts = G.default_opts(n_probes=S, seed=5, tol=1e-10, probe_tol=1e-9, max_iter=30000, precond="jacobi")
     b = G.Batch([p.x for p in probs], [params_of(p) for p in probs], precision, opts)
     info = b.info()
     print(f"[batch/{precision}] {info}", flush=True)
@@ -60,7 +60,7 @@ def test_batch_matches_single_runs_and_oracle(gpu, precision):
 def test_batch_new_hyperparameters_and_capacity(gpu):
     G = _G()
     probs = _instances()[:3]
-    opts = G.default_opts(n_probes=8, seed=1, tol=1e-9, probe_tol=1e-7)
+    opts = G.default_opts(n_probes=8, seed=1, tol=1e-9, probe_tol=1e-7, precond="jacobi")
     b = G.Batch([p.x for p in probs], [params_of(p) for p in probs], "fp64", opts)
     # smaller radius and new weights / noise: equals a fresh single-instance evaluation
     new = []

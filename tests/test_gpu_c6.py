@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import workloads
-from gpu_util import exported_user_csr, rel_entry_errors
+from gpu_util import exported_user_csr, oracle_blocks, rel_entry_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -52,9 +52,10 @@ def test_c6_entries_lml_grad_posterior(gpu, name, precision):
     rep, grad, a = G.gp2s_lml_grad(m, prob.y, opts)
     Kd = Kg.toarray()
     Z = oracle.rademacher_probes(11, S, prob.n)
-    gam, _ = oracle.logdet_same_probe(Kd, Z)
+    blocks = oracle_blocks(prob.x, prob.radius)
+    gam, _ = oracle.logdet_same_probe(Kd, Z, blocks)
     assert abs(rep.logdet - gam) <= 1e-8 * abs(gam)
-    gref, parts = oracle.grad_same_probe(prob.x, prob.y, Z, K=Kd, kernel="c6", **kw)
+    gref, parts = oracle.grad_same_probe(prob.x, prob.y, Z, K=Kd, kernel="c6", blocks=blocks, **kw)
     scale = np.maximum(np.abs(gref), 1e-6 * (np.abs(parts["fit"]) + 0.5 * np.abs(parts["tau"])))
     gerr = np.abs(grad - gref) / scale
     print(f"[{name}/{precision}] logdet rel {abs(rep.logdet - gam) / abs(gam):.2e} grad max rel {gerr.max():.2e}",
@@ -77,7 +78,7 @@ def test_c6_entries_lml_grad_posterior(gpu, name, precision):
 def test_c6_batch_matches_single(gpu):
     G = _G()
     probs = [CASES["ragged2d"](), workloads.make_random_problem(43, 1800, 3, 0.11, n_bumps=2, bump_width=0.6)]
-    opts = G.default_opts(n_probes=8, seed=2, tol=1e-10, probe_tol=1e-9, max_iter=30000)
+    opts = G.default_opts(n_probes=8, seed=2, tol=1e-10, probe_tol=1e-9, max_iter=30000, precond="jacobi")
     b = G.Batch([p.x for p in probs], [_params(G, p) for p in probs], "fp64", opts)
     lml, grads, _ = b.run([p.y for p in probs])
     for i, p in enumerate(probs):

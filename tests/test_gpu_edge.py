@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import workloads
-from gpu_util import compare_patterns, exported_user_csr, params_of, pattern_pairs
+from gpu_util import compare_patterns, exported_user_csr, imported_blocks, params_of, pattern_pairs
 
 pytestmark = pytest.mark.gpu
 
@@ -120,7 +120,7 @@ def test_imported_oracle_matrix(gpu, precision):
     np.testing.assert_allclose(G.gp2s_spmv(m, X).cpu().numpy(), Kt @ X, rtol=1e-12, atol=1e-12)
     rep, a = G.gp2s_lml(m, prob.y, G.default_opts(n_probes=8, seed=2, tol=1e-10, probe_tol=1e-9))
     Z = oracle.rademacher_probes(2, 8, prob.n)
-    gam, _ = oracle.logdet_same_probe(Kt.toarray(), Z)
+    gam, _ = oracle.logdet_same_probe(Kt.toarray(), Z, imported_blocks(prob.n))
     assert abs(rep.logdet - gam) <= 1e-8 * abs(gam)
     assert oracle.residual_rel(Kt, a.cpu().numpy(), prob.y) <= 1e-10
     with pytest.raises(G.GP2SError) as e:

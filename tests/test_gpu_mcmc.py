@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workloads
-from gpu_util import exported_user_csr, params_of
+from gpu_util import exported_user_csr, oracle_blocks, params_of
 
 pytestmark = pytest.mark.gpu
 
@@ -70,7 +70,7 @@ def test_sampler_follows_oracle_decisions(gpu):
 
     def loglik(th):
         K = oracle.covariance_dense(prob.x, th[0], prob.bump_width, prob.centers, th[1:3], th[3])
-        return oracle.lml_same_probe(K, prob.y, Z)[0]
+        return oracle.lml_same_probe(K, prob.y, Z, oracle_blocks(prob.x, th[0]))[0]
     chain_o, lls_o, acc_o, marg_o = oracle.block_mh(theta0, blocks, steps, bounds[0], bounds[1], draws, loglik)
     mh = G.BlockMH(prob.x, prob.y, p0, "fp64", opts, blocks=blocks, steps=steps, bounds=bounds)
     res = mh.run(len(draws), draws=draws)

@@ -4,14 +4,17 @@ Tolerances (float32-assembled path unless stated): sparsity pattern exact except
 pairs within 1e-6 of the support boundary; K entries 1e-5 relative (float64 path
 1e-9); ||y - K a|| / ||y|| <= 1e-8 recomputed on the CPU from the exported CSR;
 the same-probe log-determinant within 1e-8 relative; the same-probe gradient within
-1e-4 relative per component (floor 1e-6 of the magnitude of its two halves).
+1e-4 relative per component (floor 1e-6 of the magnitude of its two halves). The
+same-probe values depend on the preconditioner, so the oracle is given the same one
+(the diagonal, or blocks of 64 points of its own binned order).
 """
 import numpy as np
 import pytest
 
 import oracle
 import workloads
-from gpu_util import compare_patterns, exported_user_csr, params_of, pattern_pairs, rel_entry_errors
+from gpu_util import (compare_patterns, exported_user_csr, oracle_blocks, params_of, pattern_pairs,
+                      rel_entry_errors)
 
 pytestmark = pytest.mark.gpu
 
@@ -101,32 +104,34 @@ def test_solve_residual_and_solution(case, precision):
     np.testing.assert_allclose(a, ref.a, rtol=0, atol=1e-5 * np.abs(ref.a).max())
 
 
+@pytest.mark.parametrize("precond", ["jacobi", "block"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_lml_and_gradient_same_probe(case, precision):
+def test_lml_and_gradient_same_probe(case, precision, precond):
     G = _G()
     name, prob, Kref, gamma, ex_pts = case
     S = 16
     m = G.gp2s_assemble(prob.x, params_of(prob), precision)
     Kg, _ = exported_user_csr(m)
-    opts = G.default_opts(n_probes=S, seed=7, tol=1e-10, probe_tol=1e-10, max_iter=40000)
+    opts = G.default_opts(n_probes=S, seed=7, tol=1e-10, probe_tol=1e-10, max_iter=40000, precond=precond)
     rep, grad, a = G.gp2s_lml_grad(m, prob.y, opts)
     Z = oracle.rademacher_probes(7, S, prob.n)
     Kd = Kg.toarray()
-    gam_ref, terms = oracle.logdet_same_probe(Kd, Z)
+    blocks = oracle_blocks(prob.x, prob.radius, precond)
+    gam_ref, terms = oracle.logdet_same_probe(Kd, Z, blocks)
     rel = abs(rep.logdet - gam_ref) / abs(gam_ref)
-    lml_ref, parts = oracle.lml_same_probe(Kd, prob.y, Z)
+    lml_ref, parts = oracle.lml_same_probe(Kd, prob.y, Z, blocks)
     exact = oracle.lml_dense(Kref.toarray(), prob.y)
-    print(f"[{name}/{precision}] logdet gpu={rep.logdet:.10f} oracle(same probes)={gam_ref:.10f} rel={rel:.2e} "
+    print(f"[{name}/{precision}/{precond}] logdet gpu={rep.logdet:.10f} oracle(same probes)={gam_ref:.10f} rel={rel:.2e} "
           f"exact={exact.logdet:.6f} stderr={rep.logdet_stderr:.3f} iters={rep.iters}/{rep.probe_iters}",
           flush=True)
     assert rel <= 1e-8
     assert abs(rep.lml - lml_ref) <= 1e-8 * abs(lml_ref)
     assert abs(rep.logdet - exact.logdet) <= 5 * rep.logdet_stderr + 1e-6 * abs(exact.logdet)
     gref, gparts = oracle.grad_same_probe(prob.x, prob.y, Z, prob.radius, prob.bump_width, prob.centers,
-                                          prob.weights, prob.noise_var, K=Kd)
+                                          prob.weights, prob.noise_var, K=Kd, blocks=blocks)
     scale = np.maximum(np.abs(gref), 1e-6 * (np.abs(gparts["fit"]) + 0.5 * np.abs(gparts["tau"])))
     err = np.abs(grad - gref) / scale
-    print(f"[{name}/{precision}] grad max rel err {err.max():.2e}\n gpu={grad}\n ref={gref}", flush=True)
+    print(f"[{name}/{precision}/{precond}] grad max rel err {err.max():.2e}\n gpu={grad}\n ref={gref}", flush=True)
     assert np.all(err <= 1e-4)
     for k in range(len(gref)):
         if gref[k] == 0.0:
@@ -170,9 +175,10 @@ def test_probe_block_variants_same_probe(case, precision):
     Kd = exported_user_csr(m)[0].toarray()
     opts = G.default_opts(n_probes=S, seed=3, tol=1e-10, probe_tol=1e-10, max_iter=40000)
     Z = oracle.rademacher_probes(3, S, prob.n)
-    gam_ref, _ = oracle.logdet_same_probe(Kd, Z)
+    blocks = oracle_blocks(prob.x, prob.radius)  # the default preconditioner
+    gam_ref, _ = oracle.logdet_same_probe(Kd, Z, blocks)
     gref, gparts = oracle.grad_same_probe(prob.x, prob.y, Z, prob.radius, prob.bump_width, prob.centers,
-                                          prob.weights, prob.noise_var, K=Kd)
+                                          prob.weights, prob.noise_var, K=Kd, blocks=blocks)
     scale = np.maximum(np.abs(gref), 1e-6 * (np.abs(gparts["fit"]) + 0.5 * np.abs(gparts["tau"])))
     for v in BLOCK_VARIANTS:
         m.set_block_product(S, v)
