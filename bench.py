@@ -119,9 +119,11 @@ def cpu_baseline(prob, nnz_full, iters_y, iters_probe, S, budget_points=250_000,
     """The oracle as it stands on a bounded sample: the points inside a square window
     (about budget_points of them) around the densest cluster centre region of the same
     point cloud. Times oracle.covariance_csr (assembly) and oracle.pcg_jacobi per
-    iteration, then scales by the full instance's nnz and the GPU run's iteration
-    counts (y solve + one single-RHS solve per probe). The oracle has no sparse
-    gradient, so the projection omits the backward pass (a lower bound)."""
+    iteration, then scales by the full instance's nnz and by the iteration counts of
+    Jacobi-preconditioned CG on the full instance (the oracle's own solver; counts
+    measured on the GPU with the diagonal preconditioner): the y solve plus one
+    single-RHS solve per probe. The oracle has no sparse gradient, so the projection
+    omits the backward pass (a lower bound)."""
     import numpy as np
     import oracle
     x = prob.x
@@ -156,8 +158,8 @@ def cpu_baseline(prob, nnz_full, iters_y, iters_probe, S, budget_points=250_000,
         "sample": (f"{int(sel.sum())} points in a square window of the same cloud ({K.nnz} nnz); "
                    f"oracle.covariance_csr {t_asm:.2f}s, oracle.pcg_jacobi {t_it * 1e3:.1f} ms/iteration over "
                    f"{k_iter} iterations; "
-                   f"scaled by nnz x{scale:.1f} and by the GPU iteration counts ({iters_y} y + {S}x{iters_probe} "
-                   f"probe); gradient pass not included"),
+                   f"scaled by nnz x{scale:.1f} and by the Jacobi-PCG iteration counts of the full instance "
+                   f"({iters_y} y + {S}x{iters_probe} probe); gradient pass not included"),
         "assembly_nnz_per_s": K.nnz / t_asm,
     }
 
@@ -236,7 +238,8 @@ def bench_batch(args):
     xs = [torch.as_tensor(p.x).cuda() for p in probs]
     ys = [torch.as_tensor(p.y).cuda() for p in probs]
     params = [G.HostParams(p.dim, p.radius, p.bump_width, p.noise_var, p.centers, p.weights) for p in probs]
-    opts = G.default_opts(n_probes=S, max_iter=args.max_iter, tol=args.tol, probe_tol=args.probe_tol, check_every=32)
+    opts = G.default_opts(n_probes=S, max_iter=args.max_iter, tol=args.tol, probe_tol=args.probe_tol, check_every=32,
+                          precond="jacobi")  # the batched path uses the diagonal preconditioner
     ctx = G.default_context()
     b = G.Batch(xs, params, args.precision, opts, ctx)
     info = b.info()
@@ -288,6 +291,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-predict", action="store_true", help="skip the posterior (test-point) measurement")
     ap.add_argument("--no-mcmc", action="store_true", help="skip the block Metropolis-Hastings sweep")
+    ap.add_argument("--precond", default="block", choices=["block", "jacobi"],
+                    help="preconditioner of the timed step (the other one is timed once beside it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -320,7 +325,7 @@ def main():
     y = torch.as_tensor(prob.y).cuda()
     params = G.HostParams(prob.dim, prob.radius, prob.bump_width, prob.noise_var, prob.centers, prob.weights)
     opts = G.default_opts(n_probes=S, max_iter=args.max_iter, tol=args.tol, probe_tol=args.probe_tol,
-                          check_every=32)
+                          check_every=32, precond=args.precond)
     ctx = G.default_context()
     last = [0.0]
 
@@ -384,7 +389,8 @@ def main():
         "config": {"workload": (f"{args.config}: {n} {prob.meta.get('points', 'uniform')} {prob.dim}-D points, "
                                 f"r={prob.radius:.6g} "
                                 f"({nnz / n:.1f} stored/row), {prob.n_bumps} bumps, {S} probes"),
-                   "n": n, "nnz": nnz, "probes": S, "precision": args.precision, "parallelism": "single GPU"},
+                   "n": n, "nnz": nnz, "probes": S, "precision": args.precision, "precond": args.precond,
+                   "parallelism": "single GPU"},
         "assembly_ms": asm_ms, "assembly_nnz_per_s": nnz / (asm_ms / 1e3) if asm_ms else None,
         "cg_spmv_GBps": spmv_gbs,
         "iters_y": rep.iters, "iters_probe": rep.probe_iters, "ir_steps": rep.ir_steps,
@@ -395,6 +401,24 @@ def main():
         "kernels_ms": {k: round(v[0] / args.steps, 3) for k, v in per.items()},
         "roofline": roof,
     }
+    # the same step with the diagonal preconditioner (the comparison of preconditioners, and
+    # the iteration counts of the oracle's own Jacobi PCG for the CPU projection)
+    jac_iters = (rep.iters, rep.probe_iters)
+    if args.precond != "jacobi":
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep_j, _, _, _ = run_step(G, x, y, params, args.precision, G.default_opts(
+            n_probes=S, max_iter=args.max_iter, tol=args.tol, probe_tol=args.probe_tol, check_every=32,
+            precond="jacobi"))
+        torch.cuda.synchronize()
+        tj = time.perf_counter() - t0
+        jac_iters = (rep_j.iters, rep_j.probe_iters)
+        out["jacobi_s_per_lml_grad"] = tj
+        out["jacobi_iters"] = list(jac_iters)
+        out["jacobi_lml"] = rep_j.lml
+        out["jacobi_logdet_stderr"] = rep_j.logdet_stderr
+        log(f"[bench] jacobi preconditioner: {tj:.2f}s iters y={rep_j.iters} probes={rep_j.probe_iters} "
+            f"lml={rep_j.lml:.6f} (stderr of ln|K| {rep_j.logdet_stderr:.1f} vs {rep.logdet_stderr:.1f})")
     if not args.no_fp64 and args.precision == "mixed":
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -412,7 +436,7 @@ def main():
         out["mcmc"] = bench_mcmc(G, x, y, params, args.precision, opts)
     if not args.no_cpu:
         t0 = time.perf_counter()
-        out["cpu_baseline"] = cpu_baseline(prob, nnz, rep.iters, rep.probe_iters, S)
+        out["cpu_baseline"] = cpu_baseline(prob, nnz, jac_iters[0], jac_iters[1], S)
         log(f"[bench] cpu baseline took {time.perf_counter() - t0:.1f}s")
     print(json.dumps(out), flush=True)
 
