@@ -18,7 +18,9 @@ computes, written from the paper (arXiv 2512.06143):
   binned point order) that the estimators are defined with;
 * the posterior mean and variance of the latent function at test points (Sec. 2,
   Eq. posterior);
-* the block Metropolis-Hastings sampler of the hyperparameters (Sec. 3.5, App. D).
+* the block Metropolis-Hastings sampler of the hyperparameters (Sec. 3.5, App. D);
+* the non-stationary convolution Wendland kernel (Sec. 3.2, Eq. wendconv) with an
+  axis-anisotropic, bump-driven length-scale field (``oracle.wendconv``).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package. The product library never calls it, and it
@@ -28,7 +30,8 @@ Every function documents the passage it follows, and states the reading it takes
 where the paper is silent or garbled.
 """
 from .kernel import (wendland_c2, wendland_c2_dr, wendland_c6, wendland_c6_dr, wendland, wendland_dr,
-                     KERNELS, bump_values, kernel_params_check)
+                     wendland_dlog, KERNELS, bump_values, kernel_params_check)
+from . import wendconv
 from .pattern import (pairwise_sqdist, pattern_bruteforce, pattern_kdtree, mean_row_count,
                       boundary_exempt_pairs, boundary_exempt_points)
 from .dense import covariance_dense, dcov_dense, lml_dense, grad_exact, LMLResult
@@ -40,7 +43,8 @@ from .mcmc import block_mh
 from .precond import BLOCK, grid, bin_coords, bin_order, block_partition, jacobi_partition, block_factor
 
 __all__ = [
-    "wendland_c2", "wendland_c2_dr", "wendland_c6", "wendland_c6_dr", "wendland", "wendland_dr", "KERNELS",
+    "wendland_c2", "wendland_c2_dr", "wendland_c6", "wendland_c6_dr", "wendland", "wendland_dr", "wendland_dlog",
+    "KERNELS", "wendconv",
     "bump_values", "kernel_params_check",
     "pairwise_sqdist", "pattern_bruteforce", "pattern_kdtree", "mean_row_count",
     "boundary_exempt_pairs", "boundary_exempt_points",

@@ -84,11 +84,12 @@ def lml_dense(K, y):
     return LMLResult(lml, logdet, yTa, a)
 
 
-def grad_exact(x, y, radius, bump_width, centers, weights, noise_var, kernel="c2"):
+def grad_exact(x, y, radius, bump_width, centers, weights, noise_var, kernel="c2", dcov=None):
     """Exact gradient (n_bumps + 2,) in the order (r, a_1..a_P, sigma_n^2), with
     K^{-1} formed from the Cholesky factor. Also returns the two halves
-    (data-fit 1/2 a^T dK a and trace 1/2 tr(K^{-1} dK)) for diagnostics."""
-    K, dKs = dcov_dense(x, radius, bump_width, centers, weights, noise_var, kernel)
+    (data-fit 1/2 a^T dK a and trace 1/2 tr(K^{-1} dK)) for diagnostics. dcov = (K, [dK])
+    of another kernel replaces the stationary one."""
+    K, dKs = dcov if dcov is not None else dcov_dense(x, radius, bump_width, centers, weights, noise_var, kernel)
     res = lml_dense(K, y)
     c = scipy.linalg.cho_factor(K, lower=True)
     Kinv = scipy.linalg.cho_solve(c, np.eye(K.shape[0]))

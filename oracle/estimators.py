@@ -72,9 +72,11 @@ def hutchinson_variance(A, n_probes):
     return 2.0 * (np.sum(A * A) - np.sum(np.diag(A) ** 2)) / n_probes
 
 
-def grad_same_probe(x, y, Z, radius, bump_width, centers, weights, noise_var, K=None, kernel="c2", blocks=None):
-    """Ghat (P+2,) in the order (r, a_1..a_P, sigma_n^2), plus its halves."""
-    K_, dKs = dcov_dense(x, radius, bump_width, centers, weights, noise_var, kernel)
+def grad_same_probe(x, y, Z, radius, bump_width, centers, weights, noise_var, K=None, kernel="c2", blocks=None,
+                    dcov=None):
+    """Ghat (P+2,) in the order (r, a_1..a_P, sigma_n^2), plus its halves. dcov = (K, [dK])
+    of another kernel (``oracle.wendconv.dcov_dense``) replaces the stationary one."""
+    K_, dKs = dcov if dcov is not None else dcov_dense(x, radius, bump_width, centers, weights, noise_var, kernel)
     K = K_ if K is None else np.asarray(K, dtype=np.float64)
     res = lml_dense(K, y)
     L, Linv, _ = _factor(K, blocks)

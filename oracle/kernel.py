@@ -66,6 +66,24 @@ def wendland_c6_dr(rho, r):
 KERNELS = ("c2", "c6")
 
 
+def wendland_dlog(rho, kernel="c2"):
+    """D(rho) = -W'(rho) / rho inside the support (0 outside): 20 (1 - rho)^3 for the C^2
+    member, 22 (1 - rho)^7 (16 rho^2 + 7 rho + 1) for the C^6 member. Finite at rho = 0;
+    the radius derivative is D(rho) rho^2 / r."""
+    rho = np.asarray(rho, dtype=np.float64)
+    out = np.zeros_like(rho)
+    inside = rho < 1.0
+    p = rho[inside]
+    q = 1.0 - p
+    if kernel == "c2":
+        out[inside] = 20.0 * q ** 3
+    elif kernel == "c6":
+        out[inside] = 22.0 * q ** 7 * (16.0 * p * p + 7.0 * p + 1.0)
+    else:
+        raise ValueError(f"unknown Wendland member {kernel!r}")
+    return out
+
+
 def wendland(rho, kernel="c2"):
     """The Wendland member selected by `kernel`: "c2" (the workloads' member) or "c6"
     (Eq. wendland as printed)."""

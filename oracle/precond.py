@@ -24,39 +24,46 @@ import numpy as np
 BLOCK = 64
 
 
-def grid(x, radius):
-    """(origin, h, nb): the bin grid for points x (n, dim) and support radius r.
-    h = r (1 + 1e-6), widened if needed so that the number of cells stays within
-    max(4 n, 65536); nb[k] = floor((hi_k - lo_k) / h) + 1 cells along axis k."""
+def grid(x, radius, ell_bound=1.0):
+    """(origin, h, nb): the bin grid for points x (n, dim), support radius r (a scalar,
+    or one radius per axis) and the bound of the length-scale field l(x) (1 for a
+    stationary kernel). Along axis k, h_k = r_k (1 + 1e-6), times the bound when it is
+    not 1; all h_k are widened by a common factor if needed so that the number of
+    cells stays within max(4 n, 65536); nb[k] = floor((hi_k - lo_k) / h_k) + 1."""
     x = np.asarray(x, dtype=np.float64)
     n, dim = x.shape
+    r = np.asarray(radius, dtype=np.float64).reshape(-1)
+    radii = [float(r[0])] * dim if r.size == 1 else [float(v) for v in r]
     lo, hi = x.min(axis=0), x.max(axis=0)
-    h = float(radius) * (1.0 + 1e-6)
+    h = [rk * (1.0 + 1e-6) for rk in radii]
+    if ell_bound != 1.0:
+        h = [hk * ell_bound for hk in h]
     max_bins = max(4.0 * n, 65536.0)
     for _ in range(64):
         total = 1.0
         for k in range(dim):
-            total *= np.floor((hi[k] - lo[k]) / h) + 1.0
+            total *= np.floor((hi[k] - lo[k]) / h[k]) + 1.0
         if total <= max_bins:
             break
-        h *= (total / max_bins) ** (1.0 / dim) * 1.01
-    nb = [int(np.floor((hi[k] - lo[k]) / h) + 1.0) for k in range(dim)]
-    return lo, h, nb
+        f = (total / max_bins) ** (1.0 / dim) * 1.01
+        h = [hk * f for hk in h]
+    nb = [int(np.floor((hi[k] - lo[k]) / h[k]) + 1.0) for k in range(dim)]
+    return lo, np.array(h), nb
 
 
-def bin_coords(x, radius):
-    """(n, dim) integer cell coordinates floor((x_k - lo_k) / h), clamped to the grid."""
+def bin_coords(x, radius, ell_bound=1.0):
+    """(n, dim) integer cell coordinates floor((x_k - lo_k) (1 / h_k)), clamped to the grid."""
     x = np.asarray(x, dtype=np.float64)
-    lo, h, nb = grid(x, radius)
+    lo, h, nb = grid(x, radius, ell_bound)
     inv_h = 1.0 / h
-    c = np.floor((x - lo[None, :]) * inv_h)
+    c = np.floor((x - lo[None, :]) * inv_h[None, :])
     return np.clip(c, 0, np.array(nb) - 1).astype(np.int64), nb
 
 
-def bin_order(x, radius):
+def bin_order(x, radius, ell_bound=1.0):
     """perm (n,) int64: perm[p] is the user index of the point at position p when the
     points are sorted by cell number (first coordinate fastest), ties by user index."""
-    c, nb = bin_coords(x, radius)
+    c, nb = bin_coords(x, radius, ell_bound)
     key = np.zeros(c.shape[0], dtype=np.int64)
     for k in range(c.shape[1] - 1, -1, -1):
         key = key * nb[k] + c[:, k]
