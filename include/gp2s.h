@@ -68,7 +68,21 @@ typedef void* (*gp2s_alloc_fn)(size_t bytes, void* user);
 typedef void (*gp2s_free_fn)(void* ptr, void* user);
 
 /* Kernel hyperparameters theta = (r, a_1..a_P, sigma_n^2) plus the fixed bump
- * geometry (centres and width are not differentiated). */
+ * geometry (centres and width are not differentiated).
+ *
+ * K_ij = g_i g_j W(rho_ij) + sigma_n^2 [i == j], g the bump mask (Sec. 3.3). With
+ * radii == NULL and ls_weights == NULL (zero-initialised params) the kernel is the
+ * stationary product construction of Sec. 3.1, rho = ||x_i - x_j|| / r. Otherwise it
+ * is the non-stationary convolution form of Eq. wendconv (Sec. 3.2) with
+ * S(x) = diag(r_1^2..r_d^2) l(x)^2 and signal deviation g:
+ *   l(x) = exp(sum_q c_q bhat_q(x))  (bhat_q the unweighted bumps; l = 1 without ls_weights),
+ *   m_ij = (l_i^2 + l_j^2) / 2,  Q_ij = sum_k ((x_ik - x_jk) / r_k)^2 / m_ij,
+ *   K_ij = g_i g_j (l_i l_j / m_ij)^{d/2} W(sqrt(Q_ij)),  stored where Q_ij < 1,
+ * r_k = radii[k], or r for every axis without radii. The gradient then holds
+ * (r or r_1..r_d, a_1..a_P, [c_1..c_P when ls_weights is given], sigma_n^2). This
+ * construction is not positive semi-definite for every choice of the parameters (the
+ * argument for it assumes a Gaussian scale mixture, which a Wendland function is
+ * not); solves report GP2S_E_NOT_SPD when K is not positive definite. */
 typedef struct {
   int32_t dim;            /* 2 or 3                                                  */
   int32_t n_bumps;        /* P, 1..256                                               */
@@ -81,6 +95,10 @@ typedef struct {
                              (1-rho)^4 (4 rho + 1); GP2S_WENDLAND_C6 (1) is Eq. wendland
                              as printed, (1-rho)^8 (32 rho^3 + 25 rho^2 + 8 rho + 1).
                              Zero-initialised params select C2.                      */
+  const double* radii;    /* HOST [dim] per-axis support radii r_k > 0 (axis-anisotropic
+                             W), or NULL: every axis uses radius                     */
+  const double* ls_weights; /* HOST [n_bumps] c_q of the length-scale field l(x), or
+                             NULL: l = 1. |c_q| <= 20.                               */
 } gp2s_params;
 #define GP2S_WENDLAND_C2 0
 #define GP2S_WENDLAND_C6 1
@@ -251,15 +269,18 @@ gp2s_status gp2s_solve(gp2s_ctx ctx, gp2s_matrix m, const double* y, double* a,
 
 /* LML (Sec. 2): solves K a = y as gp2s_solve does, then estimates ln|K| from
  * opts->n_probes Rademacher probes z_s (SplitMix64 signs, counter s * 2^40 + user
- * index): ln|K| ~ sum_i ln K_ii + (1/S) sum_s z_s^T ln(Khat) z_s, Khat = D^-1/2 K
- * D^-1/2, each quadratic form by Lanczos quadrature from the Jacobi-CG coefficients
- * of the solve K q_s = D^1/2 z_s. report is required (HOST). a may be NULL. */
+ * index): ln|K| ~ ln|M| + (1/S) sum_s z_s^T ln(Khat) z_s, Khat = L^-1 K L^-T with
+ * M = L L^T the preconditioner of opts->precond, each quadratic form by Lanczos
+ * quadrature from the preconditioned-CG coefficients of the solve K q_s = L z_s.
+ * report is required (HOST). a may be NULL. */
 gp2s_status gp2s_lml(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_solve_opts* opts,
                      double* a, gp2s_report* report);
 
-/* gp2s_lml plus its gradient grad (HOST [n_bumps + 2] float64) in the order
- * (r, a_1..a_P, sigma_n^2): dLML/dtheta = 1/2 a^T dK a - 1/2 tr(K^{-1} dK), the trace
- * estimated as (1/S) sum_s q_s^T dK D^-1/2 z_s with the probe solutions q_s.
+/* gp2s_lml plus its gradient grad (HOST float64) in the order of gp2s_params: (r,
+ * a_1..a_P, sigma_n^2), n_bumps + 2 values, for the stationary kernel; (r or r_1..r_d,
+ * a_1..a_P, [c_1..c_P], sigma_n^2) otherwise. dLML/dtheta = 1/2 a^T dK a -
+ * 1/2 tr(K^{-1} dK), the trace estimated as (1/S) sum_s q_s^T dK L^-T z_s with the
+ * probe solutions q_s.
  * dK/dtheta is recomputed from the points for every stored entry; no per-parameter
  * matrix is formed. Requires a handle from gp2s_assemble and n_probes >= 1. */
 gp2s_status gp2s_lml_grad(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_solve_opts* opts,

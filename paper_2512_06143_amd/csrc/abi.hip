@@ -596,6 +596,19 @@ struct AuxJoin {
   }
 };
 
+// Per-axis geometry handed to the kernels (general == 0: isotropic stationary path).
+KernGeom kern_geom(gp2s_matrix m) {
+  KernGeom kg{};
+  for (int k = 0; k < 3; ++k) {
+    const double r = k < m->dim ? m->radii[k] : 1.0;
+    kg.inv_r[k] = 1.0 / r;
+    kg.inv_rf[k] = (float)kg.inv_r[k];
+  }
+  kg.lsq = m->lsq;
+  kg.general = (m->ard || m->lsq) ? 1 : 0;
+  return kg;
+}
+
 gp2s_status lml_common(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_solve_opts* o, double* a,
                        gp2s_report* rep, double* grad) {
   if (!ctx) return GP2S_E_INVALID;
@@ -665,10 +678,13 @@ gp2s_status lml_common(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_
   rep->lml = -0.5 * yTa - 0.5 * pr.logdet - 0.5 * (double)n * std::log(2.0 * M_PI);
   if (a) HIPCHK(launch_scatter_rows(n, 1, m->perm, ai, a, ctx->stream));
   if (grad) {
+    const int nr = m->ard ? m->dim : 1;
+    const bool ls = m->lsq != nullptr;
     double* Rr = sc.get<double>(n);
-    double* Tr = sc.get<double>(n);
+    double* Tr = sc.get<double>((size_t)nr * n);
     double* Ur = sc.get<double>(n);
-    const int ncomp = m->P + 2;
+    double* Vr = ls ? sc.get<double>(n) : nullptr;
+    const int ncomp = nr + m->P + (ls ? m->P : 0) + 1;
     double* gpart = sc.get<double>((size_t)256 * ncomp);
     double* gd = sc.get<double>(ncomp);
     uint32_t* tk2 = sc.get<uint32_t>(1);
@@ -691,8 +707,11 @@ gp2s_status lml_common(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_
     b.r2 = m->radius * m->radius;
     b.inv_r2 = 1.0 / b.r2;
     b.kern = m->kern;
-    TIMED(GP2S_T_BACKWARD, launch_backward_rows(b, m->prec, Rr, Tr, Ur, ctx->stream));
-    TIMED(GP2S_T_GRAD_REDUCE, launch_grad_reduce(n, m->dim, m->P, S, m->x64, m->g64, ai, Rr, Tr, Ur, m->centers_d,
+    b.kg = kern_geom(m);
+    b.nr = nr;
+    b.dim = m->dim;
+    TIMED(GP2S_T_BACKWARD, launch_backward_rows(b, m->prec, Rr, Tr, Ur, Vr, ctx->stream));
+    TIMED(GP2S_T_GRAD_REDUCE, launch_grad_reduce(n, m->dim, m->P, S, nr, m->x64, m->g64, ai, Rr, Tr, Ur, Vr, m->centers_d,
                               m->bump_width * m->bump_width, gpart, tk2, gd, ctx->stream));
     st = readback(ctx, gd, ncomp * sizeof(double), grad);
     if (st) return st;
@@ -829,8 +848,20 @@ gp2s_status gp2s_check_params(gp2s_ctx ctx, int64_t n, const gp2s_params* p) {
     if (!is_fin(p->centers[k])) return fail(ctx, GP2S_E_NONFINITE, "non-finite bump centre");
   for (int k = 0; k < p->n_bumps; ++k)
     if (!is_fin(p->weights[k])) return fail(ctx, GP2S_E_NONFINITE, "non-finite bump weight");
+  if (p->radii)
+    for (int k = 0; k < p->dim; ++k) {
+      if (!is_fin(p->radii[k])) return fail(ctx, GP2S_E_NONFINITE, "non-finite axis radius");
+      if (p->radii[k] <= 0) return fail(ctx, GP2S_E_INVALID, "axis radii must be > 0");
+    }
+  if (p->ls_weights)
+    for (int k = 0; k < p->n_bumps; ++k) {
+      if (!is_fin(p->ls_weights[k])) return fail(ctx, GP2S_E_NONFINITE, "non-finite length-scale weight");
+      if (std::fabs(p->ls_weights[k]) > 20.0) return fail(ctx, GP2S_E_INVALID, "length-scale weights must be in [-20, 20]");
+    }
   return GP2S_OK;
 }
+
+
 
 gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_params* p,
                           gp2s_precision prec, gp2s_matrix* out) {
@@ -867,6 +898,14 @@ gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_p
   m->weights_h.assign(p->weights, p->weights + p->n_bumps);
   const int dim = p->dim;
   hipStream_t sm = ctx->stream;
+  m->ard = p->radii != nullptr;
+  for (int k = 0; k < dim; ++k) m->radii[k] = m->ard ? p->radii[k] : p->radius;
+  if (p->ls_weights) {
+    m->ls_h.assign(p->ls_weights, p->ls_weights + p->n_bumps);
+    double pos = 0.0;
+    for (double c : m->ls_h) pos += std::max(c, 0.0);
+    m->ell_bound = std::exp(pos);  // l(x) <= exp(sum of the positive c_q): every bump is <= 1
+  }
 
   m->centers_d = own<double>(m, m->centers_h.size());
   m->weights_d = own<double>(m, m->weights_h.size());
@@ -901,25 +940,32 @@ gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_p
       hi[k] = std::max(hi[k], hp[b * 6 + 3 + k]);
     }
   }
-  // 2. grid: side h >= r (enlarged by 1e-6 relative so rounding in the bin index
-  //    cannot separate a pair closer than r by two bins); capped bin count.
-  double h = p->radius * (1.0 + 1e-6);
+  // 2. grid: side h_k >= r_k along axis k (times the bound of the length-scale
+  //    field, which widens the support to at most r_k l_max; enlarged by 1e-6 relative
+  //    so rounding in the bin index cannot separate a pair inside the support by two
+  //    bins); capped bin count.
+  double h[3] = {1.0, 1.0, 1.0};
+  for (int k = 0; k < dim; ++k) {
+    h[k] = m->radii[k] * (1.0 + 1e-6);
+    if (m->ell_bound != 1.0) h[k] *= m->ell_bound;
+  }
   const double max_bins = std::max(4.0 * (double)n, 65536.0);
   GridDev g{};
   g.dim = dim;
   for (int iter = 0; iter < 64; ++iter) {
     double nb_total = 1.0;
-    for (int k = 0; k < dim; ++k) nb_total *= std::floor((hi[k] - lo[k]) / h) + 1.0;
+    for (int k = 0; k < dim; ++k) nb_total *= std::floor((hi[k] - lo[k]) / h[k]) + 1.0;
     if (nb_total <= max_bins) break;
-    h *= std::pow(nb_total / max_bins, 1.0 / dim) * 1.01;
+    const double f = std::pow(nb_total / max_bins, 1.0 / dim) * 1.01;
+    for (int k = 0; k < dim; ++k) h[k] *= f;
   }
   g.nbins = 1;
   for (int k = 0; k < 3; ++k) {
     g.origin[k] = k < dim ? lo[k] : 0.0;
-    g.nb[k] = k < dim ? (int32_t)(std::floor((hi[k] - lo[k]) / h) + 1.0) : 1;
+    g.nb[k] = k < dim ? (int32_t)(std::floor((hi[k] - lo[k]) / h[k]) + 1.0) : 1;
+    g.inv_h[k] = 1.0 / h[k];
     g.nbins *= g.nb[k];
   }
-  g.inv_h = 1.0 / h;
   m->grid = g;
 
   // 3. prologue, counting sort into bins, internal-order point copies
@@ -965,6 +1011,14 @@ gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_p
   HIPCHK(launch_binsort(n, perm_tmp, bin_of, m->bin_start, m->perm, sm));
   HIPCHK(launch_gather_points(n, dim, x, m->perm, bin_of, g64u, gam, m->pts32, m->pts64, m->x64, m->g64,
                               m->binid, sm));
+  if (!m->ls_h.empty()) {
+    m->ls_d = own<double>(m, m->ls_h.size());
+    m->lsq = own<double>(m, n);
+    OOMCHK(m->ls_d);
+    OOMCHK(m->lsq);
+    HIPCHK(hipMemcpyAsync(m->ls_d, m->ls_h.data(), m->ls_h.size() * sizeof(double), hipMemcpyHostToDevice, sm));
+    HIPCHK(launch_ell(n, dim, m->x64, m->centers_d, m->ls_d, m->P, p->bump_width * p->bump_width, m->lsq, sm));
+  }
   }
 
   // 4. count pass, row pointers, fill pass
@@ -982,6 +1036,7 @@ gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_p
   aa.noise = p->noise_var;
   aa.r2f = (float)aa.r2;
   aa.kern = m->kern;
+  aa.kg = kern_geom(m);
   TIMED(GP2S_T_ASM_COUNT, launch_assemble_count(aa, prec, row_cnt, sm));
   HIPCHK(launch_exscan_i32_i64(row_cnt, m->row_ptr, n, scan_ws, sm));
   int64_t nnz = 0;
@@ -1110,10 +1165,13 @@ gp2s_status gp2s_matrix_refill(gp2s_ctx ctx, gp2s_matrix m, const gp2s_params* p
   if (st) return st;
   bool same = p->dim == m->dim && p->n_bumps == m->P && p->radius == m->radius && p->bump_width == m->bump_width;
   for (int k = 0; same && k < p->n_bumps * p->dim; ++k) same = p->centers[k] == m->centers_h[k];
+  same = same && (p->radii != nullptr) == m->ard && (p->ls_weights != nullptr) == !m->ls_h.empty();
+  for (int k = 0; same && m->ard && k < p->dim; ++k) same = p->radii[k] == m->radii[k];
+  for (int k = 0; same && p->ls_weights && k < p->n_bumps; ++k) same = p->ls_weights[k] == m->ls_h[k];
   if (!same)
     return fail(ctx, GP2S_E_INVALID,
-                "refill keeps the pattern: dimension, radius, bump count, centres and width must be unchanged "
-                "(assemble a new handle instead)");
+                "refill keeps the pattern: dimension, radii, length-scale weights, bump count, centres and width "
+                "must be unchanged (assemble a new handle instead)");
   st = ensure_device(ctx);
   if (st) return st;
   hipStream_t sm = ctx->stream;
@@ -1146,6 +1204,7 @@ gp2s_status gp2s_matrix_refill(gp2s_ctx ctx, gp2s_matrix m, const gp2s_params* p
   aa.noise = m->noise;
   aa.r2f = (float)aa.r2;
   aa.kern = m->kern;
+  aa.kg = kern_geom(m);
   TIMED(GP2S_T_ASM_FILL, launch_assemble_fill(aa, m->prec, m->row_ptr, m->col, m->val, m->diag, sm));
   HIPCHK(hipMemsetAsync(bad, 0, sizeof(int32_t), sm));
   HIPCHK(launch_dinv(n, m->diag, m->dinv, bad, sm));
@@ -1307,6 +1366,13 @@ gp2s_status gp2s_predict(gp2s_ctx ctx, gp2s_matrix m, int64_t n_test, const doub
   ca.inv_r2 = 1.0 / ca.r2;
   ca.r2f = (float)ca.r2;
   ca.kern = m->kern;
+  ca.kg = kern_geom(m);
+  if (m->lsq) {
+    double* lsq_t = sc.get<double>(nt);
+    if (sc.oom) return fail(ctx, GP2S_E_OOM, "prediction workspace allocation failed");
+    HIPCHK(launch_ell(nt, m->dim, x_test, m->centers_d, m->ls_d, m->P, m->bump_width * m->bump_width, lsq_t, sm));
+    ca.lsq_test = lsq_t;
+  }
   HIPCHK(launch_cross_count(ca, m->prec, row_cnt, sm));
   HIPCHK(launch_exscan_i32_i64(row_cnt, rp, nt, scan_ws, sm));
   int64_t nnz = 0;

@@ -16,6 +16,10 @@
 // Float32 path: the support test uses float32 distances. Entry values use the
 // float64 squared distance (exact for float32 coordinates) to form t = 1 - rho^2
 // without cancellation, then 1 - rho = t / (1 + rho) and the polynomial in float32.
+//
+// General kernel (Eq. wendconv, axis radii, length-scale field l): the same sweep with
+// the per-axis scaled distance tested against m_ij = (l_i^2 + l_j^2) / 2 (cells are
+// sized by the radii times the bound of l), and the prefactor (l_i l_j / m_ij)^{d/2}.
 #include "gp2s_internal.h"
 #include "pair.h"
 
@@ -71,6 +75,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs a, int64_t nbl
   const int x1 = bx + 1 < nbx ? bx + 1 : nbx - 1;
   int64_t cnt = 0;
   const double gi64 = a.g64[row];
+  const bool gen = a.kg.general != 0;
+  const double li = a.kg.lsq ? a.kg.lsq[row] : 1.0;
 
   for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
     const int zz = bz + dz;
@@ -87,23 +93,30 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs a, int64_t nbl
         bool pass;
         float4 pj32;
         double4 pj64;
+        const double lj = (a.kg.lsq && ok) ? a.kg.lsq[j] : 1.0;
         if (F32) {
           pj32 = ok ? a.pts32[j] : make_float4(0.f, 0.f, 0.f, -1.f);
-          pass = ok && (j == row || (pj32.w >= 0.0f && sqdist_f32<DIM>(pi32, pj32) < a.r2f));
+          pass = ok && (j == row || (pj32.w >= 0.0f && (gen ? gen_pass_f32<DIM>(pi32, pj32, a.kg, li, lj)
+                                                            : sqdist_f32<DIM>(pi32, pj32) < a.r2f)));
         } else {
           pj64 = ok ? a.pts64[j] : make_double4(0., 0., 0., -1.);
-          pass = ok && (j == row || (pj64.w >= 0.0 && sqdist_f64<DIM>(pi64, pj64) < a.r2));
+          pass = ok && (j == row || (pj64.w >= 0.0 && (gen ? gen_pass_f64<DIM>(pi64, pj64, a.kg, li, lj)
+                                                           : sqdist_f64<DIM>(pi64, pj64) < a.r2)));
         }
         const uint64_t m = __ballot(pass);
         const int64_t pos = base + cnt + lane_prefix(m);
         if (FILL && pass && pos < end) {  // never past the row counted by the first pass
           col[pos] = (int32_t)j;
           if (F32) {
-            float v = (j == row) ? (float)(gi64 * gi64 + a.noise) : entry_f32(pi32, pj32, a.r2, a.inv_r2, a.kern);
+            float v = (j == row) ? (float)(gi64 * gi64 + a.noise)
+                      : gen ? gen_entry_f32<DIM>(pi32, pj32, a.kg, li, lj, a.kern)
+                            : entry_f32(pi32, pj32, a.r2, a.inv_r2, a.kern);
             static_cast<float*>(val)[pos] = v;
             if (j == row) diag[row] = (double)v;
           } else {
-            double v = (j == row) ? gi64 * gi64 + a.noise : entry_f64(pi64, pj64, a.r2, a.inv_r2, a.kern);
+            double v = (j == row) ? gi64 * gi64 + a.noise
+                       : gen ? gen_entry_f64<DIM>(pi64, pj64, a.kg, li, lj, a.kern)
+                             : entry_f64(pi64, pj64, a.r2, a.inv_r2, a.kern);
             static_cast<double*>(val)[pos] = v;
             if (j == row) diag[row] = v;
           }

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_bprologue(const double* __restrict__
   const BInst& I = g.inst[i];
   const double xi[3] = {x3[u * 3], x3[u * 3 + 1], x3[u * 3 + 2]};
   int64_t b = 0;
-  for (int k = 2; k >= 0; --k) b = b * I.grid.nb[k] + bcoord(xi[k], I.grid.origin[k], I.grid.inv_h, I.grid.nb[k]);
+  for (int k = 2; k >= 0; --k) b = b * I.grid.nb[k] + bcoord(xi[k], I.grid.origin[k], I.grid.inv_h[k], I.grid.nb[k]);
   double gs = 0.0;
   bool inside = false;
   for (int p = 0; p < I.P; ++p) {

@@ -101,7 +101,7 @@ void build_grids(gp2s_batch b, int m) {
       I.grid.nb[k] = k < d ? (int32_t)(std::floor((b->bbox[i * 6 + 3 + k] - b->bbox[i * 6 + k]) / h) + 1.0) : 1;
       I.grid.nbins *= I.grid.nb[k];
     }
-    I.grid.inv_h = 1.0 / h;
+    for (int k = 0; k < 3; ++k) I.grid.inv_h[k] = 1.0 / h;
     I.row0 = b->row0[i];
     I.rows = b->n[i];
     I.bin0 = bin0;
@@ -510,6 +510,9 @@ gp2s_status time_matvec(gp2s_batch b, int S, int lanes, Scratch& sc, float* ms) 
 gp2s_status check_batch_params(gp2s_ctx ctx, int M, const int64_t* n, const gp2s_params* p) {
   for (int i = 0; i < M; ++i) {
     gp2s_status s = gp2s_check_params(ctx, n[i], &p[i]);
+    if (!s && (p[i].radii || p[i].ls_weights))
+      s = fail(ctx, GP2S_E_INVALID, "instance %d: the batched path takes the stationary isotropic kernel only "
+                                    "(radii and ls_weights must be NULL)", i);
     if (s) return fail(ctx, s, "instance %d: %s", i, ctx->err.c_str());
   }
   return GP2S_OK;

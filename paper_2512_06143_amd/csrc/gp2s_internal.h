@@ -22,7 +22,7 @@ constexpr int kBJ = 64;             // rows per block of the block-Jacobi precon
 // in the bin index can never separate two points closer than r by two bins).
 struct GridDev {
   double origin[3];
-  double inv_h;
+  double inv_h[3];  // 1 / cell side along each axis
   int32_t nb[3];
   int32_t dim;
   int64_t nbins;
@@ -168,6 +168,17 @@ hipError_t launch_exscan_i32_i64(const int32_t* in, int64_t* out, int64_t n, voi
 hipError_t launch_i64_to_i32(const int64_t* in, int32_t* out, int64_t n, hipStream_t st);
 
 // assemble.hip
+// Per-axis geometry of the general kernel (Eq. wendconv with axis radii and the
+// length-scale field l). general == 0 keeps the isotropic stationary path; otherwise
+// the support test is sum_k ((x_ik - x_jk) / r_k)^2 < m_ij, m_ij = (l_i^2 + l_j^2) / 2
+// (1 without the field), and entries carry the prefactor (l_i l_j / m_ij)^{d/2}.
+struct KernGeom {
+  double inv_r[3];    // 1 / r_k
+  float inv_rf[3];
+  const double* lsq;  // [n] l(x)^2 of the training points (internal order), or nullptr
+  int32_t general;
+};
+
 struct AssembleArgs {
   const float4* pts32;
   const double4* pts64;
@@ -179,6 +190,7 @@ struct AssembleArgs {
   double radius, r2, inv_r2, noise;
   float r2f;
   int32_t kern;  // Wendland member (0: C^2, 1: C^6)
+  KernGeom kg;
 };
 hipError_t launch_assemble_count(const AssembleArgs& a, int prec, int32_t* row_cnt, hipStream_t st);
 hipError_t launch_assemble_fill(const AssembleArgs& a, int prec, const int64_t* row_ptr,
@@ -197,6 +209,8 @@ struct CrossArgs {
   double r2, inv_r2;
   float r2f;
   int32_t kern;
+  KernGeom kg;
+  const double* lsq_test;  // [nt] l(x*)^2 of the test points, or nullptr
 };
 hipError_t launch_test_prologue(const double* x, int64_t nt, const GridDev& g, const double* centers,
                                 const double* weights, int P, double bump_w2, float4* pts32, double4* pts64,
@@ -285,13 +299,21 @@ struct BackwardArgs {
   int S;
   double radius, r2, inv_r2;
   int32_t kern;  // Wendland member (0: C^2, 1: C^6)
+  KernGeom kg;   // general kernel: radius rows T hold nr = 1 or dim components
+  int32_t nr;
+  int32_t dim;
 };
+// Rrow [n], Trow [nr * n], Urow [n], Vrow [n] (length-scale field only, else nullptr)
 hipError_t launch_backward_rows(const BackwardArgs& b, int prec, double* Rrow, double* Trow,
-                                double* Urow, hipStream_t st);
-hipError_t launch_grad_reduce(int64_t n, int dim, int P, int S, const double* x64, const double* g64,
+                                double* Urow, double* Vrow, hipStream_t st);
+// grad = (radius components [nr], a_1..a_P, [c_1..c_P when Vrow], sigma^2)
+hipError_t launch_grad_reduce(int64_t n, int dim, int P, int S, int nr, const double* x64, const double* g64,
                               const double* a, const double* Rrow, const double* Trow,
-                              const double* Urow, const double* centers, double bump_w2,
+                              const double* Urow, const double* Vrow, const double* centers, double bump_w2,
                               double* partial, uint32_t* ticket, double* grad, hipStream_t st);
+// lsq[i] = l(x_i)^2 = exp(2 sum_q c_q bhat_q(x_i)) for n points x (row-major, dim)
+hipError_t launch_ell(int64_t n, int dim, const double* x, const double* centers, const double* ls_w, int P,
+                      double bump_w2, double* lsq, hipStream_t st);
 
 // batch.hip
 hipError_t launch_bbbox(const double* x3, const BatchGeom& g, double* part, int32_t* nonfinite, hipStream_t st);

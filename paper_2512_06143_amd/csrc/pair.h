@@ -18,7 +18,7 @@ __device__ inline int32_t bin_coord(double v, double o, double inv_h, int32_t nb
 // still holds every point within r of them).
 __device__ inline int64_t bin_index(const double (&xi)[3], const GridDev& g) {
   int64_t b = 0;
-  for (int k = g.dim - 1; k >= 0; --k) b = b * g.nb[k] + bin_coord(xi[k], g.origin[k], g.inv_h, g.nb[k]);
+  for (int k = g.dim - 1; k >= 0; --k) b = b * g.nb[k] + bin_coord(xi[k], g.origin[k], g.inv_h[k], g.nb[k]);
   return b;
 }
 
@@ -139,6 +139,83 @@ __device__ inline double entry_f64(const double4& pi, const double4& pj, double 
   double rho = sqrt(d2 * inv_r2);
   double om = t / (1.0 + rho);
   return pi.w * pj.w * wendland_w<double>(kern, rho, om);
+}
+
+// ---- general kernel (Eq. wendconv with axis radii and the length-scale field) ------
+// li, lj are l(x)^2 of the two points (1 without the field).
+
+// Support test: sum_k ((x_ik - x_jk) / r_k)^2 < m_ij, in float32 with fixed rounding
+// (symmetric in i, j: the differences only change sign).
+template <int DIM>
+__device__ inline bool gen_pass_f32(const float4& a, const float4& b, const KernGeom& kg, double li, double lj) {
+  const float dx = __fmul_rn(a.x - b.x, kg.inv_rf[0]), dy = __fmul_rn(a.y - b.y, kg.inv_rf[1]);
+  float d2 = __fmaf_rn(dy, dy, __fmul_rn(dx, dx));
+  if (DIM == 3) {
+    const float dz = __fmul_rn(a.z - b.z, kg.inv_rf[2]);
+    d2 = __fmaf_rn(dz, dz, d2);
+  }
+  const float m = kg.lsq ? __fmul_rn(0.5f, __fadd_rn((float)li, (float)lj)) : 1.0f;
+  return d2 < m;
+}
+template <int DIM>
+__device__ inline bool gen_pass_f64(const double4& a, const double4& b, const KernGeom& kg, double li, double lj) {
+  const double dx = __dmul_rn(a.x - b.x, kg.inv_r[0]), dy = __dmul_rn(a.y - b.y, kg.inv_r[1]);
+  double d2 = __fma_rn(dy, dy, __dmul_rn(dx, dx));
+  if (DIM == 3) {
+    const double dz = __dmul_rn(a.z - b.z, kg.inv_r[2]);
+    d2 = __fma_rn(dz, dz, d2);
+  }
+  const double m = kg.lsq ? __dmul_rn(0.5, __dadd_rn(li, lj)) : 1.0;
+  return d2 < m;
+}
+
+// Float64 geometry of a stored pair: scaled squared differences ds[k], m, t = 1 - Q
+// (formed as (m - d) / m, accurate near the support boundary), Q = d / m, and the
+// prefactor p = (l_i l_j / m)^{DIM/2}.
+template <int DIM>
+__device__ inline void gen_geom(double ax, double ay, double az, double bx, double by, double bz, const KernGeom& kg,
+                                double li, double lj, double (&ds)[3], double& m, double& t, double& Q, double& p) {
+  const double dx = (ax - bx) * kg.inv_r[0], dy = (ay - by) * kg.inv_r[1], dz = DIM == 3 ? (az - bz) * kg.inv_r[2] : 0.0;
+  ds[0] = dx * dx;
+  ds[1] = dy * dy;
+  ds[2] = dz * dz;
+  const double d2 = ds[0] + ds[1] + ds[2];
+  m = kg.lsq ? 0.5 * (li + lj) : 1.0;
+  t = fmax((m - d2) / m, 0.0);
+  Q = d2 / m;
+  p = 1.0;
+  if (kg.lsq) {
+    const double q = sqrt(li * lj) / m;
+    p = DIM == 3 ? q * sqrt(q) : q;
+  }
+}
+
+template <int DIM>
+__device__ inline float gen_entry_f32(const float4& pi, const float4& pj, const KernGeom& kg, double li, double lj,
+                                      int kern) {
+  double ds[3], m, t, Q, p;
+  gen_geom<DIM>(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, kg, li, lj, ds, m, t, Q, p);
+  const float rho = __builtin_amdgcn_sqrtf((float)Q);
+  const float om = (float)t * __builtin_amdgcn_rcpf(1.0f + rho);
+  return pi.w * pj.w * (float)p * wendland_w<float>(kern, rho, om);
+}
+
+template <int DIM>
+__device__ inline double gen_entry_f64(const double4& pi, const double4& pj, const KernGeom& kg, double li, double lj,
+                                       int kern) {
+  double ds[3], m, t, Q, p;
+  gen_geom<DIM>(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, kg, li, lj, ds, m, t, Q, p);
+  const double rho = sqrt(Q);
+  const double om = t / (1.0 + rho);
+  return pi.w * pj.w * p * wendland_w<double>(kern, rho, om);
+}
+
+// D(rho) = -W'(rho) / rho: 20 (1 - rho)^3 (C^2), 22 (1 - rho)^7 (16 rho^2 + 7 rho + 1) (C^6).
+template <typename T>
+__device__ inline T wendland_dlog(int kern, T rho, T om) {
+  const T om2 = om * om, om3 = om2 * om;
+  if (kern == 1) return (T)22 * om3 * om3 * om * (((T)16 * rho + (T)7) * rho + (T)1);
+  return (T)20 * om3;
 }
 
 }  // namespace gp2s

@@ -92,6 +92,8 @@ __global__ __launch_bounds__(kBlock) void k_cross(CrossArgs a, int64_t nblocks_p
   const int x0 = bx > 0 ? bx - 1 : 0;
   const int x1 = bx + 1 < nbx ? bx + 1 : nbx - 1;
   int64_t cnt = 0;
+  const bool gen = a.kg.general != 0;
+  const double li = a.lsq_test ? a.lsq_test[row] : 1.0;
   for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
     const int zz = bz + dz;
     if (zz < 0 || zz >= nbz) continue;
@@ -107,21 +109,26 @@ __global__ __launch_bounds__(kBlock) void k_cross(CrossArgs a, int64_t nblocks_p
         bool pass;
         float4 pj32;
         double4 pj64;
+        const double lj = (a.kg.lsq && ok) ? a.kg.lsq[j] : 1.0;
         if (F32) {
           pj32 = ok ? a.pts32[j] : make_float4(0.f, 0.f, 0.f, -1.f);
-          pass = ok && pj32.w >= 0.0f && sqdist_f32<DIM>(pi32, pj32) < a.r2f;
+          pass = ok && pj32.w >= 0.0f &&
+                 (gen ? gen_pass_f32<DIM>(pi32, pj32, a.kg, li, lj) : sqdist_f32<DIM>(pi32, pj32) < a.r2f);
         } else {
           pj64 = ok ? a.pts64[j] : make_double4(0., 0., 0., -1.);
-          pass = ok && pj64.w >= 0.0 && sqdist_f64<DIM>(pi64, pj64) < a.r2;
+          pass = ok && pj64.w >= 0.0 &&
+                 (gen ? gen_pass_f64<DIM>(pi64, pj64, a.kg, li, lj) : sqdist_f64<DIM>(pi64, pj64) < a.r2);
         }
         const uint64_t m = __ballot(pass);
         const int64_t pos = base + cnt + lane_prefix(m);
         if (FILL && pass && pos < end) {  // never past the row counted by the first pass
           col[pos] = (int32_t)j;
           if (F32)
-            static_cast<float*>(val)[pos] = entry_f32(pi32, pj32, a.r2, a.inv_r2, a.kern);
+            static_cast<float*>(val)[pos] = gen ? gen_entry_f32<DIM>(pi32, pj32, a.kg, li, lj, a.kern)
+                                                : entry_f32(pi32, pj32, a.r2, a.inv_r2, a.kern);
           else
-            static_cast<double*>(val)[pos] = entry_f64(pi64, pj64, a.r2, a.inv_r2, a.kern);
+            static_cast<double*>(val)[pos] = gen ? gen_entry_f64<DIM>(pi64, pj64, a.kg, li, lj, a.kern)
+                                                 : entry_f64(pi64, pj64, a.r2, a.inv_r2, a.kern);
         }
         cnt += __popcll(m);
       }

@@ -200,6 +200,29 @@ hipError_t launch_gather_points(int64_t n, int dim, const double* x, const int32
   return hipGetLastError();
 }
 
+// Length-scale field of the general kernel (Eq. wendconv): lsq_i = l(x_i)^2 with
+// ln l(x) = sum_q c_q bhat_q(x), bhat_q the unweighted bumps (same centres and width as g).
+__global__ __launch_bounds__(kBlock) void k_ell(int64_t n, int dim, const double* __restrict__ x,
+                                                const double* __restrict__ centers, const double* __restrict__ ls_w,
+                                                int P, double bump_w2, double* __restrict__ lsq) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double xi[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < dim; ++k) xi[k] = x[i * dim + k];
+  double h = 0.0;
+  bool inside = false;
+  bump_mask(xi, dim, centers, ls_w, P, bump_w2, h, inside);  // sum_q c_q bhat_q(x)
+  lsq[i] = exp(2.0 * h);
+}
+
+hipError_t launch_ell(int64_t n, int dim, const double* x, const double* centers, const double* ls_w, int P,
+                      double bump_w2, double* lsq, hipStream_t st) {
+  const int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ell, dim3((unsigned)blocks), dim3(kBlock), 0, st, n, dim, x, centers, ls_w, P, bump_w2, lsq);
+  return hipGetLastError();
+}
+
 // Rademacher probe signs from counter-based SplitMix64 (Steele, Lea and Flood, 2014):
 // output k of the stream seeded with `seed` is mix(seed + (k + 1) * 0x9E3779B97F4A7C15);
 // probe s at user point u uses k = s * 2^40 + u and is negative when bit 63 is set.

@@ -54,6 +54,14 @@ struct gp2s_matrix_s {
   int dim = 0, P = 0;
   double radius = 0, bump_width = 0, noise = 0;
   int kern = 0;  // Wendland member
+  // general kernel (Eq. wendconv): per-axis radii (all equal to radius when isotropic)
+  // and the length-scale field's weights c_q; lsq = l(x)^2 per internal point
+  double radii[3] = {0.0, 0.0, 0.0};
+  bool ard = false;
+  std::vector<double> ls_h;
+  double* ls_d = nullptr;
+  double* lsq = nullptr;
+  double ell_bound = 1.0;
   std::vector<double> centers_h, weights_h;
   double* centers_d = nullptr;
   double* weights_d = nullptr;

@@ -38,7 +38,8 @@ class Params(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n_bumps", ctypes.c_int32), ("radius", ctypes.c_double),
                 ("bump_width", ctypes.c_double), ("noise_var", ctypes.c_double),
                 ("centers", ctypes.POINTER(ctypes.c_double)), ("weights", ctypes.POINTER(ctypes.c_double)),
-                ("kernel", ctypes.c_int32)]
+                ("kernel", ctypes.c_int32), ("radii", ctypes.POINTER(ctypes.c_double)),
+                ("ls_weights", ctypes.POINTER(ctypes.c_double))]
 
 
 WENDLAND = {"c2": 0, "c6": 1}  # Wendland member: C^2, or the printed C^6 of Eq. wendland
@@ -151,15 +152,25 @@ class HostParams:
     centers: np.ndarray
     weights: np.ndarray
     kernel: int | str = 0  # 0 / "c2" or 1 / "c6"
+    radii: np.ndarray | None = None       # per-axis radii (axis-anisotropic W), or None
+    ls_weights: np.ndarray | None = None  # c_q of the length-scale field (Eq. wendconv), or None
+
+    def n_grad(self) -> int:
+        """Length of the gradient: (r | r_1..r_d, a_1..a_P, [c_1..c_P], sigma^2)."""
+        P = int(np.asarray(self.weights).reshape(-1).shape[0])
+        return (self.dim if self.radii is not None else 1) + P + (P if self.ls_weights is not None else 0) + 1
 
     def to_c(self):
+        dp = ctypes.POINTER(ctypes.c_double)
         c = np.ascontiguousarray(self.centers, dtype=np.float64).reshape(-1)
         w = np.ascontiguousarray(self.weights, dtype=np.float64).reshape(-1)
+        r = None if self.radii is None else np.ascontiguousarray(self.radii, dtype=np.float64).reshape(-1)
+        ls = None if self.ls_weights is None else np.ascontiguousarray(self.ls_weights, dtype=np.float64).reshape(-1)
         kern = WENDLAND[self.kernel] if isinstance(self.kernel, str) else int(self.kernel)
         p = Params(int(self.dim), int(w.shape[0]), float(self.radius), float(self.bump_width),
-                   float(self.noise_var), c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                   w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), kern)
-        return p, (c, w)  # keep the arrays alive while p is used
+                   float(self.noise_var), c.ctypes.data_as(dp), w.ctypes.data_as(dp), kern,
+                   r.ctypes.data_as(dp) if r is not None else dp(), ls.ctypes.data_as(dp) if ls is not None else dp())
+        return p, (c, w, r, ls)  # keep the arrays alive while p is used
 
 
 def _ptr(t) -> int:
@@ -390,8 +401,8 @@ def gp2s_lml_grad(m: Matrix, y, opts: SolveOpts | None = None, want_a=True, allo
     a = ctx._torch.empty_like(yd) if want_a else None
     rep = Report()
     o = opts or default_opts()
-    P = int(m.params.weights.shape[0]) if m.params is not None else 0
-    grad = (ctypes.c_double * (P + 2))()
+    ng = m.params.n_grad() if m.params is not None else 2
+    grad = (ctypes.c_double * ng)()
     rep.status = ctx.check(lib.gp2s_lml_grad(ctx.ptr, m.handle, _ptr(yd), ctypes.byref(o), _ptr(a),
                                              ctypes.byref(rep), grad), allow_noconv)
     return rep, np.array(grad[:], dtype=np.float64), a

@@ -53,6 +53,12 @@ def _params(B, **kw):
     (dict(kernel=1), 10, 0),
     (dict(kernel="c6"), 10, 0),
     (dict(kernel=2), 10, 1),
+    (dict(radii=[0.05, 0.02]), 10, 0),
+    (dict(radii=[0.05, 0.0]), 10, 1),
+    (dict(radii=[0.05, float("nan")]), 10, 7),
+    (dict(ls_weights=[0.7]), 10, 0),
+    (dict(ls_weights=[25.0]), 10, 1),
+    (dict(ls_weights=[float("inf")]), 10, 7),
 ])
 def test_host_validation(kw, n, code):
     B, ctx = _ctx()
