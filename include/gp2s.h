@@ -99,7 +99,18 @@ typedef struct {
                              W), or NULL: every axis uses radius                     */
   const double* ls_weights; /* HOST [n_bumps] c_q of the length-scale field l(x), or
                              NULL: l = 1. |c_q| <= 20.                               */
+  const int32_t* ff_groups; /* HOST [n_bumps] group u in [0, 16) of each bump for the
+                             far-field bump kernel, or NULL (see below)              */
 } gp2s_params;
+/* Far-field bump kernel (Sec. 3.3, Eq. bump_kernel with the core kernel 1), selected by
+ * ff_groups != NULL (radii and ls_weights must then be NULL):
+ *   K_ij = sum_u g_u(x_i) g_u(x_j) + W(||x_i - x_j|| / r) + sigma_n^2 [i == j],
+ *   g_u = sum over the bumps p with ff_groups[p] == u of weights[p] bhat_p,
+ * W without a bump mask. The bump term couples points at any distance; it has rank U
+ * (the number of groups) and is applied as G (G^T v), never stored as a matrix: the
+ * handle's CSR (gp2s_matrix_export) holds K_loc = W + sigma_n^2 I only, while every
+ * solve, product (gp2s_spmv), log-determinant, gradient and prediction uses the full K.
+ * The gradient keeps the order (r, a_1..a_P, sigma_n^2). */
 #define GP2S_WENDLAND_C2 0
 #define GP2S_WENDLAND_C6 1
 

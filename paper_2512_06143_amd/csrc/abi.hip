@@ -39,6 +39,9 @@ struct Cg {
   int variant = 0;
   double* R = nullptr;
   double* Z = nullptr;  // M^-1 r (block preconditioner)
+  double* lrC = nullptr;     // far-field kernel: G^T p [U * S]
+  double* lrPart = nullptr;  // its per-workgroup partials
+  uint32_t* lrTicket = nullptr;
   void* P = nullptr;
   void* Q = nullptr;
   int32_t* si = nullptr;
@@ -200,7 +203,8 @@ gp2s_status ensure_bj(gp2s_ctx ctx, gp2s_matrix m) {
   int32_t* bad = sc.get<int32_t>(1);
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "block preconditioner workspace allocation failed");
   HIPCHK(hipMemsetAsync(bad, 0, sizeof(int32_t), ctx->stream));
-  HIPCHK(launch_bj_factor(n, m->row_ptr, m->col, m->val, m->prec, m->bj_L, m->bj_M, m->bj_piv, bad, ctx->stream));
+  HIPCHK(launch_bj_factor(n, m->row_ptr, m->col, m->val, m->prec, m->ffG, m->ffU, m->bj_L, m->bj_M, m->bj_piv, bad,
+                          ctx->stream));
   int32_t hb = 0;
   gp2s_status st = readback(ctx, bad, sizeof(int32_t), &hb);
   if (st) return st;
@@ -224,6 +228,11 @@ gp2s_status cg_begin(Cg& c, const double* B, double tol, bool keep_hist, Scratch
   const size_t vb = c.f32vec ? sizeof(float) : sizeof(double);
   c.R = sc.get<double>(nS);
   if (c.precond == GP2S_PRECOND_BLOCK) c.Z = sc.get<double>(nS);
+  if (m->ffG) {
+    c.lrC = sc.get<double>((size_t)m->ffU * S);
+    c.lrPart = sc.get<double>((size_t)m->ffU * S * ff_gtp_blocks(n));
+    c.lrTicket = sc.get<uint32_t>(1);
+  }
   c.P = sc.get<uint8_t>(nS * vb);
   c.Q = sc.get<double>(nS);
   double* sd = sc.get<double>(6 * S + (size_t)kReduceBlocks * S * 2);
@@ -251,6 +260,12 @@ gp2s_status cg_begin(Cg& c, const double* B, double tol, bool keep_hist, Scratch
   HIPCHK(hipEventCreateWithFlags(&c.ev[0], hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&c.ev[1], hipEventDisableTiming));
   HIPCHK(hipMemsetAsync(c.si, 0, (2 * S + 4) * sizeof(int32_t), c.st));
+  if (m->ffG) {
+    HIPCHK(hipMemsetAsync(c.lrC, 0, (size_t)m->ffU * S * sizeof(double), c.st));
+    HIPCHK(hipMemsetAsync(c.lrTicket, 0, sizeof(uint32_t), c.st));
+    cs.lrC = c.lrC;
+    cs.lrU = m->ffU;
+  }
   if (c.precond == GP2S_PRECOND_BLOCK) {
     if (!m->bj_ready) return fail(ctx, GP2S_E_INVALID, "block preconditioner not built (%s)", c.label);
     HIPCHK(launch_bj_update(n, S, B, c.X, c.R, nullptr, nullptr, c.f32vec, m->bj_M, c.Z, cs, c.st));
@@ -281,9 +296,12 @@ gp2s_status cg_step(Cg& c) {
   gp2s_matrix m = c.m;
   const int64_t n = m->n;
   const int S = c.S;
+  if (m->ffG)  // far-field kernel: C = G^T p before the product (k_cg_alpha adds |C|^2 to p^T q)
+    HIPCHK(launch_ff_gtp(n, S, m->ffU, m->ffG, c.P, c.f32vec, c.lrPart, c.lrTicket, c.lrC, c.st));
   TIMED_ON(S == 1 ? GP2S_T_CG_MATVEC1 : GP2S_T_CG_MATVEC_BLOCK, c.st,
            launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, n, S, (double)m->nnz / (double)n, c.variant,
                             tile_set(m), c.P, c.Q, c.f32vec, c.cs, c.st));
+  if (m->ffG) HIPCHK(launch_ff_add(n, S, m->ffU, m->ffG, c.lrC, S, 1, static_cast<double*>(c.Q), c.st));
   if (c.precond == GP2S_PRECOND_BLOCK) {
     TIMED_ON(S == 1 ? GP2S_T_CG_UPDATE1 : GP2S_T_CG_UPDATE_BLOCK, c.st,
              launch_bj_update(n, S, nullptr, c.X, c.R, c.P, c.Q, c.f32vec, m->bj_M, c.Z, c.cs, c.st));
@@ -431,6 +449,20 @@ gp2s_status dot_host(gp2s_ctx ctx, int64_t n, const double* a, const double* b, 
   return readback(ctx, buf, sizeof(double), out);
 }
 
+// Far-field kernel: Y += G (G^T X) for S columns (internal order); no-op otherwise.
+gp2s_status ff_apply(gp2s_ctx ctx, gp2s_matrix m, int S, const double* X, double* Y, Scratch& sc) {
+  if (!m->ffG) return GP2S_OK;
+  const int64_t n = m->n;
+  double* C = sc.get<double>((size_t)m->ffU * S);
+  double* part = sc.get<double>((size_t)m->ffU * S * ff_gtp_blocks(n));
+  uint32_t* tk = sc.get<uint32_t>(1);
+  if (sc.oom) return fail(ctx, GP2S_E_OOM, "far-field workspace allocation failed");
+  HIPCHK(hipMemsetAsync(tk, 0, sizeof(uint32_t), ctx->stream));
+  HIPCHK(launch_ff_gtp(n, S, m->ffU, m->ffG, X, false, part, tk, C, ctx->stream));
+  HIPCHK(launch_ff_add(n, S, m->ffU, m->ffG, C, S, 1, Y, ctx->stream));
+  return GP2S_OK;
+}
+
 // Solve K a = y (internal order) with restarts from the recomputed residual. `side`,
 // if given, is a solve begun on the second stream; its iterations are interleaved with
 // those of the first CG run of y and it is complete on return.
@@ -480,6 +512,8 @@ gp2s_status solve_internal(gp2s_ctx ctx, gp2s_matrix m, const double* y, double*
     total += cy.total_iters;
     for (;;) {
       TIMED(GP2S_T_SPMV, launch_spmv(m->prec, m->row_ptr, m->col, m->val, n, (double)m->nnz / n, a, kx, ctx->stream));
+      st = ff_apply(ctx, m, 1, a, kx, sc);
+      if (st) return st;
       HIPCHK(launch_axpy_sub(n, y, kx, r, ctx->stream));
       double rr = 0.0;
       st = dot_host(ctx, n, r, nullptr, red, tk, &rr);
@@ -711,8 +745,32 @@ gp2s_status lml_common(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_
     b.nr = nr;
     b.dim = m->dim;
     TIMED(GP2S_T_BACKWARD, launch_backward_rows(b, m->prec, Rr, Tr, Ur, Vr, ctx->stream));
-    TIMED(GP2S_T_GRAD_REDUCE, launch_grad_reduce(n, m->dim, m->P, S, nr, m->x64, m->g64, ai, Rr, Tr, Ur, Vr, m->centers_d,
-                              m->bump_width * m->bump_width, gpart, tk2, gd, ctx->stream));
+    double* Hr = nullptr;
+    if (m->ffU > 0) {
+      // far-field amplitudes: H = P G with P = a a^T - (1/2S) sum_s (q_s w_s^T + w_s q_s^T)
+      const int U = m->ffU;
+      double* Wf = Ws;
+      if (!Wf) {
+        Wf = sc.get<double>((size_t)n * S);
+        if (sc.oom) return fail(ctx, GP2S_E_OOM, "gradient workspace allocation failed");
+        HIPCHK(launch_ff_wjac(n, S, mask, m->dinv, Wf, ctx->stream));
+      }
+      double* ag = sc.get<double>(U);
+      double* wg = sc.get<double>((size_t)U * S);
+      double* qg = sc.get<double>((size_t)U * S);
+      double* part = sc.get<double>((size_t)U * S * ff_gtp_blocks(n));
+      uint32_t* tk3 = sc.get<uint32_t>(1);
+      Hr = sc.get<double>((size_t)n * U);
+      if (sc.oom) return fail(ctx, GP2S_E_OOM, "gradient workspace allocation failed");
+      HIPCHK(hipMemsetAsync(tk3, 0, sizeof(uint32_t), ctx->stream));
+      HIPCHK(launch_ff_gtp(n, 1, U, m->ffG, ai, false, part, tk3, ag, ctx->stream));
+      HIPCHK(launch_ff_gtp(n, S, U, m->ffG, Wf, false, part, tk3, wg, ctx->stream));
+      HIPCHK(launch_ff_gtp(n, S, U, m->ffG, Qs, false, part, tk3, qg, ctx->stream));
+      HIPCHK(launch_ff_h(n, S, U, ai, Qs, Wf, ag, wg, qg, Hr, ctx->stream));
+    }
+    TIMED(GP2S_T_GRAD_REDUCE, launch_grad_reduce(n, m->dim, m->P, S, nr, m->x64, m->g64, ai, Rr, Tr, Ur, Vr, Hr,
+                                                 m->ffgrp_d, m->ffU, m->centers_d, m->bump_width * m->bump_width,
+                                                 gpart, tk2, gd, ctx->stream));
     st = readback(ctx, gd, ncomp * sizeof(double), grad);
     if (st) return st;
   }
@@ -853,6 +911,13 @@ gp2s_status gp2s_check_params(gp2s_ctx ctx, int64_t n, const gp2s_params* p) {
       if (!is_fin(p->radii[k])) return fail(ctx, GP2S_E_NONFINITE, "non-finite axis radius");
       if (p->radii[k] <= 0) return fail(ctx, GP2S_E_INVALID, "axis radii must be > 0");
     }
+  if (p->ff_groups) {
+    if (p->radii || p->ls_weights)
+      return fail(ctx, GP2S_E_INVALID, "the far-field kernel takes one isotropic radius (radii and ls_weights NULL)");
+    for (int k = 0; k < p->n_bumps; ++k)
+      if (p->ff_groups[k] < 0 || p->ff_groups[k] >= kMaxGroups)
+        return fail(ctx, GP2S_E_INVALID, "ff_groups values must be in [0, %d)", kMaxGroups);
+  }
   if (p->ls_weights)
     for (int k = 0; k < p->n_bumps; ++k) {
       if (!is_fin(p->ls_weights[k])) return fail(ctx, GP2S_E_NONFINITE, "non-finite length-scale weight");
@@ -899,6 +964,10 @@ gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_p
   const int dim = p->dim;
   hipStream_t sm = ctx->stream;
   m->ard = p->radii != nullptr;
+  if (p->ff_groups) {
+    m->ffgrp_h.assign(p->ff_groups, p->ff_groups + p->n_bumps);
+    for (int32_t u : m->ffgrp_h) m->ffU = std::max(m->ffU, u + 1);
+  }
   for (int k = 0; k < dim; ++k) m->radii[k] = m->ard ? p->radii[k] : p->radius;
   if (p->ls_weights) {
     m->ls_h.assign(p->ls_weights, p->ls_weights + p->n_bumps);
@@ -1005,7 +1074,7 @@ gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_p
   Timed prep_timer(ctx, GP2S_T_ASM_PREP, ctx->stream);
   HIPCHK(hipMemsetAsync(bin_count, 0, g.nbins * sizeof(int32_t), sm));
   HIPCHK(launch_prologue(x, n, g, m->centers_d, m->weights_d, m->P, p->bump_width * p->bump_width, bin_of, slot,
-                         bin_count, g64u, gam, sm));
+                         bin_count, g64u, gam, sm, m->ffU > 0));
   HIPCHK(launch_exscan_i32_i64(bin_count, m->bin_start, g.nbins, scan_ws, sm));
   HIPCHK(launch_scatter(n, bin_of, slot, m->bin_start, perm_tmp, sm));
   HIPCHK(launch_binsort(n, perm_tmp, bin_of, m->bin_start, m->perm, sm));
@@ -1048,6 +1117,16 @@ gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_p
   OOMCHK(m->col);
   OOMCHK(m->val);
   TIMED(GP2S_T_ASM_FILL, launch_assemble_fill(aa, prec, m->row_ptr, m->col, m->val, m->diag, sm));
+  if (m->ffU > 0) {
+    m->ffgrp_d = own<int32_t>(m, m->ffgrp_h.size());
+    m->ffG = own<double>(m, (size_t)n * m->ffU);
+    OOMCHK(m->ffgrp_d);
+    OOMCHK(m->ffG);
+    HIPCHK(hipMemcpyAsync(m->ffgrp_d, m->ffgrp_h.data(), m->ffgrp_h.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                          sm));
+    HIPCHK(launch_ff_G(n, dim, m->x64, m->centers_d, m->weights_d, m->ffgrp_d, m->P, m->ffU,
+                       p->bump_width * p->bump_width, m->ffG, m->diag, sm));
+  }
   int32_t* bad = nonfinite;
   HIPCHK(hipMemsetAsync(bad, 0, sizeof(int32_t), sm));
   HIPCHK(launch_dinv(n, m->diag, m->dinv, bad, sm));
@@ -1166,6 +1245,8 @@ gp2s_status gp2s_matrix_refill(gp2s_ctx ctx, gp2s_matrix m, const gp2s_params* p
   bool same = p->dim == m->dim && p->n_bumps == m->P && p->radius == m->radius && p->bump_width == m->bump_width;
   for (int k = 0; same && k < p->n_bumps * p->dim; ++k) same = p->centers[k] == m->centers_h[k];
   same = same && (p->radii != nullptr) == m->ard && (p->ls_weights != nullptr) == !m->ls_h.empty();
+  same = same && (p->ff_groups != nullptr) == (m->ffU > 0);
+  for (int k = 0; same && p->ff_groups && k < p->n_bumps; ++k) same = p->ff_groups[k] == m->ffgrp_h[k];
   for (int k = 0; same && m->ard && k < p->dim; ++k) same = p->radii[k] == m->radii[k];
   for (int k = 0; same && p->ls_weights && k < p->n_bumps; ++k) same = p->ls_weights[k] == m->ls_h[k];
   if (!same)
@@ -1187,8 +1268,9 @@ gp2s_status gp2s_matrix_refill(gp2s_ctx ctx, gp2s_matrix m, const gp2s_params* p
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "refill workspace allocation failed");
   {
     Timed prep_timer(ctx, GP2S_T_ASM_PREP, ctx->stream);
-    HIPCHK(launch_refresh_g(n, m->dim, m->x64, m->centers_d, m->weights_d, m->P, m->bump_width * m->bump_width,
-                            m->pts32, m->pts64, m->g64, sm));
+    if (m->ffU == 0)  // (the far-field kernel's Wendland term has g = 1 at every point)
+      HIPCHK(launch_refresh_g(n, m->dim, m->x64, m->centers_d, m->weights_d, m->P, m->bump_width * m->bump_width,
+                              m->pts32, m->pts64, m->g64, sm));
   }
   AssembleArgs aa{};
   aa.pts32 = m->pts32;
@@ -1206,6 +1288,9 @@ gp2s_status gp2s_matrix_refill(gp2s_ctx ctx, gp2s_matrix m, const gp2s_params* p
   aa.kern = m->kern;
   aa.kg = kern_geom(m);
   TIMED(GP2S_T_ASM_FILL, launch_assemble_fill(aa, m->prec, m->row_ptr, m->col, m->val, m->diag, sm));
+  if (m->ffU > 0)
+    HIPCHK(launch_ff_G(n, m->dim, m->x64, m->centers_d, m->weights_d, m->ffgrp_d, m->P, m->ffU,
+                       m->bump_width * m->bump_width, m->ffG, m->diag, sm));
   HIPCHK(hipMemsetAsync(bad, 0, sizeof(int32_t), sm));
   HIPCHK(launch_dinv(n, m->diag, m->dinv, bad, sm));
   int32_t hb = 0;
@@ -1257,6 +1342,8 @@ gp2s_status gp2s_spmv(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X
     TIMED(GP2S_T_SPMM, launch_spmm(m->prec, m->row_ptr, m->col, m->val, n, nrhs, (double)m->nnz / n,
                                            m->spmm_variant[nrhs] >= 0 ? m->spmm_variant[nrhs] : -1, tile_set(m),
                                            Xi, Yi, ctx->stream));
+  st = ff_apply(ctx, m, nrhs, Xi, Yi, sc);
+  if (st) return st;
   HIPCHK(launch_scatter_rows(n, nrhs, m->perm, Yi, Y, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return GP2S_OK;
@@ -1347,7 +1434,7 @@ gp2s_status gp2s_predict(gp2s_ctx ctx, gp2s_matrix m, int64_t n_test, const doub
   // test-point prologue on the training grid
   HIPCHK(hipMemsetAsync(flag, 0, sizeof(int32_t), sm));
   HIPCHK(launch_test_prologue(x_test, nt, m->grid, m->centers_d, m->weights_d, m->P, m->bump_width * m->bump_width,
-                              t32, t64, g64t, tbin, flag, sm));
+                              t32, t64, g64t, tbin, flag, sm, m->ffU > 0));
   int32_t nf = 0;
   st = readback(ctx, flag, sizeof(int32_t), &nf);
   if (st) return st;
@@ -1385,6 +1472,20 @@ gp2s_status gp2s_predict(gp2s_ctx ctx, gp2s_matrix m, int64_t n_test, const doub
   // mean = K* a (a gathered into internal order)
   HIPCHK(launch_gather_rows(n, 1, m->perm, a, ai, sm));
   HIPCHK(launch_spmv(m->prec, rp, ccol, cval, nt, nnz > 0 ? (double)nnz / (double)nt : 1.0, ai, mean, sm));
+  double* Gt = nullptr;  // far-field kernel: G* [nt * U] of the test points
+  if (m->ffU > 0) {
+    const int U = m->ffU;
+    Gt = sc.get<double>((size_t)nt * U);
+    double* C1 = sc.get<double>(U);
+    double* part = sc.get<double>((size_t)U * ff_gtp_blocks(n));
+    uint32_t* tk = sc.get<uint32_t>(1);
+    if (sc.oom) return fail(ctx, GP2S_E_OOM, "prediction workspace allocation failed");
+    HIPCHK(hipMemsetAsync(tk, 0, sizeof(uint32_t), sm));
+    HIPCHK(launch_ff_G(nt, m->dim, x_test, m->centers_d, m->weights_d, m->ffgrp_d, m->P, U,
+                       m->bump_width * m->bump_width, Gt, nullptr, sm));
+    HIPCHK(launch_ff_gtp(n, 1, U, m->ffG, ai, false, part, tk, C1, sm));
+    HIPCHK(launch_ff_add(nt, 1, U, Gt, C1, 1, 0, mean, sm));  // mean += G* (G^T a)
+  }
   int32_t blocks = 0, worst = 0;
   bool conv = true;
   if (var) {
@@ -1400,13 +1501,22 @@ gp2s_status gp2s_predict(gp2s_ctx ctx, gp2s_matrix m, int64_t n_test, const doub
     for (int64_t t0 = 0; t0 < nt; t0 += kVarBlock) {
       const int S = (int)std::min<int64_t>(kVarBlock, nt - t0);
       HIPCHK(hipMemsetAsync(B, 0, (size_t)n * S * sizeof(double), sm));
-      HIPCHK(launch_cross_block(m->prec, rp, ccol, cval, t0, S, B, csc, sm));
+      if (Gt) {  // far-field kernel: k(X, x*) = W(X, x*) + G G*^T, dense; scaled per column
+        HIPCHK(launch_cross_block(m->prec, rp, ccol, cval, t0, S, B, csc, sm, true));
+        HIPCHK(launch_ff_add(n, S, m->ffU, m->ffG, Gt + t0 * m->ffU, 1, m->ffU, B, sm));
+        HIPCHK(launch_ff_colscale(n, S, B, csc, sm));
+      } else {
+        HIPCHK(launch_cross_block(m->prec, rp, ccol, cval, t0, S, B, csc, sm));
+      }
       Scratch scb(ctx);  // the block solve's workspace is released per block
       CgRun run;
       st = run_cg(ctx, m, S, B, Vs, o->tol, o->max_iter, o->check_every, false, scb, run, "variance block",
                   o->precond);
       if (st) return st;
-      HIPCHK(launch_cross_var(m->prec, rp, ccol, cval, t0, S, Vs, csc, g64t, var, sm));
+      if (Gt)
+        HIPCHK(launch_ff_var(n, S, m->ffU, B, Vs, csc, Gt, t0, var, sm));
+      else
+        HIPCHK(launch_cross_var(m->prec, rp, ccol, cval, t0, S, Vs, csc, g64t, var, sm));
       ++blocks;
       worst = std::max(worst, run.total_iters);
       conv = conv && run.converged;

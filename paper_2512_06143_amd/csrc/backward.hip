@@ -297,6 +297,8 @@ __global__ __launch_bounds__(kBlock) void k_grad_reduce(int64_t n, int dim, int 
                                                         const double* __restrict__ Trow,
                                                         const double* __restrict__ Urow,
                                                         const double* __restrict__ Vrow,
+                                                        const double* __restrict__ Hrow,
+                                                        const int32_t* __restrict__ group, int U,
                                                         const double* __restrict__ centers,
                                                         double bump_w2, double* __restrict__ partial,
                                                         uint32_t* __restrict__ ticket,
@@ -354,7 +356,7 @@ __global__ __launch_bounds__(kBlock) void k_grad_reduce(int64_t n, int dim, int 
           }
           if (d2 < bump_w2) {
             const double bk = exp(1.0 - 1.0 / (1.0 - d2 / bump_w2));
-            acc[q] += bk * R;
+            acc[q] += bk * (Hrow ? Hrow[i * U + group[k]] : R);
             accc[q] += bk * GV;
           }
         }
@@ -388,13 +390,14 @@ __global__ __launch_bounds__(kBlock) void k_grad_reduce(int64_t n, int dim, int 
 
 hipError_t launch_grad_reduce(int64_t n, int dim, int P, int S, int nr, const double* x64, const double* g64,
                               const double* a, const double* Rrow, const double* Trow, const double* Urow,
-                              const double* Vrow, const double* centers, double bump_w2, double* partial,
+                              const double* Vrow, const double* Hrow, const int32_t* group, int U,
+                              const double* centers, double bump_w2, double* partial,
                               uint32_t* ticket, double* grad, hipStream_t st) {
   int64_t blocks = (n + kBlock - 1) / kBlock;
   if (blocks > 256) blocks = 256;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)blocks), dim3(kBlock), 0, st, n, dim, P, S, nr, x64, g64, a,
-                     Rrow, Trow, Urow, Vrow, centers, bump_w2, partial, ticket, grad);
+                     Rrow, Trow, Urow, Vrow, Hrow, group, U, centers, bump_w2, partial, ticket, grad);
   return hipGetLastError();
 }
 

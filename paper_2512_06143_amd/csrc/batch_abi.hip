@@ -510,9 +510,9 @@ gp2s_status time_matvec(gp2s_batch b, int S, int lanes, Scratch& sc, float* ms) 
 gp2s_status check_batch_params(gp2s_ctx ctx, int M, const int64_t* n, const gp2s_params* p) {
   for (int i = 0; i < M; ++i) {
     gp2s_status s = gp2s_check_params(ctx, n[i], &p[i]);
-    if (!s && (p[i].radii || p[i].ls_weights))
+    if (!s && (p[i].radii || p[i].ls_weights || p[i].ff_groups))
       s = fail(ctx, GP2S_E_INVALID, "instance %d: the batched path takes the stationary isotropic kernel only "
-                                    "(radii and ls_weights must be NULL)", i);
+                                    "(radii, ls_weights and ff_groups must be NULL)", i);
     if (s) return fail(ctx, s, "instance %d: %s", i, ctx->err.c_str());
   }
   return GP2S_OK;

@@ -29,7 +29,8 @@ constexpr int kBJStride = kBJ + 1;  // LDS row stride of the factor kernel (doub
 template <typename V>
 __global__ __launch_bounds__(kBJThreads) void k_bj_factor(int64_t n, const int64_t* __restrict__ rp,
                                                           const int32_t* __restrict__ col,
-                                                          const V* __restrict__ val, double* __restrict__ Lout,
+                                                          const V* __restrict__ val, const double* __restrict__ G,
+                                                          int U, double* __restrict__ Lout,
                                                           double* __restrict__ Mfrag, double* __restrict__ piv,
                                                           int32_t* __restrict__ bad) {
   __shared__ double A[kBJ * kBJStride];   // block of K, then its factor L (lower part)
@@ -53,6 +54,17 @@ __global__ __launch_bounds__(kBJThreads) void k_bj_factor(int64_t n, const int64
       }
     }
     __syncthreads();
+    if (G) {  // far-field kernel: the block of K_loc + G G^T
+      for (int e = t; e < kBJ * kBJ; e += kBJThreads) {
+        const int i = e / kBJ, j = e % kBJ;
+        if (i < m && j < m) {
+          double s = 0.0;
+          for (int u = 0; u < U; ++u) s += G[(r0 + i) * U + u] * G[(r0 + j) * U + u];
+          A[i * kBJStride + j] += s;
+        }
+      }
+      __syncthreads();
+    }
     // right-looking Cholesky on the lower triangle
     for (int k = 0; k < kBJ; ++k) {
       if (t == 0) {
@@ -266,14 +278,15 @@ static unsigned bj_grid(int64_t n, int64_t cap) {
 }
 
 hipError_t launch_bj_factor(int64_t n, const int64_t* rp, const int32_t* col, const void* val, int prec,
-                            double* L, double* Mfrag, double* piv, int32_t* bad, hipStream_t st) {
+                            const double* G, int U, double* L, double* Mfrag, double* piv, int32_t* bad,
+                            hipStream_t st) {
   const unsigned g = bj_grid(n, 8192);
   if (prec == GP2S_MIXED)
     hipLaunchKernelGGL(k_bj_factor<float>, dim3(g), dim3(kBJThreads), 0, st, n, rp, col,
-                       static_cast<const float*>(val), L, Mfrag, piv, bad);
+                       static_cast<const float*>(val), G, U, L, Mfrag, piv, bad);
   else
     hipLaunchKernelGGL(k_bj_factor<double>, dim3(g), dim3(kBJThreads), 0, st, n, rp, col,
-                       static_cast<const double*>(val), L, Mfrag, piv, bad);
+                       static_cast<const double*>(val), G, U, L, Mfrag, piv, bad);
   return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@ constexpr int kMaxProbes = 64;     // one probe per lane in the block kernels
 constexpr int kMaxBumps = 256;
 constexpr int kReduceBlocks = 4096;  // max workgroups of the reduction-carrying kernels
 constexpr int kBJ = 64;             // rows per block of the block-Jacobi preconditioner
+constexpr int kMaxGroups = 16;      // bump groups U of the far-field kernel
 
 // Uniform grid of cubic bins with side h >= r (slightly enlarged so that rounding
 // in the bin index can never separate two points closer than r by two bins).
@@ -40,6 +41,8 @@ struct CgState {
   int32_t* iters;    // [S] iterations performed per column
   int32_t* flags;    // [4] 0: breakdown (p^T K p <= 0), 2: non-finite, 3: breakdown column
   double* partial;   // [kReduceBlocks * S * 2] per-workgroup partial sums
+  const double* lrC;  // far-field kernel: [U * S] G^T p of the current product (adds |G^T p|^2 to p^T q)
+  int32_t lrU;
   double* hist_a;    // [max_iter * S] alpha history (Lanczos coefficients), or null
   double* hist_b;    // [max_iter * S] beta history, or null
   int32_t max_hist;
@@ -147,7 +150,7 @@ hipError_t launch_bbox(const double* x, int64_t n, int dim, double* part, int32_
 hipError_t launch_prologue(const double* x, int64_t n, const GridDev& g, const double* centers,
                            const double* weights, int P, double bump_w2, int32_t* bin_of,
                            int32_t* slot, int32_t* bin_count, double* g64_user, uint8_t* gam,
-                           hipStream_t st);
+                           hipStream_t st, bool unit = false);  // unit: g = 1 at every point
 hipError_t launch_scatter(int64_t n, const int32_t* bin_of, const int32_t* slot,
                           const int64_t* bin_start, int32_t* perm_tmp, hipStream_t st);
 hipError_t launch_binsort(int64_t n, const int32_t* perm_tmp, const int32_t* bin_of,
@@ -214,12 +217,13 @@ struct CrossArgs {
 };
 hipError_t launch_test_prologue(const double* x, int64_t nt, const GridDev& g, const double* centers,
                                 const double* weights, int P, double bump_w2, float4* pts32, double4* pts64,
-                                double* g64, int32_t* bin, int32_t* nonfinite, hipStream_t st);
+                                double* g64, int32_t* bin, int32_t* nonfinite, hipStream_t st, bool unit = false);
 hipError_t launch_cross_count(const CrossArgs& a, int prec, int32_t* row_cnt, hipStream_t st);
 hipError_t launch_cross_fill(const CrossArgs& a, int prec, const int64_t* row_ptr, int32_t* col, void* val,
                              hipStream_t st);
+// raw: values unscaled (cs untouched), for right-hand sides completed and scaled later
 hipError_t launch_cross_block(int prec, const int64_t* rp, const int32_t* col, const void* val, int64_t t0, int S,
-                              double* B, double* cs, hipStream_t st);
+                              double* B, double* cs, hipStream_t st, bool raw = false);
 hipError_t launch_cross_var(int prec, const int64_t* rp, const int32_t* col, const void* val, int64_t t0, int S,
                             const double* Vs, const double* cs, const double* g64t, double* var, hipStream_t st);
 
@@ -257,6 +261,21 @@ hipError_t launch_gather_rows(int64_t n, int S, const int32_t* perm, const doubl
 hipError_t launch_scatter_rows(int64_t n, int S, const int32_t* perm, const double* src_int,
                                double* dst_user, hipStream_t st);
 hipError_t launch_cg_init_fin(const CgState& cs, int nb, int S, double tol, hipStream_t st);
+
+// farfield.hip: the rank-U bump term of Eq. bump_kernel (K = K_loc + G G^T)
+hipError_t launch_ff_G(int64_t n, int dim, const double* x, const double* centers, const double* weights,
+                       const int32_t* group, int P, int U, double bump_w2, double* G, double* diag, hipStream_t st);
+unsigned ff_gtp_blocks(int64_t n);  // partial needs U * S * ff_gtp_blocks(n) doubles
+hipError_t launch_ff_gtp(int64_t n, int S, int U, const double* G, const void* X, bool f32, double* partial,
+                         uint32_t* ticket, double* C, hipStream_t st);
+hipError_t launch_ff_add(int64_t n, int S, int U, const double* G, const double* C, int64_t cu, int64_t cs, double* Y,
+                         hipStream_t st);
+hipError_t launch_ff_wjac(int64_t n, int S, const uint64_t* mask, const double* dinv, double* W, hipStream_t st);
+hipError_t launch_ff_h(int64_t n, int S, int U, const double* a, const double* Q, const double* W, const double* ag,
+                       const double* wg, const double* qg, double* H, hipStream_t st);
+hipError_t launch_ff_colscale(int64_t n, int S, double* B, double* cs, hipStream_t st);
+hipError_t launch_ff_var(int64_t n, int S, int U, const double* B, const double* V, const double* cs,
+                         const double* Gt, int64_t t0, double* var, hipStream_t st);
 hipError_t launch_cg_beta(const CgState& cs, int nb, int S, int32_t iter, hipStream_t st);
 
 // blockjac.hip: block-Jacobi factor (L, M^-1 in matrix-core operand order, pivots
@@ -264,7 +283,8 @@ hipError_t launch_cg_beta(const CgState& cs, int nb, int S, int32_t iter, hipStr
 // (B != nullptr: initialisation r = B, x = 0) with z = M^-1 r, the probe right-hand
 // sides L z, and the direction copy P = Z.
 hipError_t launch_bj_factor(int64_t n, const int64_t* rp, const int32_t* col, const void* val, int prec,
-                            double* L, double* Mfrag, double* piv, int32_t* bad, hipStream_t st);
+                            const double* G, int U, double* L, double* Mfrag, double* piv, int32_t* bad,
+                            hipStream_t st);
 unsigned bj_update_blocks(int64_t n);
 hipError_t launch_bj_update(int64_t n, int S, const double* B, double* X, double* R, const void* P, const void* Q,
                             bool f32vec, const double* Mfrag, double* Z, const CgState& cs, hipStream_t st);
@@ -306,10 +326,12 @@ struct BackwardArgs {
 // Rrow [n], Trow [nr * n], Urow [n], Vrow [n] (length-scale field only, else nullptr)
 hipError_t launch_backward_rows(const BackwardArgs& b, int prec, double* Rrow, double* Trow,
                                 double* Urow, double* Vrow, hipStream_t st);
-// grad = (radius components [nr], a_1..a_P, [c_1..c_P when Vrow], sigma^2)
+// grad = (radius components [nr], a_1..a_P, [c_1..c_P when Vrow], sigma^2); with Hrow
+// (far-field kernel) amplitude p takes sum_i bhat_p(x_i) Hrow[i * U + group[p]] in place of R
 hipError_t launch_grad_reduce(int64_t n, int dim, int P, int S, int nr, const double* x64, const double* g64,
                               const double* a, const double* Rrow, const double* Trow,
-                              const double* Urow, const double* Vrow, const double* centers, double bump_w2,
+                              const double* Urow, const double* Vrow, const double* Hrow, const int32_t* group,
+                              int U, const double* centers, double bump_w2,
                               double* partial, uint32_t* ticket, double* grad, hipStream_t st);
 // lsq[i] = l(x_i)^2 = exp(2 sum_q c_q bhat_q(x_i)) for n points x (row-major, dim)
 hipError_t launch_ell(int64_t n, int dim, const double* x, const double* centers, const double* ls_w, int P,

@@ -112,8 +112,10 @@ __device__ inline double column_sum(const double* partial, int nb, int W, int wh
 __global__ __launch_bounds__(kBlock) void k_cg_alpha(CgState cs, int nb, int S) {
   __shared__ double sh[kBlock];
   const int s = blockIdx.x;
-  const double pq = column_sum(cs.partial, nb, 1, 0, S, s, sh);
+  double pq = column_sum(cs.partial, nb, 1, 0, S, s, sh);
   if (threadIdx.x == 0) {
+    if (cs.lrC)  // far-field kernel: p^T G G^T p = |G^T p|^2
+      for (int u = 0; u < cs.lrU; ++u) pq += cs.lrC[u * S + s] * cs.lrC[u * S + s];
     double a = 0.0;
     if (!cs.done[s]) {
       if (!(pq > 0.0) || !isfinite(pq)) {

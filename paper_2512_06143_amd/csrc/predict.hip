@@ -24,7 +24,7 @@ __global__ __launch_bounds__(kBlock) void k_test_prologue(const double* __restri
                                                           const double* __restrict__ weights, int P, double bump_w2,
                                                           float4* __restrict__ pts32, double4* __restrict__ pts64,
                                                           double* __restrict__ g64, int32_t* __restrict__ bin,
-                                                          int32_t* __restrict__ nonfinite) {
+                                                          int32_t* __restrict__ nonfinite, int unit) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= nt) return;
   const int dim = g.dim;
@@ -42,6 +42,10 @@ __global__ __launch_bounds__(kBlock) void k_test_prologue(const double* __restri
   double gs = 0.0;
   bool inside = false;
   bump_mask(xi, dim, centers, weights, P, bump_w2, gs, inside);
+  if (unit) {  // far-field kernel: no bump mask on the Wendland term
+    gs = 1.0;
+    inside = true;
+  }
   if (bad) inside = false;
   if (pts32) pts32[i] = make_float4((float)xi[0], (float)xi[1], (float)xi[2], inside ? (float)gs : -1.0f);
   if (pts64) pts64[i] = make_double4(xi[0], xi[1], xi[2], inside ? gs : -1.0);
@@ -51,11 +55,11 @@ __global__ __launch_bounds__(kBlock) void k_test_prologue(const double* __restri
 
 hipError_t launch_test_prologue(const double* x, int64_t nt, const GridDev& g, const double* centers,
                                 const double* weights, int P, double bump_w2, float4* pts32, double4* pts64,
-                                double* g64, int32_t* bin, int32_t* nonfinite, hipStream_t st) {
+                                double* g64, int32_t* bin, int32_t* nonfinite, hipStream_t st, bool unit) {
   const int64_t blocks = (nt + kBlock - 1) / kBlock;
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_test_prologue, dim3((unsigned)blocks), dim3(kBlock), 0, st, x, nt, g, centers, weights, P,
-                     bump_w2, pts32, pts64, g64, bin, nonfinite);
+                     bump_w2, pts32, pts64, g64, bin, nonfinite, unit ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -181,11 +185,15 @@ __device__ inline double ldv(const void* val, int64_t k) {
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_cross_block(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                         const void* __restrict__ val, int64_t t0, int S,
-                                                        double* __restrict__ B, double* __restrict__ cs) {
+                                                        double* __restrict__ B, double* __restrict__ cs, int raw) {
   const int lane = threadIdx.x & (kWave - 1);
   const int s = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
   if (s >= S) return;
   const int64_t b = rp[t0 + s], e = rp[t0 + s + 1];
+  if (raw) {
+    for (int64_t k = b + lane; k < e; k += kWave) B[(int64_t)col[k] * S + s] = ldv<V>(val, k);
+    return;
+  }
   double mx = 0.0;
   for (int64_t k = b + lane; k < e; k += kWave) mx = fmax(mx, fabs(ldv<V>(val, k)));
 #pragma unroll
@@ -218,12 +226,12 @@ __global__ __launch_bounds__(kBlock) void k_cross_var(const int64_t* __restrict_
 }
 
 hipError_t launch_cross_block(int prec, const int64_t* rp, const int32_t* col, const void* val, int64_t t0, int S,
-                              double* B, double* cs, hipStream_t st) {
+                              double* B, double* cs, hipStream_t st, bool raw) {
   const int blocks = (S + kBlock / kWave - 1) / (kBlock / kWave);
   if (prec == GP2S_MIXED)
-    hipLaunchKernelGGL(k_cross_block<float>, dim3(blocks), dim3(kBlock), 0, st, rp, col, val, t0, S, B, cs);
+    hipLaunchKernelGGL(k_cross_block<float>, dim3(blocks), dim3(kBlock), 0, st, rp, col, val, t0, S, B, cs, raw ? 1 : 0);
   else
-    hipLaunchKernelGGL(k_cross_block<double>, dim3(blocks), dim3(kBlock), 0, st, rp, col, val, t0, S, B, cs);
+    hipLaunchKernelGGL(k_cross_block<double>, dim3(blocks), dim3(kBlock), 0, st, rp, col, val, t0, S, B, cs, raw ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_prologue(const double* __restrict__ 
                                                      int32_t* __restrict__ slot,
                                                      int32_t* __restrict__ bin_count,
                                                      double* __restrict__ g64_user,
-                                                     uint8_t* __restrict__ gam) {
+                                                     uint8_t* __restrict__ gam, int unit) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int dim = g.dim;
@@ -80,6 +80,10 @@ __global__ __launch_bounds__(kBlock) void k_prologue(const double* __restrict__ 
   double gsum = 0.0;
   bool inside = false;
   bump_mask(xi, dim, centers, weights, P, bump_w2, gsum, inside);
+  if (unit) {  // far-field kernel: the Wendland term carries no bump mask
+    gsum = 1.0;
+    inside = true;
+  }
   bin_of[i] = (int32_t)b;
   slot[i] = atomicAdd(&bin_count[b], 1);
   g64_user[i] = inside ? gsum : 0.0;
@@ -89,10 +93,10 @@ __global__ __launch_bounds__(kBlock) void k_prologue(const double* __restrict__ 
 hipError_t launch_prologue(const double* x, int64_t n, const GridDev& g, const double* centers,
                            const double* weights, int P, double bump_w2, int32_t* bin_of,
                            int32_t* slot, int32_t* bin_count, double* g64_user, uint8_t* gam,
-                           hipStream_t st) {
+                           hipStream_t st, bool unit) {
   int64_t blocks = (n + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_prologue, dim3((unsigned)blocks), dim3(kBlock), 0, st, x, n, g, centers,
-                     weights, P, bump_w2, bin_of, slot, bin_count, g64_user, gam);
+                     weights, P, bump_w2, bin_of, slot, bin_count, g64_user, gam, unit ? 1 : 0);
   return hipGetLastError();
 }
 

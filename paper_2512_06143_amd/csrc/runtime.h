@@ -62,6 +62,11 @@ struct gp2s_matrix_s {
   double* ls_d = nullptr;
   double* lsq = nullptr;
   double ell_bound = 1.0;
+  // far-field kernel (Eq. bump_kernel): group of every bump, U groups, G [n * U]
+  std::vector<int32_t> ffgrp_h;
+  int32_t* ffgrp_d = nullptr;
+  int ffU = 0;
+  double* ffG = nullptr;
   std::vector<double> centers_h, weights_h;
   double* centers_d = nullptr;
   double* weights_d = nullptr;

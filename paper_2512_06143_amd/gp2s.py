@@ -39,7 +39,7 @@ class Params(ctypes.Structure):
                 ("bump_width", ctypes.c_double), ("noise_var", ctypes.c_double),
                 ("centers", ctypes.POINTER(ctypes.c_double)), ("weights", ctypes.POINTER(ctypes.c_double)),
                 ("kernel", ctypes.c_int32), ("radii", ctypes.POINTER(ctypes.c_double)),
-                ("ls_weights", ctypes.POINTER(ctypes.c_double))]
+                ("ls_weights", ctypes.POINTER(ctypes.c_double)), ("ff_groups", ctypes.POINTER(ctypes.c_int32))]
 
 
 WENDLAND = {"c2": 0, "c6": 1}  # Wendland member: C^2, or the printed C^6 of Eq. wendland
@@ -154,6 +154,7 @@ class HostParams:
     kernel: int | str = 0  # 0 / "c2" or 1 / "c6"
     radii: np.ndarray | None = None       # per-axis radii (axis-anisotropic W), or None
     ls_weights: np.ndarray | None = None  # c_q of the length-scale field (Eq. wendconv), or None
+    ff_groups: np.ndarray | None = None   # group of each bump for the far-field kernel (Eq. bump_kernel), or None
 
     def n_grad(self) -> int:
         """Length of the gradient: (r | r_1..r_d, a_1..a_P, [c_1..c_P], sigma^2)."""
@@ -166,11 +167,14 @@ class HostParams:
         w = np.ascontiguousarray(self.weights, dtype=np.float64).reshape(-1)
         r = None if self.radii is None else np.ascontiguousarray(self.radii, dtype=np.float64).reshape(-1)
         ls = None if self.ls_weights is None else np.ascontiguousarray(self.ls_weights, dtype=np.float64).reshape(-1)
+        grp = None if self.ff_groups is None else np.ascontiguousarray(self.ff_groups, dtype=np.int32).reshape(-1)
+        ip = ctypes.POINTER(ctypes.c_int32)
         kern = WENDLAND[self.kernel] if isinstance(self.kernel, str) else int(self.kernel)
         p = Params(int(self.dim), int(w.shape[0]), float(self.radius), float(self.bump_width),
                    float(self.noise_var), c.ctypes.data_as(dp), w.ctypes.data_as(dp), kern,
-                   r.ctypes.data_as(dp) if r is not None else dp(), ls.ctypes.data_as(dp) if ls is not None else dp())
-        return p, (c, w, r, ls)  # keep the arrays alive while p is used
+                   r.ctypes.data_as(dp) if r is not None else dp(), ls.ctypes.data_as(dp) if ls is not None else dp(),
+                   grp.ctypes.data_as(ip) if grp is not None else ip())
+        return p, (c, w, r, ls, grp)  # keep the arrays alive while p is used
 
 
 def _ptr(t) -> int:

@@ -59,6 +59,9 @@ def _params(B, **kw):
     (dict(ls_weights=[0.7]), 10, 0),
     (dict(ls_weights=[25.0]), 10, 1),
     (dict(ls_weights=[float("inf")]), 10, 7),
+    (dict(ff_groups=[0]), 10, 0),
+    (dict(ff_groups=[16]), 10, 1),
+    (dict(ff_groups=[0], radii=[0.05, 0.05]), 10, 1),
 ])
 def test_host_validation(kw, n, code):
     B, ctx = _ctx()
