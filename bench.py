@@ -224,6 +224,37 @@ def bench_mcmc(G, x, y, params, precision, opts, n_sweeps=1):
     return out
 
 
+def bench_variants(G, x, y, params, precision, opts, steps=1):
+    """One assemble + LML + gradient per kernel variant on the timed workload (outside
+    the timed step): the C^6 member, the non-stationary convolution form (Eq. wendconv)
+    with axis radii and a length-scale field, and the far-field bump kernel
+    (Eq. bump_kernel) with the bumps in 4 groups."""
+    import dataclasses
+    import numpy as np
+    import torch
+    P = len(np.asarray(params.weights))
+    r = params.radius
+    variants = {
+        "wendland_c6": dataclasses.replace(params, kernel=1),
+        "wendconv_ard": dataclasses.replace(params, radii=np.array([r, 0.8 * r] + [r] * (params.dim - 2)),
+                                            ls_weights=np.array([0.15 if q % 2 else -0.15 for q in range(P)])),
+        "far_field_u4": dataclasses.replace(params, ff_groups=np.arange(P, dtype=np.int32) % 4),
+    }
+    out = {}
+    for name, hp in variants.items():
+        run_step(G, x, y, hp, precision, opts)  # warm (tuning of the new matrix's products)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rep, grad, n, nnz = run_step(G, x, y, hp, precision, opts)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        out[name] = {"s_per_lml_grad": t, "nnz": nnz, "iters": [rep.iters, rep.probe_iters], "lml": rep.lml,
+                     "n_grad": len(grad)}
+        log(f"[bench] variant {name}: {t:.3f}s per LML+grad, nnz={nnz}, iters y={rep.iters} probes={rep.probe_iters}")
+    return out
+
+
 def bench_batch(args):
     """64 independent instances (c5) planned once, then evaluated together per step:
     reassembly with the step's hyperparameters, y solves, probe solves, log-dets, LMLs
@@ -291,6 +322,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-predict", action="store_true", help="skip the posterior (test-point) measurement")
     ap.add_argument("--no-mcmc", action="store_true", help="skip the block Metropolis-Hastings sweep")
+    ap.add_argument("--no-variants", action="store_true", help="skip the kernel-variant measurements")
     ap.add_argument("--precond", default="block", choices=["block", "jacobi"],
                     help="preconditioner of the timed step (the other one is timed once beside it)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -434,6 +466,8 @@ def main():
         out["posterior"] = bench_posterior(G, x, y, params, args.precision, prob)
     if not args.no_mcmc:
         out["mcmc"] = bench_mcmc(G, x, y, params, args.precision, opts)
+    if not args.no_variants:
+        out["variants"] = bench_variants(G, x, y, params, args.precision, opts)
     if not args.no_cpu:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(prob, nnz, jac_iters[0], jac_iters[1], S)
