@@ -290,7 +290,7 @@ hipError_t launch_bj_factor(int64_t n, const int64_t* rp, const int32_t* col, co
   return hipGetLastError();
 }
 
-unsigned bj_update_blocks(int64_t n) { return bj_grid(n, kReduceBlocks); }
+unsigned bj_update_blocks(int64_t n) { return bj_grid(n, kDotBlocks); }
 
 hipError_t launch_bj_update(int64_t n, int S, const double* B, double* X, double* R, const void* P, const void* Q,
                             bool f32vec, const double* Mfrag, double* Z, const CgState& cs, hipStream_t st) {

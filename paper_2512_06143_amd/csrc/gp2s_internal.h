@@ -16,6 +16,7 @@ constexpr int kBlock = 256;        // threads per workgroup for streaming kernel
 constexpr int kMaxProbes = 64;     // one probe per lane in the block kernels
 constexpr int kMaxBumps = 256;
 constexpr int kReduceBlocks = 4096;  // max workgroups of the reduction-carrying kernels
+constexpr int kDotBlocks = 1024;     // workgroups of the block-preconditioned CG update (fewer partials per finalize)
 constexpr int kBJ = 64;             // rows per block of the block-Jacobi preconditioner
 constexpr int kMaxGroups = 16;      // bump groups U of the far-field kernel
 
