@@ -62,6 +62,8 @@ def block_kernel_name(variant, S):
         return f"k_spmm_s<{S}, float, float, true>"
     if variant == 2:
         return f"k_spmm_t<{S}, float, float, true>"
+    if variant == 3:
+        return f"k_spmm_g<{S}, float, float, true>"
     return f"k_spmm_e<{variant}, {S}, float, float, true>"
 
 

@@ -128,10 +128,56 @@ gp2s_status ensure_tiles(gp2s_ctx ctx, gp2s_matrix m) {
   return GP2S_OK;
 }
 
+// Builds the row-grouped copy (pattern once; values again after a refill). Skipped
+// (variant 3 unavailable) when it would not fit in memory or in 32-bit slots.
+gp2s_status ensure_groups(gp2s_ctx ctx, gp2s_matrix m) {
+  hipStream_t st = ctx->stream;
+  const int64_t n = m->n;
+  const int64_t ng = (n + kGrp - 1) / kGrp;
+  if (!m->grp_tried) {
+    m->grp_tried = true;
+    Scratch sc(ctx);
+    int32_t* cnt = sc.get<int32_t>(ng);
+    void* ws = sc.get<uint8_t>(scan_workspace_bytes(ng));
+    int64_t* gp = own<int64_t>(m, ng + 1);
+    if (sc.oom || !gp) return GP2S_OK;
+    HIPCHK(launch_grp_count(n, m->row_ptr, m->col, ng, cnt, st));
+    HIPCHK(launch_exscan_i32_i64(cnt, gp, ng, ws, st));
+    int64_t tot = 0;
+    gp2s_status s = readback(ctx, gp + ng, sizeof(int64_t), &tot);
+    if (s) return s;
+    if (tot * kGrp >= (int64_t)INT32_MAX) return GP2S_OK;
+    int32_t* gc = own<int32_t>(m, std::max<int64_t>(tot, 1));
+    int32_t* mp = own<int32_t>(m, std::max<int64_t>(m->nnz, 1));
+    void* gv = m->prec == GP2S_MIXED ? (void*)own<float>(m, std::max<int64_t>(tot * kGrp, 1))
+                                     : (void*)own<double>(m, std::max<int64_t>(tot * kGrp, 1));
+    if (!gc || !mp || !gv) return GP2S_OK;
+    HIPCHK(launch_grp_fill(n, m->row_ptr, m->col, ng, gp, gc, mp, st));
+    m->grp_ptr = gp;
+    m->grp_col = gc;
+    m->grp_val = gv;
+    m->grp_map = mp;
+    m->grp_n = tot;
+  }
+  if (m->grp_ptr && !m->grp_values) {
+    const size_t vb = m->prec == GP2S_MIXED ? sizeof(float) : sizeof(double);
+    HIPCHK(hipMemsetAsync(m->grp_val, 0, (size_t)m->grp_n * kGrp * vb, st));
+    HIPCHK(launch_grp_values(m->nnz, m->val, m->prec, m->grp_map, m->grp_val, st));
+    m->grp_values = true;
+  }
+  return GP2S_OK;
+}
+
 TileSet tile_set(gp2s_matrix m) {
   TileSet t;
   t.t = m->tiles;
   t.n = m->ntiles;
+  if (m->grp_ptr && m->grp_values) {
+    t.gptr = m->grp_ptr;
+    t.gcol = m->grp_col;
+    t.gval = m->grp_val;
+    t.ngroups = (m->n + kGrp - 1) / kGrp;
+  }
   return t;
 }
 
@@ -145,6 +191,11 @@ gp2s_status tune_block_product(gp2s_ctx ctx, gp2s_matrix m, int S, const void* P
     gp2s_status ts = ensure_tiles(ctx, m);
     if (ts) return ts;
     if (m->tiles) cand.push_back(2);
+    if (S == 32 || S == 64) {
+      ts = ensure_groups(ctx, m);
+      if (ts) return ts;
+      if (m->grp_ptr) cand.push_back(3);
+    }
   }
   for (int G = 4; G <= 16; G *= 2)
     if (entry_product_ok(S, G)) cand.push_back(G);
@@ -287,6 +338,10 @@ gp2s_status cg_begin(Cg& c, const double* B, double tol, bool keep_hist, Scratch
     if (st) return st;
   }
   c.variant = S > 1 ? m->spmm_variant[S] : 0;
+  if (c.variant == 3) {
+    gp2s_status gs = ensure_groups(ctx, m);
+    if (gs) return gs;
+  }
   return GP2S_OK;
 }
 
@@ -1258,6 +1313,7 @@ gp2s_status gp2s_matrix_refill(gp2s_ctx ctx, gp2s_matrix m, const gp2s_params* p
   hipStream_t sm = ctx->stream;
   const int64_t n = m->n;
   m->bj_ready = false;  // the block factor belongs to the old values
+  m->grp_values = false;  // and so do the grouped copy's values
   m->weights_h.assign(p->weights, p->weights + p->n_bumps);
   m->noise = p->noise_var;
   m->kern = p->kernel;
@@ -1304,7 +1360,7 @@ gp2s_status gp2s_matrix_set_block_product(gp2s_matrix m, int32_t nrhs, int32_t v
   if (!m || nrhs < 2 || nrhs > kMaxProbes) return GP2S_E_INVALID;
   const bool sliced = nrhs == 8 || nrhs == 16 || nrhs == 32 || nrhs == 64;
   const bool ok = variant == -1 || variant == 0 || (variant == 1 && sliced) || (variant == 2 && sliced && m->assembled) ||
-                  entry_product_ok(nrhs, variant);
+                  (variant == 3 && (nrhs == 32 || nrhs == 64)) || entry_product_ok(nrhs, variant);
   if (!ok) return GP2S_E_INVALID;
   m->spmm_variant[nrhs] = variant == -1 ? -2 : variant;
   return GP2S_OK;
@@ -1331,6 +1387,10 @@ gp2s_status gp2s_spmv(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X
   double* Xi = sc.get<double>((size_t)n * nrhs);
   double* Yi = sc.get<double>((size_t)n * nrhs);
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "spmv workspace allocation failed");
+  if (nrhs > 1 && m->spmm_variant[nrhs] == 3) {
+    st = ensure_groups(ctx, m);
+    if (st) return st;
+  }
   if (nrhs > 1 && m->spmm_variant[nrhs] == 2) {
     st = ensure_tiles(ctx, m);
     if (st) return st;

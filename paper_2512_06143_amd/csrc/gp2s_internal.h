@@ -101,10 +101,21 @@ struct RowTile {
   int32_t rows, niv;
   int32_t lo[kTileMaxIv], len[kTileMaxIv];
 };
+constexpr int kGrp = 8;  // rows per group of the row-grouped block product (grouped.hip)
 struct TileSet {
   const RowTile* t = nullptr;
   int64_t n = 0;
+  // row-grouped copy (variant 3): union columns of kGrp consecutive rows, one value per row
+  const int64_t* gptr = nullptr;
+  const int32_t* gcol = nullptr;
+  const void* gval = nullptr;
+  int64_t ngroups = 0;
 };
+hipError_t launch_grp_count(int64_t n, const int64_t* rp, const int32_t* col, int64_t ngroups, int32_t* cnt,
+                            hipStream_t st);
+hipError_t launch_grp_fill(int64_t n, const int64_t* rp, const int32_t* col, int64_t ngroups, const int64_t* gptr,
+                           int32_t* gcol, int32_t* map, hipStream_t st);
+hipError_t launch_grp_values(int64_t nnz, const void* val, int prec, const int32_t* map, void* gval, hipStream_t st);
 constexpr int kTileLdsBytes = 72 * 1024;  // staged rows of X per workgroup (2 workgroups per CU)
 constexpr int kTileBlock = 1024;          // 16 waves per workgroup hide the row-pointer latency
 constexpr int kTileMaxRows = 64;          // rows per tile (at most)

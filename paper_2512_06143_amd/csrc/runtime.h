@@ -46,6 +46,13 @@ struct gp2s_matrix_s {
   gp2s::RowTile* tiles = nullptr;
   int64_t ntiles = 0;
   bool tiles_tried = false;
+  // row-grouped copy for the block product (built on first use; values refreshed after a refill)
+  int64_t* grp_ptr = nullptr;
+  int32_t* grp_col = nullptr;
+  void* grp_val = nullptr;
+  int32_t* grp_map = nullptr;
+  int64_t grp_n = 0;
+  bool grp_tried = false, grp_values = false;
   gp2s_matrix_s() {
     for (int& v : spmm_variant) v = -2;
   }

@@ -380,6 +380,104 @@ static bool spmm_entry(int G, const int64_t* rp, const int32_t* col, const V* va
   return false;
 }
 
+// Row-grouped block product (S in {32, 64}): one wave per group of kGrp consecutive
+// rows. NSUB lane sets walk interleaved union columns (LE lanes cover one row of X with
+// 16-byte slices, so every load instruction moves NSUB distinct rows of X) and apply
+// each gathered slice to all kGrp rows of the group with their values (zero where a
+// row has no entry): a row of X is read once per group instead of once per stored
+// entry. The union columns are fetched 64 at a time, one per lane, and handed to the
+// lane sets by shuffles, so the gathers do not wait on dependent loads. The NSUB
+// partial sums are combined by a fixed butterfly; products accumulate in float64.
+template <int S, typename V, typename PT, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_spmm_g(const int64_t* __restrict__ gptr, const int32_t* __restrict__ gcol,
+                                                   const V* __restrict__ gval, int64_t ngroups, int64_t n,
+                                                   const PT* __restrict__ X, double* __restrict__ Y, CgState cs) {
+  constexpr int VW = 16 / sizeof(PT);  // elements of X per lane
+  constexpr int LE = S / VW;           // lanes per row of X
+  constexpr int NSUB = kWave / LE;     // union columns per step
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int cq = lane % LE, sub = lane / LE;
+  const XcdRows rr = xcd_rows(ngroups, wid, kBlock / kWave);
+  double dot[VW];
+#pragma unroll
+  for (int c = 0; c < VW; ++c) dot[c] = 0.0;
+  for (int64_t g = rr.first; g < rr.end; g += rr.step) {
+    double acc[kGrp][VW];
+#pragma unroll
+    for (int r = 0; r < kGrp; ++r)
+#pragma unroll
+      for (int c = 0; c < VW; ++c) acc[r][c] = 0.0;
+    const int64_t b = gptr[g], e = gptr[g + 1];
+    for (int64_t k0 = b; k0 < e; k0 += kWave) {
+      const int cnt = (int)((e - k0) < kWave ? (e - k0) : kWave);
+      const int32_t colreg = lane < cnt ? gcol[k0 + lane] : 0;
+#pragma unroll 2
+      for (int j = 0; j < cnt; j += NSUB) {
+        const int idx = j + sub;
+        const int32_t c = __shfl(colreg, idx, kWave);
+        if (idx < cnt) {
+          PT x[VW];
+          *reinterpret_cast<float4*>(x) = *reinterpret_cast<const float4*>(X + (int64_t)c * S + cq * VW);
+          V v[kGrp];
+#pragma unroll
+          for (int q = 0; q < kGrp * (int)sizeof(V) / 16; ++q)
+            reinterpret_cast<float4*>(v)[q] = reinterpret_cast<const float4*>(gval + (k0 + idx) * kGrp)[q];
+#pragma unroll
+          for (int r = 0; r < kGrp; ++r)
+#pragma unroll
+            for (int cc = 0; cc < VW; ++cc) acc[r][cc] = fma((double)v[r], (double)x[cc], acc[r][cc]);
+        }
+      }
+    }
+#pragma unroll
+    for (int off = LE; off < kWave; off <<= 1)
+#pragma unroll
+      for (int r = 0; r < kGrp; ++r)
+#pragma unroll
+        for (int c = 0; c < VW; ++c) acc[r][c] += __shfl_xor(acc[r][c], off, kWave);
+    if (sub == 0) {
+#pragma unroll
+      for (int r = 0; r < kGrp; ++r) {
+        const int64_t row = g * kGrp + r;
+        if (row < n) {
+          const int64_t o = row * S + cq * VW;
+#pragma unroll
+          for (int c = 0; c < VW; ++c) {
+            Y[o + c] = acc[r][c];
+            if (DOT) dot[c] += acc[r][c] * (double)X[o + c];
+          }
+        }
+      }
+    }
+  }
+  if (!DOT) return;
+  __shared__ double sh[kBlock / kWave][S];
+  if (sub == 0)
+#pragma unroll
+    for (int c = 0; c < VW; ++c) sh[wid][cq * VW + c] = dot[c];
+  __syncthreads();
+  if ((int)threadIdx.x < S) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += sh[w][threadIdx.x];
+    cs.partial[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+// Launches k_spmm_g when S has an instance, the grouped copy exists and X is 16-byte aligned.
+template <typename V, typename PT, bool DOT>
+static bool spmm_grouped(int64_t n, int S, const TileSet& ts, const PT* X, double* Y, const CgState& cs,
+                         hipStream_t st, int64_t blocks) {
+  if ((S != 32 && S != 64) || !ts.gptr || ts.ngroups < 1 || (reinterpret_cast<uintptr_t>(X) & 15) != 0) return false;
+  const V* gv = static_cast<const V*>(ts.gval);
+  dim3 grid((unsigned)blocks), block(kBlock);
+  if (S == 32)
+    hipLaunchKernelGGL((k_spmm_g<32, V, PT, DOT>), grid, block, 0, st, ts.gptr, ts.gcol, gv, ts.ngroups, n, X, Y, cs);
+  else
+    hipLaunchKernelGGL((k_spmm_g<64, V, PT, DOT>), grid, block, 0, st, ts.gptr, ts.gcol, gv, ts.ngroups, n, X, Y, cs);
+  return true;
+}
+
 // Launches k_spmm_s when S has an instance and X is 16-byte aligned.
 template <typename V, typename PT, bool DOT>
 static bool spmm_slices(const int64_t* rp, const int32_t* col, const V* val, int64_t n, int S, const PT* X, double* Y,
@@ -420,9 +518,9 @@ static bool spmm_tiles(const int64_t* rp, const int32_t* col, const V* val, int 
   return true;
 }
 
-// variant: 0 lane per column, 1 slice per lane, 2 LDS-staged row tiles, G > 2
-// entry-parallel with G lanes per row, -1 heuristic (entry-parallel up to 32 columns,
-// else one lane per column).
+// variant: 0 lane per column, 1 slice per lane, 2 LDS-staged row tiles, 3 row groups,
+// G > 3 entry-parallel with G lanes per row, -1 heuristic (entry-parallel up to 32
+// columns, else one lane per column).
 template <typename V, typename PT, bool DOT>
 static hipError_t spmm_dispatch(const int64_t* rp, const int32_t* col, const V* val, int64_t n, int S,
                                 double mean_row, int variant, const TileSet& tiles, const PT* X, double* Y,
@@ -447,7 +545,15 @@ static hipError_t spmm_dispatch(const int64_t* rp, const int32_t* col, const V* 
       if (nblocks) *nblocks = (int)tb;
       return hipGetLastError();
     }
-  } else if (G > 2) {
+  } else if (G == 3) {
+    int64_t gb = (tiles.ngroups + kBlock / kWave - 1) / (kBlock / kWave);
+    if (gb > cap) gb = cap;
+    gb = round_up8(gb < 1 ? 1 : gb);
+    if (spmm_grouped<V, PT, DOT>(n, S, tiles, X, Y, cs, st, gb)) {
+      if (nblocks) *nblocks = (int)gb;
+      return hipGetLastError();
+    }
+  } else if (G > 3) {
     const int64_t eb = grid_for(kBlock / G);
     if (spmm_entry<V, PT, DOT>(G, rp, col, val, n, S, X, Y, cs, st, eb)) {
       if (nblocks) *nblocks = (int)eb;

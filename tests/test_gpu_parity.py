@@ -138,11 +138,11 @@ def test_lml_and_gradient_same_probe(case, precision, precond):
             assert grad[k] == 0.0
 
 
-BLOCK_VARIANTS = [0, 1, 2, 4, 8, 16]  # lane per column, column slices, LDS tiles, 4/8/16 lanes per row
+BLOCK_VARIANTS = [0, 1, 2, 3, 4, 8, 16]  # lane per column, column slices, LDS tiles, row groups, 4/8/16 lanes per row
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("nrhs", [8, 16, 64])
+@pytest.mark.parametrize("nrhs", [8, 16, 32, 64])
 def test_block_product_variants(case, precision, nrhs):
     """Every block-product kernel gives the stored matrix's product."""
     G = _G()
@@ -152,7 +152,7 @@ def test_block_product_variants(case, precision, nrhs):
     X = np.random.default_rng(11).standard_normal((prob.n, nrhs))
     ref = Kg @ X
     for v in BLOCK_VARIANTS:
-        if v > nrhs:
+        if v > nrhs or (v == 3 and nrhs not in (32, 64)):  # row groups: 32 or 64 columns
             with pytest.raises(G.GP2SError):
                 m.set_block_product(nrhs, v)
             continue
@@ -164,13 +164,14 @@ def test_block_product_variants(case, precision, nrhs):
         m.set_block_product(7, 1)
 
 
+@pytest.mark.parametrize("S", [16, 64])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_probe_block_variants_same_probe(case, precision):
+def test_probe_block_variants_same_probe(case, precision, S):
     """The CG probe block (products plus per-column p^T q partials) with every kernel
-    reaches the same-probe log-determinant and gradient of the oracle."""
+    that applies to S columns reaches the same-probe log-determinant and gradient of
+    the oracle."""
     G = _G()
     name, prob, Kref, gamma, ex_pts = case
-    S = 16
     m = G.gp2s_assemble(prob.x, params_of(prob), precision)
     Kd = exported_user_csr(m)[0].toarray()
     opts = G.default_opts(n_probes=S, seed=3, tol=1e-10, probe_tol=1e-10, max_iter=40000)
@@ -181,6 +182,8 @@ def test_probe_block_variants_same_probe(case, precision):
                                           prob.weights, prob.noise_var, K=Kd, blocks=blocks)
     scale = np.maximum(np.abs(gref), 1e-6 * (np.abs(gparts["fit"]) + 0.5 * np.abs(gparts["tau"])))
     for v in BLOCK_VARIANTS:
+        if v == 3 and S not in (32, 64):
+            continue
         m.set_block_product(S, v)
         rep, grad, _ = G.gp2s_lml_grad(m, prob.y, opts)
         rel = abs(rep.logdet - gam_ref) / abs(gam_ref)
