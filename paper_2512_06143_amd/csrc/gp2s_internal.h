@@ -101,7 +101,7 @@ struct RowTile {
   int32_t rows, niv;
   int32_t lo[kTileMaxIv], len[kTileMaxIv];
 };
-constexpr int kGrp = 8;  // rows per group of the row-grouped block product (grouped.hip)
+constexpr int kGrp = 4;  // rows per group of the row-grouped block product (grouped.hip)
 struct TileSet {
   const RowTile* t = nullptr;
   int64_t n = 0;

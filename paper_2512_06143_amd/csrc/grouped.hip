@@ -1,8 +1,8 @@
 // Row-grouped copy of a CSR matrix for the multi-column block product.
 //
 // Consecutive rows of the bin order are spatial neighbours, so their column lists
-// overlap heavily (at 63 stored entries per row, 8 consecutive rows reference about a
-// quarter as many distinct columns as they have entries). Grouping kGrp rows and
+// overlap heavily (at 63 stored entries per row, 4 consecutive rows reference 42% as
+// many distinct columns as they have entries, 8 rows 25%). Grouping kGrp rows and
 // storing, for each group, the sorted union of their columns with one value per row
 // (zero where a row has no entry) lets the block product gather each row of X once per
 // group instead of once per entry. The group layout:
@@ -17,7 +17,8 @@
 namespace gp2s {
 
 __device__ inline int32_t wave_min8(int32_t v) {
-  // minimum over lanes 0..7 (kGrp); every lane of the wave takes part in the shuffles
+  // minimum over lanes 0..7 (kGrp <= 8; lanes past kGrp hold INT32_MAX); every lane of
+  // the wave takes part in the shuffles
   v = min(v, __shfl_xor(v, 4, kWave));
   v = min(v, __shfl_xor(v, 2, kWave));
   v = min(v, __shfl_xor(v, 1, kWave));
