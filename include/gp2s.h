@@ -253,8 +253,11 @@ gp2s_status gp2s_matrix_refill(gp2s_ctx ctx, gp2s_matrix m, const gp2s_params* p
 /* Block-product kernel used for `nrhs` columns (2..64) of this matrix, in CG probe
  * blocks and gp2s_spmv: 0 one lane per column (any nrhs), 1 a 16-byte column slice
  * per lane, 2 the same with the rows of X that a tile of bin-sorted rows references
- * staged in LDS (assembled handles only), 4 / 8 / 16 that many lanes splitting each
- * row's stored entries (1, 2, 4, 8 and 16 need nrhs in {8, 16, 32, 64}, and G <= nrhs),
+ * staged in LDS (assembled handles only), 3 rows grouped by 4 with the union of their
+ * columns (each row of X gathered once per group; nrhs 32 or 64; the grouped copy is
+ * built on first use and kept with the handle), 4 / 8 / 16 that many lanes splitting
+ * each row's stored entries (1, 2, 4, 8 and 16 need nrhs in {8, 16, 32, 64}, and
+ * G <= nrhs),
  * -1 (the default) times the candidates on the first CG block product and keeps the
  * fastest. A variant that does not apply gives GP2S_E_INVALID. All variants give the
  * same products up to the order of float64 summation. */

@@ -16,6 +16,8 @@
 
 namespace gp2s {
 
+static_assert(kGrp >= 1 && kGrp <= 8, "the merge holds one row per lane among lanes 0..7");
+
 __device__ inline int32_t wave_min8(int32_t v) {
   // minimum over lanes 0..7 (kGrp <= 8; lanes past kGrp hold INT32_MAX); every lane of
   // the wave takes part in the shuffles
