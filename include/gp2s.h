@@ -273,7 +273,7 @@ gp2s_status gp2s_matrix_get_block_product(gp2s_matrix m, int32_t nrhs, int32_t* 
 gp2s_status gp2s_spmv(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X, double* Y);
 /* (n * nrhs, and n * n_probes below, must stay below 2^31.) */
 
-/* a = K^{-1} y (DEVICE [n] float64 each) by Jacobi-preconditioned CG with float64
+/* a = K^{-1} y (DEVICE [n] float64 each) by preconditioned CG (opts->precond) with float64
  * vectors and dot products, restarted from the recomputed residual (iterative
  * refinement) until ||y - K a|| <= tol ||y||. The paper's host solver is MINRES
  * (App. B.6); K is symmetric positive definite here, so CG reaches the same
@@ -309,7 +309,7 @@ gp2s_status gp2s_lml_grad(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp
  * the observations, so a test point equal to a training point gets none). The
  * cross-covariance uses the training pattern (||x* - x_j|| < r, both points inside
  * some bump) and the handle's storage precision. The variance solves K v_t =
- * k(X, x*_t) with Jacobi-PCG, 64 test points per block, to the relative residual
+ * k(X, x*_t) with preconditioned CG (opts->precond), 64 test points per block, to the relative residual
  * opts->tol within opts->max_iter iterations (opts->n_probes is not used).
  *   x_test: DEVICE [n_test * dim] float64, row-major; a: DEVICE [n] float64, user order;
  *   mean: DEVICE [n_test] float64 (test order); var: DEVICE [n_test] float64, or NULL to

@@ -17,7 +17,8 @@ struct CgRun {
   bool converged = false;
 };
 
-// Jacobi-PCG for K X = B over S columns (internal order) on stream `st`, driven one
+// Preconditioned CG (diagonal or block-Jacobi) for K X = B over S columns (internal
+// order) on stream `st`, driven one
 // iteration at a time so that two solves can be interleaved on two streams. The host
 // polls the per-column done flags without stalling the stream: every check_every
 // iterations it queues an asynchronous copy of the flags into a pinned slot plus an

@@ -1,5 +1,6 @@
 // Jacobi-preconditioned conjugate gradients over a block of S independent columns,
-// plus the small streaming kernels the runtime needs (permutations, dots, logs).
+// plus the small streaming kernels the runtime needs (permutations, dots, logs); the
+// block-Jacobi update lives in blockjac.hip and shares the finalizers here.
 //
 // Per iteration: Q = K P (spmv.hip, yields alpha = r^T z / p^T q per column), then
 // this file's update (x += alpha p, r -= alpha q, z = r / diag(K), new r^T z and

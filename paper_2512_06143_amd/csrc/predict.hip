@@ -9,7 +9,7 @@
 // tests the training points of its 3^d neighbouring bins, and survivors are
 // compacted into CSR with a wave ballot. The mean is one CSR SpMV of K* with a.
 // The variance needs K^{-1} k(X, x*_t) for every test point: test points are
-// solved 64 at a time as one block (Jacobi-PCG with the training matrix) whose
+// solved 64 at a time as one block (preconditioned CG with the training matrix) whose
 // right-hand sides are the scattered rows of K*, then var_t = g*_t^2 minus the dot of
 // row t of K* with its solution column.
 #include "gp2s_internal.h"

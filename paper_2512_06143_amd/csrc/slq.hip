@@ -1,9 +1,10 @@
-// Lanczos quadrature of z^T ln(Khat) z from the Jacobi-CG coefficients.
+// Lanczos quadrature of z^T ln(Khat) z from the preconditioned-CG coefficients.
 //
 // The paper computes ln|K| on the host without naming the method ("LOGDET",
-// Sec. 3.5, App. B.6). Here ln|K| = sum_i ln K_ii + tr ln Khat, Khat = D^-1/2 K D^-1/2,
-// and tr ln Khat is estimated with Rademacher probes. Jacobi-preconditioned CG on
-// K q = D^1/2 z is CG on Khat with initial residual z, i.e. Lanczos from z/||z||;
+// Sec. 3.5, App. B.6). Here ln|K| = ln|M| + tr ln Khat, Khat = L^-1 K L^-T with
+// M = L L^T the preconditioner (L = D^1/2, or the blockwise Cholesky factor), and
+// tr ln Khat is estimated with Rademacher probes. Preconditioned CG on K q = L z is
+// CG on Khat with initial residual z, i.e. Lanczos from z/||z||;
 // its coefficients define the Lanczos tridiagonal T (m x m):
 //   T_00 = 1/alpha_0,  T_kk = 1/alpha_k + beta_{k-1}/alpha_{k-1},
 //   T_{k-1,k}^2 = beta_{k-1} / alpha_{k-1}^2,
