@@ -89,3 +89,48 @@ def test_sampler_follows_oracle_decisions(gpu):
         np.testing.assert_allclose(res["lml"], np.array(lls_o), rtol=1e-8)
     assert compared >= len(acc_o) // 2
     assert res["refills"] > 0 and res["evals"] == sum(m is not None for m in marg_o)
+
+
+def test_sampler_with_the_general_kernel(gpu):
+    """The same decisions as the oracle sampler for Eq. wendconv with axis radii and
+    length-scale weights (theta = (r_1, r_2, a, c, sigma^2)); moves of a or sigma^2 may
+    refill (when the spare handle holds the current pattern), moves of the radii or c
+    assemble."""
+    from oracle import wendconv as WC
+    G = _G()
+    prob = workloads.make_random_problem(54, 600, 2, 0.12, n_bumps=2, bump_width=0.6)
+    S, seed = 8, 22
+    opts = G.default_opts(n_probes=S, seed=seed, tol=1e-10, probe_tol=1e-10, max_iter=50000)
+    p0 = G.HostParams(2, prob.radius, prob.bump_width, prob.noise_var, prob.centers, prob.weights, 0,
+                      np.array([0.12, 0.09]), np.array([0.3, -0.2]))
+    theta0 = G.mcmc.theta_of(p0)
+    assert len(theta0) == 2 + 2 + 2 + 1
+    steps = np.array([0.01, 0.01, 0.15, 0.15, 0.1, 0.1, 0.3 * prob.noise_var])
+    blocks = [[0, 1], [2, 3], [4, 5], [6]]
+    bounds = (np.array([0.02, 0.02, 0.05, 0.05, -3, -3, 1e-6]), np.array([0.5, 0.5, 5, 5, 3, 3, 1e-2]))
+    draws = workloads.mcmc_draws(98, 3, [len(b) for b in blocks])
+    Z = oracle.rademacher_probes(seed, S, prob.n)
+
+    def loglik(th):
+        radii, a, c, nv = th[:2], th[2:4], th[4:6], th[6]
+        K = WC.covariance_dense(prob.x, radii, prob.bump_width, prob.centers, a, nv, ls_weights=c)
+        blocks_ = oracle.block_partition(oracle.bin_order(prob.x, radii, WC.ell_bound(c)), oracle.BLOCK)
+        return oracle.lml_same_probe(K, prob.y, Z, blocks_)[0]
+    chain_o, lls_o, acc_o, marg_o = oracle.block_mh(theta0, blocks, steps, bounds[0], bounds[1], draws, loglik)
+    mh = G.BlockMH(prob.x, prob.y, p0, "fp64", opts, blocks=blocks, steps=steps, bounds=bounds)
+    res = mh.run(len(draws), draws=draws)
+    mh.free()
+    print(f"oracle accepted {acc_o}\ndevice accepted {res['accepted']} (refills {res['refills']}, "
+          f"assemblies {res['assemblies']})", flush=True)
+    tie = 1e-6 * abs(lls_o[0])
+    compared = 0
+    for k, (mo, ao, ad) in enumerate(zip(marg_o, acc_o, res["accepted"])):
+        if mo is not None and abs(mo) < tie:
+            break
+        assert ao == ad, (k, mo)
+        compared += 1
+    else:
+        np.testing.assert_allclose(res["chain"], np.array(chain_o), rtol=1e-14, atol=0)
+        np.testing.assert_allclose(res["lml"], np.array(lls_o), rtol=1e-8)
+    assert compared >= len(acc_o) // 2
+    assert res["assemblies"] + res["refills"] == res["evals"] + 1  # one handle build or refill per LML
