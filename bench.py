@@ -2,11 +2,13 @@
 product bandwidth and the roofline of the dominant kernel.
 
 A step is one pass of the whole hot path over one synthetic instance whose inputs
-are already in HBM: bin + cull + assemble K, solve K a = y (Jacobi-PCG with
-refinement), probe solves + Lanczos log-determinant, LML, and the gradient kernel.
+are already in HBM: bin + cull + assemble K, solve K a = y (block-Jacobi PCG with
+refinement), probe solves + log-determinant, LML, and the gradient kernel.
 Default workload: 200 000 uniform 2-D points, r = 0.01 (63 stored entries per row),
 8 bumps, 64 probes; float32 K with float64 CG, timed against the float64-plain path
-on the same inputs. `--config c4` runs the 10 000 000-point clustered workload.
+on the same inputs. `--config c4` runs the 10 000 000-point clustered workload; by
+default its assembly and standalone single-RHS product are measured beside the step
+(`large` in the JSON line).
 
 Prints one JSON line (last line of stdout).
 """
@@ -257,6 +259,52 @@ def bench_variants(G, x, y, params, precision, opts, steps=1):
     return out
 
 
+def bench_large(G, config="c4", reps=3, spmv_reps=20):
+    """Assembly and the standalone single-RHS product on the 10 000 000-point clustered
+    workload, float32 and float64 storage (outside the timed step: an LML+gradient at this
+    size takes minutes). Reports K nnz/s assembled and the product's algorithmic HBM rate,
+    both from the library's HIP events."""
+    import numpy as np
+    import torch
+    import workloads
+    t0 = time.perf_counter()
+    prob = workloads.make_problem(config)
+    log(f"[bench] large: generated {config}: n={prob.n} r={prob.radius:.6g} ({time.perf_counter() - t0:.1f}s)")
+    x = torch.as_tensor(prob.x).cuda()
+    params = G.HostParams(prob.dim, prob.radius, prob.bump_width, prob.noise_var, prob.centers, prob.weights)
+    v = torch.as_tensor(np.random.default_rng(0).standard_normal(prob.n)).cuda()
+    ctx = G.default_context()
+    out = {"workload": (f"{config}: {prob.n} {prob.meta.get('points', 'uniform')} {prob.dim}-D points, "
+                        f"r={prob.radius:.6g}, {prob.n_bumps} bumps"), "n": prob.n}
+    for prec in ("mixed", "fp64"):
+        G.gp2s_assemble(x, params, prec).free()  # warm
+        ctx.set_timing(True)
+        for k in range(reps):
+            m = G.gp2s_assemble(x, params, prec)
+            if k < reps - 1:
+                m.free()
+        st = ctx.stats()
+        asm_ms = sum(st[k][0] for k in ("asm_prep", "asm_count", "asm_fill")) / reps
+        n, nnz = m.n, m.nnz
+        G.gp2s_spmv(m, v)  # warm
+        ctx.set_timing(True)
+        for _ in range(spmv_reps):
+            G.gp2s_spmv(m, v)
+        ms, cnt = ctx.stats()["spmv"]
+        ctx.set_timing(False)
+        m.free()
+        b = kernel_bytes("spmv", n, nnz, 1, prec)
+        gbs = b / (ms / cnt / 1e3) / 1e9
+        out[prec] = {"nnz": nnz, "assembly_ms": asm_ms, "assembly_nnz_per_s": nnz / (asm_ms / 1e3),
+                     "spmv_ms": ms / cnt, "spmv_bytes": b, "spmv_GBps": gbs, "spmv_frac_hbm": gbs * 1e9 / PEAK_HBM}
+        log(f"[bench] large {prec}: nnz={nnz} ({nnz / n:.1f}/row), assembly {asm_ms:.2f} ms "
+            f"({nnz / (asm_ms / 1e3):.3g} nnz/s), spmv {ms / cnt:.3f} ms = {gbs:.0f} GB/s "
+            f"({100 * gbs * 1e9 / PEAK_HBM:.1f}% of HBM)")
+    del x, v
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_batch(args):
     """64 independent instances (c5) planned once, then evaluated together per step:
     reassembly with the step's hyperparameters, y solves, probe solves, log-dets, LMLs
@@ -325,6 +373,8 @@ def main():
     ap.add_argument("--no-predict", action="store_true", help="skip the posterior (test-point) measurement")
     ap.add_argument("--no-mcmc", action="store_true", help="skip the block Metropolis-Hastings sweep")
     ap.add_argument("--no-variants", action="store_true", help="skip the kernel-variant measurements")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 10 M-point assembly and single-RHS product measurement")
     ap.add_argument("--precond", default="block", choices=["block", "jacobi"],
                     help="preconditioner of the timed step (the other one is timed once beside it)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -470,6 +520,10 @@ def main():
         out["mcmc"] = bench_mcmc(G, x, y, params, args.precision, opts)
     if not args.no_variants:
         out["variants"] = bench_variants(G, x, y, params, args.precision, opts)
+    if not args.no_large and args.config != "c4":
+        del x, y
+        torch.cuda.empty_cache()
+        out["large"] = bench_large(G)
     if not args.no_cpu:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(prob, nnz, jac_iters[0], jac_iters[1], S)
