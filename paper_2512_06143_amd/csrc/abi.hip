@@ -9,6 +9,19 @@ namespace {
 
 using namespace gp2s::rt;
 
+// Readies a new matrix handle's CSR for the streaming single-RHS product: zeroes the
+// kQuadPad entries past nnz of col and val (column 0, value 0), which it may read, and
+// builds its row blocks (m->rowblk must hold rowblocks_count(nnz) + 1 entries).
+hipError_t prepare_streaming(gp2s_matrix m, hipStream_t st) {
+  const size_t vb = m->prec == GP2S_MIXED ? sizeof(float) : sizeof(double);
+  hipError_t e = hipMemsetAsync(m->col + m->nnz, 0, kQuadPad * sizeof(int32_t), st);
+  if (e == hipSuccess) e = hipMemsetAsync(static_cast<char*>(m->val) + m->nnz * vb, 0, kQuadPad * vb, st);
+  if (e == hipSuccess) e = launch_rowblocks(m->row_ptr, m->n, m->nnz, m->rowblk, st);
+  return e;
+}
+
+RowBlocks row_blocks(gp2s_matrix m) { return RowBlocks{m->rowblk, m->nrowblk}; }
+
 // ---- conjugate gradients ------------------------------------------------------------------
 struct CgRun {
   CgState cs{};
@@ -216,11 +229,11 @@ gp2s_status tune_block_product(gp2s_ctx ctx, gp2s_matrix m, int S, const void* P
   hipError_t err = hipSuccess;
   for (int v : cand) {
     err = launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, m->n, S, mean_row, v, tile_set(m), P, Q, f32vec, cs,
-                           st);
+                           st, row_blocks(m));
     if (err == hipSuccess) err = hipEventRecord(e0, st);
     for (int r = 0; r < 3 && err == hipSuccess; ++r)
       err = launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, m->n, S, mean_row, v, tile_set(m), P, Q, f32vec, cs,
-                           st);
+                           st, row_blocks(m));
     if (err == hipSuccess) err = hipEventRecord(e1, st);
     if (err == hipSuccess) err = hipEventSynchronize(e1);
     float ms = 0.f;
@@ -356,7 +369,7 @@ gp2s_status cg_step(Cg& c) {
     HIPCHK(launch_ff_gtp(n, S, m->ffU, m->ffG, c.P, c.f32vec, c.lrPart, c.lrTicket, c.lrC, c.st));
   TIMED_ON(S == 1 ? GP2S_T_CG_MATVEC1 : GP2S_T_CG_MATVEC_BLOCK, c.st,
            launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, n, S, (double)m->nnz / (double)n, c.variant,
-                            tile_set(m), c.P, c.Q, c.f32vec, c.cs, c.st));
+                            tile_set(m), c.P, c.Q, c.f32vec, c.cs, c.st, row_blocks(m)));
   if (m->ffG) HIPCHK(launch_ff_add(n, S, m->ffU, m->ffG, c.lrC, S, 1, static_cast<double*>(c.Q), c.st));
   if (c.precond == GP2S_PRECOND_BLOCK) {
     TIMED_ON(S == 1 ? GP2S_T_CG_UPDATE1 : GP2S_T_CG_UPDATE_BLOCK, c.st,
@@ -567,7 +580,8 @@ gp2s_status solve_internal(gp2s_ctx ctx, gp2s_matrix m, const double* y, double*
     if (st) return st;
     total += cy.total_iters;
     for (;;) {
-      TIMED(GP2S_T_SPMV, launch_spmv(m->prec, m->row_ptr, m->col, m->val, n, (double)m->nnz / n, a, kx, ctx->stream));
+      TIMED(GP2S_T_SPMV, launch_spmv(m->prec, m->row_ptr, m->col, m->val, n, (double)m->nnz / n, a, kx, ctx->stream,
+                                     row_blocks(m)));
       st = ff_apply(ctx, m, 1, a, kx, sc);
       if (st) return st;
       HIPCHK(launch_axpy_sub(n, y, kx, r, ctx->stream));
@@ -1168,11 +1182,15 @@ gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_p
   st = readback(ctx, m->row_ptr + n, sizeof(int64_t), &nnz);
   if (st) return st;
   m->nnz = nnz;
-  m->col = own<int32_t>(m, nnz);
-  m->val = prec == GP2S_MIXED ? (void*)own<float>(m, nnz) : (void*)own<double>(m, nnz);
+  m->col = own<int32_t>(m, nnz + kQuadPad);
+  m->val = prec == GP2S_MIXED ? (void*)own<float>(m, nnz + kQuadPad) : (void*)own<double>(m, nnz + kQuadPad);
+  m->nrowblk = rowblocks_count(nnz);
+  m->rowblk = own<int32_t>(m, m->nrowblk + 1);
   OOMCHK(m->col);
   OOMCHK(m->val);
+  OOMCHK(m->rowblk);
   TIMED(GP2S_T_ASM_FILL, launch_assemble_fill(aa, prec, m->row_ptr, m->col, m->val, m->diag, sm));
+  HIPCHK(prepare_streaming(m, sm));
   if (m->ffU > 0) {
     m->ffgrp_d = own<int32_t>(m, m->ffgrp_h.size());
     m->ffG = own<double>(m, (size_t)n * m->ffU);
@@ -1252,13 +1270,16 @@ gp2s_status gp2s_matrix_import(gp2s_ctx ctx, int64_t n, int64_t nnz, const int64
   m->assembled = false;
   const size_t vb = prec == GP2S_MIXED ? sizeof(float) : sizeof(double);
   m->row_ptr = own<int64_t>(m, n + 1);
-  m->col = own<int32_t>(m, nnz);
-  m->val = own<uint8_t>(m, nnz * vb);
+  m->col = own<int32_t>(m, nnz + kQuadPad);
+  m->val = own<uint8_t>(m, (nnz + kQuadPad) * vb);
+  m->nrowblk = rowblocks_count(nnz);
+  m->rowblk = own<int32_t>(m, m->nrowblk + 1);
   m->diag = own<double>(m, n);
   m->dinv = own<double>(m, n);
   OOMCHK(m->row_ptr);
   OOMCHK(m->col);
   OOMCHK(m->val);
+  OOMCHK(m->rowblk);
   OOMCHK(m->diag);
   OOMCHK(m->dinv);
   hipStream_t sm = ctx->stream;
@@ -1275,6 +1296,7 @@ gp2s_status gp2s_matrix_import(gp2s_ctx ctx, int64_t n, int64_t nnz, const int64
   st = readback(ctx, bad, sizeof(hb), hb);
   if (st) return st;
   if (hb[1]) return fail(ctx, GP2S_E_INVALID, "invalid CSR: a row lacks its diagonal, a column index is out of range or not ascending, or row_ptr is inconsistent");
+  HIPCHK(prepare_streaming(m, sm));  // only once the CSR is known to be valid
   m->diag_ok = hb[0] == 0;
   guard.keep = true;
   *out = m;
@@ -1398,7 +1420,8 @@ gp2s_status gp2s_spmv(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X
   }
   HIPCHK(launch_gather_rows(n, nrhs, m->perm, X, Xi, ctx->stream));
   if (nrhs == 1)
-    TIMED(GP2S_T_SPMV, launch_spmv(m->prec, m->row_ptr, m->col, m->val, n, (double)m->nnz / n, Xi, Yi, ctx->stream));
+    TIMED(GP2S_T_SPMV,
+          launch_spmv(m->prec, m->row_ptr, m->col, m->val, n, (double)m->nnz / n, Xi, Yi, ctx->stream, row_blocks(m)));
   else
     TIMED(GP2S_T_SPMM, launch_spmm(m->prec, m->row_ptr, m->col, m->val, n, nrhs, (double)m->nnz / n,
                                            m->spmm_variant[nrhs] >= 0 ? m->spmm_variant[nrhs] : -1, tile_set(m),

@@ -240,18 +240,34 @@ hipError_t launch_cross_var(int prec, const int64_t* rp, const int32_t* col, con
                             const double* Vs, const double* cs, const double* g64t, double* var, hipStream_t st);
 
 // spmv.hip
+// Entries allocated past nnz in a matrix handle's col and val (zeroed: column 0, value
+// 0), so that the streaming single-RHS product may read whole 16-byte quads.
+constexpr int64_t kQuadPad = 4;
+// Row blocks of the streaming single-RHS product: blk[b] = the first row whose first
+// entry is at or past b * 2048, b < n; blk[n] = the row count. {nullptr, 0}: the CSR has
+// no blocks (not a matrix handle's) and the lane-group product is used.
+struct RowBlocks {
+  const int32_t* blk;
+  int64_t n;
+};
+int64_t rowblocks_count(int64_t nnz);
+hipError_t launch_rowblocks(const int64_t* rp, int64_t n, int64_t nnz, int32_t* rowblk, hipStream_t st);
+// rb: the CSR's row blocks (its col and val then hold kQuadPad valid entries past nnz)
 hipError_t launch_spmv(int prec, const int64_t* rp, const int32_t* col, const void* val,
-                       int64_t n, double mean_row, const double* x, double* y, hipStream_t st);
+                       int64_t n, double mean_row, const double* x, double* y, hipStream_t st,
+                       const RowBlocks& rb = RowBlocks{nullptr, 0});
 hipError_t launch_spmm(int prec, const int64_t* rp, const int32_t* col, const void* val,
                        int64_t n, int S, double mean_row, int variant, const TileSet& tiles, const double* X,
                        double* Y, hipStream_t st);
-// CG product step: Q = K P plus p^T q per column, then alpha = rz / p^T q.
+// CG product step: Q = K P plus p^T q per column, then alpha = rz / p^T q (rb as for
+// launch_spmv, used when S == 1).
 // P is float32 when f32vec (block solves of the mixed path), else float64; Q is float64.
 // `variant` selects the block product for S > 1: 0 one lane per column, G > 0 the
 // entry-parallel product with G lanes per row, -1 a choice from S and the mean row length.
 hipError_t launch_cg_matvec(int prec, const int64_t* rp, const int32_t* col, const void* val,
                             int64_t n, int S, double mean_row, int variant, const TileSet& tiles, const void* P,
-                            void* Q, bool f32vec, const CgState& cs, hipStream_t st);
+                            void* Q, bool f32vec, const CgState& cs, hipStream_t st,
+                            const RowBlocks& rb = RowBlocks{nullptr, 0});
 
 // pcg.hip
 hipError_t launch_cg_alpha(const CgState& cs, int nb, int S, hipStream_t st);

@@ -86,8 +86,10 @@ struct gp2s_matrix_s {
   int32_t* binid = nullptr;
   int64_t* bin_start = nullptr;
   int64_t* row_ptr = nullptr;
-  int32_t* col = nullptr;
-  void* val = nullptr;
+  int32_t* col = nullptr;  // nnz + kQuadPad entries (the pad zeroed)
+  void* val = nullptr;     // nnz + kQuadPad entries (the pad zeroed)
+  int32_t* rowblk = nullptr;  // row blocks of the streaming single-RHS product [nrowblk + 1]
+  int64_t nrowblk = 0;
   double* diag = nullptr;
   double* dinv = nullptr;
   bool diag_ok = true;

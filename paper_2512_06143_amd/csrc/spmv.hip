@@ -20,38 +20,65 @@ __device__ inline double ld(const V* p, int64_t k) {
 }
 
 // ---- single right-hand side -----------------------------------------------------------
+// G lanes per row. The product is bound by how many loads are in flight: a row's
+// entries take three dependent trips to memory (row pointers, then columns and values,
+// then the gathered x), so a group issues all of a row's column and value loads at
+// once (kWave / G per lane: rows up to 64 entries in one pass) before any gather, and
+// loads the next row's pointers before it multiplies the current row. Every load is
+// unconditional, at an index clamped into the row (lanes past its end reread its last
+// entry and their products are dropped by a select): a predicated load would become a
+// branch, and the compiler then waits for each load inside its branch.
 template <int G, typename V, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_spmv(const int64_t* __restrict__ rp,
                                                  const int32_t* __restrict__ col,
                                                  const V* __restrict__ val, int64_t n,
                                                  const double* __restrict__ x,
                                                  double* __restrict__ y, CgState cs) {
+  constexpr int U = kWave / G;
   const int lane = threadIdx.x & (G - 1);
   const XcdRows rr = xcd_rows(n, threadIdx.x / G, kBlock / G);
   double dot = 0.0;
-  for (int64_t row = rr.first; row < rr.end; row += rr.step) {
-    const int64_t s = rp[row], e = rp[row + 1];
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int64_t k = s + lane;
-    for (; k + 3 * G < e; k += 4 * G) {
-      const int32_t c0 = col[k], c1 = col[k + G], c2 = col[k + 2 * G], c3 = col[k + 3 * G];
-      const double v0 = ld(val, k), v1 = ld(val, k + G), v2 = ld(val, k + 2 * G), v3 = ld(val, k + 3 * G);
-      const double x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
-      a0 += v0 * x0;
-      a1 += v1 * x1;
-      a2 += v2 * x2;
-      a3 += v3 * x3;
-    }
-    for (; k < e; k += G) a0 += ld(val, k) * x[col[k]];
-    double acc = (a0 + a1) + (a2 + a3);
+  if (rr.first >= rr.end) {
+    if (!DOT) return;
+  } else {
+    int64_t s = rp[rr.first], e = rp[rr.first + 1];
+    for (int64_t row = rr.first; row < rr.end; row += rr.step) {
+      // the next row's extent (this row's again past the range: a valid index)
+      const int64_t nrow = row + rr.step < rr.end ? row + rr.step : row;
+      const int64_t ns = rp[nrow], ne = rp[nrow + 1];
+      double acc = 0.0;
+      for (int64_t k0 = s + lane; k0 < e; k0 += (int64_t)U * G) {
+        int32_t c[U];
+        V v[U];
+        bool in[U];
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
-    if (lane == 0) {
-      y[row] = acc;
-      if (DOT) dot += acc * x[row];
+        for (int j = 0; j < U; ++j) {
+          const int64_t k = k0 + (int64_t)j * G;
+          in[j] = k < e;
+          const int64_t kk = in[j] ? k : e - 1;  // e - 1 >= k0 >= s: inside the row
+          c[j] = col[kk];
+          v[j] = val[kk];
+        }
+        double xv[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) xv[j] = x[c[j]];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+          const double t = (double)v[j] * xv[j];
+          acc += in[j] ? t : 0.0;
+        }
+      }
+#pragma unroll
+      for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+      if (lane == 0) {
+        y[row] = acc;
+        if (DOT) dot += acc * x[row];
+      }
+      s = ns;
+      e = ne;
     }
+    if (!DOT) return;
   }
-  if (!DOT) return;
   // p^T q partial of this workgroup; alpha is formed by launch_cg_alpha.
   __shared__ double sh[kBlock];
   sh[threadIdx.x] = dot;
@@ -63,6 +90,159 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const int64_t* __restrict__ rp,
   if (threadIdx.x == 0) cs.partial[blockIdx.x] = sh[0];
 }
 
+// nnz-balanced streaming product (single right-hand side; matrix handles only). The
+// rows are cut into blocks by where they start: block b holds the rows whose first
+// entry lies in [b C, (b + 1) C), C = kStreamChunk (the block boundaries rowblk[] come
+// from launch_rowblocks). Every row of a block but the last ends inside that span, so
+// one pass of C entries from the block's first entry covers all of them; only the last
+// row can run on, over further passes. A workgroup streams a pass's columns and values
+// as aligned 16-byte quads (4 entries per thread and load: far more bytes in flight
+// than lane groups per row issuing 4-byte loads), gathers x and writes the products to
+// LDS; the rows are then summed in a fixed order by L lanes each (L = 256 / rows, a
+// power of two up to 64, or one lane and several rows per thread), and a last row that
+// runs on is summed by the whole workgroup across passes. The work per workgroup is
+// balanced by entries whatever the row lengths (clustered clouds have rows from 1 to
+// thousands of entries). Quads past the block's last entry are clamped onto that
+// entry's quad (a cached reread, never summed); col and val must be 16-byte aligned
+// and hold kQuadPad valid entries past nnz.
+constexpr int kStreamChunk = 2048;  // entries per pass (16 KB of float64 products)
+
+__device__ inline void load_quad(const float* p, double (&v)[4]) {
+  const float4 q = *reinterpret_cast<const float4*>(p);
+  v[0] = q.x;
+  v[1] = q.y;
+  v[2] = q.z;
+  v[3] = q.w;
+}
+__device__ inline void load_quad(const double* p, double (&v)[4]) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  v[0] = a.x;
+  v[1] = a.y;
+  v[2] = b.x;
+  v[3] = b.y;
+}
+
+template <typename V, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_spmv_a(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                   const V* __restrict__ val, const int32_t* __restrict__ rowblk,
+                                                   int64_t nblk, const double* __restrict__ x,
+                                                   double* __restrict__ y, CgState cs) {
+  constexpr int NU = kStreamChunk / (4 * kBlock);
+  __shared__ double prod[kStreamChunk];
+  __shared__ double red[kBlock];
+  const int t = threadIdx.x;
+  double dot = 0.0;
+  for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const int64_t r0 = rowblk[b], r1 = rowblk[b + 1];
+    if (r0 == r1) continue;  // uniform: no row starts in this span
+    const int64_t E0 = rp[r0], E1 = rp[r1];
+    const int64_t A0 = E0 & ~(int64_t)3;
+    const int64_t qlast = (E1 - 1) & ~(int64_t)3;  // quad holding the block's last entry
+    const bool runs_on = E1 > A0 + kStreamChunk;    // the last row needs further passes
+    // rows summed after the first pass: all, or all but a last row that runs on
+    const int64_t nf = (r1 - r0) - (runs_on ? 1 : 0);
+    const int L = nf >= kBlock ? 1 : (nf <= kBlock / kWave ? kWave : kBlock / (int)nf);
+    const int Lp = 1 << (31 - __clz(L));  // power of two, divides 64
+    const int lane = t % Lp;
+    const int64_t grp = t / Lp, ngrp = kBlock / Lp;
+    double acc_last = 0.0;
+    for (int64_t c0 = A0; c0 < E1; c0 += kStreamChunk) {
+      int32_t c[NU][4];
+      double v[NU][4];
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int64_t q = min(c0 + 4 * t + (int64_t)(4 * kBlock) * u, qlast);
+        const int4 cq = *reinterpret_cast<const int4*>(col + q);
+        c[u][0] = cq.x;
+        c[u][1] = cq.y;
+        c[u][2] = cq.z;
+        c[u][3] = cq.w;
+        load_quad(val + q, v[u]);
+      }
+      double xv[NU][4];
+#pragma unroll
+      for (int u = 0; u < NU; ++u)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) xv[u][i] = x[c[u][i]];
+#pragma unroll
+      for (int u = 0; u < NU; ++u)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) prod[4 * t + 4 * kBlock * u + i] = v[u][i] * xv[u][i];
+      __syncthreads();
+      if (c0 == A0) {
+        // rows r0 .. r0 + nf - 1 lie inside this pass
+        for (int64_t g = grp; g < nf; g += ngrp) {
+          const int64_t row = r0 + g;
+          const int64_t s = rp[row], e = rp[row + 1];
+          double acc = 0.0;
+          for (int64_t k = s + lane; k < e; k += Lp) acc += prod[k - c0];
+          for (int o = Lp / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+          if (lane == 0) {
+            y[row] = acc;
+            if (DOT) dot += acc * x[row];
+          }
+        }
+      }
+      if (runs_on) {
+        const int64_t s = rp[r1 - 1];
+        const int64_t lo = max(s, c0), hi = min(E1, c0 + kStreamChunk);
+        for (int64_t k = lo + t; k < hi; k += kBlock) acc_last += prod[k - c0];
+      }
+      __syncthreads();
+    }
+    if (runs_on) {  // uniform per block
+      red[t] = acc_last;
+      __syncthreads();
+      for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if (t < o) red[t] += red[t + o];
+        __syncthreads();
+      }
+      if (t == 0) {
+        y[r1 - 1] = red[0];
+        if (DOT) dot += red[0] * x[r1 - 1];
+      }
+      __syncthreads();
+    }
+  }
+  if (!DOT) return;
+  red[t] = dot;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if (t < o) red[t] += red[t + o];
+    __syncthreads();
+  }
+  if (t == 0) cs.partial[blockIdx.x] = red[0];
+}
+
+// rowblk[b] = the first row whose first entry is at or past b C (b < nblk), rowblk[nblk] = n.
+__global__ void k_rowblocks(const int64_t* __restrict__ rp, int64_t n, int64_t nblk, int32_t* __restrict__ rowblk) {
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b <= nblk; b += (int64_t)gridDim.x * blockDim.x) {
+    if (b == nblk) {
+      rowblk[b] = (int32_t)n;
+      continue;
+    }
+    const int64_t target = b * kStreamChunk;
+    int64_t lo = 0, hi = n;  // first i in [0, n] with rp[i] >= target
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) / 2;
+      if (rp[mid] < target) lo = mid + 1;
+      else hi = mid;
+    }
+    rowblk[b] = (int32_t)lo;
+  }
+}
+
+int64_t rowblocks_count(int64_t nnz) { return (nnz + kStreamChunk - 1) / kStreamChunk; }
+
+hipError_t launch_rowblocks(const int64_t* rp, int64_t n, int64_t nnz, int32_t* rowblk, hipStream_t st) {
+  const int64_t nblk = rowblocks_count(nnz);
+  int64_t blocks = (nblk + 1 + kBlock - 1) / kBlock;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_rowblocks, dim3((unsigned)blocks), dim3(kBlock), 0, st, rp, n, nblk, rowblk);
+  return hipGetLastError();
+}
+
 // Lanes per row: about half the mean row length, a power of two in [4, 64].
 static int pick_group(double mean_row) {
   int g = 4;
@@ -72,12 +252,20 @@ static int pick_group(double mean_row) {
 
 template <typename V, bool DOT>
 static hipError_t spmv_dispatch(const int64_t* rp, const int32_t* col, const V* val, int64_t n,
-                                double mean_row, const double* x, double* y, const CgState& cs,
+                                double mean_row, const RowBlocks& rb, const double* x, double* y, const CgState& cs,
                                 hipStream_t st, int* nblocks = nullptr) {
+  const int64_t cap = DOT ? kReduceBlocks : (1 << 20);
+  if (rb.blk && rb.n > 0 && ((reinterpret_cast<uintptr_t>(col) | reinterpret_cast<uintptr_t>(val)) & 15) == 0) {
+    int64_t blocks = rb.n < cap ? rb.n : cap;
+    blocks = round_up8(blocks < 1 ? 1 : blocks);
+    if (nblocks) *nblocks = (int)blocks;
+    hipLaunchKernelGGL((k_spmv_a<V, DOT>), dim3((unsigned)blocks), dim3(kBlock), 0, st, rp, col, val, rb.blk, rb.n,
+                       x, y, cs);
+    return hipGetLastError();
+  }
   const int G = pick_group(mean_row);
   int64_t groups_per_block = kBlock / G;
   int64_t blocks = (n + groups_per_block - 1) / groups_per_block;
-  const int64_t cap = DOT ? kReduceBlocks : (1 << 20);
   if (blocks > cap) blocks = cap;
   blocks = round_up8(blocks < 1 ? 1 : blocks);
   if (nblocks) *nblocks = (int)blocks;
@@ -93,11 +281,11 @@ static hipError_t spmv_dispatch(const int64_t* rp, const int32_t* col, const V* 
 }
 
 hipError_t launch_spmv(int prec, const int64_t* rp, const int32_t* col, const void* val, int64_t n,
-                       double mean_row, const double* x, double* y, hipStream_t st) {
+                       double mean_row, const double* x, double* y, hipStream_t st, const RowBlocks& rb) {
   CgState cs{};
   if (prec == GP2S_MIXED)
-    return spmv_dispatch<float, false>(rp, col, static_cast<const float*>(val), n, mean_row, x, y, cs, st);
-  return spmv_dispatch<double, false>(rp, col, static_cast<const double*>(val), n, mean_row, x, y, cs, st);
+    return spmv_dispatch<float, false>(rp, col, static_cast<const float*>(val), n, mean_row, rb, x, y, cs, st);
+  return spmv_dispatch<double, false>(rp, col, static_cast<const double*>(val), n, mean_row, rb, x, y, cs, st);
 }
 
 // ---- blocks of S <= 64 right-hand sides --------------------------------------------------
@@ -580,16 +768,16 @@ hipError_t launch_spmm(int prec, const int64_t* rp, const int32_t* col, const vo
 
 hipError_t launch_cg_matvec(int prec, const int64_t* rp, const int32_t* col, const void* val,
                             int64_t n, int S, double mean_row, int variant, const TileSet& tiles, const void* P,
-                            void* Q, bool f32vec, const CgState& cs, hipStream_t st) {
+                            void* Q, bool f32vec, const CgState& cs, hipStream_t st, const RowBlocks& rb) {
   int nb = 0;
   hipError_t e;
   if (S == 1) {
     // single right-hand side: always float64 vectors
     if (prec == GP2S_MIXED)
-      e = spmv_dispatch<float, true>(rp, col, static_cast<const float*>(val), n, mean_row,
+      e = spmv_dispatch<float, true>(rp, col, static_cast<const float*>(val), n, mean_row, rb,
                                      static_cast<const double*>(P), static_cast<double*>(Q), cs, st, &nb);
     else
-      e = spmv_dispatch<double, true>(rp, col, static_cast<const double*>(val), n, mean_row,
+      e = spmv_dispatch<double, true>(rp, col, static_cast<const double*>(val), n, mean_row, rb,
                                       static_cast<const double*>(P), static_cast<double*>(Q), cs, st, &nb);
   } else if (prec == GP2S_MIXED) {
     if (f32vec)
