@@ -187,3 +187,55 @@ def test_autograd_function(gpu):
         A = 0.5 * (A + A.T)
         sd = 0.5 * math.sqrt(oracle.hutchinson_variance(A, S))
         assert abs(grad[k] - ge[k]) <= 4 * sd + 1e-7 * abs(ge[k]), (k, grad[k], ge[k], sd)
+
+
+def _irregular_spd(seed, n, hubs, hub_len):
+    """Symmetric, strictly diagonally dominant CSR with heavy-tailed row lengths: most
+    rows hold a handful of entries, `hubs` rows about `hub_len` (rows far longer than
+    one 2048-entry pass of the streaming product), and blocks of one-entry rows."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    lens = np.minimum((rng.pareto(1.3, n) * 6).astype(int), 400)
+    lens[rng.choice(n, n // 5, replace=False)] = 0  # diagonal-only rows
+    rows = np.repeat(np.arange(n), lens)
+    cols = rng.integers(0, n, rows.size)
+    for h in rng.choice(n, hubs, replace=False):
+        c = rng.choice(n, hub_len, replace=False)
+        rows = np.concatenate([rows, np.full(hub_len, h)])
+        cols = np.concatenate([cols, c])
+    A = sp.csr_matrix((rng.uniform(-1, 1, rows.size), (rows, cols)), shape=(n, n))
+    A = (A + A.T).tocsr()
+    A.setdiag(0.0)
+    A.eliminate_zeros()
+    d = np.asarray(abs(A).sum(axis=1)).ravel() + 1.0
+    A = (A + sp.diags(d)).tocsr()
+    A.sort_indices()
+    return A
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape", ["heavy_tail", "diagonal"])
+def test_product_and_solve_irregular_rows(gpu, precision, shape):
+    """The single-RHS product balances work by entries (blocks of rows by entry span, a
+    last row running over several passes): rows of 1 to several thousand entries, and
+    more rows per block than threads, against the float64 product of the stored values
+    (float32-rounded in the mixed path), and a CG solve through the same product."""
+    G = _G()
+    import scipy.sparse as sp
+    if shape == "heavy_tail":
+        A = _irregular_spd(11, 9000, hubs=4, hub_len=6000)
+        assert np.diff(A.indptr).max() > 2 * 2048
+    else:
+        A = sp.identity(5003, format="csr") * 2.0
+    At = A.astype(np.float32).astype(np.float64) if precision == "mixed" else A
+    m = G.gp2s_matrix_import(A.indptr, A.indices, A.data, precision)
+    x = np.random.default_rng(2).standard_normal(A.shape[0])
+    y = G.gp2s_spmv(m, x).cpu().numpy()
+    ref = At @ x
+    scale = abs(At) @ np.abs(x)
+    print(f"[{shape}/{precision}] n={A.shape[0]} nnz={A.nnz} max row {np.diff(A.indptr).max()} "
+          f"product err {np.max(np.abs(y - ref) / scale):.2e}", flush=True)
+    assert np.all(np.abs(y - ref) <= 1e-13 * scale)
+    a, rep = G.gp2s_solve(m, x, G.default_opts(tol=1e-12, max_iter=20000))
+    assert oracle.residual_rel(At, a.cpu().numpy(), x) <= 1e-11
+    m.free()
