@@ -356,6 +356,10 @@ gp2s_status cg_begin(Cg& c, const double* B, double tol, bool keep_hist, Scratch
     gp2s_status gs = ensure_groups(ctx, m);
     if (gs) return gs;
   }
+  if (c.variant == 2) {  // a pinned tile variant: the tiles are otherwise built by the tuner
+    gp2s_status ts = ensure_tiles(ctx, m);
+    if (ts) return ts;
+  }
   return GP2S_OK;
 }
 
