@@ -320,7 +320,7 @@ def bench_batch(args):
     ys = [torch.as_tensor(p.y).cuda() for p in probs]
     params = [G.HostParams(p.dim, p.radius, p.bump_width, p.noise_var, p.centers, p.weights) for p in probs]
     opts = G.default_opts(n_probes=S, max_iter=args.max_iter, tol=args.tol, probe_tol=args.probe_tol, check_every=32,
-                          precond="jacobi")  # the batched path uses the diagonal preconditioner
+                          precond=args.precond)
     ctx = G.default_context()
     b = G.Batch(xs, params, args.precision, opts, ctx)
     info = b.info()
@@ -347,6 +347,7 @@ def bench_batch(args):
         "config": {"workload": (f"c5: {M} instances, N {min(p.n for p in probs)}-{max(p.n for p in probs)} "
                                 f"(total {info['n_total']}), d in {{2,3}}, {S} probes each"),
                    "n_total": info["n_total"], "nnz": info["nnz"], "precision": args.precision,
+                   "precond": args.precond,
                    "autotuned": {k: info[k] for k in ("bin_refinement", "spmv_lanes", "spmm_lanes")},
                    "parallelism": "single GPU"},
         "max_iters_y": max(r["iters"] for r in reps), "max_iters_probe": max(r["probe_iters"] for r in reps),
@@ -377,6 +378,8 @@ def main():
                     help="skip the 10 M-point assembly and single-RHS product measurement")
     ap.add_argument("--only-large", action="store_true",
                     help="run only the 10 M-point assembly and single-RHS product measurement")
+    ap.add_argument("--no-jacobi", action="store_true",
+                    help="skip the same step with the diagonal preconditioner (comparison and CPU projection)")
     ap.add_argument("--precond", default="block", choices=["block", "jacobi"],
                     help="preconditioner of the timed step (the other one is timed once beside it)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -493,7 +496,7 @@ def main():
     # the same step with the diagonal preconditioner (the comparison of preconditioners, and
     # the iteration counts of the oracle's own Jacobi PCG for the CPU projection)
     jac_iters = (rep.iters, rep.probe_iters)
-    if args.precond != "jacobi":
+    if args.precond != "jacobi" and not args.no_jacobi:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rep_j, _, _, _ = run_step(G, x, y, params, args.precision, G.default_opts(

@@ -139,7 +139,9 @@ typedef struct {
                              the first solve that needs it and kept with the handle
                              (gp2s_matrix_refill drops it); a block that is not
                              positive definite fails with GP2S_E_NOT_SPD. The batched
-                             path (gp2s_batch_*) always uses the diagonal.          */
+                             path (gp2s_batch_*) takes its blocks from each instance's
+                             own bin order (its 64-row workgroup blocks) and factors
+                             them on every run.                                     */
 } gp2s_solve_opts;
 #define GP2S_PRECOND_JACOBI 0
 #define GP2S_PRECOND_BLOCK 1
@@ -328,7 +330,8 @@ gp2s_status gp2s_predict(gp2s_ctx ctx, gp2s_matrix m, int64_t n_test, const doub
 /* ---- batched instances -------------------------------------------------------------
  * Many independent instances (each its own points, dimension, targets and
  * hyperparameters; Sec. 2 per instance) evaluated together: one block-diagonal system
- * assembled in shared launches, solved by batched Jacobi-CG whose iterations run as
+ * assembled in shared launches, solved by batched preconditioned CG (diagonal or
+ * block-Jacobi per opts.precond, blocks inside each instance) whose iterations run as
  * replays of one captured hipGraph chunk, with per-instance step lengths, convergence
  * and Lanczos coefficients. A plan fixes the points, dimensions, bump centres and
  * widths, the precision and the solver options; runs may change r, the bump weights

@@ -24,21 +24,23 @@ import numpy as np
 BLOCK = 64
 
 
-def grid(x, radius, ell_bound=1.0):
+def grid(x, radius, ell_bound=1.0, refine=1, min_cells=65536):
     """(origin, h, nb): the bin grid for points x (n, dim), support radius r (a scalar,
     or one radius per axis) and the bound of the length-scale field l(x) (1 for a
-    stationary kernel). Along axis k, h_k = r_k (1 + 1e-6), times the bound when it is
-    not 1; all h_k are widened by a common factor if needed so that the number of
-    cells stays within max(4 n, 65536); nb[k] = floor((hi_k - lo_k) / h_k) + 1."""
+    stationary kernel). Along axis k, h_k = r_k (1 + 1e-6) / refine, times the bound
+    when it is not 1; all h_k are widened by a common factor if needed so that the
+    number of cells stays within max(4 n, min_cells); nb[k] = floor((hi_k - lo_k) / h_k)
+    + 1. One matrix uses refine = 1 and min_cells = 65536; an instance of a batch uses
+    the batch's bin refinement (1 or 2) and min_cells = 4096."""
     x = np.asarray(x, dtype=np.float64)
     n, dim = x.shape
     r = np.asarray(radius, dtype=np.float64).reshape(-1)
     radii = [float(r[0])] * dim if r.size == 1 else [float(v) for v in r]
     lo, hi = x.min(axis=0), x.max(axis=0)
-    h = [rk * (1.0 + 1e-6) for rk in radii]
+    h = [rk * (1.0 + 1e-6) / refine for rk in radii]
     if ell_bound != 1.0:
         h = [hk * ell_bound for hk in h]
-    max_bins = max(4.0 * n, 65536.0)
+    max_bins = max(4.0 * n, float(min_cells))
     for _ in range(64):
         total = 1.0
         for k in range(dim):
@@ -51,19 +53,19 @@ def grid(x, radius, ell_bound=1.0):
     return lo, np.array(h), nb
 
 
-def bin_coords(x, radius, ell_bound=1.0):
+def bin_coords(x, radius, ell_bound=1.0, refine=1, min_cells=65536):
     """(n, dim) integer cell coordinates floor((x_k - lo_k) (1 / h_k)), clamped to the grid."""
     x = np.asarray(x, dtype=np.float64)
-    lo, h, nb = grid(x, radius, ell_bound)
+    lo, h, nb = grid(x, radius, ell_bound, refine, min_cells)
     inv_h = 1.0 / h
     c = np.floor((x - lo[None, :]) * inv_h[None, :])
     return np.clip(c, 0, np.array(nb) - 1).astype(np.int64), nb
 
 
-def bin_order(x, radius, ell_bound=1.0):
+def bin_order(x, radius, ell_bound=1.0, refine=1, min_cells=65536):
     """perm (n,) int64: perm[p] is the user index of the point at position p when the
     points are sorted by cell number (first coordinate fastest), ties by user index."""
-    c, nb = bin_coords(x, radius, ell_bound)
+    c, nb = bin_coords(x, radius, ell_bound, refine, min_cells)
     key = np.zeros(c.shape[0], dtype=np.int64)
     for k in range(c.shape[1] - 1, -1, -1):
         key = key * nb[k] + c[:, k]

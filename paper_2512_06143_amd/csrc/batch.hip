@@ -7,7 +7,7 @@
 // coefficients are kept per (instance, column) with fixed-order reductions and no
 // atomics. The arithmetic of every step is the single-instance one (see
 // prologue.hip, assemble.hip, spmv.hip, pcg.hip, backward.hip).
-#include "gp2s_internal.h"
+#include "bj_apply.h"
 #include "pair.h"
 #include "spmm_rows.h"
 
@@ -815,8 +815,8 @@ __global__ __launch_bounds__(kBlock) void k_bcg_pupdate(BatchGeom g, int S, VEC*
   if (cs.done[c]) return;
   const double b = cs.beta[c];
   for (int64_t e = br.lo * S + threadIdx.x; e < br.hi * S; e += kBlock) {
-    const int64_t i = e / S;
-    P[e] = (VEC)(R[e] * dinv[i] + b * (double)P[e]);
+    const double z = dinv ? R[e] * dinv[e / S] : R[e];  // no dinv: R holds z = M^-1 r
+    P[e] = (VEC)(z + b * (double)P[e]);
   }
 }
 
@@ -828,6 +828,91 @@ hipError_t launch_bcg_pupdate(const BatchGeom& g, int S, void* P, const double* 
   else
     hipLaunchKernelGGL(k_bcg_pupdate<double>, dim3((unsigned)g.grid), dim3(kBlock), 0, st, g, S,
                        static_cast<double*>(P), R, dinv, cs, iter_dev);
+  return hipGetLastError();
+}
+
+// ---- block-Jacobi preconditioner ----------------------------------------------------------------
+static_assert(kBRows == kBJ, "the batch's row blocks are the preconditioner's blocks");
+// The batch's row blocks (64 rows of one instance, instance-aligned) are the
+// preconditioner's blocks, factored by launch_bj_factor with the batch's block list. One
+// CG update per workgroup and block: INIT r = b, x = 0; otherwise x += alpha p, r -=
+// alpha q with the instance's alpha per column; then z = M^-1 r on the matrix cores and
+// the per-column partials of r^T z (which 0) and r^T r (which 1) in the batch's layout.
+template <typename VEC, bool INIT>
+__global__ __launch_bounds__(kBJThreads) void k_bbj_update(BatchGeom g, int S, const double* __restrict__ B,
+                                                           double* __restrict__ X, double* __restrict__ R,
+                                                           const VEC* __restrict__ P, const double* __restrict__ Q,
+                                                           const double* __restrict__ Mfrag, double* __restrict__ Z,
+                                                           CgState cs) {
+  __shared__ double Rs[kBJ * kBJ];  // residual block [row][column], column stride 64
+  __shared__ double red[kBJThreads / kWave][kBJ];
+  const BRows br = brows(g);
+  if (!INIT && !inst_open(cs, br.inst, S)) return;
+  const int t = threadIdx.x;
+  const int nth = (kBJThreads / S) * S;
+  const int s_me = t % S;
+  const double a = (INIT || t >= nth) ? 0.0 : cs.alpha[br.inst * S + s_me];
+  const int64_t r0 = br.lo;
+  const int m = (int)(br.hi - br.lo);
+  double rr = 0.0;
+  double rz[kBJ / 16] = {0.0, 0.0, 0.0, 0.0};
+  if (t < nth) {
+    for (int e = t; e < kBJ * S; e += nth) {
+      const int i = e / S;
+      double r = 0.0;
+      if (i < m) {
+        const int64_t gi = r0 * S + e;
+        if (INIT) {
+          r = B[gi];
+          R[gi] = r;
+          X[gi] = 0.0;
+        } else {
+          r = R[gi];
+          if (a != 0.0) {
+            X[gi] += a * (double)P[gi];
+            r -= a * Q[gi];
+            R[gi] = r;
+          }
+        }
+        rr += r * r;
+      }
+      Rs[i * kBJ + s_me] = r;
+    }
+  }
+  __syncthreads();
+  bj_apply_block(Rs, Mfrag + br.blk * (int64_t)(kBJ * kBJ), m, S, r0, Z, rz);
+  __syncthreads();
+  const double rzt = bj_rz_total(rz, red, S);
+  if (t < S) cs.partial[(int64_t)t * g.nblk + br.blk] = rzt;
+  Rs[t] = rr;  // thread t holds column t % S (threads >= nth hold zero)
+  __syncthreads();
+  if (t < S) {
+    double v = 0.0;
+    for (int k = t; k < kBJThreads; k += S) v += Rs[k];
+    cs.partial[((int64_t)S + t) * g.nblk + br.blk] = v;
+  }
+}
+
+hipError_t launch_bbj_init(const BatchGeom& g, int S, const double* B, double* X, double* R, void* P, bool f32vec,
+                           const double* Mfrag, double* Z, const CgState& cs, double tol, hipStream_t st) {
+  hipLaunchKernelGGL((k_bbj_update<double, true>), dim3((unsigned)g.nblk), dim3(kBJThreads), 0, st, g, S, B, X, R,
+                     nullptr, nullptr, Mfrag, Z, cs);
+  hipLaunchKernelGGL(k_bcg_init_fin, dim3((unsigned)(g.M * S)), dim3(kBlock), 0, st, g, cs, S, tol);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_copy_dir(g.n, S, Z, P, f32vec, st);
+}
+
+hipError_t launch_bbj_update(const BatchGeom& g, int S, double* X, double* R, const void* P, const void* Q,
+                             bool f32vec, const double* Mfrag, double* Z, const CgState& cs, const int32_t* iter_dev,
+                             hipStream_t st) {
+  if (f32vec)
+    hipLaunchKernelGGL((k_bbj_update<float, false>), dim3((unsigned)g.grid), dim3(kBJThreads), 0, st, g, S, nullptr,
+                       X, R, static_cast<const float*>(P), static_cast<const double*>(Q), Mfrag, Z, cs);
+  else
+    hipLaunchKernelGGL((k_bbj_update<double, false>), dim3((unsigned)g.grid), dim3(kBJThreads), 0, st, g, S, nullptr,
+                       X, R, static_cast<const double*>(P), static_cast<const double*>(Q), Mfrag, Z, cs);
+  hipLaunchKernelGGL(k_bcg_beta, dim3((unsigned)(g.M * S)), dim3(kBlock), 0, st, g, cs, S, iter_dev);
   return hipGetLastError();
 }
 
@@ -893,7 +978,7 @@ __global__ __launch_bounds__(kBlock) void k_bbackward_rows(BBackward b, double* 
     const uint64_t mi = b.mask[row];
     const double dsi = sqrt(b.dinv[row]);
     const double qi = active ? b.Q[row * S + lane] : 0.0;
-    const double wi = active ? (((mi >> lane) & 1ull) ? -dsi : dsi) : 0.0;
+    const double wi = active ? (b.W ? b.W[row * S + lane] : (((mi >> lane) & 1ull) ? -dsi : dsi)) : 0.0;
     double accR = 0.0, accT = 0.0, aR = 0.0, aT = 0.0;
     const int64_t s0 = b.rp[row], e0 = b.rp[row + 1];
     for (int64_t k0 = s0; k0 < e0; k0 += kWave) {
@@ -939,7 +1024,7 @@ __global__ __launch_bounds__(kBlock) void k_bbackward_rows(BBackward b, double* 
         const uint64_t mm = bbu64(mj, l);
         if (active) {
           const double qj = b.Q[(int64_t)jj * S + lane];
-          const double wj = ((mm >> lane) & 1ull) ? -ds : ds;
+          const double wj = b.W ? b.W[(int64_t)jj * S + lane] : (((mm >> lane) & 1ull) ? -ds : ds);
           const double c = qi * wj + qj * wi;
           accR += gw * c;
           accT += gwp * c;

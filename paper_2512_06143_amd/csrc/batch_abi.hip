@@ -45,6 +45,13 @@ struct gp2s_batch_s {
   double* diag = nullptr;
   double* dinv = nullptr;
   int64_t cap = 0, nnz = 0;
+  // block-Jacobi preconditioner (opts.precond == GP2S_PRECOND_BLOCK): the batch's row
+  // blocks (64 rows of one instance) factored once per run
+  double* bj_L = nullptr;
+  double* bj_M = nullptr;
+  double* bj_piv = nullptr;
+  int64_t* bj_r0 = nullptr;
+  int32_t* bj_m = nullptr;
   // tuned launch shapes
   int m_ref = 1, spmv_lanes = 16, spmm_lanes = 64;
   double tune_ms[8] = {};
@@ -239,6 +246,8 @@ struct BCg {
   bool f32vec = false;
   int SM = 0, max_iter = 0, chunk = 1;
   double* R = nullptr;
+  double* Z = nullptr;  // M^-1 r (block preconditioner)
+  bool bj = false;
   void* P = nullptr;
   void* Q = nullptr;
   int32_t* si = nullptr;
@@ -274,8 +283,15 @@ gp2s_status bcg_capture(BCg& c) {
   for (int k = 0; k < c.chunk && ce == hipSuccess; ++k) {
     ce = launch_bcg_matvec(b->prec, c.gc, b->row_ptr, b->col, b->val, c.S, c.S == 1 ? b->spmv_lanes : b->spmm_lanes,
                            c.P, c.Q, c.f32vec, c.cs, c.st);
-    if (ce == hipSuccess) ce = launch_bcg_update(c.gc, c.S, c.X, c.R, c.P, c.Q, c.f32vec, b->dinv, c.cs, c.iter_dev, c.st);
-    if (ce == hipSuccess) ce = launch_bcg_pupdate(c.gc, c.S, c.P, c.R, b->dinv, c.f32vec, c.cs, c.iter_dev, c.st);
+    if (c.bj) {
+      if (ce == hipSuccess)
+        ce = launch_bbj_update(c.gc, c.S, c.X, c.R, c.P, c.Q, c.f32vec, b->bj_M, c.Z, c.cs, c.iter_dev, c.st);
+      if (ce == hipSuccess) ce = launch_bcg_pupdate(c.gc, c.S, c.P, c.Z, nullptr, c.f32vec, c.cs, c.iter_dev, c.st);
+    } else {
+      if (ce == hipSuccess)
+        ce = launch_bcg_update(c.gc, c.S, c.X, c.R, c.P, c.Q, c.f32vec, b->dinv, c.cs, c.iter_dev, c.st);
+      if (ce == hipSuccess) ce = launch_bcg_pupdate(c.gc, c.S, c.P, c.R, b->dinv, c.f32vec, c.cs, c.iter_dev, c.st);
+    }
   }
   hipError_t ee = hipStreamEndCapture(c.st, &graph);
   if (ce != hipSuccess || ee != hipSuccess) {
@@ -304,6 +320,8 @@ gp2s_status bcg_begin(BCg& c, const double* B, const double* tol_dev, double tol
   const size_t vb = c.f32vec ? sizeof(float) : sizeof(double);
   c.max_iter = b->opts.max_iter;
   c.R = sc.get<double>((size_t)n * S);
+  c.bj = b->opts.precond == GP2S_PRECOND_BLOCK && b->bj_M;
+  c.Z = c.bj ? sc.get<double>((size_t)n * S) : nullptr;
   c.P = sc.get<uint8_t>((size_t)n * S * vb);
   c.Q = sc.get<double>((size_t)n * S);
   double* sd = sc.get<double>(6 * (size_t)SM + (size_t)b->nblk * S * 2);
@@ -336,7 +354,10 @@ gp2s_status bcg_begin(BCg& c, const double* B, const double* tol_dev, double tol
   if (s) return s;
   HIPCHK(hipMemsetAsync(c.si, 0, (2 * (size_t)SM + 8) * sizeof(int32_t), c.st));
   const BatchGeom g = geom(b);
-  HIPCHK(launch_bcg_init(g, S, B, b->dinv, c.X, c.R, c.P, c.f32vec, cs, tol, c.st));
+  if (c.bj)
+    HIPCHK(launch_bbj_init(g, S, B, c.X, c.R, c.P, c.f32vec, b->bj_M, c.Z, cs, tol, c.st));
+  else
+    HIPCHK(launch_bcg_init(g, S, B, b->dinv, c.X, c.R, c.P, c.f32vec, cs, tol, c.st));
   if (tol_dev) {
     // per-column squared tolerances (refinement restarts)
     HIPCHK(hipMemcpyAsync(cs.tol2, tol_dev, SM * sizeof(double), hipMemcpyDeviceToDevice, c.st));
@@ -504,6 +525,51 @@ gp2s_status time_matvec(gp2s_batch b, int S, int lanes, Scratch& sc, float* ms) 
   ctx->pool.push_back(e0);
   ctx->pool.push_back(e1);
   *ms = t / reps;
+  return GP2S_OK;
+}
+
+BjBlocks bj_blocks(const gp2s_batch b) { return BjBlocks{b->bj_r0, b->bj_m, b->nblk}; }
+
+// Factors the block-Jacobi preconditioner of the current values: the batch's row blocks
+// (64 rows of one instance; the last block of an instance may be shorter). Arrays are
+// allocated on first use and kept with the batch.
+gp2s_status factor_blocks(gp2s_batch b) {
+  gp2s_ctx ctx = b->ctx;
+  hipStream_t st = ctx->stream;
+  if (!b->bj_M) {
+    const size_t nb = (size_t)b->nblk;
+    b->bj_L = bown<double>(b, nb * kBJ * kBJ);
+    b->bj_M = bown<double>(b, nb * kBJ * kBJ);
+    b->bj_piv = bown<double>(b, (size_t)b->N);
+    b->bj_r0 = bown<int64_t>(b, nb);
+    b->bj_m = bown<int32_t>(b, nb);
+    if (!b->bj_L || !b->bj_M || !b->bj_piv || !b->bj_r0 || !b->bj_m) {
+      b->bj_M = nullptr;
+      return fail(ctx, GP2S_E_OOM, "block preconditioner allocation failed (%zu blocks)", nb);
+    }
+    std::vector<int64_t> r0(nb);
+    std::vector<int32_t> m(nb);
+    for (int i = 0; i < b->M; ++i) {
+      const BInst& I = b->inst_h[i];
+      for (int64_t k = 0; k < I.nblk; ++k) {
+        r0[I.blk0 + k] = I.row0 + k * kBRows;
+        m[I.blk0 + k] = (int32_t)std::min<int64_t>(kBRows, I.rows - k * kBRows);
+      }
+    }
+    HIPCHK(hipMemcpyAsync(b->bj_r0, r0.data(), nb * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(b->bj_m, m.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  Scratch sc(ctx);
+  int32_t* bad = sc.get<int32_t>(1);
+  if (sc.oom) return fail(ctx, GP2S_E_OOM, "allocation failed");
+  HIPCHK(hipMemsetAsync(bad, 0, sizeof(int32_t), st));
+  HIPCHK(launch_bj_factor(b->N, b->row_ptr, b->col, b->val, b->prec, nullptr, 0, b->bj_L, b->bj_M, b->bj_piv, bad, st,
+                          bj_blocks(b)));
+  int32_t hb = 0;
+  gp2s_status s = readback(ctx, bad, sizeof(hb), &hb);
+  if (s) return s;
+  if (hb) return fail(ctx, GP2S_E_NOT_SPD, "a diagonal block of K is not positive definite");
   return GP2S_OK;
 }
 
@@ -772,6 +838,10 @@ gp2s_status gp2s_batch_run(gp2s_batch b, const double* const* y, const gp2s_para
     st = assemble_fill(b, sc2);
     if (st) return st;
   }
+  if (b->opts.precond == GP2S_PRECOND_BLOCK) {
+    st = factor_blocks(b);
+    if (st) return st;
+  }
   const int64_t N = b->N;
   const BatchGeom g = geom(b);
   Scratch sc(ctx);
@@ -807,8 +877,15 @@ gp2s_status gp2s_batch_run(gp2s_batch b, const double* const* y, const gp2s_para
     if (!is_fin(bb[i])) return fail(ctx, GP2S_E_NONFINITE, "y[%d] contains NaN or infinity", i);
   // The probe block runs on its own stream beside the y solves (both start after the
   // work queued so far on the context's stream and are joined back into it).
+  const bool bj = b->opts.precond == GP2S_PRECOND_BLOCK;
+  // trace vectors of the gradient: L^-T z (block preconditioner; the probe solve's first z)
+  double* W = bj ? sc.get<double>((size_t)N * S) : nullptr;
+  if (sc.oom) return fail(ctx, GP2S_E_OOM, "batch run workspace allocation failed");
   HIPCHK(launch_bprobe_masks(g, b->perm, b->opts.seed, S, mask, sm));
-  HIPCHK(launch_probe_rhs(N, S, mask, b->diag, Bp, sm));
+  if (bj)
+    HIPCHK(launch_bj_rhs(N, S, mask, b->bj_L, Bp, sm, bj_blocks(b)));
+  else
+    HIPCHK(launch_probe_rhs(N, S, mask, b->diag, Bp, sm));
   BCg cy, pr;
   cy.b = pr.b = b;
   cy.S = 1;
@@ -823,6 +900,8 @@ gp2s_status gp2s_batch_run(gp2s_batch b, const double* const* y, const gp2s_para
   pr.slots = b->pin + 2 * ((size_t)M + 4);
   st = bcg_begin(pr, Bp, nullptr, b->opts.probe_tol, true, sc);
   if (st) return st;
+  // z_0 = M^-1 L z = L^-T z, before the first iteration overwrites it
+  if (bj) HIPCHK(hipMemcpyAsync(W, pr.Z, (size_t)N * S * sizeof(double), hipMemcpyDeviceToDevice, pr.st));
   st = bcg_begin(cy, yi, nullptr, b->opts.tol, false, sc);
   if (st) return st;
   st = bcg_drive(&cy, &pr);
@@ -865,7 +944,7 @@ gp2s_status gp2s_batch_run(gp2s_batch b, const double* const* y, const gp2s_para
   std::vector<double> qh(SM), sumlog(M), yta(M);
   st = bread(ctx, sm, quad, SM * sizeof(double), qh.data());
   if (st) return st;
-  HIPCHK(launch_bseg_reduce(g, 1, b->diag, nullptr, seg, sm));
+  HIPCHK(launch_bseg_reduce(g, 1, bj ? b->bj_piv : b->diag, nullptr, seg, sm));  // ln|M|
   st = bread(ctx, sm, seg, M * sizeof(double), sumlog.data());
   if (st) return st;
   HIPCHK(launch_bseg_reduce(g, 0, yi, ai, seg, sm));
@@ -914,6 +993,7 @@ gp2s_status gp2s_batch_run(gp2s_batch b, const double* const* y, const gp2s_para
     bw.Q = Qs;
     bw.mask = mask;
     bw.dinv = b->dinv;
+    bw.W = W;
     bw.g64 = b->g64;
     bw.S = S;
     HIPCHK(launch_bbackward_rows(bw, b->prec, Rr, Tr, Ur, sm));

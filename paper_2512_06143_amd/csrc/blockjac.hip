@@ -14,14 +14,21 @@
 //
 // A ragged last block (n not a multiple of 64) is padded with identity rows and
 // columns; padded rows are never read or written outside the workgroup.
-#include "gp2s_internal.h"
+#include "bj_apply.h"
 
 namespace gp2s {
 
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-constexpr int kBJThreads = 256;
 constexpr int kBJStride = kBJ + 1;  // LDS row stride of the factor kernel (doubles)
+
+// Block b: rows r0 .. r0 + m - 1; consecutive 64-row runs from row 0 unless a block list
+// is given (the batched path: runs of 64 inside each instance).
+__device__ inline int64_t bj_count(const BjBlocks& bl, int64_t n) { return bl.r0 ? bl.n : (n + kBJ - 1) / kBJ; }
+__device__ inline int64_t bj_row0(const BjBlocks& bl, int64_t blk) { return bl.r0 ? bl.r0[blk] : blk * kBJ; }
+__device__ inline int bj_rows(const BjBlocks& bl, int64_t n, int64_t blk) {
+  if (bl.r0) return bl.m[blk];
+  const int64_t r0 = blk * kBJ;
+  return (int)((n - r0) < kBJ ? (n - r0) : kBJ);
+}
 
 // Operand order of M^-1 (per block, 4096 doubles): wave w = i / 16 owns rows
 // 16w..16w+15; for k-step kk (columns 4kk..4kk+3) lane l holds M^-1[16w + l % 16][4kk + l / 16]
@@ -30,17 +37,17 @@ template <typename V>
 __global__ __launch_bounds__(kBJThreads) void k_bj_factor(int64_t n, const int64_t* __restrict__ rp,
                                                           const int32_t* __restrict__ col,
                                                           const V* __restrict__ val, const double* __restrict__ G,
-                                                          int U, double* __restrict__ Lout,
+                                                          int U, BjBlocks bl, double* __restrict__ Lout,
                                                           double* __restrict__ Mfrag, double* __restrict__ piv,
                                                           int32_t* __restrict__ bad) {
   __shared__ double A[kBJ * kBJStride];   // block of K, then its factor L (lower part)
   __shared__ double Li[kBJ * kBJStride];  // L^-1 (lower part)
   const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
-  const int64_t nblk = (n + kBJ - 1) / kBJ;
+  const int64_t nblk = bj_count(bl, n);
   bool failed = false;
   for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-    const int64_t r0 = blk * kBJ;
-    const int m = (int)((n - r0) < kBJ ? (n - r0) : kBJ);
+    const int64_t r0 = bj_row0(bl, blk);
+    const int m = bj_rows(bl, n, blk);
     for (int e = t; e < kBJ * kBJ; e += kBJThreads) {
       const int i = e / kBJ, j = e % kBJ;
       A[i * kBJStride + j] = (i == j && i >= m) ? 1.0 : 0.0;
@@ -144,11 +151,10 @@ __global__ __launch_bounds__(kBJThreads) void k_bj_update(int64_t n, int S, cons
                                                           CgState cs) {
   __shared__ double Rs[kBJ * kBJ];  // residual block [row][column], column stride 64
   __shared__ double red[kBJThreads / kWave][kBJ];
-  const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
+  const int t = threadIdx.x;
   const int nth = (kBJThreads / S) * S;
   const int s_me = t % S;
   const double a = (INIT || t >= nth) ? 0.0 : cs.alpha[s_me];
-  const int ntile = (S + 15) / 16;
   const int64_t nblk = (n + kBJ - 1) / kBJ;
   double rr = 0.0;
   double rz[kBJ / 16] = {0.0, 0.0, 0.0, 0.0};
@@ -179,54 +185,12 @@ __global__ __launch_bounds__(kBJThreads) void k_bj_update(int64_t n, int S, cons
       }
     }
     __syncthreads();
-    const double* F = Mfrag + blk * (int64_t)(kBJ * kBJ) + wave * 1024;
-    double af[16];
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) af[kk] = F[kk * 64 + lane];
-    // result layout of the f64 16x16x4 instruction: lane l, register v holds row
-    // l / 16 + 4 v, column l % 16 of the 16 x 16 tile
-    const int row_base = 16 * wave + (lane >> 4);
-#pragma unroll
-    for (int jt = 0; jt < kBJ / 16; ++jt) {
-      if (jt < ntile) {
-        const int c = 16 * jt + (lane & 15);
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-          const double bv = c < S ? Rs[(4 * kk + (lane >> 4)) * kBJ + c] : 0.0;
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af[kk], bv, acc, 0, 0, 0);
-        }
-        if (c < S) {
-          double part = 0.0;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = row_base + 4 * v;
-            if (row < m) {
-              Z[(r0 + row) * S + c] = acc[v];
-              part += Rs[row * kBJ + c] * acc[v];
-            }
-          }
-          rz[jt] += part;
-        }
-      }
-    }
+    bj_apply_block(Rs, Mfrag + blk * (int64_t)(kBJ * kBJ), m, S, r0, Z, rz);
     __syncthreads();
   }
   // r^T z: lanes sharing a column (lane % 16) across row groups, then across waves
-#pragma unroll
-  for (int jt = 0; jt < kBJ / 16; ++jt) {
-    double v = rz[jt];
-    v += __shfl_xor(v, 16, kWave);
-    v += __shfl_xor(v, 32, kWave);
-    if (lane < 16) red[wave][16 * jt + lane] = v;
-  }
-  __syncthreads();
-  if (t < S) {
-    double v = 0.0;
-    for (int w = 0; w < kBJThreads / kWave; ++w) v += red[w][t];
-    cs.partial[(int64_t)t * gridDim.x + blockIdx.x] = v;
-  }
-  __syncthreads();
+  const double rzt = bj_rz_total(rz, red, S);
+  if (t < S) cs.partial[(int64_t)t * gridDim.x + blockIdx.x] = rzt;
   // r^T r: thread t holds column t % S (threads >= nth hold zero)
   Rs[t] = rr;
   __syncthreads();
@@ -238,15 +202,15 @@ __global__ __launch_bounds__(kBJThreads) void k_bj_update(int64_t n, int S, cons
 }
 
 // Probe right-hand sides B = L z (z = +-1 from the sign masks), per block.
-__global__ __launch_bounds__(kBJThreads) void k_bj_rhs(int64_t n, int S, const uint64_t* __restrict__ mask,
+__global__ __launch_bounds__(kBJThreads) void k_bj_rhs(int64_t n, int S, BjBlocks bl, const uint64_t* __restrict__ mask,
                                                        const double* __restrict__ Lg, double* __restrict__ B) {
   __shared__ double Ls[kBJ * kBJ];
   __shared__ uint64_t ms[kBJ];
   const int t = threadIdx.x;
-  const int64_t nblk = (n + kBJ - 1) / kBJ;
+  const int64_t nblk = bj_count(bl, n);
   for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-    const int64_t r0 = blk * kBJ;
-    const int m = (int)((n - r0) < kBJ ? (n - r0) : kBJ);
+    const int64_t r0 = bj_row0(bl, blk);
+    const int m = bj_rows(bl, n, blk);
     const double* Lb = Lg + blk * (int64_t)(kBJ * kBJ);
     for (int e = t; e < kBJ * kBJ; e += kBJThreads) Ls[e] = Lb[e];
     if (t < kBJ) ms[t] = t < m ? mask[r0 + t] : 0ull;
@@ -270,23 +234,24 @@ __global__ void k_copy_dir(int64_t total, const double* __restrict__ Z, VEC* __r
     P[e] = (VEC)Z[e];
 }
 
-static unsigned bj_grid(int64_t n, int64_t cap) {
-  int64_t nblk = (n + kBJ - 1) / kBJ;
+static unsigned bj_grid_blocks(int64_t nblk, int64_t cap) {
   if (nblk > cap) nblk = cap;
   if (nblk < 1) nblk = 1;
   return (unsigned)nblk;
 }
+static unsigned bj_grid(int64_t n, int64_t cap) { return bj_grid_blocks((n + kBJ - 1) / kBJ, cap); }
+static int64_t bj_count_host(const BjBlocks& bl, int64_t n) { return bl.r0 ? bl.n : (n + kBJ - 1) / kBJ; }
 
 hipError_t launch_bj_factor(int64_t n, const int64_t* rp, const int32_t* col, const void* val, int prec,
                             const double* G, int U, double* L, double* Mfrag, double* piv, int32_t* bad,
-                            hipStream_t st) {
-  const unsigned g = bj_grid(n, 8192);
+                            hipStream_t st, const BjBlocks& bl) {
+  const unsigned g = bj_grid_blocks(bj_count_host(bl, n), 8192);
   if (prec == GP2S_MIXED)
     hipLaunchKernelGGL(k_bj_factor<float>, dim3(g), dim3(kBJThreads), 0, st, n, rp, col,
-                       static_cast<const float*>(val), G, U, L, Mfrag, piv, bad);
+                       static_cast<const float*>(val), G, U, bl, L, Mfrag, piv, bad);
   else
     hipLaunchKernelGGL(k_bj_factor<double>, dim3(g), dim3(kBJThreads), 0, st, n, rp, col,
-                       static_cast<const double*>(val), G, U, L, Mfrag, piv, bad);
+                       static_cast<const double*>(val), G, U, bl, L, Mfrag, piv, bad);
   return hipGetLastError();
 }
 
@@ -314,8 +279,10 @@ hipError_t launch_bj_update(int64_t n, int S, const double* B, double* X, double
   return hipGetLastError();
 }
 
-hipError_t launch_bj_rhs(int64_t n, int S, const uint64_t* mask, const double* L, double* B, hipStream_t st) {
-  hipLaunchKernelGGL(k_bj_rhs, dim3(bj_grid(n, 8192)), dim3(kBJThreads), 0, st, n, S, mask, L, B);
+hipError_t launch_bj_rhs(int64_t n, int S, const uint64_t* mask, const double* L, double* B, hipStream_t st,
+                         const BjBlocks& bl) {
+  hipLaunchKernelGGL(k_bj_rhs, dim3(bj_grid_blocks(bj_count_host(bl, n), 8192)), dim3(kBJThreads), 0, st, n, S, bl,
+                     mask, L, B);
   return hipGetLastError();
 }
 

@@ -310,13 +310,22 @@ hipError_t launch_cg_beta(const CgState& cs, int nb, int S, int32_t iter, hipStr
 // L_ii^2; bad != 0 when a block is not positive definite), the fused update
 // (B != nullptr: initialisation r = B, x = 0) with z = M^-1 r, the probe right-hand
 // sides L z, and the direction copy P = Z.
+// Explicit block list (the batched path: 64-row runs inside each instance): block b
+// covers rows r0[b] .. r0[b] + m[b] - 1. {nullptr, nullptr, 0}: consecutive 64-row runs
+// from row 0.
+struct BjBlocks {
+  const int64_t* r0;
+  const int32_t* m;
+  int64_t n;
+};
 hipError_t launch_bj_factor(int64_t n, const int64_t* rp, const int32_t* col, const void* val, int prec,
                             const double* G, int U, double* L, double* Mfrag, double* piv, int32_t* bad,
-                            hipStream_t st);
+                            hipStream_t st, const BjBlocks& bl = BjBlocks{nullptr, nullptr, 0});
 unsigned bj_update_blocks(int64_t n);
 hipError_t launch_bj_update(int64_t n, int S, const double* B, double* X, double* R, const void* P, const void* Q,
                             bool f32vec, const double* Mfrag, double* Z, const CgState& cs, hipStream_t st);
-hipError_t launch_bj_rhs(int64_t n, int S, const uint64_t* mask, const double* L, double* B, hipStream_t st);
+hipError_t launch_bj_rhs(int64_t n, int S, const uint64_t* mask, const double* L, double* B, hipStream_t st,
+                         const BjBlocks& bl = BjBlocks{nullptr, nullptr, 0});
 hipError_t launch_copy_dir(int64_t n, int S, const double* Z, void* P, bool f32vec, hipStream_t st);
 hipError_t launch_probe_rhs(int64_t n, int S, const uint64_t* mask, const double* diag, double* B,
                             hipStream_t st);
@@ -398,6 +407,14 @@ hipError_t launch_bcg_update(const BatchGeom& g, int S, double* X, double* R, co
                              hipStream_t st);
 hipError_t launch_bcg_pupdate(const BatchGeom& g, int S, void* P, const double* R, const double* dinv, bool f32vec,
                               const CgState& cs, int32_t* iter_dev, hipStream_t st);
+// Block-Jacobi batched CG (block list: the batch's row blocks): initialisation r = B,
+// x = 0, z = M^-1 r, p = z; and the per-iteration update x, r, z = M^-1 r with beta.
+// The direction update is launch_bcg_pupdate with R = Z and dinv = nullptr.
+hipError_t launch_bbj_init(const BatchGeom& g, int S, const double* B, double* X, double* R, void* P, bool f32vec,
+                           const double* Mfrag, double* Z, const CgState& cs, double tol, hipStream_t st);
+hipError_t launch_bbj_update(const BatchGeom& g, int S, double* X, double* R, const void* P, const void* Q,
+                             bool f32vec, const double* Mfrag, double* Z, const CgState& cs, const int32_t* iter_dev,
+                             hipStream_t st);
 // out[i] over instance i's rows: mode 0 = a.b, 1 = sum ln a
 hipError_t launch_bseg_reduce(const BatchGeom& g, int mode, const double* a, const double* b, double* out,
                               hipStream_t st);
@@ -412,6 +429,7 @@ struct BBackward {
   const uint64_t* mask;
   const double* dinv;
   const double* g64;  // [n_total] bump values (float64; the mixed path's dK is evaluated in float64)
+  const double* W;    // [n_total * S] trace vectors L^-T z (block preconditioner); null: from mask and dinv
   int S;
 };
 hipError_t launch_bbackward_rows(const BBackward& b, int prec, double* Rrow, double* Trow, double* Urow,

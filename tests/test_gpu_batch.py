@@ -88,3 +88,45 @@ def test_batch_new_hyperparameters_and_capacity(gpu):
         b.run([p.y for p in probs], params=bad)
     assert e.value.status == 1
     b.free()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_block_preconditioner_against_oracle(gpu, precision):
+    """The block preconditioner in the batch: each instance's blocks are 64-point runs of
+    its own bin order (the batch's grid: the tuned bin refinement, at most max(4 n, 4096)
+    cells), so the same-probe log-determinant and gradient equal the oracle's with those
+    blocks (1e-8 and 1e-4), the y residual meets the tolerance, and the LML matches the
+    Jacobi-preconditioned batch to the probe noise of both estimates."""
+    G = _G()
+    probs = _instances()
+    S = 16
+    opts = G.default_opts(n_probes=S, seed=5, tol=1e-10, probe_tol=1e-10, max_iter=30000, precond="block")
+    b = G.Batch([p.x for p in probs], [params_of(p) for p in probs], precision, opts)
+    info = b.info()
+    lml, grads, reps = b.run([p.y for p in probs])
+    bj = G.Batch([p.x for p in probs], [params_of(p) for p in probs], precision,
+                 G.default_opts(n_probes=S, seed=5, tol=1e-10, probe_tol=1e-10, max_iter=30000, precond="jacobi"))
+    lml_j, _, reps_j = bj.run([p.y for p in probs])
+    for i, p in enumerate(probs):
+        m = G.gp2s_assemble(p.x, params_of(p), precision)
+        Kd = exported_user_csr(m)[0].toarray()
+        m.free()
+        Z = oracle.rademacher_probes(5, S, p.n)
+        order = oracle.bin_order(p.x, p.radius, refine=info["bin_refinement"], min_cells=4096)
+        blocks = oracle.block_partition(order, oracle.BLOCK)
+        gam, _ = oracle.logdet_same_probe(Kd, Z, blocks)
+        gref, parts = oracle.grad_same_probe(p.x, p.y, Z, p.radius, p.bump_width, p.centers, p.weights,
+                                             p.noise_var, K=Kd, blocks=blocks)
+        sc = np.maximum(np.abs(gref), 1e-6 * (np.abs(parts["fit"]) + 0.5 * np.abs(parts["tau"])))
+        gerr = np.max(np.abs(grads[i] - gref) / sc)
+        print(f"[batch-block/{precision}] instance {i}: logdet rel {abs(reps[i]['logdet'] - gam) / abs(gam):.2e}, "
+              f"grad {gerr:.2e}, iters {reps[i]['iters']}/{reps[i]['probe_iters']} vs jacobi "
+              f"{reps_j[i]['iters']}/{reps_j[i]['probe_iters']}, stderr {reps[i]['logdet_stderr']:.3g} vs "
+              f"{reps_j[i]['logdet_stderr']:.3g}", flush=True)
+        assert abs(reps[i]["logdet"] - gam) <= 1e-8 * abs(gam)
+        assert gerr <= 1e-4
+        assert reps[i]["resid"] <= 1e-10
+        noise = 4 * np.hypot(reps[i]["logdet_stderr"], reps_j[i]["logdet_stderr"])
+        assert abs(lml[i] - lml_j[i]) <= 0.5 * noise + 1e-8 * abs(lml[i])
+    b.free()
+    bj.free()
