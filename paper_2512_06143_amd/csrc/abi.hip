@@ -47,6 +47,7 @@ struct Cg {
   hipStream_t st = nullptr;
   int slot0 = 0;  // first of this solve's two pinned poll slots
   int precond = GP2S_PRECOND_JACOBI;
+  bool probe = false;  // a probe solve: its preconditioner enters the estimators (float64 M^-1 always)
   // state
   CgState cs{};
   bool f32vec = false;
@@ -254,6 +255,10 @@ gp2s_status tune_block_product(gp2s_ctx ctx, gp2s_matrix m, int S, const void* P
 // Builds the block-Jacobi factor of the handle's current values if it is not there
 // (on the context's stream; synchronous, since a block that is not positive definite
 // is reported here).
+// The float32 copy of M^-1 serves single-column solves that are not probe solves (their
+// preconditioner only steers convergence); everything else applies the float64 one.
+const float* bj_m32(const Cg& c) { return c.S == 1 && !c.probe ? c.m->bj_M32 : nullptr; }
+
 gp2s_status ensure_bj(gp2s_ctx ctx, gp2s_matrix m) {
   if (m->bj_ready) return GP2S_OK;
   const int64_t n = m->n;
@@ -261,14 +266,16 @@ gp2s_status ensure_bj(gp2s_ctx ctx, gp2s_matrix m) {
   if (!m->bj_L) {
     m->bj_L = own<double>(m, nblk * kBJ * kBJ);
     m->bj_M = own<double>(m, nblk * kBJ * kBJ);
+    m->bj_M32 = own<float>(m, nblk * kBJ * kBJ);
     m->bj_piv = own<double>(m, (size_t)n);
-    if (!m->bj_L || !m->bj_M || !m->bj_piv) return fail(ctx, GP2S_E_OOM, "block preconditioner allocation failed");
+    if (!m->bj_L || !m->bj_M || !m->bj_M32 || !m->bj_piv)
+      return fail(ctx, GP2S_E_OOM, "block preconditioner allocation failed");
   }
   Scratch sc(ctx);
   int32_t* bad = sc.get<int32_t>(1);
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "block preconditioner workspace allocation failed");
   HIPCHK(hipMemsetAsync(bad, 0, sizeof(int32_t), ctx->stream));
-  HIPCHK(launch_bj_factor(n, m->row_ptr, m->col, m->val, m->prec, m->ffG, m->ffU, m->bj_L, m->bj_M, m->bj_piv, bad,
+  HIPCHK(launch_bj_factor(n, m->row_ptr, m->col, m->val, m->prec, m->ffG, m->ffU, m->bj_L, m->bj_M, m->bj_M32, m->bj_piv, bad,
                           ctx->stream));
   int32_t hb = 0;
   gp2s_status st = readback(ctx, bad, sizeof(int32_t), &hb);
@@ -333,7 +340,7 @@ gp2s_status cg_begin(Cg& c, const double* B, double tol, bool keep_hist, Scratch
   }
   if (c.precond == GP2S_PRECOND_BLOCK) {
     if (!m->bj_ready) return fail(ctx, GP2S_E_INVALID, "block preconditioner not built (%s)", c.label);
-    HIPCHK(launch_bj_update(n, S, B, c.X, c.R, nullptr, nullptr, c.f32vec, m->bj_M, c.Z, cs, c.st));
+    HIPCHK(launch_bj_update(n, S, B, c.X, c.R, nullptr, nullptr, c.f32vec, m->bj_M, c.Z, cs, c.st, bj_m32(c)));
     HIPCHK(launch_cg_init_fin(cs, (int)bj_update_blocks(n), S, tol, c.st));
     HIPCHK(launch_copy_dir(n, S, c.Z, c.P, c.f32vec, c.st));
   } else {
@@ -377,7 +384,7 @@ gp2s_status cg_step(Cg& c) {
   if (m->ffG) HIPCHK(launch_ff_add(n, S, m->ffU, m->ffG, c.lrC, S, 1, static_cast<double*>(c.Q), c.st));
   if (c.precond == GP2S_PRECOND_BLOCK) {
     TIMED_ON(S == 1 ? GP2S_T_CG_UPDATE1 : GP2S_T_CG_UPDATE_BLOCK, c.st,
-             launch_bj_update(n, S, nullptr, c.X, c.R, c.P, c.Q, c.f32vec, m->bj_M, c.Z, c.cs, c.st));
+             launch_bj_update(n, S, nullptr, c.X, c.R, c.P, c.Q, c.f32vec, m->bj_M, c.Z, c.cs, c.st, bj_m32(c)));
     HIPCHK(launch_cg_beta(c.cs, (int)bj_update_blocks(n), S, c.it, c.st));
     TIMED_ON(S == 1 ? GP2S_T_CG_PUPDATE1 : GP2S_T_CG_PUPDATE_BLOCK, c.st,
              launch_cg_pupdate(n, S, c.P, c.Z, nullptr, c.f32vec, c.cs, c.st));
@@ -646,6 +653,7 @@ gp2s_status probes_begin(gp2s_ctx ctx, gp2s_matrix m, const gp2s_solve_opts* o, 
   cp.S = S;
   cp.X = Qsol;
   cp.precond = o->precond;
+  cp.probe = true;
   cp.max_iter = o->max_iter;
   cp.check_every = o->check_every;
   cp.label = "probe block";

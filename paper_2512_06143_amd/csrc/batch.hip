@@ -838,11 +838,11 @@ static_assert(kBRows == kBJ, "the batch's row blocks are the preconditioner's bl
 // CG update per workgroup and block: INIT r = b, x = 0; otherwise x += alpha p, r -=
 // alpha q with the instance's alpha per column; then z = M^-1 r on the matrix cores and
 // the per-column partials of r^T z (which 0) and r^T r (which 1) in the batch's layout.
-template <typename VEC, bool INIT>
+template <typename VEC, bool INIT, typename MT>
 __global__ __launch_bounds__(kBJThreads) void k_bbj_update(BatchGeom g, int S, const double* __restrict__ B,
                                                            double* __restrict__ X, double* __restrict__ R,
                                                            const VEC* __restrict__ P, const double* __restrict__ Q,
-                                                           const double* __restrict__ Mfrag, double* __restrict__ Z,
+                                                           const MT* __restrict__ Mfrag, double* __restrict__ Z,
                                                            CgState cs) {
   __shared__ double Rs[kBJ * kBJ];  // residual block [row][column], column stride 64
   __shared__ double red[kBJThreads / kWave][kBJ];
@@ -894,9 +894,14 @@ __global__ __launch_bounds__(kBJThreads) void k_bbj_update(BatchGeom g, int S, c
 }
 
 hipError_t launch_bbj_init(const BatchGeom& g, int S, const double* B, double* X, double* R, void* P, bool f32vec,
-                           const double* Mfrag, double* Z, const CgState& cs, double tol, hipStream_t st) {
-  hipLaunchKernelGGL((k_bbj_update<double, true>), dim3((unsigned)g.nblk), dim3(kBJThreads), 0, st, g, S, B, X, R,
-                     nullptr, nullptr, Mfrag, Z, cs);
+                           const double* Mfrag, double* Z, const CgState& cs, double tol, hipStream_t st,
+                           const float* M32) {
+  if (M32)
+    hipLaunchKernelGGL((k_bbj_update<double, true, float>), dim3((unsigned)g.nblk), dim3(kBJThreads), 0, st, g, S, B,
+                       X, R, nullptr, nullptr, M32, Z, cs);
+  else
+    hipLaunchKernelGGL((k_bbj_update<double, true, double>), dim3((unsigned)g.nblk), dim3(kBJThreads), 0, st, g, S,
+                       B, X, R, nullptr, nullptr, Mfrag, Z, cs);
   hipLaunchKernelGGL(k_bcg_init_fin, dim3((unsigned)(g.M * S)), dim3(kBlock), 0, st, g, cs, S, tol);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -905,13 +910,21 @@ hipError_t launch_bbj_init(const BatchGeom& g, int S, const double* B, double* X
 
 hipError_t launch_bbj_update(const BatchGeom& g, int S, double* X, double* R, const void* P, const void* Q,
                              bool f32vec, const double* Mfrag, double* Z, const CgState& cs, const int32_t* iter_dev,
-                             hipStream_t st) {
-  if (f32vec)
-    hipLaunchKernelGGL((k_bbj_update<float, false>), dim3((unsigned)g.grid), dim3(kBJThreads), 0, st, g, S, nullptr,
-                       X, R, static_cast<const float*>(P), static_cast<const double*>(Q), Mfrag, Z, cs);
+                             hipStream_t st, const float* M32) {
+  const dim3 grid((unsigned)g.grid), block(kBJThreads);
+  const double* Qd = static_cast<const double*>(Q);
+  if (f32vec && M32)
+    hipLaunchKernelGGL((k_bbj_update<float, false, float>), grid, block, 0, st, g, S, nullptr, X, R,
+                       static_cast<const float*>(P), Qd, M32, Z, cs);
+  else if (f32vec)
+    hipLaunchKernelGGL((k_bbj_update<float, false, double>), grid, block, 0, st, g, S, nullptr, X, R,
+                       static_cast<const float*>(P), Qd, Mfrag, Z, cs);
+  else if (M32)
+    hipLaunchKernelGGL((k_bbj_update<double, false, float>), grid, block, 0, st, g, S, nullptr, X, R,
+                       static_cast<const double*>(P), Qd, M32, Z, cs);
   else
-    hipLaunchKernelGGL((k_bbj_update<double, false>), dim3((unsigned)g.grid), dim3(kBJThreads), 0, st, g, S, nullptr,
-                       X, R, static_cast<const double*>(P), static_cast<const double*>(Q), Mfrag, Z, cs);
+    hipLaunchKernelGGL((k_bbj_update<double, false, double>), grid, block, 0, st, g, S, nullptr, X, R,
+                       static_cast<const double*>(P), Qd, Mfrag, Z, cs);
   hipLaunchKernelGGL(k_bcg_beta, dim3((unsigned)(g.M * S)), dim3(kBlock), 0, st, g, cs, S, iter_dev);
   return hipGetLastError();
 }

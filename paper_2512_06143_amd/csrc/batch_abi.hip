@@ -49,6 +49,7 @@ struct gp2s_batch_s {
   // blocks (64 rows of one instance) factored once per run
   double* bj_L = nullptr;
   double* bj_M = nullptr;
+  float* bj_M32 = nullptr;  // the same in float32 (y and refinement solves)
   double* bj_piv = nullptr;
   int64_t* bj_r0 = nullptr;
   int32_t* bj_m = nullptr;
@@ -248,6 +249,7 @@ struct BCg {
   double* R = nullptr;
   double* Z = nullptr;  // M^-1 r (block preconditioner)
   bool bj = false;
+  bool probe = false;  // the probe block: float64 M^-1 (it enters the estimators)
   void* P = nullptr;
   void* Q = nullptr;
   int32_t* si = nullptr;
@@ -285,7 +287,8 @@ gp2s_status bcg_capture(BCg& c) {
                            c.P, c.Q, c.f32vec, c.cs, c.st);
     if (c.bj) {
       if (ce == hipSuccess)
-        ce = launch_bbj_update(c.gc, c.S, c.X, c.R, c.P, c.Q, c.f32vec, b->bj_M, c.Z, c.cs, c.iter_dev, c.st);
+        ce = launch_bbj_update(c.gc, c.S, c.X, c.R, c.P, c.Q, c.f32vec, b->bj_M, c.Z, c.cs, c.iter_dev, c.st,
+                               c.S == 1 && !c.probe ? b->bj_M32 : nullptr);
       if (ce == hipSuccess) ce = launch_bcg_pupdate(c.gc, c.S, c.P, c.Z, nullptr, c.f32vec, c.cs, c.iter_dev, c.st);
     } else {
       if (ce == hipSuccess)
@@ -355,7 +358,8 @@ gp2s_status bcg_begin(BCg& c, const double* B, const double* tol_dev, double tol
   HIPCHK(hipMemsetAsync(c.si, 0, (2 * (size_t)SM + 8) * sizeof(int32_t), c.st));
   const BatchGeom g = geom(b);
   if (c.bj)
-    HIPCHK(launch_bbj_init(g, S, B, c.X, c.R, c.P, c.f32vec, b->bj_M, c.Z, cs, tol, c.st));
+    HIPCHK(launch_bbj_init(g, S, B, c.X, c.R, c.P, c.f32vec, b->bj_M, c.Z, cs, tol, c.st,
+                           S == 1 && !c.probe ? b->bj_M32 : nullptr));
   else
     HIPCHK(launch_bcg_init(g, S, B, b->dinv, c.X, c.R, c.P, c.f32vec, cs, tol, c.st));
   if (tol_dev) {
@@ -540,10 +544,11 @@ gp2s_status factor_blocks(gp2s_batch b) {
     const size_t nb = (size_t)b->nblk;
     b->bj_L = bown<double>(b, nb * kBJ * kBJ);
     b->bj_M = bown<double>(b, nb * kBJ * kBJ);
+    b->bj_M32 = bown<float>(b, nb * kBJ * kBJ);
     b->bj_piv = bown<double>(b, (size_t)b->N);
     b->bj_r0 = bown<int64_t>(b, nb);
     b->bj_m = bown<int32_t>(b, nb);
-    if (!b->bj_L || !b->bj_M || !b->bj_piv || !b->bj_r0 || !b->bj_m) {
+    if (!b->bj_L || !b->bj_M || !b->bj_M32 || !b->bj_piv || !b->bj_r0 || !b->bj_m) {
       b->bj_M = nullptr;
       return fail(ctx, GP2S_E_OOM, "block preconditioner allocation failed (%zu blocks)", nb);
     }
@@ -564,7 +569,7 @@ gp2s_status factor_blocks(gp2s_batch b) {
   int32_t* bad = sc.get<int32_t>(1);
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "allocation failed");
   HIPCHK(hipMemsetAsync(bad, 0, sizeof(int32_t), st));
-  HIPCHK(launch_bj_factor(b->N, b->row_ptr, b->col, b->val, b->prec, nullptr, 0, b->bj_L, b->bj_M, b->bj_piv, bad, st,
+  HIPCHK(launch_bj_factor(b->N, b->row_ptr, b->col, b->val, b->prec, nullptr, 0, b->bj_L, b->bj_M, b->bj_M32, b->bj_piv, bad, st,
                           bj_blocks(b)));
   int32_t hb = 0;
   gp2s_status s = readback(ctx, bad, sizeof(hb), &hb);
@@ -894,6 +899,7 @@ gp2s_status gp2s_batch_run(gp2s_batch b, const double* const* y, const gp2s_para
   cy.st = b->cap_stream;
   cy.slots = b->pin;
   pr.S = S;
+  pr.probe = true;
   pr.X = Qs;
   pr.label = "probe block";
   pr.st = b->cap2;

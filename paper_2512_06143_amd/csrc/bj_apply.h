@@ -18,14 +18,18 @@ constexpr int kBJThreads = 256;  // four waves: wave w computes rows 16w .. 16w 
 // Operands of the f64 16x16x4 instruction: lane l holds A[l % 16][l / 16] and
 // B[l / 16][l % 16] of a 16 x 4 by 4 x 16 step; the result of lane l, register v, is row
 // l / 16 + 4 v, column l % 16 of the 16 x 16 tile.
-__device__ inline void bj_apply_block(const double* Rs, const double* __restrict__ Mb, int m, int S, int64_t r0,
+// MT: float64, or float32 for solves whose preconditioner does not enter an estimator
+// (the y and refinement solves: a symmetric float32 rounding of M^-1 is still positive
+// definite and halves the bytes that dominate a single-column update).
+template <typename MT>
+__device__ inline void bj_apply_block(const double* Rs, const MT* __restrict__ Mb, int m, int S, int64_t r0,
                                       double* __restrict__ Z, double (&rz)[kBJ / 16]) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int ntile = (S + 15) / 16;
-  const double* F = Mb + wave * 1024;
+  const MT* F = Mb + wave * 1024;
   double af[16];
 #pragma unroll
-  for (int kk = 0; kk < 16; ++kk) af[kk] = F[kk * 64 + lane];
+  for (int kk = 0; kk < 16; ++kk) af[kk] = (double)F[kk * 64 + lane];
   const int row_base = 16 * wave + (lane >> 4);
 #pragma unroll
   for (int jt = 0; jt < kBJ / 16; ++jt) {

@@ -38,8 +38,8 @@ __global__ __launch_bounds__(kBJThreads) void k_bj_factor(int64_t n, const int64
                                                           const int32_t* __restrict__ col,
                                                           const V* __restrict__ val, const double* __restrict__ G,
                                                           int U, BjBlocks bl, double* __restrict__ Lout,
-                                                          double* __restrict__ Mfrag, double* __restrict__ piv,
-                                                          int32_t* __restrict__ bad) {
+                                                          double* __restrict__ Mfrag, float* __restrict__ M32,
+                                                          double* __restrict__ piv, int32_t* __restrict__ bad) {
   __shared__ double A[kBJ * kBJStride];   // block of K, then its factor L (lower part)
   __shared__ double Li[kBJ * kBJStride];  // L^-1 (lower part)
   const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
@@ -131,6 +131,7 @@ __global__ __launch_bounds__(kBJThreads) void k_bj_factor(int64_t n, const int64
       double s = 0.0;
       for (int k = i > j ? i : j; k < kBJ; ++k) s += Li[k * kBJStride + i] * Li[k * kBJStride + j];
       Mb[e] = s;
+      if (M32) M32[blk * (int64_t)(kBJ * kBJ) + e] = (float)s;
     }
     __syncthreads();
   }
@@ -143,11 +144,11 @@ __global__ __launch_bounds__(kBJThreads) void k_bj_factor(int64_t n, const int64
 // Thread t of the elementwise phase owns column t % S; waves own 16 rows of z each.
 // Operands of the f64 16x16x4 instruction: lane l holds A[l % 16][l / 16] and
 // B[l / 16][l % 16] of a 16 x 4 by 4 x 16 step.
-template <typename VEC, bool WANTX, bool INIT>
+template <typename VEC, bool WANTX, bool INIT, typename MT>
 __global__ __launch_bounds__(kBJThreads) void k_bj_update(int64_t n, int S, const double* __restrict__ B,
                                                           double* __restrict__ X, double* __restrict__ R,
                                                           const VEC* __restrict__ P, const double* __restrict__ Q,
-                                                          const double* __restrict__ Mfrag, double* __restrict__ Z,
+                                                          const MT* __restrict__ Mfrag, double* __restrict__ Z,
                                                           CgState cs) {
   __shared__ double Rs[kBJ * kBJ];  // residual block [row][column], column stride 64
   __shared__ double red[kBJThreads / kWave][kBJ];
@@ -243,28 +244,35 @@ static unsigned bj_grid(int64_t n, int64_t cap) { return bj_grid_blocks((n + kBJ
 static int64_t bj_count_host(const BjBlocks& bl, int64_t n) { return bl.r0 ? bl.n : (n + kBJ - 1) / kBJ; }
 
 hipError_t launch_bj_factor(int64_t n, const int64_t* rp, const int32_t* col, const void* val, int prec,
-                            const double* G, int U, double* L, double* Mfrag, double* piv, int32_t* bad,
+                            const double* G, int U, double* L, double* Mfrag, float* M32, double* piv, int32_t* bad,
                             hipStream_t st, const BjBlocks& bl) {
   const unsigned g = bj_grid_blocks(bj_count_host(bl, n), 8192);
   if (prec == GP2S_MIXED)
     hipLaunchKernelGGL(k_bj_factor<float>, dim3(g), dim3(kBJThreads), 0, st, n, rp, col,
-                       static_cast<const float*>(val), G, U, bl, L, Mfrag, piv, bad);
+                       static_cast<const float*>(val), G, U, bl, L, Mfrag, M32, piv, bad);
   else
     hipLaunchKernelGGL(k_bj_factor<double>, dim3(g), dim3(kBJThreads), 0, st, n, rp, col,
-                       static_cast<const double*>(val), G, U, bl, L, Mfrag, piv, bad);
+                       static_cast<const double*>(val), G, U, bl, L, Mfrag, M32, piv, bad);
   return hipGetLastError();
 }
 
 unsigned bj_update_blocks(int64_t n) { return bj_grid(n, kDotBlocks); }
 
 hipError_t launch_bj_update(int64_t n, int S, const double* B, double* X, double* R, const void* P, const void* Q,
-                            bool f32vec, const double* Mfrag, double* Z, const CgState& cs, hipStream_t st) {
+                            bool f32vec, const double* Mfrag, double* Z, const CgState& cs, hipStream_t st,
+                            const float* M32) {
   const unsigned g = bj_update_blocks(n);
   const bool wx = X != nullptr;
   const double* Qd = static_cast<const double*>(Q);
 #define GP2S_BJ(VEC, WX, INIT)                                                                                  \
-  hipLaunchKernelGGL((k_bj_update<VEC, WX, INIT>), dim3(g), dim3(kBJThreads), 0, st, n, S, B, X, R,          \
-                     static_cast<const VEC*>(P), Qd, Mfrag, Z, cs)
+  do {                                                                                                         \
+    if (M32)                                                                                                   \
+      hipLaunchKernelGGL((k_bj_update<VEC, WX, INIT, float>), dim3(g), dim3(kBJThreads), 0, st, n, S, B, X, R,\
+                         static_cast<const VEC*>(P), Qd, M32, Z, cs);                                         \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_bj_update<VEC, WX, INIT, double>), dim3(g), dim3(kBJThreads), 0, st, n, S, B, X,  \
+                         R, static_cast<const VEC*>(P), Qd, Mfrag, Z, cs);                                    \
+  } while (0)
   if (B) {
     if (wx) GP2S_BJ(double, true, true);
     else GP2S_BJ(double, false, true);

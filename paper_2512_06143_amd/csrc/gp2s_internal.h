@@ -318,12 +318,16 @@ struct BjBlocks {
   const int32_t* m;
   int64_t n;
 };
+// M32 (optional): a float32 copy of M^-1 in the same order, for the y and refinement solves.
 hipError_t launch_bj_factor(int64_t n, const int64_t* rp, const int32_t* col, const void* val, int prec,
-                            const double* G, int U, double* L, double* Mfrag, double* piv, int32_t* bad,
+                            const double* G, int U, double* L, double* Mfrag, float* M32, double* piv, int32_t* bad,
                             hipStream_t st, const BjBlocks& bl = BjBlocks{nullptr, nullptr, 0});
 unsigned bj_update_blocks(int64_t n);
+// M32 non-null: apply the float32 copy of M^-1 instead (solves whose preconditioner
+// enters no estimator).
 hipError_t launch_bj_update(int64_t n, int S, const double* B, double* X, double* R, const void* P, const void* Q,
-                            bool f32vec, const double* Mfrag, double* Z, const CgState& cs, hipStream_t st);
+                            bool f32vec, const double* Mfrag, double* Z, const CgState& cs, hipStream_t st,
+                            const float* M32 = nullptr);
 hipError_t launch_bj_rhs(int64_t n, int S, const uint64_t* mask, const double* L, double* B, hipStream_t st,
                          const BjBlocks& bl = BjBlocks{nullptr, nullptr, 0});
 hipError_t launch_copy_dir(int64_t n, int S, const double* Z, void* P, bool f32vec, hipStream_t st);
@@ -410,11 +414,13 @@ hipError_t launch_bcg_pupdate(const BatchGeom& g, int S, void* P, const double* 
 // Block-Jacobi batched CG (block list: the batch's row blocks): initialisation r = B,
 // x = 0, z = M^-1 r, p = z; and the per-iteration update x, r, z = M^-1 r with beta.
 // The direction update is launch_bcg_pupdate with R = Z and dinv = nullptr.
+// M32 as for launch_bj_update.
 hipError_t launch_bbj_init(const BatchGeom& g, int S, const double* B, double* X, double* R, void* P, bool f32vec,
-                           const double* Mfrag, double* Z, const CgState& cs, double tol, hipStream_t st);
+                           const double* Mfrag, double* Z, const CgState& cs, double tol, hipStream_t st,
+                           const float* M32 = nullptr);
 hipError_t launch_bbj_update(const BatchGeom& g, int S, double* X, double* R, const void* P, const void* Q,
                              bool f32vec, const double* Mfrag, double* Z, const CgState& cs, const int32_t* iter_dev,
-                             hipStream_t st);
+                             hipStream_t st, const float* M32 = nullptr);
 // out[i] over instance i's rows: mode 0 = a.b, 1 = sum ln a
 hipError_t launch_bseg_reduce(const BatchGeom& g, int mode, const double* a, const double* b, double* out,
                               hipStream_t st);

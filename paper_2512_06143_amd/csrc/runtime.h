@@ -96,6 +96,7 @@ struct gp2s_matrix_s {
   // block-Jacobi factor (built on first use, dropped when the values change)
   double* bj_L = nullptr;    // [nblk * 64 * 64] row-major L per block
   double* bj_M = nullptr;    // [nblk * 64 * 64] M^-1 per block, matrix-core operand order
+  float* bj_M32 = nullptr;   // the same in float32 (y and refinement solves)
   double* bj_piv = nullptr;  // [n] L_ii^2
   bool bj_ready = false;
   std::vector<void*> owned;
