@@ -2,7 +2,8 @@
 
 The order: a hand-worked five-point example; on random and clustered clouds, a
 permutation whose cell numbers never decrease, ties in user order, cells of side at
-least r, and every pair closer than r in the same or neighbouring cells.
+least r, and every pair closer than r in the same or neighbouring cells; the batched
+path's grid (refined cells, a smaller cap) keeps pairs within `refine` cells.
 
 The estimators with a block preconditioner M = L L^T: a single block holding every
 point makes Khat the identity, so Gamma equals ln|K| for any probes; averaged over
@@ -152,3 +153,27 @@ def test_planted_mistakes_fail(monkeypatch):
         return L, Linv, 0.0
     monkeypatch.setattr(E, "block_factor", no_logdet)
     _fails(test_single_block_makes_gamma_exact)
+
+
+@pytest.mark.parametrize("refine", [1, 2])
+def test_batched_grid_refinement_and_cap(refine):
+    """The batched path's grid: cells of side r (1 + 1e-6) / refine unless widened past
+    max(4 n, min_cells) cells; every pair closer than r then lies at most `refine` cells
+    apart along each axis, and refine = 1 with the single-matrix cap is the plain order."""
+    from scipy.spatial import cKDTree
+    p = workloads.make_random_problem(41, 3000, 2, 0.03, points="gmm")
+    x, r = p.x, 0.03
+    lo, h, nb = oracle.grid(x, r, refine=refine, min_cells=4096)
+    assert int(np.prod(nb)) <= max(4 * len(x), 4096)
+    base = r * (1 + 1e-6) / refine
+    assert np.all(h >= base * (1 - 1e-12))
+    if int(np.prod([np.floor((x[:, k].max() - x[:, k].min()) / base) + 1 for k in range(2)])) <= max(4 * len(x), 4096):
+        np.testing.assert_allclose(h, base, rtol=1e-15)  # no widening needed: side exactly r (1 + 1e-6) / refine
+    c, _ = oracle.bin_coords(x, r, refine=refine, min_cells=4096)
+    pairs = cKDTree(x).query_pairs(r, output_type="ndarray")
+    assert np.all(np.abs(c[pairs[:, 0]] - c[pairs[:, 1]]) <= refine)
+    order = oracle.bin_order(x, r, refine=refine, min_cells=4096)
+    key = c[order, 1] * nb[0] + c[order, 0]
+    assert np.all(np.diff(key) >= 0) and sorted(order.tolist()) == list(range(len(x)))
+    if refine == 1:
+        np.testing.assert_array_equal(oracle.bin_order(x, r, refine=1, min_cells=65536), oracle.bin_order(x, r))
