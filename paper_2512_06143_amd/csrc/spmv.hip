@@ -1,14 +1,14 @@
-// CSR products with the assembled covariance: single right-hand side (vector CSR,
-// a group of G lanes per row) and blocks of up to 64 right-hand sides (one wave per
-// row, one lane per column). These drive the solve K a = y and the probe solves of
-// the log-determinant (Sec. 3.5; App. B.6 "MINRES", "LOGDET"). Stored values
-// (float32 or float64) multiply the vectors and accumulate in float64.
+// CSR products with the assembled covariance: single right-hand side (k_spmv_a,
+// nnz-balanced row blocks streamed as 16-byte quads, for matrix handles; k_spmv, a
+// group of G lanes per row, for other CSRs) and blocks of up to 64 right-hand sides
+// (several variants, picked per matrix by timing). These drive the solve K a = y and
+// the probe solves of the log-determinant (Sec. 3.5; App. B.6 "MINRES", "LOGDET").
+// Stored values (float32 or float64) multiply the vectors and accumulate in float64.
 //
-// Both are bandwidth kernels: loads are issued in independent groups of four or
-// eight so that enough gathers are in flight per wave, and grids are large enough to
-// keep every CU's wave slots busy. The CG variants also write p^T q per column as
-// fixed per-workgroup partial sums; a finalize kernel (pcg.hip) reduces them in
-// workgroup order, so results are bitwise reproducible.
+// The single-RHS products stream the CSR from HBM; the block products are bound by the
+// vector-memory units that serve their gathered rows of X. The CG variants also write
+// p^T q per column as fixed per-workgroup partial sums; a finalize kernel (pcg.hip)
+// reduces them in workgroup order, so results are bitwise reproducible.
 #include "gp2s_internal.h"
 #include "spmm_rows.h"
 
@@ -20,11 +20,12 @@ __device__ inline double ld(const V* p, int64_t k) {
 }
 
 // ---- single right-hand side -----------------------------------------------------------
-// G lanes per row. The product is bound by how many loads are in flight: a row's
-// entries take three dependent trips to memory (row pointers, then columns and values,
-// then the gathered x), so a group issues all of a row's column and value loads at
-// once (kWave / G per lane: rows up to 64 entries in one pass) before any gather, and
-// loads the next row's pointers before it multiplies the current row. Every load is
+// G lanes per row, for CSRs without row blocks such as the posterior's cross-covariance
+// (the batched solves have their own kernel). A row's entries take three dependent trips
+// to memory (row pointers, then columns and values, then the gathered x), so a group
+// issues all of a row's column and value loads at once (kWave / G per lane: rows up to
+// 64 entries in one pass) before any gather, and loads the next row's pointers before
+// it multiplies the current row. Every load is
 // unconditional, at an index clamped into the row (lanes past its end reread its last
 // entry and their products are dropped by a select): a predicated load would become a
 // branch, and the compiler then waits for each load inside its branch.
