@@ -21,6 +21,11 @@ LIB_PATH = os.path.join(_PKG, "libgp2s.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2512_06143_amd.build`")
 
+# torch is loaded first: it brings its own HIP runtime, which has to be in the process
+# before libgp2s's (loaded the other way round, the library's device queries have
+# failed with "no ROCm-capable device" once torch initialised the GPU)
+import torch  # noqa: E402,F401
+
 lib = ctypes.CDLL(LIB_PATH)
 
 GP2S_OK, GP2S_E_INVALID, GP2S_E_HIP, GP2S_E_OOM, GP2S_E_CAPACITY = 0, 1, 2, 3, 4

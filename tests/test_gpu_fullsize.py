@@ -80,3 +80,56 @@ def test_c4_full_assembly_rows(precision):
     prob = workloads.make_problem("c4")
     m = _sampled_rows_check(prob, precision, n_rows=300)
     assert abs(m.nnz / m.n - 50.0) < 1.5
+
+
+def _sampled_product_check(m, X, Y, n_rows=300, seed=1):
+    """Y = K X at sampled rows, against the float64 product of the exported stored row
+    (user order), relative to sum_j |K_ij| |X_j|; returns the worst error."""
+    rp, col, val, perm = (t.cpu().numpy() for t in m.export())
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(len(perm), dtype=perm.dtype)
+    X2 = X.reshape(X.shape[0], -1)
+    Y2 = Y.reshape(Y.shape[0], -1)
+    worst = 0.0
+    users = np.random.default_rng(seed).choice(m.n, n_rows, replace=False)
+    lens = np.diff(rp)
+    users = np.concatenate([users, perm[np.argsort(lens)[-20:]]])  # and the 20 longest rows
+    for u in users:
+        p = inv[u]
+        cols = perm[col[rp[p]:rp[p + 1]]]
+        vals = val[rp[p]:rp[p + 1]].astype(np.float64)
+        want = vals @ X2[cols]
+        scale = np.abs(vals) @ np.abs(X2[cols])
+        worst = max(worst, float(np.max(np.abs(Y2[u] - want) / scale)))
+    return worst, int(lens.max())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c4_full_single_rhs_product(precision):
+    """The nnz-balanced single-RHS product on the 10 M-point clustered matrix (rows of 1
+    to several thousand entries, the longest over one 2048-entry pass) at sampled rows
+    and at the longest rows."""
+    G = _G()
+    prob = workloads.make_problem("c4")
+    m = G.gp2s_assemble(prob.x, params_of(prob), precision)
+    x = np.random.default_rng(3).standard_normal(prob.n)
+    y = G.gp2s_spmv(m, x).cpu().numpy()
+    worst, longest = _sampled_product_check(m, x, y)
+    print(f"[c4/{precision}] nnz={m.nnz} longest row {longest}, product max rel err {worst:.2e}", flush=True)
+    assert longest > 2048
+    assert worst <= 1e-13
+    m.free()
+
+
+def test_c2_full_block_product():
+    """The 64-column block product the probe solves use, at the benchmark's size (the
+    variant the tuner picks for this matrix), at sampled rows."""
+    G = _G()
+    prob = workloads.make_problem("c2")
+    m = G.gp2s_assemble(prob.x, params_of(prob), "mixed")
+    X = np.random.default_rng(4).standard_normal((prob.n, 64))
+    Y = G.gp2s_spmv(m, X).cpu().numpy()
+    worst, _ = _sampled_product_check(m, X, Y)
+    print(f"[c2/mixed] 64-column product max rel err {worst:.2e} (variant {m.block_product(64)})", flush=True)
+    assert worst <= 1e-13
+    m.free()
