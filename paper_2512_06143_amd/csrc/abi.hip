@@ -54,6 +54,7 @@ struct Cg {
   int variant = 0;
   double* R = nullptr;
   double* Z = nullptr;  // M^-1 r (block preconditioner)
+  float* Z32 = nullptr;  // the same in float32 after the first iteration (mixed probe block)
   double* lrC = nullptr;     // far-field kernel: G^T p [U * S]
   double* lrPart = nullptr;  // its per-workgroup partials
   uint32_t* lrTicket = nullptr;
@@ -300,6 +301,7 @@ gp2s_status cg_begin(Cg& c, const double* B, double tol, bool keep_hist, Scratch
   const size_t vb = c.f32vec ? sizeof(float) : sizeof(double);
   c.R = sc.get<double>(nS);
   if (c.precond == GP2S_PRECOND_BLOCK) c.Z = sc.get<double>(nS);
+  if (c.precond == GP2S_PRECOND_BLOCK && c.f32vec) c.Z32 = sc.get<float>(nS);
   if (m->ffG) {
     c.lrC = sc.get<double>((size_t)m->ffU * S);
     c.lrPart = sc.get<double>((size_t)m->ffU * S * ff_gtp_blocks(n));
@@ -384,10 +386,12 @@ gp2s_status cg_step(Cg& c) {
   if (m->ffG) HIPCHK(launch_ff_add(n, S, m->ffU, m->ffG, c.lrC, S, 1, static_cast<double*>(c.Q), c.st));
   if (c.precond == GP2S_PRECOND_BLOCK) {
     TIMED_ON(S == 1 ? GP2S_T_CG_UPDATE1 : GP2S_T_CG_UPDATE_BLOCK, c.st,
-             launch_bj_update(n, S, nullptr, c.X, c.R, c.P, c.Q, c.f32vec, m->bj_M, c.Z, c.cs, c.st, bj_m32(c)));
+             launch_bj_update(n, S, nullptr, c.X, c.R, c.P, c.Q, c.f32vec, m->bj_M, c.Z, c.cs, c.st, bj_m32(c),
+                              c.Z32));
     HIPCHK(launch_cg_beta(c.cs, (int)bj_update_blocks(n), S, c.it, c.st));
     TIMED_ON(S == 1 ? GP2S_T_CG_PUPDATE1 : GP2S_T_CG_PUPDATE_BLOCK, c.st,
-             launch_cg_pupdate(n, S, c.P, c.Z, nullptr, c.f32vec, c.cs, c.st));
+             c.Z32 ? launch_cg_pupdate_z32(n, S, c.P, c.Z32, c.f32vec, c.cs, c.st)
+                   : launch_cg_pupdate(n, S, c.P, c.Z, nullptr, c.f32vec, c.cs, c.st));
   } else {
     TIMED_ON(S == 1 ? GP2S_T_CG_UPDATE1 : GP2S_T_CG_UPDATE_BLOCK, c.st,
              launch_cg_update(n, S, c.X, c.R, c.P, c.Q, c.f32vec, m->dinv, c.cs, c.it, c.st));

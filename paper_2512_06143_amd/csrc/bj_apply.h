@@ -21,9 +21,11 @@ constexpr int kBJThreads = 256;  // four waves: wave w computes rows 16w .. 16w 
 // MT: float64, or float32 for solves whose preconditioner does not enter an estimator
 // (the y and refinement solves: a symmetric float32 rounding of M^-1 is still positive
 // definite and halves the bytes that dominate a single-column update).
-template <typename MT>
+// ZT: the stored z (float64, or float32 where only the float32 search directions are
+// formed from it); r^T z is taken from the float64 value either way.
+template <typename MT, typename ZT>
 __device__ inline void bj_apply_block(const double* Rs, const MT* __restrict__ Mb, int m, int S, int64_t r0,
-                                      double* __restrict__ Z, double (&rz)[kBJ / 16]) {
+                                      ZT* __restrict__ Z, double (&rz)[kBJ / 16]) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int ntile = (S + 15) / 16;
   const MT* F = Mb + wave * 1024;
@@ -47,7 +49,7 @@ __device__ inline void bj_apply_block(const double* Rs, const MT* __restrict__ M
         for (int v = 0; v < 4; ++v) {
           const int row = row_base + 4 * v;
           if (row < m) {
-            Z[(r0 + row) * S + c] = acc[v];
+            Z[(r0 + row) * S + c] = (ZT)acc[v];
             part += Rs[row * kBJ + c] * acc[v];
           }
         }

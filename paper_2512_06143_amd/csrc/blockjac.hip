@@ -144,11 +144,11 @@ __global__ __launch_bounds__(kBJThreads) void k_bj_factor(int64_t n, const int64
 // Thread t of the elementwise phase owns column t % S; waves own 16 rows of z each.
 // Operands of the f64 16x16x4 instruction: lane l holds A[l % 16][l / 16] and
 // B[l / 16][l % 16] of a 16 x 4 by 4 x 16 step.
-template <typename VEC, bool WANTX, bool INIT, typename MT>
+template <typename VEC, bool WANTX, bool INIT, typename MT, typename ZT>
 __global__ __launch_bounds__(kBJThreads) void k_bj_update(int64_t n, int S, const double* __restrict__ B,
                                                           double* __restrict__ X, double* __restrict__ R,
                                                           const VEC* __restrict__ P, const double* __restrict__ Q,
-                                                          const MT* __restrict__ Mfrag, double* __restrict__ Z,
+                                                          const MT* __restrict__ Mfrag, ZT* __restrict__ Z,
                                                           CgState cs) {
   __shared__ double Rs[kBJ * kBJ];  // residual block [row][column], column stride 64
   __shared__ double red[kBJThreads / kWave][kBJ];
@@ -260,18 +260,21 @@ unsigned bj_update_blocks(int64_t n) { return bj_grid(n, kDotBlocks); }
 
 hipError_t launch_bj_update(int64_t n, int S, const double* B, double* X, double* R, const void* P, const void* Q,
                             bool f32vec, const double* Mfrag, double* Z, const CgState& cs, hipStream_t st,
-                            const float* M32) {
+                            const float* M32, float* Z32) {
   const unsigned g = bj_update_blocks(n);
   const bool wx = X != nullptr;
   const double* Qd = static_cast<const double*>(Q);
 #define GP2S_BJ(VEC, WX, INIT)                                                                                  \
   do {                                                                                                         \
     if (M32)                                                                                                   \
-      hipLaunchKernelGGL((k_bj_update<VEC, WX, INIT, float>), dim3(g), dim3(kBJThreads), 0, st, n, S, B, X, R,\
-                         static_cast<const VEC*>(P), Qd, M32, Z, cs);                                         \
+      hipLaunchKernelGGL((k_bj_update<VEC, WX, INIT, float, double>), dim3(g), dim3(kBJThreads), 0, st, n, S,  \
+                         B, X, R, static_cast<const VEC*>(P), Qd, M32, Z, cs);                                \
+    else if (Z32)                                                                                              \
+      hipLaunchKernelGGL((k_bj_update<VEC, WX, INIT, double, float>), dim3(g), dim3(kBJThreads), 0, st, n, S,  \
+                         B, X, R, static_cast<const VEC*>(P), Qd, Mfrag, Z32, cs);                            \
     else                                                                                                       \
-      hipLaunchKernelGGL((k_bj_update<VEC, WX, INIT, double>), dim3(g), dim3(kBJThreads), 0, st, n, S, B, X,  \
-                         R, static_cast<const VEC*>(P), Qd, Mfrag, Z, cs);                                    \
+      hipLaunchKernelGGL((k_bj_update<VEC, WX, INIT, double, double>), dim3(g), dim3(kBJThreads), 0, st, n, S, \
+                         B, X, R, static_cast<const VEC*>(P), Qd, Mfrag, Z, cs);                              \
   } while (0)
   if (B) {
     if (wx) GP2S_BJ(double, true, true);

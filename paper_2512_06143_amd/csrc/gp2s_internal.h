@@ -279,6 +279,9 @@ hipError_t launch_cg_update(int64_t n, int S, double* X, double* R, const void* 
                             hipStream_t st);
 hipError_t launch_cg_pupdate(int64_t n, int S, void* P, const double* R, const double* dinv, bool f32vec,
                              const CgState& cs, hipStream_t st);
+// p = z + beta p with z in float32 (see launch_bj_update).
+hipError_t launch_cg_pupdate_z32(int64_t n, int S, void* P, const float* Z, bool f32vec, const CgState& cs,
+                                 hipStream_t st);
 hipError_t launch_axpy_sub(int64_t n, const double* b, const double* kx, double* r, hipStream_t st);
 hipError_t launch_add(int64_t n, double* x, const double* d, hipStream_t st);
 hipError_t launch_dot_partial(int64_t n, const double* a, const double* b, double* out,
@@ -325,9 +328,11 @@ hipError_t launch_bj_factor(int64_t n, const int64_t* rp, const int32_t* col, co
 unsigned bj_update_blocks(int64_t n);
 // M32 non-null: apply the float32 copy of M^-1 instead (solves whose preconditioner
 // enters no estimator).
+// Z32 non-null: store z in float32 there instead of Z (the mixed path's probe block,
+// whose float32 directions are formed from it by launch_cg_pupdate_z32).
 hipError_t launch_bj_update(int64_t n, int S, const double* B, double* X, double* R, const void* P, const void* Q,
                             bool f32vec, const double* Mfrag, double* Z, const CgState& cs, hipStream_t st,
-                            const float* M32 = nullptr);
+                            const float* M32 = nullptr, float* Z32 = nullptr);
 hipError_t launch_bj_rhs(int64_t n, int S, const uint64_t* mask, const double* L, double* B, hipStream_t st,
                          const BjBlocks& bl = BjBlocks{nullptr, nullptr, 0});
 hipError_t launch_copy_dir(int64_t n, int S, const double* Z, void* P, bool f32vec, hipStream_t st);

@@ -201,6 +201,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_pupdate(int64_t n, int S, VEC* __
   }
 }
 
+// As k_cg_pupdate with z stored in float32 (the mixed path's block preconditioner:
+// the search directions it forms are float32 anyway).
+template <typename VEC>
+__global__ __launch_bounds__(kBlock) void k_cg_pupdate_z32(int64_t n, int S, VEC* __restrict__ P,
+                                                           const float* __restrict__ Z, CgState cs) {
+  const int nth = blockDim.x;
+  const int64_t total = n * (int64_t)S;
+  const int s_me = threadIdx.x % S;
+  if (cs.done[s_me]) return;
+  const double b = cs.beta[s_me];
+  for (int64_t e = blockIdx.x * (int64_t)nth + threadIdx.x; e < total; e += (int64_t)gridDim.x * nth)
+    P[e] = (VEC)((double)Z[e] + b * (double)P[e]);
+}
+
 static unsigned reduce_blocks(int64_t total, int nth) {
   int64_t b = (total + nth - 1) / nth;
   if (b > kReduceBlocks) b = kReduceBlocks;
@@ -274,6 +288,21 @@ hipError_t launch_cg_pupdate(int64_t n, int S, void* P, const double* R, const d
   else
     hipLaunchKernelGGL(k_cg_pupdate<double>, dim3((unsigned)blocks), dim3(nth), 0, st, n, S,
                        static_cast<double*>(P), R, dinv, cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_pupdate_z32(int64_t n, int S, void* P, const float* Z, bool f32vec, const CgState& cs,
+                                 hipStream_t st) {
+  const int nth = cols_block(S);
+  int64_t blocks = (n * S + 4 * (int64_t)nth - 1) / (4 * (int64_t)nth);
+  if (blocks > (1 << 16)) blocks = 1 << 16;
+  if (blocks < 1) blocks = 1;
+  if (f32vec)
+    hipLaunchKernelGGL(k_cg_pupdate_z32<float>, dim3((unsigned)blocks), dim3(nth), 0, st, n, S,
+                       static_cast<float*>(P), Z, cs);
+  else
+    hipLaunchKernelGGL(k_cg_pupdate_z32<double>, dim3((unsigned)blocks), dim3(nth), 0, st, n, S,
+                       static_cast<double*>(P), Z, cs);
   return hipGetLastError();
 }
 
