@@ -32,16 +32,25 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(cat, n, nnz, S, prec):
+def kernel_bytes(cat, n, nnz, S, prec, precond="block"):
     """Algorithmic HBM bytes of one launch of a timed kernel category: the CSR once,
     each vector stream once, at the types the path stores them in (the probe block
-    of the mixed path keeps its search directions P in float32; products Q, x and r
-    are float64)."""
+    of the mixed path keeps its search directions P and, with the block
+    preconditioner, z = M^-1 r in float32; products Q, x and r are float64; the y
+    solve applies a float32 copy of M^-1)."""
     vb = 4 if prec == "mixed" else 8                        # stored K value
-    pb = 4 if (prec == "mixed" and "block" in cat) else 8   # P element
+    block = "block" in cat
+    pb = 4 if (prec == "mixed" and block) else 8            # P element
     K = nnz * (4 + vb) + (n + 1) * 8
     if cat in ("cg_matvec_block", "cg_matvec1", "spmv"):
         return K + n * S * (pb + 8)                 # read P once, write Q
+    if precond == "block":
+        zb = 4 if (prec == "mixed" and block) else 8        # stored z
+        mb = 8 if block else 4                              # M^-1 element (64 per row)
+        if cat in ("cg_update_block", "cg_update1"):
+            return n * S * (8 * 4 + pb + 8 + zb) + n * 64 * mb  # X, R read+write; P, Q read; z written; M^-1
+        if cat in ("cg_pupdate_block", "cg_pupdate1"):
+            return n * S * (zb + pb * 2)            # z read; P read+write
     if cat in ("cg_update_block", "cg_update1"):
         return n * S * (8 * 4 + pb + 8) + n * 8     # X, R read+write; P, Q read; 1/diag
     if cat in ("cg_pupdate_block", "cg_pupdate1"):
@@ -457,7 +466,7 @@ def main():
     dom = max(per, key=lambda k: per[k][0])
     ms_tot, cnt = per[dom]
     avg_s = ms_tot / cnt / 1e3
-    b = kernel_bytes(dom, n, nnz, S if "block" in dom else 1, args.precision)
+    b = kernel_bytes(dom, n, nnz, S if "block" in dom else 1, args.precision, args.precond)
     roof = None
     if b is not None:
         roof = {"kernel": dom, "bound": "hbm", "achieved": b / avg_s / 1e9, "peak": PEAK_HBM / 1e9,
