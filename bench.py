@@ -405,8 +405,8 @@ def main():
         return
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the multi-GPU sharding is a design note only).", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library runs on one "
+              "GPU; how the path would shard over several is described in the design notes).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
