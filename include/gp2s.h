@@ -197,6 +197,10 @@ const char* gp2s_last_error(gp2s_ctx ctx);         /* valid until the next call 
 /* Enable (1) or disable (0) per-kernel event timing on ctx; either call resets the
  * totals. Timing adds two event records per timed launch. */
 gp2s_status gp2s_set_timing(gp2s_ctx ctx, int32_t enable);
+/* Time only the categories whose bits are set in mask (bit k = GP2S_T_* value k; 0 turns
+ * timing off; bits past GP2S_NUM_TIMERS are ignored), so that a measurement of one
+ * kernel does not pay the event records of every launch. Resets the totals. */
+gp2s_status gp2s_set_timing_mask(gp2s_ctx ctx, uint32_t mask);
 /* Totals since the last gp2s_set_timing (HOST struct); waits for the stream. */
 gp2s_status gp2s_get_stats(gp2s_ctx ctx, gp2s_stats* out);
 

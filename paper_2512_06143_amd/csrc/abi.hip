@@ -916,19 +916,23 @@ gp2s_status gp2s_create(gp2s_ctx* out, void* stream, gp2s_alloc_fn alloc, gp2s_f
   return GP2S_OK;
 }
 
-gp2s_status gp2s_set_timing(gp2s_ctx ctx, int32_t enable) {
+gp2s_status gp2s_set_timing_mask(gp2s_ctx ctx, uint32_t mask) {
   if (!ctx) return GP2S_E_INVALID;
   if (ctx->aux) (void)hipStreamSynchronize(ctx->aux);
   if (!ctx->pending.empty()) {
     (void)hipStreamSynchronize(ctx->stream);
     harvest(ctx);
   }
-  ctx->timing = enable != 0;
+  ctx->timing_mask = mask & ((1u << GP2S_NUM_TIMERS) - 1u);
   for (int k = 0; k < GP2S_NUM_TIMERS; ++k) {
     ctx->ms[k] = 0.0;
     ctx->count[k] = 0;
   }
   return GP2S_OK;
+}
+
+gp2s_status gp2s_set_timing(gp2s_ctx ctx, int32_t enable) {
+  return gp2s_set_timing_mask(ctx, enable ? ~0u : 0u);
 }
 
 gp2s_status gp2s_set_progress(gp2s_ctx ctx, gp2s_progress_fn fn, void* user) {

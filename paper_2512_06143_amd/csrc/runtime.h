@@ -22,8 +22,8 @@ struct gp2s_ctx_s {
   void* pinned = nullptr;  // small pinned host buffer for scalar read-backs
   // second stream (default priority) for the probe block, which runs beside the y solve
   hipStream_t aux = nullptr;
-  // optional per-kernel timing with HIP events on the context's stream
-  bool timing = false;
+  // optional per-kernel timing with HIP events: bit k set = category k (GP2S_T_*) timed
+  uint32_t timing_mask = 0;
   struct Pending {
     int cat;
     hipEvent_t e0, e1;
@@ -215,7 +215,7 @@ struct Timed {
   hipStream_t st;
   hipEvent_t e0 = nullptr;
   Timed(gp2s_ctx cc, int k, hipStream_t s) : c(cc), cat(k), st(s) {
-    if (c->timing) {
+    if ((c->timing_mask >> cat) & 1u) {
       e0 = ev_get(c);
       if (e0) (void)hipEventRecord(e0, st);
     }

@@ -97,6 +97,7 @@ _SIGS = {
     "gp2s_last_error": (ctypes.c_char_p, [_vp]),
     "gp2s_check_params": (_i32, [_vp, _i64, ctypes.POINTER(Params)]),
     "gp2s_set_timing": (_i32, [_vp, _i32]),
+    "gp2s_set_timing_mask": (_i32, [_vp, ctypes.c_uint32]),
     "gp2s_set_progress": (_i32, [_vp, PROGRESS_FN, _vp]),
     "gp2s_get_stats": (_i32, [_vp, ctypes.POINTER(Stats)]),
     "gp2s_assemble": (_i32, [_vp, _i64, _vp, ctypes.POINTER(Params), _i32, ctypes.POINTER(_vp)]),
@@ -230,8 +231,16 @@ class Context:
             raise GP2SError(st, lib.gp2s_last_error(self.ptr).decode())
         return st
 
-    def set_timing(self, enable=True):
-        self.check(lib.gp2s_set_timing(self.ptr, 1 if enable else 0))
+    def set_timing(self, enable=True, only=None):
+        """Per-kernel event timing (resets the totals). `only`: a list of category names
+        (TIMER_NAMES) to time, the others running without event records."""
+        if only is None:
+            self.check(lib.gp2s_set_timing(self.ptr, 1 if enable else 0))
+        else:
+            mask = 0
+            for name in only:
+                mask |= 1 << TIMER_NAMES.index(name)
+            self.check(lib.gp2s_set_timing_mask(self.ptr, mask if enable else 0))
 
     def set_progress(self, fn=None):
         """fn(label: str, iters: int, open_cols: int, max_rel_resid: float) or None."""
