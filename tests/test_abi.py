@@ -92,6 +92,20 @@ def test_entry_points_reject_bad_arguments_without_gpu():
     B.lib.gp2s_destroy(ctx)
 
 
+def test_timing_mask_host_side():
+    """The timing switches need no device while nothing is pending: a null context is
+    rejected, and a set mask leaves every total at zero."""
+    B, ctx = _ctx()
+    assert B.lib.gp2s_set_timing_mask(None, 1) == 1
+    assert B.lib.gp2s_set_timing_mask(ctx, (1 << B.NUM_TIMERS) - 1) == 0
+    st = B.Stats()
+    assert B.lib.gp2s_get_stats(ctx, ctypes.byref(st)) == 0
+    assert all(c == 0 for c in st.count) and all(t == 0.0 for t in st.ms)
+    assert B.lib.gp2s_set_timing(ctx, 0) == 0
+    assert B.lib.gp2s_get_stats(None, ctypes.byref(st)) == 1
+    B.lib.gp2s_destroy(ctx)
+
+
 def test_default_opts():
     import paper_2512_06143_amd.gp2s as B
     o = B.default_opts()

@@ -239,3 +239,30 @@ def test_product_and_solve_irregular_rows(gpu, precision, shape):
     a, rep = G.gp2s_solve(m, x, G.default_opts(tol=1e-12, max_iter=20000))
     assert oracle.residual_rel(At, a.cpu().numpy(), x) <= 1e-11
     m.free()
+
+
+def test_timing_mask_records_only_selected_categories(gpu):
+    """Per-kernel event timing honours the category mask: with one category selected the
+    others run without event records (zero counts), and turning timing on for all
+    categories records the standalone product again."""
+    G = _G()
+    A = _irregular_spd(5, 3000, hubs=2, hub_len=800)
+    m = G.gp2s_matrix_import(A.indptr, A.indices, A.data, "fp64")
+    ctx = m.ctx
+    x = np.random.default_rng(4).standard_normal(A.shape[0])
+    try:
+        ctx.set_timing(True, only=["cg_matvec1"])
+        G.gp2s_spmv(m, x)
+        a, rep = G.gp2s_solve(m, x, G.default_opts(tol=1e-10))
+        st = ctx.stats()
+        print("[timing mask] " + " ".join(f"{k}={v[1]}" for k, v in st.items() if v[1]), flush=True)
+        assert st["cg_matvec1"][1] > 0 and st["cg_matvec1"][0] > 0.0
+        assert all(cnt == 0 for k, (_, cnt) in st.items() if k != "cg_matvec1")
+        ctx.set_timing(True)
+        G.gp2s_spmv(m, x)
+        st = ctx.stats()
+        assert st["spmv"][1] == 1 and st["cg_matvec1"][1] == 0
+    finally:
+        ctx.set_timing(False)
+    assert all(cnt == 0 for _, cnt in ctx.stats().values())
+    m.free()
