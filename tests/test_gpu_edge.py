@@ -156,9 +156,10 @@ def test_indefinite_matrix_reports_not_spd(gpu):
 
 
 def test_autograd_function(gpu):
-    """GP2SLML: forward value and backward gradients equal gp2s_lml_grad's; the
-    gradient agrees with central differences of the exact dense LML within the
-    Hutchinson standard deviation."""
+    """GP2SLML: forward value and backward gradients equal gp2s_lml_grad's up to rounding
+    order (each handle tunes its own block-product variant by timing, and the variants
+    sum a row in different orders); the gradient agrees with the exact dense LML's
+    within the Hutchinson standard deviation."""
     import torch
     G = _G()
     prob = workloads.make_random_problem(8, 600, 2, 0.09, n_bumps=3, bump_width=0.5, noise_var=1e-3)
@@ -174,8 +175,8 @@ def test_autograd_function(gpu):
     grad = np.concatenate([[r.grad.item()], wts.grad.numpy(), [nv.grad.item()]])
     m = G.gp2s_assemble(prob.x, params_of(prob), "fp64")
     rep, g2, _ = G.gp2s_lml_grad(m, prob.y, opts)
-    assert val.item() == rep.lml
-    np.testing.assert_array_equal(grad, g2)
+    np.testing.assert_allclose(val.item(), rep.lml, rtol=1e-8)
+    np.testing.assert_allclose(grad, g2, rtol=1e-8)
     # exact gradient and its Hutchinson spread
     ge, parts = oracle.grad_exact(prob.x, prob.y, prob.radius, prob.bump_width, prob.centers, prob.weights,
                                   prob.noise_var)
