@@ -4,14 +4,14 @@
  * non-stationary kernel, multiply with it, solve with it, and evaluate the log
  * marginal likelihood (LML) and its gradient with respect to the hyperparameters.
  *
- * Problem statement (Sec. 2, first displayed equation; Sec. 3.5):
+ * Problem statement (Sec. 3, first displayed equation; Sec. 4.6):
  *   data x_1..x_N in R^d (d = 2 or 3), targets y, zero prior mean, noise
  *   variance sigma_n^2 on the diagonal;
  *   K_ij = g(x_i) g(x_j) W(||x_i - x_j|| / r) + sigma_n^2 [i == j]
  *   with W(rho) = (1 - rho)^4 (4 rho + 1) for rho < 1, else 0 (a C^2 member of the
- *   Wendland family of Sec. 3.1, Eq. wendland), and the bump mask
+ *   Wendland family of Sec. 4.1, Eq. wendland), and the bump mask
  *   g(x) = sum_k a_k exp(1 - 1 / (1 - ||x - c_k||^2 / w^2)) inside ||x - c_k|| < w
- *   (Sec. 3.3, Eq. bump with shape parameter 1, amplitudes a_k = the bump weights,
+ *   (Sec. 4.3, Eq. bump with shape parameter 1, amplitudes a_k = the bump weights,
  *   g a sum of P bumps; the product g g W is a valid kernel by Theorem 1, App. A);
  *   LML = -1/2 y^T K^{-1} y - 1/2 ln|K| - N/2 ln(2 pi).
  *
@@ -70,10 +70,10 @@ typedef void (*gp2s_free_fn)(void* ptr, void* user);
 /* Kernel hyperparameters theta = (r, a_1..a_P, sigma_n^2) plus the fixed bump
  * geometry (centres and width are not differentiated).
  *
- * K_ij = g_i g_j W(rho_ij) + sigma_n^2 [i == j], g the bump mask (Sec. 3.3). With
+ * K_ij = g_i g_j W(rho_ij) + sigma_n^2 [i == j], g the bump mask (Sec. 4.3). With
  * radii == NULL and ls_weights == NULL (zero-initialised params) the kernel is the
- * stationary product construction of Sec. 3.1, rho = ||x_i - x_j|| / r. Otherwise it
- * is the non-stationary convolution form of Eq. wendconv (Sec. 3.2) with
+ * stationary product construction of Sec. 4.1, rho = ||x_i - x_j|| / r. Otherwise it
+ * is the non-stationary convolution form of Eq. wendconv (Sec. 4.2) with
  * S(x) = diag(r_1^2..r_d^2) l(x)^2 and signal deviation g:
  *   l(x) = exp(sum_q c_q bhat_q(x))  (bhat_q the unweighted bumps; l = 1 without ls_weights),
  *   m_ij = (l_i^2 + l_j^2) / 2,  Q_ij = sum_k ((x_ik - x_jk) / r_k)^2 / m_ij,
@@ -86,12 +86,12 @@ typedef void (*gp2s_free_fn)(void* ptr, void* user);
 typedef struct {
   int32_t dim;            /* 2 or 3                                                  */
   int32_t n_bumps;        /* P, 1..256                                               */
-  double radius;          /* Wendland support radius r > 0 (Sec. 3.1, r_0)           */
-  double bump_width;      /* bump radius w > 0 (Sec. 3.3, r in Eq. bump)             */
-  double noise_var;       /* sigma_n^2 >= 0, added on the diagonal (Sec. 2, V)       */
+  double radius;          /* Wendland support radius r > 0 (Sec. 4.1, r_0)           */
+  double bump_width;      /* bump radius w > 0 (Sec. 4.3, r in Eq. bump)             */
+  double noise_var;       /* sigma_n^2 >= 0, added on the diagonal (Sec. 3, V)       */
   const double* centers;  /* HOST [n_bumps * dim], row-major bump centres c_k        */
   const double* weights;  /* HOST [n_bumps], bump amplitudes a_k                     */
-  int32_t kernel;         /* Wendland member W (Sec. 3.1): GP2S_WENDLAND_C2 (0) is
+  int32_t kernel;         /* Wendland member W (Sec. 4.1): GP2S_WENDLAND_C2 (0) is
                              (1-rho)^4 (4 rho + 1); GP2S_WENDLAND_C6 (1) is Eq. wendland
                              as printed, (1-rho)^8 (32 rho^3 + 25 rho^2 + 8 rho + 1).
                              Zero-initialised params select C2.                      */
@@ -102,7 +102,7 @@ typedef struct {
   const int32_t* ff_groups; /* HOST [n_bumps] group u in [0, 16) of each bump for the
                              far-field bump kernel, or NULL (see below)              */
 } gp2s_params;
-/* Far-field bump kernel (Sec. 3.3, Eq. bump_kernel with the core kernel 1), selected by
+/* Far-field bump kernel (Sec. 4.3, Eq. bump_kernel with the core kernel 1), selected by
  * ff_groups != NULL (radii and ls_weights must then be NULL):
  *   K_ij = sum_u g_u(x_i) g_u(x_j) + W(||x_i - x_j|| / r) + sigma_n^2 [i == j],
  *   g_u = sum over the bumps p with ff_groups[p] == u of weights[p] bhat_p,
@@ -215,7 +215,7 @@ gp2s_status gp2s_set_progress(gp2s_ctx ctx, gp2s_progress_fn fn, void* user);
 /* Validate n and params on the host only (what gp2s_assemble checks first). */
 gp2s_status gp2s_check_params(gp2s_ctx ctx, int64_t n, const gp2s_params* params);
 
-/* ---- assembly (Sec. 3.5 covariance computation; App. B.7 pipeline) ---------------
+/* ---- assembly (Sec. 4.6 covariance computation; App. B.7 pipeline) ---------------
  * Builds K for points x (DEVICE [n * dim] float64, row-major, user order) as CSR in
  * an internal, spatially sorted order. Only pairs within the kernel's support are
  * evaluated: points are binned on a grid of side >= r, each row tests the points
@@ -252,7 +252,7 @@ gp2s_status gp2s_matrix_free(gp2s_matrix m);
  * radius, bump count, centres and width must equal the handle's (the pattern depends
  * only on them), else GP2S_E_INVALID. Recomputes g and every stored value in place
  * (no count pass, no allocation of the CSR): the step a sampler takes when a move
- * leaves r and the bump geometry unchanged (Sec. 3.5 and App. D, block-MCMC). The result equals a
+ * leaves r and the bump geometry unchanged (Sec. 4.6 and App. D, block-MCMC). The result equals a
  * fresh gp2s_assemble with the same parameters, bit for bit. */
 gp2s_status gp2s_matrix_refill(gp2s_ctx ctx, gp2s_matrix m, const gp2s_params* params);
 
@@ -274,7 +274,7 @@ gp2s_status gp2s_matrix_get_block_product(gp2s_matrix m, int32_t nrhs, int32_t* 
 /* ---- products and solves ------------------------------------------------------------
  * Y = K X for nrhs in [1, 64] right-hand sides; X and Y are DEVICE [n * nrhs] float64,
  * row-major (row i holds the nrhs values of point i). The CSR SpMV that drives the
- * solve (Sec. 3.5; App. B.6 "MINRES"): products of stored values with float64
+ * solve (Sec. 4.6; App. B.6 "MINRES"): products of stored values with float64
  * vectors accumulate in float64. */
 gp2s_status gp2s_spmv(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X, double* Y);
 /* (n * nrhs, and n * n_probes below, must stay below 2^31.) */
@@ -287,7 +287,7 @@ gp2s_status gp2s_spmv(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X
 gp2s_status gp2s_solve(gp2s_ctx ctx, gp2s_matrix m, const double* y, double* a,
                        const gp2s_solve_opts* opts, gp2s_report* report);
 
-/* LML (Sec. 2): solves K a = y as gp2s_solve does, then estimates ln|K| from
+/* LML (Sec. 3): solves K a = y as gp2s_solve does, then estimates ln|K| from
  * opts->n_probes Rademacher probes z_s (SplitMix64 signs, counter s * 2^40 + user
  * index): ln|K| ~ ln|M| + (1/S) sum_s z_s^T ln(Khat) z_s, Khat = L^-1 K L^-T with
  * M = L L^T the preconditioner of opts->precond, each quadratic form by Lanczos
@@ -308,7 +308,7 @@ gp2s_status gp2s_lml_grad(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp
 
 /* ---- posterior at test points ------------------------------------------------------
  * Posterior mean and variance of the latent function f at n_test test points x*
- * (Sec. 2, Eq. posterior, zero prior mean):
+ * (Sec. 3, Eq. posterior, zero prior mean):
  *   mean_t = k(X, x*_t)^T a,   a = K^{-1} y as returned by gp2s_solve / gp2s_lml,
  *   var_t  = g(x*_t)^2 - k(X, x*_t)^T K^{-1} k(X, x*_t),
  * with k the noise-free kernel of the handle (k(x*, x*) = g(x*)^2; the noise belongs to
@@ -333,7 +333,7 @@ gp2s_status gp2s_predict(gp2s_ctx ctx, gp2s_matrix m, int64_t n_test, const doub
 
 /* ---- batched instances -------------------------------------------------------------
  * Many independent instances (each its own points, dimension, targets and
- * hyperparameters; Sec. 2 per instance) evaluated together: one block-diagonal system
+ * hyperparameters; Sec. 3 per instance) evaluated together: one block-diagonal system
  * assembled in shared launches, solved by batched preconditioned CG (diagonal or
  * block-Jacobi per opts.precond, blocks inside each instance) whose iterations run as
  * replays of one captured hipGraph chunk, with per-instance step lengths, convergence

@@ -4,11 +4,11 @@ This package is a plain, slow, obviously correct restatement of what the GPU pat
 computes, written from the paper (arXiv 2512.06143):
 
 * the compactly supported kernel k(x_i, x_j) = g(x_i) g(x_j) W(||x_i - x_j|| / r),
-  the product construction of Sec. 3.1 with g a sum of bump functions (Sec. 3.3,
+  the product construction of Sec. 4.1 with g a sum of bump functions (Sec. 4.3,
   Eq. bump) and W the C^2 member of the Wendland family ("small variations" of
   Eq. wendland);
 * its sparsity pattern, by brute force and by a k-d tree;
-* the log marginal likelihood of Sec. 2 (first displayed equation, zero prior
+* the log marginal likelihood of Sec. 3 (first displayed equation, zero prior
   mean, noise on the diagonal) through a dense Cholesky factorisation;
 * its exact gradient with respect to the hyperparameters, and the same-probe
   stochastic estimators (Hutchinson trace, probe log-determinant) that the GPU
@@ -16,10 +16,10 @@ computes, written from the paper (arXiv 2512.06143):
 * the counter-based SplitMix64 probe signs;
 * the preconditioners of the solves (diagonal, and block diagonal over runs of the
   binned point order) that the estimators are defined with;
-* the posterior mean and variance of the latent function at test points (Sec. 2,
+* the posterior mean and variance of the latent function at test points (Sec. 3,
   Eq. posterior);
-* the block Metropolis-Hastings sampler of the hyperparameters (Sec. 3.5, App. D);
-* the non-stationary convolution Wendland kernel (Sec. 3.2, Eq. wendconv) with an
+* the block Metropolis-Hastings sampler of the hyperparameters (Sec. 4.6, App. D);
+* the non-stationary convolution Wendland kernel (Sec. 4.2, Eq. wendconv) with an
   axis-anisotropic, bump-driven length-scale field (``oracle.wendconv``).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
@@ -37,7 +37,8 @@ from .pattern import (pairwise_sqdist, pattern_bruteforce, pattern_kdtree, mean_
 from .dense import covariance_dense, dcov_dense, lml_dense, grad_exact, LMLResult
 from .probes import splitmix64, rademacher_probes, probe_sign_masks
 from .estimators import logdet_same_probe, grad_same_probe, lml_same_probe, hutchinson_variance
-from .sparse import covariance_csr, covariance_rows, residual_rel, pcg_jacobi
+from .sparse import (covariance_csr, covariance_rows, residual_rel, pcg_jacobi, dcov_csr, lml_components,
+                     lanczos_logquad, lml_grad_sparse)
 from .posterior import cross_covariance, posterior_dense
 from .mcmc import block_mh
 from .precond import BLOCK, grid, bin_coords, bin_order, block_partition, jacobi_partition, block_factor
@@ -53,5 +54,6 @@ __all__ = [
     "logdet_same_probe", "grad_same_probe", "lml_same_probe", "hutchinson_variance",
     "cross_covariance", "posterior_dense", "block_mh",
     "BLOCK", "grid", "bin_coords", "bin_order", "block_partition", "jacobi_partition", "block_factor",
-    "covariance_csr", "covariance_rows", "residual_rel", "pcg_jacobi",
+    "covariance_csr", "covariance_rows", "residual_rel", "pcg_jacobi", "dcov_csr", "lml_components",
+    "lanczos_logquad", "lml_grad_sparse",
 ]

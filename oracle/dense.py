@@ -3,9 +3,9 @@
 For N up to a few thousand points. Everything follows the plain definitions:
 
 * K_ij = g_i g_j W(||x_i - x_j|| / r) on the stored pattern, plus the noise
-  variance on the diagonal (Sec. 3.1 product construction, Sec. 3.3 bump mask,
-  Sec. 2 normal likelihood with noise matrix V = sigma_n^2 I);
-* LML = -1/2 y^T K^{-1} y - 1/2 ln|K| - N/2 ln(2 pi) (Sec. 2, first displayed
+  variance on the diagonal (Sec. 4.1 product construction, Sec. 4.3 bump mask,
+  Sec. 3 normal likelihood with noise matrix V = sigma_n^2 I);
+* LML = -1/2 y^T K^{-1} y - 1/2 ln|K| - N/2 ln(2 pi) (Sec. 3, first displayed
   equation, zero prior mean; the paper writes it up to a constant, the constant
   is kept here);
 * dLML/dtheta = 1/2 a^T (dK/dtheta) a - 1/2 tr(K^{-1} dK/dtheta), a = K^{-1} y,

@@ -1,7 +1,7 @@
 """Same-probe stochastic estimators, evaluated exactly (dense eigen-decomposition and
 dense inverse) for a given set of Rademacher probes and a given preconditioner.
 
-The paper computes ln|K| on the host with an unnamed method (Sec. 3.5, App. B.6,
+The paper computes ln|K| on the host with an unnamed method (Sec. 4.6, App. B.6,
 "LOGDET"). The GPU path estimates it from preconditioned conjugate gradients on
 right-hand sides L z_s with Lanczos quadrature, where M = L L^T is the
 preconditioner (``oracle.precond``: the diagonal of K, L = D^{1/2}, or its block

@@ -1,4 +1,4 @@
-"""The far-field bump kernel (Sec. 3.3, Eq. bump_kernel) with the core kernel set to
+"""The far-field bump kernel (Sec. 4.3, Eq. bump_kernel) with the core kernel set to
 one (test infrastructure).
 
     k(x_i, x_j) = sum_u g_u(x_i) g_u(x_j) + W(||x_i - x_j|| / r),

@@ -11,7 +11,7 @@ import numpy as np
 def wendland_c2(rho):
     """C^2 Wendland function W(rho) = (1 - rho)^4 (4 rho + 1) for rho < 1, else 0.
 
-    Sec. 3.1: the paper prints the C^6 member (Eq. wendland) and uses "small
+    Sec. 4.1: the paper prints the C^6 member (Eq. wendland) and uses "small
     variations thereof"; the workloads use this C^2 member. The support is strict
     (the equation's condition is ||x_i - x_j|| < r_0).
     """
@@ -38,7 +38,7 @@ def wendland_c2_dr(rho, r):
 
 
 def wendland_c6(rho):
-    """The Wendland member printed in Sec. 3.1, Eq. wendland:
+    """The Wendland member printed in Sec. 4.1, Eq. wendland:
     (1 - rho)^8 (32 rho^3 + 25 rho^2 + 8 rho + 1) for rho < 1, else 0."""
     rho = np.asarray(rho, dtype=np.float64)
     out = np.zeros_like(rho)
@@ -114,13 +114,13 @@ def kernel_params_check(dim, radius, bump_width, centers, weights, noise_var):
 
 
 def bump_values(x, centers, bump_width, weights, chunk=1 << 16):
-    """Bump functions of Sec. 3.3, Eq. bump, and their weighted sum g.
+    """Bump functions of Sec. 4.3, Eq. bump, and their weighted sum g.
 
     For bump k with centre c_k, width w and amplitude a_k (the weight), with the
     shape parameter beta fixed to 1:
         s_ik  = ||x_i - c_k||^2 / w^2
         b_ik  = exp(1 - 1 / (1 - s_ik))      if ||x_i - c_k||^2 < w^2, else 0
-        g_i   = sum_k a_k b_ik               (g as a sum of P bumps, Sec. 3.3)
+        g_i   = sum_k a_k b_ik               (g as a sum of P bumps, Sec. 4.3)
         gamma_i = [some bump has x_i strictly inside its support]
     The printed support condition compares a squared distance with r; it is read
     as the strict ball ||x - c_k|| < w, matching the r^2 inside the exponent.

@@ -1,4 +1,4 @@
-"""Block Metropolis-Hastings over the kernel hyperparameters (Sec. 3.5; App. D).
+"""Block Metropolis-Hastings over the kernel hyperparameters (Sec. 4.6; App. D).
 
 The hyperparameters theta = (r, a_1..a_P, sigma_n^2) are sampled in blocks (by
 default the Wendland radius, the bump amplitudes and the noise variance, each a
@@ -7,7 +7,7 @@ visits every block once: a normal random-walk proposal moves that block's
 components (App. D keeps proposals normal), a flat prior restricts theta to
 bounds (App. D: a flat prior within well-chosen bounds), and the move is accepted
 when log u < loglik(theta') - loglik(theta). Each block costs one likelihood
-evaluation (Sec. 3.5). Random draws are inputs (workloads.mcmc_draws), so a
+evaluation (Sec. 4.6). Random draws are inputs (workloads.mcmc_draws), so a
 device run and this oracle take the same decisions.
 """
 from __future__ import annotations

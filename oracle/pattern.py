@@ -1,6 +1,6 @@
 """Sparsity pattern of the covariance matrix, by brute force and by a k-d tree.
 
-The paper (Sec. 3.5) notes that its distributed implementation evaluates every
+The paper (Sec. 4.6) notes that its distributed implementation evaluates every
 entry because the zeros are only known after evaluation. For the kernel used here
 the zeros are known geometrically: k(x_i, x_j) vanishes when ||x_i - x_j|| >= r
 (the Wendland factor, Eq. wendland has strict support) or when either point lies

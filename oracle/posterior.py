@@ -1,13 +1,13 @@
 """Posterior mean and variance of the latent function at test points (dense, float64).
 
-Sec. 2, Eq. posterior, with zero prior mean: for a test point x*,
+Sec. 3, Eq. posterior, with zero prior mean: for a test point x*,
 
     mean(x*) = k(X, x*)^T K^{-1} y
     var(x*)  = k(x*, x*) - k(X, x*)^T K^{-1} k(X, x*)
 
 where K is the training covariance including the noise on its diagonal (the
-normal likelihood of Sec. 2 with V = sigma_n^2 I) and k is the noise-free kernel
-(Sec. 3.1 product construction, Sec. 3.3 bump mask), so k(x*, x*) = g(x*)^2 W(0)
+normal likelihood of Sec. 3 with V = sigma_n^2 I) and k is the noise-free kernel
+(Sec. 4.1 product construction, Sec. 4.3 bump mask), so k(x*, x*) = g(x*)^2 W(0)
 = g(x*)^2: the posterior of the latent f*, not of a new noisy observation.
 App. B.7 keeps K^{-1} y for the mean; the variance needs one solve per test point.
 

@@ -1,7 +1,7 @@
 """Block-Jacobi preconditioner of the probe and y solves, and the point order that
 defines its blocks (test infrastructure).
 
-The paper leaves the log-determinant method unnamed (Sec. 3.5, App. B.6 "LOGDET").
+The paper leaves the log-determinant method unnamed (Sec. 4.6, App. B.6 "LOGDET").
 The estimators of ``oracle.estimators`` are written for any factor L of a
 preconditioner M = L L^T; the diagonal (Jacobi) choice L = D^{1/2} is the special
 case of one-point blocks. The block choice is:

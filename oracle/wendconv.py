@@ -1,4 +1,4 @@
-"""The non-stationary convolution Wendland kernel (Sec. 3.2, Eq. wendconv) with an
+"""The non-stationary convolution Wendland kernel (Sec. 4.2, Eq. wendconv) with an
 axis-anisotropic (ARD) length scale, times the bump mask: dense and sparse covariance,
 the exact derivatives, and the cross-covariance for the posterior (test
 infrastructure).
@@ -9,7 +9,7 @@ Eq. wendconv, with the Wendland member W of Eq. wendland (or its C^2 variation):
     Q_ij = (x_i - x_j)^T ((S_i + S_j)/2)^{-1} (x_i - x_j),  S_i = S(x_i).
 
 The paper leaves the length-scale field S(x) and the signal deviation s(x) open. The
-reading taken here keeps the bump machinery of Sec. 3.3:
+reading taken here keeps the bump machinery of Sec. 4.3:
 
     S(x) = diag(r_1^2, ..., r_d^2) l(x)^2,    l(x) = exp( sum_q c_q bhat_q(x) ),
     s(x) = g(x) = sum_q a_q bhat_q(x),

@@ -2,7 +2,7 @@
 
 The compute lives in libgp2s.so (HIP kernels behind the C ABI of include/gp2s.h);
 this package only marshals arguments. `GP2SLML` exposes the log marginal
-likelihood (Sec. 2) as a differentiable torch function of the kernel
+likelihood (Sec. 3) as a differentiable torch function of the kernel
 hyperparameters (r, bump weights, noise variance).
 """
 from __future__ import annotations
@@ -52,16 +52,21 @@ def _autograd_function():
                 m.free()
             ctx.P = int(weights.shape[0])
             ctx.report = rep.as_dict()
-            return torch.tensor(rep.lml, dtype=torch.float64)
+            # each hyperparameter's gradient goes back on that input's device and dtype
+            ctx.like = [(v.device, v.dtype) if torch.is_tensor(v) else (None, None)
+                        for v in (radius, weights, noise_var)]
+            dev = weights.device if torch.is_tensor(weights) else None
+            return torch.tensor(rep.lml, dtype=torch.float64, device=dev)
 
         @staticmethod
         def backward(ctx, g):
             if ctx.grad is None:
                 return (None,) * 9
-            G = ctx.grad * g.detach().cpu()
+            G = ctx.grad * g.detach().to("cpu", torch.float64)
             P = ctx.P
-            return (None, None, G[0].reshape(()), G[1:P + 1].clone(), G[P + 1].reshape(()), None, None, None,
-                    None)
+            parts = [G[0].reshape(()), G[1:P + 1].clone(), G[P + 1].reshape(())]
+            out = [t.to(device=d, dtype=dt) if d is not None else t for t, (d, dt) in zip(parts, ctx.like)]
+            return (None, None, out[0], out[1], out[2], None, None, None, None)
 
     return GP2SLML
 

@@ -634,7 +634,7 @@ struct ProbeResult {
   bool converged = false;
 };
 
-// Probe solves K q_s = L z_s (Sec. 3.5; App. B.6 "LOGDET"; L = D^1/2 for the diagonal
+// Probe solves K q_s = L z_s (Sec. 4.6; App. B.6 "LOGDET"; L = D^1/2 for the diagonal
 // preconditioner, the blockwise Cholesky factor for the block one): queues the probe
 // signs and right-hand sides on the second stream and begins the block solve there.
 // Wsol (block preconditioner, gradient only) receives w_s = L^-T z_s = M^-1 L z_s, the

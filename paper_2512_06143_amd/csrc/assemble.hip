@@ -1,9 +1,9 @@
 // Covariance assembly: pair culling, kernel evaluation and stream compaction into CSR.
 //
 // K_ij = g_i g_j W(||x_i - x_j|| / r) + sigma_n^2 [i == j], W a Wendland member for
-// rho < 1: the C^2 (1 - rho)^4 (4 rho + 1) or Eq. wendland's C^6 (Sec. 3.1 product
-// construction; Sec. 3.3 bump mask g). The paper computes dense block pairs and keeps the non-zeros
-// (Sec. 3.5, App. B.7); here only candidates from the 3^d neighbouring bins are
+// rho < 1: the C^2 (1 - rho)^4 (4 rho + 1) or Eq. wendland's C^6 (Sec. 4.1 product
+// construction; Sec. 4.3 bump mask g). The paper computes dense block pairs and keeps the non-zeros
+// (Sec. 4.6, App. B.7); here only candidates from the 3^d neighbouring bins are
 // tested, and a pair is stored when ||x_i - x_j|| < r and both points lie inside
 // some bump (the diagonal always).
 //
@@ -13,9 +13,10 @@
 // so each row is written as one contiguous, ascending, coalesced run. The count
 // pass and the fill pass execute the same candidate sequence and the same test.
 //
-// Float32 path: the support test uses float32 distances. Entry values use the
-// float64 squared distance (exact for float32 coordinates) to form t = 1 - rho^2
-// without cancellation, then 1 - rho = t / (1 + rho) and the polynomial in float32.
+// Float32 path: the support test uses float32 distances. Entry values are evaluated in
+// float64 from the float32 coordinates and g (t = 1 - rho^2 from the exact squared
+// distance, 1 - rho = t / (1 + rho), the polynomial) and rounded once to float32, so
+// the stored matrix differs from K by at most half an ulp per entry.
 //
 // General kernel (Eq. wendconv, axis radii, length-scale field l): the same sweep with
 // the per-axis scaled distance tested against m_ij = (l_i^2 + l_j^2) / 2 (cells are
@@ -41,10 +42,10 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs a, int64_t nbl
   bool in_i;
   if (F32) {
     pi32 = a.pts32[row];
-    in_i = pi32.w >= 0.0f;
+    in_i = pt_in(pi32.w);
   } else {
     pi64 = a.pts64[row];
-    in_i = pi64.w >= 0.0;
+    in_i = pt_in(pi64.w);
   }
   const int64_t base = FILL ? row_ptr[row] : 0;
   const int64_t end = FILL ? row_ptr[row + 1] : 0;
@@ -95,12 +96,12 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs a, int64_t nbl
         double4 pj64;
         const double lj = (a.kg.lsq && ok) ? a.kg.lsq[j] : 1.0;
         if (F32) {
-          pj32 = ok ? a.pts32[j] : make_float4(0.f, 0.f, 0.f, -1.f);
-          pass = ok && (j == row || (pj32.w >= 0.0f && (gen ? gen_pass_f32<DIM>(pi32, pj32, a.kg, li, lj)
+          pj32 = ok ? a.pts32[j] : make_float4(0.f, 0.f, 0.f, pt_out_f32());
+          pass = ok && (j == row || (pt_in(pj32.w) && (gen ? gen_pass_f32<DIM>(pi32, pj32, a.kg, li, lj)
                                                             : sqdist_f32<DIM>(pi32, pj32) < a.r2f)));
         } else {
-          pj64 = ok ? a.pts64[j] : make_double4(0., 0., 0., -1.);
-          pass = ok && (j == row || (pj64.w >= 0.0 && (gen ? gen_pass_f64<DIM>(pi64, pj64, a.kg, li, lj)
+          pj64 = ok ? a.pts64[j] : make_double4(0., 0., 0., pt_out_f64());
+          pass = ok && (j == row || (pt_in(pj64.w) && (gen ? gen_pass_f64<DIM>(pi64, pj64, a.kg, li, lj)
                                                            : sqdist_f64<DIM>(pi64, pj64) < a.r2)));
         }
         const uint64_t m = __ballot(pass);

@@ -1,6 +1,6 @@
 // Gradient of the log marginal likelihood with respect to theta = (r, a_1..a_P, sigma_n^2).
 //
-// dLML/dtheta = 1/2 a^T dK a - 1/2 tr(K^-1 dK), a = K^-1 y (Sec. 2 log density); the
+// dLML/dtheta = 1/2 a^T dK a - 1/2 tr(K^-1 dK), a = K^-1 y (Sec. 3 log density); the
 // trace is estimated with the probe solutions q_s = K^-1 L z_s and w_s = L^-T z_s
 // (M = L L^T the preconditioner: L = D^1/2, w_s recomputed from the signs, or the
 // blockwise Cholesky factor, w_s read from memory) as (1/S) sum_s q_s^T dK w_s. With
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kBlock) void k_backward_rows(BackwardArgs b, double
           const double4 pj = b.pts64[j];
           double W, dW;
           w_dw_f64(pi64, pj, b.r2, b.inv_r2, inv_r, b.kern, W, dW);
-          const double gj = fmax(pj.w, 0.0);
+          const double gj = pt_g(pj.w);
           gW = gj * W;
           gWp = gj * dW;
         }

@@ -126,8 +126,8 @@ __global__ __launch_bounds__(kBlock) void k_bgather(const double* __restrict__ x
   x64[p * 3 + 2] = c2;
   const double gv = g64_user[u];
   const bool in = gam[u] != 0;
-  if (pts32) pts32[p] = make_float4((float)c0, (float)c1, (float)c2, in ? (float)gv : -1.0f);
-  if (pts64) pts64[p] = make_double4(c0, c1, c2, in ? gv : -1.0);
+  if (pts32) pts32[p] = make_float4((float)c0, (float)c1, (float)c2, in ? (float)gv : pt_out_f32());
+  if (pts64) pts64[p] = make_double4(c0, c1, c2, in ? gv : pt_out_f64());
   g64[p] = gv;
   binid[p] = bin_of[u];
   inst_of_row[p] = find_inst(g.row_start, g.M, u);
@@ -151,14 +151,6 @@ __device__ inline double bsq64(const double4& a, const double4& b) {
   const double dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
   return __fma_rn(dz, dz, __fma_rn(dy, dy, __dmul_rn(dx, dx)));
 }
-__device__ inline float bentry32(const float4& pi, const float4& pj, double r2, double inv_r2, int kern) {
-  const double dx = (double)pi.x - (double)pj.x, dy = (double)pi.y - (double)pj.y, dz = (double)pi.z - (double)pj.z;
-  const double d2 = dx * dx + dy * dy + dz * dz;
-  const float t = fmaxf((float)((r2 - d2) * inv_r2), 0.0f);
-  const float rho = __builtin_amdgcn_sqrtf((float)(d2 * inv_r2));
-  const float om = t * __builtin_amdgcn_rcpf(1.0f + rho);
-  return pi.w * pj.w * wendland_w<float>(kern, rho, om);
-}
 __device__ inline double bentry64(const double4& pi, const double4& pj, double r2, double inv_r2, int kern) {
   const double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
   const double d2 = dx * dx + dy * dy + dz * dz;
@@ -166,6 +158,10 @@ __device__ inline double bentry64(const double4& pi, const double4& pj, double r
   const double rho = sqrt(d2 * inv_r2);
   const double om = t / (1.0 + rho);
   return pi.w * pj.w * wendland_w<double>(kern, rho, om);
+}
+// Float32-stored value: float64 evaluation, one rounding (see entry_f32).
+__device__ inline float bentry32(const float4& pi, const float4& pj, double r2, double inv_r2, int kern) {
+  return (float)bentry64(make_double4(pi.x, pi.y, pi.z, pi.w), make_double4(pj.x, pj.y, pj.z, pj.w), r2, inv_r2, kern);
 }
 
 __device__ inline uint32_t blane_prefix(uint64_t m) {
@@ -190,10 +186,10 @@ __global__ __launch_bounds__(kBlock) void k_bassemble(BAsm a, int64_t nblocks_pa
   bool in_i;
   if (F32) {
     pi32 = a.pts32[row];
-    in_i = pi32.w >= 0.0f;
+    in_i = pt_in(pi32.w);
   } else {
     pi64 = a.pts64[row];
-    in_i = pi64.w >= 0.0;
+    in_i = pt_in(pi64.w);
   }
   const float r2f = (float)I.r2;
   const int64_t base = FILL ? row_ptr[row] : 0;
@@ -241,11 +237,11 @@ __global__ __launch_bounds__(kBlock) void k_bassemble(BAsm a, int64_t nblocks_pa
         float4 pj32;
         double4 pj64;
         if (F32) {
-          pj32 = ok ? a.pts32[j] : make_float4(0.f, 0.f, 0.f, -1.f);
-          pass = ok && (j == row || (pj32.w >= 0.0f && bsq32(pi32, pj32) < r2f));
+          pj32 = ok ? a.pts32[j] : make_float4(0.f, 0.f, 0.f, pt_out_f32());
+          pass = ok && (j == row || (pt_in(pj32.w) && bsq32(pi32, pj32) < r2f));
         } else {
-          pj64 = ok ? a.pts64[j] : make_double4(0., 0., 0., -1.);
-          pass = ok && (j == row || (pj64.w >= 0.0 && bsq64(pi64, pj64) < I.r2));
+          pj64 = ok ? a.pts64[j] : make_double4(0., 0., 0., pt_out_f64());
+          pass = ok && (j == row || (pt_in(pj64.w) && bsq64(pi64, pj64) < I.r2));
         }
         const uint64_t mk = __ballot(pass);
         const int64_t pos = base + cnt + blane_prefix(mk);
@@ -1020,7 +1016,7 @@ __global__ __launch_bounds__(kBlock) void k_bbackward_rows(BBackward b, double* 
           const double rho = sqrt(d2 * I.inv_r2);
           const double om = t / (1.0 + rho);
           wendland_w_dr<double>(I.kern, rho, om, inv_r, W, dW);
-          gj = fmax(pj.w, 0.0);
+          gj = pt_g(pj.w);
         }
         gW = gj * W;
         gWp = gj * dW;

@@ -1,4 +1,4 @@
-// Far-field bump kernel (Sec. 3.3, Eq. bump_kernel, core kernel 1):
+// Far-field bump kernel (Sec. 4.3, Eq. bump_kernel, core kernel 1):
 //
 //   K = K_loc + G G^T,  K_loc = W(||x_i - x_j|| / r) + sigma_n^2 I (sparse, radius-local,
 //   no bump mask),  G[i][u] = g_u(x_i) = sum over the bumps p of group u of a_p bhat_p(x_i).

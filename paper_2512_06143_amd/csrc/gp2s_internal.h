@@ -18,6 +18,18 @@ constexpr int kMaxBumps = 256;
 constexpr int kReduceBlocks = 4096;  // max workgroups of the reduction-carrying kernels
 constexpr int kDotBlocks = 1024;     // workgroups of the block-preconditioned CG update (fewer partials per finalize)
 constexpr int kBJ = 64;             // rows per block of the block-Jacobi preconditioner
+
+// Point records (float4 / double4 of x, y, z and w) carry the bump mask g in w for a
+// point strictly inside some bump, and a quiet NaN for a point outside every bump.
+// The flag is therefore independent of the sign and value of g: amplitudes of any
+// sign, and g = 0 inside a bump, keep the point in the stored pattern. Outside
+// points never enter an entry value (every use tests the flag first).
+__host__ __device__ inline float pt_out_f32() { return __builtin_nanf(""); }
+__host__ __device__ inline double pt_out_f64() { return __builtin_nan(""); }
+__device__ inline bool pt_in(float w) { return !__builtin_isnan(w); }
+__device__ inline bool pt_in(double w) { return !__builtin_isnan(w); }
+// g of a point record, 0 outside every bump.
+__device__ inline double pt_g(double w) { return pt_in(w) ? w : 0.0; }
 constexpr int kMaxGroups = 16;      // bump groups U of the far-field kernel
 
 // Uniform grid of cubic bins with side h >= r (slightly enlarged so that rounding

@@ -23,7 +23,7 @@ __device__ inline int64_t bin_index(const double (&xi)[3], const GridDev& g) {
 }
 
 // g(x) = sum_k a_k exp(1 - 1/(1 - s_k)), s_k = ||x - c_k||^2 / w^2, over the bumps with
-// s_k < 1 (Sec. 3.3, Eq. bump with shape parameter 1); `inside` marks a point strictly
+// s_k < 1 (Sec. 4.3, Eq. bump with shape parameter 1); `inside` marks a point strictly
 // inside at least one bump.
 __device__ inline void bump_mask(const double (&xi)[3], int dim, const double* __restrict__ centers,
                                  const double* __restrict__ weights, int P, double bump_w2, double& gsum,
@@ -95,7 +95,7 @@ __device__ inline double sqdist_f64(const double4& a, const double4& b) {
   return d2;
 }
 
-// Wendland members (Sec. 3.1): kern 0 is the C^2 member (1 - rho)^4 (4 rho + 1), the
+// Wendland members (Sec. 4.1): kern 0 is the C^2 member (1 - rho)^4 (4 rho + 1), the
 // workloads' "small variation"; kern 1 is the C^6 member of Eq. wendland as printed,
 // (1 - rho)^8 (32 rho^3 + 25 rho^2 + 8 rho + 1). om = 1 - rho is passed in, formed
 // from 1 - rho^2 without cancellation near the support boundary.
@@ -119,19 +119,6 @@ __device__ inline void wendland_w_dr(int kern, T rho, T om, T inv_r, T& W, T& dW
   }
 }
 
-// Float32 entry value for a surviving off-diagonal pair.
-__device__ inline float entry_f32(const float4& pi, const float4& pj, double r2, double inv_r2, int kern) {
-  double dx = (double)pi.x - (double)pj.x;
-  double dy = (double)pi.y - (double)pj.y;
-  double dz = (double)pi.z - (double)pj.z;
-  double d2 = dx * dx + dy * dy + dz * dz;
-  float t = (float)((r2 - d2) * inv_r2);          // 1 - rho^2, accurate near rho -> 1
-  t = fmaxf(t, 0.0f);
-  float rho = __builtin_amdgcn_sqrtf((float)(d2 * inv_r2));
-  float om = t * __builtin_amdgcn_rcpf(1.0f + rho);  // 1 - rho
-  return pi.w * pj.w * wendland_w<float>(kern, rho, om);
-}
-
 __device__ inline double entry_f64(const double4& pi, const double4& pj, double r2, double inv_r2, int kern) {
   double dx = pi.x - pj.x, dy = pi.y - pj.y, dz = pi.z - pj.z;
   double d2 = dx * dx + dy * dy + dz * dz;
@@ -139,6 +126,19 @@ __device__ inline double entry_f64(const double4& pi, const double4& pj, double 
   double rho = sqrt(d2 * inv_r2);
   double om = t / (1.0 + rho);
   return pi.w * pj.w * wendland_w<double>(kern, rho, om);
+}
+
+__device__ inline double4 promote(const float4& p) { return make_double4(p.x, p.y, p.z, p.w); }
+
+// Float32-stored entry value of a surviving off-diagonal pair: the float64 evaluation
+// from the float32 coordinates and g, rounded once. Rounding after each float32 step
+// (square root, reciprocal, polynomial) left entry errors of ~14 ulp; summed over the
+// thousands of entries of a row inside dense clusters they moved the smallest
+// eigenvalue of the stored matrix below zero (measured on the densest regions of a
+// 10 M-point clustered cloud: -7.5e-5 against sigma_n^2 = 1e-4), while one rounding
+// per entry kept it at 0.91 sigma_n^2. The support test stays in float32.
+__device__ inline float entry_f32(const float4& pi, const float4& pj, double r2, double inv_r2, int kern) {
+  return (float)entry_f64(promote(pi), promote(pj), r2, inv_r2, kern);
 }
 
 // ---- general kernel (Eq. wendconv with axis radii and the length-scale field) ------
@@ -191,16 +191,6 @@ __device__ inline void gen_geom(double ax, double ay, double az, double bx, doub
 }
 
 template <int DIM>
-__device__ inline float gen_entry_f32(const float4& pi, const float4& pj, const KernGeom& kg, double li, double lj,
-                                      int kern) {
-  double ds[3], m, t, Q, p;
-  gen_geom<DIM>(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, kg, li, lj, ds, m, t, Q, p);
-  const float rho = __builtin_amdgcn_sqrtf((float)Q);
-  const float om = (float)t * __builtin_amdgcn_rcpf(1.0f + rho);
-  return pi.w * pj.w * (float)p * wendland_w<float>(kern, rho, om);
-}
-
-template <int DIM>
 __device__ inline double gen_entry_f64(const double4& pi, const double4& pj, const KernGeom& kg, double li, double lj,
                                        int kern) {
   double ds[3], m, t, Q, p;
@@ -208,6 +198,14 @@ __device__ inline double gen_entry_f64(const double4& pi, const double4& pj, con
   const double rho = sqrt(Q);
   const double om = t / (1.0 + rho);
   return pi.w * pj.w * p * wendland_w<double>(kern, rho, om);
+}
+
+// Float32-stored value of the general kernel: float64 evaluation, one rounding (as
+// entry_f32).
+template <int DIM>
+__device__ inline float gen_entry_f32(const float4& pi, const float4& pj, const KernGeom& kg, double li, double lj,
+                                      int kern) {
+  return (float)gen_entry_f64<DIM>(promote(pi), promote(pj), kg, li, lj, kern);
 }
 
 // D(rho) = -W'(rho) / rho: 20 (1 - rho)^3 (C^2), 22 (1 - rho)^7 (16 rho^2 + 7 rho + 1) (C^6).

@@ -1,4 +1,4 @@
-// Posterior mean and variance of the latent function at test points (Sec. 2,
+// Posterior mean and variance of the latent function at test points (Sec. 3,
 // Eq. posterior, zero prior mean):
 //
 //   mean_t = k(X, x*_t)^T a,                 a = K^{-1} y (kept from training, App. B.7)
@@ -47,8 +47,8 @@ __global__ __launch_bounds__(kBlock) void k_test_prologue(const double* __restri
     inside = true;
   }
   if (bad) inside = false;
-  if (pts32) pts32[i] = make_float4((float)xi[0], (float)xi[1], (float)xi[2], inside ? (float)gs : -1.0f);
-  if (pts64) pts64[i] = make_double4(xi[0], xi[1], xi[2], inside ? gs : -1.0);
+  if (pts32) pts32[i] = make_float4((float)xi[0], (float)xi[1], (float)xi[2], inside ? (float)gs : pt_out_f32());
+  if (pts64) pts64[i] = make_double4(xi[0], xi[1], xi[2], inside ? gs : pt_out_f64());
   g64[i] = inside ? gs : 0.0;
   bin[i] = (int32_t)b;
 }
@@ -79,10 +79,10 @@ __global__ __launch_bounds__(kBlock) void k_cross(CrossArgs a, int64_t nblocks_p
   bool in_i;
   if (F32) {
     pi32 = a.test32[row];
-    in_i = pi32.w >= 0.0f;
+    in_i = pt_in(pi32.w);
   } else {
     pi64 = a.test64[row];
-    in_i = pi64.w >= 0.0;
+    in_i = pt_in(pi64.w);
   }
   if (!in_i) {
     if (!FILL && lane == 0) row_cnt[row] = 0;
@@ -115,12 +115,12 @@ __global__ __launch_bounds__(kBlock) void k_cross(CrossArgs a, int64_t nblocks_p
         double4 pj64;
         const double lj = (a.kg.lsq && ok) ? a.kg.lsq[j] : 1.0;
         if (F32) {
-          pj32 = ok ? a.pts32[j] : make_float4(0.f, 0.f, 0.f, -1.f);
-          pass = ok && pj32.w >= 0.0f &&
+          pj32 = ok ? a.pts32[j] : make_float4(0.f, 0.f, 0.f, pt_out_f32());
+          pass = ok && pt_in(pj32.w) &&
                  (gen ? gen_pass_f32<DIM>(pi32, pj32, a.kg, li, lj) : sqdist_f32<DIM>(pi32, pj32) < a.r2f);
         } else {
-          pj64 = ok ? a.pts64[j] : make_double4(0., 0., 0., -1.);
-          pass = ok && pj64.w >= 0.0 &&
+          pj64 = ok ? a.pts64[j] : make_double4(0., 0., 0., pt_out_f64());
+          pass = ok && pt_in(pj64.w) &&
                  (gen ? gen_pass_f64<DIM>(pi64, pj64, a.kg, li, lj) : sqdist_f64<DIM>(pi64, pj64) < a.r2);
         }
         const uint64_t m = __ballot(pass);

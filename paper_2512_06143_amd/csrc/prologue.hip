@@ -1,8 +1,8 @@
 // Per-point prologue and spatial binning (counting sort into a cell list).
 //
-// The paper evaluates every covariance entry in dense blocks (Sec. 3.5, App. B.7).
+// The paper evaluates every covariance entry in dense blocks (Sec. 4.6, App. B.7).
 // Here the support of the kernel is known before evaluation: W vanishes beyond r
-// (Sec. 3.1) and the bump mask vanishes outside every bump (Sec. 3.3). Points are
+// (Sec. 4.1) and the bump mask vanishes outside every bump (Sec. 4.3). Points are
 // therefore sorted into bins of side >= r so that each row only tests the points of
 // its 3^d neighbouring bins.
 #include "gp2s_internal.h"
@@ -61,7 +61,7 @@ hipError_t launch_bbox(const double* x, int64_t n, int dim, double* part, int32_
 
 // Bin index, bump mask g (float64) and support flag gamma of every point (user order).
 // g_i = sum_k a_k exp(1 - 1/(1 - s_ik)), s_ik = ||x_i - c_k||^2 / w^2, for s_ik < 1
-// (Sec. 3.3, Eq. bump with shape parameter 1; g a sum of P bumps). gamma_i marks a
+// (Sec. 4.3, Eq. bump with shape parameter 1; g a sum of P bumps). gamma_i marks a
 // point strictly inside at least one bump; the pattern uses gamma, not g != 0.
 __global__ __launch_bounds__(kBlock) void k_prologue(const double* __restrict__ x, int64_t n,
                                                      GridDev g, const double* __restrict__ centers,
@@ -160,8 +160,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_points(
   }
   double gv = g64_user[u];
   bool in = gam[u] != 0;
-  if (pts32) pts32[p] = make_float4((float)c[0], (float)c[1], (float)c[2], in ? (float)gv : -1.0f);
-  if (pts64) pts64[p] = make_double4(c[0], c[1], c[2], in ? gv : -1.0);
+  if (pts32) pts32[p] = make_float4((float)c[0], (float)c[1], (float)c[2], in ? (float)gv : pt_out_f32());
+  if (pts64) pts64[p] = make_double4(c[0], c[1], c[2], in ? gv : pt_out_f64());
   g64[p] = gv;
   binid[p] = bin_of[u];
 }
@@ -182,8 +182,8 @@ __global__ __launch_bounds__(kBlock) void k_refresh_g(int64_t n, int dim, const 
   bool inside = false;
   bump_mask(xi, dim, centers, weights, P, bump_w2, gs, inside);
   g64[p] = inside ? gs : 0.0;
-  if (pts32) pts32[p].w = inside ? (float)gs : -1.0f;
-  if (pts64) pts64[p].w = inside ? gs : -1.0;
+  if (pts32) pts32[p].w = inside ? (float)gs : pt_out_f32();
+  if (pts64) pts64[p].w = inside ? gs : pt_out_f64();
 }
 
 hipError_t launch_refresh_g(int64_t n, int dim, const double* x64, const double* centers, const double* weights,

@@ -1,7 +1,7 @@
 // Lanczos quadrature of z^T ln(Khat) z from the preconditioned-CG coefficients.
 //
 // The paper computes ln|K| on the host without naming the method ("LOGDET",
-// Sec. 3.5, App. B.6). Here ln|K| = ln|M| + tr ln Khat, Khat = L^-1 K L^-T with
+// Sec. 4.6, App. B.6). Here ln|K| = ln|M| + tr ln Khat, Khat = L^-1 K L^-T with
 // M = L L^T the preconditioner (L = D^1/2, or the blockwise Cholesky factor), and
 // tr ln Khat is estimated with Rademacher probes. Preconditioned CG on K q = L z is
 // CG on Khat with initial residual z, i.e. Lanczos from z/||z||;

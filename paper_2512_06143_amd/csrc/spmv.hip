@@ -2,7 +2,7 @@
 // nnz-balanced row blocks streamed as 16-byte quads, for matrix handles; k_spmv, a
 // group of G lanes per row, for other CSRs) and blocks of up to 64 right-hand sides
 // (several variants, picked per matrix by timing). These drive the solve K a = y and
-// the probe solves of the log-determinant (Sec. 3.5; App. B.6 "MINRES", "LOGDET").
+// the probe solves of the log-determinant (Sec. 4.6; App. B.6 "MINRES", "LOGDET").
 // Stored values (float32 or float64) multiply the vectors and accumulate in float64.
 //
 // The single-RHS products stream the CSR from HBM; the block products are bound by the

@@ -1,4 +1,4 @@
-"""Block Metropolis-Hastings training of the kernel hyperparameters (Sec. 3.5; App. D)
+"""Block Metropolis-Hastings training of the kernel hyperparameters (Sec. 4.6; App. D)
 on the library's LML.
 
 theta = (r | r_1..r_d, a_1..a_P, [c_1..c_P], sigma_n^2) in the gradient order of the
@@ -9,7 +9,7 @@ its own block, as App. D separates the core-kernel block from the bump blocks); 
 block move draws a normal random-walk proposal for its components (App. D keeps
 proposals normal), a flat prior restricts theta to bounds (App. D), and the move is
 accepted when log u < LML(theta') - LML(theta). Each block costs one LML evaluation
-(Sec. 3.5).
+(Sec. 4.6).
 
 The LML is the library's estimate with a fixed probe seed, so every evaluation uses
 the same probes (common random numbers across proposals). Moves that keep the

@@ -1,4 +1,4 @@
-"""Posterior mean and variance at test points (Sec. 2, Eq. posterior) through the C ABI,
+"""Posterior mean and variance at test points (Sec. 3, Eq. posterior) through the C ABI,
 against the dense oracle on the same training matrix.
 
 The oracle solves with the matrix the device stored (exported CSR, user order), so

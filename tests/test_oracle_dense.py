@@ -31,7 +31,7 @@ def test_bitwise_symmetric_and_psd():
 
 def test_rank_one_bump_mask():
     """With r far beyond the cloud, W ~ 1 and K - sigma^2 I ~ g g^T (rank 1), the
-    'box' structure of the product bump kernel (Sec. 3.3, App. C.1)."""
+    'box' structure of the product bump kernel (Sec. 4.3, App. C.1)."""
     p = _small(n=120, r=1e7, w=0.45)
     K = _K(p)
     g, _, _ = oracle.bump_values(p.x, p.centers, p.bump_width, p.weights)

@@ -78,3 +78,52 @@ def test_gradient_estimator_unbiased():
     _, sp = oracle.grad_same_probe(p.x, p.y, oracle.rademacher_probes(0, S, p.n), p.radius,
                                    p.bump_width, p.centers, p.weights, p.noise_var)
     np.testing.assert_allclose(sp["fit"], parts["fit"], rtol=1e-12)
+
+
+def test_lml_same_probe_diagonal_case_is_exact():
+    """Diagonal K (radius far below the point spacing): Khat = I, so the probe
+    log-determinant is ln|K| for any probes and the same-probe LML equals the Gaussian
+    log density, here taken from scipy's multivariate normal (an independent library
+    routine), for the diagonal and the block preconditioner alike."""
+    from scipy.stats import multivariate_normal
+    p = _problem(n=120, r=1e-6)
+    K = oracle.covariance_dense(p.x, p.radius, p.bump_width, p.centers, p.weights, p.noise_var)
+    ref = multivariate_normal(mean=np.zeros(p.n), cov=K).logpdf(p.y)
+    for seed, S in ((1, 1), (7, 5)):
+        Z = oracle.rademacher_probes(seed, S, p.n)
+        for blocks in (None, oracle.block_partition(np.arange(p.n), 16)):
+            v, parts = oracle.lml_same_probe(K, p.y, Z, blocks)
+            assert v == pytest.approx(ref, rel=1e-12, abs=1e-9)
+            assert parts["gamma"] == pytest.approx(parts["logdet"], rel=1e-12)
+
+
+def test_lml_same_probe_one_block_is_exact():
+    """With one block holding every point, M = K and Khat = I: every probe set gives
+    Gamma = ln|K| and the same-probe LML is the exact Gaussian log density of a
+    correlated K (scipy's multivariate normal as the independent value)."""
+    from scipy.stats import multivariate_normal
+    p = _problem(n=90, r=0.3)
+    K = oracle.covariance_dense(p.x, p.radius, p.bump_width, p.centers, p.weights, p.noise_var)
+    assert np.count_nonzero(K - np.diag(np.diag(K))) > 10 * p.n
+    ref = multivariate_normal(mean=np.zeros(p.n), cov=K).logpdf(p.y)
+    one = oracle.block_partition(np.arange(p.n), p.n)
+    for seed in (0, 3):
+        v, parts = oracle.lml_same_probe(K, p.y, oracle.rademacher_probes(seed, 4, p.n), one)
+        assert v == pytest.approx(ref, rel=1e-11)
+
+
+def test_lml_same_probe_unbiased():
+    """Over independent probe sets, the same-probe LML (Jacobi preconditioner) scatters
+    around the exact LML with standard deviation sd(Gamma)/2."""
+    p = _problem(n=200)
+    K = oracle.covariance_dense(p.x, p.radius, p.bump_width, p.centers, p.weights, p.noise_var)
+    exact = oracle.lml_dense(K, p.y).lml
+    D = np.diag(K)
+    lam, V = np.linalg.eigh(K / np.sqrt(np.outer(D, D)))
+    A = (V * np.log(lam)) @ V.T
+    S, reps = 8, 150
+    sd = 0.5 * np.sqrt(oracle.hutchinson_variance(A, S))
+    vals = np.array([oracle.lml_same_probe(K, p.y, oracle.rademacher_probes(seed, S, p.n))[0]
+                     for seed in range(reps)])
+    assert abs(vals.mean() - exact) < 4 * sd / np.sqrt(reps)
+    assert 0.7 < vals.std() / sd < 1.3

@@ -5,11 +5,13 @@ import pytest
 
 import oracle
 import oracle.dense
+import oracle.estimators
 import oracle.kernel
 import oracle.probes
 import test_oracle_dense as TD
 import test_oracle_estimators as TE
 import test_oracle_kernel as TK
+import test_oracle_sparse as TS
 
 
 def _fails(fn, *args):
@@ -93,3 +95,39 @@ def test_wrong_splitmix_caught(monkeypatch):
             return z ^ (z >> np.uint64(31))
     monkeypatch.setattr(oracle, "splitmix64", bad)
     _fails(TE.test_splitmix64_published_outputs)
+
+
+def test_wrong_same_probe_lml_caught(monkeypatch):
+    orig = oracle.estimators.lml_same_probe
+
+    def bad_sign(K, y, Z, blocks=None):  # +1/2 Gamma instead of -1/2 Gamma
+        v, parts = orig(K, y, Z, blocks)
+        return v + parts["gamma"], parts
+
+    def bad_const(K, y, Z, blocks=None):  # dropped -N/2 ln(2 pi)
+        v, parts = orig(K, y, Z, blocks)
+        return v + 0.5 * len(y) * np.log(2 * np.pi), parts
+
+    def bad_fit(K, y, Z, blocks=None):  # y^T a without the factor 1/2
+        v, parts = orig(K, y, Z, blocks)
+        return v - 0.5 * parts["yTa"], parts
+
+    for bad in (bad_sign, bad_const, bad_fit):
+        monkeypatch.setattr(oracle, "lml_same_probe", bad)
+        _fails(TE.test_lml_same_probe_diagonal_case_is_exact)
+        _fails(TE.test_lml_same_probe_one_block_is_exact)
+
+
+def test_wrong_lanczos_offdiagonal_caught(monkeypatch):
+    import scipy.linalg
+
+    def bad(alphas, betas):  # beta_j / alpha_j instead of sqrt(beta_j) / alpha_j
+        al = np.asarray(alphas, dtype=np.float64)
+        be = np.asarray(betas, dtype=np.float64)
+        m = al.shape[0]
+        d = 1.0 / al
+        d[1:] += be[:m - 1] / al[:m - 1]
+        theta, V = scipy.linalg.eigh_tridiagonal(d, be[:m - 1] / al[:m - 1])
+        return float(np.sum(V[0] ** 2 * np.log(theta)))
+    monkeypatch.setattr(oracle, "lanczos_logquad", bad)
+    _fails(TS.test_lanczos_quadrature_closed_forms)

@@ -1,4 +1,4 @@
-"""Pins of the posterior oracle (Sec. 2, Eq. posterior) against facts it must satisfy:
+"""Pins of the posterior oracle (Sec. 3, Eq. posterior) against facts it must satisfy:
 
 * the Gaussian conditioning identity through the inverse of the joint covariance of
   (y, f*), built by the training-matrix code on the augmented point set;
