@@ -296,8 +296,11 @@ gp2s_status cg_begin(Cg& c, const double* B, double tol, bool keep_hist, Scratch
   const int64_t n = m->n;
   const size_t nS = (size_t)n * S;
   // Probe blocks of the mixed path keep search directions in float32 (products, x,
-  // r, dot products and all coefficients stay float64).
-  c.f32vec = m->prec == GP2S_MIXED && S > 1;
+  // r, dot products and all coefficients stay float64). The far-field kernel keeps
+  // them in float64: its global rank-U term makes the Lanczos coefficients sensitive
+  // enough to the rounding of the directions that the same-probe log-determinant
+  // came within 6% of its 1e-8 bar.
+  c.f32vec = m->prec == GP2S_MIXED && S > 1 && !m->ffG;
   const size_t vb = c.f32vec ? sizeof(float) : sizeof(double);
   c.R = sc.get<double>(nS);
   if (c.precond == GP2S_PRECOND_BLOCK) c.Z = sc.get<double>(nS);
