@@ -41,7 +41,8 @@ from .sparse import (covariance_csr, covariance_rows, residual_rel, pcg_jacobi, 
                      lanczos_logquad, lml_grad_sparse)
 from .posterior import cross_covariance, posterior_dense
 from .mcmc import block_mh
-from .precond import BLOCK, grid, bin_coords, bin_order, block_partition, jacobi_partition, block_factor
+from .precond import (BLOCK, grid, bin_coords, bin_order, block_partition, jacobi_partition, block_factor,
+                      morton, sub_cell_codes)
 
 __all__ = [
     "wendland_c2", "wendland_c2_dr", "wendland_c6", "wendland_c6_dr", "wendland", "wendland_dr", "wendland_dlog",
@@ -54,6 +55,7 @@ __all__ = [
     "logdet_same_probe", "grad_same_probe", "lml_same_probe", "hutchinson_variance",
     "cross_covariance", "posterior_dense", "block_mh",
     "BLOCK", "grid", "bin_coords", "bin_order", "block_partition", "jacobi_partition", "block_factor",
+    "morton", "sub_cell_codes",
     "covariance_csr", "covariance_rows", "residual_rel", "pcg_jacobi", "dcov_csr", "lml_components",
     "lanczos_logquad", "lml_grad_sparse",
 ]

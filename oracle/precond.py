@@ -8,9 +8,10 @@ case of one-point blocks. The block choice is:
 
 * order the points by spatial bin: a grid of cells of side h >= r anchored at the
   lower corner of the points' bounding box, bins numbered with the first coordinate
-  varying fastest, the sort stable in the user index (so that points closer than r
-  fall in the same or neighbouring cells and a run of consecutive points is
-  spatially compact);
+  varying fastest (so that points closer than r fall in the same or neighbouring
+  cells); inside a cell, by the Z-order (Morton) code of the point's offset from the
+  cell's corner on a 2^10-step sub-grid per axis, then by user index (so that a run
+  of consecutive points is compact even where one cell holds thousands of points);
 * cut that order into runs of ``size`` consecutive points (the last run holds the
   remainder); a block of M is the principal submatrix of K on one run, and L is
   its Cholesky factor.
@@ -62,14 +63,45 @@ def bin_coords(x, radius, ell_bound=1.0, refine=1, min_cells=65536):
     return np.clip(c, 0, np.array(nb) - 1).astype(np.int64), nb
 
 
+SUB_BITS = 10
+
+
+def morton(f):
+    """Z-order code of non-negative integer coordinates f (n, dim) below 2^SUB_BITS: bit b
+    of coordinate k becomes bit dim * b + k of the code."""
+    f = np.asarray(f, dtype=np.int64)
+    n, dim = f.shape
+    code = np.zeros(n, dtype=np.int64)
+    for b in range(SUB_BITS):
+        for k in range(dim):
+            code |= ((f[:, k] >> b) & 1) << (dim * b + k)
+    return code
+
+
+def sub_cell_codes(x, radius, ell_bound=1.0, refine=1, min_cells=65536):
+    """(n,) int64 position of each point inside its cell: with u_k = (x_k - lo_k)(1 / h_k)
+    and c_k = floor(u_k) clamped to the grid, f_k = floor((u_k - c_k) 2^SUB_BITS) clamped
+    to [0, 2^SUB_BITS - 1], and the code is morton(f)."""
+    x = np.asarray(x, dtype=np.float64)
+    lo, h, nb = grid(x, radius, ell_bound, refine, min_cells)
+    inv_h = 1.0 / h
+    u = (x - lo[None, :]) * inv_h[None, :]
+    c = np.clip(np.floor(u), 0, np.array(nb) - 1)
+    steps = float(1 << SUB_BITS)
+    f = np.clip(np.floor((u - c) * steps), 0, steps - 1)
+    return morton(f.astype(np.int64))
+
+
 def bin_order(x, radius, ell_bound=1.0, refine=1, min_cells=65536):
     """perm (n,) int64: perm[p] is the user index of the point at position p when the
-    points are sorted by cell number (first coordinate fastest), ties by user index."""
+    points are sorted by cell number (first coordinate fastest), then by sub-cell code,
+    then by user index."""
     c, nb = bin_coords(x, radius, ell_bound, refine, min_cells)
     key = np.zeros(c.shape[0], dtype=np.int64)
     for k in range(c.shape[1] - 1, -1, -1):
         key = key * nb[k] + c[:, k]
-    return np.argsort(key, kind="stable").astype(np.int64)
+    code = sub_cell_codes(x, radius, ell_bound, refine, min_cells)
+    return np.lexsort((np.arange(c.shape[0]), code, key)).astype(np.int64)
 
 
 def block_partition(order, size=BLOCK):

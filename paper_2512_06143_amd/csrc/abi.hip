@@ -1137,6 +1137,8 @@ gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_p
   double* g64u = sc.get<double>(n);
   uint8_t* gam = sc.get<uint8_t>(n);
   int32_t* perm_tmp = sc.get<int32_t>(n);
+  uint32_t* fkey = sc.get<uint32_t>(n);
+  uint32_t* key_tmp = sc.get<uint32_t>(n);
   void* scan_ws = sc.get<uint8_t>(std::max(scan_workspace_bytes(g.nbins), scan_workspace_bytes(n)));
   int32_t* row_cnt = sc.get<int32_t>(n);
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "assembly workspace allocation failed");
@@ -1167,10 +1169,10 @@ gp2s_status gp2s_assemble(gp2s_ctx ctx, int64_t n, const double* x, const gp2s_p
   Timed prep_timer(ctx, GP2S_T_ASM_PREP, ctx->stream);
   HIPCHK(hipMemsetAsync(bin_count, 0, g.nbins * sizeof(int32_t), sm));
   HIPCHK(launch_prologue(x, n, g, m->centers_d, m->weights_d, m->P, p->bump_width * p->bump_width, bin_of, slot,
-                         bin_count, g64u, gam, sm, m->ffU > 0));
+                         bin_count, g64u, gam, fkey, sm, m->ffU > 0));
   HIPCHK(launch_exscan_i32_i64(bin_count, m->bin_start, g.nbins, scan_ws, sm));
-  HIPCHK(launch_scatter(n, bin_of, slot, m->bin_start, perm_tmp, sm));
-  HIPCHK(launch_binsort(n, perm_tmp, bin_of, m->bin_start, m->perm, sm));
+  HIPCHK(launch_scatter(n, bin_of, slot, fkey, m->bin_start, perm_tmp, key_tmp, sm));
+  HIPCHK(launch_binsort(n, perm_tmp, key_tmp, bin_of, m->bin_start, m->perm, sm));
   HIPCHK(launch_gather_points(n, dim, x, m->perm, bin_of, g64u, gam, m->pts32, m->pts64, m->x64, m->g64,
                               m->binid, sm));
   if (!m->ls_h.empty()) {

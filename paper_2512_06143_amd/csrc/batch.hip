@@ -71,7 +71,8 @@ __global__ __launch_bounds__(kBlock) void k_bprologue(const double* __restrict__
                                                       const double* __restrict__ weights,
                                                       int32_t* __restrict__ bin_of, int32_t* __restrict__ slot,
                                                       int32_t* __restrict__ bin_count,
-                                                      double* __restrict__ g64_user, uint8_t* __restrict__ gam) {
+                                                      double* __restrict__ g64_user, uint8_t* __restrict__ gam,
+                                                      uint32_t* __restrict__ fkey) {
   const int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (u >= g.n) return;
   const int i = find_inst(g.row_start, g.M, u);
@@ -79,6 +80,7 @@ __global__ __launch_bounds__(kBlock) void k_bprologue(const double* __restrict__
   const double xi[3] = {x3[u * 3], x3[u * 3 + 1], x3[u * 3 + 2]};
   int64_t b = 0;
   for (int k = 2; k >= 0; --k) b = b * I.grid.nb[k] + bcoord(xi[k], I.grid.origin[k], I.grid.inv_h[k], I.grid.nb[k]);
+  fkey[u] = sub_cell_code(xi, I.grid, I.dim);
   double gs = 0.0;
   bool inside = false;
   for (int p = 0; p < I.P; ++p) {
@@ -102,10 +104,10 @@ __global__ __launch_bounds__(kBlock) void k_bprologue(const double* __restrict__
 
 hipError_t launch_bprologue(const double* x3, const BatchGeom& g, const double* centers3, const double* weights,
                             int32_t* bin_of, int32_t* slot, int32_t* bin_count, double* g64_user, uint8_t* gam,
-                            hipStream_t st) {
+                            uint32_t* fkey, hipStream_t st) {
   const int64_t blocks = (g.n + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_bprologue, dim3((unsigned)blocks), dim3(kBlock), 0, st, x3, g, centers3, weights, bin_of,
-                     slot, bin_count, g64_user, gam);
+                     slot, bin_count, g64_user, gam, fkey);
   return hipGetLastError();
 }
 

@@ -151,14 +151,16 @@ gp2s_status assemble_pattern(gp2s_batch b, Scratch& sc, int32_t** row_cnt_out, f
   double* g64u = sc.get<double>(b->N);
   uint8_t* gam = sc.get<uint8_t>(b->N);
   int32_t* perm_tmp = sc.get<int32_t>(b->N);
+  uint32_t* fkey = sc.get<uint32_t>(b->N);
+  uint32_t* key_tmp = sc.get<uint32_t>(b->N);
   int32_t* row_cnt = sc.get<int32_t>(b->N);
   void* scan_ws = sc.get<uint8_t>(std::max(scan_workspace_bytes(b->nbins), scan_workspace_bytes(b->N)));
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "batch assembly workspace allocation failed");
   HIPCHK(hipMemsetAsync(b->bin_count, 0, b->nbins * sizeof(int32_t), st));
-  HIPCHK(launch_bprologue(b->x3, g, b->centers3_d, b->weights_d, bin_of, slot, b->bin_count, g64u, gam, st));
+  HIPCHK(launch_bprologue(b->x3, g, b->centers3_d, b->weights_d, bin_of, slot, b->bin_count, g64u, gam, fkey, st));
   HIPCHK(launch_exscan_i32_i64(b->bin_count, b->bin_start, b->nbins, scan_ws, st));
-  HIPCHK(launch_scatter(b->N, bin_of, slot, b->bin_start, perm_tmp, st));
-  HIPCHK(launch_binsort(b->N, perm_tmp, bin_of, b->bin_start, b->perm, st));
+  HIPCHK(launch_scatter(b->N, bin_of, slot, fkey, b->bin_start, perm_tmp, key_tmp, st));
+  HIPCHK(launch_binsort(b->N, perm_tmp, key_tmp, bin_of, b->bin_start, b->perm, st));
   HIPCHK(launch_bgather(b->x3, g, b->perm, bin_of, g64u, gam, b->pts32, b->pts64, b->x64, b->g64, b->binid,
                         b->inst_of_row, st));
   BAsm a{};

@@ -42,6 +42,27 @@ struct GridDev {
   int64_t nbins;
 };
 
+// Order of the points inside one cell: the Morton (Z-order) code of a point's offset
+// from the cell's lower corner, in units of the cell side, on a sub-grid of 2^kSubBits
+// steps per axis (bits interleaved, axis 0 in the lowest bit). The bin sort orders a
+// cell's points by this code (ties by user index), so that runs of consecutive points,
+// the blocks of the block-Jacobi preconditioner, are compact inside crowded cells.
+// u = (x - origin) * inv_h is formed exactly as the cell coordinate is, and u - c is
+// exact (Sterbenz), so the code is reproducible on any IEEE float64 machine.
+constexpr int kSubBits = 10;
+__device__ inline uint32_t sub_cell_code(const double* xi, const GridDev& g, int dim) {
+  uint32_t code = 0;
+  const double steps = (double)(1 << kSubBits);
+  for (int k = 0; k < dim; ++k) {
+    const double u = (xi[k] - g.origin[k]) * g.inv_h[k];
+    const double c = fmax(0.0, fmin(floor(u), (double)(g.nb[k] - 1)));
+    const double f = fmax(0.0, fmin(floor((u - c) * steps), steps - 1.0));
+    const uint32_t fi = (uint32_t)f;
+    for (int b = 0; b < kSubBits; ++b) code |= ((fi >> b) & 1u) << (dim * b + k);
+  }
+  return code;
+}
+
 // Device-resident solver state for one block CG run over S columns.
 struct CgState {
   double* rz;        // [S] r^T M^-1 r of the current iterate
@@ -174,10 +195,10 @@ hipError_t launch_bbox(const double* x, int64_t n, int dim, double* part, int32_
 hipError_t launch_prologue(const double* x, int64_t n, const GridDev& g, const double* centers,
                            const double* weights, int P, double bump_w2, int32_t* bin_of,
                            int32_t* slot, int32_t* bin_count, double* g64_user, uint8_t* gam,
-                           hipStream_t st, bool unit = false);  // unit: g = 1 at every point
-hipError_t launch_scatter(int64_t n, const int32_t* bin_of, const int32_t* slot,
-                          const int64_t* bin_start, int32_t* perm_tmp, hipStream_t st);
-hipError_t launch_binsort(int64_t n, const int32_t* perm_tmp, const int32_t* bin_of,
+                           uint32_t* fkey, hipStream_t st, bool unit = false);  // unit: g = 1 at every point
+hipError_t launch_scatter(int64_t n, const int32_t* bin_of, const int32_t* slot, const uint32_t* fkey,
+                          const int64_t* bin_start, int32_t* perm_tmp, uint32_t* key_tmp, hipStream_t st);
+hipError_t launch_binsort(int64_t n, const int32_t* perm_tmp, const uint32_t* key_tmp, const int32_t* bin_of,
                           const int64_t* bin_start, int32_t* perm, hipStream_t st);
 hipError_t launch_refresh_g(int64_t n, int dim, const double* x64, const double* centers, const double* weights,
                             int P, double bump_w2, float4* pts32, double4* pts64, double* g64, hipStream_t st);
@@ -399,6 +420,7 @@ hipError_t launch_ell(int64_t n, int dim, const double* x, const double* centers
 hipError_t launch_bbbox(const double* x3, const BatchGeom& g, double* part, int32_t* nonfinite, hipStream_t st);
 hipError_t launch_bprologue(const double* x3, const BatchGeom& g, const double* centers3, const double* weights,
                             int32_t* bin_of, int32_t* slot, int32_t* bin_count, double* g64_user, uint8_t* gam,
+                            uint32_t* fkey,
                             hipStream_t st);
 hipError_t launch_bgather(const double* x3, const BatchGeom& g, const int32_t* perm, const int32_t* bin_of,
                           const double* g64_user, const uint8_t* gam, float4* pts32, double4* pts64, double* x64,

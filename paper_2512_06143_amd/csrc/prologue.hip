@@ -70,13 +70,15 @@ __global__ __launch_bounds__(kBlock) void k_prologue(const double* __restrict__ 
                                                      int32_t* __restrict__ slot,
                                                      int32_t* __restrict__ bin_count,
                                                      double* __restrict__ g64_user,
-                                                     uint8_t* __restrict__ gam, int unit) {
+                                                     uint8_t* __restrict__ gam, uint32_t* __restrict__ fkey,
+                                                     int unit) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int dim = g.dim;
   double xi[3] = {0.0, 0.0, 0.0};
   for (int k = 0; k < dim; ++k) xi[k] = x[i * dim + k];
   const int64_t b = bin_index(xi, g);
+  fkey[i] = sub_cell_code(xi, g, dim);
   double gsum = 0.0;
   bool inside = false;
   bump_mask(xi, dim, centers, weights, P, bump_w2, gsum, inside);
@@ -93,51 +95,61 @@ __global__ __launch_bounds__(kBlock) void k_prologue(const double* __restrict__ 
 hipError_t launch_prologue(const double* x, int64_t n, const GridDev& g, const double* centers,
                            const double* weights, int P, double bump_w2, int32_t* bin_of,
                            int32_t* slot, int32_t* bin_count, double* g64_user, uint8_t* gam,
-                           hipStream_t st, bool unit) {
+                           uint32_t* fkey, hipStream_t st, bool unit) {
   int64_t blocks = (n + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_prologue, dim3((unsigned)blocks), dim3(kBlock), 0, st, x, n, g, centers,
-                     weights, P, bump_w2, bin_of, slot, bin_count, g64_user, gam, unit ? 1 : 0);
+                     weights, P, bump_w2, bin_of, slot, bin_count, g64_user, gam, fkey, unit ? 1 : 0);
   return hipGetLastError();
 }
 
 __global__ __launch_bounds__(kBlock) void k_scatter(int64_t n, const int32_t* __restrict__ bin_of,
                                                     const int32_t* __restrict__ slot,
+                                                    const uint32_t* __restrict__ fkey,
                                                     const int64_t* __restrict__ bin_start,
-                                                    int32_t* __restrict__ perm_tmp) {
+                                                    int32_t* __restrict__ perm_tmp,
+                                                    uint32_t* __restrict__ key_tmp) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  perm_tmp[bin_start[bin_of[i]] + slot[i]] = (int32_t)i;
+  const int64_t pos = bin_start[bin_of[i]] + slot[i];
+  perm_tmp[pos] = (int32_t)i;
+  key_tmp[pos] = fkey[i];
 }
 
-hipError_t launch_scatter(int64_t n, const int32_t* bin_of, const int32_t* slot,
-                            const int64_t* bin_start, int32_t* perm_tmp, hipStream_t st) {
+hipError_t launch_scatter(int64_t n, const int32_t* bin_of, const int32_t* slot, const uint32_t* fkey,
+                          const int64_t* bin_start, int32_t* perm_tmp, uint32_t* key_tmp, hipStream_t st) {
   int64_t blocks = (n + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(kBlock), 0, st, n, bin_of, slot,
-                     bin_start, perm_tmp);
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(kBlock), 0, st, n, bin_of, slot, fkey,
+                     bin_start, perm_tmp, key_tmp);
   return hipGetLastError();
 }
 
-// The atomic slots give an arbitrary order inside a bin. Make it deterministic:
-// the final position of a point is its bin start plus the number of points of the
-// same bin with a smaller user index (a stable counting sort by (bin, user index)).
+// The atomic slots give an arbitrary order inside a bin. Make it deterministic: the
+// final position of a point is its bin start plus the number of points of the same
+// bin that precede it in (sub-cell code, user index) order, i.e. a counting sort by
+// bin followed by a rank sort inside each bin.
 __global__ __launch_bounds__(kBlock) void k_binsort(int64_t n, const int32_t* __restrict__ perm_tmp,
+                                                    const uint32_t* __restrict__ key_tmp,
                                                     const int32_t* __restrict__ bin_of,
                                                     const int64_t* __restrict__ bin_start,
                                                     int32_t* __restrict__ perm) {
   int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= n) return;
-  int32_t me = perm_tmp[p];
-  int32_t b = bin_of[me];
-  int64_t s = bin_start[b], e = bin_start[b + 1];
+  const int32_t me = perm_tmp[p];
+  const uint32_t mk = key_tmp[p];
+  const int32_t b = bin_of[me];
+  const int64_t s = bin_start[b], e = bin_start[b + 1];
   int64_t rank = 0;
-  for (int64_t q = s; q < e; ++q) rank += (perm_tmp[q] < me) ? 1 : 0;
+  for (int64_t q = s; q < e; ++q) {
+    const uint32_t k = key_tmp[q];
+    rank += (k < mk || (k == mk && perm_tmp[q] < me)) ? 1 : 0;
+  }
   perm[s + rank] = me;
 }
 
-hipError_t launch_binsort(int64_t n, const int32_t* perm_tmp, const int32_t* bin_of,
-                            const int64_t* bin_start, int32_t* perm, hipStream_t st) {
+hipError_t launch_binsort(int64_t n, const int32_t* perm_tmp, const uint32_t* key_tmp, const int32_t* bin_of,
+                          const int64_t* bin_start, int32_t* perm, hipStream_t st) {
   int64_t blocks = (n + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_binsort, dim3((unsigned)blocks), dim3(kBlock), 0, st, n, perm_tmp, bin_of,
+  hipLaunchKernelGGL(k_binsort, dim3((unsigned)blocks), dim3(kBlock), 0, st, n, perm_tmp, key_tmp, bin_of,
                      bin_start, perm);
   return hipGetLastError();
 }

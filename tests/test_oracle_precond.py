@@ -1,7 +1,8 @@
 """Pins of the binned point order and of the block-preconditioned estimators.
 
-The order: a hand-worked five-point example; on random and clustered clouds, a
-permutation whose cell numbers never decrease, ties in user order, cells of side at
+The order: a hand-worked five-point example and hand-worked Z-order codes; on random
+and clustered clouds, a permutation whose cell numbers never decrease, sub-cell codes
+non-decreasing inside a cell, remaining ties in user order, cells of side at
 least r, and every pair closer than r in the same or neighbouring cells; the batched
 path's grid (refined cells, a smaller cap) keeps pairs within `refine` cells.
 
@@ -25,11 +26,23 @@ import workloads
 def test_bin_order_worked_example():
     # r = 0.5: bounding box (0.1, 0.05)-(0.9, 0.7), h = r (1 + 1e-6), 2 x 2 cells.
     # Cells (first coordinate fastest): p0 (1, 0) -> 1; p1 (0, 0) -> 0; p2: x offset 0.5 < h
-    # -> (0, 1) -> 2; p3 (0, 1) -> 2; p4 (0, 0) -> 0. Stable: [p1, p4, p0, p2, p3].
+    # -> (0, 1) -> 2; p3 (0, 1) -> 2; p4 (0, 0) -> 0.
+    # Inside cell 0, sub-cell steps f = floor(frac * 1024): p1 (0, 102), p4 (614, 0); the
+    # highest set bit of the Z-order code is p4's x bit 9 (code bit 18) against p1's y
+    # bit 6 (code bit 13), so p1 comes first. Inside cell 2: p2 (1023, 307), p3 (0, 102):
+    # p3 first. Order: [p1, p4, p0, p3, p2].
     x = np.array([[0.9, 0.1], [0.1, 0.1], [0.6, 0.7], [0.1, 0.6], [0.4, 0.05]])
-    assert list(oracle.bin_order(x, 0.5)) == [1, 4, 0, 2, 3]
+    assert list(oracle.bin_order(x, 0.5)) == [1, 4, 0, 3, 2]
     lo, h, nb = oracle.grid(x, 0.5)
     assert nb == [2, 2] and np.all(h >= 0.5)
+    assert list(oracle.sub_cell_codes(x, 0.5)[[1, 4]]) == [oracle.morton([[0, 102]])[0], oracle.morton([[614, 0]])[0]]
+
+
+def test_morton_codes_worked():
+    # x = 3 = 0b011, y = 5 = 0b101: x bits 0, 1 -> code bits 0, 2; y bits 0, 2 -> code bits 1, 5
+    assert list(oracle.morton([[1, 0], [0, 1], [3, 5], [1023, 1023]])) == [1, 2, 39, (1 << 20) - 1]
+    # 3-D: bit b of axis k goes to 3 b + k
+    assert list(oracle.morton([[1, 0, 0], [0, 0, 1], [2, 0, 0], [0, 2, 1]])) == [1, 4, 8, 16 + 4]
 
 
 @pytest.mark.parametrize("dim,kind,r", [(2, "uniform", 0.05), (3, "uniform", 0.15), (2, "gmm", 0.02),
@@ -50,7 +63,11 @@ def test_bin_order_properties(dim, kind, r):
     ks = key[order]
     assert np.all(np.diff(ks) >= 0)
     same = np.diff(ks) == 0
-    assert np.all(np.diff(order)[same] > 0)
+    code = oracle.sub_cell_codes(x, r)[order]
+    assert np.all(np.diff(code)[same] >= 0)
+    tie = same & (np.diff(code) == 0)
+    assert np.all(np.diff(order)[tie] > 0)
+    assert np.all(code < (1 << (10 * dim)))
     # unclamped coordinates already lie on the grid
     raw = np.floor((x - lo[None, :]) / h[None, :])
     assert np.all(raw >= 0) and np.all(raw <= np.array(nb) - 1)
