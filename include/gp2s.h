@@ -279,6 +279,18 @@ gp2s_status gp2s_matrix_get_block_product(gp2s_matrix m, int32_t nrhs, int32_t* 
 gp2s_status gp2s_spmv(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X, double* Y);
 /* (n * nrhs, and n * n_probes below, must stay below 2^31.) */
 
+/* gp2s_spmv without any device allocation, for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc). Same
+ * arguments, layout and result as gp2s_spmv (up to the order of float64 summation); its
+ * workspace is a fixed array of 2 x 2^22 float64 values (64 MiB) that the library holds
+ * on every GPU it runs on until the process ends, so n * nrhs must be at most 2^22
+ * (else GP2S_E_INVALID). Handles with the far-field term are rejected (GP2S_E_INVALID).
+ * Block-product structures that a handle would build on first use are not built here:
+ * the call then uses the default kernel. All calls on one GPU share the workspace:
+ * calls that overlap on one GPU (other streams, other threads, other contexts) race
+ * and must be serialised by the caller. Synchronises the context's stream. */
+gp2s_status gp2s_spmv_noalloc(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X, double* Y);
+
 /* a = K^{-1} y (DEVICE [n] float64 each) by preconditioned CG (opts->precond) with float64
  * vectors and dot products, restarted from the recomputed residual (iterative
  * refinement) until ||y - K a|| <= tol ||y||. The paper's host solver is MINRES

@@ -11,13 +11,13 @@ import numpy as np
 
 from .gp2s import (GP2S_FP64, GP2S_MIXED, Batch, GP2SError, Context, HostParams, Matrix, Report, SolveOpts,
                    default_context, default_opts, gp2s_assemble, gp2s_lml, gp2s_lml_grad,
-                   gp2s_matrix_import, gp2s_predict, gp2s_solve, gp2s_spmv, lib)
+                   gp2s_matrix_import, gp2s_predict, gp2s_solve, gp2s_spmv, gp2s_spmv_noalloc, lib)
 
 from .mcmc import BlockMH  # noqa: E402
 
 __all__ = ["BlockMH", "GP2S_FP64", "GP2S_MIXED", "Batch", "GP2SError", "Context", "HostParams", "Matrix", "Report", "SolveOpts",
            "default_context", "default_opts", "gp2s_assemble", "gp2s_lml", "gp2s_lml_grad",
-           "gp2s_matrix_import", "gp2s_predict", "gp2s_solve", "gp2s_spmv", "GP2SLML", "lml"]
+           "gp2s_matrix_import", "gp2s_predict", "gp2s_solve", "gp2s_spmv", "gp2s_spmv_noalloc", "GP2SLML", "lml"]
 
 
 def _autograd_function():

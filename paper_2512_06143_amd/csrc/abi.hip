@@ -1,6 +1,8 @@
 // Host runtime and C ABI of libgp2s: argument validation, contexts and matrix
 // handles, and the orchestration of the device kernels for assembly, products,
 // solves, the log marginal likelihood and its gradient.
+#include <mutex>
+
 #include "runtime.h"
 
 using namespace gp2s;
@@ -875,6 +877,38 @@ gp2s_status lml_common(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_
 using namespace gp2s::rt;
 
 // =====================================================================================
+// ---- allocation-free product ------------------------------------------------------------
+// Workspace of gp2s_spmv_noalloc: X gathered into internal order, then the product in
+// internal order, kNoAllocElems float64 values each (2 x 32 MiB). Every GPU the library
+// runs on holds its own copy until the process ends. In host code `scratch` names a
+// host-side stand-in, never the device memory: host code uses only the per-device
+// address that hipGetSymbolAddress returns.
+constexpr int64_t kNoAllocElems = int64_t(1) << 22;
+static __device__ __align__(256) double scratch[2 * kNoAllocElems];
+
+namespace {
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_ptr[kNoAllocDevices] = {};
+
+// The device address of `scratch` on the current device, looked up once per device
+// (with that device current) and kept.
+gp2s_status noalloc_workspace(gp2s_ctx ctx, double** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocDevices) return fail(ctx, GP2S_E_INVALID, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(ctx, GP2S_E_HIP, "hipGetSymbolAddress returned NULL for the workspace");
+    g_noalloc_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_noalloc_ptr[dev];
+  return GP2S_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int32_t gp2s_abi_version(void) { return GP2S_ABI_VERSION; }
@@ -1453,6 +1487,42 @@ gp2s_status gp2s_spmv(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X
                                            Xi, Yi, ctx->stream));
   st = ff_apply(ctx, m, nrhs, Xi, Yi, sc);
   if (st) return st;
+  HIPCHK(launch_scatter_rows(n, nrhs, m->perm, Yi, Y, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return GP2S_OK;
+}
+
+
+gp2s_status gp2s_spmv_noalloc(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X, double* Y) {
+  if (!ctx) return GP2S_E_INVALID;
+  gp2s_status st = check_matrix(ctx, m);
+  if (st) return st;
+  if (nrhs < 1 || nrhs > kMaxProbes) return fail(ctx, GP2S_E_INVALID, "nrhs must be in [1, %d]", kMaxProbes);
+  if (!X || !Y) return fail(ctx, GP2S_E_INVALID, "X and Y must be non-NULL");
+  const int64_t n = m->n;
+  if (n * nrhs > kNoAllocElems)
+    return fail(ctx, GP2S_E_INVALID, "n * nrhs = %lld exceeds the allocation-free workspace of %lld values",
+                (long long)(n * nrhs), (long long)kNoAllocElems);
+  if (m->ffG) return fail(ctx, GP2S_E_INVALID, "the far-field term needs workspace: use gp2s_spmv");
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count == 0) return fail(ctx, GP2S_E_HIP, "no HIP device available");
+  double* ws = nullptr;
+  st = noalloc_workspace(ctx, &ws);
+  if (st) return st;
+  double* Xi = ws;
+  double* Yi = ws + kNoAllocElems;
+  // block-product variants whose per-matrix structures are not built yet (they would be
+  // allocated on first use) give way to the heuristic choice; every variant gives the
+  // same product up to the order of float64 summation
+  int variant = nrhs > 1 ? m->spmm_variant[nrhs] : -1;
+  if (variant == 2 && !m->tiles) variant = -1;
+  if (variant == 3 && !(m->grp_ptr && m->grp_values)) variant = -1;
+  HIPCHK(launch_gather_rows(n, nrhs, m->perm, X, Xi, ctx->stream));
+  if (nrhs == 1)
+    HIPCHK(launch_spmv(m->prec, m->row_ptr, m->col, m->val, n, (double)m->nnz / n, Xi, Yi, ctx->stream, row_blocks(m)));
+  else
+    HIPCHK(launch_spmm(m->prec, m->row_ptr, m->col, m->val, n, nrhs, (double)m->nnz / n, variant, tile_set(m), Xi, Yi,
+                       ctx->stream));
   HIPCHK(launch_scatter_rows(n, nrhs, m->perm, Yi, Y, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return GP2S_OK;

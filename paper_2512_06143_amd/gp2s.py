@@ -109,6 +109,7 @@ _SIGS = {
     "gp2s_matrix_set_block_product": (_i32, [_vp, _i32, _i32]),
     "gp2s_matrix_get_block_product": (_i32, [_vp, _i32, ctypes.POINTER(_i32)]),
     "gp2s_spmv": (_i32, [_vp, _vp, _i32, _vp, _vp]),
+    "gp2s_spmv_noalloc": (_i32, [_vp, _vp, _i32, _vp, _vp]),
     "gp2s_solve": (_i32, [_vp, _vp, _vp, _vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(Report)]),
     "gp2s_lml": (_i32, [_vp, _vp, _vp, ctypes.POINTER(SolveOpts), _vp, ctypes.POINTER(Report)]),
     "gp2s_lml_grad": (_i32, [_vp, _vp, _vp, ctypes.POINTER(SolveOpts), _vp, ctypes.POINTER(Report),
@@ -370,6 +371,20 @@ def gp2s_spmv(m: Matrix, X):
     nrhs = 1 if Xd.dim() == 1 else int(Xd.shape[1])
     Y = ctx._torch.empty_like(Xd)
     ctx.check(lib.gp2s_spmv(ctx.ptr, m.handle, nrhs, _ptr(Xd), _ptr(Y)))
+    return Y
+
+
+def gp2s_spmv_noalloc(m: Matrix, X, Y):
+    """Y = K X into the caller's Y (DEVICE float64, X's shape) through the allocation-free
+    entry point: the library allocates nothing (see gp2s_spmv_noalloc in gp2s.h)."""
+    ctx = m.ctx
+    nrhs = 1 if X.dim() == 1 else int(X.shape[1])
+    for t in (X, Y):
+        if not (t.is_cuda and t.dtype == ctx._torch.float64 and t.is_contiguous()):
+            raise ValueError("X and Y must be contiguous float64 device tensors")
+    if tuple(Y.shape) != tuple(X.shape) or int(X.shape[0]) != m.n:
+        raise ValueError("X and Y must both have n rows and the same shape")
+    ctx.check(lib.gp2s_spmv_noalloc(ctx.ptr, m.handle, nrhs, _ptr(X), _ptr(Y)))
     return Y
 
 
