@@ -6,9 +6,19 @@ are already in HBM: bin + cull + assemble K, solve K a = y (block-Jacobi PCG wit
 refinement), probe solves + log-determinant, LML, and the gradient kernel.
 Default workload: 200 000 uniform 2-D points, r = 0.01 (63 stored entries per row),
 8 bumps, 64 probes; float32 K with float64 CG, timed against the float64-plain path
-on the same inputs. `--config c4` runs the 10 000 000-point clustered workload; by
-default its assembly and standalone single-RHS product are measured beside the step
-(`large` in the JSON line).
+on the same inputs. Beside the timed steps (not in `value`):
+
+* `parity`: every parity error against the oracle at the solver settings the steps
+  use (the 4 000-point workload and a 5 000-point subsample of the timed one, dense
+  same-probe oracle; sampled rows and the CPU-recomputed residual of the timed
+  matrix itself);
+* `large`: the 10 000 000-point clustered workload (the size the metric names):
+  assembly nnz/s, the single-RHS product, per-kernel times and rooflines of the
+  64-column probe block at that size from LML+gradient runs capped at two iteration
+  counts (their difference gives the time per iteration), the y solve to convergence,
+  and the projected seconds per LML+gradient;
+* `batch`: the 64-instance batched workload, instances per second;
+* `cpu_baseline`: the oracle's sparse LML+gradient timed on a bounded window.
 
 The timed steps bracket only the dominant kernel with HIP events (for its roofline);
 the per-kernel breakdown comes from one extra, untimed, fully instrumented step.
@@ -114,70 +124,175 @@ def make_inputs(args):
 
 
 BLOCK_PRODUCT = {}  # variant of the probe-block product chosen in the last step
+NOCONV = {"steps": 0, "noconv": 0}  # steps run / steps whose CG stopped at max_iter
 
 
-def run_step(G, x, y, params, precision, opts, block_product=None):
+def run_step(G, x, y, params, precision, opts, block_product=None, keep=False):
     m = G.gp2s_assemble(x, params, precision)
     S = opts.n_probes
     if block_product is not None and S > 1:
         m.set_block_product(S, block_product)
-    rep, grad, _ = G.gp2s_lml_grad(m, y, opts, want_a=False, allow_noconv=True)
+    rep, grad, a = G.gp2s_lml_grad(m, y, opts, want_a=keep, allow_noconv=True)
+    NOCONV["steps"] += 1
     if rep.status:
+        NOCONV["noconv"] += 1
         log(f"[bench] WARNING: CG stopped at max_iter ({precision}): y iters={rep.iters} probe iters={rep.probe_iters}")
     if S > 1:
         BLOCK_PRODUCT[precision] = m.block_product(S)
     n, nnz = m.n, m.nnz
+    if keep:
+        return rep, grad, n, nnz, m, a
     m.free()
     return rep, grad, n, nnz
 
 
-def cpu_baseline(prob, nnz_full, iters_y, iters_probe, S, budget_points=250_000, budget_s=15.0):
-    """The oracle as it stands on a bounded sample: the points inside a square window
-    (about budget_points of them) around the densest cluster centre region of the same
-    point cloud. Times oracle.covariance_csr (assembly) and oracle.pcg_jacobi per
-    iteration, then scales by the full instance's nnz and by the iteration counts of
-    Jacobi-preconditioned CG on the full instance (the oracle's own solver; counts
-    measured on the GPU with the diagonal preconditioner): the y solve plus one
-    single-RHS solve per probe. The oracle has no sparse gradient, so the projection
-    omits the backward pass (a lower bound)."""
+def cpu_baseline(prob, opts, side=0.06):
+    """The oracle as it stands, timed on a bounded sample: a complete LML + gradient of
+    its sparse float64 path (oracle.lml_grad_sparse: k-d tree assembly, Jacobi-PCG y
+    solve, one Jacobi-PCG solve per probe with Lanczos quadrature from its coefficients,
+    sparse dK contraction) on the points of the same cloud inside a square window of
+    side `side` centred at (0.5, 0.5), with the step's probe count and tolerances, on one
+    thread (BLAS limited to one thread). Measured, not projected."""
     import numpy as np
     import oracle
-    x = prob.x
-    rng = np.random.default_rng(0)
-    c = x[rng.integers(0, prob.n)]
-    # window side so that it holds ~budget_points points
-    lo, hi = 1e-4, 1.0
-    for _ in range(40):
-        h = math.sqrt(lo * hi)
-        cnt = int(np.all(np.abs(x - c) <= h / 2, axis=1).sum())
-        if cnt > budget_points:
-            hi = h
-        else:
-            lo = h
-    sel = np.all(np.abs(x - c) <= lo / 2, axis=1)
-    xs, ys = x[sel], prob.y[sel]
-    t0 = time.perf_counter()
-    K = oracle.covariance_csr(xs, prob.radius, prob.bump_width, prob.centers, prob.weights, prob.noise_var)
-    t_asm = time.perf_counter() - t0
-    # iteration count sized so that the whole sample takes about budget_s seconds
-    t0 = time.perf_counter()
-    oracle.pcg_jacobi(K, ys, tol=1e-300, max_iter=20)
-    t_est = (time.perf_counter() - t0) / 20
-    k_iter = int(min(5000, max(50, (budget_s - t_asm - 20 * t_est) / max(t_est, 1e-6))))
-    t0 = time.perf_counter()
-    oracle.pcg_jacobi(K, ys, tol=1e-300, max_iter=k_iter)
-    t_it = (time.perf_counter() - t0) / k_iter
-    scale = nnz_full / K.nnz
-    proj = t_asm * scale + t_it * scale * (iters_y + S * iters_probe)
+    from threadpoolctl import threadpool_limits
+    c = np.full(prob.dim, 0.5)
+    sel = np.all(np.abs(prob.x - c) <= side / 2, axis=1)
+    xs, ys = prob.x[sel], prob.y[sel]
+    S = int(opts.n_probes)
+    Z = oracle.rademacher_probes(int(opts.seed), S, xs.shape[0])
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        lml, grad, parts = oracle.lml_grad_sparse(xs, ys, prob.radius, prob.bump_width, prob.centers, prob.weights,
+                                                  prob.noise_var, Z, tol=float(opts.tol),
+                                                  probe_tol=float(opts.probe_tol))
+        dt = time.perf_counter() - t0
+    its = int(parts["iters_y"]) + int(np.sum(parts["iters_probe"]))
+    log(f"[bench] cpu oracle: {xs.shape[0]} points, {parts['nnz']} nnz, {S} probes: {dt:.1f}s "
+        f"(y {parts['iters_y']} iterations, probes {int(np.max(parts['iters_probe']))} max)")
     return {
-        "value": proj, "unit": "s per LML+grad (projected)", "cores": 1, "kind": "oracle",
-        "sample": (f"{int(sel.sum())} points in a square window of the same cloud ({K.nnz} nnz); "
-                   f"oracle.covariance_csr {t_asm:.2f}s, oracle.pcg_jacobi {t_it * 1e3:.1f} ms/iteration over "
-                   f"{k_iter} iterations; "
-                   f"scaled by nnz x{scale:.1f} and by the Jacobi-PCG iteration counts of the full instance "
-                   f"({iters_y} y + {S}x{iters_probe} probe); gradient pass not included"),
-        "assembly_nnz_per_s": K.nnz / t_asm,
+        "value": dt, "unit": "s per LML+grad (measured, on the sample)", "cores": 1, "kind": "oracle",
+        "sample": (f"{xs.shape[0]} points of the timed cloud in the square of side {side} centred at (0.5, 0.5) "
+                   f"({parts['nnz']} stored entries), {S} probes, tol {opts.tol:g}, probe tol {opts.probe_tol:g}, "
+                   f"Jacobi preconditioner; oracle.lml_grad_sparse complete: assembly, y solve "
+                   f"({parts['iters_y']} CG iterations), {S} probe solves ({its - int(parts['iters_y'])} CG "
+                   f"iterations in all) with Lanczos quadrature, gradient contraction"),
+        "n": int(xs.shape[0]), "nnz": int(parts["nnz"]), "cg_iterations": its,
+        "nnz_iterations_per_s": parts["nnz"] * its / dt,
     }
+
+
+def _export_user(m):
+    """The handle's CSR in user order (scipy, float64 values) and the raw arrays."""
+    import numpy as np
+    import scipy.sparse as sp
+    rp, col, val, perm = m.export()
+    rp, col, val = rp.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy().astype(np.float64)
+    perm = perm.cpu().numpy().astype(np.int64)
+    rows = perm[np.repeat(np.arange(m.n), np.diff(rp))]
+    K = sp.csr_matrix((val, (rows, perm[col])), shape=(m.n, m.n))
+    K.sort_indices()
+    return K
+
+
+def _pattern_errors(Kg, Kref, prob):
+    """(mismatches, exempt): pairs in one stored pattern and not the other, except pairs
+    with |rho^2 - 1| <= 1e-6 or touching a point within 1e-6 (in s) of a bump boundary."""
+    import numpy as np
+    import oracle
+    a, b = Kg.tocoo(), Kref.tocoo()
+    ka = a.row.astype(np.int64) * prob.n + a.col
+    kb = b.row.astype(np.int64) * prob.n + b.col
+    diff = np.setxor1d(ka, kb)
+    if diff.size == 0:
+        return 0, 0
+    pairs = np.stack([diff // prob.n, diff % prob.n], 1)
+    ex = oracle.boundary_exempt_pairs(prob.x, prob.radius, pairs)
+    pts = oracle.boundary_exempt_points(prob.x, prob.centers, prob.bump_width)
+    ex |= pts[pairs[:, 0]] | pts[pairs[:, 1]]
+    return int((~ex).sum()), int(ex.sum())
+
+
+def _max_rel_entry_err(Kg, Kref):
+    import numpy as np
+    A = Kg.tocoo()
+    want = np.asarray(Kref.tocsr()[A.row, A.col]).ravel()
+    mask = np.abs(want) >= 1e-30 * np.abs(Kref.diagonal()).max()
+    return float(np.max(np.abs(A.data[mask] - want[mask]) / np.abs(want[mask]))) if mask.any() else 0.0
+
+
+def parity_case(G, prob, precision, opts):
+    """One LML + gradient through the C ABI at the given solver settings, against the
+    oracle on the same probes, the same stored matrix and the same preconditioner
+    blocks: the bars of the hot path (pattern exact but for the support boundary, K
+    entries 1e-5 relative in float32 storage, residual 1e-8, same-probe ln|K| and LML
+    1e-8, same-probe gradient 1e-4 per component)."""
+    import numpy as np
+    import oracle
+    params = G.HostParams(prob.dim, prob.radius, prob.bump_width, prob.noise_var, prob.centers, prob.weights)
+    m = G.gp2s_assemble(prob.x, params, precision)
+    rep, grad, a = G.gp2s_lml_grad(m, prob.y, opts, allow_noconv=True)
+    a = a.cpu().numpy()
+    Kg = _export_user(m)
+    m.free()
+    Kref = oracle.covariance_csr(prob.x, prob.radius, prob.bump_width, prob.centers, prob.weights, prob.noise_var)
+    nmis, nex = _pattern_errors(Kg, Kref, prob)
+    S = int(opts.n_probes)
+    Z = oracle.rademacher_probes(int(opts.seed), S, prob.n)
+    blocks = (oracle.block_partition(oracle.bin_order(prob.x, prob.radius), oracle.BLOCK)
+              if int(opts.precond) == 1 else None)
+    Kd = Kg.toarray()
+    lml_ref, parts = oracle.lml_same_probe(Kd, prob.y, Z, blocks)
+    gref, gparts = oracle.grad_same_probe(prob.x, prob.y, Z, prob.radius, prob.bump_width, prob.centers,
+                                          prob.weights, prob.noise_var, K=Kd, blocks=blocks)
+    scale = np.maximum(np.abs(gref), 1e-6 * (np.abs(gparts["fit"]) + 0.5 * np.abs(gparts["tau"])))
+    exact = oracle.lml_dense(Kref.toarray(), prob.y)
+    out = {
+        "n": prob.n, "nnz": int(Kg.nnz), "converged": rep.status == 0, "iters": [rep.iters, rep.probe_iters],
+        "pattern_mismatch": nmis, "pattern_exempt": nex, "max_rel_K_err": _max_rel_entry_err(Kg, Kref),
+        "resid_stored_K": oracle.residual_rel(Kg, a, prob.y), "resid_fp64_K": oracle.residual_rel(Kref, a, prob.y),
+        "logdet_rel_err_same_probe": abs(rep.logdet - parts["gamma"]) / abs(parts["gamma"]),
+        "lml_rel_err_same_probe": abs(rep.lml - lml_ref) / abs(lml_ref),
+        "grad_max_rel_err_same_probe": float(np.max(np.abs(grad - gref) / scale)),
+        "logdet_z_vs_exact": (rep.logdet - exact.logdet) / rep.logdet_stderr,
+        "logdet_storage_rel": abs(parts["logdet"] - exact.logdet) / abs(exact.logdet),
+    }
+    log(f"[bench] parity {prob.name}/{precision}: " + ", ".join(
+        f"{k}={v:.2e}" if isinstance(v, float) else f"{k}={v}" for k, v in out.items()))
+    return out
+
+
+def parity_rows(m, a, prob, n_rows=2000):
+    """The timed matrix itself: sampled rows against the oracle's rows (pattern and
+    values) and the residual of the step's solution recomputed on the CPU from the
+    exported CSR."""
+    import numpy as np
+    import oracle
+    Kg = _export_user(m)
+    rows = np.random.default_rng(1).choice(prob.n, size=min(n_rows, prob.n), replace=False)
+    ref = oracle.covariance_rows(prob.x, prob.radius, prob.bump_width, prob.centers, prob.weights, prob.noise_var,
+                                 rows)
+    pts = oracle.boundary_exempt_points(prob.x, prob.centers, prob.bump_width)
+    nmis = nex = 0
+    err = 0.0
+    dmax = np.abs(Kg.diagonal()).max()
+    for i, (cols, vals) in zip(rows, ref):
+        got = Kg.getrow(i)
+        gc, gv = got.indices, got.data
+        diff = np.setxor1d(gc, cols)
+        if diff.size:
+            pairs = np.stack([np.full(diff.size, i), diff], 1)
+            ex = oracle.boundary_exempt_pairs(prob.x, prob.radius, pairs) | pts[diff] | pts[i]
+            nmis += int((~ex).sum())
+            nex += int(ex.sum())
+        common, ia, ib = np.intersect1d(gc, cols, return_indices=True)
+        keep = np.abs(vals[ib]) >= 1e-30 * dmax
+        if keep.any():
+            err = max(err, float(np.max(np.abs(gv[ia][keep] - vals[ib][keep]) / np.abs(vals[ib][keep]))))
+    out = {"rows": int(rows.size), "pattern_mismatch": nmis, "pattern_exempt": nex, "max_rel_K_err": err,
+           "resid_stored_K": oracle.residual_rel(Kg, a, prob.y)}
+    log(f"[bench] parity on the timed matrix: {out}")
+    return out
 
 
 def bench_posterior(G, x, y, params, precision, prob, n_mean=100_000, n_var=64):
@@ -271,11 +386,23 @@ def bench_variants(G, x, y, params, precision, opts, steps=1):
     return out
 
 
-def bench_large(G, config="c4", reps=3, spmv_reps=20):
-    """Assembly and the standalone single-RHS product on the 10 000 000-point clustered
-    workload, float32 and float64 storage (outside the timed step: an LML+gradient at this
-    size takes minutes). Reports K nnz/s assembled and the product's algorithmic HBM rate,
-    both from the library's HIP events."""
+def bench_large(G, opts, config="c4", reps=3, spmv_reps=20, caps=(20, 100, 300), converge_y=True):
+    """The 10 000 000-point clustered workload, float32 and float64 storage (outside the
+    timed steps: a converged LML+gradient at this size takes minutes).
+
+    * assembly: K nnz/s from the library's HIP events (mean of `reps`);
+    * the standalone single-RHS product: algorithmic HBM rate;
+    * LML + gradient with 64 probes capped at caps[0] (fresh handle: includes the
+      block factorisation and the product's tuning), caps[1] and caps[2] iterations on
+      the same handle: their wall-time difference gives the time per iteration of the
+      two concurrent chains (y solve + probe block) at full size, the rest the fixed
+      cost (right-hand sides, quadrature, gradient kernel); one more capped run with
+      every kernel bracketed by events gives per-kernel times and the rooflines of the
+      probe-block product and update at this size;
+    * the float32-stored y solve to convergence (its iteration count);
+    * projected s per LML+gradient = assembly + first-call extra + fixed + per-iteration
+      x the y solve's iteration count to convergence (an upper bound: the probe block
+      stops at its looser tolerance no later than the y solve in every run seen)."""
     import numpy as np
     import torch
     import workloads
@@ -283,11 +410,18 @@ def bench_large(G, config="c4", reps=3, spmv_reps=20):
     prob = workloads.make_problem(config)
     log(f"[bench] large: generated {config}: n={prob.n} r={prob.radius:.6g} ({time.perf_counter() - t0:.1f}s)")
     x = torch.as_tensor(prob.x).cuda()
+    y = torch.as_tensor(prob.y).cuda()
     params = G.HostParams(prob.dim, prob.radius, prob.bump_width, prob.noise_var, prob.centers, prob.weights)
     v = torch.as_tensor(np.random.default_rng(0).standard_normal(prob.n)).cuda()
     ctx = G.default_context()
-    out = {"workload": (f"{config}: {prob.n} {prob.meta.get('points', 'uniform')} {prob.dim}-D points, "
-                        f"r={prob.radius:.6g}, {prob.n_bumps} bumps"), "n": prob.n}
+    S = prob.n_probes
+    out = {"workload": (f"{config}: {prob.n} clustered {prob.dim}-D points (200-component mixture), "
+                        f"r={prob.radius:.6g}, {prob.n_bumps} bumps, {S} probes"), "n": prob.n, "probes": S}
+
+    def capped(cap):
+        return G.default_opts(n_probes=S, max_iter=cap, tol=float(opts.tol), probe_tol=float(opts.probe_tol),
+                              check_every=32, precond=int(opts.precond))
+
     for prec in ("mixed", "fp64"):
         G.gp2s_assemble(x, params, prec).free()  # warm
         ctx.set_timing(True)
@@ -304,69 +438,143 @@ def bench_large(G, config="c4", reps=3, spmv_reps=20):
             G.gp2s_spmv(m, v)
         ms, cnt = ctx.stats()["spmv"]
         ctx.set_timing(False)
-        m.free()
         b = kernel_bytes("spmv", n, nnz, 1, prec)
         gbs = b / (ms / cnt / 1e3) / 1e9
-        out[prec] = {"nnz": nnz, "assembly_ms": asm_ms, "assembly_nnz_per_s": nnz / (asm_ms / 1e3),
-                     "spmv_ms": ms / cnt, "spmv_bytes": b, "spmv_GBps": gbs, "spmv_frac_hbm": gbs * 1e9 / PEAK_HBM}
+        r = {"nnz": nnz, "assembly_ms": asm_ms, "assembly_nnz_per_s": nnz / (asm_ms / 1e3),
+             "assembly_count_ms": st["asm_count"][0] / reps, "assembly_fill_ms": st["asm_fill"][0] / reps,
+             "spmv_ms": ms / cnt, "spmv_bytes": b, "spmv_GBps": gbs, "spmv_frac_hbm": gbs * 1e9 / PEAK_HBM}
         log(f"[bench] large {prec}: nnz={nnz} ({nnz / n:.1f}/row), assembly {asm_ms:.2f} ms "
             f"({nnz / (asm_ms / 1e3):.3g} nnz/s), spmv {ms / cnt:.3f} ms = {gbs:.0f} GB/s "
             f"({100 * gbs * 1e9 / PEAK_HBM:.1f}% of HBM)")
-    del x, v
+        walls = []
+        for cap in caps:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep, grad, _ = G.gp2s_lml_grad(m, y, capped(cap), want_a=False, allow_noconv=True)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+            log(f"[bench] large {prec}: LML+grad capped at {cap} iterations: {walls[-1]:.2f}s "
+                f"(y {rep.iters}, probes {rep.probe_iters})")
+        slope = (walls[2] - walls[1]) / (caps[2] - caps[1])
+        fixed = walls[1] - caps[1] * slope
+        first = walls[0] - (fixed + caps[0] * slope)
+        ctx.set_timing(True)
+        G.gp2s_lml_grad(m, y, capped(caps[1]), want_a=False, allow_noconv=True)
+        st = ctx.stats()
+        ctx.set_timing(False)
+        kern = {k: {"ms_avg": v[0] / v[1], "launches": v[1]} for k, v in st.items() if v[1]}
+        roof = {}
+        for cat in ("cg_matvec_block", "cg_update_block", "cg_pupdate_block", "cg_matvec1", "cg_update1"):
+            if cat in kern:
+                bb = kernel_bytes(cat, n, nnz, S if "block" in cat else 1, prec,
+                                  "block" if int(opts.precond) == 1 else "jacobi")
+                avg = kern[cat]["ms_avg"] / 1e3
+                roof[cat] = {"bound": "hbm", "achieved": bb / avg / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                             "frac": bb / avg / PEAK_HBM, "bytes_per_launch": bb, "avg_ms": avg * 1e3}
+        r.update({"capped_runs": {str(c): w for c, w in zip(caps, walls)}, "s_per_iteration": slope,
+                  "fixed_s": fixed, "first_call_extra_s": first, "kernels": kern, "rooflines": roof})
+        log(f"[bench] large {prec}: {slope * 1e3:.2f} ms per iteration (both chains), fixed {fixed:.2f}s, "
+            f"first-call extra {first:.2f}s; probe block product "
+            f"{roof.get('cg_matvec_block', {}).get('frac', float('nan')):.3f} of HBM")
+        if converge_y and prec == "mixed":
+            last = [time.perf_counter()]
+
+            def prog(label, it, open_cols, res):
+                if time.perf_counter() - last[0] > 10.0:
+                    last[0] = time.perf_counter()
+                    log(f"[bench]   ... large y solve: {it} iterations, max rel resid {res:.2e}")
+            ctx.set_progress(prog)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            a, rep = G.gp2s_solve(m, y, G.default_opts(max_iter=200000, tol=float(opts.tol), precond=int(opts.precond),
+                                                       check_every=32), allow_noconv=True)
+            torch.cuda.synchronize()
+            ty = time.perf_counter() - t0
+            ctx.set_progress(None)
+            out["y_solve_mixed"] = {"iters": rep.iters, "ir_steps": rep.ir_steps, "resid": rep.resid, "s": ty,
+                                    "converged": rep.status == 0}
+            log(f"[bench] large mixed y solve: {rep.iters} iterations, resid {rep.resid:.2e}, {ty:.1f}s")
+        out[prec] = r
+        m.free()
+        torch.cuda.empty_cache()
+    if "y_solve_mixed" in out:
+        iters = out["y_solve_mixed"]["iters"]
+        for prec in ("mixed", "fp64"):
+            r = out[prec]
+            r["projected_s_per_lml_grad"] = (r["assembly_ms"] / 1e3 + r["first_call_extra_s"] + r["fixed_s"]
+                                             + r["s_per_iteration"] * iters)
+        out["projected_speedup_mixed_vs_fp64"] = (out["fp64"]["projected_s_per_lml_grad"]
+                                                  / out["mixed"]["projected_s_per_lml_grad"])
+        log(f"[bench] large projected s per LML+grad at {iters} iterations: mixed "
+            f"{out['mixed']['projected_s_per_lml_grad']:.1f}s, fp64 {out['fp64']['projected_s_per_lml_grad']:.1f}s")
+    del x, y, v
     torch.cuda.empty_cache()
     return out
 
 
-def bench_batch(args):
+def batch_leg(G, precision="mixed", precond="block", steps=2, warmup=1, S=16, max_iter=40000, tol=1e-8,
+              probe_tol=1e-5):
     """64 independent instances (c5) planned once, then evaluated together per step:
     reassembly with the step's hyperparameters, y solves, probe solves, log-dets, LMLs
-    and gradients of all instances. Reports instances per second."""
+    and gradients of all instances. Instances per second."""
     import numpy as np
     import torch
-    import paper_2512_06143_amd as G
     import workloads
     t0 = time.perf_counter()
     probs = workloads.make_c5()
-    S = args.probes if args.probes is not None else 16
     xs = [torch.as_tensor(p.x).cuda() for p in probs]
     ys = [torch.as_tensor(p.y).cuda() for p in probs]
     params = [G.HostParams(p.dim, p.radius, p.bump_width, p.noise_var, p.centers, p.weights) for p in probs]
-    opts = G.default_opts(n_probes=S, max_iter=args.max_iter, tol=args.tol, probe_tol=args.probe_tol, check_every=32,
-                          precond=args.precond)
+    opts = G.default_opts(n_probes=S, max_iter=max_iter, tol=tol, probe_tol=probe_tol, check_every=32,
+                          precond=precond)
     ctx = G.default_context()
-    b = G.Batch(xs, params, args.precision, opts, ctx)
+    b = G.Batch(xs, params, precision, opts, ctx)
     info = b.info()
-    log(f"[bench] planned {len(probs)} instances, {info} ({time.perf_counter() - t0:.1f}s)")
-    for w in range(args.warmup):
+    log(f"[bench] batch: planned {len(probs)} instances, {info} ({time.perf_counter() - t0:.1f}s)")
+    for w in range(warmup):
         lml, grads, reps = b.run(ys, params=params, allow_noconv=True)
-        log(f"[bench] warmup {w}: max iters y={max(r['iters'] for r in reps)} "
-            f"probes={max(r['probe_iters'] for r in reps)}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    noconv = 0
+    for k in range(steps):
         lml, grads, reps = b.run(ys, params=params, allow_noconv=True)
-        log(f"[bench] step {k}: iters y max {max(r['iters'] for r in reps)} median "
-            f"{int(np.median([r['iters'] for r in reps]))}, probes max {max(r['probe_iters'] for r in reps)} "
-            f"median {int(np.median([r['probe_iters'] for r in reps]))}, max resid {max(r['resid'] for r in reps):.2e}")
+        noconv += sum(1 for r in reps if r["iters"] >= max_iter or r["probe_iters"] >= max_iter)
+        log(f"[bench] batch step {k}: iters y max {max(r['iters'] for r in reps)} median "
+            f"{int(np.median([r['iters'] for r in reps]))}, probes max {max(r['probe_iters'] for r in reps)}, "
+            f"max resid {max(r['resid'] for r in reps):.2e}")
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    dt = (time.perf_counter() - t0) / steps
     M = len(probs)
+    b.free()
+    return {
+        "value": M / dt, "unit": "instances/s", "s_per_batch": dt, "steps": steps, "warmup": warmup,
+        "workload": (f"c5: {M} instances, N {min(p.n for p in probs)}-{max(p.n for p in probs)} "
+                     f"(total {info['n_total']}), d in {{2,3}}, {S} probes each"),
+        "n_total": info["n_total"], "nnz": info["nnz"], "precision": precision, "precond": precond,
+        "autotuned": {k: info[k] for k in ("bin_refinement", "spmv_lanes", "spmm_lanes")},
+        "max_iters_y": max(r["iters"] for r in reps), "max_iters_probe": max(r["probe_iters"] for r in reps),
+        "median_iters_y": int(np.median([r["iters"] for r in reps])),
+        "all_converged": noconv == 0 and max(r["resid"] for r in reps) <= tol,
+    }
+
+
+def bench_batch(args):
+    """`--config c5`: the batched workload as the timed metric."""
+    import paper_2512_06143_amd as G
+    S = args.probes if args.probes is not None else 16
+    r = batch_leg(G, args.precision, args.precond, args.steps, args.warmup, S, args.max_iter, args.tol,
+                  args.probe_tol)
     out = {
         "metric": "instances/s, batched LML+grad (64 uneven instances)",
-        "value": M / dt, "unit": "instances/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "value": r["value"], "unit": "instances/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r["s_per_batch"] * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 K / f64 CG" if args.precision == "mixed" else "f64", "data": "synthetic",
-        "config": {"workload": (f"c5: {M} instances, N {min(p.n for p in probs)}-{max(p.n for p in probs)} "
-                                f"(total {info['n_total']}), d in {{2,3}}, {S} probes each"),
-                   "n_total": info["n_total"], "nnz": info["nnz"], "precision": args.precision,
-                   "precond": args.precond,
-                   "autotuned": {k: info[k] for k in ("bin_refinement", "spmv_lanes", "spmm_lanes")},
+        "config": {"workload": r["workload"], "n_total": r["n_total"], "nnz": r["nnz"],
+                   "precision": args.precision, "precond": args.precond, "autotuned": r["autotuned"],
                    "parallelism": "single GPU"},
-        "max_iters_y": max(r["iters"] for r in reps), "max_iters_probe": max(r["probe_iters"] for r in reps),
-        "roofline": None,
+        "max_iters_y": r["max_iters_y"], "max_iters_probe": r["max_iters_probe"], "roofline": None,
     }
     print(json.dumps(out), flush=True)
-    b.free()
 
 
 def main():
@@ -386,10 +594,10 @@ def main():
     ap.add_argument("--no-predict", action="store_true", help="skip the posterior (test-point) measurement")
     ap.add_argument("--no-mcmc", action="store_true", help="skip the block Metropolis-Hastings sweep")
     ap.add_argument("--no-variants", action="store_true", help="skip the kernel-variant measurements")
-    ap.add_argument("--no-large", action="store_true",
-                    help="skip the 10 M-point assembly and single-RHS product measurement")
-    ap.add_argument("--only-large", action="store_true",
-                    help="run only the 10 M-point assembly and single-RHS product measurement")
+    ap.add_argument("--no-large", action="store_true", help="skip the 10 M-point measurements")
+    ap.add_argument("--only-large", action="store_true", help="run only the 10 M-point measurements")
+    ap.add_argument("--no-parity", action="store_true", help="skip the in-run parity comparison with the oracle")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched (64-instance) measurement")
     ap.add_argument("--no-jacobi", action="store_true",
                     help="skip the same step with the diagonal preconditioner (comparison and CPU projection)")
     ap.add_argument("--precond", default="block", choices=["block", "jacobi"],
@@ -421,7 +629,9 @@ def main():
     if args.config == "c5":
         return bench_batch(args)
     if args.only_large:
-        print(json.dumps({"large": bench_large(G)}), flush=True)
+        opts = G.default_opts(max_iter=args.max_iter, tol=args.tol, probe_tol=args.probe_tol, check_every=32,
+                              precond=args.precond)
+        print(json.dumps({"large": bench_large(G, opts)}), flush=True)
         return
     prob = make_inputs(args)
     S = args.probes if args.probes is not None else prob.n_probes
@@ -544,19 +754,52 @@ def main():
         out["fp64_iters"] = [rep64.iters, rep64.probe_iters]
         out["fp64_lml"] = rep64.lml
         log(f"[bench] fp64 plain: {t64:.2f}s iters y={rep64.iters} probes={rep64.probe_iters} lml={rep64.lml:.6f}")
+    out["all_converged"] = NOCONV["noconv"] == 0
+    out["noconv_steps"] = NOCONV["noconv"]
+    out["steps_run"] = NOCONV["steps"]
+    if not args.no_parity:
+        # the timed matrix itself (one more, untimed, step that keeps its handle), then the
+        # dense same-probe oracle at the same solver settings
+        rep_k, _, _, _, m_k, a_k = run_step(G, x, y, params, args.precision, opts, keep=True)
+        par = {"settings": {"tol": args.tol, "probe_tol": args.probe_tol, "probes": S, "precond": args.precond,
+                            "max_iter": args.max_iter, "seed": int(opts.seed)},
+               "timed_matrix": parity_rows(m_k, a_k.cpu().numpy(), prob)}
+        m_k.free()
+        import workloads
+        c1 = workloads.make_problem("c1")
+        o1 = G.default_opts(n_probes=S, max_iter=args.max_iter, tol=args.tol, probe_tol=args.probe_tol,
+                            check_every=32, precond=args.precond)
+        par["c1_mixed"] = parity_case(G, c1, "mixed", o1)
+        par["c1_fp64"] = parity_case(G, c1, "fp64", o1)
+        if args.config == "c2":
+            par["c2_sub5000_mixed"] = parity_case(G, prob.subsample(5000, seed=1), args.precision, o1)
+        bars = {"pattern_mismatch": 0, "resid_stored_K": 1e-8, "logdet_rel_err_same_probe": 1e-8,
+                "lml_rel_err_same_probe": 1e-8, "grad_max_rel_err_same_probe": 1e-4}
+        ok = True
+        for k, v in par.items():
+            if not k.startswith("c"):
+                continue
+            ok &= bool(v["converged"]) and v["max_rel_K_err"] <= (1e-5 if "mixed" in k else 1e-9)
+            ok &= all(v[b] <= lim for b, lim in bars.items())
+        tm = par["timed_matrix"]
+        ok &= tm["pattern_mismatch"] == 0 and tm["resid_stored_K"] <= 1e-8 and tm["max_rel_K_err"] <= 1e-5
+        par["all_within_bars"] = bool(ok)
+        out["parity"] = par
     if not args.no_predict:
         out["posterior"] = bench_posterior(G, x, y, params, args.precision, prob)
     if not args.no_mcmc:
         out["mcmc"] = bench_mcmc(G, x, y, params, args.precision, opts)
     if not args.no_variants:
         out["variants"] = bench_variants(G, x, y, params, args.precision, opts)
+    if not args.no_batch:
+        out["batch"] = batch_leg(G, args.precision, args.precond)
     if not args.no_large and args.config != "c4":
         del x, y
         torch.cuda.empty_cache()
-        out["large"] = bench_large(G)
+        out["large"] = bench_large(G, opts)
     if not args.no_cpu:
         t0 = time.perf_counter()
-        out["cpu_baseline"] = cpu_baseline(prob, nnz, jac_iters[0], jac_iters[1], S)
+        out["cpu_baseline"] = cpu_baseline(prob, opts)
         log(f"[bench] cpu baseline took {time.perf_counter() - t0:.1f}s")
     print(json.dumps(out), flush=True)
 

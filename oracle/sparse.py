@@ -11,7 +11,6 @@ host solver is MINRES (App. B.6), which reaches the same solution K^{-1} y.
 from __future__ import annotations
 
 import numpy as np
-import scipy.linalg
 import scipy.sparse as sp
 from scipy.spatial import cKDTree
 
@@ -182,7 +181,8 @@ def lml_components(K, y):
 
 def lanczos_logquad(alphas, betas):
     """e_1^T ln(T) e_1 for the Lanczos tridiagonal T that a CG run with coefficients
-    (alpha_j, beta_j) builds (Golub-Welsch: T = V diag(theta) V^T, the quadrature is
+    (alpha_j, beta_j) builds (Golub-Welsch: T = V diag(theta) V^T, here the dense
+    symmetric eigendecomposition of T; the quadrature is
     sum_k V_0k^2 ln theta_k):
       T_00 = 1/alpha_0,  T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},
       T_j,j+1 = T_j+1,j = sqrt(beta_j)/alpha_j."""
@@ -192,7 +192,8 @@ def lanczos_logquad(alphas, betas):
     d = 1.0 / al
     d[1:] += be[:m - 1] / al[:m - 1]
     e = np.sqrt(be[:m - 1]) / al[:m - 1]
-    theta, V = scipy.linalg.eigh_tridiagonal(d, e)
+    T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    theta, V = np.linalg.eigh(T)
     return float(np.sum(V[0] ** 2 * np.log(theta)))
 
 
