@@ -20,7 +20,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgp2s.so")
 
 SOURCES = ["abi.hip", "batch_abi.hip", "batch.hip", "prologue.hip", "scan.hip", "assemble.hip", "spmv.hip", "pcg.hip", "slq.hip",
-           "backward.hip", "predict.hip", "blockjac.hip", "farfield.hip", "grouped.hip"]
+           "backward.hip", "predict.hip", "blockjac.hip", "farfield.hip", "grouped.hip", "bsplit.hip"]
 
 ARCH = os.environ.get("GP2S_OFFLOAD_ARCH", "gfx950")
 # Packed FP32 instructions are disabled for all device code.

@@ -186,6 +186,29 @@ gp2s_status ensure_groups(gp2s_ctx ctx, gp2s_matrix m) {
   return GP2S_OK;
 }
 
+// Dense diagonal blocks and per-row in-block runs of the block-split product (variant 5),
+// built on first use; after a refill only the block values are rewritten. 64 float32 (or
+// float64) values per row.
+gp2s_status ensure_bsplit(gp2s_ctx ctx, gp2s_matrix m) {
+  hipStream_t st = ctx->stream;
+  if (!m->bs_tried) {
+    m->bs_tried = true;
+    const size_t nblk = (size_t)((m->n + kBJ - 1) / kBJ);
+    void* bv = m->prec == GP2S_MIXED ? (void*)own<float>(m, nblk * kBJ * kBJ) : (void*)own<double>(m, nblk * kBJ * kBJ);
+    int2* seg = own<int2>(m, (size_t)m->n);
+    if (!bv || !seg) return GP2S_OK;  // the variant is simply not offered
+    HIPCHK(launch_bs_build(m->n, m->row_ptr, m->col, m->val, m->prec, bv, seg, false, st));
+    m->bs_val = bv;
+    m->bs_seg = seg;
+    m->bs_values = true;
+  }
+  if (m->bs_val && !m->bs_values) {
+    HIPCHK(launch_bs_build(m->n, m->row_ptr, m->col, m->val, m->prec, m->bs_val, m->bs_seg, true, st));
+    m->bs_values = true;
+  }
+  return GP2S_OK;
+}
+
 TileSet tile_set(gp2s_matrix m) {
   TileSet t;
   t.t = m->tiles;
@@ -195,6 +218,10 @@ TileSet tile_set(gp2s_matrix m) {
     t.gcol = m->grp_col;
     t.gval = m->grp_val;
     t.ngroups = (m->n + kGrp - 1) / kGrp;
+  }
+  if (m->bs_val && m->bs_values) {
+    t.bval = m->bs_val;
+    t.bseg = m->bs_seg;
   }
   return t;
 }
@@ -214,6 +241,8 @@ gp2s_status tune_block_product(gp2s_ctx ctx, gp2s_matrix m, int S, const void* P
       if (ts) return ts;
       if (m->grp_ptr) cand.push_back(3);
     }
+    // The block split (variant 5) is not a candidate: measured slower than the column
+    // slices (see bsplit.hip), and its dense blocks cost 64 values per row. It can be pinned.
   }
   for (int G = 4; G <= 16; G *= 2)
     if (entry_product_ok(S, G)) cand.push_back(G);
@@ -373,6 +402,10 @@ gp2s_status cg_begin(Cg& c, const double* B, double tol, bool keep_hist, Scratch
   if (c.variant == 2) {  // a pinned tile variant: the tiles are otherwise built by the tuner
     gp2s_status ts = ensure_tiles(ctx, m);
     if (ts) return ts;
+  }
+  if (c.variant == 5) {  // the block split (its block values are refreshed after a refill)
+    gp2s_status bs = ensure_bsplit(ctx, m);
+    if (bs) return bs;
   }
   return GP2S_OK;
 }
@@ -1396,6 +1429,7 @@ gp2s_status gp2s_matrix_refill(gp2s_ctx ctx, gp2s_matrix m, const gp2s_params* p
   const int64_t n = m->n;
   m->bj_ready = false;  // the block factor belongs to the old values
   m->grp_values = false;  // and so do the grouped copy's values
+  m->bs_values = false;   // and the block split's dense blocks
   m->weights_h.assign(p->weights, p->weights + p->n_bumps);
   m->noise = p->noise_var;
   m->kern = p->kernel;
@@ -1442,7 +1476,8 @@ gp2s_status gp2s_matrix_set_block_product(gp2s_matrix m, int32_t nrhs, int32_t v
   if (!m || nrhs < 2 || nrhs > kMaxProbes) return GP2S_E_INVALID;
   const bool sliced = nrhs == 8 || nrhs == 16 || nrhs == 32 || nrhs == 64;
   const bool ok = variant == -1 || variant == 0 || (variant == 1 && sliced) || (variant == 2 && sliced && m->assembled) ||
-                  (variant == 3 && (nrhs == 32 || nrhs == 64)) || entry_product_ok(nrhs, variant);
+                  (variant == 3 && (nrhs == 32 || nrhs == 64)) || (variant == 5 && sliced) ||
+                  entry_product_ok(nrhs, variant);
   if (!ok) return GP2S_E_INVALID;
   m->spmm_variant[nrhs] = variant == -1 ? -2 : variant;
   return GP2S_OK;
@@ -1475,6 +1510,10 @@ gp2s_status gp2s_spmv(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const double* X
   }
   if (nrhs > 1 && m->spmm_variant[nrhs] == 2) {
     st = ensure_tiles(ctx, m);
+    if (st) return st;
+  }
+  if (nrhs > 1 && m->spmm_variant[nrhs] == 5) {
+    st = ensure_bsplit(ctx, m);
     if (st) return st;
   }
   HIPCHK(launch_gather_rows(n, nrhs, m->perm, X, Xi, ctx->stream));
@@ -1517,6 +1556,7 @@ gp2s_status gp2s_spmv_noalloc(gp2s_ctx ctx, gp2s_matrix m, int32_t nrhs, const d
   int variant = nrhs > 1 ? m->spmm_variant[nrhs] : -1;
   if (variant == 2 && !m->tiles) variant = -1;
   if (variant == 3 && !(m->grp_ptr && m->grp_values)) variant = -1;
+  if (variant == 5 && !(m->bs_val && m->bs_values)) variant = -1;
   HIPCHK(launch_gather_rows(n, nrhs, m->perm, X, Xi, ctx->stream));
   if (nrhs == 1)
     HIPCHK(launch_spmv(m->prec, m->row_ptr, m->col, m->val, n, (double)m->nnz / n, Xi, Yi, ctx->stream, row_blocks(m)));

@@ -143,7 +143,16 @@ struct TileSet {
   const int32_t* gcol = nullptr;
   const void* gval = nullptr;
   int64_t ngroups = 0;
+  // block split (variant 5): dense 64 x 64 diagonal blocks in matrix-core operand order,
+  // and per row the run [lo, hi) of its in-block entries
+  const void* bval = nullptr;
+  const int2* bseg = nullptr;
 };
+hipError_t launch_bs_build(int64_t n, const int64_t* rp, const int32_t* col, const void* val, int prec, void* Bv,
+                           int2* seg, bool values_only, hipStream_t st);
+template <typename V, typename PT, bool DOT>
+bool spmm_split(const int64_t* rp, const int32_t* col, const V* val, int64_t n, int S, const TileSet& tiles,
+                const PT* X, double* Y, const CgState& cs, hipStream_t st, int64_t row_blocks, int* nblocks);
 hipError_t launch_grp_count(int64_t n, const int64_t* rp, const int32_t* col, int64_t ngroups, int32_t* cnt,
                             hipStream_t st);
 hipError_t launch_grp_fill(int64_t n, const int64_t* rp, const int32_t* col, int64_t ngroups, const int64_t* gptr,

@@ -53,6 +53,11 @@ struct gp2s_matrix_s {
   int32_t* grp_map = nullptr;
   int64_t grp_n = 0;
   bool grp_tried = false, grp_values = false;
+  // block split of the block product (variant 5; built on first use, values refreshed
+  // after a refill)
+  void* bs_val = nullptr;
+  int2* bs_seg = nullptr;
+  bool bs_tried = false, bs_values = false;
   gp2s_matrix_s() {
     for (int& v : spmm_variant) v = -2;
   }

@@ -708,7 +708,7 @@ static bool spmm_tiles(const int64_t* rp, const int32_t* col, const V* val, int 
 }
 
 // variant: 0 lane per column, 1 slice per lane, 2 LDS-staged row tiles, 3 row groups,
-// G > 3 entry-parallel with G lanes per row, -1 heuristic (entry-parallel up to 32
+// 5 block split (bsplit.hip), G in {4, 8, 16} entry-parallel with G lanes per row, -1 heuristic (entry-parallel up to 32
 // columns, else one lane per column).
 template <typename V, typename PT, bool DOT>
 static hipError_t spmm_dispatch(const int64_t* rp, const int32_t* col, const V* val, int64_t n, int S,
@@ -742,6 +742,9 @@ static hipError_t spmm_dispatch(const int64_t* rp, const int32_t* col, const V* 
       if (nblocks) *nblocks = (int)gb;
       return hipGetLastError();
     }
+  } else if (G == 5) {
+    if (spmm_split<V, PT, DOT>(rp, col, val, n, S, tiles, X, Y, cs, st, grid_for(kBlock / kWave), nblocks))
+      return hipGetLastError();
   } else if (G > 3) {
     const int64_t eb = grid_for(kBlock / G);
     if (spmm_entry<V, PT, DOT>(G, rp, col, val, n, S, X, Y, cs, st, eb)) {

@@ -138,7 +138,8 @@ def test_lml_and_gradient_same_probe(case, precision, precond):
             assert grad[k] == 0.0
 
 
-BLOCK_VARIANTS = [0, 1, 2, 3, 4, 8, 16]  # lane per column, column slices, LDS tiles, row groups, 4/8/16 lanes per row
+# lane per column, column slices, LDS tiles, row groups, block split, 4/8/16 lanes per row
+BLOCK_VARIANTS = [0, 1, 2, 3, 5, 4, 8, 16]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -190,3 +191,24 @@ def test_probe_block_variants_same_probe(case, precision, S):
         print(f"[{name}/{precision}] variant {v}: logdet rel {rel:.2e} probe iters {rep.probe_iters}", flush=True)
         assert rel <= 1e-8
         assert np.all(np.abs(grad - gref) <= 1e-4 * scale)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_block_split_after_refill(case, precision):
+    """The block split's dense blocks follow a refill: the product after new amplitudes
+    and noise equals the refilled matrix's (exported) product."""
+    G = _G()
+    name, prob, Kref, gamma, ex_pts = case
+    m = G.gp2s_assemble(prob.x, params_of(prob), precision)
+    m.set_block_product(64, 5)
+    X = np.random.default_rng(12).standard_normal((prob.n, 64))
+    Y0 = G.gp2s_spmv(m, X).cpu().numpy()
+    ref0 = exported_user_csr(m)[0] @ X
+    np.testing.assert_allclose(Y0, ref0, rtol=1e-12, atol=1e-12 * np.abs(ref0).max())
+    p2 = G.HostParams(prob.dim, prob.radius, prob.bump_width, 2.5 * prob.noise_var, prob.centers,
+                      prob.weights * np.linspace(0.7, 1.3, prob.n_bumps))
+    m.refill(p2)
+    Y1 = G.gp2s_spmv(m, X).cpu().numpy()
+    ref1 = exported_user_csr(m)[0] @ X
+    assert np.abs(ref1 - ref0).max() > 1e-3 * np.abs(ref0).max()
+    np.testing.assert_allclose(Y1, ref1, rtol=1e-12, atol=1e-12 * np.abs(ref1).max())
