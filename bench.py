@@ -597,6 +597,9 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 10 M-point measurements")
     ap.add_argument("--only-large", action="store_true", help="run only the 10 M-point measurements")
     ap.add_argument("--no-parity", action="store_true", help="skip the in-run parity comparison with the oracle")
+    ap.add_argument("--only-assembly", action="store_true",
+                    help="only assemble the --config workload (float32 and float64 storage, --steps times each) and "
+                         "print the library's per-stage times: the driver for profiling the assembly kernels")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched (64-instance) measurement")
     ap.add_argument("--no-jacobi", action="store_true",
                     help="skip the same step with the diagonal preconditioner (comparison and CPU projection)")
@@ -628,6 +631,28 @@ def main():
     torch.cuda.set_device(0)
     if args.config == "c5":
         return bench_batch(args)
+    if args.only_assembly:
+        import workloads
+        prob = workloads.make_problem(args.config, n=args.n)
+        x = torch.as_tensor(prob.x).cuda()
+        params = G.HostParams(prob.dim, prob.radius, prob.bump_width, prob.noise_var, prob.centers, prob.weights)
+        ctx = G.default_context()
+        res = {"workload": f"{args.config}: n={prob.n} r={prob.radius:.6g}"}
+        for prec in ("mixed", "fp64"):
+            G.gp2s_assemble(x, params, prec).free()
+            ctx.set_timing(True)
+            for _ in range(args.steps):
+                m = G.gp2s_assemble(x, params, prec)
+                nnz = m.nnz
+                m.free()
+            st = ctx.stats()
+            ctx.set_timing(False)
+            ms = {k: st[k][0] / args.steps for k in ("asm_prep", "asm_count", "asm_fill")}
+            tot = sum(ms.values())
+            res[prec] = {"nnz": nnz, "ms": ms, "nnz_per_s": nnz / (tot / 1e3)}
+            log(f"[bench] assembly {prec}: nnz={nnz} {ms} -> {nnz / (tot / 1e3):.3g} nnz/s")
+        print(json.dumps(res), flush=True)
+        return
     if args.only_large:
         opts = G.default_opts(max_iter=args.max_iter, tol=args.tol, probe_tol=args.probe_tol, check_every=32,
                               precond=args.precond)

@@ -36,13 +36,36 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+# Host-side sanitizers for the CPU check of the runtime and validation layer (device
+# code is built as usual; each -fsanitize applies to the host pass only).
+SANITIZE = "-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined -Xarch_host -fno-omit-frame-pointer".split()
+BUILD_SAN = os.path.join(PKG, "_build_asan")
+LIB_SAN = os.path.join(BUILD_SAN, "libgp2s_asan.so")
+
+
+def _compile(src: str, sanitize: bool = False) -> str:
+    obj = os.path.join(BUILD_SAN if sanitize else BUILD, os.path.splitext(src)[0] + ".o")
+    cmd = [_hipcc(), *COMMON, *(SANITIZE if sanitize else []), "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{res.stderr[-6000:]}")
     return obj
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """libgp2s_asan.so: the same sources with the host code under AddressSanitizer and
+    UndefinedBehaviorSanitizer, for the CPU-only check of the host runtime."""
+    os.makedirs(BUILD_SAN, exist_ok=True)
+    workers = min(len(SOURCES), max(1, (os.cpu_count() or 4)))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(lambda s: _compile(s, True), SOURCES))
+    cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *SANITIZE, *objs, "-o", LIB_SAN]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"sanitized link failed:\n{res.stderr[-6000:]}")
+    if verbose:
+        print(f"built {LIB_SAN}")
+    return LIB_SAN
 
 
 def build(verbose: bool = False) -> str:

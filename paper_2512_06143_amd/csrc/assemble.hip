@@ -7,8 +7,9 @@
 // tested, and a pair is stored when ||x_i - x_j|| < r and both points lie inside
 // some bump (the diagonal always).
 //
-// One wavefront owns one row. Lanes take consecutive candidates of a neighbour-bin
-// run (bins adjacent along x are contiguous in the sorted order), test them, and the
+// One wavefront owns one row. Lanes take consecutive candidates of the row's neighbour-
+// bin runs (bins adjacent along x are contiguous in the sorted order; the runs are
+// concatenated in ascending order), test them, and the
 // wave ballot plus the lane's popcount prefix (mbcnt) give every survivor its slot,
 // so each row is written as one contiguous, ascending, coalesced run. The count
 // pass and the fill pass execute the same candidate sequence and the same test.
@@ -74,57 +75,73 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs a, int64_t nbl
   const int nbx = a.grid.nb[0], nby = a.grid.nb[1], nbz = a.grid.nb[2];
   const int x0 = bx > 0 ? bx - 1 : 0;
   const int x1 = bx + 1 < nbx ? bx + 1 : nbx - 1;
+  // The 3^(d-1) runs of neighbouring bins (bins adjacent along x are contiguous in the
+  // sorted order), in ascending order, concatenated into one candidate list: run r starts
+  // at rs[r] and takes candidate indices pre[r] .. pre[r + 1] - 1. Lanes then take 64
+  // consecutive candidates of the list, across run boundaries, so short runs do not leave
+  // most lanes of a step idle.
+  constexpr int NR = DIM == 3 ? 9 : 3;
+  int64_t rs[NR];
+  int32_t pre[NR + 1];
+  pre[0] = 0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int dz = DIM == 3 ? r / 3 - 1 : 0, dy = r % 3 - 1;
+    const int zz = bz + dz, yy = by + dy;
+    int64_t s0 = 0, e0 = 0;
+    if (zz >= 0 && zz < nbz && yy >= 0 && yy < nby) {
+      const int64_t rb = ((int64_t)zz * nby + yy) * nbx;
+      s0 = a.bin_start[rb + x0];
+      e0 = a.bin_start[rb + x1 + 1];
+    }
+    rs[r] = s0;
+    pre[r + 1] = pre[r] + (int32_t)(e0 - s0);
+  }
+  const int32_t C = pre[NR];
   int64_t cnt = 0;
   const double gi64 = a.g64[row];
   const bool gen = a.kg.general != 0;
   const double li = a.kg.lsq ? a.kg.lsq[row] : 1.0;
 
-  for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
-    const int zz = bz + dz;
-    if (zz < 0 || zz >= nbz) continue;
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int yy = by + dy;
-      if (yy < 0 || yy >= nby) continue;
-      const int64_t rb = ((int64_t)zz * nby + yy) * nbx;
-      const int64_t s = a.bin_start[rb + x0];
-      const int64_t e = a.bin_start[rb + x1 + 1];
-      for (int64_t c = s; c < e; c += kWave) {
-        const int64_t j = c + lane;
-        const bool ok = j < e;
-        bool pass;
-        float4 pj32;
-        double4 pj64;
-        const double lj = (a.kg.lsq && ok) ? a.kg.lsq[j] : 1.0;
-        if (F32) {
-          pj32 = ok ? a.pts32[j] : make_float4(0.f, 0.f, 0.f, pt_out_f32());
-          pass = ok && (j == row || (pt_in(pj32.w) && (gen ? gen_pass_f32<DIM>(pi32, pj32, a.kg, li, lj)
-                                                            : sqdist_f32<DIM>(pi32, pj32) < a.r2f)));
-        } else {
-          pj64 = ok ? a.pts64[j] : make_double4(0., 0., 0., pt_out_f64());
-          pass = ok && (j == row || (pt_in(pj64.w) && (gen ? gen_pass_f64<DIM>(pi64, pj64, a.kg, li, lj)
-                                                           : sqdist_f64<DIM>(pi64, pj64) < a.r2)));
-        }
-        const uint64_t m = __ballot(pass);
-        const int64_t pos = base + cnt + lane_prefix(m);
-        if (FILL && pass && pos < end) {  // never past the row counted by the first pass
-          col[pos] = (int32_t)j;
-          if (F32) {
-            float v = (j == row) ? (float)(gi64 * gi64 + a.noise)
-                      : gen ? gen_entry_f32<DIM>(pi32, pj32, a.kg, li, lj, a.kern)
-                            : entry_f32(pi32, pj32, a.r2, a.inv_r2, a.kern);
-            static_cast<float*>(val)[pos] = v;
-            if (j == row) diag[row] = (double)v;
-          } else {
-            double v = (j == row) ? gi64 * gi64 + a.noise
-                       : gen ? gen_entry_f64<DIM>(pi64, pj64, a.kg, li, lj, a.kern)
-                             : entry_f64(pi64, pj64, a.r2, a.inv_r2, a.kern);
-            static_cast<double*>(val)[pos] = v;
-            if (j == row) diag[row] = v;
-          }
-        }
-        cnt += __popcll(m);
+  for (int32_t c0 = 0; c0 < C; c0 += kWave) {
+    const int32_t idx = c0 + lane;
+    const bool ok = idx < C;
+    int64_t j = rs[0] + idx;
+#pragma unroll
+    for (int r = 1; r < NR; ++r)
+      if (idx >= pre[r]) j = rs[r] + (idx - pre[r]);  // empty runs are overridden by the next
+    bool pass;
+    float4 pj32;
+    double4 pj64;
+    const double lj = (a.kg.lsq && ok) ? a.kg.lsq[j] : 1.0;
+    if (F32) {
+      pj32 = ok ? a.pts32[j] : make_float4(0.f, 0.f, 0.f, pt_out_f32());
+      pass = ok && (j == row || (pt_in(pj32.w) && (gen ? gen_pass_f32<DIM>(pi32, pj32, a.kg, li, lj)
+                                                        : sqdist_f32<DIM>(pi32, pj32) < a.r2f)));
+    } else {
+      pj64 = ok ? a.pts64[j] : make_double4(0., 0., 0., pt_out_f64());
+      pass = ok && (j == row || (pt_in(pj64.w) && (gen ? gen_pass_f64<DIM>(pi64, pj64, a.kg, li, lj)
+                                                       : sqdist_f64<DIM>(pi64, pj64) < a.r2)));
+    }
+    const uint64_t m = __ballot(pass);
+    const int64_t pos = base + cnt + lane_prefix(m);
+    if (FILL && pass && pos < end) {  // never past the row counted by the first pass
+      col[pos] = (int32_t)j;
+      if (F32) {
+        float v = (j == row) ? (float)(gi64 * gi64 + a.noise)
+                  : gen ? gen_entry_f32<DIM>(pi32, pj32, a.kg, li, lj, a.kern)
+                        : entry_f32(pi32, pj32, a.r2, a.inv_r2, a.kern);
+        static_cast<float*>(val)[pos] = v;
+        if (j == row) diag[row] = (double)v;
+      } else {
+        double v = (j == row) ? gi64 * gi64 + a.noise
+                   : gen ? gen_entry_f64<DIM>(pi64, pj64, a.kg, li, lj, a.kern)
+                         : entry_f64(pi64, pj64, a.r2, a.inv_r2, a.kern);
+        static_cast<double*>(val)[pos] = v;
+        if (j == row) diag[row] = v;
       }
     }
+    cnt += __popcll(m);
   }
   if (!FILL && lane == 0) row_cnt[row] = (int32_t)cnt;
 }

@@ -137,8 +137,16 @@ __device__ inline double4 promote(const float4& p) { return make_double4(p.x, p.
 // eigenvalue of the stored matrix below zero (measured on the densest regions of a
 // 10 M-point clustered cloud: -7.5e-5 against sigma_n^2 = 1e-4), while one rounding
 // per entry kept it at 0.91 sigma_n^2. The support test stays in float32.
+// In float64, 1 - rho = 1 - sqrt(rho^2) is accurate to ~2e-16 absolute, so W's relative
+// error, about 8e-16 / (1 - rho), stays below the float32 rounding (6e-8) wherever
+// 1 - rho > 1.3e-8 (W > 1.4e-31): the division of the float64 path's t / (1 + rho) is
+// not needed for a float32-stored value.
 __device__ inline float entry_f32(const float4& pi, const float4& pj, double r2, double inv_r2, int kern) {
-  return (float)entry_f64(promote(pi), promote(pj), r2, inv_r2, kern);
+  const double dx = (double)pi.x - (double)pj.x, dy = (double)pi.y - (double)pj.y, dz = (double)pi.z - (double)pj.z;
+  const double d2 = dx * dx + dy * dy + dz * dz;
+  const double rho = sqrt(d2 * inv_r2);
+  const double om = fmax(1.0 - rho, 0.0);
+  return (float)((double)pi.w * (double)pj.w * wendland_w<double>(kern, rho, om));
 }
 
 // ---- general kernel (Eq. wendconv with axis radii and the length-scale field) ------

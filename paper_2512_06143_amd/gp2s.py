@@ -192,7 +192,9 @@ class Context:
     """A library context bound to a HIP stream (default: torch's current stream) whose
     device allocations go through torch's caching allocator."""
 
-    def __init__(self, stream=None, use_torch_allocator=True):
+    def __init__(self, stream=None, use_torch_allocator=True, alloc=None, free=None):
+        """alloc(nbytes) -> device pointer or None, free(ptr): custom device allocator
+        callbacks (both or neither); otherwise torch's caching allocator (or hipMalloc)."""
         import torch
         self._torch = torch
         self.device = torch.device("cuda", torch.cuda.current_device()) if torch.cuda.is_available() else None
@@ -200,7 +202,10 @@ class Context:
             stream = torch.cuda.current_stream()
         self.stream = stream
         handle = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
-        if use_torch_allocator and torch.cuda.is_available():
+        if alloc is not None and free is not None:
+            self._alloc = ALLOC_FN(lambda nbytes, user: alloc(int(nbytes)))
+            self._free = FREE_FN(lambda ptr, user: free(int(ptr)))
+        elif use_torch_allocator and torch.cuda.is_available():
             dev = self.device.index
             tstream = stream
 

@@ -130,3 +130,29 @@ def test_batch_block_preconditioner_against_oracle(gpu, precision):
         assert abs(lml[i] - lml_j[i]) <= 0.5 * noise + 1e-8 * abs(lml[i])
     b.free()
     bj.free()
+
+
+def test_batch_with_a_large_instance(gpu):
+    """A 60 000-point instance beside two small ones (2-D and 3-D): each instance equals
+    its own single-instance run on the same probes (diagonal preconditioner, so both
+    define the same estimator), and every residual meets the tolerance."""
+    G = _G()
+    probs = [workloads.make_random_problem(90, 60_000, 2, 0.0146, n_bumps=4, bump_width=0.55),
+             workloads.make_random_problem(91, 1800, 3, 0.1, n_bumps=3, bump_width=0.5, points="gmm"),
+             workloads.make_random_problem(92, 900, 2, 0.06, n_bumps=2, bump_width=0.55)]
+    S = 16
+    opts = G.default_opts(n_probes=S, seed=8, tol=1e-10, probe_tol=1e-9, max_iter=40000, precond="jacobi")
+    b = G.Batch([p.x for p in probs], [params_of(p) for p in probs], "mixed", opts)
+    print(f"[batch/large] {b.info()}", flush=True)
+    lml, grads, reps = b.run([p.y for p in probs])
+    for i, p in enumerate(probs):
+        m = G.gp2s_assemble(p.x, params_of(p), "mixed")
+        rep, g1, _ = G.gp2s_lml_grad(m, p.y, opts)
+        print(f"[batch/large] instance {i}: n={p.n} lml {lml[i]:.8f} single {rep.lml:.8f} iters "
+              f"{reps[i]['iters']}/{reps[i]['probe_iters']}", flush=True)
+        assert abs(lml[i] - rep.lml) <= 1e-9 * abs(rep.lml)
+        scale = np.maximum(np.abs(g1), 1e-8 * np.abs(g1).max())
+        assert np.all(np.abs(grads[i] - g1) <= 1e-6 * scale), (i, grads[i], g1)
+        assert reps[i]["resid"] <= 1e-10
+        m.free()
+    b.free()

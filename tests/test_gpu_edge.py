@@ -267,3 +267,49 @@ def test_timing_mask_records_only_selected_categories(gpu):
         ctx.set_timing(False)
     assert all(cnt == 0 for _, cnt in ctx.stats().values())
     m.free()
+
+
+def test_allocator_failure_reports_oom_without_leak(gpu):
+    """A device allocator that fails on its k-th call: assembly or the LML+gradient
+    returns GP2S_E_OOM (never a crash or another status), and once the handles and the
+    context are released every allocation has been freed."""
+    import torch
+    G = _G()
+    prob = workloads.make_random_problem(17, 900, 2, 0.08, n_bumps=3, bump_width=0.5)
+    opts = G.default_opts(n_probes=8, seed=1)
+    live = {}
+    calls = [0, -1]  # calls so far, the call that fails
+
+    def alloc(nbytes):
+        calls[0] += 1
+        if calls[0] == calls[1]:
+            return None
+        p = torch.cuda.caching_allocator_alloc(nbytes, 0, torch.cuda.current_stream())
+        live[p] = nbytes
+        return p
+
+    def free(p):
+        live.pop(p)
+        torch.cuda.caching_allocator_delete(p)
+
+    def run():
+        ctx = G.Context(alloc=alloc, free=free)
+        try:
+            m = G.gp2s_assemble(prob.x, params_of(prob), "mixed", ctx)
+            try:
+                G.gp2s_lml_grad(m, prob.y, opts)
+            finally:
+                m.free()
+        finally:
+            ctx.close()
+
+    run()
+    total = calls[0]
+    assert total > 5 and not live
+    for k in sorted(set(np.linspace(1, total, 15).astype(int))):
+        calls[0], calls[1] = 0, int(k)
+        with pytest.raises(G.GP2SError) as e:
+            run()
+        print(f"[oom] failing allocation {k} of {total}: status {e.value.status}", flush=True)
+        assert e.value.status == 3
+        assert not live, f"{len(live)} allocations leaked after failing call {k}"
