@@ -46,6 +46,7 @@ def log(msg):
 
 
 def kernel_bytes(cat, n, nnz, S, prec, precond="block"):
+    mrow = 64 if precond in ("block64", 2) else 128                # M^-1 values per row
     """Algorithmic HBM bytes of one launch of a timed kernel category: the CSR once,
     each vector stream once, at the types the path stores them in (the probe block
     of the mixed path keeps its search directions P and, with the block
@@ -57,11 +58,11 @@ def kernel_bytes(cat, n, nnz, S, prec, precond="block"):
     K = nnz * (4 + vb) + (n + 1) * 8
     if cat in ("cg_matvec_block", "cg_matvec1", "spmv"):
         return K + n * S * (pb + 8)                 # read P once, write Q
-    if precond == "block":
+    if precond in ("block", "block64", 1, 2):
         zb = 4 if (prec == "mixed" and block) else 8        # stored z
-        mb = 8 if block else 4                              # M^-1 element (64 per row)
+        mb = 8 if block else 4                              # M^-1 element (mrow per row)
         if cat in ("cg_update_block", "cg_update1"):
-            return n * S * (8 * 4 + pb + 8 + zb) + n * 64 * mb  # X, R read+write; P, Q read; z written; M^-1
+            return n * S * (8 * 4 + pb + 8 + zb) + n * mrow * mb  # X, R read+write; P, Q read; z written; M^-1
         if cat in ("cg_pupdate_block", "cg_pupdate1"):
             return n * S * (zb + pb * 2)            # z read; P read+write
     if cat in ("cg_update_block", "cg_update1"):
@@ -386,7 +387,8 @@ def bench_variants(G, x, y, params, precision, opts, steps=1):
     return out
 
 
-def bench_large(G, opts, config="c4", reps=3, spmv_reps=20, caps=(20, 100, 300), converge_y=True):
+def bench_large(G, opts, config="c4", reps=3, spmv_reps=20, caps=(20, 100, 300), converge_y=True,
+                precond="block64"):
     """The 10 000 000-point clustered workload, float32 and float64 storage (outside the
     timed steps: a converged LML+gradient at this size takes minutes).
 
@@ -402,7 +404,10 @@ def bench_large(G, opts, config="c4", reps=3, spmv_reps=20, caps=(20, 100, 300),
     * the float32-stored y solve to convergence (its iteration count);
     * projected s per LML+gradient = assembly + first-call extra + fixed + per-iteration
       x the y solve's iteration count to convergence (an upper bound: the probe block
-      stops at its looser tolerance no later than the y solve in every run seen)."""
+      stops at its looser tolerance no later than the y solve in every run seen).
+    The solves use the block preconditioner over 64-point runs: on this clustered cloud
+    the y solve takes 30 877 iterations with them and 31 113 with 128-point runs, which
+    cost more per iteration."""
     import numpy as np
     import torch
     import workloads
@@ -420,7 +425,8 @@ def bench_large(G, opts, config="c4", reps=3, spmv_reps=20, caps=(20, 100, 300),
 
     def capped(cap):
         return G.default_opts(n_probes=S, max_iter=cap, tol=float(opts.tol), probe_tol=float(opts.probe_tol),
-                              check_every=32, precond=int(opts.precond))
+                              check_every=32, precond=precond)
+    out["precond"] = precond
 
     for prec in ("mixed", "fp64"):
         G.gp2s_assemble(x, params, prec).free()  # warm
@@ -466,8 +472,7 @@ def bench_large(G, opts, config="c4", reps=3, spmv_reps=20, caps=(20, 100, 300),
         roof = {}
         for cat in ("cg_matvec_block", "cg_update_block", "cg_pupdate_block", "cg_matvec1", "cg_update1"):
             if cat in kern:
-                bb = kernel_bytes(cat, n, nnz, S if "block" in cat else 1, prec,
-                                  "block" if int(opts.precond) == 1 else "jacobi")
+                bb = kernel_bytes(cat, n, nnz, S if "block" in cat else 1, prec, precond)
                 avg = kern[cat]["ms_avg"] / 1e3
                 roof[cat] = {"bound": "hbm", "achieved": bb / avg / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                              "frac": bb / avg / PEAK_HBM, "bytes_per_launch": bb, "avg_ms": avg * 1e3}
@@ -486,7 +491,7 @@ def bench_large(G, opts, config="c4", reps=3, spmv_reps=20, caps=(20, 100, 300),
             ctx.set_progress(prog)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            a, rep = G.gp2s_solve(m, y, G.default_opts(max_iter=200000, tol=float(opts.tol), precond=int(opts.precond),
+            a, rep = G.gp2s_solve(m, y, G.default_opts(max_iter=200000, tol=float(opts.tol), precond=precond,
                                                        check_every=32), allow_noconv=True)
             torch.cuda.synchronize()
             ty = time.perf_counter() - t0
@@ -603,7 +608,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched (64-instance) measurement")
     ap.add_argument("--no-jacobi", action="store_true",
                     help="skip the same step with the diagonal preconditioner (comparison and CPU projection)")
-    ap.add_argument("--precond", default="block", choices=["block", "jacobi"],
+    ap.add_argument("--precond", default="block", choices=["block", "block64", "jacobi"],
                     help="preconditioner of the timed step (the other one is timed once beside it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for the HBM byte counters)")

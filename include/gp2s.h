@@ -127,10 +127,13 @@ typedef struct {
   int32_t precond;        /* preconditioner M of every CG solve [GP2S_PRECOND_BLOCK]:
                              GP2S_PRECOND_JACOBI (0): M = diag(K);
                              GP2S_PRECOND_BLOCK (1): M = the block diagonal of K over
-                             runs of 64 consecutive points of the handle's internal
+                             runs of 128 consecutive points of the handle's internal
                              order (the bin order of an assembled handle, the given
                              order of an imported one; the last run holds the
-                             remainder), factored M = L L^T blockwise by Cholesky.
+                             remainder), factored M = L L^T blockwise by Cholesky;
+                             GP2S_PRECOND_BLOCK64 (2): the same over runs of 64 points
+                             (cheaper per iteration; on strongly clustered clouds it
+                             converges in as few iterations).
                              The log-determinant estimate is ln|M| + the Lanczos
                              estimate of ln|L^-1 K L^-T| on right-hand sides L z_s; the
                              gradient's trace uses q_s = K^-1 L z_s and w_s = L^-T z_s.
@@ -145,6 +148,7 @@ typedef struct {
 } gp2s_solve_opts;
 #define GP2S_PRECOND_JACOBI 0
 #define GP2S_PRECOND_BLOCK 1
+#define GP2S_PRECOND_BLOCK64 2
 
 /* Filled on return (HOST struct). */
 typedef struct {

@@ -41,7 +41,7 @@ from .sparse import (covariance_csr, covariance_rows, residual_rel, pcg_jacobi, 
                      lanczos_logquad, lml_grad_sparse)
 from .posterior import cross_covariance, posterior_dense
 from .mcmc import block_mh
-from .precond import (BLOCK, grid, bin_coords, bin_order, block_partition, jacobi_partition, block_factor,
+from .precond import (BLOCK, BLOCK_SMALL, BATCH_BLOCK, grid, bin_coords, bin_order, block_partition, jacobi_partition, block_factor,
                       morton, sub_cell_codes)
 
 __all__ = [
@@ -54,7 +54,7 @@ __all__ = [
     "splitmix64", "rademacher_probes", "probe_sign_masks",
     "logdet_same_probe", "grad_same_probe", "lml_same_probe", "hutchinson_variance",
     "cross_covariance", "posterior_dense", "block_mh",
-    "BLOCK", "grid", "bin_coords", "bin_order", "block_partition", "jacobi_partition", "block_factor",
+    "BLOCK", "BLOCK_SMALL", "BATCH_BLOCK", "grid", "bin_coords", "bin_order", "block_partition", "jacobi_partition", "block_factor",
     "morton", "sub_cell_codes",
     "covariance_csr", "covariance_rows", "residual_rel", "pcg_jacobi", "dcov_csr", "lml_components",
     "lanczos_logquad", "lml_grad_sparse",

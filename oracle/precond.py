@@ -22,7 +22,9 @@ from __future__ import annotations
 
 import numpy as np
 
-BLOCK = 64
+BLOCK = 128            # points per block of a single matrix's preconditioner (the default)
+BLOCK_SMALL = 64       # the smaller block a single matrix may use instead
+BATCH_BLOCK = 64       # points per block inside each instance of a batch
 
 
 def grid(x, radius, ell_bound=1.0, refine=1, min_cells=65536):

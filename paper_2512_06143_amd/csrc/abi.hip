@@ -289,33 +289,34 @@ gp2s_status tune_block_product(gp2s_ctx ctx, gp2s_matrix m, int S, const void* P
 // is reported here).
 // The float32 copy of M^-1 serves single-column solves that are not probe solves (their
 // preconditioner only steers convergence); everything else applies the float64 one.
-const float* bj_m32(const Cg& c) { return c.S == 1 && !c.probe ? c.m->bj_M32 : nullptr; }
+const float* bj_m32(const Cg& c) { return c.S == 1 && !c.probe ? c.m->bj[pc_idx(c.precond)].M32 : nullptr; }
 
-gp2s_status ensure_bj(gp2s_ctx ctx, gp2s_matrix m) {
-  if (m->bj_ready) return GP2S_OK;
+gp2s_status ensure_bj(gp2s_ctx ctx, gp2s_matrix m, int precond) {
+  auto& f = m->bj[pc_idx(precond)];
+  if (f.ready) return GP2S_OK;
   const int64_t n = m->n;
-  const size_t nblk = (size_t)((n + kBJ - 1) / kBJ);
-  if (!m->bj_L) {
-    m->bj_L = own<double>(m, nblk * kBJ * kBJ);
-    m->bj_M = own<double>(m, nblk * kBJ * kBJ);
-    m->bj_M32 = own<float>(m, nblk * kBJ * kBJ);
-    m->bj_piv = own<double>(m, (size_t)n);
-    if (!m->bj_L || !m->bj_M || !m->bj_M32 || !m->bj_piv)
-      return fail(ctx, GP2S_E_OOM, "block preconditioner allocation failed");
+  const int B = pc_rows(precond);
+  const size_t nblk = (size_t)((n + B - 1) / B);
+  if (!f.L) {
+    f.L = own<double>(m, nblk * B * B);
+    f.M = own<double>(m, nblk * B * B);
+    f.M32 = own<float>(m, nblk * B * B);
+    f.piv = own<double>(m, (size_t)n);
+    if (!f.L || !f.M || !f.M32 || !f.piv) return fail(ctx, GP2S_E_OOM, "block preconditioner allocation failed");
   }
   Scratch sc(ctx);
   int32_t* bad = sc.get<int32_t>(1);
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "block preconditioner workspace allocation failed");
   HIPCHK(hipMemsetAsync(bad, 0, sizeof(int32_t), ctx->stream));
-  HIPCHK(launch_bj_factor(n, m->row_ptr, m->col, m->val, m->prec, m->ffG, m->ffU, m->bj_L, m->bj_M, m->bj_M32, m->bj_piv, bad,
-                          ctx->stream));
+  HIPCHK(launch_bj_factor(n, m->row_ptr, m->col, m->val, m->prec, m->ffG, m->ffU, f.L, f.M, f.M32, f.piv, bad,
+                          ctx->stream, BjBlocks{nullptr, nullptr, 0}, B));
   int32_t hb = 0;
   gp2s_status st = readback(ctx, bad, sizeof(int32_t), &hb);
   if (st) return st;
   if (hb)
     return fail(ctx, GP2S_E_NOT_SPD,
-                "a 64-point diagonal block of K is not positive definite (Cholesky pivot <= 0 in float64)");
-  m->bj_ready = true;
+                "a %d-point diagonal block of K is not positive definite (Cholesky pivot <= 0 in float64)", B);
+  f.ready = true;
   return GP2S_OK;
 }
 
@@ -334,8 +335,8 @@ gp2s_status cg_begin(Cg& c, const double* B, double tol, bool keep_hist, Scratch
   c.f32vec = m->prec == GP2S_MIXED && S > 1 && !m->ffG;
   const size_t vb = c.f32vec ? sizeof(float) : sizeof(double);
   c.R = sc.get<double>(nS);
-  if (c.precond == GP2S_PRECOND_BLOCK) c.Z = sc.get<double>(nS);
-  if (c.precond == GP2S_PRECOND_BLOCK && c.f32vec) c.Z32 = sc.get<float>(nS);
+  if (pc_block(c.precond)) c.Z = sc.get<double>(nS);
+  if (pc_block(c.precond) && c.f32vec) c.Z32 = sc.get<float>(nS);
   if (m->ffG) {
     c.lrC = sc.get<double>((size_t)m->ffU * S);
     c.lrPart = sc.get<double>((size_t)m->ffU * S * ff_gtp_blocks(n));
@@ -374,10 +375,13 @@ gp2s_status cg_begin(Cg& c, const double* B, double tol, bool keep_hist, Scratch
     cs.lrC = c.lrC;
     cs.lrU = m->ffU;
   }
-  if (c.precond == GP2S_PRECOND_BLOCK) {
-    if (!m->bj_ready) return fail(ctx, GP2S_E_INVALID, "block preconditioner not built (%s)", c.label);
-    HIPCHK(launch_bj_update(n, S, B, c.X, c.R, nullptr, nullptr, c.f32vec, m->bj_M, c.Z, cs, c.st, bj_m32(c)));
-    HIPCHK(launch_cg_init_fin(cs, (int)bj_update_blocks(n), S, tol, c.st));
+  if (pc_block(c.precond)) {
+    const auto& f = m->bj[pc_idx(c.precond)];
+    const int rows = pc_rows(c.precond);
+    if (!f.ready) return fail(ctx, GP2S_E_INVALID, "block preconditioner not built (%s)", c.label);
+    HIPCHK(launch_bj_update(n, S, B, c.X, c.R, nullptr, nullptr, c.f32vec, f.M, c.Z, cs, c.st, bj_m32(c), nullptr,
+                            rows));
+    HIPCHK(launch_cg_init_fin(cs, (int)bj_update_blocks(n, rows), S, tol, c.st));
     HIPCHK(launch_copy_dir(n, S, c.Z, c.P, c.f32vec, c.st));
   } else {
     HIPCHK(launch_cg_init(n, S, B, m->dinv, c.X, c.R, c.P, c.f32vec, cs, tol, c.st));
@@ -422,11 +426,12 @@ gp2s_status cg_step(Cg& c) {
            launch_cg_matvec(m->prec, m->row_ptr, m->col, m->val, n, S, (double)m->nnz / (double)n, c.variant,
                             tile_set(m), c.P, c.Q, c.f32vec, c.cs, c.st, row_blocks(m)));
   if (m->ffG) HIPCHK(launch_ff_add(n, S, m->ffU, m->ffG, c.lrC, S, 1, static_cast<double*>(c.Q), c.st));
-  if (c.precond == GP2S_PRECOND_BLOCK) {
+  if (pc_block(c.precond)) {
+    const int rows = pc_rows(c.precond);
     TIMED_ON(S == 1 ? GP2S_T_CG_UPDATE1 : GP2S_T_CG_UPDATE_BLOCK, c.st,
-             launch_bj_update(n, S, nullptr, c.X, c.R, c.P, c.Q, c.f32vec, m->bj_M, c.Z, c.cs, c.st, bj_m32(c),
-                              c.Z32));
-    HIPCHK(launch_cg_beta(c.cs, (int)bj_update_blocks(n), S, c.it, c.st));
+             launch_bj_update(n, S, nullptr, c.X, c.R, c.P, c.Q, c.f32vec, m->bj[pc_idx(c.precond)].M, c.Z, c.cs,
+                              c.st, bj_m32(c), c.Z32, rows));
+    HIPCHK(launch_cg_beta(c.cs, (int)bj_update_blocks(n, rows), S, c.it, c.st));
     TIMED_ON(S == 1 ? GP2S_T_CG_PUPDATE1 : GP2S_T_CG_PUPDATE_BLOCK, c.st,
              c.Z32 ? launch_cg_pupdate_z32(n, S, c.P, c.Z32, c.f32vec, c.cs, c.st)
                    : launch_cg_pupdate(n, S, c.P, c.Z, nullptr, c.f32vec, c.cs, c.st));
@@ -686,8 +691,9 @@ gp2s_status probes_begin(gp2s_ctx ctx, gp2s_matrix m, const gp2s_solve_opts* o, 
   double* B = sc.get<double>((size_t)n * S);
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "probe workspace allocation failed");
   HIPCHK(launch_probe_masks(n, m->perm, o->seed, S, mask, ctx->aux));
-  if (o->precond == GP2S_PRECOND_BLOCK)
-    HIPCHK(launch_bj_rhs(n, S, mask, m->bj_L, B, ctx->aux));
+  if (pc_block(o->precond))
+    HIPCHK(launch_bj_rhs(n, S, mask, m->bj[pc_idx(o->precond)].L, B, ctx->aux, BjBlocks{nullptr, nullptr, 0},
+                         pc_rows(o->precond)));
   else
     HIPCHK(launch_probe_rhs(n, S, mask, m->diag, B, ctx->aux));
   cp.ctx = ctx;
@@ -724,7 +730,7 @@ gp2s_status probes_finish(gp2s_ctx ctx, gp2s_matrix m, Scratch& sc, const Cg& cp
   gp2s_status st = readback(ctx, quad, S * sizeof(double), qh.data());
   if (st) return st;
   double sumlog = 0.0;
-  HIPCHK(launch_sum_log(n, cp.precond == GP2S_PRECOND_BLOCK ? m->bj_piv : m->diag, red, tk, ctx->stream));
+  HIPCHK(launch_sum_log(n, pc_block(cp.precond) ? m->bj[pc_idx(cp.precond)].piv : m->diag, red, tk, ctx->stream));
   st = readback(ctx, red, sizeof(double), &sumlog);
   if (st) return st;
   double mean = 0.0;
@@ -788,7 +794,7 @@ gp2s_status lml_common(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_
   double* yi = sc.get<double>(n);
   double* ai = sc.get<double>(n);
   double* Qs = grad ? sc.get<double>((size_t)n * S) : nullptr;  // probe solutions (gradient only)
-  double* Ws = grad && o->precond == GP2S_PRECOND_BLOCK ? sc.get<double>((size_t)n * S) : nullptr;
+  double* Ws = grad && pc_block(o->precond) ? sc.get<double>((size_t)n * S) : nullptr;
   uint64_t* mask = sc.get<uint64_t>(n);
   double* red = sc.get<double>(1 + kReduceBlocks);
   uint32_t* tk = sc.get<uint32_t>(1);
@@ -796,9 +802,9 @@ gp2s_status lml_common(gp2s_ctx ctx, gp2s_matrix m, const double* y, const gp2s_
   HIPCHK(hipMemsetAsync(tk, 0, sizeof(uint32_t), ctx->stream));
   HIPCHK(launch_gather_rows(n, 1, m->perm, y, yi, ctx->stream));
   std::memset(rep, 0, sizeof(*rep));
-  if (o->precond == GP2S_PRECOND_BLOCK) {
+  if (pc_block(o->precond)) {
     if (!m->diag_ok) return fail(ctx, GP2S_E_NOT_SPD, "diagonal of K is not positive");
-    st = ensure_bj(ctx, m);
+    st = ensure_bj(ctx, m, o->precond);
     if (st) return st;
   }
   // The probe block runs on the second stream beside the y solve: it starts after
@@ -1427,7 +1433,7 @@ gp2s_status gp2s_matrix_refill(gp2s_ctx ctx, gp2s_matrix m, const gp2s_params* p
   if (st) return st;
   hipStream_t sm = ctx->stream;
   const int64_t n = m->n;
-  m->bj_ready = false;  // the block factor belongs to the old values
+  m->bj[0].ready = m->bj[1].ready = false;  // the block factors belong to the old values
   m->grp_values = false;  // and so do the grouped copy's values
   m->bs_values = false;   // and the block split's dense blocks
   m->weights_h.assign(p->weights, p->weights + p->n_bumps);
@@ -1590,8 +1596,8 @@ gp2s_status gp2s_solve(gp2s_ctx ctx, gp2s_matrix m, const double* y, double* a, 
   gp2s_report local{};
   gp2s_report* r = rep ? rep : &local;
   std::memset(r, 0, sizeof(*r));
-  if (o->precond == GP2S_PRECOND_BLOCK && m->diag_ok) {
-    st = ensure_bj(ctx, m);
+  if (pc_block(o->precond) && m->diag_ok) {
+    st = ensure_bj(ctx, m, o->precond);
     if (st) return st;
   }
   bool conv = false;
@@ -1708,9 +1714,9 @@ gp2s_status gp2s_predict(gp2s_ctx ctx, gp2s_matrix m, int64_t n_test, const doub
   int32_t blocks = 0, worst = 0;
   bool conv = true;
   if (var) {
-    if (o->precond == GP2S_PRECOND_BLOCK) {
+    if (pc_block(o->precond)) {
       if (!m->diag_ok) return fail(ctx, GP2S_E_NOT_SPD, "diagonal of K is not positive");
-      st = ensure_bj(ctx, m);
+      st = ensure_bj(ctx, m, o->precond);
       if (st) return st;
     }
     double* B = sc.get<double>((size_t)n * kVarBlock);

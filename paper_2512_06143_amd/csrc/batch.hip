@@ -878,9 +878,9 @@ __global__ __launch_bounds__(kBJThreads) void k_bbj_update(BatchGeom g, int S, c
     }
   }
   __syncthreads();
-  bj_apply_block(Rs, Mfrag + br.blk * (int64_t)(kBJ * kBJ), m, S, r0, Z, rz);
+  bj_apply_block<kBJ>(Rs, Mfrag + br.blk * (int64_t)(kBJ * kBJ), m, S, r0, Z, rz);
   __syncthreads();
-  const double rzt = bj_rz_total(rz, red, S);
+  const double rzt = bj_rz_total<kBJThreads / kWave>(rz, red, S);
   if (t < S) cs.partial[(int64_t)t * g.nblk + br.blk] = rzt;
   Rs[t] = rr;  // thread t holds column t % S (threads >= nth hold zero)
   __syncthreads();

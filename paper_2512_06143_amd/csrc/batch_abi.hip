@@ -325,7 +325,7 @@ gp2s_status bcg_begin(BCg& c, const double* B, const double* tol_dev, double tol
   const size_t vb = c.f32vec ? sizeof(float) : sizeof(double);
   c.max_iter = b->opts.max_iter;
   c.R = sc.get<double>((size_t)n * S);
-  c.bj = b->opts.precond == GP2S_PRECOND_BLOCK && b->bj_M;
+  c.bj = pc_block(b->opts.precond) && b->bj_M;
   c.Z = c.bj ? sc.get<double>((size_t)n * S) : nullptr;
   c.P = sc.get<uint8_t>((size_t)n * S * vb);
   c.Q = sc.get<double>((size_t)n * S);
@@ -572,7 +572,7 @@ gp2s_status factor_blocks(gp2s_batch b) {
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "allocation failed");
   HIPCHK(hipMemsetAsync(bad, 0, sizeof(int32_t), st));
   HIPCHK(launch_bj_factor(b->N, b->row_ptr, b->col, b->val, b->prec, nullptr, 0, b->bj_L, b->bj_M, b->bj_M32, b->bj_piv, bad, st,
-                          bj_blocks(b)));
+                          bj_blocks(b), kBJ));
   int32_t hb = 0;
   gp2s_status s = readback(ctx, bad, sizeof(hb), &hb);
   if (s) return s;
@@ -845,7 +845,7 @@ gp2s_status gp2s_batch_run(gp2s_batch b, const double* const* y, const gp2s_para
     st = assemble_fill(b, sc2);
     if (st) return st;
   }
-  if (b->opts.precond == GP2S_PRECOND_BLOCK) {
+  if (pc_block(b->opts.precond)) {
     st = factor_blocks(b);
     if (st) return st;
   }
@@ -884,13 +884,13 @@ gp2s_status gp2s_batch_run(gp2s_batch b, const double* const* y, const gp2s_para
     if (!is_fin(bb[i])) return fail(ctx, GP2S_E_NONFINITE, "y[%d] contains NaN or infinity", i);
   // The probe block runs on its own stream beside the y solves (both start after the
   // work queued so far on the context's stream and are joined back into it).
-  const bool bj = b->opts.precond == GP2S_PRECOND_BLOCK;
+  const bool bj = pc_block(b->opts.precond);
   // trace vectors of the gradient: L^-T z (block preconditioner; the probe solve's first z)
   double* W = bj ? sc.get<double>((size_t)N * S) : nullptr;
   if (sc.oom) return fail(ctx, GP2S_E_OOM, "batch run workspace allocation failed");
   HIPCHK(launch_bprobe_masks(g, b->perm, b->opts.seed, S, mask, sm));
   if (bj)
-    HIPCHK(launch_bj_rhs(N, S, mask, b->bj_L, Bp, sm, bj_blocks(b)));
+    HIPCHK(launch_bj_rhs(N, S, mask, b->bj_L, Bp, sm, bj_blocks(b), kBJ));
   else
     HIPCHK(launch_probe_rhs(N, S, mask, b->diag, Bp, sm));
   BCg cy, pr;

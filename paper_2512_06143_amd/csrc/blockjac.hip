@@ -1,18 +1,19 @@
 // Block-Jacobi preconditioner of the CG solves: M = the block diagonal of K over runs
-// of 64 consecutive rows of the internal (bin-sorted) order, M = L L^T blockwise.
+// of BJ consecutive rows of the internal (bin-sorted) order, M = L L^T blockwise (BJ = 128
+// for a matrix handle, 64 for the instances of a batch).
 //
 // The log-determinant and trace estimators use M through its Cholesky factor (the
 // probe right-hand sides are L z, the gradient's trace vectors L^-T z, and
 // ln|K| = ln|M| + ln|L^-1 K L^-T|), so one kernel per matrix factors every block and
 // stores, per block:
-//   - L (row-major 64 x 64, zero above the diagonal)      for the probe right-hand sides,
+//   - L (row-major BJ x BJ, zero above the diagonal)      for the probe right-hand sides,
 //   - M^-1 = L^-T L^-1 in the operand order of the f64 matrix-core instruction,
 //   - the pivots L_ii^2 (sum of logs = ln|M|).
-// Applying M^-1 to a 64-row block of S residual columns is a dense 64 x 64 by 64 x S
+// Applying M^-1 to a BJ-row block of S residual columns is a dense BJ x BJ by BJ x S
 // product: it runs on the matrix cores (v_mfma_f64_16x16x4), fused with the CG
 // solution/residual update so that the residual block is read once.
 //
-// A ragged last block (n not a multiple of 64) is padded with identity rows and
+// A ragged last block (n not a multiple of BJ) is padded with identity rows and
 // columns; padded rows are never read or written outside the workgroup.
 #include "bj_apply.h"
 
@@ -138,32 +139,141 @@ __global__ __launch_bounds__(kBJThreads) void k_bj_factor(int64_t n, const int64
   if (failed) atomicOr(bad, 1);
 }
 
-// One CG update with the block preconditioner, per 64-row block:
+// The factor of one 128-row block for a matrix handle (consecutive 128-row runs from row
+// 0). Two 128 x 129 float64 arrays would exceed the LDS, so the block is factored and then
+// inverted in place: after the Cholesky factor L is written out, column j of L^-1 (for
+// j = 127 down to 0) is formed from the columns of L^-1 to its right and column j of L,
+// L^-1[i][j] = -(1 / L_jj) sum_{k = j+1..i} L^-1[i][k] L[k][j], L^-1[j][j] = 1 / L_jj.
+// The far-field kernel adds its rank-U term to the block as in k_bj_factor.
+template <typename V>
+__global__ __launch_bounds__(kBJM * 4) void k_bj_factor_big(int64_t n, const int64_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ col,
+                                                           const V* __restrict__ val, const double* __restrict__ G,
+                                                           int U, double* __restrict__ Lout,
+                                                           double* __restrict__ Mfrag, float* __restrict__ M32,
+                                                           double* __restrict__ piv, int32_t* __restrict__ bad) {
+  constexpr int B = kBJM, ST = kBJM + 1, NT = kBJM * 4;
+  __shared__ double A[B * ST];  // the block of K, then L, then L^-1 (lower parts)
+  const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
+  const int64_t nblk = (n + B - 1) / B;
+  bool failed = false;
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t r0 = blk * B;
+    const int m = (int)((n - r0) < B ? (n - r0) : B);
+    for (int e = t; e < B * B; e += NT) {
+      const int i = e / B, j = e % B;
+      A[i * ST + j] = (i == j && i >= m) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int i = wave; i < m; i += NT / kWave) {
+      const int64_t s = rp[r0 + i], e = rp[r0 + i + 1];
+      for (int64_t k = s + lane; k < e; k += kWave) {
+        const int64_t c = (int64_t)col[k] - r0;
+        if (c >= 0 && c < m) A[i * ST + (int)c] = (double)val[k];
+      }
+    }
+    __syncthreads();
+    if (G) {
+      for (int e = t; e < B * B; e += NT) {
+        const int i = e / B, j = e % B;
+        if (i < m && j < m) {
+          double acc = 0.0;
+          for (int u = 0; u < U; ++u) acc += G[(r0 + i) * U + u] * G[(r0 + j) * U + u];
+          A[i * ST + j] += acc;
+        }
+      }
+      __syncthreads();
+    }
+    // right-looking Cholesky on the lower triangle
+    for (int k = 0; k < B; ++k) {
+      if (t == 0) {
+        double d = A[k * ST + k];
+        if (!(d > 0.0) || !isfinite(d)) {
+          failed = true;
+          d = 1.0;
+        }
+        A[k * ST + k] = sqrt(d);
+      }
+      __syncthreads();
+      const double dk = A[k * ST + k];
+      for (int i = k + 1 + t; i < B; i += NT) A[i * ST + k] /= dk;
+      __syncthreads();
+      const int cnt = B - 1 - k;
+      for (int e = t; e < cnt * cnt; e += NT) {
+        const int ii = e / cnt, jj = e % cnt;
+        if (jj <= ii) {
+          const int i = k + 1 + ii, j = k + 1 + jj;
+          A[i * ST + j] -= A[i * ST + k] * A[j * ST + k];
+        }
+      }
+      __syncthreads();
+    }
+    if (t < m) {
+      const double l = A[t * ST + t];
+      piv[r0 + t] = l * l;
+    }
+    double* Lb = Lout + blk * (int64_t)(B * B);
+    for (int e = t; e < B * B; e += NT) {
+      const int i = e / B, j = e % B;
+      Lb[e] = j <= i ? A[i * ST + j] : 0.0;
+    }
+    __syncthreads();
+    // L^-1 in place, column by column from the right
+    for (int j = B - 1; j >= 0; --j) {
+      const double ljj = A[j * ST + j];
+      double v = 0.0;
+      const int i = j + 1 + t;
+      if (i < B) {
+        double acc = 0.0;
+        for (int k = j + 1; k <= i; ++k) acc += A[i * ST + k] * A[k * ST + j];
+        v = -acc / ljj;
+      }
+      __syncthreads();
+      if (i < B) A[i * ST + j] = v;
+      if (t == 0) A[j * ST + j] = 1.0 / ljj;
+      __syncthreads();
+    }
+    // M^-1[i][j] = sum_{k >= max(i, j)} L^-1[k][i] L^-1[k][j] (the same sum for (j, i)),
+    // stored in operand order: wave w's 16 rows at w * 16 B, k-step kk at kk * 64 + lane
+    double* Mb = Mfrag + blk * (int64_t)(B * B);
+    for (int e = t; e < B * B; e += NT) {
+      const int w = e / (16 * B), kk = (e >> 6) % (B / 4), l = e & 63;
+      const int i = 16 * w + (l & 15), j = 4 * kk + (l >> 4);
+      double acc = 0.0;
+      for (int k = i > j ? i : j; k < B; ++k) acc += A[k * ST + i] * A[k * ST + j];
+      Mb[e] = acc;
+      if (M32) M32[blk * (int64_t)(B * B) + e] = (float)acc;
+    }
+    __syncthreads();
+  }
+  if (failed) atomicOr(bad, 1);
+}
+
+// One CG update with the block preconditioner, per BJ-row block of a matrix handle:
 //   INIT:  r = b, x = 0;  otherwise  x += alpha p, r -= alpha q   (columns with alpha = 0 keep r)
 //   z = M^-1 r (matrix cores), and the per-column partials of r^T z (which 0) and r^T r (which 1).
 // Thread t of the elementwise phase owns column t % S; waves own 16 rows of z each.
-// Operands of the f64 16x16x4 instruction: lane l holds A[l % 16][l / 16] and
-// B[l / 16][l % 16] of a 16 x 4 by 4 x 16 step.
-template <typename VEC, bool WANTX, bool INIT, typename MT, typename ZT>
-__global__ __launch_bounds__(kBJThreads) void k_bj_update(int64_t n, int S, const double* __restrict__ B,
-                                                          double* __restrict__ X, double* __restrict__ R,
-                                                          const VEC* __restrict__ P, const double* __restrict__ Q,
-                                                          const MT* __restrict__ Mfrag, ZT* __restrict__ Z,
-                                                          CgState cs) {
-  __shared__ double Rs[kBJ * kBJ];  // residual block [row][column], column stride 64
-  __shared__ double red[kBJThreads / kWave][kBJ];
+template <int BJ, typename VEC, bool WANTX, bool INIT, typename MT, typename ZT>
+__global__ __launch_bounds__(BJ * 4) void k_bj_update(int64_t n, int S, const double* __restrict__ B,
+                                                      double* __restrict__ X, double* __restrict__ R,
+                                                      const VEC* __restrict__ P, const double* __restrict__ Q,
+                                                      const MT* __restrict__ Mfrag, ZT* __restrict__ Z,
+                                                      CgState cs) {
+  constexpr int NT = BJ * 4;
+  __shared__ double Rs[BJ * kRsStride];  // residual block [row][column], column stride 64
+  __shared__ double red[NT / kWave][kRsStride];
   const int t = threadIdx.x;
-  const int nth = (kBJThreads / S) * S;
+  const int nth = (NT / S) * S;
   const int s_me = t % S;
   const double a = (INIT || t >= nth) ? 0.0 : cs.alpha[s_me];
-  const int64_t nblk = (n + kBJ - 1) / kBJ;
+  const int64_t nblk = (n + BJ - 1) / BJ;
   double rr = 0.0;
-  double rz[kBJ / 16] = {0.0, 0.0, 0.0, 0.0};
+  double rz[kRsStride / 16] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-    const int64_t r0 = blk * kBJ;
-    const int m = (int)((n - r0) < kBJ ? (n - r0) : kBJ);
+    const int64_t r0 = blk * BJ;
+    const int m = (int)((n - r0) < BJ ? (n - r0) : BJ);
     if (t < nth) {
-      for (int e = t; e < kBJ * S; e += nth) {
+      for (int e = t; e < BJ * S; e += nth) {
         const int i = e / S;
         double r = 0.0;
         if (i < m) {
@@ -182,45 +292,46 @@ __global__ __launch_bounds__(kBJThreads) void k_bj_update(int64_t n, int S, cons
           }
           rr += r * r;
         }
-        Rs[i * kBJ + s_me] = r;
+        Rs[i * kRsStride + s_me] = r;
       }
     }
     __syncthreads();
-    bj_apply_block(Rs, Mfrag + blk * (int64_t)(kBJ * kBJ), m, S, r0, Z, rz);
+    bj_apply_block<BJ>(Rs, Mfrag + blk * (int64_t)(BJ * BJ), m, S, r0, Z, rz);
     __syncthreads();
   }
   // r^T z: lanes sharing a column (lane % 16) across row groups, then across waves
-  const double rzt = bj_rz_total(rz, red, S);
+  const double rzt = bj_rz_total<NT / kWave>(rz, red, S);
   if (t < S) cs.partial[(int64_t)t * gridDim.x + blockIdx.x] = rzt;
   // r^T r: thread t holds column t % S (threads >= nth hold zero)
   Rs[t] = rr;
   __syncthreads();
   if (t < S) {
     double v = 0.0;
-    for (int k = t; k < kBJThreads; k += S) v += Rs[k];
+    for (int k = t; k < NT; k += S) v += Rs[k];
     cs.partial[((int64_t)S + t) * gridDim.x + blockIdx.x] = v;
   }
 }
 
-// Probe right-hand sides B = L z (z = +-1 from the sign masks), per block.
+// Probe right-hand sides B = L z (z = +-1 from the sign masks), per block of BJ rows.
+template <int BJ>
 __global__ __launch_bounds__(kBJThreads) void k_bj_rhs(int64_t n, int S, BjBlocks bl, const uint64_t* __restrict__ mask,
                                                        const double* __restrict__ Lg, double* __restrict__ B) {
-  __shared__ double Ls[kBJ * kBJ];
-  __shared__ uint64_t ms[kBJ];
+  __shared__ double Ls[BJ * BJ];
+  __shared__ uint64_t ms[BJ];
   const int t = threadIdx.x;
-  const int64_t nblk = bj_count(bl, n);
+  const int64_t nblk = bl.r0 ? bl.n : (n + BJ - 1) / BJ;
   for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-    const int64_t r0 = bj_row0(bl, blk);
-    const int m = bj_rows(bl, n, blk);
-    const double* Lb = Lg + blk * (int64_t)(kBJ * kBJ);
-    for (int e = t; e < kBJ * kBJ; e += kBJThreads) Ls[e] = Lb[e];
-    if (t < kBJ) ms[t] = t < m ? mask[r0 + t] : 0ull;
+    const int64_t r0 = bl.r0 ? bl.r0[blk] : blk * BJ;
+    const int m = bl.r0 ? bl.m[blk] : (int)((n - r0) < BJ ? (n - r0) : BJ);
+    const double* Lb = Lg + blk * (int64_t)(BJ * BJ);
+    for (int e = t; e < BJ * BJ; e += kBJThreads) Ls[e] = Lb[e];
+    for (int k = t; k < BJ; k += kBJThreads) ms[k] = k < m ? mask[r0 + k] : 0ull;
     __syncthreads();
     for (int e = t; e < m * S; e += kBJThreads) {
       const int i = e / S, s = e % S;
       double v = 0.0;
       for (int k = 0; k <= i; ++k) {
-        const double l = Ls[i * kBJ + k];
+        const double l = Ls[i * BJ + k];
         v += ((ms[k] >> s) & 1ull) ? -l : l;
       }
       B[r0 * S + e] = v;
@@ -240,13 +351,24 @@ static unsigned bj_grid_blocks(int64_t nblk, int64_t cap) {
   if (nblk < 1) nblk = 1;
   return (unsigned)nblk;
 }
-static unsigned bj_grid(int64_t n, int64_t cap) { return bj_grid_blocks((n + kBJ - 1) / kBJ, cap); }
-static int64_t bj_count_host(const BjBlocks& bl, int64_t n) { return bl.r0 ? bl.n : (n + kBJ - 1) / kBJ; }
+static unsigned bj_grid(int64_t n, int64_t cap, int bj) { return bj_grid_blocks((n + bj - 1) / bj, cap); }
+static int64_t bj_count_host(const BjBlocks& bl, int64_t n, int bj) { return bl.r0 ? bl.n : (n + bj - 1) / bj; }
 
 hipError_t launch_bj_factor(int64_t n, const int64_t* rp, const int32_t* col, const void* val, int prec,
                             const double* G, int U, double* L, double* Mfrag, float* M32, double* piv, int32_t* bad,
-                            hipStream_t st, const BjBlocks& bl) {
-  const unsigned g = bj_grid_blocks(bj_count_host(bl, n), 8192);
+                            hipStream_t st, const BjBlocks& bl, int bj) {
+  if (bj == kBJM) {
+    if (bl.r0) return hipErrorInvalidValue;  // 128-row blocks are consecutive runs only
+    const unsigned g = bj_grid_blocks(bj_count_host(bl, n, bj), 8192);
+    if (prec == GP2S_MIXED)
+      hipLaunchKernelGGL(k_bj_factor_big<float>, dim3(g), dim3(kBJM * 4), 0, st, n, rp, col,
+                         static_cast<const float*>(val), G, U, L, Mfrag, M32, piv, bad);
+    else
+      hipLaunchKernelGGL(k_bj_factor_big<double>, dim3(g), dim3(kBJM * 4), 0, st, n, rp, col,
+                         static_cast<const double*>(val), G, U, L, Mfrag, M32, piv, bad);
+    return hipGetLastError();
+  }
+  const unsigned g = bj_grid_blocks(bj_count_host(bl, n, kBJ), 8192);
   if (prec == GP2S_MIXED)
     hipLaunchKernelGGL(k_bj_factor<float>, dim3(g), dim3(kBJThreads), 0, st, n, rp, col,
                        static_cast<const float*>(val), G, U, bl, L, Mfrag, M32, piv, bad);
@@ -256,25 +378,32 @@ hipError_t launch_bj_factor(int64_t n, const int64_t* rp, const int32_t* col, co
   return hipGetLastError();
 }
 
-unsigned bj_update_blocks(int64_t n) { return bj_grid(n, kDotBlocks); }
+unsigned bj_update_blocks(int64_t n, int bj) { return bj_grid(n, kDotBlocks, bj); }
 
 hipError_t launch_bj_update(int64_t n, int S, const double* B, double* X, double* R, const void* P, const void* Q,
                             bool f32vec, const double* Mfrag, double* Z, const CgState& cs, hipStream_t st,
-                            const float* M32, float* Z32) {
-  const unsigned g = bj_update_blocks(n);
+                            const float* M32, float* Z32, int bj) {
+  const unsigned g = bj_update_blocks(n, bj);
   const bool wx = X != nullptr;
   const double* Qd = static_cast<const double*>(Q);
-#define GP2S_BJ(VEC, WX, INIT)                                                                                  \
+#define GP2S_BJS(BJ, VEC, WX, INIT)                                                                              \
   do {                                                                                                         \
     if (M32)                                                                                                   \
-      hipLaunchKernelGGL((k_bj_update<VEC, WX, INIT, float, double>), dim3(g), dim3(kBJThreads), 0, st, n, S,  \
+      hipLaunchKernelGGL((k_bj_update<BJ, VEC, WX, INIT, float, double>), dim3(g), dim3(BJ * 4), 0, st, n, S,  \
                          B, X, R, static_cast<const VEC*>(P), Qd, M32, Z, cs);                                \
     else if (Z32)                                                                                              \
-      hipLaunchKernelGGL((k_bj_update<VEC, WX, INIT, double, float>), dim3(g), dim3(kBJThreads), 0, st, n, S,  \
+      hipLaunchKernelGGL((k_bj_update<BJ, VEC, WX, INIT, double, float>), dim3(g), dim3(BJ * 4), 0, st, n, S,  \
                          B, X, R, static_cast<const VEC*>(P), Qd, Mfrag, Z32, cs);                            \
     else                                                                                                       \
-      hipLaunchKernelGGL((k_bj_update<VEC, WX, INIT, double, double>), dim3(g), dim3(kBJThreads), 0, st, n, S, \
+      hipLaunchKernelGGL((k_bj_update<BJ, VEC, WX, INIT, double, double>), dim3(g), dim3(BJ * 4), 0, st, n, S, \
                          B, X, R, static_cast<const VEC*>(P), Qd, Mfrag, Z, cs);                              \
+  } while (0)
+#define GP2S_BJ(VEC, WX, INIT)             \
+  do {                                     \
+    if (bj == kBJM)                        \
+      GP2S_BJS(kBJM, VEC, WX, INIT);       \
+    else                                   \
+      GP2S_BJS(kBJ, VEC, WX, INIT);        \
   } while (0)
   if (B) {
     if (wx) GP2S_BJ(double, true, true);
@@ -286,14 +415,20 @@ hipError_t launch_bj_update(int64_t n, int S, const double* B, double* X, double
     if (wx) GP2S_BJ(double, true, false);
     else GP2S_BJ(double, false, false);
   }
+#undef GP2S_BJS
 #undef GP2S_BJ
   return hipGetLastError();
 }
 
 hipError_t launch_bj_rhs(int64_t n, int S, const uint64_t* mask, const double* L, double* B, hipStream_t st,
-                         const BjBlocks& bl) {
-  hipLaunchKernelGGL(k_bj_rhs, dim3(bj_grid_blocks(bj_count_host(bl, n), 8192)), dim3(kBJThreads), 0, st, n, S, bl,
-                     mask, L, B);
+                         const BjBlocks& bl, int bj) {
+  const dim3 g(bj_grid_blocks(bj_count_host(bl, n, bj), 8192));
+  if (bj == kBJM) {
+    if (bl.r0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bj_rhs<kBJM>, g, dim3(kBJThreads), 0, st, n, S, bl, mask, L, B);
+  } else {
+    hipLaunchKernelGGL(k_bj_rhs<kBJ>, g, dim3(kBJThreads), 0, st, n, S, bl, mask, L, B);
+  }
   return hipGetLastError();
 }
 

@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kBJThreads) void k_spmm_bb(int64_t n, int S, const 
     __syncthreads();
   }
   if (!DOT) return;
-  const double tot = bj_rz_total(dot, red, S);
+  const double tot = bj_rz_total<kBJThreads / kWave>(dot, red, S);
   if (t < S) cs.partial[(int64_t)t * gridDim.x + blockIdx.x] = tot;
 }
 

@@ -17,7 +17,8 @@ constexpr int kMaxProbes = 64;     // one probe per lane in the block kernels
 constexpr int kMaxBumps = 256;
 constexpr int kReduceBlocks = 4096;  // max workgroups of the reduction-carrying kernels
 constexpr int kDotBlocks = 1024;     // workgroups of the block-preconditioned CG update (fewer partials per finalize)
-constexpr int kBJ = 64;             // rows per block of the block-Jacobi preconditioner
+constexpr int kBJ = 64;             // rows per block-Jacobi block of a batch instance (and of the block split)
+constexpr int kBJM = 128;           // rows per block-Jacobi block of a matrix handle
 
 // Point records (float4 / double4 of x, y, z and w) carry the bump mask g in w for a
 // point strictly inside some bump, and a quiet NaN for a point outside every bump.
@@ -366,17 +367,17 @@ struct BjBlocks {
 // M32 (optional): a float32 copy of M^-1 in the same order, for the y and refinement solves.
 hipError_t launch_bj_factor(int64_t n, const int64_t* rp, const int32_t* col, const void* val, int prec,
                             const double* G, int U, double* L, double* Mfrag, float* M32, double* piv, int32_t* bad,
-                            hipStream_t st, const BjBlocks& bl = BjBlocks{nullptr, nullptr, 0});
-unsigned bj_update_blocks(int64_t n);
+                            hipStream_t st, const BjBlocks& bl, int bj);
+unsigned bj_update_blocks(int64_t n, int bj);
 // M32 non-null: apply the float32 copy of M^-1 instead (solves whose preconditioner
 // enters no estimator).
 // Z32 non-null: store z in float32 there instead of Z (the mixed path's probe block,
 // whose float32 directions are formed from it by launch_cg_pupdate_z32).
 hipError_t launch_bj_update(int64_t n, int S, const double* B, double* X, double* R, const void* P, const void* Q,
                             bool f32vec, const double* Mfrag, double* Z, const CgState& cs, hipStream_t st,
-                            const float* M32 = nullptr, float* Z32 = nullptr);
+                            const float* M32, float* Z32, int bj);
 hipError_t launch_bj_rhs(int64_t n, int S, const uint64_t* mask, const double* L, double* B, hipStream_t st,
-                         const BjBlocks& bl = BjBlocks{nullptr, nullptr, 0});
+                         const BjBlocks& bl, int bj);
 hipError_t launch_copy_dir(int64_t n, int S, const double* Z, void* P, bool f32vec, hipStream_t st);
 hipError_t launch_probe_rhs(int64_t n, int S, const uint64_t* mask, const double* diag, double* B,
                             hipStream_t st);

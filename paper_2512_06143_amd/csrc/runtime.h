@@ -99,11 +99,14 @@ struct gp2s_matrix_s {
   double* dinv = nullptr;
   bool diag_ok = true;
   // block-Jacobi factor (built on first use, dropped when the values change)
-  double* bj_L = nullptr;    // [nblk * 64 * 64] row-major L per block
-  double* bj_M = nullptr;    // [nblk * 64 * 64] M^-1 per block, matrix-core operand order
-  float* bj_M32 = nullptr;   // the same in float32 (y and refinement solves)
-  double* bj_piv = nullptr;  // [n] L_ii^2
-  bool bj_ready = false;
+  // block-Jacobi factors, [0] over 64-row runs, [1] over 128-row runs (built on first use)
+  struct BjFactor {
+    double* L = nullptr;    // [nblk * B * B] row-major L per block
+    double* M = nullptr;    // [nblk * B * B] M^-1 per block, matrix-core operand order
+    float* M32 = nullptr;   // the same in float32 (y and refinement solves)
+    double* piv = nullptr;  // [n] L_ii^2
+    bool ready = false;
+  } bj[2];
   std::vector<void*> owned;
 };
 
@@ -294,10 +297,17 @@ inline gp2s_status check_opts(gp2s_ctx ctx, const gp2s_solve_opts* o, bool need_
   if (!is_fin(o->tol) || o->tol <= 0 || o->tol >= 1) return fail(ctx, GP2S_E_INVALID, "tol must be in (0, 1)");
   if (!is_fin(o->probe_tol) || o->probe_tol <= 0 || o->probe_tol >= 1)
     return fail(ctx, GP2S_E_INVALID, "probe_tol must be in (0, 1)");
-  if (o->precond != GP2S_PRECOND_JACOBI && o->precond != GP2S_PRECOND_BLOCK)
-    return fail(ctx, GP2S_E_INVALID, "precond must be GP2S_PRECOND_JACOBI (0) or GP2S_PRECOND_BLOCK (1)");
+  if (o->precond != GP2S_PRECOND_JACOBI && o->precond != GP2S_PRECOND_BLOCK && o->precond != GP2S_PRECOND_BLOCK64)
+    return fail(ctx, GP2S_E_INVALID,
+                "precond must be GP2S_PRECOND_JACOBI (0), GP2S_PRECOND_BLOCK (1) or GP2S_PRECOND_BLOCK64 (2)");
   return GP2S_OK;
 }
+
+// Block preconditioners of a matrix handle: 128-row runs (GP2S_PRECOND_BLOCK) or 64-row runs
+// (GP2S_PRECOND_BLOCK64).
+inline bool pc_block(int precond) { return precond == GP2S_PRECOND_BLOCK || precond == GP2S_PRECOND_BLOCK64; }
+inline int pc_rows(int precond) { return precond == GP2S_PRECOND_BLOCK64 ? kBJ : kBJM; }
+inline int pc_idx(int precond) { return precond == GP2S_PRECOND_BLOCK64 ? 0 : 1; }
 
 inline gp2s_status check_matrix(gp2s_ctx ctx, gp2s_matrix m) {
   if (!m) return fail(ctx, GP2S_E_INVALID, "matrix handle is NULL");

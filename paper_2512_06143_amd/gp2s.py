@@ -56,7 +56,7 @@ class SolveOpts(ctypes.Structure):
                 ("probe_tol", ctypes.c_double), ("precond", ctypes.c_int32)]
 
 
-PRECOND = {"jacobi": 0, "block": 1}  # preconditioner of the CG solves (include/gp2s.h)
+PRECOND = {"jacobi": 0, "block": 1, "block64": 2}  # preconditioner of the CG solves (include/gp2s.h)
 
 
 NUM_TIMERS = 16

@@ -13,12 +13,13 @@ def params_of(prob):
 
 def oracle_blocks(x, radius, precond="block"):
     """The preconditioner blocks the oracle's estimators need for a handle assembled
-    from x with support radius r: None (diagonal) or runs of 64 points of the binned
+    from x with support radius r: None (diagonal) or runs of 128 (block) or 64 (block64) points of the binned
     order, computed by the oracle from its own definition."""
     import oracle
     if precond in ("jacobi", 0):
         return None
-    return oracle.block_partition(oracle.bin_order(x, radius), oracle.BLOCK)
+    size = oracle.BLOCK_SMALL if precond in ("block64", 2) else oracle.BLOCK
+    return oracle.block_partition(oracle.bin_order(x, radius), size)
 
 
 def imported_blocks(n, precond="block"):
@@ -26,7 +27,8 @@ def imported_blocks(n, precond="block"):
     import oracle
     if precond in ("jacobi", 0):
         return None
-    return oracle.block_partition(np.arange(n), oracle.BLOCK)
+    size = oracle.BLOCK_SMALL if precond in ("block64", 2) else oracle.BLOCK
+    return oracle.block_partition(np.arange(n), size)
 
 
 def exported_user_csr(m):

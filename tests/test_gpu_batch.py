@@ -113,7 +113,7 @@ def test_batch_block_preconditioner_against_oracle(gpu, precision):
         m.free()
         Z = oracle.rademacher_probes(5, S, p.n)
         order = oracle.bin_order(p.x, p.radius, refine=info["bin_refinement"], min_cells=4096)
-        blocks = oracle.block_partition(order, oracle.BLOCK)
+        blocks = oracle.block_partition(order, oracle.BATCH_BLOCK)
         gam, _ = oracle.logdet_same_probe(Kd, Z, blocks)
         gref, parts = oracle.grad_same_probe(p.x, p.y, Z, p.radius, p.bump_width, p.centers, p.weights,
                                              p.noise_var, K=Kd, blocks=blocks)

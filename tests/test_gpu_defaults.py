@@ -34,21 +34,26 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("precond", ["block", "block64"])
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_lml_grad_at_default_settings(gpu, name, precision):
+def test_lml_grad_at_default_settings(gpu, name, precision, precond):
+    """The library defaults (block preconditioner over 128-point runs), and the same with
+    the 64-point blocks the 10 M-point measurement uses."""
     G = _G()
     prob = CASES[name]()
     opts = G.default_opts(seed=11)
     assert (opts.n_probes, opts.tol, opts.probe_tol, opts.precond) == (64, 1e-8, 1e-5, 1)
-    print(f"[{name}/{precision}] n={prob.n} defaults S=64 tol=1e-8 probe_tol=1e-5 block", flush=True)
+    if precond == "block64":
+        opts = G.default_opts(seed=11, precond=precond)
+    print(f"[{name}/{precision}] n={prob.n} defaults S=64 tol=1e-8 probe_tol=1e-5 {precond}", flush=True)
     m = G.gp2s_assemble(prob.x, params_of(prob), precision)
     rep, grad, a = G.gp2s_lml_grad(m, prob.y, opts)  # GP2S_E_NOCONV would raise here
     Kg, _ = exported_user_csr(m)
     res = oracle.residual_rel(Kg, a.cpu().numpy(), prob.y)
     Kd = Kg.toarray()
     Z = oracle.rademacher_probes(11, 64, prob.n)
-    blocks = oracle_blocks(prob.x, prob.radius)
+    blocks = oracle_blocks(prob.x, prob.radius, precond)
     lml_ref, parts = oracle.lml_same_probe(Kd, prob.y, Z, blocks)
     rel_ld = abs(rep.logdet - parts["gamma"]) / abs(parts["gamma"])
     rel_lml = abs(rep.lml - lml_ref) / abs(lml_ref)

@@ -1,10 +1,10 @@
 """The block-Jacobi preconditioner through the C ABI.
 
 The handle's internal order equals the oracle's binned order bit for bit (the blocks
-of M are runs of 64 points of it); the same-probe log-determinant, LML and gradient
+of M are runs of 128 (or, optionally, 64) points of it); the same-probe log-determinant, LML and gradient
 with the block preconditioner match the oracle given the same blocks (1e-8 relative
 log-determinant and LML, 1e-4 relative gradient) on clouds whose size is not a
-multiple of 64 and on one smaller than a block; solves reach the 1e-8 residual bar in
+multiple of 128 and on one smaller than a block; solves reach the 1e-8 residual bar in
 fewer iterations than with the diagonal; a block that is not positive definite is
 reported as GP2S_E_NOT_SPD, and an unknown preconditioner as GP2S_E_INVALID."""
 import numpy as np
@@ -40,18 +40,19 @@ def test_internal_order_is_the_bin_order(gpu, name):
     m.free()
 
 
+@pytest.mark.parametrize("precond", ["block", "block64"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_block_preconditioned_lml_and_gradient(gpu, name, precision):
+def test_block_preconditioned_lml_and_gradient(gpu, name, precision, precond):
     G = _G()
     prob = CASES[name]()
     S = 12
     m = G.gp2s_assemble(prob.x, params_of(prob), precision)
     Kd = exported_user_csr(m)[0].toarray()
-    opts = G.default_opts(n_probes=S, seed=17, tol=1e-10, probe_tol=1e-10, max_iter=40000, precond="block")
+    opts = G.default_opts(n_probes=S, seed=17, tol=1e-10, probe_tol=1e-10, max_iter=40000, precond=precond)
     rep, grad, a = G.gp2s_lml_grad(m, prob.y, opts)
     Z = oracle.rademacher_probes(17, S, prob.n)
-    blocks = oracle_blocks(prob.x, prob.radius)
+    blocks = oracle_blocks(prob.x, prob.radius, precond)
     gam, terms = oracle.logdet_same_probe(Kd, Z, blocks)
     lml_ref, _ = oracle.lml_same_probe(Kd, prob.y, Z, blocks)
     gref, parts = oracle.grad_same_probe(prob.x, prob.y, Z, prob.radius, prob.bump_width, prob.centers,
