@@ -606,6 +606,9 @@ def main():
                     help="only assemble the --config workload (float32 and float64 storage, --steps times each) and "
                          "print the library's per-stage times: the driver for profiling the assembly kernels")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched (64-instance) measurement")
+    ap.add_argument("--no-breakdown", action="store_true",
+                    help="skip the extra, fully instrumented step (the per-kernel breakdown); the timed steps then "
+                         "bracket the probe-block product for the roofline")
     ap.add_argument("--no-jacobi", action="store_true",
                     help="skip the same step with the diagonal preconditioner (comparison and CPU projection)")
     ap.add_argument("--precond", default="block", choices=["block", "block64", "jacobi"],
@@ -691,16 +694,18 @@ def main():
     # per-kernel breakdown, and the dominant kernel. The timed steps then record events
     # for that kernel only (its roofline), so the host work of ~10^4 event pairs per step
     # does not enter the step time.
-    ctx.set_timing(True)
-    rep, grad, n, nnz = run_step(G, x, y, params, args.precision, opts)
-    stats = ctx.stats()
-    ctx.set_timing(False)
-    for name, (ms, cnt) in stats.items():
-        if cnt:
-            log(f"[bench]   {name:18s} {ms:10.2f} ms  {cnt:7d} launches  {ms / cnt:9.4f} ms avg (instrumented step)")
-    per = {k: v for k, v in stats.items() if v[1] > 0}
-    dom = max(per, key=lambda k: per[k][0])
-
+    if args.no_breakdown:
+        stats, per, dom = None, {}, "cg_matvec_block"
+    else:
+        ctx.set_timing(True)
+        rep, grad, n, nnz = run_step(G, x, y, params, args.precision, opts)
+        stats = ctx.stats()
+        ctx.set_timing(False)
+        for name, (ms, cnt) in stats.items():
+            if cnt:
+                log(f"[bench]   {name:18s} {ms:10.2f} ms  {cnt:7d} launches  {ms / cnt:9.4f} ms avg (instrumented step)")
+        per = {k: v for k, v in stats.items() if v[1] > 0}
+        dom = max(per, key=lambda k: per[k][0])
     ctx.set_timing(True, only=[dom])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -728,8 +733,9 @@ def main():
                                             block_kernel_name(BLOCK_PRODUCT.get(args.precision), S)
                                             if dom == "cg_matvec_block" and args.precision == "mixed" else None),
                 "bytes_per_launch": b, "avg_ms": avg_s * 1e3, "launches": cnt}
+    if stats is None:  # no instrumented step: the timed steps' dominant-kernel events only
+        stats = {k: (0.0, 0) for k in ("asm_prep", "asm_count", "asm_fill", "cg_matvec1")}
     asm_ms = sum(stats[k][0] for k in ("asm_prep", "asm_count", "asm_fill"))  # the instrumented step
-    mv1 = stats["cg_matvec1"]
     spmv_gbs = (kernel_bytes("cg_matvec1", n, nnz, 1, args.precision) / (mv1[0] / mv1[1] / 1e3) / 1e9
                 if mv1[1] else None)
     out = {
