@@ -736,6 +736,7 @@ def main():
     if stats is None:  # no instrumented step: the timed steps' dominant-kernel events only
         stats = {k: (0.0, 0) for k in ("asm_prep", "asm_count", "asm_fill", "cg_matvec1")}
     asm_ms = sum(stats[k][0] for k in ("asm_prep", "asm_count", "asm_fill"))  # the instrumented step
+    mv1 = stats["cg_matvec1"]
     spmv_gbs = (kernel_bytes("cg_matvec1", n, nnz, 1, args.precision) / (mv1[0] / mv1[1] / 1e3) / 1e9
                 if mv1[1] else None)
     out = {
