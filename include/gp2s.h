@@ -268,7 +268,9 @@ gp2s_status gp2s_matrix_refill(gp2s_ctx ctx, gp2s_matrix m, const gp2s_params* p
  * built on first use and kept with the handle), 5 the block split K = B + R (B the dense
  * 64 x 64 diagonal blocks of K over runs of 64 rows, multiplied on the float64 matrix
  * cores; R the other entries, gathered by column slices; nrhs 8, 16, 32 or 64; B is
- * built on first use and kept with the handle, 64 values per row), 4 / 8 / 16 that many lanes splitting
+ * built on first use and kept with the handle, 64 values per row), 6 the column slices of
+ * variant 1 in two launches, each over half of every XCD's rows (nrhs 8, 16, 32 or 64),
+ * 4 / 8 / 16 that many lanes splitting
  * each row's stored entries (1, 2, 4, 8 and 16 need nrhs in {8, 16, 32, 64}, and
  * G <= nrhs),
  * -1 (the default) times the candidates on the first CG block product and keeps the

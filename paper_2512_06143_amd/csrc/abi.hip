@@ -233,6 +233,7 @@ gp2s_status tune_block_product(gp2s_ctx ctx, gp2s_matrix m, int S, const void* P
   std::vector<int> cand{0};
   if (S == 8 || S == 16 || S == 32 || S == 64) {
     cand.push_back(1);
+    cand.push_back(6);
     gp2s_status ts = ensure_tiles(ctx, m);
     if (ts) return ts;
     if (m->tiles) cand.push_back(2);
@@ -1482,7 +1483,7 @@ gp2s_status gp2s_matrix_set_block_product(gp2s_matrix m, int32_t nrhs, int32_t v
   if (!m || nrhs < 2 || nrhs > kMaxProbes) return GP2S_E_INVALID;
   const bool sliced = nrhs == 8 || nrhs == 16 || nrhs == 32 || nrhs == 64;
   const bool ok = variant == -1 || variant == 0 || (variant == 1 && sliced) || (variant == 2 && sliced && m->assembled) ||
-                  (variant == 3 && (nrhs == 32 || nrhs == 64)) || (variant == 5 && sliced) ||
+                  (variant == 3 && (nrhs == 32 || nrhs == 64)) || ((variant == 5 || variant == 6) && sliced) ||
                   entry_product_ok(nrhs, variant);
   if (!ok) return GP2S_E_INVALID;
   m->spmm_variant[nrhs] = variant == -1 ? -2 : variant;

@@ -411,16 +411,26 @@ __global__ __launch_bounds__(kBlock) void k_spmm_e(const int64_t* __restrict__ r
 
 // Slice-per-lane block product (spmm_rows.h) for S in {8, 16, 32, 64}: one wave per
 // row, 16-byte column slices per lane. p^T q partials per workgroup and column as in k_spmm.
+// With npart > 1 a launch covers part `part` of each XCD's row range (the ranges split
+// into npart consecutive pieces), so that the rows of X one XCD gathers in a launch fit
+// its L2; the partials of launch `part` sit at part * gridDim.x in a row of npart *
+// gridDim.x per column.
 template <int S, typename V, typename PT, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_spmm_s(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                    const V* __restrict__ val, int64_t n, const PT* __restrict__ X,
-                                                   double* __restrict__ Y, CgState cs) {
+                                                   double* __restrict__ Y, CgState cs, int part, int npart) {
   constexpr int VW = 16 / sizeof(PT);
   constexpr int LE = S / VW;
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   const int cq = lane % LE;
-  const XcdRows rr = xcd_rows(n, wid, kBlock / kWave);
+  XcdRows rr = xcd_rows(n, wid, kBlock / kWave);
+  if (npart > 1) {
+    const int64_t x = blockIdx.x % 8, lo = n * x / 8, len = n * (x + 1) / 8 - lo;
+    const int64_t sub = lo + len * part / npart;
+    rr.first = sub + (rr.first - lo);
+    rr.end = lo + len * (part + 1) / npart;
+  }
   double dot[VW];
 #pragma unroll
   for (int c = 0; c < VW; ++c) dot[c] = 0.0;
@@ -445,7 +455,7 @@ __global__ __launch_bounds__(kBlock) void k_spmm_s(const int64_t* __restrict__ r
   if ((int)threadIdx.x < S) {
     double t = 0.0;
     for (int w = 0; w < kBlock / kWave; ++w) t += sh[w][threadIdx.x];
-    cs.partial[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+    cs.partial[(int64_t)threadIdx.x * gridDim.x * npart + (int64_t)part * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -670,14 +680,24 @@ static bool spmm_grouped(int64_t n, int S, const TileSet& ts, const PT* X, doubl
 // Launches k_spmm_s when S has an instance and X is 16-byte aligned.
 template <typename V, typename PT, bool DOT>
 static bool spmm_slices(const int64_t* rp, const int32_t* col, const V* val, int64_t n, int S, const PT* X, double* Y,
-                        const CgState& cs, hipStream_t st, int64_t blocks) {
+                        const CgState& cs, hipStream_t st, int64_t blocks, int npart = 1) {
   if ((S != 8 && S != 16 && S != 32 && S != 64) || (reinterpret_cast<uintptr_t>(X) & 15) != 0) return false;
   dim3 grid((unsigned)blocks), block(kBlock);
-  switch (S) {
-    case 8: hipLaunchKernelGGL((k_spmm_s<8, V, PT, DOT>), grid, block, 0, st, rp, col, val, n, X, Y, cs); break;
-    case 16: hipLaunchKernelGGL((k_spmm_s<16, V, PT, DOT>), grid, block, 0, st, rp, col, val, n, X, Y, cs); break;
-    case 32: hipLaunchKernelGGL((k_spmm_s<32, V, PT, DOT>), grid, block, 0, st, rp, col, val, n, X, Y, cs); break;
-    default: hipLaunchKernelGGL((k_spmm_s<64, V, PT, DOT>), grid, block, 0, st, rp, col, val, n, X, Y, cs); break;
+  for (int part = 0; part < npart; ++part) {
+    switch (S) {
+      case 8:
+        hipLaunchKernelGGL((k_spmm_s<8, V, PT, DOT>), grid, block, 0, st, rp, col, val, n, X, Y, cs, part, npart);
+        break;
+      case 16:
+        hipLaunchKernelGGL((k_spmm_s<16, V, PT, DOT>), grid, block, 0, st, rp, col, val, n, X, Y, cs, part, npart);
+        break;
+      case 32:
+        hipLaunchKernelGGL((k_spmm_s<32, V, PT, DOT>), grid, block, 0, st, rp, col, val, n, X, Y, cs, part, npart);
+        break;
+      default:
+        hipLaunchKernelGGL((k_spmm_s<64, V, PT, DOT>), grid, block, 0, st, rp, col, val, n, X, Y, cs, part, npart);
+        break;
+    }
   }
   return true;
 }
@@ -740,6 +760,14 @@ static hipError_t spmm_dispatch(const int64_t* rp, const int32_t* col, const V* 
     gb = round_up8(gb < 1 ? 1 : gb);
     if (spmm_grouped<V, PT, DOT>(n, S, tiles, X, Y, cs, st, gb)) {
       if (nblocks) *nblocks = (int)gb;
+      return hipGetLastError();
+    }
+  } else if (G == 6) {
+    // column slices in two launches over halves of each XCD's rows (L2-sized gathers)
+    int64_t sb = grid_for(kBlock / kWave);
+    if (sb > cap / 2) sb = round_up8(cap / 2 - 7);
+    if (spmm_slices<V, PT, DOT>(rp, col, val, n, S, X, Y, cs, st, sb, 2)) {
+      if (nblocks) *nblocks = (int)(2 * sb);
       return hipGetLastError();
     }
   } else if (G == 5) {

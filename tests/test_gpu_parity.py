@@ -138,8 +138,9 @@ def test_lml_and_gradient_same_probe(case, precision, precond):
             assert grad[k] == 0.0
 
 
-# lane per column, column slices, LDS tiles, row groups, block split, 4/8/16 lanes per row
-BLOCK_VARIANTS = [0, 1, 2, 3, 5, 4, 8, 16]
+# lane per column, column slices, LDS tiles, row groups, block split, two-pass column slices,
+# 4/8/16 lanes per row
+BLOCK_VARIANTS = [0, 1, 2, 3, 5, 6, 4, 8, 16]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
