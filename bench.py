@@ -403,11 +403,13 @@ def bench_large(G, opts, config="c4", reps=3, spmv_reps=20, caps=(20, 100, 300),
       probe-block product and update at this size;
     * the float32-stored y solve to convergence (its iteration count);
     * projected s per LML+gradient = assembly + first-call extra + fixed + per-iteration
-      x the y solve's iteration count to convergence (an upper bound: the probe block
-      stops at its looser tolerance no later than the y solve in every run seen).
+      x the y solve's iteration count to convergence. This is an estimate, not a bound:
+      the two chains run side by side until the longer one ends, and the probe block,
+      despite its looser tolerance, can need a few percent more iterations than the y
+      solve (31 800 against 30 897 in a full float32-stored run at this size).
     The solves use the block preconditioner over 64-point runs: on this clustered cloud
-    the y solve takes 30 877 iterations with them and 31 113 with 128-point runs, which
-    cost more per iteration."""
+    the y solve takes ~30 900 iterations with them and ~31 100 with 128-point runs,
+    which cost more per iteration."""
     import numpy as np
     import torch
     import workloads

@@ -103,23 +103,40 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AssembleArgs a, int64_t nbl
   const bool gen = a.kg.general != 0;
   const double li = a.kg.lsq ? a.kg.lsq[row] : 1.0;
 
-  for (int32_t c0 = 0; c0 < C; c0 += kWave) {
-    const int32_t idx = c0 + lane;
-    const bool ok = idx < C;
-    int64_t j = rs[0] + idx;
+  // Candidates are taken 64 at a time from the concatenated runs. In the count pass and
+  // the float32-stored fill the next step's candidate is loaded before the current one is
+  // tested, so that its latency overlaps the test (rows in crowded cells take many steps);
+  // the float64-stored fill loads in place (its registers would cost occupancy).
+  constexpr bool kAhead = !FILL || F32;
+  auto cand = [&](int32_t idx, int64_t& j, bool& ok, float4& p32, double4& p64, double& l) {
+    j = rs[0] + idx;
 #pragma unroll
     for (int r = 1; r < NR; ++r)
       if (idx >= pre[r]) j = rs[r] + (idx - pre[r]);  // empty runs are overridden by the next
+    ok = idx < C;
+    if (F32) p32 = ok ? a.pts32[j] : make_float4(0.f, 0.f, 0.f, pt_out_f32());
+    else p64 = ok ? a.pts64[j] : make_double4(0., 0., 0., pt_out_f64());
+    l = (a.kg.lsq && ok) ? a.kg.lsq[j] : 1.0;
+  };
+  int64_t jn = 0;
+  bool okn = false;
+  float4 pn32 = make_float4(0.f, 0.f, 0.f, pt_out_f32());
+  double4 pn64 = make_double4(0., 0., 0., pt_out_f64());
+  double ln = 1.0;
+  if (kAhead) cand(lane, jn, okn, pn32, pn64, ln);
+  for (int32_t c0 = 0; c0 < C; c0 += kWave) {
+    int64_t j = jn;
+    bool ok = okn;
+    float4 pj32 = pn32;
+    double4 pj64 = pn64;
+    double lj = ln;
+    if (!kAhead) cand(c0 + lane, j, ok, pj32, pj64, lj);
+    else if (c0 + kWave < C) cand(c0 + kWave + lane, jn, okn, pn32, pn64, ln);
     bool pass;
-    float4 pj32;
-    double4 pj64;
-    const double lj = (a.kg.lsq && ok) ? a.kg.lsq[j] : 1.0;
     if (F32) {
-      pj32 = ok ? a.pts32[j] : make_float4(0.f, 0.f, 0.f, pt_out_f32());
       pass = ok && (j == row || (pt_in(pj32.w) && (gen ? gen_pass_f32<DIM>(pi32, pj32, a.kg, li, lj)
                                                         : sqdist_f32<DIM>(pi32, pj32) < a.r2f)));
     } else {
-      pj64 = ok ? a.pts64[j] : make_double4(0., 0., 0., pt_out_f64());
       pass = ok && (j == row || (pt_in(pj64.w) && (gen ? gen_pass_f64<DIM>(pi64, pj64, a.kg, li, lj)
                                                        : sqdist_f64<DIM>(pi64, pj64) < a.r2)));
     }
