@@ -46,12 +46,12 @@ def log(msg):
 
 
 def kernel_bytes(cat, n, nnz, S, prec, precond="block"):
-    mrow = 64 if precond in ("block64", 2) else 128                # M^-1 values per row
     """Algorithmic HBM bytes of one launch of a timed kernel category: the CSR once,
     each vector stream once, at the types the path stores them in (the probe block
     of the mixed path keeps its search directions P and, with the block
     preconditioner, z = M^-1 r in float32; products Q, x and r are float64; the y
     solve applies a float32 copy of M^-1)."""
+    mrow = 64 if precond in ("block64", 2) else 128                # M^-1 values per row
     vb = 4 if prec == "mixed" else 8                        # stored K value
     block = "block" in cat
     pb = 4 if (prec == "mixed" and block) else 8            # P element
@@ -80,7 +80,13 @@ TRAFFIC_KERNEL = {"cg_update_block": "k_cg_update<float>", "cg_pupdate_block": "
 
 
 def block_kernel_name(variant, S):
-    """Kernel name (as rocprofv3 prints it) of the mixed path's probe-block product."""
+    """Kernel name (as rocprofv3 prints it) of the mixed path's probe-block product, or
+    None for the split product (variant 5, two different kernels). Variant 6 launches
+    k_spmm_s twice per product."""
+    if variant == 5:
+        return None
+    if variant == 6:
+        return f"k_spmm_s<{S}, float, float, true>"
     if variant == 0:
         return "k_spmm<float, float, double, true>"
     if variant == 1:
@@ -92,10 +98,10 @@ def block_kernel_name(variant, S):
     return f"k_spmm_e<{variant}, {S}, float, float, true>"
 
 
-def measured_traffic(cat, config, precision, kernel_name=None):
+def measured_traffic(cat, config, precision, kernel_name=None, launches=1):
     """Scaled FETCH_SIZE + WRITE_SIZE bytes per dispatch from the committed rocprofv3
-    summary, or None when it does not cover this kernel/workload or the kernel
-    sources changed since the counters were taken."""
+    summary, times the dispatches per timed launch, or None when it does not cover
+    this kernel/workload or the kernel sources changed since the counters were taken."""
     import hashlib
     name = kernel_name or TRAFFIC_KERNEL.get(cat)
     if config != "c2" or precision != "mixed" or name is None or not os.path.exists(TRAFFIC_FILE):
@@ -110,7 +116,7 @@ def measured_traffic(cat, config, precision, kernel_name=None):
     for line in text.splitlines():
         if line.startswith(f"| `{name}` |"):
             cells = [c.strip() for c in line.strip("|").split("|")]
-            return (float(cells[2]) + float(cells[5])) * 1e6
+            return (float(cells[2]) + float(cells[5])) * 1e6 * launches
     return None
 
 
@@ -607,6 +613,9 @@ def main():
     ap.add_argument("--only-assembly", action="store_true",
                     help="only assemble the --config workload (float32 and float64 storage, --steps times each) and "
                          "print the library's per-stage times: the driver for profiling the assembly kernels")
+    ap.add_argument("--only-product", action="store_true",
+                    help="only assemble the --config workload (float32 and float64 storage) and time the single-RHS "
+                         "product gp2s_spmv (--steps launches each): the driver for profiling that kernel")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched (64-instance) measurement")
     ap.add_argument("--no-breakdown", action="store_true",
                     help="skip the extra, fully instrumented step (the per-kernel breakdown); the timed steps then "
@@ -661,6 +670,31 @@ def main():
             tot = sum(ms.values())
             res[prec] = {"nnz": nnz, "ms": ms, "nnz_per_s": nnz / (tot / 1e3)}
             log(f"[bench] assembly {prec}: nnz={nnz} {ms} -> {nnz / (tot / 1e3):.3g} nnz/s")
+        print(json.dumps(res), flush=True)
+        return
+    if args.only_product:
+        import workloads
+        prob = workloads.make_problem(args.config, n=args.n)
+        x = torch.as_tensor(prob.x).cuda()
+        v = torch.as_tensor(np.random.default_rng(0).standard_normal(prob.n)).cuda()
+        params = G.HostParams(prob.dim, prob.radius, prob.bump_width, prob.noise_var, prob.centers, prob.weights)
+        ctx = G.default_context()
+        res = {"workload": f"{args.config}: n={prob.n} r={prob.radius:.6g}"}
+        for prec in ("mixed", "fp64"):
+            m = G.gp2s_assemble(x, params, prec)
+            G.gp2s_spmv(m, v)  # warm
+            ctx.set_timing(True)
+            for _ in range(args.steps):
+                G.gp2s_spmv(m, v)
+            ms, cnt = ctx.stats()["spmv"]
+            ctx.set_timing(False)
+            b = kernel_bytes("spmv", m.n, m.nnz, 1, prec)
+            gbs = b / (ms / cnt / 1e3) / 1e9
+            res[prec] = {"nnz": m.nnz, "spmv_ms": ms / cnt, "spmv_bytes": b, "spmv_GBps": gbs,
+                         "spmv_frac_hbm": gbs * 1e9 / PEAK_HBM}
+            log(f"[bench] product {prec}: nnz={m.nnz} {ms / cnt:.3f} ms = {gbs:.0f} GB/s "
+                f"({100 * gbs * 1e9 / PEAK_HBM:.1f}% of HBM)")
+            m.free()
         print(json.dumps(res), flush=True)
         return
     if args.only_large:
@@ -733,7 +767,9 @@ def main():
                 "unit": "GB/s", "frac": b / avg_s / PEAK_HBM,
                 "traffic": measured_traffic(dom, args.config, args.precision,
                                             block_kernel_name(BLOCK_PRODUCT.get(args.precision), S)
-                                            if dom == "cg_matvec_block" and args.precision == "mixed" else None),
+                                            if dom == "cg_matvec_block" and args.precision == "mixed" else None,
+                                            2 if dom == "cg_matvec_block" and BLOCK_PRODUCT.get(args.precision) == 6
+                                            else 1),
                 "bytes_per_launch": b, "avg_ms": avg_s * 1e3, "launches": cnt}
     if stats is None:  # no instrumented step: the timed steps' dominant-kernel events only
         stats = {k: (0.0, 0) for k in ("asm_prep", "asm_count", "asm_fill", "cg_matvec1")}
@@ -757,7 +793,7 @@ def main():
         "assembly_ms": asm_ms, "assembly_nnz_per_s": nnz / (asm_ms / 1e3) if asm_ms else None,
         "cg_spmv_GBps": spmv_gbs,
         "iters_y": rep.iters, "iters_probe": rep.probe_iters, "ir_steps": rep.ir_steps,
-        "block_product": (block_kernel_name(BLOCK_PRODUCT[args.precision], S)
+        "block_product": ((block_kernel_name(BLOCK_PRODUCT[args.precision], S) or "split: k_spmm_sr + k_spmm_bb")
                           if BLOCK_PRODUCT.get(args.precision) is not None else None),
         "resid": rep.resid, "lml": rep.lml, "logdet": rep.logdet, "logdet_stderr": rep.logdet_stderr,
         "grad_r": float(grad[0]),
