@@ -312,6 +312,82 @@ __global__ __launch_bounds__(BJ * 4) void k_bj_update(int64_t n, int S, const do
   }
 }
 
+// Single-column form of the same update (the y and refinement solves, float64 search
+// direction, z stored in float64). z = M^-1 r runs on the vector ALUs from the same
+// operand-order M^-1: lane l of wave w holds row 16w + l % 16 at the columns congruent to
+// l / 16 modulo 4, sums them against r from LDS, and the four lane groups combine by
+// shuffles. The workgroup keeps only BJ doubles of r in LDS (the column-block form keeps
+// BJ x 64), so many more workgroups stay resident, and the next block's M^-1 is loaded
+// before the barrier that publishes r. Partials: r^T z at [b], r^T r at [gridDim + b].
+template <int BJ, bool WANTX, bool INIT, typename MT>
+__global__ __launch_bounds__(BJ * 4) void k_bj_update1(int64_t n, const double* __restrict__ B,
+                                                       double* __restrict__ X, double* __restrict__ R,
+                                                       const double* __restrict__ P, const double* __restrict__ Q,
+                                                       const MT* __restrict__ Mfrag, double* __restrict__ Z,
+                                                       CgState cs) {
+  constexpr int NW = BJ * 4 / kWave;
+  __shared__ double Rs[BJ];
+  __shared__ double red[NW][2];
+  const int t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
+  const int q = lane >> 4, row = 16 * wave + (lane & 15);
+  const double a = INIT ? 0.0 : cs.alpha[0];
+  const int64_t nblk = (n + BJ - 1) / BJ;
+  double rr = 0.0, rz = 0.0;
+  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+    const int64_t r0 = blk * BJ;
+    const int m = (int)((n - r0) < BJ ? (n - r0) : BJ);
+    const MT* F = Mfrag + blk * (int64_t)(BJ * BJ) + wave * (16 * BJ);
+    MT af[BJ / 4];
+#pragma unroll
+    for (int kk = 0; kk < BJ / 4; ++kk) af[kk] = F[kk * 64 + lane];
+    if (t < BJ) {
+      double r = 0.0;
+      if (t < m) {
+        const int64_t g = r0 + t;
+        if (INIT) {
+          r = B[g];
+          R[g] = r;
+          if (WANTX) X[g] = 0.0;
+        } else {
+          r = R[g];
+          if (a != 0.0) {
+            if (WANTX) X[g] += a * P[g];
+            r -= a * Q[g];
+            R[g] = r;
+          }
+        }
+        rr += r * r;
+      }
+      Rs[t] = r;
+    }
+    __syncthreads();
+    double acc = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < BJ / 4; ++kk) acc += (double)af[kk] * Rs[4 * kk + q];
+    acc += __shfl_xor(acc, 16, kWave);
+    acc += __shfl_xor(acc, 32, kWave);
+    if (q == 0 && row < m) {
+      Z[r0 + row] = acc;
+      rz += Rs[row] * acc;
+    }
+    __syncthreads();  // Rs is rewritten by the next block
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    rz += __shfl_xor(rz, o, kWave);
+    rr += __shfl_xor(rr, o, kWave);
+  }
+  if (lane == 0) {
+    red[wave][0] = rz;
+    red[wave][1] = rr;
+  }
+  __syncthreads();
+  if (t < 2) {
+    double v = 0.0;
+    for (int w = 0; w < NW; ++w) v += red[w][t];
+    cs.partial[(int64_t)t * gridDim.x + blockIdx.x] = v;
+  }
+}
+
 // Probe right-hand sides B = L z (z = +-1 from the sign masks), per block of BJ rows.
 template <int BJ>
 __global__ __launch_bounds__(kBJThreads) void k_bj_rhs(int64_t n, int S, BjBlocks bl, const uint64_t* __restrict__ mask,
@@ -405,7 +481,33 @@ hipError_t launch_bj_update(int64_t n, int S, const double* B, double* X, double
     else                                   \
       GP2S_BJS(kBJ, VEC, WX, INIT);        \
   } while (0)
-  if (B) {
+  if (S == 1 && !f32vec && !Z32) {
+#define GP2S_BJ1(BJ, WX, INIT)                                                                                   \
+  do {                                                                                                         \
+    if (M32)                                                                                                   \
+      hipLaunchKernelGGL((k_bj_update1<BJ, WX, INIT, float>), dim3(g), dim3(BJ * 4), 0, st, n, B, X, R,        \
+                         static_cast<const double*>(P), Qd, M32, Z, cs);                                      \
+    else                                                                                                       \
+      hipLaunchKernelGGL((k_bj_update1<BJ, WX, INIT, double>), dim3(g), dim3(BJ * 4), 0, st, n, B, X, R,       \
+                         static_cast<const double*>(P), Qd, Mfrag, Z, cs);                                    \
+  } while (0)
+#define GP2S_BJ1R(WX, INIT)          \
+  do {                               \
+    if (bj == kBJM)                  \
+      GP2S_BJ1(kBJM, WX, INIT);      \
+    else                             \
+      GP2S_BJ1(kBJ, WX, INIT);       \
+  } while (0)
+    if (B) {
+      if (wx) GP2S_BJ1R(true, true);
+      else GP2S_BJ1R(false, true);
+    } else {
+      if (wx) GP2S_BJ1R(true, false);
+      else GP2S_BJ1R(false, false);
+    }
+#undef GP2S_BJ1R
+#undef GP2S_BJ1
+  } else if (B) {
     if (wx) GP2S_BJ(double, true, true);
     else GP2S_BJ(double, false, true);
   } else if (f32vec) {
