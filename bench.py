@@ -75,8 +75,10 @@ def kernel_bytes(cat, n, nnz, S, prec, precond="block"):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c2_mixed.md")
-TRAFFIC_KERNEL = {"cg_update_block": "k_cg_update<float>", "cg_pupdate_block": "k_cg_pupdate<float>",
-                  "cg_matvec1": "k_spmv_a<float, true>"}
+TRAFFIC_KERNEL = {"cg_update_block": "k_bj_update<128, float, true, false, double, float>",
+                  "cg_pupdate_block": "k_cg_pupdate_z32<float>", "cg_matvec1": "k_spmv_a<float, true>"}
+# sources of the CG kernels whose counters the summary holds (hashed in this order)
+TRAFFIC_SOURCES = ("spmv.hip", "spmm_rows.h", "grouped.hip", "pcg.hip", "blockjac.hip", "bj_apply.h", "gp2s_internal.h")
 
 
 def block_kernel_name(variant, S):
@@ -107,7 +109,7 @@ def measured_traffic(cat, config, precision, kernel_name=None, launches=1):
     if config != "c2" or precision != "mixed" or name is None or not os.path.exists(TRAFFIC_FILE):
         return None
     h = hashlib.sha256()
-    for fn in ("spmv.hip", "spmm_rows.h", "pcg.hip"):
+    for fn in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, "paper_2512_06143_amd", "csrc", fn), "rb") as fh:
             h.update(fh.read())
     text = open(TRAFFIC_FILE).read()
