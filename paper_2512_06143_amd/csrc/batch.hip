@@ -854,27 +854,49 @@ __global__ __launch_bounds__(kBJThreads) void k_bbj_update(BatchGeom g, int S, c
   const int m = (int)(br.hi - br.lo);
   double rr = 0.0;
   double rz[kBJ / 16] = {0.0, 0.0, 0.0, 0.0};
-  if (t < nth) {
-    for (int e = t; e < kBJ * S; e += nth) {
-      const int i = e / S;
-      double r = 0.0;
-      if (i < m) {
-        const int64_t gi = r0 * S + e;
+  if (t < nth && m > 0) {
+    // Four elements per thread and pass with unconditional loads (past the block's last
+    // row, its last element is read instead; a finished column still reads p, q, x), so
+    // their loads are all in flight before the first use.
+    constexpr int kU = 4;
+    const int elast = m * S - 1;
+    for (int e0 = t; e0 < kBJ * S; e0 += kU * nth) {
+      double rv[kU], qv[kU], xv[kU];
+      VEC pv[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int e = e0 + u * nth;
+        const int64_t gi = r0 * S + (e < elast ? e : elast);
         if (INIT) {
-          r = B[gi];
-          R[gi] = r;
-          X[gi] = 0.0;
+          rv[u] = B[gi];
         } else {
-          r = R[gi];
-          if (a != 0.0) {
-            X[gi] += a * (double)P[gi];
-            r -= a * Q[gi];
-            R[gi] = r;
-          }
+          rv[u] = R[gi];
+          qv[u] = Q[gi];
+          pv[u] = P[gi];
+          xv[u] = X[gi];
         }
-        rr += r * r;
       }
-      Rs[i * kBJ + s_me] = r;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int e = e0 + u * nth;
+        if (e < kBJ * S) {
+          const int i = e / S;
+          double r = i < m ? rv[u] : 0.0;
+          if (i < m) {
+            const int64_t gi = r0 * S + e;
+            if (INIT) {
+              R[gi] = r;
+              X[gi] = 0.0;
+            } else if (a != 0.0) {
+              X[gi] = xv[u] + a * (double)pv[u];
+              r -= a * qv[u];
+              R[gi] = r;
+            }
+            rr += r * r;
+          }
+          Rs[i * kBJ + s_me] = r;
+        }
+      }
     }
   }
   __syncthreads();

@@ -19,6 +19,8 @@
 
 namespace gp2s {
 
+constexpr double kInfinityCacheBytes = 256.0 * 1024 * 1024;  // the GPU's last-level cache (MI355X)
+
 constexpr int kBJStride = kBJ + 1;  // LDS row stride of the factor kernel (doubles)
 
 // Block b: rows r0 .. r0 + m - 1; consecutive 64-row runs from row 0 unless a block list
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(kBJM * 4) void k_bj_factor_big(int64_t n, const int
 //   INIT:  r = b, x = 0;  otherwise  x += alpha p, r -= alpha q   (columns with alpha = 0 keep r)
 //   z = M^-1 r (matrix cores), and the per-column partials of r^T z (which 0) and r^T r (which 1).
 // Thread t of the elementwise phase owns column t % S; waves own 16 rows of z each.
-template <int BJ, typename VEC, bool WANTX, bool INIT, typename MT, typename ZT>
+template <int BJ, int kU, typename VEC, bool WANTX, bool INIT, typename MT, typename ZT>
 __global__ __launch_bounds__(BJ * 4) void k_bj_update(int64_t n, int S, const double* __restrict__ B,
                                                       double* __restrict__ X, double* __restrict__ R,
                                                       const VEC* __restrict__ P, const double* __restrict__ Q,
@@ -273,26 +275,51 @@ __global__ __launch_bounds__(BJ * 4) void k_bj_update(int64_t n, int S, const do
     const int64_t r0 = blk * BJ;
     const int m = (int)((n - r0) < BJ ? (n - r0) : BJ);
     if (t < nth) {
-      for (int e = t; e < BJ * S; e += nth) {
-        const int i = e / S;
-        double r = 0.0;
-        if (i < m) {
-          const int64_t g = r0 * S + e;
+      // kU elements per thread and pass. Their loads are unconditional (elements past the
+      // block's last row read its last element instead, and a finished column still reads
+      // its p, q, x), so all 4 kU of them are in flight before the first use. kU = 4 pays
+      // where the vectors sit in the Infinity Cache and the loads wait on latency; where
+      // they stream from HBM the extra streams per wave cost more than they hide.
+      const int elast = m * S - 1;
+      for (int e0 = t; e0 < BJ * S; e0 += kU * nth) {
+        double rv[kU], qv[kU], xv[kU];
+        VEC pv[kU];  // converted where used
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int e = e0 + u * nth;
+          const int64_t g = r0 * S + (e < elast ? e : elast);
           if (INIT) {
-            r = B[g];
-            R[g] = r;
-            if (WANTX) X[g] = 0.0;
+            rv[u] = B[g];
           } else {
-            r = R[g];
-            if (a != 0.0) {
-              if (WANTX) X[g] += a * (double)P[g];
-              r -= a * Q[g];
-              R[g] = r;
+            rv[u] = R[g];
+            qv[u] = Q[g];
+            if (WANTX) {
+              pv[u] = P[g];
+              xv[u] = X[g];
             }
           }
-          rr += r * r;
         }
-        Rs[i * kRsStride + s_me] = r;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int e = e0 + u * nth;
+          if (e < BJ * S) {
+            const int i = e / S;
+            double r = i < m ? rv[u] : 0.0;
+            if (i < m) {
+              const int64_t g = r0 * S + e;
+              if (INIT) {
+                R[g] = r;
+                if (WANTX) X[g] = 0.0;
+              } else if (a != 0.0) {
+                if (WANTX) X[g] = xv[u] + a * (double)pv[u];
+                r -= a * qv[u];
+                R[g] = r;
+              }
+              rr += r * r;
+            }
+            Rs[i * kRsStride + s_me] = r;
+          }
+        }
       }
     }
     __syncthreads();
@@ -461,18 +488,23 @@ hipError_t launch_bj_update(int64_t n, int S, const double* B, double* X, double
                             const float* M32, float* Z32, int bj) {
   const unsigned g = bj_update_blocks(n, bj);
   const bool wx = X != nullptr;
+  const bool cached = (double)n * S * sizeof(double) <= kInfinityCacheBytes;
   const double* Qd = static_cast<const double*>(Q);
-#define GP2S_BJS(BJ, VEC, WX, INIT)                                                                              \
+#define GP2S_BJU(BJ, U, VEC, WX, INIT)                                                                          \
   do {                                                                                                         \
-    if (M32)                                                                                                   \
-      hipLaunchKernelGGL((k_bj_update<BJ, VEC, WX, INIT, float, double>), dim3(g), dim3(BJ * 4), 0, st, n, S,  \
-                         B, X, R, static_cast<const VEC*>(P), Qd, M32, Z, cs);                                \
-    else if (Z32)                                                                                              \
-      hipLaunchKernelGGL((k_bj_update<BJ, VEC, WX, INIT, double, float>), dim3(g), dim3(BJ * 4), 0, st, n, S,  \
-                         B, X, R, static_cast<const VEC*>(P), Qd, Mfrag, Z32, cs);                            \
+    if (Z32)                                                                                                   \
+      hipLaunchKernelGGL((k_bj_update<BJ, U, VEC, WX, INIT, double, float>), dim3(g), dim3(BJ * 4), 0, st, n,  \
+                         S, B, X, R, static_cast<const VEC*>(P), Qd, Mfrag, Z32, cs);                         \
     else                                                                                                       \
-      hipLaunchKernelGGL((k_bj_update<BJ, VEC, WX, INIT, double, double>), dim3(g), dim3(BJ * 4), 0, st, n, S, \
-                         B, X, R, static_cast<const VEC*>(P), Qd, Mfrag, Z, cs);                              \
+      hipLaunchKernelGGL((k_bj_update<BJ, U, VEC, WX, INIT, double, double>), dim3(g), dim3(BJ * 4), 0, st, n, \
+                         S, B, X, R, static_cast<const VEC*>(P), Qd, Mfrag, Z, cs);                           \
+  } while (0)
+#define GP2S_BJS(BJ, VEC, WX, INIT)       \
+  do {                                    \
+    if (cached)                           \
+      GP2S_BJU(BJ, 4, VEC, WX, INIT);     \
+    else                                  \
+      GP2S_BJU(BJ, 1, VEC, WX, INIT);     \
   } while (0)
 #define GP2S_BJ(VEC, WX, INIT)             \
   do {                                     \
@@ -507,6 +539,8 @@ hipError_t launch_bj_update(int64_t n, int S, const double* B, double* X, double
     }
 #undef GP2S_BJ1R
 #undef GP2S_BJ1
+  } else if (M32) {
+    return hipErrorInvalidValue;  // the float32 M^-1 serves single-column solves only
   } else if (B) {
     if (wx) GP2S_BJ(double, true, true);
     else GP2S_BJ(double, false, true);
@@ -517,6 +551,7 @@ hipError_t launch_bj_update(int64_t n, int S, const double* B, double* X, double
     if (wx) GP2S_BJ(double, true, false);
     else GP2S_BJ(double, false, false);
   }
+#undef GP2S_BJU
 #undef GP2S_BJS
 #undef GP2S_BJ
   return hipGetLastError();

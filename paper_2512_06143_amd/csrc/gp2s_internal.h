@@ -369,8 +369,8 @@ hipError_t launch_bj_factor(int64_t n, const int64_t* rp, const int32_t* col, co
                             const double* G, int U, double* L, double* Mfrag, float* M32, double* piv, int32_t* bad,
                             hipStream_t st, const BjBlocks& bl, int bj);
 unsigned bj_update_blocks(int64_t n, int bj);
-// M32 non-null: apply the float32 copy of M^-1 instead (solves whose preconditioner
-// enters no estimator).
+// M32 non-null: apply the float32 copy of M^-1 instead (single-column solves whose
+// preconditioner enters no estimator; with S > 1 the call fails).
 // Z32 non-null: store z in float32 there instead of Z (the mixed path's probe block,
 // whose float32 directions are formed from it by launch_cg_pupdate_z32).
 hipError_t launch_bj_update(int64_t n, int S, const double* B, double* X, double* R, const void* P, const void* Q,
