@@ -274,7 +274,10 @@ gp2s_status gp2s_matrix_refill(gp2s_ctx ctx, gp2s_matrix m, const gp2s_params* p
  * each row's stored entries (1, 2, 4, 8 and 16 need nrhs in {8, 16, 32, 64}, and
  * G <= nrhs),
  * -1 (the default) times the candidates on the first CG block product and keeps the
- * fastest. A variant that does not apply gives GP2S_E_INVALID. All variants give the
+ * fastest. The context remembers that choice for the handle's shape (N, nnz, precision,
+ * nrhs and direction type); a later handle of the same shape in the same context takes
+ * it without timing, unless -1 is set on that handle explicitly, which times afresh and
+ * replaces the remembered choice. A variant that does not apply gives GP2S_E_INVALID. All variants give the
  * same products up to the order of float64 summation. */
 gp2s_status gp2s_matrix_set_block_product(gp2s_matrix m, int32_t nrhs, int32_t variant);
 /* The variant in use for `nrhs` columns (HOST output), -1 while not yet chosen. */

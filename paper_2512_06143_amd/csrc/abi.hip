@@ -395,9 +395,22 @@ gp2s_status cg_begin(Cg& c, const double* B, double tol, bool keep_hist, Scratch
   int open = 0;
   for (int s = 0; s < S; ++s) open += pin[s] == 0;
   c.open = open > 0;
-  if (S > 1 && m->spmm_variant[S] == -2) {
-    gp2s_status st = tune_block_product(ctx, m, S, c.P, c.Q, c.f32vec, cs, c.st);
-    if (st) return st;
+  if (S > 1 && (m->spmm_variant[S] == -2 || m->spmm_variant[S] == -3)) {
+    // a handle of the same shape tuned earlier in this context lends its choice
+    auto same = [&](const gp2s_ctx_s::TunedShape& t) {
+      return t.n == m->n && t.nnz == m->nnz && t.prec == m->prec && t.S == S && t.f32vec == c.f32vec;
+    };
+    auto it = std::find_if(ctx->tuned.begin(), ctx->tuned.end(), same);
+    if (m->spmm_variant[S] == -2 && it != ctx->tuned.end()) {
+      m->spmm_variant[S] = it->variant;
+    } else {
+      gp2s_status st = tune_block_product(ctx, m, S, c.P, c.Q, c.f32vec, cs, c.st);
+      if (st) return st;
+      if (it != ctx->tuned.end())
+        it->variant = m->spmm_variant[S];
+      else
+        ctx->tuned.push_back({m->n, m->nnz, m->prec, S, c.f32vec, m->spmm_variant[S]});
+    }
   }
   c.variant = S > 1 ? m->spmm_variant[S] : 0;
   if (c.variant == 3) {
@@ -1486,13 +1499,13 @@ gp2s_status gp2s_matrix_set_block_product(gp2s_matrix m, int32_t nrhs, int32_t v
                   (variant == 3 && (nrhs == 32 || nrhs == 64)) || ((variant == 5 || variant == 6) && sliced) ||
                   entry_product_ok(nrhs, variant);
   if (!ok) return GP2S_E_INVALID;
-  m->spmm_variant[nrhs] = variant == -1 ? -2 : variant;
+  m->spmm_variant[nrhs] = variant == -1 ? -3 : variant;
   return GP2S_OK;
 }
 
 gp2s_status gp2s_matrix_get_block_product(gp2s_matrix m, int32_t nrhs, int32_t* variant) {
   if (!m || !variant || nrhs < 2 || nrhs > kMaxProbes) return GP2S_E_INVALID;
-  *variant = m->spmm_variant[nrhs] == -2 ? -1 : m->spmm_variant[nrhs];
+  *variant = m->spmm_variant[nrhs] < 0 ? -1 : m->spmm_variant[nrhs];
   return GP2S_OK;
 }
 

@@ -34,6 +34,15 @@ struct gp2s_ctx_s {
   int64_t count[GP2S_NUM_TIMERS] = {};
   gp2s_progress_fn progress = nullptr;
   void* progress_user = nullptr;
+  // block-product choices of earlier handles, by shape: a new handle of the same shape
+  // takes the choice instead of timing the candidates again
+  struct TunedShape {
+    int64_t n, nnz;
+    int prec, S;
+    bool f32vec;
+    int variant;
+  };
+  std::vector<TunedShape> tuned;
 };
 
 struct gp2s_matrix_s {
@@ -41,6 +50,8 @@ struct gp2s_matrix_s {
   int64_t n = 0, nnz = 0;
   int prec = GP2S_FP64;
   // block-product variant per column count, measured on first use (-2: not yet)
+  // block product per column count: >= 0 the variant, -2 to be chosen (a remembered
+  // choice for the shape allowed), -3 to be timed afresh
   int spmm_variant[gp2s::kMaxProbes + 1];
   // row tiles of the LDS-staged block product (assembled handles; built on first use)
   gp2s::RowTile* tiles = nullptr;

@@ -213,3 +213,25 @@ def test_block_split_after_refill(case, precision):
     ref1 = exported_user_csr(m)[0] @ X
     assert np.abs(ref1 - ref0).max() > 1e-3 * np.abs(ref0).max()
     np.testing.assert_allclose(Y1, ref1, rtol=1e-12, atol=1e-12 * np.abs(ref1).max())
+
+
+def test_block_product_choice_remembered_per_shape(case):
+    """A second handle of the same shape in the context takes the tuned block product of
+    the first without timing the candidates; -1 set on a handle times them afresh."""
+    G = _G()
+    name, prob, Kref, gamma, ex_pts = case
+    opts = G.default_opts(n_probes=16, max_iter=64, check_every=32)
+    m1 = G.gp2s_assemble(prob.x, params_of(prob), "mixed")
+    m2 = G.gp2s_assemble(prob.x, params_of(prob), "mixed")
+    G.gp2s_lml_grad(m1, prob.y, opts, want_a=False, allow_noconv=True)
+    v1 = m1.block_product(16)
+    assert v1 >= 0
+    assert m2.block_product(16) == -1
+    G.gp2s_lml_grad(m2, prob.y, opts, want_a=False, allow_noconv=True)
+    assert m2.block_product(16) == v1
+    m2.set_block_product(16, -1)
+    assert m2.block_product(16) == -1
+    G.gp2s_lml_grad(m2, prob.y, opts, want_a=False, allow_noconv=True)
+    assert m2.block_product(16) >= 0
+    m1.free()
+    m2.free()
