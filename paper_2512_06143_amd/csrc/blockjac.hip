@@ -89,13 +89,11 @@ __global__ __launch_bounds__(kBJThreads) void k_bj_factor(int64_t n, const int64
       const double dk = A[k * kBJStride + k];
       for (int i = k + 1 + t; i < kBJ; i += kBJThreads) A[i * kBJStride + k] /= dk;
       __syncthreads();
-      const int cnt = kBJ - 1 - k;
-      for (int e = t; e < cnt * cnt; e += kBJThreads) {
-        const int ii = e / cnt, jj = e % cnt;
-        if (jj <= ii) {
-          const int i = k + 1 + ii, j = k + 1 + jj;
-          A[i * kBJStride + j] -= A[i * kBJStride + k] * A[j * kBJStride + k];
-        }
+      // trailing update of the lower triangle: wave w takes rows k+1+w, k+5+w, ..., its
+      // lanes the columns of a row
+      for (int i = k + 1 + wave; i < kBJ; i += kBJThreads / kWave) {
+        const double lik = A[i * kBJStride + k];
+        for (int j = k + 1 + lane; j <= i; j += kWave) A[i * kBJStride + j] -= lik * A[j * kBJStride + k];
       }
       __syncthreads();
     }
@@ -118,9 +116,17 @@ __global__ __launch_bounds__(kBJThreads) void k_bj_factor(int64_t n, const int64
         } else if (i == j) {
           v = 1.0 / A[j * kBJStride + j];
         } else {
-          double s = 0.0;
-          for (int k = j; k < i; ++k) s += A[i * kBJStride + k] * Li[k * kBJStride + j];
-          v = -s / A[i * kBJStride + i];
+          // four independent partial sums, so that the LDS reads of a chain overlap
+          double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+          int k = j;
+          for (; k + 4 <= i; k += 4) {
+            a0 += A[i * kBJStride + k] * Li[k * kBJStride + j];
+            a1 += A[i * kBJStride + k + 1] * Li[(k + 1) * kBJStride + j];
+            a2 += A[i * kBJStride + k + 2] * Li[(k + 2) * kBJStride + j];
+            a3 += A[i * kBJStride + k + 3] * Li[(k + 3) * kBJStride + j];
+          }
+          for (; k < i; ++k) a0 += A[i * kBJStride + k] * Li[k * kBJStride + j];
+          v = -((a0 + a1) + (a2 + a3)) / A[i * kBJStride + i];
         }
         Li[i * kBJStride + j] = v;
       }
@@ -131,8 +137,16 @@ __global__ __launch_bounds__(kBJThreads) void k_bj_factor(int64_t n, const int64
     for (int e = t; e < kBJ * kBJ; e += kBJThreads) {
       const int w = e >> 10, kk = (e >> 6) & 15, l = e & 63;
       const int i = 16 * w + (l & 15), j = 4 * kk + (l >> 4);
-      double s = 0.0;
-      for (int k = i > j ? i : j; k < kBJ; ++k) s += Li[k * kBJStride + i] * Li[k * kBJStride + j];
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int k = i > j ? i : j;
+      for (; k + 3 < kBJ; k += 4) {
+        a0 += Li[k * kBJStride + i] * Li[k * kBJStride + j];
+        a1 += Li[(k + 1) * kBJStride + i] * Li[(k + 1) * kBJStride + j];
+        a2 += Li[(k + 2) * kBJStride + i] * Li[(k + 2) * kBJStride + j];
+        a3 += Li[(k + 3) * kBJStride + i] * Li[(k + 3) * kBJStride + j];
+      }
+      for (; k < kBJ; ++k) a0 += Li[k * kBJStride + i] * Li[k * kBJStride + j];
+      const double s = (a0 + a1) + (a2 + a3);
       Mb[e] = s;
       if (M32) M32[blk * (int64_t)(kBJ * kBJ) + e] = (float)s;
     }
@@ -200,13 +214,11 @@ __global__ __launch_bounds__(kBJM * 4) void k_bj_factor_big(int64_t n, const int
       const double dk = A[k * ST + k];
       for (int i = k + 1 + t; i < B; i += NT) A[i * ST + k] /= dk;
       __syncthreads();
-      const int cnt = B - 1 - k;
-      for (int e = t; e < cnt * cnt; e += NT) {
-        const int ii = e / cnt, jj = e % cnt;
-        if (jj <= ii) {
-          const int i = k + 1 + ii, j = k + 1 + jj;
-          A[i * ST + j] -= A[i * ST + k] * A[j * ST + k];
-        }
+      // trailing update of the lower triangle: wave w takes rows k+1+w, k+1+w+8, ..., its
+      // lanes the columns of a row
+      for (int i = k + 1 + wave; i < B; i += NT / kWave) {
+        const double lik = A[i * ST + k];
+        for (int j = k + 1 + lane; j <= i; j += kWave) A[i * ST + j] -= lik * A[j * ST + k];
       }
       __syncthreads();
     }
@@ -226,9 +238,17 @@ __global__ __launch_bounds__(kBJM * 4) void k_bj_factor_big(int64_t n, const int
       double v = 0.0;
       const int i = j + 1 + t;
       if (i < B) {
-        double acc = 0.0;
-        for (int k = j + 1; k <= i; ++k) acc += A[i * ST + k] * A[k * ST + j];
-        v = -acc / ljj;
+        // four independent partial sums, so that the LDS reads of a chain overlap
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int k = j + 1;
+        for (; k + 3 <= i; k += 4) {
+          a0 += A[i * ST + k] * A[k * ST + j];
+          a1 += A[i * ST + k + 1] * A[(k + 1) * ST + j];
+          a2 += A[i * ST + k + 2] * A[(k + 2) * ST + j];
+          a3 += A[i * ST + k + 3] * A[(k + 3) * ST + j];
+        }
+        for (; k <= i; ++k) a0 += A[i * ST + k] * A[k * ST + j];
+        v = -((a0 + a1) + (a2 + a3)) / ljj;
       }
       __syncthreads();
       if (i < B) A[i * ST + j] = v;
@@ -241,8 +261,16 @@ __global__ __launch_bounds__(kBJM * 4) void k_bj_factor_big(int64_t n, const int
     for (int e = t; e < B * B; e += NT) {
       const int w = e / (16 * B), kk = (e >> 6) % (B / 4), l = e & 63;
       const int i = 16 * w + (l & 15), j = 4 * kk + (l >> 4);
-      double acc = 0.0;
-      for (int k = i > j ? i : j; k < B; ++k) acc += A[k * ST + i] * A[k * ST + j];
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int k = i > j ? i : j;
+      for (; k + 3 < B; k += 4) {
+        a0 += A[k * ST + i] * A[k * ST + j];
+        a1 += A[(k + 1) * ST + i] * A[(k + 1) * ST + j];
+        a2 += A[(k + 2) * ST + i] * A[(k + 2) * ST + j];
+        a3 += A[(k + 3) * ST + i] * A[(k + 3) * ST + j];
+      }
+      for (; k < B; ++k) a0 += A[k * ST + i] * A[k * ST + j];
+      const double acc = (a0 + a1) + (a2 + a3);
       Mb[e] = acc;
       if (M32) M32[blk * (int64_t)(B * B) + e] = (float)acc;
     }
