@@ -75,7 +75,7 @@ def kernel_bytes(cat, n, nnz, S, prec, precond="block"):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c2_mixed.md")
-TRAFFIC_KERNEL = {"cg_update_block": "k_bj_update<128, float, true, false, double, float>",
+TRAFFIC_KERNEL = {"cg_update_block": "k_bj_update<128, 4, float, true, false, double, float>",
                   "cg_pupdate_block": "k_cg_pupdate_z32<float>", "cg_matvec1": "k_spmv_a<float, true>"}
 # sources of the CG kernels whose counters the summary holds (hashed in this order)
 TRAFFIC_SOURCES = ("spmv.hip", "spmm_rows.h", "grouped.hip", "pcg.hip", "blockjac.hip", "bj_apply.h", "gp2s_internal.h")
