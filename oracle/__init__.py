@@ -5,8 +5,8 @@ computes, written from the paper (arXiv 2512.06143):
 
 * the compactly supported kernel k(x_i, x_j) = g(x_i) g(x_j) W(||x_i - x_j|| / r),
   the product construction of Sec. 4.1 with g a sum of bump functions (Sec. 4.3,
-  Eq. bump) and W the C^2 member of the Wendland family ("small variations" of
-  Eq. wendland);
+  Eq. bump) and W the C^2 member of the Wendland family (a variant of Eq. wendland,
+  which Sec. 4.1 allows);
 * its sparsity pattern, by brute force and by a k-d tree;
 * the log marginal likelihood of Sec. 3 (first displayed equation, zero prior
   mean, noise on the diagonal) through a dense Cholesky factorisation;

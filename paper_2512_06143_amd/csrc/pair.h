@@ -96,7 +96,7 @@ __device__ inline double sqdist_f64(const double4& a, const double4& b) {
 }
 
 // Wendland members (Sec. 4.1): kern 0 is the C^2 member (1 - rho)^4 (4 rho + 1), the
-// workloads' "small variation"; kern 1 is the C^6 member of Eq. wendland as printed,
+// variant the workloads use; kern 1 is the C^6 member of Eq. wendland as printed,
 // (1 - rho)^8 (32 rho^3 + 25 rho^2 + 8 rho + 1). om = 1 - rho is passed in, formed
 // from 1 - rho^2 without cancellation near the support boundary.
 template <typename T>
