@@ -18,6 +18,9 @@ on the same inputs. Beside the timed steps (not in `value`):
   counts (their difference gives the time per iteration), the y solve to convergence,
   and the projected seconds per LML+gradient;
 * `batch`: the 64-instance batched workload, instances per second;
+* `posterior`, `mcmc`, `variants`: the posterior at 100 000 test points, one block
+  Metropolis-Hastings sweep, and one LML+gradient with each other kernel (the C^6
+  member, Eq. wendconv with axis radii, the far-field bump kernel) on the timed cloud;
 * `cpu_baseline`: the oracle's sparse LML+gradient timed on a bounded window.
 
 The timed steps bracket only the dominant kernel with HIP events (for its roofline);
