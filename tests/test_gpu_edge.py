@@ -6,7 +6,8 @@ import pytest
 
 import oracle
 import workloads
-from gpu_util import compare_patterns, exported_user_csr, imported_blocks, params_of, pattern_pairs
+from gpu_util import (compare_patterns, exported_user_csr, imported_blocks, params_of, pattern_pairs,
+                      rel_entry_errors)
 
 pytestmark = pytest.mark.gpu
 
@@ -313,3 +314,51 @@ def test_allocator_failure_reports_oom_without_leak(gpu):
         print(f"[oom] failing allocation {k} of {total}: status {e.value.status}", flush=True)
         assert e.value.status == 3
         assert not live, f"{len(live)} allocations leaked after failing call {k}"
+
+
+def _grouping_case(shape):
+    """Clouds that stress the 16-row groups of the assembly: all rows in one cell with
+    fewer or more candidates than a wave's 64 lanes, every row in a cell of its own, and
+    groups mixing rows inside and outside the bumps (sizes not multiples of 16)."""
+    rng = np.random.default_rng(17)
+    if shape == "one_cell_small":
+        x = 0.5 + 0.01 * rng.standard_normal((50, 2))
+        return x, 0.5, np.array([[0.5, 0.5]]), np.array([1.2]), 0.8
+    if shape == "one_cell_big":
+        x = 0.5 + 0.01 * rng.standard_normal((301, 2))
+        return x, 0.5, np.array([[0.5, 0.5]]), np.array([1.2]), 0.8
+    if shape == "cell_per_row":
+        x = rng.uniform(0.0, 1.0, (37, 2))
+        return x, 0.004, np.array([[0.5, 0.5]]), np.array([1.0]), 2.0
+    x = rng.uniform(0.0, 1.0, (203, 2))  # mixed support: the bump covers about half the points
+    return x, 0.15, np.array([[0.0, 0.5]]), np.array([0.9]), 0.7
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape", ["one_cell_small", "one_cell_big", "cell_per_row", "mixed_support"])
+def test_assembly_row_groups(gpu, precision, shape):
+    """Pattern and values against the oracle on clouds whose binned rows fill the
+    assembly's 16-row groups in unusual ways."""
+    G = _G()
+    x, r, c, w, bw = _grouping_case(shape)
+    x = workloads.f32(x)  # float32-representable, as the workloads' coordinates are
+    noise = 1e-3
+    p = G.HostParams(2, r, bw, noise, c, w)
+    Kref = oracle.covariance_csr(x, r, bw, c, w, noise)
+    m = G.gp2s_assemble(x, p, precision)
+    Kg, raw = exported_user_csr(m)
+    rp, col = raw["rp"], raw["col"]
+    for i in range(m.n):
+        cc = col[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(cc) > 0) and i in cc
+    ex_pts = oracle.boundary_exempt_points(x, c, bw)
+
+    class _P:  # the fields compare_patterns reads
+        radius = r
+    nmis, nex = compare_patterns(pattern_pairs(Kg), pattern_pairs(Kref), x, _P, ex_pts)
+    err, _ = rel_entry_errors(Kg, Kref)
+    print(f"[{shape}/{precision}] n={m.n} nnz={m.nnz} (oracle {Kref.nnz}) mismatches={nmis} exempt={nex} "
+          f"max rel entry err {err:.2e}", flush=True)
+    assert nmis == 0
+    assert err <= (1e-5 if precision == "mixed" else 1e-9)
+    m.free()
