@@ -49,7 +49,6 @@ struct gp2s_matrix_s {
   gp2s_ctx ctx = nullptr;
   int64_t n = 0, nnz = 0;
   int prec = GP2S_FP64;
-  // block-product variant per column count, measured on first use (-2: not yet)
   // block product per column count: >= 0 the variant, -2 to be chosen (a remembered
   // choice for the shape allowed), -3 to be timed afresh
   int spmm_variant[gp2s::kMaxProbes + 1];
@@ -109,8 +108,8 @@ struct gp2s_matrix_s {
   double* diag = nullptr;
   double* dinv = nullptr;
   bool diag_ok = true;
-  // block-Jacobi factor (built on first use, dropped when the values change)
-  // block-Jacobi factors, [0] over 64-row runs, [1] over 128-row runs (built on first use)
+  // block-Jacobi factors, [0] over 64-row runs, [1] over 128-row runs (built on first use,
+  // dropped when the values change)
   struct BjFactor {
     double* L = nullptr;    // [nblk * B * B] row-major L per block
     double* M = nullptr;    // [nblk * B * B] M^-1 per block, matrix-core operand order

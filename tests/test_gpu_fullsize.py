@@ -121,16 +121,18 @@ def test_c4_full_single_rhs_product(precision):
     m.free()
 
 
-def test_c2_full_block_product():
-    """The 64-column block product the probe solves use, at the benchmark's size (the
-    variant the tuner picks for this matrix), at sampled rows."""
+@pytest.mark.parametrize("variant", [-1, 1, 3])
+def test_c2_full_block_product(variant):
+    """The 64-column block product the probe solves use, at the benchmark's size, at
+    sampled rows: the default choice, the column slices and the row groups."""
     G = _G()
     prob = workloads.make_problem("c2")
     m = G.gp2s_assemble(prob.x, params_of(prob), "mixed")
+    m.set_block_product(64, variant)
     X = np.random.default_rng(4).standard_normal((prob.n, 64))
     Y = G.gp2s_spmv(m, X).cpu().numpy()
     worst, _ = _sampled_product_check(m, X, Y)
-    print(f"[c2/mixed] 64-column product max rel err {worst:.2e} (variant {m.block_product(64)})", flush=True)
+    print(f"[c2/mixed] 64-column product, variant {variant}: max rel err {worst:.2e}", flush=True)
     assert worst <= 1e-13
     m.free()
 
